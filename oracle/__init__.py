@@ -1,0 +1,250 @@
+"""Plain FP64 CPU oracle for the Scylla LP hot path.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg may import this package; the HIP library and its Python binding
+never do.  The heavy loops (PDHG, KKT, fix-and-propagate) are plain C in
+``scylla_oracle.c``; the pump objective update (Algorithm 1, objective update
+step; Section 2.4) and the tolerance schedule (Section 2.2) are written here
+with numpy.
+
+Parity status of each function (pins live in tests/test_oracle_*.py):
+  precondition, pdhg, kkt       pinned (brute force, closed forms, HiGHS,
+                                independent KKT, invariants, fixed point,
+                                nonexpansiveness, ||A~|| <= 1)
+  fix_propagate                 pinned (integrality/bounds, identity on
+                                feasible integral input, set-cover success,
+                                brute-force propagation soundness)
+  objective_update, eps_schedule pinned (closed forms / norm identities)
+  pump                          parity unpinned: the round of first success
+                                depends on rounding choices the paper leaves
+                                open; only its invariants are checked.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "scylla_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OPTIMAL, ITERATION_LIMIT, NUMERICAL_ERROR = 1, 2, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, no vectorisation tricks)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _LPStruct(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("c", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("sense", ctypes.c_void_p), ("l", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("iter_limit", ctypes.c_int64),
+                ("check_period", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("ruiz_iters", ctypes.c_int32),
+                ("pock_chambolle", ctypes.c_int32), ("omega0", ctypes.c_double)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("iterations", ctypes.c_int64), ("rel_kkt", ctypes.c_double),
+                ("rho_p", ctypes.c_double), ("rho_d", ctypes.c_double),
+                ("rho_g", ctypes.c_double), ("pobj", ctypes.c_double),
+                ("dobj", ctypes.c_double), ("omega", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_fix_propagate"):
+            getattr(lib, fn).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+class _Pinned:
+    """Keeps contiguous numpy copies alive while C uses them."""
+
+    def __init__(self, lp, c=None):
+        self.row_ptr = np.ascontiguousarray(lp.row_ptr, dtype=np.int64)
+        self.col_idx = np.ascontiguousarray(lp.col_idx, dtype=np.int32)
+        self.val = np.ascontiguousarray(lp.val, dtype=np.float64)
+        self.c = np.ascontiguousarray(lp.c if c is None else c, dtype=np.float64)
+        self.b = np.ascontiguousarray(lp.b, dtype=np.float64)
+        self.sense = np.ascontiguousarray(lp.senses, dtype=np.uint8)
+        self.l = np.ascontiguousarray(lp.l, dtype=np.float64)
+        self.u = np.ascontiguousarray(lp.u, dtype=np.float64)
+        self.s = _LPStruct(lp.m, lp.n, _p(self.row_ptr), _p(self.col_idx), _p(self.val),
+                           _p(self.c), _p(self.b), _p(self.sense), _p(self.l), _p(self.u))
+
+
+@dataclass
+class PDHGResult:
+    x: np.ndarray
+    y: np.ndarray
+    status: int
+    iterations: int
+    restarts: int
+    rel_kkt: float
+    rho_p: float
+    rho_d: float
+    rho_g: float
+    pobj: float
+    dobj: float
+    omega: float
+
+
+def precondition(lp, ruiz_iters: int = 10, pock_chambolle: bool = True):
+    """Diagonal preconditioner (d_r, d_c); A~ = diag(d_r) A diag(d_c)."""
+    pin = _Pinned(lp)
+    dr = np.empty(lp.m)
+    dc = np.empty(lp.n)
+    rc = _load().orc_precondition(ctypes.byref(pin.s), ruiz_iters, int(pock_chambolle), _p(dr), _p(dc))
+    assert rc == 0
+    return dr, dc
+
+
+def kkt(lp, x, y, c=None):
+    """Relative KKT of (x, y): dict with rel, rho_p, rho_d, rho_g, pobj, dobj."""
+    pin = _Pinned(lp, c)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(8)
+    rc = _load().orc_kkt(ctypes.byref(pin.s), _p(x), _p(y), _p(out))
+    assert rc == 0
+    return dict(rel=out[0], rho_p=out[1], rho_d=out[2], rho_g=out[3], pobj=out[4],
+                dobj=out[5], bnorm=out[6], cnorm=out[7])
+
+
+def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 64,
+         restarts: bool = True, eta: float = 0.99, x0=None, y0=None, omega0: float = 0.0,
+         c=None, ruiz_iters: int = 10, pock_chambolle: bool = True) -> PDHGResult:
+    """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop)."""
+    pin = _Pinned(lp, c)
+    x = np.empty(lp.n)
+    y = np.empty(lp.m)
+    x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+    y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+    prm = _Params(tol, iter_limit, check_period, int(restarts), eta, ruiz_iters,
+                  int(pock_chambolle), omega0)
+    res = _Result()
+    rc = _load().orc_pdhg(ctypes.byref(pin.s), ctypes.byref(prm), _p(x0a), _p(y0a), _p(x), _p(y),
+                          ctypes.byref(res))
+    assert rc == 0
+    return PDHGResult(x, y, res.status, res.iterations, res.restarts, res.rel_kkt, res.rho_p,
+                      res.rho_d, res.rho_g, res.pobj, res.dobj, res.omega)
+
+
+def fix_propagate(lp, xbar, is_int=None):
+    """Fix-and-propagate rounding (Section 2.3).  Returns (x_hat, feasible,
+    ignored_rows)."""
+    pin = _Pinned(lp)
+    is_int = np.ascontiguousarray(lp.is_int if is_int is None else is_int, dtype=np.uint8)
+    xb = np.ascontiguousarray(xbar, dtype=np.float64)
+    xhat = np.empty(lp.n)
+    info = np.zeros(2, dtype=np.int32)
+    rc = _load().orc_fix_propagate(ctypes.byref(pin.s), _p(is_int), _p(xb), _p(xhat), _p(info))
+    assert rc == 0
+    return xhat, bool(info[0]), int(info[1])
+
+
+# ------------------------------------------------ objective update (O3)
+ALPHA = 0.9
+
+
+def distance_gradient(xhat, l, u, is_int):
+    """Coefficients g of the L1 distance Delta(x, x_hat) on binary variables:
+    Delta = g^T x + sum_j x_hat_j for x in [0,1]^n, with g_j = +1 where x_hat_j
+    sits at its lower bound and -1 where it sits at its upper bound; 0 on
+    continuous variables.  General integers strictly inside their bounds
+    would need auxiliary variables (Section 4) and are rejected."""
+    g = np.zeros(len(xhat))
+    ii = is_int.astype(bool)
+    at_l = ii & (xhat == l)
+    at_u = ii & (xhat == u) & ~at_l
+    if np.any(ii & ~at_l & ~at_u):
+        raise ValueError("general-integer distance needs auxiliary variables")
+    g[at_l] = 1.0
+    g[at_u] = -1.0
+    return g
+
+
+def objective_update(c, xhat, l, u, is_int, K: int, alpha: float = ALPHA):
+    """Algorithm 1 objective update after the K-th rounding:
+    c_hat = alpha^K * (sqrt(|I|) / ||c||_2) * c + (1 - alpha^K) * grad Delta."""
+    a = alpha ** K
+    nI = int(np.count_nonzero(is_int))
+    cn = float(np.linalg.norm(c))
+    g = distance_gradient(xhat, l, u, is_int)
+    scaled = (np.sqrt(nI) / cn) * c if cn > 0 else np.zeros_like(c)
+    return a * scaled + (1.0 - a) * g
+
+
+def eps_schedule(K: int, eps1: float = 0.01, beta: float = 0.98, floor: float = 1e-8) -> float:
+    """Section 2.2: eps(1) = 0.01, eps(K+1) = max(beta eps(K), 1e-8)."""
+    e = eps1
+    for _ in range(K - 1):
+        e = max(beta * e, floor)
+    return e
+
+
+def mip_feasible(lp, x, tol: float = 1e-6) -> bool:
+    """Rows within tol (1 + |b_i|), bounds within tol, integrality within tol."""
+    rows = lp.row_of_entry()
+    ax = np.bincount(rows, weights=lp.val * x[lp.col_idx], minlength=lp.m)
+    t = tol * (1.0 + np.abs(lp.b))
+    s = lp.senses
+    ok = np.where(s == ord("G"), ax >= lp.b - t,
+                  np.where(s == ord("L"), ax <= lp.b + t, np.abs(ax - lp.b) <= t))
+    ii = lp.is_int.astype(bool)
+    return bool(ok.all() and np.all(x >= lp.l - tol) and np.all(x <= lp.u + tol)
+                and np.all(np.abs(x[ii] - np.round(x[ii])) <= tol))
+
+
+def pump(lp, rounds: int = 20, tol: float = 1e-4, iter_limit: int = 20_000,
+         xhat_sequence=None, **kw):
+    """Warm-started pump rounds on one instance (Algorithm 1 outer loop with
+    cycle perturbation off, every round run).  Round 1 solves with c; round
+    K >= 2 solves with the blend built from the (K-1)-th rounding.  If
+    ``xhat_sequence`` is given, those roundings are used instead of the
+    oracle's own (open-loop replay).  Returns per-round records."""
+    c_hat = lp.c.copy()
+    x = y = None
+    omega = 0.0
+    out = []
+    for K in range(1, rounds + 1):
+        r = pdhg(lp, tol=tol, iter_limit=iter_limit, x0=x, y0=y, omega0=omega, c=c_hat, **kw)
+        x, y, omega = r.x, r.y, r.omega
+        xhat, feas, ign = fix_propagate(lp, r.x)
+        if xhat_sequence is not None:
+            xhat = xhat_sequence[K - 1]
+            feas = mip_feasible(lp, xhat)
+        out.append(dict(K=K, status=r.status, iterations=r.iterations, rel_kkt=r.rel_kkt,
+                        x=r.x, y=r.y, omega=r.omega, lp_mip_feasible=mip_feasible(lp, r.x),
+                        xhat=xhat, xhat_feasible=feas, ignored=ign,
+                        obj=float(lp.c @ xhat)))
+        c_hat = objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K)
+    return out

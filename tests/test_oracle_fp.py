@@ -1,0 +1,185 @@
+"""Pins of the oracle's fix-and-propagate (Section 2.3), objective update
+(Algorithm 1 objective step, Section 2.4) and tolerance schedule
+(Section 2.2)."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03466_amd import instances as I
+from lp_util import GOLDEN, dense, lp_from_dense
+
+with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+    PAPER = json.load(f)
+
+
+def _row_ok(lp, x, tol=1e-9):
+    A = dense(lp)
+    ax = A @ x
+    s = lp.senses
+    return np.where(s == ord("G"), ax >= lp.b - tol,
+                    np.where(s == ord("L"), ax <= lp.b + tol, np.abs(ax - lp.b) <= tol))
+
+
+# ------------------------------------------- P10 integral and within bounds
+@pytest.mark.parametrize("seed", range(6))
+def test_fp_output_integral_and_in_bounds(seed):
+    rng = np.random.default_rng(seed)
+    lp = I.cover_knapsack(300, seed=seed)
+    xbar = rng.random(lp.n)
+    xhat, feas, ign = oracle.fix_propagate(lp, xbar)
+    assert PAPER["fp_output_integer_feasible"]["value"]
+    assert np.all(xhat == np.round(xhat))
+    assert np.all(xhat >= lp.l) and np.all(xhat <= lp.u)
+    assert feas == bool(_row_ok(lp, xhat, 1e-6 * (1 + np.abs(lp.b))).all())
+
+
+def test_fp_mixed_integer_continuous_projection():
+    """Continuous variables keep the reference value projected on their
+    (possibly tightened) domain; integers are integral."""
+    rng = np.random.default_rng(4)
+    lp = I.tiny_lp(rng, 4, 8)
+    lp.is_int = (rng.random(lp.n) < 0.5).astype(np.uint8)
+    xbar = lp.l + rng.random(lp.n) * (lp.u - lp.l)
+    xhat, _, _ = oracle.fix_propagate(lp, xbar)
+    ii = lp.is_int.astype(bool)
+    assert np.all(xhat[ii] == np.round(xhat[ii]))
+    assert np.all(xhat >= lp.l - 1e-12) and np.all(xhat <= lp.u + 1e-12)
+
+
+# ------------------------------------------ P11 identity on feasible input
+def test_fp_identity_on_feasible_integral_point():
+    lp = I.workload(1)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        # random minimal-ish cover: start from all ones, drop columns greedily
+        x = np.ones(lp.n)
+        A = dense(lp)
+        for j in rng.permutation(lp.n):
+            x[j] = 0
+            if np.any(A @ x < 1):
+                x[j] = 1
+        xhat, feas, ign = oracle.fix_propagate(lp, x)
+        np.testing.assert_array_equal(xhat, x)
+        assert feas and ign == 0
+
+
+# --------------------------------------------- P12 set cover always feasible
+@pytest.mark.parametrize("seed", range(8))
+def test_fp_always_succeeds_on_set_cover(seed):
+    lp = I.set_cover(200, 500, seed=seed + 10)
+    rng = np.random.default_rng(seed)
+    xbar = rng.random(lp.n) * rng.random(lp.n)  # mostly small values
+    xhat, feas, ign = oracle.fix_propagate(lp, xbar)
+    assert feas and ign == 0
+    assert np.all(dense(lp) @ xhat >= 1)
+
+
+# ---------------------------------- P13 propagation soundness by brute force
+@pytest.mark.parametrize("seed", range(10))
+def test_fp_never_cuts_off_a_feasible_point(seed):
+    """For every feasible binary point x' of a small cover/knapsack problem,
+    a reference that rounds to x' must come back as x' exactly: a fixing
+    sequence consistent with x' can only leave x' if propagation removed a
+    feasible point (unsound) or ignored a row that x' satisfies."""
+    rng = np.random.default_rng(seed)
+    n = 10
+    m = 6
+    A = np.zeros((m, n))
+    senses = []
+    b = []
+    for i in range(m):
+        cols = rng.choice(n, size=int(rng.integers(2, 6)), replace=False)
+        if rng.random() < 0.5:
+            A[i, cols] = 1
+            senses.append("G")
+            b.append(1.0)
+        else:
+            w = rng.integers(1, 20, size=cols.size)
+            A[i, cols] = w
+            senses.append("L")
+            b.append(float(np.floor(0.5 * w.sum())))
+    lp = lp_from_dense(A, b, "".join(senses), rng.integers(1, 10, size=n), np.zeros(n), np.ones(n),
+                       is_int=np.ones(n))
+    feasible = []
+    for bits in itertools.product([0.0, 1.0], repeat=n):
+        x = np.array(bits)
+        if _row_ok(lp, x).all():
+            feasible.append(x)
+    assert feasible
+    for x in feasible[:: max(1, len(feasible) // 40)]:
+        noise = rng.uniform(-0.45, 0.45, size=n)
+        xbar = np.clip(x + noise, 0, 1)
+        xhat, feas, ign = oracle.fix_propagate(lp, xbar)
+        np.testing.assert_array_equal(xhat, x)
+        assert feas and ign == 0
+
+
+def test_fp_ignores_conflicting_rows_and_still_returns_integral():
+    # x0 + x1 >= 2 forces both to 1; 3 x0 + 3 x1 <= 4 then conflicts
+    A = np.array([[1.0, 1.0], [3.0, 3.0]])
+    lp = lp_from_dense(A, [2.0, 4.0], "GL", [1.0, 1.0], [0, 0], [1, 1], is_int=[1, 1])
+    xhat, feas, ign = oracle.fix_propagate(lp, np.array([0.9, 0.8]))
+    assert np.all(xhat == np.round(xhat)) and not feas and ign >= 1
+
+
+# ------------------------------------------------ P9 objective update / eps
+def test_eps_schedule_closed_form():
+    e1 = PAPER["eps_initial"]["value"]
+    beta = PAPER["eps_beta"]["value"]
+    floor = PAPER["eps_floor"]["value"]
+    assert oracle.eps_schedule(1) == e1
+    for K in (2, 3, 10, 100, 500, 684, 685, 686, 1000):
+        closed = max(e1 * beta ** (K - 1), floor)
+        assert abs(oracle.eps_schedule(K) - closed) <= 1e-12 * closed
+    # first floored round: 0.01 * 0.98^(K-1) < 1e-8  <=>  K - 1 > ln(1e-6) / ln(0.98)
+    kstar = int(np.floor(np.log(1e-6) / np.log(0.98))) + 2
+    assert oracle.eps_schedule(kstar) == floor and oracle.eps_schedule(kstar - 1) > floor
+
+
+@pytest.mark.parametrize("K", [1, 2, 5, 20])
+def test_objective_update_identities(K):
+    alpha = PAPER["alpha"]["value"]
+    lp = I.cover_knapsack(500, seed=K)
+    rng = np.random.default_rng(K)
+    xhat = (rng.random(lp.n) < 0.3).astype(float)
+    c_hat = oracle.objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K)
+    nI = int(lp.is_int.sum())
+    g = c_hat - alpha ** K * np.sqrt(nI) / np.linalg.norm(lp.c) * lp.c
+    g /= (1 - alpha ** K)
+    # the distance part is the +-1 subgradient of the L1 distance
+    np.testing.assert_allclose(g, np.where(xhat == 0, 1.0, -1.0), atol=1e-9)
+    # the objective part has norm alpha^K sqrt(|I|)
+    part = c_hat - (1 - alpha ** K) * np.where(xhat == 0, 1.0, -1.0)
+    assert abs(np.linalg.norm(part) - alpha ** K * np.sqrt(nI)) < 1e-9 * np.sqrt(nI)
+    assert abs(np.linalg.norm(np.where(xhat == 0, 1.0, -1.0)) - np.sqrt(nI)) < 1e-9
+    # Delta(x, x_hat) = g^T x + sum x_hat on [0,1]^n (L1 distance)
+    for _ in range(5):
+        x = rng.random(lp.n)
+        gg = oracle.distance_gradient(xhat, lp.l, lp.u, lp.is_int)
+        assert abs(np.abs(x - xhat).sum() - (gg @ x + xhat.sum())) < 1e-9
+
+
+def test_objective_update_zero_c_drops_term_and_rejects_general_integers():
+    n = 4
+    z = oracle.objective_update(np.zeros(n), np.array([0.0, 1, 0, 1]), np.zeros(n), np.ones(n),
+                                np.ones(n, dtype=np.uint8), 1)
+    np.testing.assert_allclose(z, 0.1 * np.array([1.0, -1, 1, -1]))
+    with pytest.raises(ValueError):
+        oracle.distance_gradient(np.array([1.0]), np.zeros(1), np.array([3.0]), np.ones(1, np.uint8))
+
+
+# ------------------------------------------------------------ pump (P14)
+def test_pump_invariants_small():
+    """Parity unpinned (round of first success depends on open rounding
+    choices); check invariants only: every rounding is integral and in
+    bounds, the set-cover instance is always rounded to a feasible point."""
+    lp = I.workload(1)
+    recs = oracle.pump(lp, rounds=3, tol=1e-4, iter_limit=20_000)
+    assert len(recs) == 3
+    for r in recs:
+        assert np.all(r["xhat"] == np.round(r["xhat"]))
+        assert r["xhat_feasible"]

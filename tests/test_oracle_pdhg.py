@@ -1,0 +1,272 @@
+"""Pins of the FP64 oracle's PDHG, preconditioner and KKT evaluator against
+mathematics that does not come from the oracle itself: brute-force vertex
+enumeration, HiGHS, closed-form optima, an independent KKT evaluator, the
+projection invariants, an exact primal-dual fixed point, nonexpansiveness
+of the PDHG map in its metric, and the Ruiz / Pock-Chambolle properties."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03466_amd import instances as I
+from lp_util import (brute_force_lp, dense, highs, kkt_numpy, load_wyndor, lp_from_dense)
+
+
+# ----------------------------------------------------------- P1 brute force
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_vertices(seed):
+    rng = np.random.default_rng(1000 + seed)
+    m = int(rng.integers(1, 5))
+    n = int(rng.integers(2, 6))
+    lp = I.tiny_lp(rng, m, n)
+    p_star, _ = brute_force_lp(lp)
+    assert np.isfinite(p_star)
+    r = oracle.pdhg(lp, tol=1e-9, iter_limit=2_000_000)
+    assert r.status == oracle.OPTIMAL
+    assert abs(r.pobj - p_star) <= 1e-6 * (1 + abs(p_star))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_highs_objective_mixed_bound_types(seed):
+    """Variables with only a lower, only an upper, or no bound (exercises the
+    sign cone of the reduced cost in the KKT test and the infinite clamps)."""
+    rng = np.random.default_rng(500 + seed)
+    lp = I.tiny_lp(rng, 5, 9, bounded=False)
+    ref = highs(lp).fun
+    r = oracle.pdhg(lp, tol=1e-9, iter_limit=3_000_000)
+    assert r.status == oracle.OPTIMAL
+    assert abs(r.pobj - ref) <= 1e-6 * (1 + abs(ref))
+    assert abs(r.dobj - ref) <= 1e-6 * (1 + abs(ref))
+
+
+def test_textbook_lp_golden():
+    """Wyndor LP: closed-form optimum x = (2, 6), value -36 (as a min), duals
+    (0, -3/2, -1) in the <= -row sign convention."""
+    lp, d = load_wyndor()
+    r = oracle.pdhg(lp, tol=1e-10, iter_limit=2_000_000)
+    assert r.status == oracle.OPTIMAL
+    np.testing.assert_allclose(r.x, d["x_opt"], atol=1e-7)
+    np.testing.assert_allclose(r.y, d["y_opt"], atol=1e-7)
+    assert abs(r.pobj - d["obj_opt"]) < 1e-7
+
+
+# --------------------------------------------------------------- P2 HiGHS
+@pytest.mark.parametrize("k,scale", [(1, 1.0), (2, 0.001), (3, 0.001), (4, 0.004), (5, 0.01)])
+def test_highs_objective(k, scale):
+    w = I.workload(k, scale=scale)
+    lp = w[0] if isinstance(w, list) else w
+    ref = highs(lp).fun
+    r = oracle.pdhg(lp, tol=1e-7, iter_limit=3_000_000)
+    assert r.status == oracle.OPTIMAL
+    assert abs(r.pobj - ref) <= 1e-5 * (1 + abs(ref))
+    kk = kkt_numpy(lp, r.x, r.y)
+    assert kk["rel"] <= 1e-7 * 1.0001
+
+
+# --------------------------------------------------- P3 independent KKT
+@pytest.mark.parametrize("seed", range(4))
+def test_kkt_matches_independent_evaluator(seed):
+    rng = np.random.default_rng(seed)
+    lp = I.tiny_lp(rng, 6, 9, bounded=False)
+    x = np.clip(rng.normal(size=lp.n), lp.l, lp.u)
+    y = rng.normal(size=lp.m)
+    y = np.where(lp.senses == ord("G"), np.abs(y), np.where(lp.senses == ord("L"), -np.abs(y), y))
+    a = oracle.kkt(lp, x, y)
+    b = kkt_numpy(lp, x, y)
+    for key in ("rel", "rho_p", "rho_d", "rho_g", "pobj", "dobj"):
+        assert abs(a[key] - b[key]) <= 1e-12 * (1 + abs(b[key])), key
+
+
+def test_weak_duality_when_dual_feasible():
+    """With r_d = 0 the dual objective is a lower bound on the optimum."""
+    lp = I.workload(1)
+    p_star = highs(lp).fun
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        y = rng.random(lp.m) * 3.0
+        k = oracle.kkt(lp, np.zeros(lp.n), y)
+        assert k["rho_d"] == 0.0  # all bounds finite: lambda = g
+        assert k["dobj"] <= p_star + 1e-9
+
+
+# ------------------------------------------------------- P4 invariants
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 64, 65, 130, 400])
+def test_iterates_stay_in_bounds_and_cones(k):
+    lp = I.workload(3, scale=0.0005)
+    r = oracle.pdhg(lp, tol=-1.0, iter_limit=k, restarts=True)
+    assert r.iterations == k
+    assert np.all(r.x >= lp.l) and np.all(r.x <= lp.u)
+    s = lp.senses
+    assert np.all(r.y[s == ord("G")] >= 0.0)
+    assert np.all(r.y[s == ord("L")] <= 0.0)
+
+
+def test_iteration_limit_zero_returns_projected_start():
+    lp = I.workload(2, scale=0.0005)
+    rng = np.random.default_rng(3)
+    x0 = rng.normal(size=lp.n) * 20
+    y0 = rng.normal(size=lp.m)
+    r = oracle.pdhg(lp, tol=-1.0, iter_limit=0, x0=x0, y0=y0)
+    assert r.status == oracle.ITERATION_LIMIT and r.iterations == 0
+    np.testing.assert_array_equal(r.x, np.clip(x0, lp.l, lp.u))
+    yp = np.where(lp.senses == ord("G"), np.maximum(y0, 0), y0)
+    np.testing.assert_array_equal(r.y, yp)
+    assert abs(r.rel_kkt - kkt_numpy(lp, r.x, r.y)["rel"]) < 1e-12
+
+
+# ------------------------------------------------------- P5 closed forms
+def test_closed_form_empty_rows():
+    rng = np.random.default_rng(11)
+    n = 7
+    c = rng.normal(size=n)
+    l = -rng.random(n)
+    u = rng.random(n) + 0.5
+    lp = lp_from_dense(np.zeros((3, n)), [-1.0, -2.0, -0.5], "GGG", c, l, u)
+    r = oracle.pdhg(lp, tol=1e-10, iter_limit=100_000)
+    assert r.status == oracle.OPTIMAL
+    np.testing.assert_allclose(r.x, np.where(c > 0, l, u), atol=1e-8)
+
+
+def test_closed_form_continuous_knapsack():
+    """max v^T x s.t. w^T x <= W, 0 <= x <= 1: greedy by v/w (Dantzig)."""
+    rng = np.random.default_rng(12)
+    n = 9
+    v = rng.integers(1, 50, size=n).astype(float)
+    w = rng.integers(1, 30, size=n).astype(float)
+    W = 0.4 * w.sum()
+    order = np.argsort(-v / w)
+    x = np.zeros(n)
+    cap = W
+    for j in order:
+        take = min(1.0, cap / w[j])
+        x[j] = take
+        cap -= take * w[j]
+        if cap <= 0:
+            break
+    lp = lp_from_dense(w[None, :], [W], "L", -v, np.zeros(n), np.ones(n))
+    r = oracle.pdhg(lp, tol=1e-10, iter_limit=1_000_000)
+    assert r.status == oracle.OPTIMAL
+    np.testing.assert_allclose(r.x, x, atol=1e-6)
+    assert abs(r.pobj + v @ x) < 1e-6 * (1 + v @ x)
+
+
+def test_closed_form_single_cover_row():
+    c = np.array([5.0, 3.0, 8.0, 4.0, 9.0])
+    lp = lp_from_dense(np.ones((1, 5)), [1.0], "G", c, np.zeros(5), np.ones(5))
+    r = oracle.pdhg(lp, tol=1e-10, iter_limit=1_000_000)
+    e = np.zeros(5)
+    e[np.argmin(c)] = 1.0
+    np.testing.assert_allclose(r.x, e, atol=1e-7)
+
+
+def test_closed_form_identity_equalities():
+    rng = np.random.default_rng(13)
+    n = 6
+    b = rng.random(n) * 2 - 1
+    lp = lp_from_dense(np.eye(n), b, "E" * n, rng.normal(size=n), -2 * np.ones(n), 2 * np.ones(n))
+    r = oracle.pdhg(lp, tol=1e-11, iter_limit=1_000_000)
+    np.testing.assert_allclose(r.x, b, atol=1e-9)
+
+
+# -------------------------------------------------- P6 preconditioner
+@pytest.mark.parametrize("k,scale", [(1, 1.0), (2, 0.0005), (3, 0.0005), (4, 0.002)])
+def test_pock_chambolle_spectral_norm_at_most_one(k, scale):
+    w = I.workload(k, scale=scale)
+    lp = w[0] if isinstance(w, list) else w
+    dr, dc = oracle.precondition(lp)
+    At = dr[:, None] * dense(lp) * dc[None, :]
+    assert np.linalg.norm(At, 2) <= 1.0 + 1e-12
+
+
+def test_ruiz_equilibrates_infinity_norms():
+    """Ruiz alone drives every nonzero row and column infinity norm of
+    D_r A D_c to 1 (its fixed point); 10 rounds get within 1e-2 here."""
+    lp = I.workload(2, scale=0.0005)
+    dr, dc = oracle.precondition(lp, ruiz_iters=10, pock_chambolle=False)
+    At = np.abs(dr[:, None] * dense(lp) * dc[None, :])
+    rmax = At.max(axis=1)
+    cmax = At.max(axis=0)
+    rmax, cmax = rmax[rmax > 0], cmax[cmax > 0]
+    assert np.all(np.abs(rmax - 1) < 1e-2) and np.all(np.abs(cmax - 1) < 1e-2)
+    dr0, dc0 = oracle.precondition(lp, ruiz_iters=0, pock_chambolle=False)
+    assert np.all(dr0 == 1.0) and np.all(dc0 == 1.0)
+
+
+# ------------------------------------------------ P7 exact fixed point
+def _constructed_optimum(rng, m=6, n=10):
+    """LP with a known optimal pair built from complementary slackness."""
+    A = rng.integers(-4, 5, size=(m, n)).astype(float)
+    l = -rng.integers(0, 3, size=n).astype(float)
+    u = l + rng.integers(1, 4, size=n)
+    where = rng.integers(0, 3, size=n)  # 0 at l, 1 at u, 2 interior
+    x = np.where(where == 0, l, np.where(where == 1, u, (l + u) / 2))
+    senses = rng.choice(np.frombuffer(b"GLE", dtype=np.uint8), size=m)
+    active = rng.random(m) < 0.6
+    active |= senses == ord("E")
+    y = rng.integers(1, 4, size=m).astype(float)
+    y = np.where(senses == ord("L"), -y, y)
+    y = np.where(active, y, 0.0)
+    ax = A @ x
+    slack = rng.integers(1, 3, size=m).astype(float)
+    b = np.where(active, ax, np.where(senses == ord("G"), ax - slack, ax + slack))
+    lam = np.where(where == 0, rng.integers(1, 4, size=n), np.where(where == 1, -rng.integers(1, 4, size=n), 0)).astype(float)
+    c = A.T @ y + lam
+    return lp_from_dense(A, b, senses, c, l, u), x, y
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_exact_optimum_is_a_fixed_point(seed):
+    rng = np.random.default_rng(77 + seed)
+    lp, xs, ys = _constructed_optimum(rng)
+    assert kkt_numpy(lp, xs, ys)["rel"] < 1e-14
+    for k in (1, 50):
+        r = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=xs, y0=ys, restarts=False)
+        assert np.max(np.abs(r.x - xs)) <= 1e-12
+        assert np.max(np.abs(r.y - ys)) <= 1e-12
+
+
+# ---------------------------------------------- P8 nonexpansiveness
+def test_pdhg_map_nonexpansive_in_its_metric():
+    """Chambolle-Pock: with K = -A~ (coupling -y^T A~ x) the iteration is
+    nonexpansive in ||z||_M^2 = |x|^2/t + |y|^2/s + 2 y^T A~ x (t s ||A~||^2 < 1),
+    evaluated in the preconditioned variables x / d_c, y / d_r."""
+    lp = I.workload(2, scale=0.0003)
+    dr, dc = oracle.precondition(lp)
+    At = dr[:, None] * dense(lp) * dc[None, :]
+    omega, eta = 1.7, 0.99
+    t, s = eta / omega, eta * omega
+    rng = np.random.default_rng(2)
+    x0a, x0b = rng.normal(size=lp.n) * 3, rng.normal(size=lp.n) * 3
+    y0a, y0b = rng.normal(size=lp.m), rng.normal(size=lp.m)
+
+    def mnorm(dx, dy):
+        xs, ys = dx / dc, dy / dr
+        return np.sqrt(xs @ xs / t + ys @ ys / s + 2 * ys @ (At @ xs))
+
+    prev = None
+    for k in range(0, 40):
+        ra = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=x0a, y0=y0a, omega0=omega, restarts=False, eta=eta)
+        rb = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=x0b, y0=y0b, omega0=omega, restarts=False, eta=eta)
+        d = mnorm(ra.x - rb.x, ra.y - rb.y)
+        if prev is not None:
+            assert d <= prev * (1 + 1e-12) + 1e-12
+        prev = d
+
+
+# ---------------------------------------------------- determinism / status
+def test_restart_counter_and_status_fields():
+    lp = I.workload(1)
+    r = oracle.pdhg(lp, tol=1e-4, iter_limit=100_000)
+    assert r.status == oracle.OPTIMAL and r.restarts > 0
+    assert r.iterations % 64 == 0
+    kk = kkt_numpy(lp, r.x, r.y)
+    assert abs(kk["rel"] - r.rel_kkt) < 1e-12 and r.rel_kkt <= 1e-4
+    r2 = oracle.pdhg(lp, tol=1e-4, iter_limit=100)
+    assert r2.status == oracle.ITERATION_LIMIT and r2.iterations == 100
+
+
+def test_nan_objective_is_numerical_error():
+    lp = I.workload(1)
+    c = lp.c.copy()
+    c[3] = np.nan
+    r = oracle.pdhg(lp, tol=1e-4, iter_limit=1000, c=c)
+    assert r.status == oracle.NUMERICAL_ERROR

@@ -1,0 +1,209 @@
+/*
+ * scylla_pdhg.h - C ABI of the MI355X (gfx950) PDHG library.
+ *
+ * The library solves LP relaxations
+ *     min c^T x   subject to   A x (>=, <= or =) b,   l <= x <= u
+ * with the Primal-Dual Hybrid Gradient method used as the inner loop of the
+ * Scylla heuristic (Mexi et al., arXiv 2307.03466, Algorithm 1 and
+ * Section 2.1), stopped by a relative KKT test (Section 2.2), and re-solves
+ * such LPs warm-started from the previous primal-dual pair with only the
+ * objective changed (Section 2.1, warm start; Algorithm 1, objective update).
+ *
+ * Conventions for every entry point:
+ *   - All pointers in the problem description are HOST pointers and are
+ *     only read during the call; the library keeps no pointer after it
+ *     returns.  Handles own their device copies.
+ *   - Return value: 0 on success (the solve status is reported separately in
+ *     scylla_result.status), a negative errno-style code on failure:
+ *       -EINVAL (-22) invalid argument (nothing is written to outputs),
+ *       -ENOMEM (-12) host or device allocation failed,
+ *       -EIO    (-5)  a HIP runtime call failed,
+ *       -ENODEV (-19) no usable gfx950 device.
+ *     scylla_last_error() returns a thread-local message for the last error.
+ *   - No C++ exception crosses this boundary.
+ *   - A handle (scylla_batch) must be used by one host thread at a time; its
+ *     work is ordered on the HIP stream given at creation.
+ *   - Limits: total rows, columns and nonzeros of a handle each < 2^31 - 1.
+ */
+#ifndef SCYLLA_PDHG_H
+#define SCYLLA_PDHG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Constraint matrix in CSR form.  row_ptr[0] = 0, row_ptr[m] = nnz,
+ * nondecreasing; col_idx strictly increasing within each row and in [0, n);
+ * val finite (explicit zeros allowed). */
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;
+    const int64_t *row_ptr; /* [m + 1] */
+    const int32_t *col_idx; /* [nnz]   */
+    const double *val;      /* [nnz]   */
+} scylla_csr;
+
+/* One LP: A plus objective c[n], right-hand side b[m], senses[m] in
+ * {'G' (>=), 'L' (<=), 'E' (=)}, bounds l[n], u[n] (-inf / +inf allowed;
+ * l <= u, l != +inf, u != -inf).  c and b must be finite. */
+typedef struct {
+    scylla_csr A;
+    const double *c;
+    const double *b;
+    const char *senses;
+    const double *l;
+    const double *u;
+} scylla_lp;
+
+enum { SCYLLA_SENSE_GE = 'G', SCYLLA_SENSE_LE = 'L', SCYLLA_SENSE_EQ = 'E' };
+
+/* Arithmetic / storage precision of the device path.
+ * SCYLLA_FP64: values, iterates and accumulation in FP64.
+ * SCYLLA_FP32: iterates and accumulation in FP32; the matrix is stored
+ *   exactly (small integers packed into the index word, else BF16 when every
+ *   value is BF16-exact, else FP32); residual and gap norms, the
+ *   termination test and the restart decision stay in FP64. */
+enum { SCYLLA_FP64 = 0, SCYLLA_FP32 = 1 };
+
+/* Solve parameters; scylla_params_default() fills the defaults noted. */
+typedef struct {
+    double tol;           /* relative KKT tolerance, > 0 (1e-4)            */
+    int64_t iter_limit;   /* >= 0 iterations per call (100000); 0 = only
+                             evaluate the (projected) start point          */
+    int32_t precision;    /* SCYLLA_FP64 | SCYLLA_FP32 (SCYLLA_FP32)       */
+    int32_t check_period; /* R: iterations between KKT checks, 1..1024 (64) */
+    int32_t restarts;     /* 1 = restart scheme on (default), 0 = off      */
+    int32_t autotune;     /* 1 = time the tile-size candidates once per
+                             handle and keep the fastest (default 1)       */
+    double eta;           /* step-size factor in (0, 1) (0.99)             */
+    double time_limit_s;  /* <= 0: none (0)                                */
+} scylla_params;
+
+enum {
+    SCYLLA_RUNNING = 0,
+    SCYLLA_OPTIMAL = 1,          /* relative KKT <= tol                     */
+    SCYLLA_ITERATION_LIMIT = 2,  /* iter_limit reached                      */
+    SCYLLA_TIME_LIMIT = 3,       /* time_limit_s reached                    */
+    SCYLLA_NUMERICAL_ERROR = 4   /* a residual or gap norm is not finite    */
+};
+
+/* Result of one LP solve.  rel_kkt = max(rho_primal, rho_dual, rho_gap):
+ *   rho_primal = ||primal residual||_2 / (1 + ||b||_2)
+ *   rho_dual   = ||c - A^T y - lambda||_2 / (1 + ||c||_2)
+ *   rho_gap    = |P - D| / (1 + |P| + |D|)
+ * evaluated in FP64 on the original (unscaled) problem at the returned
+ * iterate.  primal_obj = c^T x, dual_obj = b^T y + bound terms. */
+typedef struct {
+    int32_t status;
+    int32_t restarts;
+    int64_t iterations;
+    double rel_kkt, rho_primal, rho_dual, rho_gap;
+    double primal_obj, dual_obj;
+    double omega;          /* final primal weight                           */
+    double solve_seconds;  /* wall time of the iteration loop               */
+    double setup_seconds;  /* handle creation (upload + preconditioning)    */
+} scylla_result;
+
+/* Fills *p with the defaults listed in scylla_params.  Returns 0, or
+ * -EINVAL if p is NULL. */
+int scylla_params_default(scylla_params *p);
+
+/* Thread-local message describing the last failed call ("" if none).  The
+ * string stays valid until the next library call on the same thread. */
+const char *scylla_last_error(void);
+
+/* Checks an LP description without touching the GPU (Algorithm 1 input form
+ * with senses G/L/E).  Returns 0 or -EINVAL (message in scylla_last_error). */
+int scylla_validate_lp(const scylla_lp *lp);
+
+/* One-shot solve (Algorithm 1 inner loop): creates a device copy of the LP,
+ * runs PDHG from the projection of (x0, y0) onto the bounds and the dual
+ * sign cone (x0 / y0 may be NULL: 0 is used), and writes the last iterate to
+ * x_out[n], y_out[m] (host) for every status.  On a negative return nothing
+ * is written.  res may not be NULL. */
+int scylla_pdhg_solve(const scylla_csr *A, const double *c, const double *b, const char *senses,
+                      const double *l, const double *u, const scylla_params *p,
+                      const double *x0, const double *y0, double *x_out, double *y_out,
+                      scylla_result *res);
+
+/* ------------------------------------------------------------ handles
+ * A batch holds `count` independent LPs resident on the device (the problem
+ * data, preconditioner and warm state (x, y, omega) per instance).  All
+ * instances are iterated together in one sequence of launches; finished
+ * instances stop updating while the others continue.  count = 1 is the
+ * single-LP handle used for objective-only re-solves. */
+typedef struct scylla_batch scylla_batch;
+
+/* Uploads and preconditions `count` LPs (precision fixed for the handle).
+ * hip_stream: a hipStream_t cast to void* on which all work of the handle is
+ * ordered, or NULL to let the library create one. */
+int scylla_batch_create(const scylla_lp *lps, int32_t count, int32_t precision, void *hip_stream,
+                        scylla_batch **out);
+void scylla_batch_destroy(scylla_batch *h);
+
+/* Replaces the objective of instance `inst` by c_hat[n_inst] (host, finite).
+ * The original objective passed at creation is kept for blending. */
+int scylla_batch_set_objective(scylla_batch *h, int32_t inst, const double *c_hat);
+
+/* Pump objective update on the device (Algorithm 1, objective update):
+ *   c_hat_j = a * kappa * c_j + (1 - a) * g_j
+ * with c the objective given at creation, g_j = +1 if bit j of xhat_bits is 0
+ * (rounded value at its lower bound), -1 if it is 1 (at its upper bound), and
+ * g_j = 0 where bit j of int_bits is 0 (continuous variable).  Bits are
+ * little-endian within each byte; each array holds ceil(n_inst / 8) bytes
+ * (host).  int_bits may be NULL (all integer).  Typically a = 0.9^K and
+ * kappa = sqrt(|I|) / ||c||_2. */
+int scylla_batch_set_blend(scylla_batch *h, int32_t inst, const uint8_t *xhat_bits,
+                           const uint8_t *int_bits, double a, double kappa);
+
+/* Sets the start point of instance `inst` from host x0[n_inst] / y0[m_inst]
+ * (either may be NULL: keep the current one); it is projected on entry.
+ * omega0 > 0 also sets the primal weight. */
+int scylla_batch_set_start(scylla_batch *h, int32_t inst, const double *x0, const double *y0,
+                           double omega0);
+
+/* Runs PDHG on every instance of the batch.  warm = 0: every instance starts
+ * from 0 (projected) with the primal weight from its data; warm = 1: every
+ * instance continues from its current (x, y, omega) (the last solve's, or
+ * what scylla_batch_set_start installed).  results[count] receives one
+ * record per instance. */
+int scylla_batch_solve(scylla_batch *h, const scylla_params *p, int32_t warm,
+                       scylla_result *results);
+
+/* Copies instance `inst`'s current iterate to host x[n_inst] / y[m_inst] as
+ * FP64 (either may be NULL). */
+int scylla_batch_get_solution(scylla_batch *h, int32_t inst, double *x, double *y);
+
+/* Copies the concatenated primal iterate of all instances (sum of n_inst
+ * values, instance order) to host memory as FP64 in one transfer. */
+int scylla_batch_get_x_all(scylla_batch *h, double *x_all);
+
+/* Device buffers of the current iterates (for zero-copy consumers).  *x and
+ * *y receive device pointers to the concatenated primal / dual iterates,
+ * *elem_bytes 4 (FP32 handle) or 8 (FP64 handle).  The pointers stay valid
+ * until the handle is destroyed. */
+int scylla_batch_device_iterates(scylla_batch *h, void **x, void **y, int32_t *elem_bytes);
+
+/* Shape of the handle: total rows, columns, nonzeros, instance count and the
+ * matrix storage format chosen (0 packed integers, 1 BF16, 2 FP32, 3 FP64). */
+typedef struct {
+    int32_t count, precision, format, reserved;
+    int64_t m_total, n_total, nnz_total;
+    int32_t row_chunk, col_chunk; /* tile sizes in use (nonzeros per tile) */
+    int32_t long_rows, long_cols; /* rows / columns split over several tiles */
+} scylla_batch_info;
+int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
+
+/* Profiling aid: launches the column pass (primal step) and the row pass
+ * (dual step) of the handle `reps` times each on the handle's stream, with
+ * the solve's tiles, launch shape and inputs but scratch outputs (the
+ * iterates are not changed), and returns the average duration of one launch
+ * of each in milliseconds, measured with HIP events.  reps >= 1. */
+int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, double *ms_col);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCYLLA_PDHG_H */

@@ -1,0 +1,222 @@
+// Host-side preparation of a batch of LPs: input validation, concatenation
+// into one block-diagonal matrix, the explicit transposed copy used by the
+// column pass (so A^T y needs no atomics), exact compact value formats, and
+// the tile plans both passes launch over.  Plain C++, no GPU calls.
+#include <errno.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "scylla_internal.h"
+
+namespace scy {
+
+static int fail(std::string &err, const char *fmt, long long a = 0, long long b = 0)
+{
+    char buf[256];
+    snprintf(buf, sizeof(buf), fmt, a, b);
+    err = buf;
+    return -EINVAL;
+}
+
+int validate_lp(const scylla_lp *lp, std::string &err)
+{
+    if (!lp) return fail(err, "lp is NULL");
+    const scylla_csr &A = lp->A;
+    if (A.m < 0 || A.n < 1) return fail(err, "need m >= 0 and n >= 1 (m=%lld, n=%lld)", A.m, A.n);
+    if (A.nnz < 0 || A.nnz >= 0x7fffffffLL) return fail(err, "nnz out of range (%lld)", A.nnz);
+    if (!A.row_ptr) return fail(err, "row_ptr is NULL");
+    if (A.nnz > 0 && (!A.col_idx || !A.val)) return fail(err, "col_idx/val is NULL");
+    if (!lp->c || !lp->l || !lp->u) return fail(err, "c, l or u is NULL");
+    if (A.m > 0 && (!lp->b || !lp->senses)) return fail(err, "b or senses is NULL");
+    if (A.row_ptr[0] != 0) return fail(err, "row_ptr[0] = %lld, expected 0", A.row_ptr[0]);
+    if (A.row_ptr[A.m] != A.nnz)
+        return fail(err, "row_ptr[m] = %lld differs from nnz = %lld", A.row_ptr[A.m], A.nnz);
+    for (int32_t i = 0; i < A.m; ++i) {
+        int64_t a = A.row_ptr[i], b = A.row_ptr[i + 1];
+        if (b < a) return fail(err, "row_ptr decreases at row %lld", i);
+        int32_t prev = -1;
+        for (int64_t e = a; e < b; ++e) {
+            int32_t j = A.col_idx[e];
+            if (j < 0 || j >= A.n) return fail(err, "col_idx out of range at nonzero %lld (%lld)", e, j);
+            if (j <= prev) return fail(err, "col_idx not strictly increasing in row %lld", i);
+            prev = j;
+            if (!isfinite(A.val[e])) return fail(err, "non-finite matrix value at nonzero %lld", e);
+        }
+        char s = lp->senses[i];
+        if (s != 'G' && s != 'L' && s != 'E') return fail(err, "bad sense %lld at row %lld", (unsigned char)s, i);
+        if (!isfinite(lp->b[i])) return fail(err, "non-finite b at row %lld", i);
+    }
+    for (int32_t j = 0; j < A.n; ++j) {
+        double l = lp->l[j], u = lp->u[j];
+        if (isnan(l) || isnan(u)) return fail(err, "NaN bound at column %lld", j);
+        if (l > u) return fail(err, "l > u at column %lld", j);
+        if (l == INFINITY || u == -INFINITY) return fail(err, "infeasible infinite bound at column %lld", j);
+        if (!isfinite(lp->c[j])) return fail(err, "non-finite objective at column %lld", j);
+    }
+    return 0;
+}
+
+uint16_t f64_to_bf16_exact(double v, bool &exact)
+{
+    float f = (float)v;
+    uint32_t w;
+    memcpy(&w, &f, 4);
+    exact = ((double)f == v) && ((w & 0xffffu) == 0u);
+    return (uint16_t)(w >> 16);
+}
+
+static int32_t bits_for(int64_t maxval)
+{
+    int32_t b = 1;
+    while (b < 31 && ((int64_t)1 << b) <= maxval) ++b;
+    return b;
+}
+
+int build_orientations(const scylla_lp *lps, int32_t count, int32_t precision, HostOrient &csr,
+                       HostOrient &csc, int32_t &fmt, std::vector<int32_t> &row_off,
+                       std::vector<int32_t> &col_off, std::string &err)
+{
+    int64_t M = 0, N = 0, NNZ = 0;
+    row_off.assign(count + 1, 0);
+    col_off.assign(count + 1, 0);
+    for (int32_t q = 0; q < count; ++q) {
+        row_off[q] = (int32_t)M;
+        col_off[q] = (int32_t)N;
+        M += lps[q].A.m;
+        N += lps[q].A.n;
+        NNZ += lps[q].A.nnz;
+        if (M >= 0x7fffffffLL || N >= 0x7fffffffLL || NNZ >= 0x7fffffffLL)
+            return fail(err, "batch too large: totals must stay below 2^31 - 1");
+    }
+    row_off[count] = (int32_t)M;
+    col_off[count] = (int32_t)N;
+
+    // storage format: FP64 path stores FP64; FP32 path picks the most compact
+    // exact format for every value of the batch
+    const int32_t sh_r = bits_for(N > 1 ? N - 1 : 1);  // CSR words hold column ids
+    const int32_t sh_c = bits_for(M > 1 ? M - 1 : 1);  // CSC words hold row ids
+    if (precision == SCYLLA_FP64) {
+        fmt = FMT_F64;
+    } else {
+        const int32_t sh = std::max(sh_r, sh_c);
+        const int64_t vmax = ((int64_t)1 << (31 - sh)) - 1, vmin = -((int64_t)1 << (31 - sh));
+        bool packed = sh <= 30, bf16 = true;
+        for (int32_t q = 0; q < count && (packed || bf16); ++q) {
+            const scylla_csr &A = lps[q].A;
+            for (int64_t e = 0; e < A.nnz; ++e) {
+                double v = A.val[e];
+                if (packed && !(v == floor(v) && v >= (double)vmin && v <= (double)vmax)) packed = false;
+                bool ex;
+                f64_to_bf16_exact(v, ex);
+                if (!ex) bf16 = false;
+                if (!packed && !bf16) break;
+            }
+        }
+        fmt = packed ? FMT_PACKED : (bf16 ? FMT_BF16 : FMT_F32);
+    }
+
+    csr.rows = (int32_t)M;
+    csc.rows = (int32_t)N;
+    csr.ptr.assign(M + 1, 0);
+    csc.ptr.assign(N + 1, 0);
+    csr.ent.resize(NNZ);
+    csc.ent.resize(NNZ);
+    std::vector<double> cval(NNZ), rval(NNZ);
+    std::vector<int32_t> crow(NNZ);
+    // CSR (global column ids)
+    int64_t e_out = 0;
+    for (int32_t q = 0; q < count; ++q) {
+        const scylla_csr &A = lps[q].A;
+        for (int32_t i = 0; i < A.m; ++i) {
+            for (int64_t e = A.row_ptr[i]; e < A.row_ptr[i + 1]; ++e) {
+                csr.ent[e_out] = (uint32_t)(A.col_idx[e] + col_off[q]);
+                rval[e_out] = A.val[e];
+                ++e_out;
+            }
+            csr.ptr[row_off[q] + i + 1] = (int32_t)e_out;
+        }
+    }
+    // CSC by a stable counting sort over the CSR entries (row order), so the
+    // rows of every column are increasing
+    for (int64_t e = 0; e < NNZ; ++e) csc.ptr[csr.ent[e] + 1]++;
+    for (int64_t j = 0; j < N; ++j) csc.ptr[j + 1] += csc.ptr[j];
+    {
+        std::vector<int32_t> fill(csc.ptr.begin(), csc.ptr.end() - 1);
+        for (int64_t i = 0; i < M; ++i)
+            for (int32_t e = csr.ptr[i]; e < csr.ptr[i + 1]; ++e) {
+                int32_t pos = fill[csr.ent[e]]++;
+                csc.ent[pos] = (uint32_t)i;
+                cval[pos] = rval[e];
+            }
+    }
+    auto finish = [&](HostOrient &o, std::vector<double> &vals, int32_t sh) {
+        if (fmt == FMT_PACKED) {
+            o.shift = sh;
+            o.mask = (sh >= 32) ? 0xffffffffu : ((1u << sh) - 1u);
+            for (int64_t e = 0; e < NNZ; ++e)
+                o.ent[e] |= ((uint32_t)(int32_t)vals[e]) << sh;
+        } else if (fmt == FMT_BF16) {
+            o.v16.resize(NNZ);
+            bool ex;
+            for (int64_t e = 0; e < NNZ; ++e) o.v16[e] = f64_to_bf16_exact(vals[e], ex);
+        } else if (fmt == FMT_F32) {
+            o.v32.resize(NNZ);
+            for (int64_t e = 0; e < NNZ; ++e) o.v32[e] = (float)vals[e];
+        } else {
+            o.v64 = vals;
+        }
+    };
+    finish(csr, rval, sh_r);
+    finish(csc, cval, sh_c);
+    return 0;
+}
+
+void plan_tiles(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
+                int32_t chunk, int32_t max_rows, TilePlan &plan)
+{
+    const int32_t count = (int32_t)inst_off.size() - 1;
+    plan.chunk = chunk;
+    plan.tiles.clear();
+    plan.longs.clear();
+    plan.nslots = 0;
+    plan.t_begin.assign(count, 0);
+    plan.t_end.assign(count, 0);
+    plan.l_begin.assign(count, 0);
+    plan.l_end.assign(count, 0);
+    for (int32_t q = 0; q < count; ++q) {
+        plan.t_begin[q] = (int32_t)(plan.tiles.size() / 4);
+        plan.l_begin[q] = (int32_t)(plan.longs.size() / 4);
+        int32_t r = inst_off[q];
+        const int32_t rend = inst_off[q + 1];
+        while (r < rend) {
+            int32_t len = ptr[r + 1] - ptr[r];
+            if (len > chunk) {
+                int32_t nseg = (len + chunk - 1) / chunk;
+                plan.longs.insert(plan.longs.end(), {r, plan.nslots, nseg, q});
+                for (int32_t s = 0; s < nseg; ++s) {
+                    int32_t a = ptr[r] + s * chunk;
+                    int32_t b = std::min(a + chunk, ptr[r + 1]);
+                    plan.tiles.insert(plan.tiles.end(), {a, b, q, plan.nslots + s});
+                }
+                plan.nslots += nseg;
+                ++r;
+                continue;
+            }
+            int32_t start = r, nz = 0;
+            while (r < rend && r - start < max_rows) {
+                int32_t l2 = ptr[r + 1] - ptr[r];
+                if (l2 > chunk || nz + l2 > chunk) break;
+                nz += l2;
+                ++r;
+            }
+            plan.tiles.insert(plan.tiles.end(), {start, r, q, -1});
+        }
+        plan.t_end[q] = (int32_t)(plan.tiles.size() / 4);
+        plan.l_end[q] = (int32_t)(plan.longs.size() / 4);
+    }
+}
+
+}  // namespace scy

@@ -1,0 +1,77 @@
+// Kernel argument blocks and host launchers of the PDHG kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "scylla_internal.h"
+
+namespace scy {
+
+enum { DIR_ROW = 0, DIR_COL = 1 };
+
+// One orientation of the matrix in device memory.
+struct MatView {
+    const int32_t *ptr;   // [rows + 1]
+    const uint32_t *ent;  // [nnz] index or packed word
+    const void *val;      // [nnz] values (format dependent) or null
+    int32_t shift;        // packed: value = (int32)word >> shift
+    uint32_t mask;        // packed: index = word & mask
+};
+
+// Arguments of one pass (row pass = dual step over the CSR, column pass =
+// primal step over the CSC) and of its FP64 check variant.
+template <class V>
+struct PassArgs {
+    MatView M;
+    const int4 *tiles;
+    int32_t ntiles;
+    const int4 *longs;    // long-row descriptors {row, slot0, nseg, inst}
+    int32_t nlong;
+    const V *gvec;        // gathered vector: x_bar (row pass), y (column
+                          // pass); x (row check)
+    V *own;               // y (row) / x (column), updated in place
+    V *bar;               // x_bar output (column pass)
+    V *own_ref;           // restart reference y_r / x_r
+    const V *rhs;         // b (row) / c_hat (column)
+    const V *diag2;       // D_r^2 / D_c^2
+    const V *lo, *hi;     // l, u (column)
+    const uint8_t *sense; // row senses
+    InstState *st;
+    V *seg;               // long-row segment partials
+    double *seg64;        // long-row segment partials (check)
+    // check variant
+    const double *rhs64;  // b / c_hat in FP64
+    const double *lo64, *hi64;
+    const double *d64;    // d_r / d_c
+    double *part;         // 4 doubles per tile
+    double *lpart;        // 4 doubles per long row
+};
+
+struct DecideArgs {
+    InstState *st;
+    const InstInfo *info;
+    const double *rpart, *lrpart, *cpart, *lcpart;
+    int32_t R;
+};
+
+template <class V>
+void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, hipStream_t s);
+void launch_decide(const DecideArgs &d, int count, hipStream_t s);
+void launch_force_stop(InstState *st, int count, hipStream_t s);
+void launch_scale_reduce(const MatView &M, int fmt, int rows, const double *drow, const double *dcol,
+                         double *out, int mode, hipStream_t s);
+void launch_scale_apply(double *d, const double *r, int len, hipStream_t s);
+void launch_inst_norms(const InstInfo *info, int count, const double *b, const double *c,
+                       const double *dr, const double *dc, InstState *st, hipStream_t s);
+template <class V>
+void launch_finish_diag(const double *d, V *d2, int len, hipStream_t s);
+template <class V>
+void launch_cast(const double *src, V *dst, int len, hipStream_t s);
+template <class V>
+void launch_project(V *x, const V *l, const V *u, int clo, int chi, V *y, const uint8_t *sense, int rlo,
+                    int rhi, int zero, hipStream_t s);
+template <class V>
+void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibits, double a, double kappa,
+                  double *c64, V *cv, int lo, int hi, hipStream_t s);
+
+}  // namespace scy

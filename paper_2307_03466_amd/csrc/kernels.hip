@@ -1,0 +1,684 @@
+// Device kernels of the PDHG library (gfx950, wave64).
+//
+// One PDHG iteration (Algorithm 1 inner loop, diagonal steps from the
+// preconditioner) is two bandwidth-bound passes:
+//   column pass over the CSC copy:  g = c_hat - A^T y,
+//       x+ = proj_[l,u](x - t D_c^2 g),  x_bar = 2 x+ - x     (primal step)
+//   row pass over the CSR:          y+ = proj_Y(y + s D_r^2 (b - A x_bar))
+//                                                             (dual step)
+// Both passes use the same tile kernel: a workgroup streams a contiguous
+// run of nonzeros (coalesced, non-temporal so the gathered vector keeps the
+// L2), multiplies by the gathered vector into LDS, then reduces each row
+// with a power-of-two group of lanes sized to the tile's row count and
+// applies the fused projection epilogue.  Rows longer than a tile are cut
+// into segments whose partial sums a small combine kernel adds in a fixed
+// order, so no floating-point atomics are used anywhere and every result is
+// bitwise reproducible.
+//
+// Every R iterations a check (FP64 accumulation) evaluates the relative KKT
+// errors of Section 2.2 and the restart quantities; a one-workgroup-per-
+// instance decision kernel reduces them in a fixed order and sets status,
+// restart and step sizes in FP64 on the device.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "scylla_internal.h"
+#include "kernels.h"
+
+namespace scy {
+
+// ------------------------------------------------------------------ utils
+// The hardware hands consecutive workgroups to the 8 XCDs in turn; map them
+// so every XCD works on one contiguous range of tiles (neighbouring tiles
+// share cache lines of the row-side vectors in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int xcd = b & 7, local = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    const int base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return base + local;
+}
+
+template <class V>
+__device__ __forceinline__ V wave_sum_width(V v, int width)
+{
+    for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, width);
+    return v;
+}
+
+// Fixed-order block sum (result valid in thread 0).
+template <class V, int NT>
+__device__ __forceinline__ V block_sum(V v, V *red)
+{
+    v = wave_sum_width(v, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    V s = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) s += red[q];
+    }
+    return s;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// Loads of the streamed matrix words / values (read once per pass).
+template <int FMT>
+struct Entry {
+    uint32_t w;
+    float f;
+    double d;
+};
+
+template <int FMT, class A>
+__device__ __forceinline__ void load_entry(const MatView &M, int e, uint32_t &w, A &a)
+{
+    w = __builtin_nontemporal_load(M.ent + e);
+    if constexpr (FMT == FMT_BF16) {
+        a = (A)bf16_to_f32(__builtin_nontemporal_load((const uint16_t *)M.val + e));
+    } else if constexpr (FMT == FMT_F32) {
+        a = (A)__builtin_nontemporal_load((const float *)M.val + e);
+    } else if constexpr (FMT == FMT_F64) {
+        a = (A)__builtin_nontemporal_load((const double *)M.val + e);
+    } else {
+        a = (A)0;
+    }
+}
+
+template <int FMT, class A>
+__device__ __forceinline__ int decode_entry(const MatView &M, uint32_t w, A &a)
+{
+    if constexpr (FMT == FMT_PACKED) {
+        a = (A)((int32_t)w >> M.shift);
+        return (int)(w & M.mask);
+    } else {
+        return (int)w;
+    }
+}
+
+// Stage prod[e - e0] = a_e * vec[idx_e] for e in [e0, e1), e1 - e0 <= NT*EPT.
+template <class A, class GV, int FMT, int NT, int EPT>
+__device__ __forceinline__ void stage_products(const MatView &M, const GV *__restrict__ vec, int e0,
+                                               int e1, A *prod)
+{
+    const int tid = threadIdx.x;
+    uint32_t w[EPT];
+    A a[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = e0 + q * NT + tid;
+        w[q] = 0;
+        a[q] = (A)0;
+        if (e < e1) load_entry<FMT, A>(M, e, w[q], a[q]);
+    }
+    A g[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = e0 + q * NT + tid;
+        g[q] = (A)0;
+        if (e < e1) {
+            const int idx = decode_entry<FMT, A>(M, w[q], a[q]);
+            g[q] = (A)vec[idx];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = e0 + q * NT + tid;
+        if (e < e1) prod[e - e0] = a[q] * g[q];
+    }
+}
+
+// ------------------------------------------------------------ epilogues
+// Dual step of Algorithm 1 for row i given (A x_bar)_i.
+template <class V>
+__device__ __forceinline__ void dual_update(const PassArgs<V> &p, int i, V axb, V s, bool copy_ref)
+{
+    const V yi = p.own[i];
+    V v = yi + s * p.diag2[i] * (p.rhs[i] - axb);
+    const uint8_t sn = p.sense[i];
+    if (sn == 'G') v = v > (V)0 ? v : (V)0;
+    else if (sn == 'L') v = v < (V)0 ? v : (V)0;
+    if (copy_ref) p.own_ref[i] = yi;
+    p.own[i] = v;
+}
+
+// Primal step of Algorithm 1 for column j given (A^T y)_j.
+template <class V>
+__device__ __forceinline__ void primal_update(const PassArgs<V> &p, int j, V aty, V t, bool copy_ref)
+{
+    const V xj = p.own[j];
+    V xn = xj + t * p.diag2[j] * (aty - p.rhs[j]);
+    const V lo = p.lo[j], hi = p.hi[j];
+    xn = xn < lo ? lo : xn;
+    xn = xn > hi ? hi : xn;
+    if (copy_ref) p.own_ref[j] = xj;
+    p.bar[j] = (V)2 * xn - xj;
+    p.own[j] = xn;
+}
+
+// ------------------------------------------------------- iteration pass
+template <class V, int FMT, int DIR, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
+{
+    constexpr int CH = NT * EPT;
+    __shared__ V prod[CH];
+    __shared__ V red[NT / 64];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int4 T = p.tiles[t];
+    const InstState &S = p.st[T.z];
+    if (S.status != ST_RUN || jw >= S.nrun) return;
+    const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+    const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    int e0, e1;
+    if (T.w >= 0) {
+        e0 = T.x;
+        e1 = T.y;
+    } else {
+        e0 = p.M.ptr[T.x];
+        e1 = p.M.ptr[T.y];
+    }
+    stage_products<V, V, FMT, NT, EPT>(p.M, p.gvec, e0, e1, prod);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    if (T.w >= 0) {  // one segment of a long row: partial sum only
+        V s = 0;
+        for (int q = tid; q < e1 - e0; q += NT) s += prod[q];
+        s = block_sum<V, NT>(s, red);
+        if (tid == 0) p.seg[T.w] = s;
+        return;
+    }
+    const int r0 = T.x, nrows = T.y - T.x;
+    int L = 1;
+    while (L < 64 && nrows * (L << 1) <= NT) L <<= 1;
+    const int groups = NT / L, lane = tid & (L - 1);
+    for (int r = tid / L; r < nrows; r += groups) {
+        const int rb = p.M.ptr[r0 + r] - e0, re = p.M.ptr[r0 + r + 1] - e0;
+        V s = 0;
+        for (int q = rb + lane; q < re; q += L) s += prod[q];
+        if (L > 1) s = wave_sum_width(s, L);
+        if (lane == 0) {
+            if (DIR == DIR_COL) primal_update(p, r0 + r, s, step, copy_ref);
+            else dual_update(p, r0 + r, s, step, copy_ref);
+        }
+    }
+}
+
+// Long rows: add the segment partials in segment order, then the epilogue.
+template <class V, int DIR>
+__global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int jw)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.nlong) return;
+    const int4 L = p.longs[q];
+    const InstState &S = p.st[L.w];
+    if (S.status != ST_RUN || jw >= S.nrun) return;
+    const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+    V s = 0;
+    for (int k = 0; k < L.z; ++k) s += p.seg[L.y + k];
+    if (DIR == DIR_COL) primal_update(p, L.x, s, (V)S.t, copy_ref);
+    else dual_update(p, L.x, s, (V)S.s, copy_ref);
+}
+
+// ------------------------------------------------------------ KKT check
+// Per-row / per-column FP64 contributions (Section 2.2, original problem).
+//   row i : q0 = r_p,i^2, q1 = b_i y_i, q2 = ((y_i - yr_i) / d_r,i)^2
+//   col j : q0 = r_d,j^2, q1 = c_j x_j, q2 = l_j max(lam_j,0) + u_j min(lam_j,0),
+//           q3 = ((x_j - xr_j) / d_c,j)^2
+template <class V>
+__device__ __forceinline__ void row_terms(const PassArgs<V> &p, int i, double ax, double q[4])
+{
+    const double b = p.rhs64[i];
+    const uint8_t sn = p.sense[i];
+    double r;
+    if (sn == 'G') r = fmax(b - ax, 0.0);
+    else if (sn == 'L') r = fmax(ax - b, 0.0);
+    else r = b - ax;
+    const double y = (double)p.own[i];
+    const double dy = (y - (double)p.own_ref[i]) / p.d64[i];
+    q[0] += r * r;
+    q[1] += b * y;
+    q[2] += dy * dy;
+}
+
+template <class V>
+__device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double aty, double q[4])
+{
+    const double g = p.rhs64[j] - aty;
+    const double l = p.lo64[j], u = p.hi64[j];
+    const bool lf = isfinite(l), uf = isfinite(u);
+    double lam;
+    if (lf && uf) lam = g;
+    else if (lf) lam = fmax(g, 0.0);
+    else if (uf) lam = fmin(g, 0.0);
+    else lam = 0.0;
+    const double rd = g - lam;
+    const double x = (double)p.own[j];
+    const double dx = (x - (double)p.own_ref[j]) / p.d64[j];
+    q[0] += rd * rd;
+    q[1] += p.rhs64[j] * x;
+    if (lf && lam > 0.0) q[2] += l * lam;
+    if (uf && lam < 0.0) q[2] += u * lam;
+    q[3] += dx * dx;
+}
+
+template <class V, int FMT, int DIR, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_check(const PassArgs<V> p)
+{
+    constexpr int CH = NT * EPT;
+    __shared__ double prod[CH];
+    __shared__ double red[NT / 64];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int4 T = p.tiles[t];
+    const InstState &S = p.st[T.z];
+    if (S.status != ST_RUN) return;
+    int e0, e1;
+    if (T.w >= 0) {
+        e0 = T.x;
+        e1 = T.y;
+    } else {
+        e0 = p.M.ptr[T.x];
+        e1 = p.M.ptr[T.y];
+    }
+    // row check gathers x (not x_bar), column check gathers y
+    stage_products<double, V, FMT, NT, EPT>(p.M, p.gvec, e0, e1, prod);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    if (T.w >= 0) {
+        // a segment's row terms are added once by the combine kernel; its own
+        // tile slot contributes nothing
+        double s = 0;
+        for (int q = tid; q < e1 - e0; q += NT) s += prod[q];
+        s = block_sum<double, NT>(s, red);
+        if (tid == 0) {
+            p.seg64[T.w] = s;
+            for (int k = 0; k < 4; ++k) p.part[4 * t + k] = 0.0;
+        }
+        return;
+    }
+    const int r0 = T.x, nrows = T.y - T.x;
+    int L = 1;
+    while (L < 64 && nrows * (L << 1) <= NT) L <<= 1;
+    const int groups = NT / L, lane = tid & (L - 1);
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = tid / L; r < nrows; r += groups) {
+        const int rb = p.M.ptr[r0 + r] - e0, re = p.M.ptr[r0 + r + 1] - e0;
+        double s = 0;
+        for (int k = rb + lane; k < re; k += L) s += prod[k];
+        if (L > 1) s = wave_sum_width(s, L);
+        if (lane == 0) {
+            if (DIR == DIR_COL) col_terms(p, r0 + r, s, q);
+            else row_terms(p, r0 + r, s, q);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        __syncthreads();
+        const double v = block_sum<double, NT>(q[k], red);
+        if (tid == 0) p.part[4 * t + k] = v;
+    }
+}
+
+template <class V, int DIR>
+__global__ __launch_bounds__(256) void k_combine_check(const PassArgs<V> p)
+{
+    const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= p.nlong) return;
+    const int4 L = p.longs[qi];
+    const InstState &S = p.st[L.w];
+    if (S.status != ST_RUN) return;
+    double s = 0;
+    for (int k = 0; k < L.z; ++k) s += p.seg64[L.y + k];
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    if (DIR == DIR_COL) col_terms(p, L.x, s, q);
+    else row_terms(p, L.x, s, q);
+    for (int k = 0; k < 4; ++k) p.lpart[4 * qi + k] = q[k];
+}
+
+// ------------------------------------------------------------- decision
+// One workgroup per instance: fixed-order FP64 reduction of the check
+// partials, then termination (Section 2.2), restart and primal-weight
+// update, all in FP64.
+__global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
+{
+    const int inst = blockIdx.x;
+    InstState &S = d.st[inst];
+    if (S.status != ST_RUN) return;
+    const InstInfo I = d.info[inst];
+    __shared__ double red[4];
+    // q: 0 rp2, 1 by, 2 dy2 (rows); 3 rd2, 4 cx, 5 bound, 6 dx2 (columns)
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int t = I.rt0 + threadIdx.x; t < I.rt1; t += 256)
+        for (int k = 0; k < 3; ++k) acc[k] += d.rpart[4 * t + k];
+    for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256)
+        for (int k = 0; k < 3; ++k) acc[k] += d.lrpart[4 * t + k];
+    for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256)
+        for (int k = 0; k < 4; ++k) acc[3 + k] += d.cpart[4 * t + k];
+    for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256)
+        for (int k = 0; k < 4; ++k) acc[3 + k] += d.lcpart[4 * t + k];
+    double tot[7];
+    for (int k = 0; k < 7; ++k) {
+        __syncthreads();
+        tot[k] = block_sum<double, 256>(acc[k], red);
+    }
+    if (threadIdx.x != 0) return;
+    const int64_t k = S.k + S.nrun;
+    S.k = k;
+    S.nrun = 0;
+    S.restart_now = 0;
+    const double rho_p = sqrt(tot[0]) / (1.0 + S.bnorm);
+    const double rho_d = sqrt(tot[3]) / (1.0 + S.cnorm);
+    const double P = tot[4], D = tot[1] + tot[5];
+    const double rho_g = fabs(P - D) / (1.0 + fabs(P) + fabs(D));
+    double E = fmax(rho_p, fmax(rho_d, rho_g));
+    if (!isfinite(rho_p) || !isfinite(rho_d) || !isfinite(rho_g)) E = NAN;
+    S.rho_p = rho_p;
+    S.rho_d = rho_d;
+    S.rho_g = rho_g;
+    S.pobj = P;
+    S.dobj = D;
+    S.rel = E;
+    if (!isfinite(E)) { S.status = ST_NUM; return; }
+    if (E <= S.tol) { S.status = ST_OPT; return; }
+    if (k >= S.k_limit) { S.status = ST_ITER; return; }
+    if (S.force_stop) { S.status = ST_TIME; return; }
+    if (k == 0) {
+        S.Er = E;
+        S.kr = 0;
+        S.restart_now = 1;
+    } else if (S.restart_on) {
+        const bool fire = (E <= 0.2 * S.Er) || (E <= 0.8 * S.Er && E > S.Ep) ||
+                          ((double)(k - S.kr) >= 0.36 * (double)k);
+        if (fire) {
+            const double dx = sqrt(tot[6]), dy = sqrt(tot[2]);
+            if (dx > 1e-10 && dy > 1e-10) {
+                S.omega = exp(0.5 * log(dy / dx) + 0.5 * log(S.omega));
+                S.t = S.eta / S.omega;
+                S.s = S.eta * S.omega;
+            }
+            S.Er = E;
+            S.kr = k;
+            S.restarts += 1;
+            S.restart_now = 1;
+        }
+    }
+    S.Ep = E;
+    const int64_t left = S.k_limit - k;
+    S.nrun = (int32_t)(left < (int64_t)d.R ? left : (int64_t)d.R);
+}
+
+__global__ void k_force_stop(InstState *st, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count && st[i].status == ST_RUN) st[i].force_stop = 1;
+}
+
+// ---------------------------------------------------------------- setup
+// Preconditioner reductions over one orientation (one wave per row):
+// mode 0: r_i = max_j |d_r,i a_ij d_c,j|;  mode 1: r_i = sum_j |...|.
+// `drow` scales the rows of this orientation, `dcol` the columns.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_scale_reduce(const MatView M, int rows, const double *drow,
+                                                      const double *dcol, double *out, int mode)
+{
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    const int e0 = M.ptr[row], e1 = M.ptr[row + 1];
+    double acc = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) {
+        uint32_t w;
+        double a;
+        load_entry<FMT, double>(M, e, w, a);
+        const int idx = decode_entry<FMT, double>(M, w, a);
+        const double v = fabs(drow[row] * a * dcol[idx]);
+        acc = mode == 0 ? fmax(acc, v) : acc + v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(acc, off, 64);
+        acc = mode == 0 ? fmax(acc, o) : acc + o;
+    }
+    if (lane == 0) out[row] = acc;
+}
+
+__global__ void k_scale_apply(double *d, const double *r, int len)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len && r[i] > 0.0) d[i] /= sqrt(r[i]);
+}
+
+// Per-instance norms of the current objective c_hat and of b: ||b||,
+// ||c_hat||, and the cold-start primal weight ||D_c c_hat|| / ||D_r b|| (or 1).
+__global__ __launch_bounds__(256) void k_inst_norms(const InstInfo *info, const double *b,
+                                                    const double *c, const double *dr,
+                                                    const double *dc, InstState *st)
+{
+    const int inst = blockIdx.x;
+    const InstInfo I = info[inst];
+    __shared__ double red[4];
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int i = I.row0 + threadIdx.x; i < I.row1; i += 256) {
+        a0 += b[i] * b[i];
+        const double v = dr[i] * b[i];
+        a1 += v * v;
+    }
+    for (int j = I.col0 + threadIdx.x; j < I.col1; j += 256) {
+        a2 += c[j] * c[j];
+        const double v = dc[j] * c[j];
+        a3 += v * v;
+    }
+    const double s0 = block_sum<double, 256>(a0, red);
+    __syncthreads();
+    const double s1 = block_sum<double, 256>(a1, red);
+    __syncthreads();
+    const double s2 = block_sum<double, 256>(a2, red);
+    __syncthreads();
+    const double s3 = block_sum<double, 256>(a3, red);
+    if (threadIdx.x == 0) {
+        InstState &S = st[inst];
+        S.cnorm = sqrt(s2);
+        S.bnorm = sqrt(s0);
+        const double bs = sqrt(s1), cs = sqrt(s3);
+        S.omega0 = (cs > 0.0 && bs > 0.0) ? cs / bs : 1.0;
+    }
+}
+
+template <class V>
+__global__ void k_finish_diag(const double *d, V *d2, int len)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) d2[i] = (V)(d[i] * d[i]);
+}
+
+template <class V>
+__global__ void k_cast(const double *src, V *dst, int len)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) dst[i] = (V)src[i];
+}
+
+// Start point: x = proj_[l,u](x), y = proj_Y(y) on [lo, hi) ranges; zero
+// first when `zero` is set.
+template <class V>
+__global__ void k_project_primal(V *x, const V *l, const V *u, int lo, int hi, int zero)
+{
+    const int j = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= hi) return;
+    V v = zero ? (V)0 : x[j];
+    v = v < l[j] ? l[j] : v;
+    v = v > u[j] ? u[j] : v;
+    x[j] = v;
+}
+
+template <class V>
+__global__ void k_project_dual(V *y, const uint8_t *sense, int lo, int hi, int zero)
+{
+    const int i = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hi) return;
+    V v = zero ? (V)0 : y[i];
+    const uint8_t sn = sense[i];
+    if (sn == 'G') v = v > (V)0 ? v : (V)0;
+    else if (sn == 'L') v = v < (V)0 ? v : (V)0;
+    y[i] = v;
+}
+
+// Pump objective (Algorithm 1, objective update) on columns [lo, hi):
+// c_hat_j = a kappa c_j + (1 - a) g_j, g_j = +1 / -1 from the rounding bit,
+// 0 for continuous columns.
+template <class V>
+__global__ void k_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibits, double a,
+                        double kappa, double *c64, V *cv, int lo, int hi)
+{
+    const int j = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= hi) return;
+    const int q = j - lo;
+    const bool integer = ibits ? ((ibits[q >> 3] >> (q & 7)) & 1) : true;
+    const bool up = (xbits[q >> 3] >> (q & 7)) & 1;
+    const double g = integer ? (up ? -1.0 : 1.0) : 0.0;
+    const double v = a * kappa * c_orig[j] + (1.0 - a) * g;
+    c64[j] = v;
+    cv[j] = (V)v;
+}
+
+// ------------------------------------------------------ host launchers
+template <class V, int FMT, int DIR, int NT, int EPT>
+static void launch_pass_t(const PassArgs<V> &p, int jw, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pass<V, FMT, DIR, NT, EPT>), dim3(p.ntiles), dim3(NT), 0, s, p, jw);
+}
+
+template <class V, int FMT, int DIR, int NT, int EPT>
+static void launch_check_t(const PassArgs<V> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_check<V, FMT, DIR, NT, EPT>), dim3(p.ntiles), dim3(NT), 0, s, p);
+}
+
+template <class V, int FMT, int DIR>
+static void dispatch_pass(const PassArgs<V> &p, int ept, int jw, bool check, hipStream_t s)
+{
+    switch (ept) {
+    case 4:
+        check ? launch_check_t<V, FMT, DIR, 256, 4>(p, s) : launch_pass_t<V, FMT, DIR, 256, 4>(p, jw, s);
+        break;
+    case 8:
+        check ? launch_check_t<V, FMT, DIR, 256, 8>(p, s) : launch_pass_t<V, FMT, DIR, 256, 8>(p, jw, s);
+        break;
+    default:
+        check ? launch_check_t<V, FMT, DIR, 256, 16>(p, s) : launch_pass_t<V, FMT, DIR, 256, 16>(p, jw, s);
+        break;
+    }
+}
+
+template <class V>
+void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, hipStream_t s)
+{
+    if (p.ntiles > 0) {
+        if constexpr (sizeof(V) == 8) {
+            if (dir == DIR_COL) dispatch_pass<V, FMT_F64, DIR_COL>(p, ept, jw, check, s);
+            else dispatch_pass<V, FMT_F64, DIR_ROW>(p, ept, jw, check, s);
+        } else {
+            if (fmt == FMT_PACKED) {
+                if (dir == DIR_COL) dispatch_pass<V, FMT_PACKED, DIR_COL>(p, ept, jw, check, s);
+                else dispatch_pass<V, FMT_PACKED, DIR_ROW>(p, ept, jw, check, s);
+            } else if (fmt == FMT_BF16) {
+                if (dir == DIR_COL) dispatch_pass<V, FMT_BF16, DIR_COL>(p, ept, jw, check, s);
+                else dispatch_pass<V, FMT_BF16, DIR_ROW>(p, ept, jw, check, s);
+            } else {
+                if (dir == DIR_COL) dispatch_pass<V, FMT_F32, DIR_COL>(p, ept, jw, check, s);
+                else dispatch_pass<V, FMT_F32, DIR_ROW>(p, ept, jw, check, s);
+            }
+        }
+    }
+    if (p.nlong > 0) {
+        const int nb = (p.nlong + 255) / 256;
+        if (check) {
+            if (dir == DIR_COL) hipLaunchKernelGGL((k_combine_check<V, DIR_COL>), dim3(nb), dim3(256), 0, s, p);
+            else hipLaunchKernelGGL((k_combine_check<V, DIR_ROW>), dim3(nb), dim3(256), 0, s, p);
+        } else {
+            if (dir == DIR_COL) hipLaunchKernelGGL((k_combine<V, DIR_COL>), dim3(nb), dim3(256), 0, s, p, jw);
+            else hipLaunchKernelGGL((k_combine<V, DIR_ROW>), dim3(nb), dim3(256), 0, s, p, jw);
+        }
+    }
+}
+
+void launch_decide(const DecideArgs &d, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_decide, dim3(count), dim3(256), 0, s, d);
+}
+
+void launch_force_stop(InstState *st, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_force_stop, dim3((count + 255) / 256), dim3(256), 0, s, st, count);
+}
+
+void launch_scale_reduce(const MatView &M, int fmt, int rows, const double *drow, const double *dcol,
+                         double *out, int mode, hipStream_t s)
+{
+    if (rows <= 0) return;
+    dim3 g((rows + 3) / 4), b(256);
+    switch (fmt) {
+    case FMT_PACKED: hipLaunchKernelGGL(k_scale_reduce<FMT_PACKED>, g, b, 0, s, M, rows, drow, dcol, out, mode); break;
+    case FMT_BF16: hipLaunchKernelGGL(k_scale_reduce<FMT_BF16>, g, b, 0, s, M, rows, drow, dcol, out, mode); break;
+    case FMT_F32: hipLaunchKernelGGL(k_scale_reduce<FMT_F32>, g, b, 0, s, M, rows, drow, dcol, out, mode); break;
+    default: hipLaunchKernelGGL(k_scale_reduce<FMT_F64>, g, b, 0, s, M, rows, drow, dcol, out, mode); break;
+    }
+}
+
+void launch_scale_apply(double *d, const double *r, int len, hipStream_t s)
+{
+    if (len > 0) hipLaunchKernelGGL(k_scale_apply, dim3((len + 255) / 256), dim3(256), 0, s, d, r, len);
+}
+
+void launch_inst_norms(const InstInfo *info, int count, const double *b, const double *c,
+                       const double *dr, const double *dc, InstState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_inst_norms, dim3(count), dim3(256), 0, s, info, b, c, dr, dc, st);
+}
+
+template <class V>
+void launch_finish_diag(const double *d, V *d2, int len, hipStream_t s)
+{
+    if (len > 0) hipLaunchKernelGGL(k_finish_diag<V>, dim3((len + 255) / 256), dim3(256), 0, s, d, d2, len);
+}
+
+template <class V>
+void launch_cast(const double *src, V *dst, int len, hipStream_t s)
+{
+    if (len > 0) hipLaunchKernelGGL(k_cast<V>, dim3((len + 255) / 256), dim3(256), 0, s, src, dst, len);
+}
+
+template <class V>
+void launch_project(V *x, const V *l, const V *u, int clo, int chi, V *y, const uint8_t *sense, int rlo,
+                    int rhi, int zero, hipStream_t s)
+{
+    if (chi > clo)
+        hipLaunchKernelGGL(k_project_primal<V>, dim3((chi - clo + 255) / 256), dim3(256), 0, s, x, l, u, clo, chi, zero);
+    if (rhi > rlo)
+        hipLaunchKernelGGL(k_project_dual<V>, dim3((rhi - rlo + 255) / 256), dim3(256), 0, s, y, sense, rlo, rhi, zero);
+}
+
+template <class V>
+void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibits, double a, double kappa,
+                  double *c64, V *cv, int lo, int hi, hipStream_t s)
+{
+    if (hi > lo)
+        hipLaunchKernelGGL(k_blend<V>, dim3((hi - lo + 255) / 256), dim3(256), 0, s, c_orig, xbits, ibits, a,
+                           kappa, c64, cv, lo, hi);
+}
+
+#define SCY_INST(V)                                                                                    \
+    template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, hipStream_t);          \
+    template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
+    template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \
+    template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \
+                                    int, hipStream_t);                                                 \
+    template void launch_blend<V>(const double *, const uint8_t *, const uint8_t *, double, double,    \
+                                  double *, V *, int, int, hipStream_t);
+SCY_INST(float)
+SCY_INST(double)
+
+}  // namespace scy

@@ -1,0 +1,903 @@
+// Runtime and C ABI of the PDHG library: device-resident batches of LPs,
+// device-side preconditioning, tile plans and their autotuner, hipGraph
+// capture of one check window (KKT check + decision + R iterations), and
+// the host loop that launches windows and polls one status copy per window.
+#include <errno.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "scylla_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Err {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void throw_err(int code, const std::string &msg) { throw Err{code, msg}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        const int code = (e == hipErrorOutOfMemory) ? -ENOMEM : -EIO;
+        throw_err(code, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+#define HIPC(x) hip_check((x), #x)
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Owned device allocation.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b)
+    {
+        release();
+        bytes = b;
+        HIPC(hipMalloc(&p, b > 0 ? b : 16));
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+template <class T>
+void upload(DevMem &d, const std::vector<T> &h, hipStream_t s)
+{
+    d.alloc(h.size() * sizeof(T));
+    if (!h.empty()) HIPC(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+}  // namespace
+
+using namespace scy;
+
+struct scylla_batch {
+    int32_t count = 0, precision = SCYLLA_FP32, fmt = FMT_PACKED;
+    int32_t vbytes = 4;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap = nullptr;  // private stream used for graph capture
+    int32_t M = 0, N = 0;
+    int64_t NNZ = 0;
+    std::vector<int32_t> row_off, col_off;
+    std::vector<int32_t> csr_ptr_h, csc_ptr_h;
+    // matrix
+    DevMem csr_ptr, csr_ent, csr_val, csc_ptr, csc_ent, csc_val;
+    MatView csr{}, csc{};
+    // vectors in the path precision
+    DevMem x, xbar, xr, y, yr, cv, lv, uv, dc2, b_v, dr2;
+    DevMem sense;
+    // FP64 data
+    DevMem c64, corig64, l64, u64, b64, dr64, dc64;
+    DevMem st, info;
+    // plans
+    TilePlan prow, pcol;
+    int32_t ept_row = 8, ept_col = 8;
+    DevMem rtiles, ctiles, rlongs, clongs, rseg, cseg, rseg64, cseg64, rpart, cpart, lrpart, lcpart;
+    DevMem bits_tmp, ibits_tmp;
+    // graph
+    hipGraphExec_t gexec = nullptr;
+    int32_t graph_R = 0;
+    bool tuned = false;
+    // host mirrors
+    std::vector<InstInfo> hinfo;
+    InstState *pinned = nullptr;  // 2 * count states
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double setup_seconds = 0.0;
+
+    ~scylla_batch()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (pinned) (void)hipHostFree(pinned);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+void check_device()
+{
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        throw_err(-ENODEV, "no HIP device visible");
+    }
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        throw_err(-ENODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+}
+
+template <class V>
+PassArgs<V> row_args(scylla_batch *h, bool check)
+{
+    PassArgs<V> p{};
+    p.M = h->csr;
+    p.tiles = h->rtiles.as<int4>();
+    p.ntiles = (int32_t)(h->prow.tiles.size() / 4);
+    p.longs = h->rlongs.as<int4>();
+    p.nlong = (int32_t)(h->prow.longs.size() / 4);
+    p.gvec = check ? h->x.as<V>() : h->xbar.as<V>();
+    p.own = h->y.as<V>();
+    p.own_ref = h->yr.as<V>();
+    p.rhs = h->b_v.as<V>();
+    p.diag2 = h->dr2.as<V>();
+    p.sense = h->sense.as<uint8_t>();
+    p.st = h->st.as<InstState>();
+    p.seg = h->rseg.as<V>();
+    p.seg64 = h->rseg64.as<double>();
+    p.rhs64 = h->b64.as<double>();
+    p.d64 = h->dr64.as<double>();
+    p.part = h->rpart.as<double>();
+    p.lpart = h->lrpart.as<double>();
+    return p;
+}
+
+template <class V>
+PassArgs<V> col_args(scylla_batch *h, bool check)
+{
+    (void)check;
+    PassArgs<V> p{};
+    p.M = h->csc;
+    p.tiles = h->ctiles.as<int4>();
+    p.ntiles = (int32_t)(h->pcol.tiles.size() / 4);
+    p.longs = h->clongs.as<int4>();
+    p.nlong = (int32_t)(h->pcol.longs.size() / 4);
+    p.gvec = h->y.as<V>();
+    p.own = h->x.as<V>();
+    p.bar = h->xbar.as<V>();
+    p.own_ref = h->xr.as<V>();
+    p.rhs = h->cv.as<V>();
+    p.diag2 = h->dc2.as<V>();
+    p.lo = h->lv.as<V>();
+    p.hi = h->uv.as<V>();
+    p.st = h->st.as<InstState>();
+    p.seg = h->cseg.as<V>();
+    p.seg64 = h->cseg64.as<double>();
+    p.rhs64 = h->c64.as<double>();
+    p.lo64 = h->l64.as<double>();
+    p.hi64 = h->u64.as<double>();
+    p.d64 = h->dc64.as<double>();
+    p.part = h->cpart.as<double>();
+    p.lpart = h->lcpart.as<double>();
+    return p;
+}
+
+void upload_plan(scylla_batch *h, bool row)
+{
+    TilePlan &pl = row ? h->prow : h->pcol;
+    const size_t vb = (size_t)h->vbytes;
+    upload(row ? h->rtiles : h->ctiles, pl.tiles, h->stream);
+    upload(row ? h->rlongs : h->clongs, pl.longs, h->stream);
+    (row ? h->rseg : h->cseg).alloc(std::max<size_t>(1, pl.nslots) * vb);
+    (row ? h->rseg64 : h->cseg64).alloc(std::max<size_t>(1, pl.nslots) * 8);
+    (row ? h->rpart : h->cpart).alloc(std::max<size_t>(1, pl.tiles.size() / 4) * 4 * 8);
+    (row ? h->lrpart : h->lcpart).alloc(std::max<size_t>(1, pl.longs.size() / 4) * 4 * 8);
+}
+
+void make_plan(scylla_batch *h, bool row, int32_t ept)
+{
+    const int32_t chunk = 256 * ept;
+    if (row) {
+        plan_tiles(h->csr_ptr_h, h->row_off, chunk, 1024, h->prow);
+        h->ept_row = ept;
+    } else {
+        plan_tiles(h->csc_ptr_h, h->col_off, chunk, 1024, h->pcol);
+        h->ept_col = ept;
+    }
+}
+
+void refresh_info(scylla_batch *h)
+{
+    h->hinfo.resize(h->count);
+    for (int32_t q = 0; q < h->count; ++q) {
+        InstInfo &I = h->hinfo[q];
+        I.row0 = h->row_off[q];
+        I.row1 = h->row_off[q + 1];
+        I.col0 = h->col_off[q];
+        I.col1 = h->col_off[q + 1];
+        I.rt0 = h->prow.t_begin[q];
+        I.rt1 = h->prow.t_end[q];
+        I.ct0 = h->pcol.t_begin[q];
+        I.ct1 = h->pcol.t_end[q];
+        I.lr0 = h->prow.l_begin[q];
+        I.lr1 = h->prow.l_end[q];
+        I.lc0 = h->pcol.l_begin[q];
+        I.lc1 = h->pcol.l_end[q];
+    }
+    upload(h->info, h->hinfo, h->stream);
+}
+
+void invalidate_graph(scylla_batch *h)
+{
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->graph_R = 0;
+}
+
+template <class V>
+void enqueue_window(scylla_batch *h, int32_t R, hipStream_t s)
+{
+    const PassArgs<V> rc = row_args<V>(h, true), cc = col_args<V>(h, true);
+    launch_pass<V>(rc, h->fmt, DIR_ROW, h->ept_row, 0, true, s);
+    launch_pass<V>(cc, h->fmt, DIR_COL, h->ept_col, 0, true, s);
+    DecideArgs d{h->st.as<InstState>(), h->info.as<InstInfo>(), h->rpart.as<double>(),
+                 h->lrpart.as<double>(), h->cpart.as<double>(), h->lcpart.as<double>(), R};
+    launch_decide(d, h->count, s);
+    const PassArgs<V> ri = row_args<V>(h, false), ci = col_args<V>(h, false);
+    for (int32_t j = 0; j < R; ++j) {
+        launch_pass<V>(ci, h->fmt, DIR_COL, h->ept_col, j, false, s);
+        launch_pass<V>(ri, h->fmt, DIR_ROW, h->ept_row, j, false, s);
+    }
+}
+
+void ensure_graph(scylla_batch *h, int32_t R)
+{
+    if (h->gexec && h->graph_R == R) return;
+    invalidate_graph(h);
+    hipGraph_t g = nullptr;
+    HIPC(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    if (h->vbytes == 4) enqueue_window<float>(h, R, h->cap);
+    else enqueue_window<double>(h, R, h->cap);
+    HIPC(hipStreamEndCapture(h->cap, &g));
+    hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPC(e);
+    h->graph_R = R;
+}
+
+// Scratch outputs and an always-running state so a pass can be launched on
+// its own without changing the iterates (autotuning and pass timing).  The
+// gathered vectors are the real ones, so cache behaviour is representative.
+template <class V>
+struct PassTimer {
+    DevMem trial_st, sx, sbar, sy;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    scylla_batch *h;
+    explicit PassTimer(scylla_batch *hh) : h(hh)
+    {
+        std::vector<InstState> ts(h->count);
+        for (auto &S : ts) {
+            memset(&S, 0, sizeof(S));
+            S.status = ST_RUN;
+            S.nrun = 1 << 30;
+        }
+        upload(trial_st, ts, h->stream);
+        sx.alloc((size_t)std::max(h->N, 1) * sizeof(V));
+        sbar.alloc((size_t)std::max(h->N, 1) * sizeof(V));
+        sy.alloc((size_t)std::max(h->M, 1) * sizeof(V));
+        HIPC(hipMemsetAsync(sx.p, 0, sx.bytes, h->stream));
+        HIPC(hipMemsetAsync(sbar.p, 0, sbar.bytes, h->stream));
+        HIPC(hipMemsetAsync(sy.p, 0, sy.bytes, h->stream));
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        HIPC(hipStreamSynchronize(h->stream));
+    }
+    ~PassTimer()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    // average milliseconds of one launch of the row (row = true) or column pass
+    double time(bool row, int reps)
+    {
+        PassArgs<V> p = row ? row_args<V>(h, false) : col_args<V>(h, false);
+        p.st = trial_st.as<InstState>();
+        p.own = row ? sy.as<V>() : sx.as<V>();
+        p.bar = sbar.as<V>();
+        const int ept = row ? h->ept_row : h->ept_col;
+        const int dir = row ? DIR_ROW : DIR_COL;
+        launch_pass<V>(p, h->fmt, dir, ept, 1, false, h->stream);
+        HIPC(hipEventRecord(e0, h->stream));
+        for (int r = 0; r < reps; ++r) launch_pass<V>(p, h->fmt, dir, ept, 1, false, h->stream);
+        HIPC(hipEventRecord(e1, h->stream));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        return (double)ms / reps;
+    }
+};
+
+// Times the candidate tile sizes of each pass and keeps the fastest.
+template <class V>
+void autotune(scylla_batch *h)
+{
+    const int cands[3] = {4, 8, 16};
+    PassTimer<V> timer(h);
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool row = dir == 0;
+        double best = 1e30;
+        int best_ept = 8;
+        for (int ept : cands) {
+            make_plan(h, row, ept);
+            upload_plan(h, row);
+            const double ms = timer.time(row, 10);
+            if (ms < best) {
+                best = ms;
+                best_ept = ept;
+            }
+        }
+        make_plan(h, row, best_ept);
+        upload_plan(h, row);
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+    refresh_info(h);
+    invalidate_graph(h);
+    h->tuned = true;
+}
+
+template <class V>
+void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOrient &csc)
+{
+    hipStream_t s = h->stream;
+    const int32_t M = h->M, N = h->N;
+    // matrix
+    upload(h->csr_ptr, csr.ptr, s);
+    upload(h->csr_ent, csr.ent, s);
+    upload(h->csc_ptr, csc.ptr, s);
+    upload(h->csc_ent, csc.ent, s);
+    if (h->fmt == FMT_BF16) {
+        upload(h->csr_val, csr.v16, s);
+        upload(h->csc_val, csc.v16, s);
+    } else if (h->fmt == FMT_F32) {
+        upload(h->csr_val, csr.v32, s);
+        upload(h->csc_val, csc.v32, s);
+    } else if (h->fmt == FMT_F64) {
+        upload(h->csr_val, csr.v64, s);
+        upload(h->csc_val, csc.v64, s);
+    }
+    h->csr = MatView{h->csr_ptr.as<int32_t>(), h->csr_ent.as<uint32_t>(), h->csr_val.p, csr.shift, csr.mask};
+    h->csc = MatView{h->csc_ptr.as<int32_t>(), h->csc_ent.as<uint32_t>(), h->csc_val.p, csc.shift, csc.mask};
+    h->csr_ptr_h.swap(csr.ptr);
+    h->csc_ptr_h.swap(csc.ptr);
+    // FP64 problem vectors (concatenated)
+    std::vector<double> c(N), l(N), u(N), b(M);
+    std::vector<uint8_t> sn(M);
+    for (int32_t q = 0; q < h->count; ++q) {
+        const scylla_lp &lp = lps[q];
+        memcpy(c.data() + h->col_off[q], lp.c, sizeof(double) * lp.A.n);
+        memcpy(l.data() + h->col_off[q], lp.l, sizeof(double) * lp.A.n);
+        memcpy(u.data() + h->col_off[q], lp.u, sizeof(double) * lp.A.n);
+        if (lp.A.m > 0) {
+            memcpy(b.data() + h->row_off[q], lp.b, sizeof(double) * lp.A.m);
+            memcpy(sn.data() + h->row_off[q], lp.senses, lp.A.m);
+        }
+    }
+    upload(h->c64, c, s);
+    upload(h->corig64, c, s);
+    upload(h->l64, l, s);
+    upload(h->u64, u, s);
+    upload(h->b64, b, s);
+    upload(h->sense, sn, s);
+    const size_t vb = sizeof(V);
+    for (DevMem *d : {&h->x, &h->xbar, &h->xr, &h->cv, &h->lv, &h->uv, &h->dc2}) d->alloc((size_t)N * vb);
+    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2}) d->alloc((size_t)M * vb);
+    for (DevMem *d : {&h->x, &h->xbar, &h->xr}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
+    for (DevMem *d : {&h->y, &h->yr}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
+    launch_cast<V>(h->c64.as<double>(), h->cv.as<V>(), N, s);
+    launch_cast<V>(h->l64.as<double>(), h->lv.as<V>(), N, s);
+    launch_cast<V>(h->u64.as<double>(), h->uv.as<V>(), N, s);
+    launch_cast<V>(h->b64.as<double>(), h->b_v.as<V>(), M, s);
+    // preconditioner: 10 Ruiz rounds (infinity norm) + one Pock-Chambolle
+    // round (alpha = 1), FP64; A itself stays unscaled
+    std::vector<double> ones_m(M, 1.0), ones_n(N, 1.0);
+    upload(h->dr64, ones_m, s);
+    upload(h->dc64, ones_n, s);
+    DevMem rt, ct;
+    rt.alloc((size_t)std::max(M, 1) * 8);
+    ct.alloc((size_t)std::max(N, 1) * 8);
+    for (int it = 0; it < 11; ++it) {
+        const int mode = it < 10 ? 0 : 1;
+        launch_scale_reduce(h->csr, h->fmt, M, h->dr64.as<double>(), h->dc64.as<double>(), rt.as<double>(), mode, s);
+        launch_scale_reduce(h->csc, h->fmt, N, h->dc64.as<double>(), h->dr64.as<double>(), ct.as<double>(), mode, s);
+        launch_scale_apply(h->dr64.as<double>(), rt.as<double>(), M, s);
+        launch_scale_apply(h->dc64.as<double>(), ct.as<double>(), N, s);
+    }
+    launch_finish_diag<V>(h->dr64.as<double>(), h->dr2.as<V>(), M, s);
+    launch_finish_diag<V>(h->dc64.as<double>(), h->dc2.as<V>(), N, s);
+    // states and norms
+    std::vector<InstState> st(h->count);
+    memset(st.data(), 0, sizeof(InstState) * st.size());
+    for (auto &S : st) S.status = ST_ITER;  // idle until the first solve
+    upload(h->st, st, s);
+    make_plan(h, true, 8);
+    make_plan(h, false, 8);
+    upload_plan(h, true);
+    upload_plan(h, false);
+    refresh_info(h);
+    launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
+                      h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), s);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+}
+
+int fail_code(const Err &e)
+{
+    g_err = e.msg;
+    return e.code;
+}
+
+template <class F>
+int guarded(F &&f)
+{
+    try {
+        g_err.clear();
+        return f();
+    } catch (const Err &e) {
+        return fail_code(e);
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return -ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return -EIO;
+    } catch (...) {
+        g_err = "unknown error";
+        return -EIO;
+    }
+}
+
+int validate_params(const scylla_params *p)
+{
+    if (!p) throw_err(-EINVAL, "params is NULL");
+    if (!(p->tol > 0.0) && !(p->tol <= 0.0)) throw_err(-EINVAL, "tol is NaN");
+    if (p->iter_limit < 0) throw_err(-EINVAL, "iter_limit < 0");
+    if (p->check_period < 1 || p->check_period > 1024) throw_err(-EINVAL, "check_period must be in [1, 1024]");
+    if (!(p->eta > 0.0 && p->eta < 1.0)) throw_err(-EINVAL, "eta must be in (0, 1)");
+    if (p->precision != SCYLLA_FP32 && p->precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
+    return 0;
+}
+
+void check_inst(scylla_batch *h, int32_t inst)
+{
+    if (!h) throw_err(-EINVAL, "handle is NULL");
+    if (inst < 0 || inst >= h->count) throw_err(-EINVAL, "instance index out of range");
+}
+
+template <class V>
+void project_start(scylla_batch *h, int32_t inst, int zero)
+{
+    const int clo = inst < 0 ? 0 : h->col_off[inst], chi = inst < 0 ? h->N : h->col_off[inst + 1];
+    const int rlo = inst < 0 ? 0 : h->row_off[inst], rhi = inst < 0 ? h->M : h->row_off[inst + 1];
+    launch_project<V>(h->x.as<V>(), h->lv.as<V>(), h->uv.as<V>(), clo, chi, h->y.as<V>(),
+                      h->sense.as<uint8_t>(), rlo, rhi, zero, h->stream);
+}
+
+void read_states(scylla_batch *h, std::vector<InstState> &out)
+{
+    out.resize(h->count);
+    HIPC(hipMemcpyAsync(out.data(), h->st.p, sizeof(InstState) * h->count, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+}
+
+void fill_result(const InstState &S, scylla_result &r, double solve_s, double setup_s)
+{
+    memset(&r, 0, sizeof(r));
+    r.status = S.status;
+    r.restarts = S.restarts;
+    r.iterations = S.k;
+    r.rel_kkt = S.rel;
+    r.rho_primal = S.rho_p;
+    r.rho_dual = S.rho_d;
+    r.rho_gap = S.rho_g;
+    r.primal_obj = S.pobj;
+    r.dual_obj = S.dobj;
+    r.omega = S.omega;
+    r.solve_seconds = solve_s;
+    r.setup_seconds = setup_s;
+}
+
+int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results)
+{
+    if (!h || !results) throw_err(-EINVAL, "handle or results is NULL");
+    validate_params(p);
+    if (p->precision != h->precision) throw_err(-EINVAL, "params precision differs from the handle's");
+    if (p->autotune && !h->tuned) {
+        if (h->vbytes == 4) autotune<float>(h);
+        else autotune<double>(h);
+    }
+    std::vector<InstState> st;
+    read_states(h, st);
+    for (auto &S : st) {
+        const double omega = (warm && S.omega > 0.0) ? S.omega : S.omega0;
+        S.status = ST_RUN;
+        S.nrun = 0;
+        S.restarts = 0;
+        S.restart_now = 0;
+        S.restart_on = p->restarts ? 1 : 0;
+        S.force_stop = 0;
+        S.k = 0;
+        S.k_limit = p->iter_limit;
+        S.kr = 0;
+        S.omega = omega;
+        S.eta = p->eta;
+        S.t = p->eta / omega;
+        S.s = p->eta * omega;
+        S.tol = p->tol;
+        S.Er = S.Ep = 0.0;
+        S.rel = S.rho_p = S.rho_d = S.rho_g = S.pobj = S.dobj = 0.0;
+    }
+    if (h->vbytes == 4) project_start<float>(h, -1, warm ? 0 : 1);
+    else project_start<double>(h, -1, warm ? 0 : 1);
+    HIPC(hipMemcpyAsync(h->st.p, st.data(), sizeof(InstState) * h->count, hipMemcpyHostToDevice, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    ensure_graph(h, p->check_period);
+
+    const size_t sb = sizeof(InstState) * (size_t)h->count;
+    const double t0 = now_s();
+    int64_t next = 0, insp = 0;
+    bool done = false, forced = false;
+    int64_t last_slot = 0;
+    for (;;) {
+        while (!done && next - insp < 2) {
+            const int slot = (int)(next & 1);
+            HIPC(hipGraphLaunch(h->gexec, h->stream));
+            HIPC(hipMemcpyAsync(h->pinned + (size_t)slot * h->count, h->st.p, sb, hipMemcpyDeviceToHost, h->stream));
+            HIPC(hipEventRecord(h->ev[slot], h->stream));
+            ++next;
+        }
+        if (insp == next) break;
+        const int slot = (int)(insp & 1);
+        HIPC(hipEventSynchronize(h->ev[slot]));
+        last_slot = slot;
+        ++insp;
+        bool running = false;
+        for (int32_t q = 0; q < h->count; ++q)
+            if (h->pinned[(size_t)slot * h->count + q].status == ST_RUN) running = true;
+        if (!running) {
+            done = true;
+        } else if (!forced && p->time_limit_s > 0.0 && now_s() - t0 > p->time_limit_s) {
+            launch_force_stop(h->st.as<InstState>(), h->count, h->stream);
+            HIPC(hipGetLastError());
+            forced = true;
+        }
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+    const double solve_s = now_s() - t0;
+    for (int32_t q = 0; q < h->count; ++q)
+        fill_result(h->pinned[(size_t)last_slot * h->count + q], results[q], solve_s, h->setup_seconds);
+    return 0;
+}
+
+template <class V>
+void get_range(scylla_batch *h, const DevMem &d, int32_t lo, int32_t len, double *out)
+{
+    if (len <= 0 || !out) return;
+    if (sizeof(V) == 8) {
+        HIPC(hipMemcpyAsync(out, d.as<char>() + (size_t)lo * 8, (size_t)len * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> tmp(len);
+        HIPC(hipMemcpyAsync(tmp.data(), d.as<char>() + (size_t)lo * 4, (size_t)len * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+        for (int32_t i = 0; i < len; ++i) out[i] = (double)tmp[i];
+    }
+}
+
+template <class V>
+void put_range(scylla_batch *h, DevMem &d, int32_t lo, int32_t len, const double *in)
+{
+    if (len <= 0) return;
+    if (sizeof(V) == 8) {
+        HIPC(hipMemcpyAsync(d.as<char>() + (size_t)lo * 8, in, (size_t)len * 8, hipMemcpyHostToDevice, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> tmp(len);
+        for (int32_t i = 0; i < len; ++i) tmp[i] = (float)in[i];
+        HIPC(hipMemcpyAsync(d.as<char>() + (size_t)lo * 4, tmp.data(), (size_t)len * 4, hipMemcpyHostToDevice, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+    }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int scylla_params_default(scylla_params *p)
+{
+    if (!p) {
+        g_err = "params is NULL";
+        return -EINVAL;
+    }
+    p->tol = 1e-4;
+    p->iter_limit = 100000;
+    p->precision = SCYLLA_FP32;
+    p->check_period = 64;
+    p->restarts = 1;
+    p->autotune = 1;
+    p->eta = 0.99;
+    p->time_limit_s = 0.0;
+    return 0;
+}
+
+const char *scylla_last_error(void) { return g_err.c_str(); }
+
+int scylla_validate_lp(const scylla_lp *lp)
+{
+    return guarded([&]() {
+        std::string err;
+        int rc = validate_lp(lp, err);
+        if (rc) throw_err(rc, err);
+        return 0;
+    });
+}
+
+int scylla_batch_create(const scylla_lp *lps, int32_t count, int32_t precision, void *hip_stream,
+                        scylla_batch **out)
+{
+    return guarded([&]() {
+        if (!out) throw_err(-EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!lps || count < 1) throw_err(-EINVAL, "need at least one LP");
+        if (precision != SCYLLA_FP32 && precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
+        std::string err;
+        for (int32_t q = 0; q < count; ++q) {
+            int rc = validate_lp(&lps[q], err);
+            if (rc) throw_err(rc, "instance " + std::to_string(q) + ": " + err);
+        }
+        const double t0 = now_s();
+        auto h = std::make_unique<scylla_batch>();
+        h->count = count;
+        h->precision = precision;
+        h->vbytes = precision == SCYLLA_FP32 ? 4 : 8;
+        HostOrient csr, csc;
+        int32_t fmt = 0;
+        int rc = build_orientations(lps, count, precision, csr, csc, fmt, h->row_off, h->col_off, err);
+        if (rc) throw_err(rc, err);
+        h->fmt = fmt;
+        h->M = csr.rows;
+        h->N = csc.rows;
+        h->NNZ = (int64_t)csr.ent.size();
+        check_device();
+        if (hip_stream) {
+            h->stream = (hipStream_t)hip_stream;
+        } else {
+            HIPC(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            h->own_stream = true;
+        }
+        HIPC(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIPC(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
+        HIPC(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
+        HIPC(hipHostMalloc((void **)&h->pinned, sizeof(InstState) * 2 * (size_t)count, hipHostMallocDefault));
+        if (h->vbytes == 4) setup_device<float>(h.get(), lps, csr, csc);
+        else setup_device<double>(h.get(), lps, csr, csc);
+        h->setup_seconds = now_s() - t0;
+        *out = h.release();
+        return 0;
+    });
+}
+
+void scylla_batch_destroy(scylla_batch *h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+int scylla_batch_set_objective(scylla_batch *h, int32_t inst, const double *c_hat)
+{
+    return guarded([&]() {
+        check_inst(h, inst);
+        if (!c_hat) throw_err(-EINVAL, "c_hat is NULL");
+        const int32_t lo = h->col_off[inst], len = h->col_off[inst + 1] - lo;
+        for (int32_t j = 0; j < len; ++j)
+            if (!isfinite(c_hat[j])) throw_err(-EINVAL, "non-finite objective");
+        HIPC(hipMemcpyAsync(h->c64.as<double>() + lo, c_hat, sizeof(double) * len, hipMemcpyHostToDevice, h->stream));
+        if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>(), h->cv.as<float>(), h->N, h->stream);
+        else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), h->N, h->stream);
+        launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
+                          h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(h->stream));
+        return 0;
+    });
+}
+
+int scylla_batch_set_blend(scylla_batch *h, int32_t inst, const uint8_t *xhat_bits, const uint8_t *int_bits,
+                           double a, double kappa)
+{
+    return guarded([&]() {
+        check_inst(h, inst);
+        if (!xhat_bits) throw_err(-EINVAL, "xhat_bits is NULL");
+        if (!isfinite(a) || !isfinite(kappa)) throw_err(-EINVAL, "a and kappa must be finite");
+        const int32_t lo = h->col_off[inst], hi = h->col_off[inst + 1];
+        const size_t nb = (size_t)(hi - lo + 7) / 8;
+        if (h->bits_tmp.bytes < nb) h->bits_tmp.alloc(nb);
+        if (int_bits && h->ibits_tmp.bytes < nb) h->ibits_tmp.alloc(nb);
+        HIPC(hipMemcpyAsync(h->bits_tmp.p, xhat_bits, nb, hipMemcpyHostToDevice, h->stream));
+        if (int_bits) HIPC(hipMemcpyAsync(h->ibits_tmp.p, int_bits, nb, hipMemcpyHostToDevice, h->stream));
+        const uint8_t *ib = int_bits ? h->ibits_tmp.as<uint8_t>() : nullptr;
+        if (h->vbytes == 4)
+            launch_blend<float>(h->corig64.as<double>(), h->bits_tmp.as<uint8_t>(), ib, a, kappa,
+                                h->c64.as<double>(), h->cv.as<float>(), lo, hi, h->stream);
+        else
+            launch_blend<double>(h->corig64.as<double>(), h->bits_tmp.as<uint8_t>(), ib, a, kappa,
+                                 h->c64.as<double>(), h->cv.as<double>(), lo, hi, h->stream);
+        launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
+                          h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(h->stream));
+        return 0;
+    });
+}
+
+int scylla_batch_set_start(scylla_batch *h, int32_t inst, const double *x0, const double *y0, double omega0)
+{
+    return guarded([&]() {
+        check_inst(h, inst);
+        const int32_t clo = h->col_off[inst], clen = h->col_off[inst + 1] - clo;
+        const int32_t rlo = h->row_off[inst], rlen = h->row_off[inst + 1] - rlo;
+        if (x0)
+            for (int32_t j = 0; j < clen; ++j)
+                if (isnan(x0[j])) throw_err(-EINVAL, "NaN in x0");
+        if (y0)
+            for (int32_t i = 0; i < rlen; ++i)
+                if (!isfinite(y0[i])) throw_err(-EINVAL, "non-finite y0");
+        if (h->vbytes == 4) {
+            if (x0) put_range<float>(h, h->x, clo, clen, x0);
+            if (y0) put_range<float>(h, h->y, rlo, rlen, y0);
+            project_start<float>(h, inst, 0);
+        } else {
+            if (x0) put_range<double>(h, h->x, clo, clen, x0);
+            if (y0) put_range<double>(h, h->y, rlo, rlen, y0);
+            project_start<double>(h, inst, 0);
+        }
+        if (omega0 > 0.0) {
+            std::vector<InstState> st;
+            read_states(h, st);
+            st[inst].omega = omega0;
+            HIPC(hipMemcpyAsync(h->st.as<InstState>() + inst, &st[inst], sizeof(InstState), hipMemcpyHostToDevice,
+                                h->stream));
+        }
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(h->stream));
+        return 0;
+    });
+}
+
+int scylla_batch_solve(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results)
+{
+    return guarded([&]() { return batch_solve_impl(h, p, warm, results); });
+}
+
+int scylla_batch_get_solution(scylla_batch *h, int32_t inst, double *x, double *y)
+{
+    return guarded([&]() {
+        check_inst(h, inst);
+        const int32_t clo = h->col_off[inst], clen = h->col_off[inst + 1] - clo;
+        const int32_t rlo = h->row_off[inst], rlen = h->row_off[inst + 1] - rlo;
+        if (h->vbytes == 4) {
+            get_range<float>(h, h->x, clo, clen, x);
+            get_range<float>(h, h->y, rlo, rlen, y);
+        } else {
+            get_range<double>(h, h->x, clo, clen, x);
+            get_range<double>(h, h->y, rlo, rlen, y);
+        }
+        return 0;
+    });
+}
+
+int scylla_batch_get_x_all(scylla_batch *h, double *x_all)
+{
+    return guarded([&]() {
+        if (!h || !x_all) throw_err(-EINVAL, "handle or x_all is NULL");
+        if (h->vbytes == 4) get_range<float>(h, h->x, 0, h->N, x_all);
+        else get_range<double>(h, h->x, 0, h->N, x_all);
+        return 0;
+    });
+}
+
+int scylla_batch_device_iterates(scylla_batch *h, void **x, void **y, int32_t *elem_bytes)
+{
+    return guarded([&]() {
+        if (!h || !x || !y || !elem_bytes) throw_err(-EINVAL, "NULL argument");
+        *x = h->x.p;
+        *y = h->y.p;
+        *elem_bytes = h->vbytes;
+        return 0;
+    });
+}
+
+int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
+{
+    return guarded([&]() {
+        if (!h || !info) throw_err(-EINVAL, "NULL argument");
+        memset(info, 0, sizeof(*info));
+        info->count = h->count;
+        info->precision = h->precision;
+        info->format = h->fmt;
+        info->m_total = h->M;
+        info->n_total = h->N;
+        info->nnz_total = h->NNZ;
+        info->row_chunk = h->prow.chunk;
+        info->col_chunk = h->pcol.chunk;
+        info->long_rows = (int32_t)(h->prow.longs.size() / 4);
+        info->long_cols = (int32_t)(h->pcol.longs.size() / 4);
+        return 0;
+    });
+}
+
+int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, double *ms_col)
+{
+    return guarded([&]() {
+        if (!h || !ms_row || !ms_col || reps < 1) throw_err(-EINVAL, "bad argument");
+        HIPC(hipStreamSynchronize(h->stream));
+        if (h->vbytes == 4) {
+            PassTimer<float> t(h);
+            *ms_row = t.time(true, reps);
+            *ms_col = t.time(false, reps);
+        } else {
+            PassTimer<double> t(h);
+            *ms_row = t.time(true, reps);
+            *ms_col = t.time(false, reps);
+        }
+        HIPC(hipStreamSynchronize(h->stream));
+        return 0;
+    });
+}
+
+int scylla_pdhg_solve(const scylla_csr *A, const double *c, const double *b, const char *senses, const double *l,
+                      const double *u, const scylla_params *p, const double *x0, const double *y0, double *x_out,
+                      double *y_out, scylla_result *res)
+{
+    return guarded([&]() {
+        if (!A || !res || !x_out || (A->m > 0 && !y_out)) throw_err(-EINVAL, "NULL argument");
+        validate_params(p);
+        scylla_lp lp{*A, c, b, senses, l, u};
+        std::string err;
+        int rc = validate_lp(&lp, err);
+        if (rc) throw_err(rc, err);
+        scylla_batch *h = nullptr;
+        rc = scylla_batch_create(&lp, 1, p->precision, nullptr, &h);
+        if (rc) return rc;
+        std::unique_ptr<scylla_batch, void (*)(scylla_batch *)> guard(h, scylla_batch_destroy);
+        const bool warm = x0 || y0;
+        if (warm) {
+            rc = scylla_batch_set_start(h, 0, x0, y0, 0.0);
+            if (rc) return rc;
+        }
+        scylla_result r;
+        rc = scylla_batch_solve(h, p, warm ? 1 : 0, &r);
+        if (rc) return rc;
+        rc = scylla_batch_get_solution(h, 0, x_out, y_out);
+        if (rc) return rc;
+        *res = r;
+        return 0;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations shared by the host preparation, the kernels and the
+// runtime of the PDHG library.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/scylla_pdhg.h"
+
+namespace scy {
+
+// Matrix storage formats (per handle and orientation).
+enum Fmt : int32_t {
+    FMT_PACKED = 0,  // 32-bit word: index in the low `shift` bits, signed
+                     // integer value in the high bits (0/1 and small-integer
+                     // matrices: 4 bytes per nonzero, exact)
+    FMT_BF16 = 1,    // int32 index + bfloat16 value (every value BF16-exact)
+    FMT_F32 = 2,     // int32 index + float value
+    FMT_F64 = 3      // int32 index + double value (FP64 path)
+};
+
+enum Status : int32_t { ST_RUN = 0, ST_OPT = 1, ST_ITER = 2, ST_TIME = 3, ST_NUM = 4 };
+
+// Per-instance solver state, resident in device memory and updated only by
+// the decision kernel (one writer per instance).
+struct InstState {
+    int32_t status;       // Status
+    int32_t nrun;         // iterations to run in the current window
+    int32_t restarts;     // restarts taken in this call
+    int32_t restart_now;  // 1: copy (x, y) to the restart reference in the
+                          //    first iteration of the window
+    int32_t restart_on;   // restart scheme enabled
+    int32_t force_stop;   // host-requested stop (time limit)
+    int32_t pad0, pad1;
+    int64_t k;            // iterations done at the last check
+    int64_t k_limit;      // iteration limit of this call
+    int64_t kr;           // iteration of the last restart
+    int64_t pad2;
+    double t, s;          // primal / dual step (eta / omega, eta * omega)
+    double omega, eta;
+    double tol;
+    double Er, Ep;        // KKT error at the last restart / previous check
+    double rel, rho_p, rho_d, rho_g, pobj, dobj;
+    double bnorm, cnorm;  // ||b||_2, ||c_hat||_2 of the instance
+    double omega0;        // primal weight from the data (cold start)
+};
+
+// Static per-instance ranges in the concatenated arrays.
+struct InstInfo {
+    int32_t row0, row1, col0, col1;  // row / column ranges
+    int32_t rt0, rt1, ct0, ct1;      // CSR / CSC tile ranges
+    int32_t lr0, lr1, lc0, lc1;      // long-row / long-column ranges
+};
+
+// Tile of an orientation: {a, b, inst, slot}.  slot < 0: rows [a, b);
+// slot >= 0: nonzeros [a, b) of one long row, partial sum goes to slot.
+// Long row descriptor: {row, first slot, number of segments, inst}.
+
+// ----------------------------------------------------------- host side
+struct HostOrient {
+    int32_t rows = 0;
+    std::vector<int32_t> ptr;    // [rows + 1]
+    std::vector<uint32_t> ent;   // index or packed word
+    std::vector<uint16_t> v16;   // BF16 values
+    std::vector<float> v32;      // FP32 values
+    std::vector<double> v64;     // FP64 values
+    int32_t shift = 0;           // packed: value bits start here
+    uint32_t mask = 0xffffffffu; // packed: index mask
+};
+
+struct TilePlan {
+    int32_t chunk = 0;                 // nonzeros per tile (NT * EPT)
+    std::vector<int32_t> tiles;        // 4 ints per tile
+    std::vector<int32_t> longs;        // 4 ints per long row
+    int32_t nslots = 0;                // segment partial slots
+    std::vector<int32_t> t_begin, t_end, l_begin, l_end;  // per instance
+};
+
+// Validation of one LP description (no GPU).  Returns 0 or -EINVAL.
+int validate_lp(const scylla_lp *lp, std::string &err);
+
+// Concatenates `count` LPs into one block-diagonal CSR and its CSC copy,
+// choosing the storage format (FMT_F64 for the FP64 path; for FP32 the most
+// compact exact one).  Row/column offsets per instance are returned.
+int build_orientations(const scylla_lp *lps, int32_t count, int32_t precision, HostOrient &csr,
+                       HostOrient &csc, int32_t &fmt, std::vector<int32_t> &row_off,
+                       std::vector<int32_t> &col_off, std::string &err);
+
+// Splits the rows of an orientation into tiles of at most `chunk` nonzeros
+// and at most `max_rows` rows; rows longer than `chunk` become long rows cut
+// into `chunk`-sized segments.  Tiles never straddle instances.
+void plan_tiles(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
+                int32_t chunk, int32_t max_rows, TilePlan &plan);
+
+uint16_t f64_to_bf16_exact(double v, bool &exact);
+
+}  // namespace scy

@@ -1,0 +1,260 @@
+"""Thin Python binding of the HIP PDHG library (libscylla_pdhg.so).
+
+Argument marshalling only: every step of the solve runs in the library's
+kernels.  Names follow the C ABI in include/scylla_pdhg.h.  The binding
+raises if the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscylla_pdhg.so")
+
+FP64, FP32 = 0, 1
+RUNNING, OPTIMAL, ITERATION_LIMIT, TIME_LIMIT, NUMERICAL_ERROR = 0, 1, 2, 3, 4
+FORMATS = {0: "packed-int", 1: "bf16", 2: "fp32", 3: "fp64"}
+
+EXPORTS = [
+    "scylla_params_default", "scylla_last_error", "scylla_validate_lp", "scylla_pdhg_solve",
+    "scylla_batch_create", "scylla_batch_destroy", "scylla_batch_set_objective",
+    "scylla_batch_set_blend", "scylla_batch_set_start", "scylla_batch_solve",
+    "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
+    "scylla_batch_get_info", "scylla_batch_time_passes",
+]
+
+
+class ScyllaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"scylla error {code}: {msg}")
+        self.code = code
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class LPDesc(ctypes.Structure):
+    _fields_ = [("A", CSR), ("c", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("senses", ctypes.c_void_p), ("l", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("iter_limit", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("check_period", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("iterations", ctypes.c_int64), ("rel_kkt", ctypes.c_double),
+                ("rho_primal", ctypes.c_double), ("rho_dual", ctypes.c_double),
+                ("rho_gap", ctypes.c_double), ("primal_obj", ctypes.c_double),
+                ("dual_obj", ctypes.c_double), ("omega", ctypes.c_double),
+                ("solve_seconds", ctypes.c_double), ("setup_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("format", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("m_total", ctypes.c_int64), ("n_total", ctypes.c_int64),
+                ("nnz_total", ctypes.c_int64), ("row_chunk", ctypes.c_int32),
+                ("col_chunk", ctypes.c_int32), ("long_rows", ctypes.c_int32),
+                ("long_cols", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads the built library (raises if it is missing: no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "scylla_params_default": ([ctypes.POINTER(Params)], ctypes.c_int),
+            "scylla_last_error": ([], ctypes.c_char_p),
+            "scylla_validate_lp": ([ctypes.POINTER(LPDesc)], ctypes.c_int),
+            "scylla_pdhg_solve": ([ctypes.POINTER(CSR), vp, vp, vp, vp, vp, ctypes.POINTER(Params),
+                                   vp, vp, vp, vp, ctypes.POINTER(Result)], ctypes.c_int),
+            "scylla_batch_create": ([ctypes.POINTER(LPDesc), i32, i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
+            "scylla_batch_destroy": ([vp], None),
+            "scylla_batch_set_objective": ([vp, i32, vp], ctypes.c_int),
+            "scylla_batch_set_blend": ([vp, i32, vp, vp, dbl, dbl], ctypes.c_int),
+            "scylla_batch_set_start": ([vp, i32, vp, vp, dbl], ctypes.c_int),
+            "scylla_batch_solve": ([vp, ctypes.POINTER(Params), i32, ctypes.POINTER(Result)], ctypes.c_int),
+            "scylla_batch_get_solution": ([vp, i32, vp, vp], ctypes.c_int),
+            "scylla_batch_get_x_all": ([vp, vp], ctypes.c_int),
+            "scylla_batch_device_iterates": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(i32)], ctypes.c_int),
+            "scylla_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
+            "scylla_batch_time_passes": ([vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise ScyllaError(rc, lib().scylla_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def params(**kw) -> Params:
+    p = Params()
+    _check(lib().scylla_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+class _LPArrays:
+    """Contiguous host copies of one LP kept alive for the duration of a call."""
+
+    def __init__(self, lp, c=None):
+        self.row_ptr = np.ascontiguousarray(lp.row_ptr, dtype=np.int64)
+        self.col_idx = np.ascontiguousarray(lp.col_idx, dtype=np.int32)
+        self.val = np.ascontiguousarray(lp.val, dtype=np.float64)
+        self.c = np.ascontiguousarray(lp.c if c is None else c, dtype=np.float64)
+        self.b = np.ascontiguousarray(lp.b, dtype=np.float64)
+        self.senses = np.ascontiguousarray(lp.senses, dtype=np.uint8)
+        self.l = np.ascontiguousarray(lp.l, dtype=np.float64)
+        self.u = np.ascontiguousarray(lp.u, dtype=np.float64)
+        self.csr = CSR(lp.m, lp.n, int(self.row_ptr[-1]) if self.row_ptr.size else 0,
+                       _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.val))
+        self.desc = LPDesc(self.csr, _ptr(self.c), _ptr(self.b), _ptr(self.senses), _ptr(self.l),
+                           _ptr(self.u))
+
+
+def validate(lp) -> None:
+    a = _LPArrays(lp)
+    _check(lib().scylla_validate_lp(ctypes.byref(a.desc)))
+
+
+@dataclass
+class Solution:
+    x: np.ndarray
+    y: np.ndarray
+    result: dict
+
+
+def solve(lp, x0=None, y0=None, **kw) -> Solution:
+    """One-shot solve (scylla_pdhg_solve) of an LP with host arrays."""
+    a = _LPArrays(lp)
+    p = params(**kw)
+    x = np.empty(lp.n)
+    y = np.empty(max(lp.m, 1))
+    x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+    y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+    r = Result()
+    _check(lib().scylla_pdhg_solve(ctypes.byref(a.csr), _ptr(a.c), _ptr(a.b), _ptr(a.senses), _ptr(a.l),
+                                   _ptr(a.u), ctypes.byref(p), _ptr(x0a), _ptr(y0a), _ptr(x), _ptr(y),
+                                   ctypes.byref(r)))
+    return Solution(x, y[: lp.m], r.as_dict())
+
+
+class Batch:
+    """Device-resident batch of LPs (scylla_batch_*)."""
+
+    def __init__(self, lps: Sequence, precision: int = FP32, stream=None):
+        self._arrays = [_LPArrays(lp) for lp in lps]
+        descs = (LPDesc * len(lps))(*[a.desc for a in self._arrays])
+        h = ctypes.c_void_p()
+        s = None if stream is None else ctypes.c_void_p(stream)
+        _check(lib().scylla_batch_create(descs, len(lps), precision, s, ctypes.byref(h)))
+        self._h = h
+        self.count = len(lps)
+        self.precision = precision
+        self.m = [lp.m for lp in lps]
+        self.n = [lp.n for lp in lps]
+        self._arrays = None  # data is on the device now
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().scylla_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        _check(lib().scylla_batch_get_info(self._h, ctypes.byref(inf)))
+        d = {k: getattr(inf, k) for k, _ in inf._fields_}
+        d["format_name"] = FORMATS.get(d["format"], "?")
+        return d
+
+    def solve(self, warm: bool = False, **kw) -> List[dict]:
+        p = params(precision=self.precision, **kw)
+        res = (Result * self.count)()
+        _check(lib().scylla_batch_solve(self._h, ctypes.byref(p), int(warm), res))
+        return [r.as_dict() for r in res]
+
+    def solution(self, inst: int = 0):
+        x = np.empty(self.n[inst])
+        y = np.empty(max(self.m[inst], 1))
+        _check(lib().scylla_batch_get_solution(self._h, inst, _ptr(x), _ptr(y)))
+        return x, y[: self.m[inst]]
+
+    def x_all(self) -> np.ndarray:
+        x = np.empty(sum(self.n))
+        _check(lib().scylla_batch_get_x_all(self._h, _ptr(x)))
+        return x
+
+    def set_objective(self, inst: int, c_hat) -> None:
+        c = np.ascontiguousarray(c_hat, dtype=np.float64)
+        assert c.size == self.n[inst]
+        _check(lib().scylla_batch_set_objective(self._h, inst, _ptr(c)))
+
+    def set_blend(self, inst: int, xhat_up: np.ndarray, a: float, kappa: float, is_int=None) -> None:
+        """xhat_up[j] = True where the rounded value sits at the upper bound."""
+        bits = np.packbits(np.asarray(xhat_up, dtype=bool), bitorder="little")
+        ib = None if is_int is None else np.packbits(np.asarray(is_int, dtype=bool), bitorder="little")
+        _check(lib().scylla_batch_set_blend(self._h, inst, _ptr(bits), _ptr(ib), a, kappa))
+
+    def set_start(self, inst: int, x0=None, y0=None, omega0: float = 0.0) -> None:
+        x = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        y = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+        _check(lib().scylla_batch_set_start(self._h, inst, _ptr(x), _ptr(y), omega0))
+
+    def time_passes(self, reps: int = 20):
+        """Average ms of one launch of the row pass and of the column pass."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().scylla_batch_time_passes(self._h, reps, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def device_iterates(self):
+        x, y, eb = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int32()
+        _check(lib().scylla_batch_device_iterates(self._h, ctypes.byref(x), ctypes.byref(y), ctypes.byref(eb)))
+        return x.value, y.value, eb.value

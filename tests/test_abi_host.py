@@ -1,0 +1,258 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+public header declares, rejects invalid input with -EINVAL before touching
+any GPU, and its host preparation (block-diagonal concatenation, the
+transposed copy, exact compact formats, tile plans) is correct."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2307_03466_amd import instances as I
+from paper_2307_03466_amd import pdhg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+EINVAL = -22
+
+
+def _declared_functions():
+    names = set()
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(scylla_[a-z0-9_]+)\s*\(", txt):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pdhg.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return pdhg.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    declared = _declared_functions()
+    assert declared, "no declarations parsed"
+    assert declared == set(pdhg.EXPORTS), declared ^ set(pdhg.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", pdhg.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(scylla_[a-z0-9_]+)\b", out))
+    missing = declared - exported
+    assert not missing, missing
+
+
+def test_params_default(L):
+    p = pdhg.params()
+    assert p.tol == 1e-4 and p.check_period == 64 and p.eta == 0.99 and p.restarts == 1
+    assert L.scylla_params_default(None) == EINVAL
+
+
+def _bad(lp, **changes):
+    a = pdhg._LPArrays(lp)
+    for k, v in changes.items():
+        setattr(a, k, v)
+    a.csr = pdhg.CSR(lp.m, lp.n, int(a.row_ptr[-1]), pdhg._ptr(a.row_ptr), pdhg._ptr(a.col_idx), pdhg._ptr(a.val))
+    a.desc = pdhg.LPDesc(a.csr, pdhg._ptr(a.c), pdhg._ptr(a.b), pdhg._ptr(a.senses), pdhg._ptr(a.l), pdhg._ptr(a.u))
+    return a
+
+
+@pytest.mark.parametrize("case", ["ok", "col_range", "col_order", "nan_val", "sense", "l_gt_u",
+                                  "inf_lower", "nan_c", "inf_b", "rowptr"])
+def test_validation(L, case):
+    lp = I.workload(1)
+    if case == "ok":
+        a = _bad(lp)
+    elif case == "col_range":
+        ci = lp.col_idx.copy(); ci[5] = lp.n
+        a = _bad(lp, col_idx=ci)
+    elif case == "col_order":
+        ci = lp.col_idx.copy(); s = lp.row_ptr[3]; ci[s], ci[s + 1] = ci[s + 1], ci[s]
+        a = _bad(lp, col_idx=ci)
+    elif case == "nan_val":
+        v = lp.val.copy(); v[7] = np.nan
+        a = _bad(lp, val=v)
+    elif case == "sense":
+        s = lp.senses.copy(); s[2] = ord("X")
+        a = _bad(lp, senses=s)
+    elif case == "l_gt_u":
+        l = lp.l.copy(); l[4] = 2.0
+        a = _bad(lp, l=l)
+    elif case == "inf_lower":
+        l = lp.l.copy(); l[4] = np.inf
+        a = _bad(lp, l=l)
+    elif case == "nan_c":
+        c = lp.c.copy(); c[0] = np.nan
+        a = _bad(lp, c=c)
+    elif case == "inf_b":
+        b = lp.b.copy(); b[0] = np.inf
+        a = _bad(lp, b=b)
+    elif case == "rowptr":
+        rp = lp.row_ptr.copy(); rp[5] = rp[6] + 1
+        a = _bad(lp, row_ptr=rp)
+    rc = L.scylla_validate_lp(ctypes.byref(a.desc))
+    if case == "ok":
+        assert rc == 0
+    else:
+        assert rc == EINVAL and L.scylla_last_error()
+        # the one-shot solve rejects it before any device work and writes nothing
+        x = np.full(lp.n, 7.0)
+        y = np.full(lp.m, 7.0)
+        res = pdhg.Result()
+        rc2 = L.scylla_pdhg_solve(ctypes.byref(a.csr), pdhg._ptr(a.c), pdhg._ptr(a.b), pdhg._ptr(a.senses),
+                                  pdhg._ptr(a.l), pdhg._ptr(a.u), ctypes.byref(pdhg.params()), None, None,
+                                  pdhg._ptr(x), pdhg._ptr(y), ctypes.byref(res))
+        assert rc2 == EINVAL
+        assert np.all(x == 7.0) and np.all(y == 7.0)
+
+
+def test_bad_params_rejected(L):
+    lp = I.workload(1)
+    for kw in (dict(check_period=0), dict(eta=1.5), dict(iter_limit=-1), dict(precision=7)):
+        with pytest.raises(pdhg.ScyllaError) as e:
+            pdhg.solve(lp, **kw)
+        assert e.value.code == EINVAL
+
+
+# ------------------------------------------------------------- host prep
+_DRIVER = None
+
+
+def _driver():
+    global _DRIVER
+    if _DRIVER is None:
+        exe = os.path.join(tempfile.mkdtemp(), "prep_driver")
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-o", exe,
+                               os.path.join(ROOT, "tests", "host", "prep_driver.cpp"),
+                               os.path.join(ROOT, "paper_2307_03466_amd", "csrc", "host_prep.cpp")])
+        _DRIVER = exe
+    return _DRIVER
+
+
+def _run_prep(lps, precision, chunk, max_rows):
+    d = tempfile.mkdtemp()
+    fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
+    with open(fin, "wb") as f:
+        f.write(np.array([len(lps), precision], dtype=np.int32).tobytes())
+        for lp in lps:
+            f.write(np.array([lp.m, lp.n], dtype=np.int32).tobytes())
+            f.write(np.array([lp.nnz], dtype=np.int64).tobytes())
+            for arr, dt in ((lp.row_ptr, np.int64), (lp.col_idx, np.int32), (lp.val, np.float64),
+                            (lp.c, np.float64), (lp.b, np.float64), (lp.senses, np.uint8),
+                            (lp.l, np.float64), (lp.u, np.float64)):
+                f.write(np.ascontiguousarray(arr, dtype=dt).tobytes())
+    subprocess.check_call([_driver(), fin, fout, str(chunk), str(max_rows)])
+    raw = open(fout, "rb").read()
+    pos = 0
+    out = []
+
+    def take(dt):
+        nonlocal pos
+        n = int(np.frombuffer(raw, np.int64, 1, pos)[0])
+        pos += 8
+        a = np.frombuffer(raw, dt, n, pos).copy()
+        pos += n * np.dtype(dt).itemsize
+        return a
+    hdr = take(np.int32)
+    ro, co = take(np.int32), take(np.int32)
+    orient = [dict(ptr=take(np.int32), ent=take(np.uint32), v16=take(np.uint16), v32=take(np.float32),
+                   v64=take(np.float64)) for _ in range(2)]
+    plans = [dict(tiles=take(np.int32).reshape(-1, 4), longs=take(np.int32).reshape(-1, 4),
+                  tb=take(np.int32), te=take(np.int32), lb=take(np.int32), le=take(np.int32)) for _ in range(2)]
+    return hdr, ro, co, orient, plans
+
+
+def _decode(o, hdr, which, fmt):
+    shift, mask = (hdr[1], hdr[2]) if which == 0 else (hdr[3], hdr[4])
+    mask = np.uint32(int(mask) & 0xFFFFFFFF)
+    if fmt == 0:
+        idx = (o["ent"] & mask).astype(np.int64)
+        val = (o["ent"].view(np.int32) >> shift).astype(np.float64)
+    else:
+        idx = o["ent"].astype(np.int64)
+        if fmt == 1:
+            val = (o["v16"].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        elif fmt == 2:
+            val = o["v32"].astype(np.float64)
+        else:
+            val = o["v64"]
+    return idx, val
+
+
+def _block_diag(lps):
+    import scipy.sparse as sps
+    return sps.block_diag([sps.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+                           for lp in lps], format="csr")
+
+
+@pytest.mark.parametrize("kind,precision,expect_fmt", [
+    ("cover_knapsack", 1, 0), ("skewed", 1, 0), ("general", 0, 3), ("bf16", 1, 1), ("real", 1, 2)])
+def test_orientations_and_formats(kind, precision, expect_fmt):
+    rng = np.random.default_rng(0)
+    if kind == "cover_knapsack":
+        lps = I.uneven_batch(count=5, lo=50, hi=400, seed=1)
+    elif kind == "skewed":
+        lps = [I.workload(3, scale=0.001)]
+    elif kind == "general":
+        lps = [I.workload(2, scale=0.0005), I.workload(2, scale=0.0003)]
+    else:
+        lp = I.workload(2, scale=0.0005)
+        lp.val = lp.val * (1000.5 if kind == "bf16" else np.pi)
+        if kind == "bf16":
+            # BF16-exact values too large for the packed integer range
+            lp.val = np.sign(lp.val) * 2.0 ** rng.integers(24, 30, size=lp.val.size)
+        lps = [lp]
+    hdr, ro, co, orient, plans = _run_prep(lps, precision, 256, 64)
+    assert hdr[0] == expect_fmt
+    ref = _block_diag(lps)
+    # CSR
+    idx, val = _decode(orient[0], hdr, 0, hdr[0])
+    np.testing.assert_array_equal(orient[0]["ptr"], ref.indptr)
+    np.testing.assert_array_equal(idx, ref.indices)
+    rnd = (lambda v: v.astype(np.float32).astype(np.float64)) if hdr[0] == 2 else (lambda v: v)
+    np.testing.assert_array_equal(val, rnd(ref.data))
+    # CSC = CSR of the transpose with increasing rows per column
+    refT = ref.T.tocsr()
+    refT.sort_indices()
+    idx, val = _decode(orient[1], hdr, 1, hdr[0])
+    np.testing.assert_array_equal(orient[1]["ptr"], refT.indptr)
+    np.testing.assert_array_equal(idx, refT.indices)
+    np.testing.assert_array_equal(val, rnd(refT.data))
+    np.testing.assert_array_equal(ro, np.cumsum([0] + [lp.m for lp in lps]))
+    np.testing.assert_array_equal(co, np.cumsum([0] + [lp.n for lp in lps]))
+
+
+@pytest.mark.parametrize("chunk,max_rows", [(256, 64), (1024, 1024), (64, 8)])
+def test_tile_plan_covers_every_row_once(chunk, max_rows):
+    lps = [I.workload(3, scale=0.002), I.workload(2, scale=0.0003)]
+    hdr, ro, co, orient, plans = _run_prep(lps, 1, chunk, max_rows)
+    for o, plan, off in ((orient[0], plans[0], ro), (orient[1], plans[1], co)):
+        ptr = o["ptr"]
+        rows = ptr.size - 1
+        covered = np.zeros(rows, dtype=np.int64)
+        seg_cover = {}
+        for t, (a, b, inst, slot) in enumerate(plan["tiles"]):
+            assert plan["tb"][inst] <= t < plan["te"][inst]
+            if slot < 0:
+                assert off[inst] <= a < b <= off[inst + 1]
+                assert b - a <= max_rows
+                assert ptr[b] - ptr[a] <= chunk
+                covered[a:b] += 1
+            else:
+                assert 0 < b - a <= chunk
+                seg_cover[slot] = (a, b)
+        for q, (row, slot0, nseg, inst) in enumerate(plan["longs"]):
+            assert plan["lb"][inst] <= q < plan["le"][inst]
+            length = ptr[row + 1] - ptr[row]
+            assert length > chunk and nseg == -(-length // chunk)
+            spans = [seg_cover[slot0 + s] for s in range(nseg)]
+            assert spans[0][0] == ptr[row] and spans[-1][1] == ptr[row + 1]
+            assert all(spans[s][1] == spans[s + 1][0] for s in range(nseg - 1))
+            covered[row] += 1
+        assert np.all(covered == 1)

@@ -1,0 +1,183 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (restarts off for fixed-iteration comparisons, so no discrete decision
+can flip):  after 100 iterations  max(e_x, e_y) <= 1e-10 on the FP64 path
+and <= 1e-4 on the FP32 path, with e_v = ||v_gpu - v_ref|| / max(1, ||v_ref||);
+at termination the oracle's own KKT evaluation of the returned iterate must
+meet the tolerance the device reported."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03466_amd import instances as I
+from lp_util import kkt_numpy, rel_err
+
+pytestmark = pytest.mark.gpu
+
+pdhg = pytest.importorskip("paper_2307_03466_amd.pdhg")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pdhg.lib()
+
+
+def _case(name):
+    if name == "cover200":
+        return I.workload(1)
+    if name == "general_small":
+        return I.workload(2, scale=0.002)
+    if name == "skewed_small":       # no row longer than a tile
+        return I.workload(3, scale=0.002)
+    if name == "skewed_longrows":    # rows up to 10k nonzeros: segmented rows
+        return I.workload(3, scale=0.01)
+    if name == "knapsack":
+        return I.cover_knapsack(3000, seed=7)
+    if name == "mixed_bounds":
+        return I.tiny_lp(np.random.default_rng(3), 40, 70, bounded=False)
+    raise KeyError(name)
+
+
+CASES = ["cover200", "general_small", "skewed_small", "skewed_longrows", "knapsack", "mixed_bounds"]
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
+def test_fixed_iteration_parity(name, prec, bar):
+    lp = _case(name)
+    print(f"case {name} prec {prec} m={lp.m} n={lp.n} nnz={lp.nnz}", flush=True)
+    s = pdhg.solve(lp, tol=1e-300, iter_limit=100, restarts=0, precision=prec, autotune=0)
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
+    assert s.result["iterations"] == 100 and s.result["status"] == pdhg.ITERATION_LIMIT
+    ex, ey = rel_err(s.x, ref.x), rel_err(s.y, ref.y)
+    assert max(ex, ey) <= bar, (ex, ey)
+    # invariants hold exactly on the device iterates too
+    assert np.all(s.x >= lp.l) and np.all(s.x <= lp.u)
+    assert np.all(s.y[lp.senses == ord("G")] >= 0) and np.all(s.y[lp.senses == ord("L")] <= 0)
+    # device KKT at the limit equals the oracle's KKT of the returned iterate
+    k = oracle.kkt(lp, s.x, s.y)
+    assert abs(s.result["rel_kkt"] - k["rel"]) <= 1e-9 * max(1.0, k["rel"])
+
+
+@pytest.mark.parametrize("name", ["cover200", "general_small", "skewed_longrows", "knapsack"])
+def test_termination_parity(name):
+    lp = _case(name)
+    tol = 1e-4
+    ref = oracle.pdhg(lp, tol=tol, iter_limit=400_000)
+    assert ref.status == oracle.OPTIMAL
+    for prec in (0, 1):
+        s = pdhg.solve(lp, tol=tol, iter_limit=400_000, precision=prec)
+        assert s.result["status"] == pdhg.OPTIMAL, s.result
+        k = oracle.kkt(lp, s.x, s.y)
+        assert k["rel"] <= tol * (1 + 1e-6), (prec, k)
+        # same LP optimum within the accuracy both reached
+        assert abs(k["pobj"] - ref.pobj) <= 20 * tol * (1 + abs(ref.pobj))
+        if prec == 0:
+            # the FP64 path takes the oracle's decisions: same iteration count
+            assert s.result["iterations"] == ref.iterations, (s.result["iterations"], ref.iterations)
+
+
+def test_iteration_limit_zero_is_projected_start():
+    lp = _case("general_small")
+    rng = np.random.default_rng(1)
+    x0 = rng.normal(size=lp.n) * 30
+    y0 = rng.normal(size=lp.m)
+    s = pdhg.solve(lp, x0=x0, y0=y0, tol=1e-300, iter_limit=0, precision=0, autotune=0)
+    assert s.result["iterations"] == 0 and s.result["status"] == pdhg.ITERATION_LIMIT
+    np.testing.assert_array_equal(s.x, np.clip(x0, lp.l, lp.u))
+    np.testing.assert_array_equal(s.y, np.where(lp.senses == ord("G"), np.maximum(y0, 0), y0))
+    k = kkt_numpy(lp, s.x, s.y)
+    assert abs(s.result["rel_kkt"] - k["rel"]) <= 1e-12 * max(1, k["rel"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_warm_resume_equals_longer_run(prec):
+    lp = _case("skewed_longrows")
+    with pdhg.Batch([lp], precision=prec) as b:
+        b.solve(tol=1e-300, iter_limit=130, restarts=0, autotune=0)
+        b.solve(warm=True, tol=1e-300, iter_limit=70, restarts=0, autotune=0)
+        x1, y1 = b.solution(0)
+    with pdhg.Batch([lp], precision=prec) as b:
+        b.solve(tol=1e-300, iter_limit=200, restarts=0, autotune=0)
+        x2, y2 = b.solution(0)
+    np.testing.assert_array_equal(x1, x2)
+    np.testing.assert_array_equal(y1, y2)
+
+
+def test_run_to_run_bit_identical():
+    lp = _case("skewed_longrows")
+    outs = []
+    for _ in range(2):
+        s = pdhg.solve(lp, tol=1e-4, iter_limit=5000, precision=1, autotune=0)
+        outs.append(s)
+    np.testing.assert_array_equal(outs[0].x, outs[1].x)
+    np.testing.assert_array_equal(outs[0].y, outs[1].y)
+    assert outs[0].result["iterations"] == outs[1].result["iterations"]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_matches_single_instances(prec):
+    lps = I.uneven_batch(count=6, lo=200, hi=3000, seed=11) + [_case("mixed_bounds")]
+    with pdhg.Batch(lps, precision=prec) as b:
+        res = b.solve(tol=1e-4, iter_limit=20_000, autotune=0)
+        sols = [b.solution(i) for i in range(len(lps))]
+    for i, lp in enumerate(lps):
+        s = pdhg.solve(lp, tol=1e-4, iter_limit=20_000, precision=prec, autotune=0)
+        assert res[i]["iterations"] == s.result["iterations"]
+        assert res[i]["status"] == s.result["status"]
+        np.testing.assert_array_equal(sols[i][0], s.x)
+        np.testing.assert_array_equal(sols[i][1], s.y)
+
+
+def test_blend_objective_parity():
+    """Device pump objective (Algorithm 1 objective update) vs the oracle's."""
+    lp = I.cover_knapsack(2000, seed=3)
+    rng = np.random.default_rng(0)
+    xhat = (rng.random(lp.n) < 0.4).astype(float)
+    K = 3
+    c_hat = oracle.objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K)
+    kappa = np.sqrt(lp.is_int.sum()) / np.linalg.norm(lp.c)
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False, c=c_hat)
+    for prec, bar in ((0, 1e-10), (1, 1e-4)):
+        with pdhg.Batch([lp], precision=prec) as b:
+            b.set_blend(0, xhat == lp.u, oracle.ALPHA ** K, kappa)
+            r = b.solve(tol=1e-300, iter_limit=100, restarts=0, autotune=0)[0]
+            x, y = b.solution(0)
+        assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= bar
+        k = oracle.kkt(lp, x, y, c=c_hat)
+        assert abs(r["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
+
+
+def test_set_objective_and_warm_start_parity():
+    lp = _case("general_small")
+    rng = np.random.default_rng(5)
+    c2 = rng.normal(size=lp.n)
+    c2 = np.where(np.isinf(lp.u), np.abs(c2), c2)
+    x0 = np.clip(rng.normal(size=lp.n), lp.l, lp.u)
+    y0 = np.where(lp.senses == ord("G"), np.abs(rng.normal(size=lp.m)), rng.normal(size=lp.m))
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False, c=c2, x0=x0, y0=y0, omega0=2.5)
+    with pdhg.Batch([lp], precision=0) as b:
+        b.set_objective(0, c2)
+        b.set_start(0, x0, y0, omega0=2.5)
+        b.solve(warm=True, tol=1e-300, iter_limit=100, restarts=0, autotune=0)
+        x, y = b.solution(0)
+    assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= 1e-10
+
+
+def test_numerical_error_status():
+    lp = _case("cover200")
+    lp.c = lp.c * 1e306
+    s = pdhg.solve(lp, tol=1e-4, iter_limit=1000, precision=0, autotune=0)
+    assert s.result["status"] == pdhg.NUMERICAL_ERROR
+
+
+def test_time_limit_status():
+    lp = I.workload(2, scale=0.05)
+    s = pdhg.solve(lp, tol=1e-12, iter_limit=10_000_000, precision=1, time_limit_s=0.05, autotune=0)
+    assert s.result["status"] == pdhg.TIME_LIMIT
+    k = oracle.kkt(lp, s.x, s.y)
+    assert abs(s.result["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])

@@ -193,8 +193,19 @@ typedef struct {
     int64_t m_total, n_total, nnz_total;
     int32_t row_chunk, col_chunk; /* tile sizes in use (nonzeros per tile) */
     int32_t long_rows, long_cols; /* rows / columns split over several tiles */
+    int32_t row_blocks, col_blocks; /* gather blocks of each pass (0: the
+                                       normal layout)                        */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
+
+/* Pins the tile plan of both passes instead of autotuning it.  The
+ * floating-point summation order (so the last bits of the iterates) is a
+ * function of the plan; a pinned plan makes results reproducible across
+ * runs and devices.  *_blocks: 0 = normal layout, 4 or 8 = gather-blocked
+ * layout with that many blocks (one per XCD or per XCD pair); *_ept: 4, 8 or
+ * 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL otherwise. */
+int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,
+                            int32_t col_ept);
 
 /* Profiling aid: launches the column pass (primal step) and the row pass
  * (dual step) of the handle `reps` times each on the handle's stream, with

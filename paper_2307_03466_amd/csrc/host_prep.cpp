@@ -219,4 +219,105 @@ void plan_tiles(const std::vector<int32_t> &ptr, const std::vector<int32_t> &ins
     }
 }
 
+static inline int32_t entry_index(const HostOrient &o, int32_t fmt, int64_t e)
+{
+    return fmt == FMT_PACKED ? (int32_t)(o.ent[e] & o.mask) : (int32_t)o.ent[e];
+}
+
+void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_t B, BlockedHost &out)
+{
+    const int32_t rows = o.rows;
+    const int64_t nnz = (int64_t)o.ent.size();
+    out.B = B;
+    out.bounds.assign(B + 1, 0);
+    for (int32_t b = 0; b <= B; ++b) out.bounds[b] = (int32_t)(((int64_t)gather_size * b) / B);
+    // count nonzeros per (block, row)
+    out.bptr.assign((size_t)B * (rows + 1), 0);
+    for (int32_t i = 0; i < rows; ++i) {
+        int32_t b = 0;
+        for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e) {
+            const int32_t g = entry_index(o, fmt, e);
+            while (g >= out.bounds[b + 1]) ++b;
+            out.bptr[(size_t)b * (rows + 1) + i + 1]++;
+        }
+    }
+    int64_t base = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        int32_t *p = out.bptr.data() + (size_t)b * (rows + 1);
+        p[0] = (int32_t)base;
+        for (int32_t i = 0; i < rows; ++i) p[i + 1] += p[i];
+        base = p[rows];
+    }
+    out.ent.resize(nnz);
+    if (fmt == FMT_BF16) out.v16.resize(nnz);
+    if (fmt == FMT_F32) out.v32.resize(nnz);
+    if (fmt == FMT_F64) out.v64.resize(nnz);
+    std::vector<int32_t> fill(B);
+    for (int32_t i = 0; i < rows; ++i) {
+        for (int32_t b = 0; b < B; ++b) fill[b] = out.bptr[(size_t)b * (rows + 1) + i];
+        int32_t b = 0;
+        for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e) {
+            const int32_t g = entry_index(o, fmt, e);
+            while (g >= out.bounds[b + 1]) ++b;
+            const int32_t pos = fill[b]++;
+            out.ent[pos] = o.ent[e];
+            if (fmt == FMT_BF16) out.v16[pos] = o.v16[e];
+            if (fmt == FMT_F32) out.v32[pos] = o.v32[e];
+            if (fmt == FMT_F64) out.v64[pos] = o.v64[e];
+        }
+    }
+}
+
+void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t> &inst_off, int32_t chunk,
+                  int32_t max_rows, BlockedPlan &plan)
+{
+    const int32_t B = bh.B, XCD = 8, G = XCD / B;
+    const int32_t count = (int32_t)inst_off.size() - 1;
+    plan.chunk = chunk;
+    plan.tiles.clear();
+    plan.longs.clear();
+    plan.nslots = 0;
+    std::vector<std::vector<int32_t>> per_xcd(XCD);
+    for (int32_t b = 0; b < B; ++b) {
+        std::vector<int32_t> ptr(bh.bptr.begin() + (size_t)b * (rows + 1),
+                                 bh.bptr.begin() + (size_t)(b + 1) * (rows + 1));
+        TilePlan tp;
+        plan_tiles(ptr, inst_off, chunk, max_rows, tp);
+        const int32_t ntile = (int32_t)(tp.tiles.size() / 4);
+        for (int32_t k = 0; k < ntile; ++k) {
+            const int32_t *t = tp.tiles.data() + 4 * k;
+            const int32_t slot = t[3] >= 0 ? t[3] + plan.nslots : -1;
+            auto &dst = per_xcd[b + (k % G) * B];
+            dst.insert(dst.end(), {t[0], t[1], t[2] | (b << 24), slot});
+        }
+        for (size_t q = 0; q < tp.longs.size(); q += 4)
+            plan.longs.insert(plan.longs.end(),
+                              {tp.longs[q], tp.longs[q + 1] + plan.nslots, tp.longs[q + 2], tp.longs[q + 3] | (b << 24)});
+        plan.nslots += tp.nslots;
+    }
+    size_t K = 0;
+    for (auto &v : per_xcd) K = std::max(K, v.size() / 4);
+    plan.tiles.assign(K * XCD * 4, 0);
+    for (size_t j = 0; j < K; ++j)
+        for (int32_t x = 0; x < XCD; ++x) {
+            int32_t *d = plan.tiles.data() + 4 * (j * XCD + x);
+            if (4 * j < per_xcd[x].size()) {
+                for (int c = 0; c < 4; ++c) d[c] = per_xcd[x][4 * j + c];
+            } else {
+                d[0] = d[1] = d[2] = 0;
+                d[3] = -1;
+            }
+        }
+    // combine tiles: up to 256 rows of one instance each
+    plan.ctiles.clear();
+    plan.ct_begin.assign(count, 0);
+    plan.ct_end.assign(count, 0);
+    for (int32_t q = 0; q < count; ++q) {
+        plan.ct_begin[q] = (int32_t)(plan.ctiles.size() / 4);
+        for (int32_t r = inst_off[q]; r < inst_off[q + 1]; r += 256)
+            plan.ctiles.insert(plan.ctiles.end(), {r, std::min(r + 256, inst_off[q + 1]), q, -1});
+        plan.ct_end[q] = (int32_t)(plan.ctiles.size() / 4);
+    }
+}
+
 }  // namespace scy

@@ -43,8 +43,16 @@ struct PassArgs {
     const double *rhs64;  // b / c_hat in FP64
     const double *lo64, *hi64;
     const double *d64;    // d_r / d_c
-    double *part;         // 4 doubles per tile
+    double *part;         // 4 doubles per tile (blocked: per combine tile)
     double *lpart;        // 4 doubles per long row
+    // gather-blocked orientation
+    const int32_t *bptr;  // [B * (rows + 1)] block row pointers
+    int32_t rows;         // rows of the orientation
+    int32_t B;            // number of gather blocks
+    V *P;                 // [B * rows] block partial sums
+    double *P64;          // [B * rows] block partial sums (check)
+    const int4 *ctiles;   // combine tiles {r0, r1, inst, -1}
+    int32_t nctiles;
 };
 
 struct DecideArgs {
@@ -54,8 +62,11 @@ struct DecideArgs {
     int32_t R;
 };
 
+// One pass (or its FP64 check variant): the tile kernel, the long-row
+// combine, and for a gather-blocked orientation the row combine.
 template <class V>
-void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, hipStream_t s);
+void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, bool blocked,
+                 hipStream_t s);
 void launch_decide(const DecideArgs &d, int count, hipStream_t s);
 void launch_force_stop(InstState *st, int count, hipStream_t s);
 void launch_scale_reduce(const MatView &M, int fmt, int rows, const double *drow, const double *dcol,

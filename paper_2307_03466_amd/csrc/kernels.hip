@@ -161,6 +161,58 @@ __device__ __forceinline__ void primal_update(const PassArgs<V> &p, int j, V aty
     p.own[j] = xn;
 }
 
+// Operands of one row's epilogue, loaded before the LDS barrier so their
+// latency overlaps the matrix stream.
+template <class V>
+struct RowOps {
+    V own, rhs, diag2, lo, hi;
+    uint8_t sense;
+};
+
+template <class V, int DIR>
+__device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> &o)
+{
+    o.own = p.own[i];
+    o.rhs = p.rhs[i];
+    o.diag2 = p.diag2[i];
+    if (DIR == DIR_COL) {
+        o.lo = p.lo[i];
+        o.hi = p.hi[i];
+    } else {
+        o.sense = p.sense[i];
+    }
+}
+
+template <class V, int DIR>
+__device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V step, bool copy_ref,
+                                          const RowOps<V> &o)
+{
+    if (DIR == DIR_COL) {
+        V xn = o.own + step * o.diag2 * (sum - o.rhs);
+        xn = xn < o.lo ? o.lo : xn;
+        xn = xn > o.hi ? o.hi : xn;
+        if (copy_ref) p.own_ref[i] = o.own;
+        p.bar[i] = (V)2 * xn - o.own;
+        p.own[i] = xn;
+    } else {
+        V v = o.own + step * o.diag2 * (o.rhs - sum);
+        if (o.sense == 'G') v = v > (V)0 ? v : (V)0;
+        else if (o.sense == 'L') v = v < (V)0 ? v : (V)0;
+        if (copy_ref) p.own_ref[i] = o.own;
+        p.own[i] = v;
+    }
+}
+
+// Lanes per row for a tile of `nrows` rows: the largest power of two (<= 64)
+// with nrows * L <= NT.
+template <int NT>
+__device__ __forceinline__ int lanes_per_row(int nrows)
+{
+    int L = 1;
+    while (L < 64 && nrows * (L << 1) <= NT) L <<= 1;
+    return L;
+}
+
 // ------------------------------------------------------- iteration pass
 template <class V, int FMT, int DIR, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
@@ -174,38 +226,132 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
-    int e0, e1;
-    if (T.w >= 0) {
-        e0 = T.x;
-        e1 = T.y;
-    } else {
-        e0 = p.M.ptr[T.x];
-        e1 = p.M.ptr[T.y];
-    }
-    stage_products<V, V, FMT, NT, EPT>(p.M, p.gvec, e0, e1, prod);
-    __syncthreads();
     const int tid = threadIdx.x;
     if (T.w >= 0) {  // one segment of a long row: partial sum only
+        stage_products<V, V, FMT, NT, EPT>(p.M, p.gvec, T.x, T.y, prod);
+        __syncthreads();
         V s = 0;
-        for (int q = tid; q < e1 - e0; q += NT) s += prod[q];
+        for (int q = tid; q < T.y - T.x; q += NT) s += prod[q];
         s = block_sum<V, NT>(s, red);
         if (tid == 0) p.seg[T.w] = s;
         return;
     }
     const int r0 = T.x, nrows = T.y - T.x;
-    int L = 1;
-    while (L < 64 && nrows * (L << 1) <= NT) L <<= 1;
+    const int e0 = p.M.ptr[r0], e1 = p.M.ptr[T.y];
+    const int L = lanes_per_row<NT>(nrows);
     const int groups = NT / L, lane = tid & (L - 1);
-    for (int r = tid / L; r < nrows; r += groups) {
-        const int rb = p.M.ptr[r0 + r] - e0, re = p.M.ptr[r0 + r + 1] - e0;
+    // first row of this lane group: bounds and epilogue operands up front
+    int r = tid / L;
+    int rb = 0, re = 0;
+    RowOps<V> ops;
+    if (r < nrows) {
+        rb = p.M.ptr[r0 + r] - e0;
+        re = p.M.ptr[r0 + r + 1] - e0;
+        if (lane == 0) load_ops<V, DIR>(p, r0 + r, ops);
+    }
+    stage_products<V, V, FMT, NT, EPT>(p.M, p.gvec, e0, e1, prod);
+    __syncthreads();
+    for (; r < nrows; r += groups) {
         V s = 0;
         for (int q = rb + lane; q < re; q += L) s += prod[q];
         if (L > 1) s = wave_sum_width(s, L);
-        if (lane == 0) {
-            if (DIR == DIR_COL) primal_update(p, r0 + r, s, step, copy_ref);
-            else dual_update(p, r0 + r, s, step, copy_ref);
+        if (lane == 0) apply_ops<V, DIR>(p, r0 + r, s, step, copy_ref, ops);
+        const int rn = r + groups;
+        if (rn < nrows) {
+            rb = p.M.ptr[r0 + rn] - e0;
+            re = p.M.ptr[r0 + rn + 1] - e0;
+            if (lane == 0) load_ops<V, DIR>(p, r0 + rn, ops);
         }
     }
+}
+
+// ------------------------------------------- gather-blocked pass (partials)
+// Tile of block b (bits 24.. of T.z) of a gather-blocked orientation: row
+// sums over the block's nonzeros go to P[b * rows + i] (A = V for the
+// iteration, double for the check); long sub-rows go to segment slots.
+template <class V, class A, int FMT, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_bpart(const PassArgs<V> p, const int jw, const int check)
+{
+    constexpr int CH = NT * EPT;
+    __shared__ A prod[CH];
+    __shared__ A red[NT / 64];
+    const int4 T = p.tiles[blockIdx.x];
+    const int inst = T.z & 0xffffff, b = T.z >> 24;
+    const InstState &S = p.st[inst];
+    if (S.status != ST_RUN || (!check && jw >= S.nrun)) return;
+    const int tid = threadIdx.x;
+    A *P = (A *)(check ? (void *)p.P64 : (void *)p.P);
+    if (T.w >= 0) {
+        stage_products<A, V, FMT, NT, EPT>(p.M, p.gvec, T.x, T.y, prod);
+        __syncthreads();
+        A s = 0;
+        for (int q = tid; q < T.y - T.x; q += NT) s += prod[q];
+        s = block_sum<A, NT>(s, red);
+        A *seg = (A *)(check ? (void *)p.seg64 : (void *)p.seg);
+        if (tid == 0) seg[T.w] = s;
+        return;
+    }
+    const int32_t *ptr = p.bptr + (size_t)b * (p.rows + 1);
+    const int r0 = T.x, nrows = T.y - T.x;
+    const int e0 = ptr[r0], e1 = ptr[T.y];
+    const int L = lanes_per_row<NT>(nrows);
+    const int groups = NT / L, lane = tid & (L - 1);
+    int r = tid / L;
+    int rb = 0, re = 0;
+    if (r < nrows) {
+        rb = ptr[r0 + r] - e0;
+        re = ptr[r0 + r + 1] - e0;
+    }
+    stage_products<A, V, FMT, NT, EPT>(p.M, p.gvec, e0, e1, prod);
+    __syncthreads();
+    A *Pb = P + (size_t)b * p.rows;
+    for (; r < nrows; r += groups) {
+        A s = 0;
+        for (int q = rb + lane; q < re; q += L) s += prod[q];
+        if (L > 1) s = wave_sum_width(s, L);
+        if (lane == 0) Pb[r0 + r] = s;
+        const int rn = r + groups;
+        if (rn < nrows) {
+            rb = ptr[r0 + rn] - e0;
+            re = ptr[r0 + rn + 1] - e0;
+        }
+    }
+}
+
+// Long sub-rows of a blocked orientation: P[b][row] = sum of its segments.
+template <class V, class A>
+__global__ __launch_bounds__(256) void k_bseg(const PassArgs<V> p, const int jw, const int check)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.nlong) return;
+    const int4 L = p.longs[q];
+    const int inst = L.w & 0xffffff, b = L.w >> 24;
+    const InstState &S = p.st[inst];
+    if (S.status != ST_RUN || (!check && jw >= S.nrun)) return;
+    const A *seg = (const A *)(check ? (const void *)p.seg64 : (const void *)p.seg);
+    A s = 0;
+    for (int k = 0; k < L.z; ++k) s += seg[L.y + k];
+    A *P = (A *)(check ? (void *)p.P64 : (void *)p.P);
+    P[(size_t)b * p.rows + L.x] = s;
+}
+
+// Combine of a blocked orientation (one thread per row, 256 rows of one
+// instance per workgroup): sum the B block partials in block order, then the
+// fused epilogue.
+template <class V, int DIR>
+__global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int jw)
+{
+    const int4 T = p.ctiles[blockIdx.x];
+    const InstState &S = p.st[T.z];
+    if (S.status != ST_RUN || jw >= S.nrun) return;
+    const int i = T.x + threadIdx.x;
+    if (i >= T.y) return;
+    const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+    RowOps<V> ops;
+    load_ops<V, DIR>(p, i, ops);
+    V s = 0;
+    for (int b = 0; b < p.B; ++b) s += p.P[(size_t)b * p.rows + i];
+    apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops);
 }
 
 // Long rows: add the segment partials in segment order, then the epilogue.
@@ -337,6 +483,32 @@ __global__ __launch_bounds__(256) void k_combine_check(const PassArgs<V> p)
     if (DIR == DIR_COL) col_terms(p, L.x, s, q);
     else row_terms(p, L.x, s, q);
     for (int k = 0; k < 4; ++k) p.lpart[4 * qi + k] = q[k];
+}
+
+// Check combine of a blocked orientation: FP64 row sums from the block
+// partials, row / column KKT terms, fixed-order sum per combine tile.
+template <class V, int DIR>
+__global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
+{
+    __shared__ double red[4];
+    const int ct = blockIdx.x;
+    const int4 T = p.ctiles[ct];
+    const InstState &S = p.st[T.z];
+    if (S.status != ST_RUN) return;
+    const int i = T.x + threadIdx.x;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < T.y) {
+        double s = 0;
+        for (int b = 0; b < p.B; ++b) s += p.P64[(size_t)b * p.rows + i];
+        if (DIR == DIR_COL) col_terms(p, i, s, q);
+        else row_terms(p, i, s, q);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        __syncthreads();
+        const double v = block_sum<double, 256>(q[k], red);
+        if (threadIdx.x == 0) p.part[4 * ct + k] = v;
+    }
 }
 
 // ------------------------------------------------------------- decision
@@ -573,9 +745,54 @@ static void dispatch_pass(const PassArgs<V> &p, int ept, int jw, bool check, hip
     }
 }
 
-template <class V>
-void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, hipStream_t s)
+template <class V, class A, int FMT>
+static void dispatch_bpart(const PassArgs<V> &p, int ept, int jw, int check, hipStream_t s)
 {
+    const dim3 g(p.ntiles), b(256);
+    switch (ept) {
+    case 4: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 4>), g, b, 0, s, p, jw, check); break;
+    case 8: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 8>), g, b, 0, s, p, jw, check); break;
+    default: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 16>), g, b, 0, s, p, jw, check); break;
+    }
+}
+
+template <class V, class A>
+static void bpart_fmt(const PassArgs<V> &p, int fmt, int ept, int jw, int check, hipStream_t s)
+{
+    if constexpr (sizeof(V) == 8) {
+        dispatch_bpart<V, A, FMT_F64>(p, ept, jw, check, s);
+    } else {
+        if (fmt == FMT_PACKED) dispatch_bpart<V, A, FMT_PACKED>(p, ept, jw, check, s);
+        else if (fmt == FMT_BF16) dispatch_bpart<V, A, FMT_BF16>(p, ept, jw, check, s);
+        else dispatch_bpart<V, A, FMT_F32>(p, ept, jw, check, s);
+    }
+}
+
+template <class V>
+void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, bool blocked, hipStream_t s)
+{
+    if (blocked) {
+        if (p.ntiles > 0) {
+            if (check) bpart_fmt<V, double>(p, fmt, ept, jw, 1, s);
+            else bpart_fmt<V, V>(p, fmt, ept, jw, 0, s);
+        }
+        if (p.nlong > 0) {
+            const int nb = (p.nlong + 255) / 256;
+            if (check) hipLaunchKernelGGL((k_bseg<V, double>), dim3(nb), dim3(256), 0, s, p, jw, 1);
+            else hipLaunchKernelGGL((k_bseg<V, V>), dim3(nb), dim3(256), 0, s, p, jw, 0);
+        }
+        if (p.nctiles > 0) {
+            const dim3 g(p.nctiles), b(256);
+            if (check) {
+                if (dir == DIR_COL) hipLaunchKernelGGL((k_bcombine_check<V, DIR_COL>), g, b, 0, s, p);
+                else hipLaunchKernelGGL((k_bcombine_check<V, DIR_ROW>), g, b, 0, s, p);
+            } else {
+                if (dir == DIR_COL) hipLaunchKernelGGL((k_bcombine<V, DIR_COL>), g, b, 0, s, p, jw);
+                else hipLaunchKernelGGL((k_bcombine<V, DIR_ROW>), g, b, 0, s, p, jw);
+            }
+        }
+        return;
+    }
     if (p.ntiles > 0) {
         if constexpr (sizeof(V) == 8) {
             if (dir == DIR_COL) dispatch_pass<V, FMT_F64, DIR_COL>(p, ept, jw, check, s);
@@ -671,7 +888,7 @@ void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibi
 }
 
 #define SCY_INST(V)                                                                                    \
-    template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, hipStream_t);          \
+    template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, bool, hipStream_t);    \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
     template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \
     template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \

@@ -79,6 +79,30 @@ void upload(DevMem &d, const std::vector<T> &h, hipStream_t s)
 
 using namespace scy;
 
+// One orientation of the matrix on the device: the CSR (row pass, dual
+// step) or the CSC copy (column pass, primal step), in its normal layout or
+// its gather-blocked layout, with the tile plan in use and its buffers.
+struct OrientRT {
+    bool row = true;
+    int32_t rows = 0, gather = 0;
+    HostOrient host;  // normal layout (host copy kept for re-planning)
+    DevMem ptr, ent, val;
+    MatView mat{};
+    TilePlan plan;
+    int32_t ept = 8;
+    // gather-blocked layout (when chosen)
+    bool blocked = false;
+    BlockedHost bh;  // host copy of the block pointers (entries dropped after upload)
+    DevMem bptr, bent, bval;
+    MatView bmat{};
+    BlockedPlan bplan;
+    DevMem P, P64, ctiles;
+    // plan buffers
+    DevMem tiles, longs, seg, seg64, part, lpart;
+    int32_t ntiles() const { return (int32_t)((blocked ? bplan.tiles.size() : plan.tiles.size()) / 4); }
+    int32_t nlong() const { return (int32_t)((blocked ? bplan.longs.size() : plan.longs.size()) / 4); }
+};
+
 struct scylla_batch {
     int32_t count = 0, precision = SCYLLA_FP32, fmt = FMT_PACKED;
     int32_t vbytes = 4;
@@ -88,20 +112,13 @@ struct scylla_batch {
     int32_t M = 0, N = 0;
     int64_t NNZ = 0;
     std::vector<int32_t> row_off, col_off;
-    std::vector<int32_t> csr_ptr_h, csc_ptr_h;
-    // matrix
-    DevMem csr_ptr, csr_ent, csr_val, csc_ptr, csc_ent, csc_val;
-    MatView csr{}, csc{};
+    OrientRT orow, ocol;
     // vectors in the path precision
     DevMem x, xbar, xr, y, yr, cv, lv, uv, dc2, b_v, dr2;
     DevMem sense;
     // FP64 data
     DevMem c64, corig64, l64, u64, b64, dr64, dc64;
     DevMem st, info;
-    // plans
-    TilePlan prow, pcol;
-    int32_t ept_row = 8, ept_col = 8;
-    DevMem rtiles, ctiles, rlongs, clongs, rseg, cseg, rseg64, cseg64, rpart, cpart, lrpart, lcpart;
     DevMem bits_tmp, ibits_tmp;
     // graph
     hipGraphExec_t gexec = nullptr;
@@ -142,82 +159,120 @@ void check_device()
 }
 
 template <class V>
-PassArgs<V> row_args(scylla_batch *h, bool check)
+PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
 {
     PassArgs<V> p{};
-    p.M = h->csr;
-    p.tiles = h->rtiles.as<int4>();
-    p.ntiles = (int32_t)(h->prow.tiles.size() / 4);
-    p.longs = h->rlongs.as<int4>();
-    p.nlong = (int32_t)(h->prow.longs.size() / 4);
-    p.gvec = check ? h->x.as<V>() : h->xbar.as<V>();
-    p.own = h->y.as<V>();
-    p.own_ref = h->yr.as<V>();
-    p.rhs = h->b_v.as<V>();
-    p.diag2 = h->dr2.as<V>();
-    p.sense = h->sense.as<uint8_t>();
+    p.M = o.blocked ? o.bmat : o.mat;
+    p.tiles = o.tiles.as<int4>();
+    p.ntiles = o.ntiles();
+    p.longs = o.longs.as<int4>();
+    p.nlong = o.nlong();
     p.st = h->st.as<InstState>();
-    p.seg = h->rseg.as<V>();
-    p.seg64 = h->rseg64.as<double>();
-    p.rhs64 = h->b64.as<double>();
-    p.d64 = h->dr64.as<double>();
-    p.part = h->rpart.as<double>();
-    p.lpart = h->lrpart.as<double>();
+    p.seg = o.seg.as<V>();
+    p.seg64 = o.seg64.as<double>();
+    p.part = o.part.as<double>();
+    p.lpart = o.lpart.as<double>();
+    p.bptr = o.bptr.as<int32_t>();
+    p.rows = o.rows;
+    p.B = o.blocked ? o.bh.B : 0;
+    p.P = o.P.as<V>();
+    p.P64 = o.P64.as<double>();
+    p.ctiles = o.ctiles.as<int4>();
+    p.nctiles = o.blocked ? (int32_t)(o.bplan.ctiles.size() / 4) : 0;
+    if (o.row) {
+        p.gvec = check ? h->x.as<V>() : h->xbar.as<V>();
+        p.own = h->y.as<V>();
+        p.own_ref = h->yr.as<V>();
+        p.rhs = h->b_v.as<V>();
+        p.diag2 = h->dr2.as<V>();
+        p.sense = h->sense.as<uint8_t>();
+        p.rhs64 = h->b64.as<double>();
+        p.d64 = h->dr64.as<double>();
+    } else {
+        p.gvec = h->y.as<V>();
+        p.own = h->x.as<V>();
+        p.bar = h->xbar.as<V>();
+        p.own_ref = h->xr.as<V>();
+        p.rhs = h->cv.as<V>();
+        p.diag2 = h->dc2.as<V>();
+        p.lo = h->lv.as<V>();
+        p.hi = h->uv.as<V>();
+        p.rhs64 = h->c64.as<double>();
+        p.lo64 = h->l64.as<double>();
+        p.hi64 = h->u64.as<double>();
+        p.d64 = h->dc64.as<double>();
+    }
     return p;
 }
 
-template <class V>
-PassArgs<V> col_args(scylla_batch *h, bool check)
+void upload_vals(scylla_batch *h, DevMem &d, const std::vector<uint16_t> &v16, const std::vector<float> &v32,
+                 const std::vector<double> &v64)
 {
-    (void)check;
-    PassArgs<V> p{};
-    p.M = h->csc;
-    p.tiles = h->ctiles.as<int4>();
-    p.ntiles = (int32_t)(h->pcol.tiles.size() / 4);
-    p.longs = h->clongs.as<int4>();
-    p.nlong = (int32_t)(h->pcol.longs.size() / 4);
-    p.gvec = h->y.as<V>();
-    p.own = h->x.as<V>();
-    p.bar = h->xbar.as<V>();
-    p.own_ref = h->xr.as<V>();
-    p.rhs = h->cv.as<V>();
-    p.diag2 = h->dc2.as<V>();
-    p.lo = h->lv.as<V>();
-    p.hi = h->uv.as<V>();
-    p.st = h->st.as<InstState>();
-    p.seg = h->cseg.as<V>();
-    p.seg64 = h->cseg64.as<double>();
-    p.rhs64 = h->c64.as<double>();
-    p.lo64 = h->l64.as<double>();
-    p.hi64 = h->u64.as<double>();
-    p.d64 = h->dc64.as<double>();
-    p.part = h->cpart.as<double>();
-    p.lpart = h->lcpart.as<double>();
-    return p;
+    if (h->fmt == FMT_BF16) upload(d, v16, h->stream);
+    else if (h->fmt == FMT_F32) upload(d, v32, h->stream);
+    else if (h->fmt == FMT_F64) upload(d, v64, h->stream);
 }
 
-void upload_plan(scylla_batch *h, bool row)
-{
-    TilePlan &pl = row ? h->prow : h->pcol;
-    const size_t vb = (size_t)h->vbytes;
-    upload(row ? h->rtiles : h->ctiles, pl.tiles, h->stream);
-    upload(row ? h->rlongs : h->clongs, pl.longs, h->stream);
-    (row ? h->rseg : h->cseg).alloc(std::max<size_t>(1, pl.nslots) * vb);
-    (row ? h->rseg64 : h->cseg64).alloc(std::max<size_t>(1, pl.nslots) * 8);
-    (row ? h->rpart : h->cpart).alloc(std::max<size_t>(1, pl.tiles.size() / 4) * 4 * 8);
-    (row ? h->lrpart : h->lcpart).alloc(std::max<size_t>(1, pl.longs.size() / 4) * 4 * 8);
-}
-
-void make_plan(scylla_batch *h, bool row, int32_t ept)
+// Plans the orientation with `ept` nonzeros per thread, normal layout
+// (B = 0) or gather-blocked with B blocks, and uploads the plan buffers.
+void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
 {
     const int32_t chunk = 256 * ept;
-    if (row) {
-        plan_tiles(h->csr_ptr_h, h->row_off, chunk, 1024, h->prow);
-        h->ept_row = ept;
+    const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
+    const size_t vb = (size_t)h->vbytes;
+    o.ept = ept;
+    if (B > 0) {
+        if (!o.blocked || o.bh.B != B) {
+            build_blocked(o.host, h->fmt, o.gather, B, o.bh);
+            upload(o.bptr, o.bh.bptr, h->stream);
+            upload(o.bent, o.bh.ent, h->stream);
+            upload_vals(h, o.bval, o.bh.v16, o.bh.v32, o.bh.v64);
+            HIPC(hipStreamSynchronize(h->stream));
+            o.bh.ent.clear();
+            o.bh.ent.shrink_to_fit();
+            o.bh.v16.clear();
+            o.bh.v16.shrink_to_fit();
+            o.bh.v32.clear();
+            o.bh.v32.shrink_to_fit();
+            o.bh.v64.clear();
+            o.bh.v64.shrink_to_fit();
+            o.bmat = MatView{o.bptr.as<int32_t>(), o.bent.as<uint32_t>(), o.bval.p, o.host.shift, o.host.mask};
+            o.P.alloc((size_t)B * std::max(o.rows, 1) * vb);
+            o.P64.alloc((size_t)B * std::max(o.rows, 1) * 8);
+        }
+        o.blocked = true;
+        plan_blocked(o.bh, o.rows, off, chunk, 1024, o.bplan);
+        upload(o.tiles, o.bplan.tiles, h->stream);
+        upload(o.longs, o.bplan.longs, h->stream);
+        upload(o.ctiles, o.bplan.ctiles, h->stream);
+        o.seg.alloc(std::max<size_t>(1, o.bplan.nslots) * vb);
+        o.seg64.alloc(std::max<size_t>(1, o.bplan.nslots) * 8);
+        o.part.alloc(std::max<size_t>(1, o.bplan.ctiles.size() / 4) * 4 * 8);
+        o.lpart.alloc(8 * 4);
     } else {
-        plan_tiles(h->csc_ptr_h, h->col_off, chunk, 1024, h->pcol);
-        h->ept_col = ept;
+        o.blocked = false;
+        plan_tiles(o.host.ptr, off, chunk, 1024, o.plan);
+        upload(o.tiles, o.plan.tiles, h->stream);
+        upload(o.longs, o.plan.longs, h->stream);
+        o.seg.alloc(std::max<size_t>(1, o.plan.nslots) * vb);
+        o.seg64.alloc(std::max<size_t>(1, o.plan.nslots) * 8);
+        o.part.alloc(std::max<size_t>(1, o.plan.tiles.size() / 4) * 4 * 8);
+        o.lpart.alloc(std::max<size_t>(1, o.plan.longs.size() / 4) * 4 * 8);
     }
+    HIPC(hipStreamSynchronize(h->stream));
+}
+
+// Drops the blocked layout's device copy (after the tuner chose normal).
+void drop_blocked(OrientRT &o)
+{
+    o.bptr.release();
+    o.bent.release();
+    o.bval.release();
+    o.P.release();
+    o.P64.release();
+    o.ctiles.release();
+    o.bh = BlockedHost();
+    o.bplan = BlockedPlan();
 }
 
 void refresh_info(scylla_batch *h)
@@ -229,16 +284,27 @@ void refresh_info(scylla_batch *h)
         I.row1 = h->row_off[q + 1];
         I.col0 = h->col_off[q];
         I.col1 = h->col_off[q + 1];
-        I.rt0 = h->prow.t_begin[q];
-        I.rt1 = h->prow.t_end[q];
-        I.ct0 = h->pcol.t_begin[q];
-        I.ct1 = h->pcol.t_end[q];
-        I.lr0 = h->prow.l_begin[q];
-        I.lr1 = h->prow.l_end[q];
-        I.lc0 = h->pcol.l_begin[q];
-        I.lc1 = h->pcol.l_end[q];
+        for (int d = 0; d < 2; ++d) {
+            OrientRT &o = d == 0 ? h->orow : h->ocol;
+            int32_t t0, t1, l0 = 0, l1 = 0;
+            if (o.blocked) {
+                t0 = o.bplan.ct_begin[q];
+                t1 = o.bplan.ct_end[q];
+            } else {
+                t0 = o.plan.t_begin[q];
+                t1 = o.plan.t_end[q];
+                l0 = o.plan.l_begin[q];
+                l1 = o.plan.l_end[q];
+            }
+            if (d == 0) {
+                I.rt0 = t0; I.rt1 = t1; I.lr0 = l0; I.lr1 = l1;
+            } else {
+                I.ct0 = t0; I.ct1 = t1; I.lc0 = l0; I.lc1 = l1;
+            }
+        }
     }
     upload(h->info, h->hinfo, h->stream);
+    HIPC(hipStreamSynchronize(h->stream));
 }
 
 void invalidate_graph(scylla_batch *h)
@@ -249,18 +315,24 @@ void invalidate_graph(scylla_batch *h)
 }
 
 template <class V>
+void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, bool check, hipStream_t s)
+{
+    launch_pass<V>(p, h->fmt, o.row ? DIR_ROW : DIR_COL, o.ept, jw, check, o.blocked, s);
+}
+
+template <class V>
 void enqueue_window(scylla_batch *h, int32_t R, hipStream_t s)
 {
-    const PassArgs<V> rc = row_args<V>(h, true), cc = col_args<V>(h, true);
-    launch_pass<V>(rc, h->fmt, DIR_ROW, h->ept_row, 0, true, s);
-    launch_pass<V>(cc, h->fmt, DIR_COL, h->ept_col, 0, true, s);
-    DecideArgs d{h->st.as<InstState>(), h->info.as<InstInfo>(), h->rpart.as<double>(),
-                 h->lrpart.as<double>(), h->cpart.as<double>(), h->lcpart.as<double>(), R};
+    const PassArgs<V> rc = orient_args<V>(h, h->orow, true), cc = orient_args<V>(h, h->ocol, true);
+    launch_orient<V>(h, h->orow, rc, 0, true, s);
+    launch_orient<V>(h, h->ocol, cc, 0, true, s);
+    DecideArgs d{h->st.as<InstState>(), h->info.as<InstInfo>(), h->orow.part.as<double>(),
+                 h->orow.lpart.as<double>(), h->ocol.part.as<double>(), h->ocol.lpart.as<double>(), R};
     launch_decide(d, h->count, s);
-    const PassArgs<V> ri = row_args<V>(h, false), ci = col_args<V>(h, false);
+    const PassArgs<V> ri = orient_args<V>(h, h->orow, false), ci = orient_args<V>(h, h->ocol, false);
     for (int32_t j = 0; j < R; ++j) {
-        launch_pass<V>(ci, h->fmt, DIR_COL, h->ept_col, j, false, s);
-        launch_pass<V>(ri, h->fmt, DIR_ROW, h->ept_row, j, false, s);
+        launch_orient<V>(h, h->ocol, ci, j, false, s);
+        launch_orient<V>(h, h->orow, ri, j, false, s);
     }
 }
 
@@ -311,49 +383,57 @@ struct PassTimer {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     }
-    // average milliseconds of one launch of the row (row = true) or column pass
-    double time(bool row, int reps)
+    // average milliseconds of one pass (all its launches) of orientation o
+    double time(OrientRT &o, int reps)
     {
-        PassArgs<V> p = row ? row_args<V>(h, false) : col_args<V>(h, false);
+        PassArgs<V> p = orient_args<V>(h, o, false);
         p.st = trial_st.as<InstState>();
-        p.own = row ? sy.as<V>() : sx.as<V>();
+        p.own = o.row ? sy.as<V>() : sx.as<V>();
         p.bar = sbar.as<V>();
-        const int ept = row ? h->ept_row : h->ept_col;
-        const int dir = row ? DIR_ROW : DIR_COL;
-        launch_pass<V>(p, h->fmt, dir, ept, 1, false, h->stream);
+        launch_orient<V>(h, o, p, 1, false, h->stream);
         HIPC(hipEventRecord(e0, h->stream));
-        for (int r = 0; r < reps; ++r) launch_pass<V>(p, h->fmt, dir, ept, 1, false, h->stream);
+        for (int r = 0; r < reps; ++r) launch_orient<V>(h, o, p, 1, false, h->stream);
         HIPC(hipEventRecord(e1, h->stream));
         HIPC(hipEventSynchronize(e1));
+        HIPC(hipGetLastError());
         float ms = 0;
         HIPC(hipEventElapsedTime(&ms, e0, e1));
         return (double)ms / reps;
     }
 };
 
-// Times the candidate tile sizes of each pass and keeps the fastest.
+// Times the layout / tile-size candidates of each orientation and keeps the
+// fastest: the normal layout with 4, 8 or 16 nonzeros per thread, and, when
+// the gathered vector is larger than 2 MB, the gather-blocked layout with 4
+// or 8 blocks (one block per XCD or per XCD pair).
 template <class V>
 void autotune(scylla_batch *h)
 {
-    const int cands[3] = {4, 8, 16};
+    const int epts[3] = {4, 8, 16};
     PassTimer<V> timer(h);
-    for (int dir = 0; dir < 2; ++dir) {
-        const bool row = dir == 0;
+    for (int d = 0; d < 2; ++d) {
+        OrientRT &o = d == 0 ? h->orow : h->ocol;
         double best = 1e30;
-        int best_ept = 8;
-        for (int ept : cands) {
-            make_plan(h, row, ept);
-            upload_plan(h, row);
-            const double ms = timer.time(row, 10);
-            if (ms < best) {
-                best = ms;
-                best_ept = ept;
+        int best_B = 0, best_ept = 8;
+        std::vector<int> Bs = {0};
+        if ((int64_t)o.gather * h->vbytes > (2 << 20) && o.rows > 0) {
+            Bs.push_back(4);
+            Bs.push_back(8);
+        }
+        for (int B : Bs) {
+            for (int ept : epts) {
+                set_plan(h, o, B, ept);
+                const double ms = timer.time(o, 10);
+                if (ms < best) {
+                    best = ms;
+                    best_B = B;
+                    best_ept = ept;
+                }
             }
         }
-        make_plan(h, row, best_ept);
-        upload_plan(h, row);
+        set_plan(h, o, best_B, best_ept);
+        if (best_B == 0) drop_blocked(o);
     }
-    HIPC(hipStreamSynchronize(h->stream));
     refresh_info(h);
     invalidate_graph(h);
     h->tuned = true;
@@ -364,25 +444,18 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
 {
     hipStream_t s = h->stream;
     const int32_t M = h->M, N = h->N;
-    // matrix
-    upload(h->csr_ptr, csr.ptr, s);
-    upload(h->csr_ent, csr.ent, s);
-    upload(h->csc_ptr, csc.ptr, s);
-    upload(h->csc_ent, csc.ent, s);
-    if (h->fmt == FMT_BF16) {
-        upload(h->csr_val, csr.v16, s);
-        upload(h->csc_val, csc.v16, s);
-    } else if (h->fmt == FMT_F32) {
-        upload(h->csr_val, csr.v32, s);
-        upload(h->csc_val, csc.v32, s);
-    } else if (h->fmt == FMT_F64) {
-        upload(h->csr_val, csr.v64, s);
-        upload(h->csc_val, csc.v64, s);
+    // matrix: both orientations in their normal layout
+    for (int d = 0; d < 2; ++d) {
+        OrientRT &o = d == 0 ? h->orow : h->ocol;
+        o.row = d == 0;
+        o.host = std::move(d == 0 ? csr : csc);
+        o.rows = o.host.rows;
+        o.gather = d == 0 ? N : M;
+        upload(o.ptr, o.host.ptr, s);
+        upload(o.ent, o.host.ent, s);
+        upload_vals(h, o.val, o.host.v16, o.host.v32, o.host.v64);
+        o.mat = MatView{o.ptr.as<int32_t>(), o.ent.as<uint32_t>(), o.val.p, o.host.shift, o.host.mask};
     }
-    h->csr = MatView{h->csr_ptr.as<int32_t>(), h->csr_ent.as<uint32_t>(), h->csr_val.p, csr.shift, csr.mask};
-    h->csc = MatView{h->csc_ptr.as<int32_t>(), h->csc_ent.as<uint32_t>(), h->csc_val.p, csc.shift, csc.mask};
-    h->csr_ptr_h.swap(csr.ptr);
-    h->csc_ptr_h.swap(csc.ptr);
     // FP64 problem vectors (concatenated)
     std::vector<double> c(N), l(N), u(N), b(M);
     std::vector<uint8_t> sn(M);
@@ -421,8 +494,8 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     ct.alloc((size_t)std::max(N, 1) * 8);
     for (int it = 0; it < 11; ++it) {
         const int mode = it < 10 ? 0 : 1;
-        launch_scale_reduce(h->csr, h->fmt, M, h->dr64.as<double>(), h->dc64.as<double>(), rt.as<double>(), mode, s);
-        launch_scale_reduce(h->csc, h->fmt, N, h->dc64.as<double>(), h->dr64.as<double>(), ct.as<double>(), mode, s);
+        launch_scale_reduce(h->orow.mat, h->fmt, M, h->dr64.as<double>(), h->dc64.as<double>(), rt.as<double>(), mode, s);
+        launch_scale_reduce(h->ocol.mat, h->fmt, N, h->dc64.as<double>(), h->dr64.as<double>(), ct.as<double>(), mode, s);
         launch_scale_apply(h->dr64.as<double>(), rt.as<double>(), M, s);
         launch_scale_apply(h->dc64.as<double>(), ct.as<double>(), N, s);
     }
@@ -433,10 +506,8 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     memset(st.data(), 0, sizeof(InstState) * st.size());
     for (auto &S : st) S.status = ST_ITER;  // idle until the first solve
     upload(h->st, st, s);
-    make_plan(h, true, 8);
-    make_plan(h, false, 8);
-    upload_plan(h, true);
-    upload_plan(h, false);
+    set_plan(h, h->orow, 0, 8);
+    set_plan(h, h->ocol, 0, 8);
     refresh_info(h);
     launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
                       h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), s);
@@ -843,10 +914,33 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->m_total = h->M;
         info->n_total = h->N;
         info->nnz_total = h->NNZ;
-        info->row_chunk = h->prow.chunk;
-        info->col_chunk = h->pcol.chunk;
-        info->long_rows = (int32_t)(h->prow.longs.size() / 4);
-        info->long_cols = (int32_t)(h->pcol.longs.size() / 4);
+        info->row_chunk = 256 * h->orow.ept;
+        info->col_chunk = 256 * h->ocol.ept;
+        info->long_rows = h->orow.nlong();
+        info->long_cols = h->ocol.nlong();
+        info->row_blocks = h->orow.blocked ? h->orow.bh.B : 0;
+        info->col_blocks = h->ocol.blocked ? h->ocol.bh.B : 0;
+        return 0;
+    });
+}
+
+int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,
+                            int32_t col_ept)
+{
+    return guarded([&]() {
+        if (!h) throw_err(-EINVAL, "handle is NULL");
+        auto okB = [](int32_t B) { return B == 0 || B == 4 || B == 8; };
+        auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16; };
+        if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
+            throw_err(-EINVAL, "blocks must be 0, 4 or 8 and ept 4, 8 or 16");
+        HIPC(hipStreamSynchronize(h->stream));
+        set_plan(h, h->orow, h->orow.rows > 0 ? row_blocks : 0, row_ept);
+        set_plan(h, h->ocol, h->ocol.rows > 0 ? col_blocks : 0, col_ept);
+        if (h->orow.rows == 0 || row_blocks == 0) drop_blocked(h->orow);
+        if (col_blocks == 0) drop_blocked(h->ocol);
+        refresh_info(h);
+        invalidate_graph(h);
+        h->tuned = true;
         return 0;
     });
 }
@@ -858,12 +952,12 @@ int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, doub
         HIPC(hipStreamSynchronize(h->stream));
         if (h->vbytes == 4) {
             PassTimer<float> t(h);
-            *ms_row = t.time(true, reps);
-            *ms_col = t.time(false, reps);
+            *ms_row = t.time(h->orow, reps);
+            *ms_col = t.time(h->ocol, reps);
         } else {
             PassTimer<double> t(h);
-            *ms_row = t.time(true, reps);
-            *ms_col = t.time(false, reps);
+            *ms_row = t.time(h->orow, reps);
+            *ms_col = t.time(h->ocol, reps);
         }
         HIPC(hipStreamSynchronize(h->stream));
         return 0;

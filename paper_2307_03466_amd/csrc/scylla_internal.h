@@ -78,6 +78,36 @@ struct TilePlan {
     std::vector<int32_t> t_begin, t_end, l_begin, l_end;  // per instance
 };
 
+// Gather-blocked copy of an orientation: the gathered index space is cut
+// into B contiguous blocks and every row's nonzeros are regrouped block by
+// block (rows stay sorted inside a block).  Block b's nonzeros form one
+// contiguous CSR with row pointers bptr[b * (rows + 1) + i].
+struct BlockedHost {
+    int32_t B = 0;
+    std::vector<int32_t> bounds;  // [B + 1] gathered-index boundaries
+    std::vector<int32_t> bptr;    // [B * (rows + 1)]
+    std::vector<uint32_t> ent;
+    std::vector<uint16_t> v16;
+    std::vector<float> v32;
+    std::vector<double> v64;
+};
+
+// Tile list of a blocked orientation, laid out so that workgroup w runs on
+// XCD w % 8 and every XCD only touches the gathered slice of one block.
+// Tiles carry the block in bits 24.. of the instance field.
+struct BlockedPlan {
+    int32_t chunk = 0;
+    std::vector<int32_t> tiles;   // 4 ints per tile, empty tiles {0,0,0,-1}
+    std::vector<int32_t> longs;   // {row, slot0, nseg, inst | block << 24}
+    int32_t nslots = 0;
+    std::vector<int32_t> ctiles;  // combine tiles {r0, r1, inst, -1}
+    std::vector<int32_t> ct_begin, ct_end;  // combine tiles per instance
+};
+
+void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_t B, BlockedHost &out);
+void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t> &inst_off, int32_t chunk,
+                  int32_t max_rows, BlockedPlan &plan);
+
 // Validation of one LP description (no GPU).  Returns 0 or -EINVAL.
 int validate_lp(const scylla_lp *lp, std::string &err);
 

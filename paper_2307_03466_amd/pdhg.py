@@ -25,7 +25,7 @@ EXPORTS = [
     "scylla_batch_create", "scylla_batch_destroy", "scylla_batch_set_objective",
     "scylla_batch_set_blend", "scylla_batch_set_start", "scylla_batch_solve",
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
-    "scylla_batch_get_info", "scylla_batch_time_passes",
+    "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
 ]
 
 
@@ -70,7 +70,8 @@ class BatchInfo(ctypes.Structure):
                 ("m_total", ctypes.c_int64), ("n_total", ctypes.c_int64),
                 ("nnz_total", ctypes.c_int64), ("row_chunk", ctypes.c_int32),
                 ("col_chunk", ctypes.c_int32), ("long_rows", ctypes.c_int32),
-                ("long_cols", ctypes.c_int32)]
+                ("long_cols", ctypes.c_int32), ("row_blocks", ctypes.c_int32),
+                ("col_blocks", ctypes.c_int32)]
 
 
 _lib = None
@@ -102,6 +103,7 @@ def lib():
                                               ctypes.POINTER(i32)], ctypes.c_int),
             "scylla_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
             "scylla_batch_time_passes": ([vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
+            "scylla_batch_set_layout": ([vp, i32, i32, i32, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -247,6 +249,10 @@ class Batch:
         x = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
         y = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
         _check(lib().scylla_batch_set_start(self._h, inst, _ptr(x), _ptr(y), omega0))
+
+    def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
+        """Pin the tile plan (0 / 4 / 8 gather blocks, 4 / 8 / 16 nonzeros per thread)."""
+        _check(lib().scylla_batch_set_layout(self._h, row_blocks, row_ept, col_blocks, col_ept))
 
     def time_passes(self, reps: int = 20):
         """Average ms of one launch of the row pass and of the column pass."""

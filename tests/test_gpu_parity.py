@@ -181,3 +181,51 @@ def test_time_limit_status():
     assert s.result["status"] == pdhg.TIME_LIMIT
     k = oracle.kkt(lp, s.x, s.y)
     assert abs(s.result["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
+
+
+LAYOUTS = [(0, 4, 0, 16), (4, 8, 4, 4), (8, 4, 8, 8), (8, 16, 0, 8)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("name", ["general_small", "skewed_longrows"])
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
+def test_layout_parity(layout, name, prec, bar):
+    """Every tile plan (normal or gather-blocked, any tile size) gives the
+    oracle's iterates and the oracle's KKT."""
+    lp = _case(name)
+    print(f"layout {layout} case {name} prec {prec}", flush=True)
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
+    with pdhg.Batch([lp], precision=prec) as b:
+        b.set_layout(*layout)
+        info = b.info()
+        assert (info["row_blocks"], info["col_blocks"]) == (layout[0], layout[2])
+        r = b.solve(tol=1e-300, iter_limit=100, restarts=0)[0]
+        x, y = b.solution(0)
+    assert r["iterations"] == 100
+    assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= bar
+    k = oracle.kkt(lp, x, y)
+    assert abs(r["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
+
+
+@pytest.mark.parametrize("layout", [(8, 8, 4, 8), (4, 4, 8, 16)])
+def test_blocked_batch_termination(layout):
+    lps = I.uneven_batch(count=5, lo=300, hi=4000, seed=21)
+    with pdhg.Batch(lps, precision=1) as b:
+        b.set_layout(*layout)
+        res = b.solve(tol=1e-4, iter_limit=50_000)
+        for i, lp in enumerate(lps):
+            x, y = b.solution(i)
+            assert res[i]["status"] == pdhg.OPTIMAL
+            k = oracle.kkt(lp, x, y)
+            assert k["rel"] <= 1e-4 * (1 + 1e-6)
+            assert abs(res[i]["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
+
+
+def test_autotuned_solve_reaches_tolerance():
+    lp = I.workload(2, scale=0.01)
+    with pdhg.Batch([lp], precision=1) as b:
+        r = b.solve(tol=1e-4, iter_limit=100_000)[0]
+        x, y = b.solution(0)
+        print(b.info(), flush=True)
+    assert r["status"] == pdhg.OPTIMAL
+    assert oracle.kkt(lp, x, y)["rel"] <= 1e-4 * (1 + 1e-6)

@@ -430,7 +430,7 @@ static int fp_row(fp_state *st, int32_t i, int32_t *changed, int32_t *nchanged,
         /* a x_j >= b - (max activity of the other terms)   (G / E rows) */
         if (sn == 'G' || sn == 'E') {
             double own = a > 0 ? hi : lo; /* the term's contribution to max */
-            int own_inf = isinf(own);
+            int own_inf = isinf(own) ? 1 : 0; /* isinf may return -1 for -inf */
             int others_inf = xi - own_inf;
             if (others_inf == 0) {
                 double rest = mx - (own_inf ? 0.0 : a * own);
@@ -442,7 +442,7 @@ static int fp_row(fp_state *st, int32_t i, int32_t *changed, int32_t *nchanged,
         /* a x_j <= b - (min activity of the other terms)   (L / E rows) */
         if (sn == 'L' || sn == 'E') {
             double own = a > 0 ? lo : hi;
-            int own_inf = isinf(own);
+            int own_inf = isinf(own) ? 1 : 0; /* isinf may return -1 for -inf */
             int others_inf = ni - own_inf;
             if (others_inf == 0) {
                 double rest = mn - (own_inf ? 0.0 : a * own);

@@ -183,3 +183,16 @@ def test_pump_invariants_small():
     for r in recs:
         assert np.all(r["xhat"] == np.round(r["xhat"]))
         assert r["xhat_feasible"]
+
+
+def test_fp_propagates_through_a_single_infinite_term():
+    """A row whose activity bound has exactly one infinite term still bounds
+    that term's variable (closed form): with x0 fixed to 1,
+    x0 + 2 x1 <= 3 gives x1 <= 1, and x0 - x2 >= -4 gives x2 <= 5."""
+    inf = np.inf
+    A = np.array([[1.0, 2.0, 0.0], [1.0, 0.0, -1.0]])
+    lp = lp_from_dense(A, [3.0, -4.0], "LG", [0.0, 0.0, 0.0], [0.0, -inf, -inf], [1.0, inf, inf],
+                       is_int=[1, 0, 0])
+    xhat, feas, ign = oracle.fix_propagate(lp, np.array([0.9, 10.0, 20.0]))
+    np.testing.assert_array_equal(xhat, [1.0, 1.0, 5.0])
+    assert feas and ign == 0

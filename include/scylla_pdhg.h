@@ -198,6 +198,52 @@ typedef struct {
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 
+/* ------------------------------------------------------ pump loop
+ * Fix-and-propagate rounding on the host (Section 2.3): integer variables
+ * are fixed one at a time (increasing distance to the nearest integer, ties
+ * by index) to the reference value rounded half down and clamped to the
+ * current domain, each fixing followed by activity-based propagation of the
+ * rows containing the variable (first-in first-out); a row whose activity
+ * bounds exclude b, or whose derived bounds would empty a domain, is
+ * ignored for the rest of the call.  Continuous variables take the
+ * reference value projected onto their domain.  x_ref, x_hat: [n] host;
+ * is_int: [n] 0/1 or NULL (all integer); info[0] = 1 if every row holds at
+ * x_hat within 1e-6 (1 + |b_i|), info[1] = number of ignored rows.  Host
+ * only (no GPU needed).  Returns 0 or -EINVAL. */
+int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const double *x_ref, double *x_hat,
+                         int32_t *info);
+
+/* One record per (round, instance) of scylla_batch_pump. */
+typedef struct {
+    int32_t round;          /* K, 1-based                                     */
+    int32_t status;         /* status of this round's PDHG solve              */
+    int64_t iterations;     /* PDHG iterations of this round                  */
+    double rel_kkt;         /* relative KKT at the returned iterate           */
+    int32_t lp_feasible;    /* the PDHG iterate itself is MIP-feasible (1e-6) */
+    int32_t xhat_feasible;  /* the rounded point satisfies every row (1e-6)   */
+    int32_t ignored_rows;   /* rows ignored by fix-and-propagate              */
+    int32_t reserved;
+    double xhat_obj;        /* c^T x_hat with the original objective          */
+    double solve_seconds;   /* device solve of the round (whole batch)        */
+    double round_seconds;   /* whole round: solve, copy-out, rounding, blend  */
+} scylla_pump_record;
+
+/* Feasibility-pump-like loop of Algorithm 1 on every instance of the batch,
+ * with all `rounds` rounds run: round 1 solves with the original objective
+ * from the projected origin; after round K every instance is rounded on
+ * the host by fix-and-propagate (thread pool of `threads` workers, 0 = one
+ * per hardware thread) and its objective is replaced on the device by
+ * alpha^K sqrt(|I|)/||c|| c + (1 - alpha^K) * (L1-distance gradient to the
+ * rounding); round K + 1 is warm-started from (x, y, omega) of round K.
+ * Cycle perturbation and early exit are not performed.  is_int: [n_total]
+ * 0/1 (instance order) or NULL (all integer; general integers strictly
+ * inside their bounds are rejected with -EINVAL when met).  records:
+ * [rounds * count] (round-major).  xhat_out: [n_total] or NULL, receives per
+ * instance the rounding of the first round whose rounding is feasible, else
+ * the last round's. */
+int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds,
+                      double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out);
+
 /* Pins the tile plan of both passes instead of autotuning it.  The
  * floating-point summation order (so the last bits of the iterates) is a
  * function of the plan; a pinned plan makes results reproducible across

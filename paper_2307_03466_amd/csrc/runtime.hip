@@ -15,6 +15,10 @@
 #include <string>
 #include <vector>
 
+#include <atomic>
+#include <thread>
+
+#include "fixprop.h"
 #include "kernels.h"
 #include "scylla_internal.h"
 
@@ -124,6 +128,15 @@ struct scylla_batch {
     hipGraphExec_t gexec = nullptr;
     int32_t graph_R = 0;
     bool tuned = false;
+    // host copy of the problem (for the pump's rounding on the host)
+    std::vector<double> hval, hb, hl, hu, hc;
+    std::vector<char> hsense;
+    struct LocalLP {
+        std::vector<int32_t> ptr, col, cptr, crow;
+        FPProblem P;
+    };
+    std::vector<LocalLP> local;  // built on the first pump call
+    std::vector<double> pump_best;
     // host mirrors
     std::vector<InstInfo> hinfo;
     InstState *pinned = nullptr;  // 2 * count states
@@ -469,6 +482,11 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
             memcpy(sn.data() + h->row_off[q], lp.senses, lp.A.m);
         }
     }
+    h->hb = b;
+    h->hl = l;
+    h->hu = u;
+    h->hc = c;
+    h->hsense.assign(sn.begin(), sn.end());
     upload(h->c64, c, s);
     upload(h->corig64, c, s);
     upload(h->l64, l, s);
@@ -693,6 +711,172 @@ void put_range(scylla_batch *h, DevMem &d, int32_t lo, int32_t len, const double
     }
 }
 
+void build_locals(scylla_batch *h)
+{
+    if (!h->local.empty()) return;
+    h->local.resize(h->count);
+    const OrientRT &o = h->orow;
+    for (int32_t q = 0; q < h->count; ++q) {
+        auto &L = h->local[q];
+        const int32_t r0 = h->row_off[q], r1 = h->row_off[q + 1], c0 = h->col_off[q];
+        const int32_t e0 = o.host.ptr[r0];
+        L.ptr.resize(r1 - r0 + 1);
+        for (int32_t i = r0; i <= r1; ++i) L.ptr[i - r0] = o.host.ptr[i] - e0;
+        const int32_t nnz = o.host.ptr[r1] - e0;
+        L.col.resize(nnz);
+        for (int32_t e = 0; e < nnz; ++e) {
+            const uint32_t w = o.host.ent[e0 + e];
+            L.col[e] = (int32_t)(h->fmt == FMT_PACKED ? (w & o.host.mask) : w) - c0;
+        }
+        FPProblem &P = L.P;
+        P.m = r1 - r0;
+        P.n = h->col_off[q + 1] - c0;
+        P.ptr = L.ptr.data();
+        P.col = L.col.data();
+        P.val = h->hval.data() + e0;
+        P.b = h->hb.data() + r0;
+        P.sense = h->hsense.data() + r0;
+        P.l = h->hl.data() + c0;
+        P.u = h->hu.data() + c0;
+        build_incidence(P, L.cptr, L.crow);
+    }
+}
+
+template <class F>
+void parallel_for(int32_t count, int32_t threads, F &&f)
+{
+    int32_t nt = threads > 0 ? threads : (int32_t)std::max(1u, std::thread::hardware_concurrency());
+    nt = std::max(1, std::min(nt, count));
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+        for (int32_t q = next++; q < count; q = next++) f(q);
+    };
+    std::vector<std::thread> pool;
+    for (int32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
+}
+
+void reset_objective(scylla_batch *h)
+{
+    HIPC(hipMemcpyAsync(h->c64.p, h->corig64.p, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
+    if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>(), h->cv.as<float>(), h->N, h->stream);
+    else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), h->N, h->stream);
+    launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
+                      h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
+    HIPC(hipGetLastError());
+}
+
+int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds, double alpha,
+              int32_t threads, scylla_pump_record *rec)
+{
+    if (!h || !rec) throw_err(-EINVAL, "handle or records is NULL");
+    if (rounds < 1) throw_err(-EINVAL, "rounds must be >= 1");
+    if (!(alpha >= 0.0 && alpha < 1.0)) throw_err(-EINVAL, "alpha must be in [0, 1)");
+    validate_params(p);
+    build_locals(h);
+    const int32_t N = h->N, count = h->count;
+    std::vector<uint8_t> isint(N, 1);
+    if (is_int)
+        for (int32_t j = 0; j < N; ++j) isint[j] = is_int[j] ? 1 : 0;
+    // kappa_q = sqrt(|I_q|) / ||c_q|| (0 when c = 0: the term is dropped)
+    std::vector<double> kappa(count, 0.0);
+    std::vector<size_t> boff(count + 1, 0);
+    for (int32_t q = 0; q < count; ++q) {
+        double cn = 0.0;
+        int64_t nI = 0;
+        for (int32_t j = h->col_off[q]; j < h->col_off[q + 1]; ++j) {
+            cn += h->hc[j] * h->hc[j];
+            nI += isint[j];
+        }
+        kappa[q] = cn > 0.0 ? sqrt((double)nI) / sqrt(cn) : 0.0;
+        boff[q + 1] = boff[q] + (size_t)(h->col_off[q + 1] - h->col_off[q] + 7) / 8;
+    }
+    std::vector<uint8_t> xbits(boff[count]), ibits(boff[count]);
+    for (int32_t q = 0; q < count; ++q)
+        for (int32_t j = h->col_off[q]; j < h->col_off[q + 1]; ++j) {
+            const int32_t k = j - h->col_off[q];
+            if (isint[j]) ibits[boff[q] + k / 8] |= (uint8_t)(1u << (k % 8));
+        }
+    if (h->bits_tmp.bytes < boff[count]) h->bits_tmp.alloc(boff[count]);
+    if (h->ibits_tmp.bytes < boff[count]) h->ibits_tmp.alloc(boff[count]);
+    HIPC(hipMemcpyAsync(h->ibits_tmp.p, ibits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
+    reset_objective(h);
+    HIPC(hipStreamSynchronize(h->stream));
+
+    std::vector<double> x(N), xhat(N);
+    h->pump_best.assign(N, 0.0);
+    std::vector<uint8_t> found(count, 0);
+    std::vector<scylla_result> res(count);
+    for (int32_t K = 1; K <= rounds; ++K) {
+        const double t0 = now_s();
+        batch_solve_impl(h, p, K > 1 ? 1 : 0, res.data());
+        if (h->vbytes == 4) get_range<float>(h, h->x, 0, N, x.data());
+        else get_range<double>(h, h->x, 0, N, x.data());
+        std::atomic<int> bad{0};
+        parallel_for(count, threads, [&](int32_t q) {
+            const auto &P = h->local[q].P;
+            const int32_t c0 = h->col_off[q];
+            const uint8_t *ii = isint.data() + c0;
+            const double *xq = x.data() + c0;
+            double *xh = xhat.data() + c0;
+            bool integral = true;
+            for (int32_t j = 0; j < P.n; ++j) {
+                if (xq[j] < P.l[j] - 1e-6 || xq[j] > P.u[j] + 1e-6) integral = false;
+                if (ii[j] && fabs(xq[j] - round(xq[j])) > 1e-6) integral = false;
+            }
+            scylla_pump_record &r = rec[(size_t)(K - 1) * count + q];
+            memset(&r, 0, sizeof(r));
+            r.round = K;
+            r.status = res[q].status;
+            r.iterations = res[q].iterations;
+            r.rel_kkt = res[q].rel_kkt;
+            r.lp_feasible = (integral && rows_satisfied(P, xq, 1e-6)) ? 1 : 0;
+            fix_and_propagate(P, ii, xq, xh, &r.xhat_feasible, &r.ignored_rows);
+            double obj = 0.0;
+            for (int32_t j = 0; j < P.n; ++j) obj += h->hc[c0 + j] * xh[j];
+            r.xhat_obj = obj;
+            r.solve_seconds = res[q].solve_seconds;
+            if (!found[q]) {
+                memcpy(h->pump_best.data() + c0, xh, sizeof(double) * P.n);
+                if (r.xhat_feasible) found[q] = 1;
+            }
+            // L1-distance gradient needs every integer at a bound
+            uint8_t *xb = xbits.data() + boff[q];
+            memset(xb, 0, boff[q + 1] - boff[q]);
+            for (int32_t j = 0; j < P.n; ++j) {
+                if (!ii[j]) continue;
+                if (xh[j] == P.u[j] && xh[j] != P.l[j]) xb[j / 8] |= (uint8_t)(1u << (j % 8));
+                else if (xh[j] != P.l[j]) bad = 1;
+            }
+        });
+        if (bad) throw_err(-EINVAL, "an integer variable is rounded strictly inside its bounds: the L1 distance "
+                                    "of general integers needs auxiliary variables");
+        if (K < rounds) {
+            const double a = pow(alpha, (double)K);
+            HIPC(hipMemcpyAsync(h->bits_tmp.p, xbits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
+            for (int32_t q = 0; q < count; ++q) {
+                const int lo = h->col_off[q], hi = h->col_off[q + 1];
+                const uint8_t *xb = h->bits_tmp.as<uint8_t>() + boff[q];
+                const uint8_t *ib = h->ibits_tmp.as<uint8_t>() + boff[q];
+                if (h->vbytes == 4)
+                    launch_blend<float>(h->corig64.as<double>(), xb, ib, a, kappa[q], h->c64.as<double>(),
+                                        h->cv.as<float>(), lo, hi, h->stream);
+                else
+                    launch_blend<double>(h->corig64.as<double>(), xb, ib, a, kappa[q], h->c64.as<double>(),
+                                         h->cv.as<double>(), lo, hi, h->stream);
+            }
+            launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
+                              h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
+            HIPC(hipGetLastError());
+            HIPC(hipStreamSynchronize(h->stream));
+        }
+        const double dt = now_s() - t0;
+        for (int32_t q = 0; q < count; ++q) rec[(size_t)(K - 1) * count + q].round_seconds = dt;
+    }
+    return 0;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -766,6 +950,11 @@ int scylla_batch_create(const scylla_lp *lps, int32_t count, int32_t precision, 
         HIPC(hipHostMalloc((void **)&h->pinned, sizeof(InstState) * 2 * (size_t)count, hipHostMallocDefault));
         if (h->vbytes == 4) setup_device<float>(h.get(), lps, csr, csc);
         else setup_device<double>(h.get(), lps, csr, csc);
+        h->hval.resize(h->NNZ);
+        for (int32_t q = 0, e = 0; q < count; ++q) {
+            memcpy(h->hval.data() + e, lps[q].A.val, sizeof(double) * lps[q].A.nnz);
+            e += (int32_t)lps[q].A.nnz;
+        }
         h->setup_seconds = now_s() - t0;
         *out = h.release();
         return 0;
@@ -920,6 +1109,48 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->long_cols = h->ocol.nlong();
         info->row_blocks = h->orow.blocked ? h->orow.bh.B : 0;
         info->col_blocks = h->ocol.blocked ? h->ocol.bh.B : 0;
+        return 0;
+    });
+}
+
+int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const double *x_ref, double *x_hat,
+                         int32_t *info)
+{
+    return guarded([&]() {
+        std::string err;
+        int rc = validate_lp(lp, err);
+        if (rc) throw_err(rc, err);
+        if (!x_ref || !x_hat || !info) throw_err(-EINVAL, "NULL argument");
+        const scylla_csr &A = lp->A;
+        for (int32_t j = 0; j < A.n; ++j)
+            if (!isfinite(x_ref[j])) throw_err(-EINVAL, "non-finite reference value");
+        std::vector<int32_t> ptr(A.m + 1), cptr, crow;
+        for (int32_t i = 0; i <= A.m; ++i) ptr[i] = (int32_t)A.row_ptr[i];
+        FPProblem P;
+        P.m = A.m;
+        P.n = A.n;
+        P.ptr = ptr.data();
+        P.col = A.col_idx;
+        P.val = A.val;
+        P.b = lp->b;
+        P.sense = lp->senses;
+        P.l = lp->l;
+        P.u = lp->u;
+        build_incidence(P, cptr, crow);
+        std::vector<uint8_t> ii(A.n, 1);
+        if (is_int)
+            for (int32_t j = 0; j < A.n; ++j) ii[j] = is_int[j] ? 1 : 0;
+        fix_and_propagate(P, ii.data(), x_ref, x_hat, &info[0], &info[1]);
+        return 0;
+    });
+}
+
+int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds,
+                      double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out)
+{
+    return guarded([&]() {
+        pump_impl(h, p, is_int, rounds, alpha, threads, records);
+        if (xhat_out) memcpy(xhat_out, h->pump_best.data(), sizeof(double) * h->N);
         return 0;
     });
 }

@@ -26,6 +26,7 @@ EXPORTS = [
     "scylla_batch_set_blend", "scylla_batch_set_start", "scylla_batch_solve",
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
+    "scylla_fix_propagate", "scylla_batch_pump",
 ]
 
 
@@ -104,6 +105,9 @@ def lib():
             "scylla_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
             "scylla_batch_time_passes": ([vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
             "scylla_batch_set_layout": ([vp, i32, i32, i32, i32], ctypes.c_int),
+            "scylla_fix_propagate": ([ctypes.POINTER(LPDesc), vp, vp, vp, vp], ctypes.c_int),
+            "scylla_batch_pump": ([vp, ctypes.POINTER(Params), vp, i32, dbl, i32, ctypes.POINTER(PumpRecord), vp],
+                                  ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -132,6 +136,17 @@ def params(**kw) -> Params:
     return p
 
 
+class PumpRecord(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
+                ("rel_kkt", ctypes.c_double), ("lp_feasible", ctypes.c_int32),
+                ("xhat_feasible", ctypes.c_int32), ("ignored_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("xhat_obj", ctypes.c_double),
+                ("solve_seconds", ctypes.c_double), ("round_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class _LPArrays:
     """Contiguous host copies of one LP kept alive for the duration of a call."""
 
@@ -153,6 +168,18 @@ class _LPArrays:
 def validate(lp) -> None:
     a = _LPArrays(lp)
     _check(lib().scylla_validate_lp(ctypes.byref(a.desc)))
+
+
+def fix_propagate(lp, x_ref, is_int=None):
+    """Host fix-and-propagate rounding (library implementation).  Returns
+    (x_hat, feasible, ignored_rows)."""
+    a = _LPArrays(lp)
+    ii = np.ascontiguousarray(lp.is_int if is_int is None else is_int, dtype=np.uint8)
+    xr = np.ascontiguousarray(x_ref, dtype=np.float64)
+    xh = np.empty(lp.n)
+    info = np.zeros(2, dtype=np.int32)
+    _check(lib().scylla_fix_propagate(ctypes.byref(a.desc), _ptr(ii), _ptr(xr), _ptr(xh), _ptr(info)))
+    return xh, bool(info[0]), int(info[1])
 
 
 @dataclass
@@ -249,6 +276,16 @@ class Batch:
         x = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
         y = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
         _check(lib().scylla_batch_set_start(self._h, inst, _ptr(x), _ptr(y), omega0))
+
+    def pump(self, rounds: int = 20, alpha: float = 0.9, is_int=None, threads: int = 0, **kw):
+        """Native pump loop; returns (records [rounds][count] as dicts, x_hat_all)."""
+        p = params(precision=self.precision, **kw)
+        recs = (PumpRecord * (rounds * self.count))()
+        ii = None if is_int is None else np.ascontiguousarray(is_int, dtype=np.uint8)
+        xh = np.empty(sum(self.n))
+        _check(lib().scylla_batch_pump(self._h, ctypes.byref(p), _ptr(ii), rounds, alpha, threads, recs, _ptr(xh)))
+        out = [[recs[k * self.count + q].as_dict() for q in range(self.count)] for k in range(rounds)]
+        return out, xh
 
     def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
         """Pin the tile plan (0 / 4 / 8 gather blocks, 4 / 8 / 16 nonzeros per thread)."""

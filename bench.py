@@ -1,17 +1,19 @@
 #!/usr/bin/env python
 """Benchmark of the PDHG hot path on one MI355X.
 
-Workload: the single large general LP (m = 1,000,000 rows, n = 2,000,000
-columns, ~10M nonzeros, geometric row lengths, integer coefficients in
-[-20, 20]), synthetic and seeded.  A step is one check window of the
-solver: the FP64 KKT check and decision plus R = 64 PDHG iterations (column
-pass + row pass), all replayed from one hipGraph.  value = PDHG iterations/s
-of the FP32 path with the problem resident in HBM.
+Headline workload: the single large general LP (m = 1,000,000 rows,
+n = 2,000,000 columns, ~10M nonzeros, geometric row lengths, integer
+coefficients in [-20, 20]), synthetic and seeded.  A step is one check
+window of the solver: the FP64 KKT check and decision plus R = 64 PDHG
+iterations (column pass + row pass), replayed from one hipGraph.
+value = PDHG iterations/s of the FP32 path with the problem resident in HBM.
 
-Also reported: the plain FP64 path's iteration rate on the same LP, the time
-of both paths to reach relative KKT <= 1e-4, the dominant kernel's roofline
-(algorithmic bytes per launch over its HIP-event launch time, against the
-8 TB/s HBM peak) and, as a baseline, the FP64 CPU oracle on a bounded sample.
+Also reported: the plain FP64 path on the same LP, both paths' time to
+relative KKT <= 1e-4, the dominant kernel's HBM roofline (algorithmic bytes
+per launch over its HIP-event launch time) and its random-gather ceiling
+(measured live), the other four workloads (tiny set cover, skewed LP,
+256-instance batch, 64-instance pump loop), and the FP64 CPU oracle on a
+bounded sample as a baseline.
 """
 from __future__ import annotations
 
@@ -45,9 +47,9 @@ def pass_bytes(info: dict, vb: int):
 
 
 def canonical_bytes(m, n, nnz, fp64=False):
-    """Per-iteration byte model of the survey's FP32 / FP64 path (BF16 / FP64
-    values, int32 indices): both passes' matrix streams and pointers, the
-    per-column and per-row vector traffic and one full gather of each vector."""
+    """Per-iteration byte model of the survey (BF16 / FP64 values, int32
+    indices): both matrix streams and pointers, per-column and per-row vector
+    traffic, one full gather of each vector."""
     if fp64:
         return 2 * nnz * 12 + 4 * (m + 1) + 4 * (n + 1) + 56 * n + 33 * m + 8 * (m + n)
     return 2 * nnz * 6 + 4 * (m + 1) + 4 * (n + 1) + 28 * n + 17 * m + 4 * (m + n)
@@ -57,11 +59,36 @@ def timed_steps(batch, steps, R):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = batch.solve(tol=1e-300, iter_limit=steps * R, check_period=R)[0]
+    res = batch.solve(tol=1e-300, iter_limit=steps * R, check_period=R)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    assert res["iterations"] == steps * R, res
+    assert all(r["iterations"] == steps * R for r in res), res[0]
     return dt, res
+
+
+def measure(pdhg, lps, prec, steps, warmup, R, to_tol, tol_time_limit, passes=True):
+    """Iteration rate (timed windows), pass timings and time to 1e-4 of one
+    handle holding `lps`."""
+    b = pdhg.Batch(lps, precision=prec)
+    setup = b.solve(tol=1e-300, iter_limit=0)[0]["setup_seconds"]  # includes the tuning run
+    b.solve(tol=1e-300, iter_limit=max(1, warmup) * R, check_period=R)
+    info = b.info()
+    dt, _ = timed_steps(b, steps, R)
+    its = steps * R
+    rec = dict(info=info, setup_s=setup, seconds=dt, iters=its, iter_per_s=its / dt,
+               ms_per_step=1000 * dt / steps)
+    if passes:
+        ms_row, ms_col = b.time_passes(20)
+        rb, cb = pass_bytes(info, 4 if prec == pdhg.FP32 else 8)
+        rec.update(ms_row=ms_row, ms_col=ms_col, bytes_row=rb, bytes_col=cb)
+    if to_tol:
+        res = b.solve(tol=1e-4, iter_limit=2_000_000, time_limit_s=tol_time_limit)
+        rec["to_tol"] = dict(status=max(r["status"] for r in res), optimal=sum(r["status"] == 1 for r in res),
+                             count=len(res), iterations_max=max(r["iterations"] for r in res),
+                             iterations_sum=sum(r["iterations"] for r in res),
+                             seconds=res[0]["solve_seconds"], rel_kkt_max=max(r["rel_kkt"] for r in res))
+    b.close()
+    return rec
 
 
 def cpu_baseline(lp, iters):
@@ -72,9 +99,84 @@ def cpu_baseline(lp, iters):
     oracle.pdhg(lp, tol=-1.0, iter_limit=iters)
     t2 = time.perf_counter()
     per_iter = ((t2 - t1) - (t1 - t0)) / iters
-    return dict(value=1.0 / per_iter, unit="iter/s", cores=1, kind="oracle",
+    return dict(value=round(1.0 / per_iter, 3), unit="iter/s", cores=1, kind="oracle",
                 sample=f"{iters} FP64 PDHG iterations of the same 1M x 2M LP by the single-threaded C "
                        f"oracle (preconditioning and the start check subtracted; {t2 - t0:.1f} s of CPU)")
+
+
+def other_workloads(pdhg, instances, args, R):
+    out = {}
+    sel = set(args.workloads.split(","))
+    if "1" in sel:  # tiny set cover, FP64, latency-bound; then rounding on the host
+        lp = instances.workload(1)
+        r = measure(pdhg, [lp], pdhg.FP64, 50, 3, R, True, 30, passes=False)
+        s = pdhg.solve(lp, tol=1e-4, iter_limit=200_000, precision=pdhg.FP64)
+        t = time.perf_counter()
+        xh, feas, ign = pdhg.fix_propagate(lp, s.x)
+        out["set_cover_200x500_fp64"] = dict(iter_per_s=round(r["iter_per_s"], 1), to_tol=r["to_tol"],
+                                             rounding_s=round(time.perf_counter() - t, 6),
+                                             rounding_feasible=feas, rounded_obj=float(lp.c @ xh))
+        log(f"w1: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} rounding feasible={feas}")
+    if "3" in sel:  # skewed LP, FP32 and FP64
+        lp = instances.workload(3)
+        rec = {}
+        for prec, tag in ((pdhg.FP32, "fp32"), (pdhg.FP64, "fp64")):
+            r = measure(pdhg, [lp], prec, 20, 2, R, True, args.tol_time_limit)
+            rb, cb = r["bytes_row"], r["bytes_col"]
+            rec[tag] = dict(iter_per_s=round(r["iter_per_s"], 1), ms_row=round(r["ms_row"], 4),
+                            ms_col=round(r["ms_col"], 4), row_GBps=round(rb / r["ms_row"] / 1e6, 1),
+                            col_GBps=round(cb / r["ms_col"] / 1e6, 1), to_tol=r["to_tol"],
+                            layout=[r["info"]["row_blocks"], r["info"]["row_chunk"], r["info"]["col_blocks"],
+                                    r["info"]["col_chunk"]], long_rows=r["info"]["long_rows"])
+            log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']}")
+        rec["canonical_GBps_fp32"] = round(canonical_bytes(lp.m, lp.n, lp.nnz) * rec["fp32"]["iter_per_s"] / 1e9, 1)
+        out["skewed_lp_500kx1M"] = rec
+        del lp
+    if "4" in sel:  # 256 uneven LPs in one handle; FP64 plain = one instance at a time
+        lps = instances.workload(4)
+        r = measure(pdhg, lps, pdhg.FP32, 20, 2, R, True, args.tol_time_limit)
+        rec = dict(count=len(lps), batch_iter_per_s=round(r["iter_per_s"], 1),
+                   instance_iter_per_s=round(r["iter_per_s"] * len(lps), 1), ms_row=round(r["ms_row"], 4),
+                   ms_col=round(r["ms_col"], 4), to_tol_fp32_batched=r["to_tol"],
+                   canonical_GBps=round(canonical_bytes(sum(l.m for l in lps), sum(l.n for l in lps),
+                                                        sum(l.nnz for l in lps)) * r["iter_per_s"] / 1e9, 1))
+        log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r['to_tol']}")
+        if args.fp64_plain_batch:
+            t = time.perf_counter()
+            done = 0
+            for lp in lps:
+                s = pdhg.solve(lp, tol=1e-4, iter_limit=2_000_000, precision=pdhg.FP64, autotune=0)
+                done += s.result["status"] == 1
+                if time.perf_counter() - t > args.tol_time_limit * 3:
+                    break
+            n_done = lps.index(lp) + 1
+            el = time.perf_counter() - t
+            rec["to_tol_fp64_plain_sequential"] = dict(seconds=round(el, 3), instances=n_done, optimal=done)
+            if n_done == len(lps) and r["to_tol"]["optimal"] == len(lps):
+                rec["speedup_fp32_batched_vs_fp64_plain_to_tol"] = round(el / r["to_tol"]["seconds"], 2)
+            log(f"w4 fp64 plain sequential: {n_done} instances in {el:.1f}s")
+        out["batch_256_uneven"] = rec
+        del lps
+    if "5" in sel:  # pump loop: 64 x (20k x 40k), 20 rounds
+        lps = instances.workload(5)
+        b = pdhg.Batch(lps, precision=pdhg.FP32)
+        t = time.perf_counter()
+        recs, xh = b.pump(rounds=args.pump_rounds, alpha=0.9, tol=1e-4, iter_limit=200_000)
+        el = time.perf_counter() - t
+        its = [max(r["iterations"] for r in rnd) for rnd in recs]
+        solve_s = sum(rnd[0]["solve_seconds"] for rnd in recs)
+        first = [next((k + 1 for k in range(len(recs)) if recs[k][q]["xhat_feasible"]), None)
+                 for q in range(len(lps))]
+        out["pump_64x20k"] = dict(rounds=len(recs), seconds=round(el, 3), solve_seconds=round(solve_s, 3),
+                                  batch_iterations=sum(its),
+                                  batch_iter_per_s=round(sum(its) / solve_s, 1),
+                                  iterations_round1=its[0], iterations_last=its[-1],
+                                  instances_feasible=sum(f is not None for f in first),
+                                  mean_first_feasible_round=(round(sum(f for f in first if f) /
+                                                                   max(1, sum(f is not None for f in first)), 2)))
+        log(f"w5 pump: {out['pump_64x20k']}")
+        b.close()
+    return out
 
 
 def main():
@@ -83,12 +185,15 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--check-period", type=int, default=64)
-    ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1 = full size)")
+    ap.add_argument("--scale", type=float, default=1.0, help="headline workload scale (1 = full size)")
     ap.add_argument("--to-tol", type=int, default=1, help="also time both paths to 1e-4 rel KKT")
     ap.add_argument("--tol-time-limit", type=float, default=60.0)
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="fp32,fp64", help="paths to run (profiling runs may pick one)")
+    ap.add_argument("--workloads", default="1,3,4,5", help="other workloads to measure ('' for none)")
+    ap.add_argument("--pump-rounds", type=int, default=20)
+    ap.add_argument("--fp64-plain-batch", type=int, default=1)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -99,7 +204,6 @@ def main():
               "and a multi-GPU run would only shard them; pass --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2307_03466_amd import instances, pdhg
@@ -122,44 +226,37 @@ def main():
     log(f"generated {lp.name}: m={lp.m} n={lp.n} nnz={lp.nnz} in {time.perf_counter() - t:.1f}s")
 
     out = {}
-    legs = [(p, t) for p, t in ((pdhg.FP32, "fp32"), (pdhg.FP64, "fp64")) if t in args.legs.split(",")]
+    legs = [(p, tg) for p, tg in ((pdhg.FP32, "fp32"), (pdhg.FP64, "fp64")) if tg in args.legs.split(",")]
     for prec, tag in legs:
-        b = pdhg.Batch([lp], precision=prec)
-        info = b.info()
-        setup = b.solve(tol=1e-300, iter_limit=0)[0]["setup_seconds"]
-        b.solve(tol=1e-300, iter_limit=max(1, args.warmup) * R, check_period=R)  # autotune + warm-up
-        dt, res = timed_steps(b, args.steps, R)
-        its = args.steps * R
-        ms_row, ms_col = b.time_passes(20)
-        vb = 4 if prec == pdhg.FP32 else 8
-        rb, cb = pass_bytes(info, vb)
-        rec = dict(info=info, setup_s=setup, seconds=dt, iters=its, iter_per_s=its / dt,
-                   ms_per_step=1000 * dt / args.steps, ms_row=ms_row, ms_col=ms_col,
-                   bytes_row=rb, bytes_col=cb, rel_kkt_end=res["rel_kkt"])
-        log(f"{tag}: {its / dt:,.0f} iter/s  row pass {ms_row * 1e3:.1f} us ({rb / ms_row / 1e6:,.0f} GB/s)  "
-            f"col pass {ms_col * 1e3:.1f} us ({cb / ms_col / 1e6:,.0f} GB/s)  format={info['format_name']} "
-            f"chunks={info['row_chunk']}/{info['col_chunk']}")
+        rec = measure(pdhg, [lp], prec, args.steps, args.warmup, R, args.to_tol, args.tol_time_limit)
+        info = rec["info"]
+        log(f"{tag}: {rec['iter_per_s']:,.0f} iter/s  row pass {rec['ms_row'] * 1e3:.1f} us "
+            f"({rec['bytes_row'] / rec['ms_row'] / 1e6:,.0f} GB/s)  col pass {rec['ms_col'] * 1e3:.1f} us "
+            f"({rec['bytes_col'] / rec['ms_col'] / 1e6:,.0f} GB/s)  format={info['format_name']} "
+            f"layout row B={info['row_blocks']}/{info['row_chunk']} col B={info['col_blocks']}/{info['col_chunk']}")
         if args.to_tol:
-            r = b.solve(tol=1e-4, iter_limit=2_000_000, time_limit_s=args.tol_time_limit)[0]
-            rec["to_tol"] = dict(status=r["status"], iterations=r["iterations"], seconds=r["solve_seconds"],
-                                 rel_kkt=r["rel_kkt"], restarts=r["restarts"], primal_obj=r["primal_obj"])
-            log(f"{tag}: to 1e-4: status={r['status']} iters={r['iterations']} "
-                f"{r['solve_seconds']:.2f}s rel={r['rel_kkt']:.3e} obj={r['primal_obj']:.6f}")
-        b.close()
+            log(f"{tag}: to 1e-4: {rec['to_tol']}")
         out[tag] = rec
 
     if "fp32" not in out or "fp64" not in out:
         log("partial run (--legs): no JSON line")
         return
     f32 = out["fp32"]
+    info = f32["info"]
     dom_is_col = f32["ms_col"] >= f32["ms_row"]
     dom_ms = f32["ms_col"] if dom_is_col else f32["ms_row"]
     dom_bytes = f32["bytes_col"] if dom_is_col else f32["bytes_row"]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    blocks = info["col_blocks"] if dom_is_col else info["row_blocks"]
+    gathered = (info["m_total"] if dom_is_col else info["n_total"]) * 4 // max(1, blocks)
+    probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
-                    kernel="k_pass<float,packed,%s>" % ("column" if dom_is_col else "row"),
-                    bytes_per_launch=dom_bytes, launch_ms=round(dom_ms, 5))
+                    kernel=("column" if dom_is_col else "row") + " pass (" +
+                    ("k_bpart + k_bcombine, %d gather blocks" % blocks if blocks else "k_pass") + ")",
+                    bytes_per_launch=dom_bytes, launch_ms=round(dom_ms, 5),
+                    gather_ceiling={"gathers": info["nnz_total"], "vector_bytes_per_xcd": gathered,
+                                    "probe_ms": round(probe_ms, 5), "frac": round(probe_ms / dom_ms, 3)})
     path_bytes = f32["bytes_row"] + f32["bytes_col"]
     line = {
         "metric": METRIC,
@@ -177,7 +274,9 @@ def main():
         "config": {"workload": f"general LP {lp.m} x {lp.n}, {lp.nnz} nonzeros (geometric row lengths, "
                                f"integers in [-20,20]), one instance",
                    "m": lp.m, "n": lp.n, "nnz": lp.nnz, "check_period": R,
-                   "matrix_format": f32["info"]["format_name"],
+                   "matrix_format": info["format_name"],
+                   "layout": {"row_blocks": info["row_blocks"], "row_chunk": info["row_chunk"],
+                              "col_blocks": info["col_blocks"], "col_chunk": info["col_chunk"]},
                    "step": f"KKT check + decision + {R} PDHG iterations (one hipGraph)"},
         "roofline": roofline,
         "path_GBps": round(path_bytes * f32["iter_per_s"] / 1e9, 1),
@@ -194,10 +293,11 @@ def main():
         if out["fp32"]["to_tol"]["status"] == 1 and out["fp64"]["to_tol"]["status"] == 1:
             line["speedup_fp32_vs_fp64_to_tol"] = round(out["fp64"]["to_tol"]["seconds"]
                                                         / out["fp32"]["to_tol"]["seconds"], 3)
+    if args.workloads:
+        line["workloads"] = other_workloads(pdhg, instances, args, R)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters)
-        line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 3)
     print(json.dumps(line), flush=True)
 
 

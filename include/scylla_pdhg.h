@@ -260,6 +260,14 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
  * of each in milliseconds, measured with HIP events.  reps >= 1. */
 int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, double *ms_col);
 
+/* Profiling aid: the device's rate of random 4-byte gathers, the cost that
+ * bounds both passes (every nonzero gathers one element of the other
+ * vector).  Runs `gathers` gathers at hashed positions of a float vector of
+ * `vec_bytes` bytes (4 <= vec_bytes <= 1 GiB, 1 <= gathers <= 2^31) on the
+ * current device and returns the average duration of one launch in ms
+ * (HIP events, 10 launches after a warm-up).  Allocates its own buffers. */
+int scylla_probe_gather(int64_t vec_bytes, int64_t gathers, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

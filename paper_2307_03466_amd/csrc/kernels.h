@@ -68,6 +68,8 @@ template <class V>
 void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, bool blocked,
                  hipStream_t s);
 void launch_decide(const DecideArgs &d, int count, hipStream_t s);
+void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s);
+void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, hipStream_t s);
 void launch_force_stop(InstState *st, int count, hipStream_t s);
 void launch_scale_reduce(const MatView &M, int fmt, int rows, const double *drow, const double *dcol,
                          double *out, int mode, hipStream_t s);

@@ -716,6 +716,56 @@ __global__ void k_blend(const double *c_orig, const uint8_t *xbits, const uint8_
     cv[j] = (V)v;
 }
 
+// ----------------------------------------------------- gather probe
+// Device ceiling of the passes' dominant cost: random 4-byte gathers from a
+// vector of a given size.  Indices are a fixed hash of the position, taken
+// modulo the vector length (always in range).
+__global__ void k_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (int64_t)len) vec[i] = (float)(i & 1023) * 0.001f;
+    if (i >= n) return;
+    uint32_t x = (uint32_t)i * 2654435761u ^ 0x9e3779b9u;
+    x ^= x >> 13;
+    x *= 0x5bd1e995u;
+    x ^= x >> 15;
+    x *= 0x27d4eb2du;
+    x ^= x >> 16;
+    idx[i] = x % len;
+}
+
+__global__ __launch_bounds__(256) void k_probe_gather(const uint32_t *__restrict__ idx,
+                                                     const float *__restrict__ vec, float *__restrict__ out,
+                                                     int64_t n)
+{
+    constexpr int K = 8;
+    const int64_t base = (int64_t)blockIdx.x * 256 * K + threadIdx.x;
+    uint32_t w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t e = base + (int64_t)k * 256;
+        w[k] = e < n ? __builtin_nontemporal_load(idx + e) : 0u;
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t e = base + (int64_t)k * 256;
+        if (e < n) s += vec[w[k]];
+    }
+    out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s)
+{
+    const int64_t m = n > (int64_t)len ? n : (int64_t)len;
+    hipLaunchKernelGGL(k_probe_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, idx, n, len, vec);
+}
+
+void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_probe_gather, dim3((unsigned)((n + 2047) / 2048)), dim3(256), 0, s, idx, vec, out, n);
+}
+
 // ------------------------------------------------------ host launchers
 template <class V, int FMT, int DIR, int NT, int EPT>
 static void launch_pass_t(const PassArgs<V> &p, int jw, hipStream_t s)

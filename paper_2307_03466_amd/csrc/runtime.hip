@@ -1195,6 +1195,40 @@ int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, doub
     });
 }
 
+int scylla_probe_gather(int64_t vec_bytes, int64_t gathers, double *ms)
+{
+    return guarded([&]() {
+        if (!ms || vec_bytes < 4 || vec_bytes > ((int64_t)1 << 30) || gathers < 1 || gathers > ((int64_t)1 << 31))
+            throw_err(-EINVAL, "bad argument");
+        check_device();
+        const uint32_t len = (uint32_t)(vec_bytes / 4);
+        DevMem idx, vec, out;
+        idx.alloc((size_t)gathers * 4);
+        vec.alloc((size_t)len * 4);
+        out.alloc((size_t)((gathers + 2047) / 2048) * 256 * 4);
+        hipStream_t s = nullptr;
+        HIPC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        std::unique_ptr<std::remove_pointer<hipStream_t>::type, void (*)(hipStream_t)> sg(
+            s, [](hipStream_t x) { (void)hipStreamDestroy(x); });
+        hipEvent_t e0, e1;
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        launch_probe_init(idx.as<uint32_t>(), gathers, len, vec.as<float>(), s);
+        launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, s);
+        HIPC(hipEventRecord(e0, s));
+        for (int r = 0; r < 10; ++r) launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, s);
+        HIPC(hipEventRecord(e1, s));
+        HIPC(hipEventSynchronize(e1));
+        HIPC(hipGetLastError());
+        float t = 0;
+        HIPC(hipEventElapsedTime(&t, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms = (double)t / 10.0;
+        return 0;
+    });
+}
+
 int scylla_pdhg_solve(const scylla_csr *A, const double *c, const double *b, const char *senses, const double *l,
                       const double *u, const scylla_params *p, const double *x0, const double *y0, double *x_out,
                       double *y_out, scylla_result *res)

@@ -26,7 +26,7 @@ EXPORTS = [
     "scylla_batch_set_blend", "scylla_batch_set_start", "scylla_batch_solve",
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
-    "scylla_fix_propagate", "scylla_batch_pump",
+    "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
             "scylla_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
             "scylla_batch_time_passes": ([vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
             "scylla_batch_set_layout": ([vp, i32, i32, i32, i32], ctypes.c_int),
+            "scylla_probe_gather": ([ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(dbl)], ctypes.c_int),
             "scylla_fix_propagate": ([ctypes.POINTER(LPDesc), vp, vp, vp, vp], ctypes.c_int),
             "scylla_batch_pump": ([vp, ctypes.POINTER(Params), vp, i32, dbl, i32, ctypes.POINTER(PumpRecord), vp],
                                   ctypes.c_int),
@@ -180,6 +181,14 @@ def fix_propagate(lp, x_ref, is_int=None):
     info = np.zeros(2, dtype=np.int32)
     _check(lib().scylla_fix_propagate(ctypes.byref(a.desc), _ptr(ii), _ptr(xr), _ptr(xh), _ptr(info)))
     return xh, bool(info[0]), int(info[1])
+
+
+def probe_gather(vec_bytes: int, gathers: int) -> float:
+    """Average ms of one launch of `gathers` random 4-byte gathers from a
+    vector of `vec_bytes` bytes (the passes' ceiling)."""
+    ms = ctypes.c_double()
+    _check(lib().scylla_probe_gather(int(vec_bytes), int(gathers), ctypes.byref(ms)))
+    return ms.value
 
 
 @dataclass

@@ -193,8 +193,12 @@ typedef struct {
     int64_t m_total, n_total, nnz_total;
     int32_t row_chunk, col_chunk; /* tile sizes in use (nonzeros per tile) */
     int32_t long_rows, long_cols; /* rows / columns split over several tiles */
-    int32_t row_blocks, col_blocks; /* gather blocks of each pass (0: the
-                                       normal layout)                        */
+    int32_t row_blocks, col_blocks; /* layout of each pass: 0 normal, 4 or 8
+                                       gather blocks, -1 LDS-staged          */
+    int32_t row_staged_nnz, col_staged_nnz; /* staged tile size (nonzeros)  */
+    int32_t row_staged_variant, col_staged_variant; /* staged kernel variant:
+                                       sub-tile 4096 (0, 1) or 8192 (2, 3)
+                                       nonzeros; odd = operand prefetch      */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 
@@ -248,8 +252,11 @@ int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is
  * floating-point summation order (so the last bits of the iterates) is a
  * function of the plan; a pinned plan makes results reproducible across
  * runs and devices.  *_blocks: 0 = normal layout, 4 or 8 = gather-blocked
- * layout with that many blocks (one per XCD or per XCD pair); *_ept: 4, 8 or
- * 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL otherwise. */
+ * layout with that many blocks (one per XCD or per XCD pair), -1 = LDS-staged
+ * layout (instances whose gathered vector fits in LDS are processed with
+ * that vector copied to LDS, in tiles of about 32768 nonzeros); *_ept: 4, 8
+ * or 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL
+ * otherwise. */
 int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,
                             int32_t col_ept);
 

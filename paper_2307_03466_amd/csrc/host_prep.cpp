@@ -175,7 +175,7 @@ int build_orientations(const scylla_lp *lps, int32_t count, int32_t precision, H
 }
 
 void plan_tiles(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
-                int32_t chunk, int32_t max_rows, TilePlan &plan)
+                int32_t chunk, int32_t max_rows, TilePlan &plan, const uint8_t *skip)
 {
     const int32_t count = (int32_t)inst_off.size() - 1;
     plan.chunk = chunk;
@@ -190,7 +190,7 @@ void plan_tiles(const std::vector<int32_t> &ptr, const std::vector<int32_t> &ins
         plan.t_begin[q] = (int32_t)(plan.tiles.size() / 4);
         plan.l_begin[q] = (int32_t)(plan.longs.size() / 4);
         int32_t r = inst_off[q];
-        const int32_t rend = inst_off[q + 1];
+        const int32_t rend = (skip && skip[q]) ? r : inst_off[q + 1];
         while (r < rend) {
             int32_t len = ptr[r + 1] - ptr[r];
             if (len > chunk) {
@@ -318,6 +318,44 @@ void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t
             plan.ctiles.insert(plan.ctiles.end(), {r, std::min(r + 256, inst_off[q + 1]), q, -1});
         plan.ct_end[q] = (int32_t)(plan.ctiles.size() / 4);
     }
+}
+
+void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
+                 const std::vector<int32_t> &gofs, int32_t max_vec, int32_t sub_chunk, int32_t group_nnz,
+                 int32_t rest_chunk, StagedPlan &plan)
+{
+    const int32_t count = (int32_t)inst_off.size() - 1;
+    plan.tiles.clear();
+    plan.staged.assign(count, 0);
+    plan.max_vec = 0;
+    std::vector<uint8_t> not_staged(count, 1);
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t glen = gofs[q + 1] - gofs[q];
+        if (glen > max_vec || inst_off[q + 1] == inst_off[q]) continue;
+        bool short_rows = true;
+        for (int32_t r = inst_off[q]; r < inst_off[q + 1] && short_rows; ++r)
+            short_rows = ptr[r + 1] - ptr[r] <= sub_chunk;
+        if (!short_rows) continue;
+        plan.staged[q] = 1;
+        not_staged[q] = 0;
+        plan.max_vec = std::max(plan.max_vec, glen);
+    }
+    plan_tiles(ptr, inst_off, sub_chunk, 4 * 1024, plan.sub, not_staged.data());
+    for (int32_t q = 0; q < count; ++q) {
+        if (!plan.staged[q]) continue;
+        int32_t t = plan.sub.t_begin[q];
+        while (t < plan.sub.t_end[q]) {
+            const int32_t start = t;
+            int64_t nz = 0;
+            while (t < plan.sub.t_end[q] && nz < group_nnz) {
+                const int32_t *d = plan.sub.tiles.data() + 4 * t;
+                nz += ptr[d[1]] - ptr[d[0]];
+                ++t;
+            }
+            plan.tiles.insert(plan.tiles.end(), {start, t, q, -1});
+        }
+    }
+    plan_tiles(ptr, inst_off, rest_chunk, 1024, plan.rest, plan.staged.data());
 }
 
 }  // namespace scy

@@ -53,7 +53,16 @@ struct PassArgs {
     double *P64;          // [B * rows] block partial sums (check)
     const int4 *ctiles;   // combine tiles {r0, r1, inst, -1}
     int32_t nctiles;
+    // LDS-staged pass
+    const int32_t *gofs;  // [count + 1] gathered-vector offsets per instance
+    const int4 *sub;      // sub-tiles {r0, r1, inst, -1} of the staged tiles
 };
+
+// LDS-staged pass: 1024 threads; variant v: nonzeros per thread per
+// sub-tile 4 (v = 0, 1) or 8 (v = 2, 3); odd v prefetch the next
+// sub-tile's row bounds and epilogue operands as well.
+constexpr int SPASS_NT = 1024;
+inline int spass_chunk(int variant) { return SPASS_NT * (variant >= 2 ? 8 : 4); }
 
 struct DecideArgs {
     InstState *st;
@@ -67,6 +76,12 @@ struct DecideArgs {
 template <class V>
 void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool check, bool blocked,
                  hipStream_t s);
+// LDS-staged pass over staged tiles {sub0, sub1, inst, -1} (ranges of
+// sub-tiles); shmem = product buffer + largest staged vector, in bytes.  prepare = true only raises the
+// kernel's dynamic-LDS limit (call once before launching or capturing).
+template <class V>
+void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, size_t shmem, hipStream_t s,
+                   bool prepare);
 void launch_decide(const DecideArgs &d, int count, hipStream_t s);
 void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s);
 void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, hipStream_t s);

@@ -354,6 +354,122 @@ __global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int
     apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops);
 }
 
+// ------------------------------------------- LDS-staged pass (small instances)
+// When an instance's whole gathered vector fits in LDS, one workgroup copies
+// it there once and then walks a run of sub-tiles of that instance (whole
+// rows, <= NT*EPT nonzeros each): every gather is an LDS read.  The loop is
+// software-pipelined: the coalesced loads of sub-tile t+1's nonzeros are in
+// flight while sub-tile t's rows are reduced and updated.
+template <class V, int FMT, int NT, int EPT>
+__device__ __forceinline__ void spass_load(const MatView &M, int e0, int e1, uint32_t (&w)[EPT], V (&a)[EPT])
+{
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = e0 + q * NT + (int)threadIdx.x;
+        w[q] = 0;
+        a[q] = (V)0;
+        if (e < e1) load_entry<FMT, V>(M, e, w[q], a[q]);
+    }
+}
+
+template <class V, int FMT, int DIR, int NT, int EPT, bool PF>
+__global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
+{
+    constexpr int CH = NT * EPT;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V *prod = reinterpret_cast<V *>(lds_raw);  // [CH]
+    V *sv = prod + CH;                         // [gathered length]
+    const int4 T = p.tiles[xcd_tile(blockIdx.x, gridDim.x)];  // {sub0, sub1, inst, -}
+    const InstState &S = p.st[T.z];
+    if (S.status != ST_RUN || jw >= S.nrun) return;
+    const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+    const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    const int tid = threadIdx.x;
+    const int g0 = p.gofs[T.z], glen = p.gofs[T.z + 1] - g0;
+    // sub-tile state (nonzeros in registers one sub-tile ahead; with PF also
+    // this thread's first row bounds and epilogue operands)
+    int4 D = p.sub[T.x];
+    int e0 = p.M.ptr[D.x], e1 = p.M.ptr[D.y];
+    uint32_t w[EPT];
+    V a[EPT];
+    spass_load<V, FMT, NT, EPT>(p.M, e0, e1, w, a);
+    int L = 1, r = 0, rb = 0, re = 0;
+    RowOps<V> ops;
+    if (PF) {
+        L = lanes_per_row<NT>(D.y - D.x);
+        r = tid / L;
+        if (r < D.y - D.x) {
+            rb = p.M.ptr[D.x + r] - e0;
+            re = p.M.ptr[D.x + r + 1] - e0;
+            if ((tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
+        }
+    }
+    for (int k = tid; k < glen; k += NT) sv[k] = p.gvec[g0 + k];
+    __syncthreads();
+    for (int t = T.x; t < T.y; ++t) {
+        // products of sub-tile t from the registers
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = e0 + q * NT + tid;
+            if (e < e1) {
+                const int idx = decode_entry<FMT, V>(p.M, w[q], a[q]);
+                prod[e - e0] = a[q] * sv[idx - g0];
+            }
+        }
+        const int r0c = D.x, nrows = D.y - D.x, e0c = e0;
+        int Lc, rc, rbc, rec;
+        RowOps<V> opc;
+        if (PF) {
+            Lc = L;
+            rc = r;
+            rbc = rb;
+            rec = re;
+            opc = ops;
+        } else {
+            Lc = lanes_per_row<NT>(nrows);
+            rc = tid / Lc;
+            rbc = rec = 0;
+            if (rc < nrows) {
+                rbc = p.M.ptr[r0c + rc] - e0c;
+                rec = p.M.ptr[r0c + rc + 1] - e0c;
+                if ((tid & (Lc - 1)) == 0) load_ops<V, DIR>(p, r0c + rc, opc);
+            }
+        }
+        __syncthreads();
+        // sub-tile t+1's nonzeros (and with PF its row bounds and operands)
+        // are in flight during this reduction
+        if (t + 1 < T.y) {
+            D = p.sub[t + 1];
+            e0 = p.M.ptr[D.x];
+            e1 = p.M.ptr[D.y];
+            spass_load<V, FMT, NT, EPT>(p.M, e0, e1, w, a);
+            if (PF) {
+                L = lanes_per_row<NT>(D.y - D.x);
+                r = tid / L;
+                if (r < D.y - D.x) {
+                    rb = p.M.ptr[D.x + r] - e0;
+                    re = p.M.ptr[D.x + r + 1] - e0;
+                    if ((tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
+                }
+            }
+        }
+        const int groups = NT / Lc, lane = tid & (Lc - 1);
+        for (; rc < nrows; rc += groups) {
+            V sum = 0;
+            for (int q = rbc + lane; q < rec; q += Lc) sum += prod[q];
+            if (Lc > 1) sum = wave_sum_width(sum, Lc);
+            if (lane == 0) apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc);
+            const int rn = rc + groups;
+            if (rn < nrows) {
+                rbc = p.M.ptr[r0c + rn] - e0c;
+                rec = p.M.ptr[r0c + rn + 1] - e0c;
+                if (lane == 0) load_ops<V, DIR>(p, r0c + rn, opc);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Long rows: add the segment partials in segment order, then the epilogue.
 template <class V, int DIR>
 __global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int jw)
@@ -872,6 +988,50 @@ void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool c
     }
 }
 
+template <class V, int FMT, int DIR, int EPT, bool PF>
+static void staged_v(const PassArgs<V> &p, int jw, size_t shmem, hipStream_t s, bool prepare)
+{
+    auto fn = k_spass<V, FMT, DIR, SPASS_NT, EPT, PF>;
+    if (prepare) {
+        (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        return;
+    }
+    hipLaunchKernelGGL(fn, dim3(p.ntiles), dim3(SPASS_NT), shmem, s, p, jw);
+}
+
+template <class V, int FMT, int DIR>
+static void staged_t(const PassArgs<V> &p, int variant, int jw, size_t shmem, hipStream_t s, bool prepare)
+{
+    switch (variant) {
+    case 0: staged_v<V, FMT, DIR, 4, false>(p, jw, shmem, s, prepare); break;
+    case 1: staged_v<V, FMT, DIR, 4, true>(p, jw, shmem, s, prepare); break;
+    case 2: staged_v<V, FMT, DIR, 8, false>(p, jw, shmem, s, prepare); break;
+    default: staged_v<V, FMT, DIR, 8, true>(p, jw, shmem, s, prepare); break;
+    }
+}
+
+template <class V>
+void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, size_t shmem, hipStream_t s,
+                   bool prepare)
+{
+    if (!prepare && p.ntiles <= 0) return;
+    if constexpr (sizeof(V) == 8) {
+        if (dir == DIR_COL) staged_t<V, FMT_F64, DIR_COL>(p, variant, jw, shmem, s, prepare);
+        else staged_t<V, FMT_F64, DIR_ROW>(p, variant, jw, shmem, s, prepare);
+    } else {
+        if (fmt == FMT_PACKED) {
+            if (dir == DIR_COL) staged_t<V, FMT_PACKED, DIR_COL>(p, variant, jw, shmem, s, prepare);
+            else staged_t<V, FMT_PACKED, DIR_ROW>(p, variant, jw, shmem, s, prepare);
+        } else if (fmt == FMT_BF16) {
+            if (dir == DIR_COL) staged_t<V, FMT_BF16, DIR_COL>(p, variant, jw, shmem, s, prepare);
+            else staged_t<V, FMT_BF16, DIR_ROW>(p, variant, jw, shmem, s, prepare);
+        } else {
+            if (dir == DIR_COL) staged_t<V, FMT_F32, DIR_COL>(p, variant, jw, shmem, s, prepare);
+            else staged_t<V, FMT_F32, DIR_ROW>(p, variant, jw, shmem, s, prepare);
+        }
+    }
+}
+
 void launch_decide(const DecideArgs &d, int count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_decide, dim3(count), dim3(256), 0, s, d);
@@ -938,6 +1098,7 @@ void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibi
 }
 
 #define SCY_INST(V)                                                                                    \
+    template void launch_staged<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, bool, hipStream_t);    \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
     template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \

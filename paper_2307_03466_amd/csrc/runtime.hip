@@ -101,6 +101,14 @@ struct OrientRT {
     MatView bmat{};
     BlockedPlan bplan;
     DevMem P, P64, ctiles;
+    // LDS-staged layout (when chosen): staged tiles for instances whose
+    // gathered vector fits in LDS, normal tiles for the rest
+    bool staged = false;
+    StagedPlan splan;
+    DevMem stiles, subtiles, gofs, rtiles, rlongs, rseg;
+    size_t shmem = 0;
+    int32_t staged_nnz = 0;
+    int32_t svariant = 0;
     // plan buffers
     DevMem tiles, longs, seg, seg64, part, lpart;
     int32_t ntiles() const { return (int32_t)((blocked ? bplan.tiles.size() : plan.tiles.size()) / 4); }
@@ -113,6 +121,8 @@ struct scylla_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap = nullptr;  // private stream used for graph capture
+    hipStream_t side = nullptr; // second branch (staged and normal tiles overlap)
+    hipEvent_t fork = nullptr, join = nullptr;
     int32_t M = 0, N = 0;
     int64_t NNZ = 0;
     std::vector<int32_t> row_off, col_off;
@@ -128,6 +138,7 @@ struct scylla_batch {
     hipGraphExec_t gexec = nullptr;
     int32_t graph_R = 0;
     bool tuned = false;
+    int32_t lds_max = 65536;  // dynamic LDS bytes a workgroup may use
     // host copy of the problem (for the pump's rounding on the host)
     std::vector<double> hval, hb, hl, hu, hc;
     std::vector<char> hsense;
@@ -150,6 +161,9 @@ struct scylla_batch {
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         if (cap) (void)hipStreamDestroy(cap);
+        if (side) (void)hipStreamDestroy(side);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -234,6 +248,7 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
     const size_t vb = (size_t)h->vbytes;
     o.ept = ept;
+    o.staged = false;
     if (B > 0) {
         if (!o.blocked || o.bh.B != B) {
             build_blocked(o.host, h->fmt, o.gather, B, o.bh);
@@ -273,6 +288,36 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
         o.lpart.alloc(std::max<size_t>(1, o.plan.longs.size() / 4) * 4 * 8);
     }
     HIPC(hipStreamSynchronize(h->stream));
+}
+
+// LDS-staged layout: the normal plan (used by the check) with `ept`, plus
+// staged tiles of about `group_nnz` nonzeros for every instance whose
+// gathered vector fits in LDS and normal tiles for the others.
+void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, int32_t variant)
+{
+    set_plan(h, o, 0, ept);
+    const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
+    const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
+    const int32_t chunk = spass_chunk(variant);
+    const int32_t max_vec = h->lds_max / h->vbytes - chunk;
+    plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * ept, o.splan);
+    upload(o.stiles, o.splan.tiles, h->stream);
+    upload(o.subtiles, o.splan.sub.tiles, h->stream);
+    upload(o.gofs, gofs, h->stream);
+    upload(o.rtiles, o.splan.rest.tiles, h->stream);
+    upload(o.rlongs, o.splan.rest.longs, h->stream);
+    o.rseg.alloc(std::max<size_t>(1, o.splan.rest.nslots) * h->vbytes);
+    o.shmem = (size_t)(chunk + std::max(o.splan.max_vec, 1)) * h->vbytes;
+    PassArgs<float> pf{};
+    PassArgs<double> pd{};
+    if (h->vbytes == 4)
+        launch_staged<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, variant, 0, o.shmem, h->stream, true);
+    else
+        launch_staged<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, variant, 0, o.shmem, h->stream, true);
+    HIPC(hipStreamSynchronize(h->stream));
+    o.staged = !o.splan.tiles.empty();
+    o.staged_nnz = group_nnz;
+    o.svariant = variant;
 }
 
 // Drops the blocked layout's device copy (after the tuner chose normal).
@@ -330,7 +375,34 @@ void invalidate_graph(scylla_batch *h)
 template <class V>
 void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, bool check, hipStream_t s)
 {
-    launch_pass<V>(p, h->fmt, o.row ? DIR_ROW : DIR_COL, o.ept, jw, check, o.blocked, s);
+    const int dir = o.row ? DIR_ROW : DIR_COL;
+    if (o.staged && !check) {
+        PassArgs<V> ps = p;
+        ps.tiles = o.stiles.as<int4>();
+        ps.ntiles = (int32_t)(o.splan.tiles.size() / 4);
+        ps.gofs = o.gofs.as<int32_t>();
+        ps.sub = o.subtiles.as<int4>();
+        PassArgs<V> pr = p;
+        pr.tiles = o.rtiles.as<int4>();
+        pr.ntiles = (int32_t)(o.splan.rest.tiles.size() / 4);
+        pr.longs = o.rlongs.as<int4>();
+        pr.nlong = (int32_t)(o.splan.rest.longs.size() / 4);
+        pr.seg = o.rseg.as<V>();
+        if (pr.ntiles == 0 && pr.nlong == 0) {
+            launch_staged<V>(ps, h->fmt, dir, o.svariant, jw, o.shmem, s, false);
+            return;
+        }
+        // the two kinds of tiles touch disjoint instances: run them as two
+        // branches (fork on s, normal tiles on the side stream, join)
+        HIPC(hipEventRecord(h->fork, s));
+        HIPC(hipStreamWaitEvent(h->side, h->fork, 0));
+        launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
+        HIPC(hipEventRecord(h->join, h->side));
+        launch_staged<V>(ps, h->fmt, dir, o.svariant, jw, o.shmem, s, false);
+        HIPC(hipStreamWaitEvent(s, h->join, 0));
+        return;
+    }
+    launch_pass<V>(p, h->fmt, dir, o.ept, jw, check, o.blocked, s);
 }
 
 template <class V>
@@ -444,8 +516,33 @@ void autotune(scylla_batch *h)
                 }
             }
         }
-        set_plan(h, o, best_B, best_ept);
-        if (best_B == 0) drop_blocked(o);
+        // LDS-staged candidates when some instance's gathered vector fits
+        const std::vector<int32_t> &g = o.row ? h->col_off : h->row_off;
+        bool any = false;
+        for (int32_t q = 0; q < h->count; ++q)
+            any |= (int64_t)(g[q + 1] - g[q] + spass_chunk(0)) * h->vbytes <= h->lds_max;
+        int best_nnz = 0, best_var = 0;
+        if (any && o.rows > 0) {
+            for (int var = 0; var < 4; ++var)
+                for (int nnz : {16384, 32768, 65536}) {
+                    set_staged(h, o, best_ept, nnz, var);
+                    if (!o.staged) continue;
+                    const double ms = timer.time(o, 10);
+                    if (ms < best) {
+                        best = ms;
+                        best_nnz = nnz;
+                        best_var = var;
+                        best_B = -1;
+                    }
+                }
+        }
+        if (best_B < 0) {
+            set_staged(h, o, best_ept, best_nnz, best_var);
+            drop_blocked(o);
+        } else {
+            set_plan(h, o, best_B, best_ept);
+            if (best_B == 0) drop_blocked(o);
+        }
     }
     refresh_info(h);
     invalidate_graph(h);
@@ -938,6 +1035,12 @@ int scylla_batch_create(const scylla_lp *lps, int32_t count, int32_t precision, 
         h->N = csc.rows;
         h->NNZ = (int64_t)csr.ent.size();
         check_device();
+        {
+            int dev = 0, lds = 0;
+            HIPC(hipGetDevice(&dev));
+            HIPC(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            h->lds_max = lds;
+        }
         if (hip_stream) {
             h->stream = (hipStream_t)hip_stream;
         } else {
@@ -945,6 +1048,9 @@ int scylla_batch_create(const scylla_lp *lps, int32_t count, int32_t precision, 
             h->own_stream = true;
         }
         HIPC(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIPC(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        HIPC(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+        HIPC(hipEventCreateWithFlags(&h->join, hipEventDisableTiming));
         HIPC(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
         HIPC(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
         HIPC(hipHostMalloc((void **)&h->pinned, sizeof(InstState) * 2 * (size_t)count, hipHostMallocDefault));
@@ -1107,8 +1213,12 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->col_chunk = 256 * h->ocol.ept;
         info->long_rows = h->orow.nlong();
         info->long_cols = h->ocol.nlong();
-        info->row_blocks = h->orow.blocked ? h->orow.bh.B : 0;
-        info->col_blocks = h->ocol.blocked ? h->ocol.bh.B : 0;
+        info->row_blocks = h->orow.staged ? -1 : (h->orow.blocked ? h->orow.bh.B : 0);
+        info->col_blocks = h->ocol.staged ? -1 : (h->ocol.blocked ? h->ocol.bh.B : 0);
+        info->row_staged_nnz = h->orow.staged ? h->orow.staged_nnz : 0;
+        info->col_staged_nnz = h->ocol.staged ? h->ocol.staged_nnz : 0;
+        info->row_staged_variant = h->orow.staged ? h->orow.svariant : 0;
+        info->col_staged_variant = h->ocol.staged ? h->ocol.svariant : 0;
         return 0;
     });
 }
@@ -1160,15 +1270,23 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
 {
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
-        auto okB = [](int32_t B) { return B == 0 || B == 4 || B == 8; };
+        auto okB = [](int32_t B) { return B == 0 || B == 4 || B == 8 || B == -1; };
         auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be 0, 4 or 8 and ept 4, 8 or 16");
+            throw_err(-EINVAL, "blocks must be -1, 0, 4 or 8 and ept 4, 8 or 16");
         HIPC(hipStreamSynchronize(h->stream));
-        set_plan(h, h->orow, h->orow.rows > 0 ? row_blocks : 0, row_ept);
-        set_plan(h, h->ocol, h->ocol.rows > 0 ? col_blocks : 0, col_ept);
-        if (h->orow.rows == 0 || row_blocks == 0) drop_blocked(h->orow);
-        if (col_blocks == 0) drop_blocked(h->ocol);
+        for (int d = 0; d < 2; ++d) {
+            OrientRT &o = d == 0 ? h->orow : h->ocol;
+            int32_t B = d == 0 ? row_blocks : col_blocks, ept = d == 0 ? row_ept : col_ept;
+            if (o.rows == 0 && B > 0) B = 0;
+            if (B < 0) {
+                set_staged(h, o, ept, 32768, 0);
+                drop_blocked(o);
+            } else {
+                set_plan(h, o, B, ept);
+                if (B == 0) drop_blocked(o);
+            }
+        }
         refresh_info(h);
         invalidate_graph(h);
         h->tuned = true;

@@ -104,6 +104,22 @@ struct BlockedPlan {
     std::vector<int32_t> ct_begin, ct_end;  // combine tiles per instance
 };
 
+// Plan of an LDS-staged orientation.  Instances whose gathered vector has at
+// most max_vec elements and no row longer than sub_chunk get sub-tiles
+// (whole rows, <= sub_chunk nonzeros) grouped into staged tiles of about
+// group_nnz nonzeros; the other instances get normal tiles (rest).
+struct StagedPlan {
+    std::vector<int32_t> tiles;   // {sub0, sub1, inst, -1}
+    TilePlan sub;                 // sub-tiles of the staged instances
+    std::vector<uint8_t> staged;  // per instance
+    TilePlan rest;                // normal tiles of the other instances
+    int32_t max_vec = 0;          // largest staged gathered vector (elements)
+};
+
+void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
+                 const std::vector<int32_t> &gofs, int32_t max_vec, int32_t sub_chunk, int32_t group_nnz,
+                 int32_t rest_chunk, StagedPlan &plan);
+
 void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_t B, BlockedHost &out);
 void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t> &inst_off, int32_t chunk,
                   int32_t max_rows, BlockedPlan &plan);
@@ -122,7 +138,7 @@ int build_orientations(const scylla_lp *lps, int32_t count, int32_t precision, H
 // and at most `max_rows` rows; rows longer than `chunk` become long rows cut
 // into `chunk`-sized segments.  Tiles never straddle instances.
 void plan_tiles(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
-                int32_t chunk, int32_t max_rows, TilePlan &plan);
+                int32_t chunk, int32_t max_rows, TilePlan &plan, const uint8_t *skip = nullptr);
 
 uint16_t f64_to_bf16_exact(double v, bool &exact);
 

@@ -72,7 +72,9 @@ class BatchInfo(ctypes.Structure):
                 ("nnz_total", ctypes.c_int64), ("row_chunk", ctypes.c_int32),
                 ("col_chunk", ctypes.c_int32), ("long_rows", ctypes.c_int32),
                 ("long_cols", ctypes.c_int32), ("row_blocks", ctypes.c_int32),
-                ("col_blocks", ctypes.c_int32)]
+                ("col_blocks", ctypes.c_int32), ("row_staged_nnz", ctypes.c_int32),
+                ("col_staged_nnz", ctypes.c_int32), ("row_staged_variant", ctypes.c_int32),
+                ("col_staged_variant", ctypes.c_int32)]
 
 
 _lib = None

@@ -239,6 +239,8 @@ def main():
         out[tag] = rec
 
     if "fp32" not in out or "fp64" not in out:
+        if args.workloads:
+            log(json.dumps(other_workloads(pdhg, instances, args, R)))
         log("partial run (--legs): no JSON line")
         return
     f32 = out["fp32"]

@@ -79,6 +79,11 @@ typedef struct {
                              handle and keep the fastest (default 1)       */
     double eta;           /* step-size factor in (0, 1) (0.99)             */
     double time_limit_s;  /* <= 0: none (0)                                */
+    int32_t fused_window; /* 1 = when every instance fits in LDS, run each
+                             check window (check, decision, R iterations)
+                             as one kernel, one workgroup per instance
+                             (default 1); 0 = always per-pass kernels     */
+    int32_t reserved;
 } scylla_params;
 
 enum {
@@ -189,7 +194,8 @@ int scylla_batch_device_iterates(scylla_batch *h, void **x, void **y, int32_t *e
 /* Shape of the handle: total rows, columns, nonzeros, instance count and the
  * matrix storage format chosen (0 packed integers, 1 BF16, 2 FP32, 3 FP64). */
 typedef struct {
-    int32_t count, precision, format, reserved;
+    int32_t count, precision, format;
+    int32_t fused_eligible; /* 1 if every instance fits the fused window  */
     int64_t m_total, n_total, nnz_total;
     int32_t row_chunk, col_chunk; /* tile sizes in use (nonzeros per tile) */
     int32_t long_rows, long_cols; /* rows / columns split over several tiles */

@@ -64,6 +64,30 @@ struct PassArgs {
 constexpr int SPASS_NT = 1024;
 inline int spass_chunk(int variant) { return SPASS_NT * (variant >= 2 ? 8 : 4); }
 
+// Fused check window for instances that fit in LDS (k_tiny).
+template <class V>
+struct TinyArgs {
+    MatView R, C;  // CSR and CSC (normal layout)
+    V *x, *xbar, *xr, *y, *yr;
+    const V *c, *l, *u, *dc2, *b, *dr2;
+    const uint8_t *sense;
+    const double *c64, *l64, *u64, *b64, *dr64, *dc64;
+    InstState *st;
+    const InstInfo *info;
+};
+
+// LDS bytes k_tiny needs for an instance (must match its carving).
+inline size_t tiny_lds_bytes(int m, int n, int rnnz, int cnnz, int vb)
+{
+    auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    return al(4 * (size_t)(m + 1)) + al(4 * (size_t)(n + 1)) + al(4 * (size_t)rnnz) + al(4 * (size_t)cnnz) +
+           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 7 * al((size_t)vb * n) + 4 * al((size_t)vb * m) +
+           al((size_t)m);
+}
+
+template <class V>
+void launch_tiny(const TinyArgs<V> &a, int fmt, int count, int R, size_t shmem, hipStream_t s, bool prepare);
+
 struct DecideArgs {
     InstState *st;
     const InstInfo *info;

@@ -628,32 +628,11 @@ __global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
 }
 
 // ------------------------------------------------------------- decision
-// One workgroup per instance: fixed-order FP64 reduction of the check
-// partials, then termination (Section 2.2), restart and primal-weight
-// update, all in FP64.
-__global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
+// Termination test (Section 2.2), restart rule and primal-weight update in
+// FP64 for one instance, from the check window's reduced sums
+// tot = {||r_p||^2, b^T y, ||dy~||^2, ||r_d||^2, c^T x, bound terms, ||dx~||^2}.
+__device__ void decide_state(InstState &S, const double tot[7], int R)
 {
-    const int inst = blockIdx.x;
-    InstState &S = d.st[inst];
-    if (S.status != ST_RUN) return;
-    const InstInfo I = d.info[inst];
-    __shared__ double red[4];
-    // q: 0 rp2, 1 by, 2 dy2 (rows); 3 rd2, 4 cx, 5 bound, 6 dx2 (columns)
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int t = I.rt0 + threadIdx.x; t < I.rt1; t += 256)
-        for (int k = 0; k < 3; ++k) acc[k] += d.rpart[4 * t + k];
-    for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256)
-        for (int k = 0; k < 3; ++k) acc[k] += d.lrpart[4 * t + k];
-    for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256)
-        for (int k = 0; k < 4; ++k) acc[3 + k] += d.cpart[4 * t + k];
-    for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256)
-        for (int k = 0; k < 4; ++k) acc[3 + k] += d.lcpart[4 * t + k];
-    double tot[7];
-    for (int k = 0; k < 7; ++k) {
-        __syncthreads();
-        tot[k] = block_sum<double, 256>(acc[k], red);
-    }
-    if (threadIdx.x != 0) return;
     const int64_t k = S.k + S.nrun;
     S.k = k;
     S.nrun = 0;
@@ -696,7 +675,256 @@ __global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
     }
     S.Ep = E;
     const int64_t left = S.k_limit - k;
-    S.nrun = (int32_t)(left < (int64_t)d.R ? left : (int64_t)d.R);
+    S.nrun = (int32_t)(left < (int64_t)R ? left : (int64_t)R);
+}
+
+
+// One workgroup per instance: fixed-order FP64 reduction of the check
+// partials, then termination (Section 2.2), restart and primal-weight
+// update, all in FP64.
+__global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
+{
+    const int inst = blockIdx.x;
+    InstState &S = d.st[inst];
+    if (S.status != ST_RUN) return;
+    const InstInfo I = d.info[inst];
+    __shared__ double red[4];
+    // q: 0 rp2, 1 by, 2 dy2 (rows); 3 rd2, 4 cx, 5 bound, 6 dx2 (columns)
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int t = I.rt0 + threadIdx.x; t < I.rt1; t += 256)
+        for (int k = 0; k < 3; ++k) acc[k] += d.rpart[4 * t + k];
+    for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256)
+        for (int k = 0; k < 3; ++k) acc[k] += d.lrpart[4 * t + k];
+    for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256)
+        for (int k = 0; k < 4; ++k) acc[3 + k] += d.cpart[4 * t + k];
+    for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256)
+        for (int k = 0; k < 4; ++k) acc[3 + k] += d.lcpart[4 * t + k];
+    double tot[7];
+    for (int k = 0; k < 7; ++k) {
+        __syncthreads();
+        tot[k] = block_sum<double, 256>(acc[k], red);
+    }
+    if (threadIdx.x != 0) return;
+    decide_state(S, tot, d.R);
+}
+
+// --------------------------------------------- fused window (tiny instances)
+// One workgroup per instance runs a whole check window -- FP64 KKT check,
+// decision, then up to R iterations -- with the instance's matrix (both
+// orientations, decoded to local index + value) and vectors held in LDS and
+// workgroup barriers between the passes.  Used when every instance of the
+// handle fits in LDS; it removes the per-pass launch latency that dominates
+// such instances.  No workgroup ever waits for another.
+template <class V>
+struct TinyLds {
+    int *rptr, *cptr, *rcol, *ccol;
+    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *y, *yr, *b, *dr2;
+    uint8_t *sense;
+};
+
+template <class V>
+__device__ __forceinline__ TinyLds<V> tiny_carve(unsigned char *base, int m, int n, int rnnz, int cnnz)
+{
+    TinyLds<V> t;
+    unsigned char *q = base;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = q;
+        q += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    t.rptr = (int *)take(4 * (size_t)(m + 1));
+    t.cptr = (int *)take(4 * (size_t)(n + 1));
+    t.rcol = (int *)take(4 * (size_t)rnnz);
+    t.ccol = (int *)take(4 * (size_t)cnnz);
+    t.rval = (V *)take(sizeof(V) * (size_t)rnnz);
+    t.cval = (V *)take(sizeof(V) * (size_t)cnnz);
+    t.x = (V *)take(sizeof(V) * (size_t)n);
+    t.xb = (V *)take(sizeof(V) * (size_t)n);
+    t.xr = (V *)take(sizeof(V) * (size_t)n);
+    t.c = (V *)take(sizeof(V) * (size_t)n);
+    t.l = (V *)take(sizeof(V) * (size_t)n);
+    t.u = (V *)take(sizeof(V) * (size_t)n);
+    t.dc2 = (V *)take(sizeof(V) * (size_t)n);
+    t.y = (V *)take(sizeof(V) * (size_t)m);
+    t.yr = (V *)take(sizeof(V) * (size_t)m);
+    t.b = (V *)take(sizeof(V) * (size_t)m);
+    t.dr2 = (V *)take(sizeof(V) * (size_t)m);
+    t.sense = (uint8_t *)take((size_t)m);
+    return t;
+}
+
+template <class V, int FMT>
+__global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
+{
+    constexpr int NT = 1024;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[NT / 64];
+    __shared__ int sh_nrun, sh_restart;
+    __shared__ V sh_t, sh_s;
+    const int inst = blockIdx.x, tid = threadIdx.x;
+    InstState &S = a.st[inst];
+    if (S.status != ST_RUN) return;
+    const InstInfo I = a.info[inst];
+    const int m = I.row1 - I.row0, n = I.col1 - I.col0;
+    const int re0 = a.R.ptr[I.row0], rnnz = a.R.ptr[I.row1] - re0;
+    const int ce0 = a.C.ptr[I.col0], cnnz = a.C.ptr[I.col1] - ce0;
+    const TinyLds<V> L = tiny_carve<V>(lds_raw, m, n, rnnz, cnnz);
+    // ---- load the instance into LDS
+    for (int i = tid; i <= m; i += NT) L.rptr[i] = a.R.ptr[I.row0 + i] - re0;
+    for (int j = tid; j <= n; j += NT) L.cptr[j] = a.C.ptr[I.col0 + j] - ce0;
+    for (int e = tid; e < rnnz; e += NT) {
+        uint32_t w;
+        V v;
+        load_entry<FMT, V>(a.R, re0 + e, w, v);
+        L.rcol[e] = decode_entry<FMT, V>(a.R, w, v) - I.col0;
+        L.rval[e] = v;
+    }
+    for (int e = tid; e < cnnz; e += NT) {
+        uint32_t w;
+        V v;
+        load_entry<FMT, V>(a.C, ce0 + e, w, v);
+        L.ccol[e] = decode_entry<FMT, V>(a.C, w, v) - I.row0;
+        L.cval[e] = v;
+    }
+    for (int j = tid; j < n; j += NT) {
+        const int g = I.col0 + j;
+        L.x[j] = a.x[g];
+        L.xb[j] = a.xbar[g];
+        L.xr[j] = a.xr[g];
+        L.c[j] = a.c[g];
+        L.l[j] = a.l[g];
+        L.u[j] = a.u[g];
+        L.dc2[j] = a.dc2[g];
+    }
+    for (int i = tid; i < m; i += NT) {
+        const int g = I.row0 + i;
+        L.y[i] = a.y[g];
+        L.yr[i] = a.yr[g];
+        L.b[i] = a.b[g];
+        L.dr2[i] = a.dr2[g];
+        L.sense[i] = a.sense[g];
+    }
+    __syncthreads();
+    // ---- FP64 KKT check of the current point (Section 2.2)
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = tid; i < m; i += NT) {
+        double ax = 0.0;
+        for (int e = L.rptr[i]; e < L.rptr[i + 1]; ++e) ax += (double)L.rval[e] * (double)L.x[L.rcol[e]];
+        const double bb = a.b64[I.row0 + i];
+        const uint8_t sn = L.sense[i];
+        double r;
+        if (sn == 'G') r = fmax(bb - ax, 0.0);
+        else if (sn == 'L') r = fmax(ax - bb, 0.0);
+        else r = bb - ax;
+        const double yy = (double)L.y[i];
+        const double dy = (yy - (double)L.yr[i]) / a.dr64[I.row0 + i];
+        acc[0] += r * r;
+        acc[1] += bb * yy;
+        acc[2] += dy * dy;
+    }
+    for (int j = tid; j < n; j += NT) {
+        double aty = 0.0;
+        for (int e = L.cptr[j]; e < L.cptr[j + 1]; ++e) aty += (double)L.cval[e] * (double)L.y[L.ccol[e]];
+        const int g = I.col0 + j;
+        const double cc = a.c64[g], lo = a.l64[g], hi = a.u64[g];
+        const double gr = cc - aty;
+        const bool lf = isfinite(lo), uf = isfinite(hi);
+        double lam;
+        if (lf && uf) lam = gr;
+        else if (lf) lam = fmax(gr, 0.0);
+        else if (uf) lam = fmin(gr, 0.0);
+        else lam = 0.0;
+        const double rd = gr - lam;
+        const double xx = (double)L.x[j];
+        const double dx = (xx - (double)L.xr[j]) / a.dc64[g];
+        acc[3] += rd * rd;
+        acc[4] += cc * xx;
+        if (lf && lam > 0.0) acc[5] += lo * lam;
+        if (uf && lam < 0.0) acc[5] += hi * lam;
+        acc[6] += dx * dx;
+    }
+    double tot[7];
+    for (int k = 0; k < 7; ++k) {
+        __syncthreads();
+        tot[k] = block_sum<double, NT>(acc[k], red);
+    }
+    if (tid == 0) {
+        decide_state(S, tot, R);
+        sh_nrun = S.status == ST_RUN ? S.nrun : 0;
+        sh_restart = S.restart_now;
+        sh_t = (V)S.t;
+        sh_s = (V)S.s;
+    }
+    __syncthreads();
+    const int nrun = sh_nrun;
+    if (nrun == 0) return;
+    const V t = sh_t, sd = sh_s;
+    // lane groups: a power of two of lanes per column / row, as many as fit
+    const int Lc = lanes_per_row<NT>(n), Lr = lanes_per_row<NT>(m);
+    const int lc = tid & (Lc - 1), lr = tid & (Lr - 1);
+    // ---- nrun PDHG iterations (Algorithm 1): column pass, barrier, row pass
+    for (int it = 0; it < nrun; ++it) {
+        const bool copy_ref = it == 0 && sh_restart != 0;
+        for (int j = tid / Lc; j < n; j += NT / Lc) {
+            V aty = 0;
+            for (int e = L.cptr[j] + lc; e < L.cptr[j + 1]; e += Lc) aty += L.cval[e] * L.y[L.ccol[e]];
+            if (Lc > 1) aty = wave_sum_width(aty, Lc);
+            if (lc == 0) {
+                const V xj = L.x[j];
+                V xn = xj + t * L.dc2[j] * (aty - L.c[j]);
+                xn = xn < L.l[j] ? L.l[j] : xn;
+                xn = xn > L.u[j] ? L.u[j] : xn;
+                if (copy_ref) L.xr[j] = xj;
+                L.xb[j] = (V)2 * xn - xj;
+                L.x[j] = xn;
+            }
+        }
+        __syncthreads();
+        for (int i = tid / Lr; i < m; i += NT / Lr) {
+            V axb = 0;
+            for (int e = L.rptr[i] + lr; e < L.rptr[i + 1]; e += Lr) axb += L.rval[e] * L.xb[L.rcol[e]];
+            if (Lr > 1) axb = wave_sum_width(axb, Lr);
+            if (lr == 0) {
+                const V yi = L.y[i];
+                V v = yi + sd * L.dr2[i] * (L.b[i] - axb);
+                const uint8_t sn = L.sense[i];
+                if (sn == 'G') v = v > (V)0 ? v : (V)0;
+                else if (sn == 'L') v = v < (V)0 ? v : (V)0;
+                if (copy_ref) L.yr[i] = yi;
+                L.y[i] = v;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- write the iterates back
+    for (int j = tid; j < n; j += NT) {
+        const int g = I.col0 + j;
+        a.x[g] = L.x[j];
+        a.xbar[g] = L.xb[j];
+        a.xr[g] = L.xr[j];
+    }
+    for (int i = tid; i < m; i += NT) {
+        const int g = I.row0 + i;
+        a.y[g] = L.y[i];
+        a.yr[g] = L.yr[i];
+    }
+}
+
+template <class V>
+void launch_tiny(const TinyArgs<V> &a, int fmt, int count, int R, size_t shmem, hipStream_t s, bool prepare)
+{
+    auto run = [&](auto fn) {
+        if (prepare) (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)shmem);
+        else hipLaunchKernelGGL(fn, dim3(count), dim3(1024), shmem, s, a, R);
+    };
+    if constexpr (sizeof(V) == 8) {
+        run(k_tiny<V, FMT_F64>);
+    } else {
+        if (fmt == FMT_PACKED) run(k_tiny<V, FMT_PACKED>);
+        else if (fmt == FMT_BF16) run(k_tiny<V, FMT_BF16>);
+        else run(k_tiny<V, FMT_F32>);
+    }
 }
 
 __global__ void k_force_stop(InstState *st, int count)
@@ -1098,6 +1326,7 @@ void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibi
 }
 
 #define SCY_INST(V)                                                                                    \
+    template void launch_tiny<V>(const TinyArgs<V> &, int, int, int, size_t, hipStream_t, bool);       \
     template void launch_staged<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, bool, hipStream_t);    \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \

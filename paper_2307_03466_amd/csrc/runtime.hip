@@ -139,6 +139,9 @@ struct scylla_batch {
     int32_t graph_R = 0;
     bool tuned = false;
     int32_t lds_max = 65536;  // dynamic LDS bytes a workgroup may use
+    bool tiny_ok = false;     // every instance fits the fused window
+    size_t tiny_shmem = 0;
+    bool graph_tiny = false;
     // host copy of the problem (for the pump's rounding on the host)
     std::vector<double> hval, hb, hl, hu, hc;
     std::vector<char> hsense;
@@ -406,8 +409,41 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
 }
 
 template <class V>
-void enqueue_window(scylla_batch *h, int32_t R, hipStream_t s)
+TinyArgs<V> tiny_args(scylla_batch *h)
 {
+    TinyArgs<V> a{};
+    a.R = h->orow.mat;
+    a.C = h->ocol.mat;
+    a.x = h->x.as<V>();
+    a.xbar = h->xbar.as<V>();
+    a.xr = h->xr.as<V>();
+    a.y = h->y.as<V>();
+    a.yr = h->yr.as<V>();
+    a.c = h->cv.as<V>();
+    a.l = h->lv.as<V>();
+    a.u = h->uv.as<V>();
+    a.dc2 = h->dc2.as<V>();
+    a.b = h->b_v.as<V>();
+    a.dr2 = h->dr2.as<V>();
+    a.sense = h->sense.as<uint8_t>();
+    a.c64 = h->c64.as<double>();
+    a.l64 = h->l64.as<double>();
+    a.u64 = h->u64.as<double>();
+    a.b64 = h->b64.as<double>();
+    a.dr64 = h->dr64.as<double>();
+    a.dc64 = h->dc64.as<double>();
+    a.st = h->st.as<InstState>();
+    a.info = h->info.as<InstInfo>();
+    return a;
+}
+
+template <class V>
+void enqueue_window(scylla_batch *h, int32_t R, bool tiny, hipStream_t s)
+{
+    if (tiny) {
+        launch_tiny<V>(tiny_args<V>(h), h->fmt, h->count, R, h->tiny_shmem, s, false);
+        return;
+    }
     const PassArgs<V> rc = orient_args<V>(h, h->orow, true), cc = orient_args<V>(h, h->ocol, true);
     launch_orient<V>(h, h->orow, rc, 0, true, s);
     launch_orient<V>(h, h->ocol, cc, 0, true, s);
@@ -421,19 +457,20 @@ void enqueue_window(scylla_batch *h, int32_t R, hipStream_t s)
     }
 }
 
-void ensure_graph(scylla_batch *h, int32_t R)
+void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
 {
-    if (h->gexec && h->graph_R == R) return;
+    if (h->gexec && h->graph_R == R && h->graph_tiny == tiny) return;
     invalidate_graph(h);
     hipGraph_t g = nullptr;
     HIPC(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    if (h->vbytes == 4) enqueue_window<float>(h, R, h->cap);
-    else enqueue_window<double>(h, R, h->cap);
+    if (h->vbytes == 4) enqueue_window<float>(h, R, tiny, h->cap);
+    else enqueue_window<double>(h, R, tiny, h->cap);
     HIPC(hipStreamEndCapture(h->cap, &g));
     hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIPC(e);
     h->graph_R = R;
+    h->graph_tiny = tiny;
 }
 
 // Scratch outputs and an always-running state so a pass can be launched on
@@ -627,6 +664,20 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
                       h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), s);
     HIPC(hipGetLastError());
+    // fused-window eligibility: every instance fits in LDS
+    size_t need = 0;
+    for (int32_t q = 0; q < h->count; ++q) {
+        const int32_t m = h->row_off[q + 1] - h->row_off[q], n = h->col_off[q + 1] - h->col_off[q];
+        const int32_t rn = h->orow.host.ptr[h->row_off[q + 1]] - h->orow.host.ptr[h->row_off[q]];
+        const int32_t cn = h->ocol.host.ptr[h->col_off[q + 1]] - h->ocol.host.ptr[h->col_off[q]];
+        need = std::max(need, tiny_lds_bytes(m, n, rn, cn, (int)sizeof(V)));
+    }
+    h->tiny_ok = need <= (size_t)h->lds_max;
+    h->tiny_shmem = need;
+    if (h->tiny_ok) {
+        TinyArgs<V> a{};
+        launch_tiny<V>(a, h->fmt, h->count, 1, need, s, true);
+    }
     HIPC(hipStreamSynchronize(s));
 }
 
@@ -711,7 +762,8 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     if (!h || !results) throw_err(-EINVAL, "handle or results is NULL");
     validate_params(p);
     if (p->precision != h->precision) throw_err(-EINVAL, "params precision differs from the handle's");
-    if (p->autotune && !h->tuned) {
+    const bool tiny = h->tiny_ok && p->fused_window != 0;
+    if (p->autotune && !h->tuned && !tiny) {
         if (h->vbytes == 4) autotune<float>(h);
         else autotune<double>(h);
     }
@@ -740,7 +792,7 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     else project_start<double>(h, -1, warm ? 0 : 1);
     HIPC(hipMemcpyAsync(h->st.p, st.data(), sizeof(InstState) * h->count, hipMemcpyHostToDevice, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
-    ensure_graph(h, p->check_period);
+    ensure_graph(h, p->check_period, tiny);
 
     const size_t sb = sizeof(InstState) * (size_t)h->count;
     const double t0 = now_s();
@@ -993,6 +1045,8 @@ int scylla_params_default(scylla_params *p)
     p->autotune = 1;
     p->eta = 0.99;
     p->time_limit_s = 0.0;
+    p->fused_window = 1;
+    p->reserved = 0;
     return 0;
 }
 
@@ -1206,6 +1260,7 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->count = h->count;
         info->precision = h->precision;
         info->format = h->fmt;
+        info->fused_eligible = h->tiny_ok ? 1 : 0;
         info->m_total = h->M;
         info->n_total = h->N;
         info->nnz_total = h->NNZ;

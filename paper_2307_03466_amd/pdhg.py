@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("iter_limit", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("check_period", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double)]
+                ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
+                ("fused_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -67,7 +68,7 @@ class Result(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("format", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("format", ctypes.c_int32), ("fused_eligible", ctypes.c_int32),
                 ("m_total", ctypes.c_int64), ("n_total", ctypes.c_int64),
                 ("nnz_total", ctypes.c_int64), ("row_chunk", ctypes.c_int32),
                 ("col_chunk", ctypes.c_int32), ("long_rows", ctypes.c_int32),

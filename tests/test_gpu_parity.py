@@ -123,10 +123,10 @@ def test_run_to_run_bit_identical():
 def test_batch_matches_single_instances(prec):
     lps = I.uneven_batch(count=6, lo=200, hi=3000, seed=11) + [_case("mixed_bounds")]
     with pdhg.Batch(lps, precision=prec) as b:
-        res = b.solve(tol=1e-4, iter_limit=20_000, autotune=0)
+        res = b.solve(tol=1e-4, iter_limit=20_000, autotune=0, fused_window=0)
         sols = [b.solution(i) for i in range(len(lps))]
     for i, lp in enumerate(lps):
-        s = pdhg.solve(lp, tol=1e-4, iter_limit=20_000, precision=prec, autotune=0)
+        s = pdhg.solve(lp, tol=1e-4, iter_limit=20_000, precision=prec, autotune=0, fused_window=0)
         assert res[i]["iterations"] == s.result["iterations"]
         assert res[i]["status"] == s.result["status"]
         np.testing.assert_array_equal(sols[i][0], s.x)
@@ -234,3 +234,45 @@ def test_autotuned_solve_reaches_tolerance():
         print(b.info(), flush=True)
     assert r["status"] == pdhg.OPTIMAL
     assert oracle.kkt(lp, x, y)["rel"] <= 1e-4 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
+def test_fused_window_parity(prec, bar):
+    """Tiny instances run whole check windows in one workgroup each; the
+    per-pass path and the fused path both match the oracle and take the
+    same decisions."""
+    lps = [I.set_cover(200, 500, seed=s) for s in range(5)] + [_case("mixed_bounds")]
+    for fused in (1, 0):
+        with pdhg.Batch(lps, precision=prec) as b:
+            assert b.info()["fused_eligible"] == 1
+            res = b.solve(tol=1e-300, iter_limit=100, restarts=0, fused_window=fused, autotune=0)
+            sols = [b.solution(i) for i in range(len(lps))]
+            res2 = b.solve(tol=1e-4, iter_limit=200_000, fused_window=fused, autotune=0)
+            sols2 = [b.solution(i) for i in range(len(lps))]
+        for i, lp in enumerate(lps):
+            ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
+            assert res[i]["iterations"] == 100
+            assert max(rel_err(sols[i][0], ref.x), rel_err(sols[i][1], ref.y)) <= bar, (fused, i)
+            k = oracle.kkt(lp, *sols2[i])
+            assert res2[i]["status"] == pdhg.OPTIMAL and k["rel"] <= 1e-4 * (1 + 1e-6)
+            if prec == 0:
+                assert res2[i]["iterations"] == oracle.pdhg(lp, tol=1e-4, iter_limit=200_000).iterations
+
+
+def test_fused_window_time_limit():
+    lp = I.set_cover(200, 500, seed=3)
+    s = pdhg.solve(lp, tol=1e-300, iter_limit=100_000_000, precision=1, time_limit_s=0.02)
+    assert s.result["status"] == pdhg.TIME_LIMIT
+    assert abs(s.result["rel_kkt"] - oracle.kkt(lp, s.x, s.y)["rel"]) <= 1e-9
+
+
+def test_fused_batch_matches_fused_single_instances():
+    lps = [I.set_cover(200, 500, seed=s) for s in range(4)]
+    with pdhg.Batch(lps, precision=1) as b:
+        res = b.solve(tol=1e-4, iter_limit=50_000)
+        sols = [b.solution(i) for i in range(len(lps))]
+    for i, lp in enumerate(lps):
+        s = pdhg.solve(lp, tol=1e-4, iter_limit=50_000, precision=1)
+        assert res[i]["iterations"] == s.result["iterations"]
+        np.testing.assert_array_equal(sols[i][0], s.x)
+        np.testing.assert_array_equal(sols[i][1], s.y)

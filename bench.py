@@ -55,6 +55,23 @@ def canonical_bytes(m, n, nnz, fp64=False):
     return 2 * nnz * 6 + 4 * (m + 1) + 4 * (n + 1) + 28 * n + 17 * m + 4 * (m + n)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE x calibration + WRITE_SIZE)
+    from profiles/pmc_traffic.json, or None when the counters were taken on
+    another version of the kernel source."""
+    from paper_2307_03466_amd import profsum
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernels_hip_sha256") != profsum.kernels_sha256():
+        return None
+    k = d["kernels"].get(kernel)
+    if not k or "fetch_bytes" not in k or "write_bytes" not in k:
+        return None
+    return int(k["fetch_bytes"] + k["write_bytes"])
+
+
 def timed_steps(batch, steps, R):
     import torch
     torch.cuda.synchronize()
@@ -252,8 +269,14 @@ def main():
     blocks = info["col_blocks"] if dom_is_col else info["row_blocks"]
     gathered = (info["m_total"] if dom_is_col else info["n_total"]) * 4 // max(1, blocks)
     probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
+    fmt = info["format"]
+    dom_kernel = None
+    if not blocks:
+        ept = (info["col_chunk"] if dom_is_col else info["row_chunk"]) // 256
+        dom_kernel = f"void k_pass<float, {fmt}, {1 if dom_is_col else 0}, 256, {ept}>(PassArgs<float>, int)"
+    traffic = measured_traffic(dom_kernel) if dom_kernel else None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
                     kernel=("column" if dom_is_col else "row") + " pass (" +
                     ("k_bpart + k_bcombine, %d gather blocks" % blocks if blocks else "k_pass") + ")",
                     bytes_per_launch=dom_bytes, launch_ms=round(dom_ms, 5),

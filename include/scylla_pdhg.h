@@ -24,6 +24,10 @@
  *   - A handle (scylla_batch) must be used by one host thread at a time; its
  *     work is ordered on the HIP stream given at creation.
  *   - Limits: total rows, columns and nonzeros of a handle each < 2^31 - 1.
+ *   - Environment: SCYLLA_TUNE_CACHE=<file> makes the autotuner read its
+ *     choices (keyed by device architecture, precision, storage format and a
+ *     hash of the batch's shape) from that file and append new ones; without
+ *     it choices are cached for the life of the process only.
  */
 #ifndef SCYLLA_PDHG_H
 #define SCYLLA_PDHG_H

@@ -16,6 +16,11 @@
 #include <vector>
 
 #include <atomic>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <thread>
 
 #include "fixprop.h"
@@ -524,6 +529,112 @@ struct PassTimer {
     }
 };
 
+// ------------------------------------------------------------ tuning cache
+// Layout choices per (device arch, precision, format, shape) so handles of
+// the same shape skip the timing runs.  Kept per process; when the
+// environment variable SCYLLA_TUNE_CACHE names a file, entries are read from
+// it once and new ones appended (one line: key and 8 integers).
+struct TuneChoice {
+    int32_t v[8];  // row: mode(B, -1 staged), ept, staged nnz, variant; col: same
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(scylla_batch *h)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    // shape hash: sizes, instance offsets and log2 row-length histograms
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        hsh ^= v;
+        hsh *= 1099511628211ull;
+    };
+    mix((uint64_t)h->count);
+    mix((uint64_t)h->M);
+    mix((uint64_t)h->N);
+    mix((uint64_t)h->NNZ);
+    for (int32_t q = 0; q <= h->count; ++q) {
+        mix((uint64_t)h->row_off[q]);
+        mix((uint64_t)h->col_off[q]);
+    }
+    for (int d = 0; d < 2; ++d) {
+        const std::vector<int32_t> &ptr = d == 0 ? h->orow.host.ptr : h->ocol.host.ptr;
+        uint64_t hist[33] = {0};
+        for (size_t i = 0; i + 1 < ptr.size(); ++i) {
+            int32_t len = ptr[i + 1] - ptr[i], b = 0;
+            while (len > 0) {
+                len >>= 1;
+                ++b;
+            }
+            hist[b]++;
+        }
+        for (uint64_t c : hist) mix(c);
+    }
+    std::ostringstream os;
+    os << arch << ":p" << h->precision << ":f" << h->fmt << ":" << std::hex << hsh;
+    return os.str();
+}
+
+bool tune_lookup(const std::string &key, TuneChoice &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const char *path = getenv("SCYLLA_TUNE_CACHE");
+    if (!g_tune_loaded && path) {
+        std::ifstream f(path);
+        std::string k;
+        TuneChoice c;
+        while (f >> k >> c.v[0] >> c.v[1] >> c.v[2] >> c.v[3] >> c.v[4] >> c.v[5] >> c.v[6] >> c.v[7]) g_tune[k] = c;
+    }
+    g_tune_loaded = true;
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, const TuneChoice &c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = c;
+    if (const char *path = getenv("SCYLLA_TUNE_CACHE")) {
+        std::ofstream f(path, std::ios::app);
+        f << key;
+        for (int i = 0; i < 8; ++i) f << ' ' << c.v[i];
+        f << '\n';
+    }
+}
+
+void apply_choice(scylla_batch *h, OrientRT &o, const int32_t *v)
+{
+    if (v[0] < 0) {
+        set_staged(h, o, v[1], v[2], v[3]);
+        drop_blocked(o);
+    } else {
+        set_plan(h, o, v[0], v[1]);
+        if (v[0] == 0) drop_blocked(o);
+    }
+}
+
+TuneChoice current_choice(scylla_batch *h)
+{
+    TuneChoice c;
+    for (int d = 0; d < 2; ++d) {
+        const OrientRT &o = d == 0 ? h->orow : h->ocol;
+        int32_t *v = c.v + 4 * d;
+        v[0] = o.staged ? -1 : (o.blocked ? o.bh.B : 0);
+        v[1] = o.ept;
+        v[2] = o.staged ? o.staged_nnz : 0;
+        v[3] = o.staged ? o.svariant : 0;
+    }
+    return c;
+}
+
 // Times the layout / tile-size candidates of each orientation and keeps the
 // fastest: the normal layout with 4, 8 or 16 nonzeros per thread, and, when
 // the gathered vector is larger than 2 MB, the gather-blocked layout with 4
@@ -531,6 +642,16 @@ struct PassTimer {
 template <class V>
 void autotune(scylla_batch *h)
 {
+    const std::string key = tune_key(h);
+    TuneChoice cached;
+    if (tune_lookup(key, cached)) {
+        apply_choice(h, h->orow, cached.v);
+        apply_choice(h, h->ocol, cached.v + 4);
+        refresh_info(h);
+        invalidate_graph(h);
+        h->tuned = true;
+        return;
+    }
     const int epts[3] = {4, 8, 16};
     PassTimer<V> timer(h);
     for (int d = 0; d < 2; ++d) {
@@ -584,6 +705,7 @@ void autotune(scylla_batch *h)
     refresh_info(h);
     invalidate_graph(h);
     h->tuned = true;
+    tune_store(key, current_choice(h));
 }
 
 template <class V>

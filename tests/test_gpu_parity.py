@@ -276,3 +276,17 @@ def test_fused_batch_matches_fused_single_instances():
         assert res[i]["iterations"] == s.result["iterations"]
         np.testing.assert_array_equal(sols[i][0], s.x)
         np.testing.assert_array_equal(sols[i][1], s.y)
+
+
+def test_tuning_cache_reuses_choices(tmp_path, monkeypatch):
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("SCYLLA_TUNE_CACHE", str(path))
+    lp = I.workload(2, scale=0.013)  # a shape no other test tunes
+    infos = []
+    for _ in range(2):
+        with pdhg.Batch([lp], precision=1) as b:
+            b.solve(tol=1e-300, iter_limit=64)
+            infos.append(b.info())
+    lines = path.read_text().strip().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("gfx950")
+    assert infos[0] == infos[1]

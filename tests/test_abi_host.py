@@ -256,3 +256,15 @@ def test_tile_plan_covers_every_row_once(chunk, max_rows):
             assert all(spans[s][1] == spans[s + 1][0] for s in range(nseg - 1))
             covered[row] += 1
         assert np.all(covered == 1)
+
+
+def test_nnz_limit_rejected_before_reading_arrays(L):
+    rp = np.array([0, 2 ** 31], dtype=np.int64)
+    ci = np.zeros(1, dtype=np.int32)
+    v = np.zeros(1)
+    one = np.ones(1)
+    sense = np.array([ord("G")], dtype=np.uint8)
+    csr = pdhg.CSR(1, 1, 2 ** 31, pdhg._ptr(rp), pdhg._ptr(ci), pdhg._ptr(v))
+    desc = pdhg.LPDesc(csr, pdhg._ptr(one), pdhg._ptr(one), pdhg._ptr(sense), pdhg._ptr(one), pdhg._ptr(one))
+    assert L.scylla_validate_lp(ctypes.byref(desc)) == EINVAL
+    assert "nnz" in L.scylla_last_error().decode()

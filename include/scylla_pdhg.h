@@ -227,7 +227,8 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const double *x_ref, double *x_hat,
                          int32_t *info);
 
-/* One record per (round, instance) of scylla_batch_pump. */
+/* One record per (round, instance) of scylla_batch_pump and
+ * scylla_batch_pump_ex (round = 0: the instance took no part in that round). */
 typedef struct {
     int32_t round;          /* K, 1-based                                     */
     int32_t status;         /* status of this round's PDHG solve              */
@@ -236,7 +237,8 @@ typedef struct {
     int32_t lp_feasible;    /* the PDHG iterate itself is MIP-feasible (1e-6) */
     int32_t xhat_feasible;  /* the rounded point satisfies every row (1e-6)   */
     int32_t ignored_rows;   /* rows ignored by fix-and-propagate              */
-    int32_t reserved;
+    int32_t perturbed;      /* the rounding repeated an earlier one and was
+                               perturbed (scylla_batch_pump_ex only)          */
     double xhat_obj;        /* c^T x_hat with the original objective          */
     double solve_seconds;   /* device solve of the round (whole batch)        */
     double round_seconds;   /* whole round: solve, copy-out, rounding, blend  */
@@ -257,6 +259,73 @@ typedef struct {
  * the last round's. */
 int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds,
                       double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out);
+
+/* Options of the complete Algorithm 1 loop (scylla_batch_pump_ex). */
+typedef struct {
+    int32_t rounds;           /* most rounds K per instance, >= 1             */
+    int32_t eps_schedule;     /* 1: round K solves to eps(K), eps(1) = eps1,
+                                 eps(K+1) = max(beta eps(K), eps_floor)
+                                 (Section 2.2); 0: params->tol every round     */
+    double eps1, beta, eps_floor;
+    double alpha;             /* objective-update factor, in [0, 1)           */
+    int64_t total_iter_limit; /* cumulative PDHG iterations per instance over
+                                 all rounds (0: none); a round may run at most
+                                 min(params->iter_limit, what is left), and an
+                                 instance with nothing left stops             */
+    int32_t early_exit;       /* 1: an instance stops at the first round whose
+                                 PDHG iterate or rounding is MIP-feasible      */
+    int32_t perturb;          /* 1: a rounding equal to an earlier rounding of
+                                 the instance is perturbed                    */
+    uint64_t seed;            /* seed of the perturbation counts              */
+    int32_t threads;          /* host rounding workers, 0 = one per hardware
+                                 thread                                       */
+    int32_t reserved;
+} scylla_pump_params;
+
+/* Per-instance outcome of scylla_batch_pump_ex. */
+typedef struct {
+    int32_t found_kind;     /* 0 none, 1 the PDHG iterate, 2 the rounding     */
+    int32_t found_round;    /* round of the first find, 0 if none             */
+    int32_t rounds_run;     /* rounds in which the instance was solved        */
+    int32_t perturbations;  /* roundings that were perturbed                  */
+    int64_t iterations;     /* PDHG iterations over all its rounds            */
+    double obj;             /* c^T of the returned point                      */
+} scylla_pump_outcome;
+
+/* Defaults of the paper's configuration: 20 rounds, eps schedule on
+ * (0.01, 0.98, 1e-8), alpha 0.9, no cumulative limit, early exit and
+ * perturbation on, seed 0, threads 0. */
+int scylla_pump_params_default(scylla_pump_params *o);
+
+/* The complete outer loop of Algorithm 1 on every instance of the batch:
+ * each round solves all unfinished instances together on the device
+ * (warm-started from the previous round, round 1 from the projected origin),
+ * copies the iterates to the host, and per instance (thread pool): returns
+ * the PDHG iterate if it is MIP-feasible (rows within 1e-6 (1 + |b_i|),
+ * bounds and integrality within 1e-6); else rounds it by fix-and-propagate
+ * and returns the rounding if every row holds; else, when the rounding
+ * equals one of the instance's earlier roundings (after their
+ * perturbation), flips the T binary variables with the largest
+ * |x_bar_j - x_hat_j| (ties by lower index) to their other bound, where
+ * T = 10 + (SplitMix64(seed, instance * 2^20 + K) mod 21) and SplitMix64
+ * (Steele, Lea and Flood 2014) is the output for the state
+ * seed + (counter + 1) * 0x9E3779B97F4A7C15 (cycle perturbation, Algorithm 1
+ * and Section 2.3); then replaces the instance's objective on the device by
+ * alpha^K sqrt(|I|)/||c|| c + (1 - alpha^K) * (L1-distance gradient to the
+ * rounding).  With early_exit = 0 every instance runs all rounds and the
+ * first find is still reported.  The perturbation needs binary integer
+ * variables (-EINVAL otherwise, when it is needed); general integers
+ * strictly inside their bounds are rejected as in scylla_batch_pump.
+ * is_int: [n_total] 0/1 or NULL (all integer).  records: [rounds * count]
+ * round-major, or NULL.  outcome: [count] or NULL.  x_out: [n_total] or NULL,
+ * receives per instance the point of its first find, else its last
+ * rounding before perturbation (zeros if it ran no round).  params supplies
+ * precision, check period, restarts, eta, per-round iteration and time
+ * limits and, without the schedule, the tolerance.  Returns 0, -EINVAL or
+ * -EIO (device error). */
+int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uint8_t *is_int,
+                         const scylla_pump_params *opt, scylla_pump_record *records,
+                         scylla_pump_outcome *outcome, double *x_out);
 
 /* Pins the tile plan of both passes instead of autotuning it.  The
  * floating-point summation order (so the last bits of the iterates) is a

@@ -15,9 +15,11 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
                                 feasible integral input, set-cover success,
                                 brute-force propagation soundness)
   objective_update, eps_schedule pinned (closed forms / norm identities)
-  pump                          parity unpinned: the round of first success
+  pump, scylla                  parity unpinned: the round of first success
                                 depends on rounding choices the paper leaves
-                                open; only its invariants are checked.
+                                open; only invariants are checked (early
+                                exit, schedule, budget, perturbation rule).
+  splitmix64                    pinned (published reference outputs)
 """
 from __future__ import annotations
 
@@ -248,3 +250,97 @@ def pump(lp, rounds: int = 20, tol: float = 1e-4, iter_limit: int = 20_000,
                         obj=float(lp.c @ xhat)))
         c_hat = objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K)
     return out
+
+
+# ------------------------------------------------- Algorithm 1 outer loop
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    """SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the output for the
+    state seed + (counter + 1) * golden gamma.  The perturbation draws its
+    random numbers from this counter-based generator so that independent
+    implementations draw the same numbers."""
+    z = (seed + (counter + 1) * 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def perturb_count(seed: int, instance: int, K: int) -> int:
+    """Number of variables the K-th perturbation of an instance flips:
+    T = 10 + (splitmix64(seed, instance * 2^20 + K) mod 21), in [10, 30]."""
+    return 10 + splitmix64(seed, instance * 1048576 + K) % 21
+
+
+def perturb(lp, xbar, xhat, T):
+    """Cycle perturbation (Algorithm 1; Section 2.3 following the 2005
+    feasibility pump): flip the T binary variables with the largest
+    |x_bar_j - x_hat_j| (ties by index) to their other bound."""
+    ii = np.flatnonzero(lp.is_int.astype(bool))
+    if np.any((lp.u[ii] - lp.l[ii]) != 1.0):
+        raise ValueError("perturbation is defined here for binary variables only")
+    d = np.abs(xbar[ii] - xhat[ii])
+    order = np.lexsort((ii, -d))[: min(T, ii.size)]
+    out = xhat.copy()
+    j = ii[order]
+    out[j] = np.where(out[j] == lp.l[j], lp.u[j], lp.l[j])
+    return out
+
+
+def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter_limit: int = 100_000,
+           total_iter_limit: int = 0, early_exit: bool = True, cycle_perturb: bool = True, seed: int = 0,
+           instance: int = 0, alpha: float = ALPHA, **kw):
+    """Algorithm 1 on one instance.  Round K solves the LP relaxation with the
+    current objective to tolerance eps(K) (Section 2.2; `tol` if eps_sched
+    is off), warm-started from the previous round, with at most iter_limit
+    iterations and, if total_iter_limit > 0, at most what remains of the
+    cumulative budget (no budget left: the loop ends).  The first round whose
+    PDHG iterate, else whose rounding, is MIP-feasible is the find; with
+    early_exit the loop returns there.  A rounding equal to an earlier one
+    (history of roundings as used, i.e. after perturbation) is perturbed; the
+    objective is then updated with alpha^K from the rounding as used.
+    Returns (found_kind, found_round, point, records): found_kind 0 (none),
+    1 (PDHG iterate), 2 (rounding); point is the find, else the last
+    rounding before perturbation (None if no round ran)."""
+    c_hat = lp.c.copy()
+    x = y = None
+    omega = 0.0
+    history = []
+    used = 0
+    recs = []
+    kind, found_K, point = 0, 0, None
+    for K in range(1, rounds + 1):
+        lim = iter_limit
+        if total_iter_limit > 0:
+            lim = min(lim, total_iter_limit - used)
+        if lim <= 0:
+            break
+        tk = eps_schedule(K) if eps_sched else tol
+        r = pdhg(lp, tol=tk, iter_limit=lim, x0=x, y0=y, omega0=omega, c=c_hat, **kw)
+        used += r.iterations
+        x, y, omega = r.x, r.y, r.omega
+        rec = dict(K=K, tol=tk, status=r.status, iterations=r.iterations, rel_kkt=r.rel_kkt,
+                   lp_mip_feasible=mip_feasible(lp, r.x), perturbed=False, x=r.x)
+        recs.append(rec)
+        if rec["lp_mip_feasible"] and not kind:
+            kind, found_K, point = 1, K, r.x
+            if early_exit:
+                break
+        xhat, feas, ign = fix_propagate(lp, r.x)
+        rec.update(xhat=xhat, xhat_feasible=feas, ignored=ign, obj=float(lp.c @ xhat))
+        if not kind:
+            point = xhat
+            if feas:
+                kind, found_K = 2, K
+                if early_exit:
+                    break
+        if cycle_perturb:
+            if any(np.array_equal(xhat, h) for h in history):
+                xhat = perturb(lp, r.x, xhat, perturb_count(seed, instance, K))
+                rec["perturbed"] = True
+            history.append(xhat)
+        rec["xhat_used"] = xhat
+        if K < rounds:
+            c_hat = objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K, alpha)
+    return kind, found_K, point, recs

@@ -879,7 +879,10 @@ void fill_result(const InstState &S, scylla_result &r, double solve_s, double se
     r.setup_seconds = setup_s;
 }
 
-int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results)
+// k_limits (optional, [count]): per-instance iteration limit of this solve;
+// an instance with a limit <= 0 takes no part (its state is left as it is).
+int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results,
+                     const int64_t *k_limits = nullptr)
 {
     if (!h || !results) throw_err(-EINVAL, "handle or results is NULL");
     validate_params(p);
@@ -891,7 +894,12 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     }
     std::vector<InstState> st;
     read_states(h, st);
-    for (auto &S : st) {
+    for (int32_t q = 0; q < h->count; ++q) {
+        InstState &S = st[q];
+        if (k_limits && k_limits[q] <= 0) {
+            if (S.status == ST_RUN) S.status = ST_ITER;
+            continue;
+        }
         const double omega = (warm && S.omega > 0.0) ? S.omega : S.omega0;
         S.status = ST_RUN;
         S.nrun = 0;
@@ -900,7 +908,7 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
         S.restart_on = p->restarts ? 1 : 0;
         S.force_stop = 0;
         S.k = 0;
-        S.k_limit = p->iter_limit;
+        S.k_limit = k_limits ? std::min<int64_t>(k_limits[q], p->iter_limit) : p->iter_limit;
         S.kr = 0;
         S.omega = omega;
         S.eta = p->eta;
@@ -1038,12 +1046,79 @@ void reset_objective(scylla_batch *h)
     HIPC(hipGetLastError());
 }
 
-int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds, double alpha,
-              int32_t threads, scylla_pump_record *rec)
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as a counter-based
+// generator: the output function applied to the state seed + (counter + 1) *
+// the golden-ratio increment.
+uint64_t splitmix64(uint64_t seed, uint64_t counter)
 {
-    if (!h || !rec) throw_err(-EINVAL, "handle or records is NULL");
-    if (rounds < 1) throw_err(-EINVAL, "rounds must be >= 1");
-    if (!(alpha >= 0.0 && alpha < 1.0)) throw_err(-EINVAL, "alpha must be in [0, 1)");
+    uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Number of binaries the K-th perturbation of instance q flips, in [10, 30].
+int32_t perturb_count(uint64_t seed, int32_t q, int32_t K)
+{
+    return 10 + (int32_t)(splitmix64(seed, (uint64_t)q * 1048576ull + (uint64_t)K) % 21ull);
+}
+
+// Per-instance history of roundings for cycle detection: value hashes first,
+// then exact comparison (0.0 and -0.0 compare equal).
+struct RoundingHistory {
+    std::vector<uint64_t> hash;
+    std::vector<std::vector<double>> pts;
+
+    static uint64_t digest(const double *x, int32_t n)
+    {
+        uint64_t hsh = 1469598103934665603ull;
+        for (int32_t j = 0; j < n; ++j) {
+            double v = x[j] + 0.0;
+            uint64_t w;
+            memcpy(&w, &v, 8);
+            hsh = (hsh ^ w) * 1099511628211ull;
+        }
+        return hsh;
+    }
+    bool seen(const double *x, int32_t n) const
+    {
+        const uint64_t d = digest(x, n);
+        for (size_t k = 0; k < pts.size(); ++k) {
+            if (hash[k] != d) continue;
+            bool eq = true;
+            for (int32_t j = 0; j < n && eq; ++j) eq = pts[k][j] == x[j];
+            if (eq) return true;
+        }
+        return false;
+    }
+    void add(const double *x, int32_t n)
+    {
+        hash.push_back(digest(x, n));
+        pts.emplace_back(x, x + n);
+    }
+};
+
+struct PumpOpts {
+    int32_t rounds;
+    bool eps_sched;
+    double eps1, beta, eps_floor, alpha;
+    int64_t total_iter_limit;
+    bool early_exit, perturb;
+    uint64_t seed;
+    int32_t threads;
+};
+
+// Algorithm 1 outer loop.  legacy_best: also keep, per instance, the first
+// feasible rounding else the last one (scylla_batch_pump's output).
+int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, const PumpOpts &o,
+              scylla_pump_record *rec, scylla_pump_outcome *outc, double *x_out, bool legacy_best)
+{
+    if (!h) throw_err(-EINVAL, "handle is NULL");
+    if (o.rounds < 1) throw_err(-EINVAL, "rounds must be >= 1");
+    if (!(o.alpha >= 0.0 && o.alpha < 1.0)) throw_err(-EINVAL, "alpha must be in [0, 1)");
+    if (o.eps_sched && !(o.eps1 > 0.0 && o.beta > 0.0 && o.beta <= 1.0 && o.eps_floor > 0.0))
+        throw_err(-EINVAL, "eps schedule needs eps1 > 0, 0 < beta <= 1, eps_floor > 0");
+    if (o.total_iter_limit < 0) throw_err(-EINVAL, "total_iter_limit must be >= 0");
     validate_params(p);
     build_locals(h);
     const int32_t N = h->N, count = h->count;
@@ -1075,42 +1150,107 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, in
     reset_objective(h);
     HIPC(hipStreamSynchronize(h->stream));
 
-    std::vector<double> x(N), xhat(N);
-    h->pump_best.assign(N, 0.0);
-    std::vector<uint8_t> found(count, 0);
+    std::vector<double> x(N), xhat(N), xres(N, 0.0);
+    if (legacy_best) h->pump_best.assign(N, 0.0);
+    std::vector<uint8_t> found_best(count, 0), active(count, 1);
+    std::vector<scylla_pump_outcome> out(count);
+    memset(out.data(), 0, sizeof(scylla_pump_outcome) * count);
+    std::vector<RoundingHistory> hist(o.perturb ? count : 0);
+    std::vector<int64_t> limits(count);
     std::vector<scylla_result> res(count);
-    for (int32_t K = 1; K <= rounds; ++K) {
+    if (rec) memset(rec, 0, sizeof(scylla_pump_record) * (size_t)o.rounds * count);
+    double eps = o.eps1;
+    for (int32_t K = 1; K <= o.rounds; ++K) {
         const double t0 = now_s();
-        batch_solve_impl(h, p, K > 1 ? 1 : 0, res.data());
+        if (K > 1) eps = std::max(o.beta * eps, o.eps_floor);
+        int32_t n_active = 0;
+        for (int32_t q = 0; q < count; ++q) {
+            int64_t lim = p->iter_limit;
+            if (o.total_iter_limit > 0) lim = std::min(lim, o.total_iter_limit - out[q].iterations);
+            if (active[q] && lim <= 0) active[q] = 0;
+            limits[q] = active[q] ? lim : 0;
+            n_active += active[q];
+        }
+        if (n_active == 0) break;
+        scylla_params pk = *p;
+        if (o.eps_sched) pk.tol = eps;
+        batch_solve_impl(h, &pk, K > 1 ? 1 : 0, res.data(), limits.data());
         if (h->vbytes == 4) get_range<float>(h, h->x, 0, N, x.data());
         else get_range<double>(h, h->x, 0, N, x.data());
-        std::atomic<int> bad{0};
-        parallel_for(count, threads, [&](int32_t q) {
+        std::atomic<int> bad{0}, nonbinary{0};
+        parallel_for(count, o.threads, [&](int32_t q) {
+            if (!active[q]) return;
             const auto &P = h->local[q].P;
             const int32_t c0 = h->col_off[q];
             const uint8_t *ii = isint.data() + c0;
             const double *xq = x.data() + c0;
             double *xh = xhat.data() + c0;
+            scylla_pump_outcome &oc = out[q];
+            oc.rounds_run = K;
+            oc.iterations += res[q].iterations;
             bool integral = true;
             for (int32_t j = 0; j < P.n; ++j) {
                 if (xq[j] < P.l[j] - 1e-6 || xq[j] > P.u[j] + 1e-6) integral = false;
                 if (ii[j] && fabs(xq[j] - round(xq[j])) > 1e-6) integral = false;
             }
-            scylla_pump_record &r = rec[(size_t)(K - 1) * count + q];
+            scylla_pump_record rtmp;
+            scylla_pump_record &r = rec ? rec[(size_t)(K - 1) * count + q] : rtmp;
             memset(&r, 0, sizeof(r));
             r.round = K;
             r.status = res[q].status;
             r.iterations = res[q].iterations;
             r.rel_kkt = res[q].rel_kkt;
+            r.solve_seconds = res[q].solve_seconds;
             r.lp_feasible = (integral && rows_satisfied(P, xq, 1e-6)) ? 1 : 0;
+            if (r.lp_feasible && !oc.found_kind) {
+                oc.found_kind = 1;
+                oc.found_round = K;
+                memcpy(xres.data() + c0, xq, sizeof(double) * P.n);
+                if (o.early_exit) {
+                    active[q] = 0;
+                    return;
+                }
+            }
             fix_and_propagate(P, ii, xq, xh, &r.xhat_feasible, &r.ignored_rows);
             double obj = 0.0;
             for (int32_t j = 0; j < P.n; ++j) obj += h->hc[c0 + j] * xh[j];
             r.xhat_obj = obj;
-            r.solve_seconds = res[q].solve_seconds;
-            if (!found[q]) {
+            if (legacy_best && !found_best[q]) {
                 memcpy(h->pump_best.data() + c0, xh, sizeof(double) * P.n);
-                if (r.xhat_feasible) found[q] = 1;
+                if (r.xhat_feasible) found_best[q] = 1;
+            }
+            if (!oc.found_kind) memcpy(xres.data() + c0, xh, sizeof(double) * P.n);
+            if (r.xhat_feasible && !oc.found_kind) {
+                oc.found_kind = 2;
+                oc.found_round = K;
+                if (o.early_exit) {
+                    active[q] = 0;
+                    return;
+                }
+            }
+            if (o.perturb) {
+                if (hist[q].seen(xh, P.n)) {
+                    // flip the T binaries farthest from the PDHG iterate
+                    std::vector<int32_t> idx;
+                    for (int32_t j = 0; j < P.n; ++j)
+                        if (ii[j]) {
+                            if (P.u[j] - P.l[j] != 1.0) nonbinary = 1;
+                            idx.push_back(j);
+                        }
+                    if (!nonbinary) {
+                        const size_t T = std::min<size_t>((size_t)perturb_count(o.seed, q, K), idx.size());
+                        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+                            return fabs(xq[a] - xh[a]) > fabs(xq[b] - xh[b]);
+                        });
+                        for (size_t t = 0; t < T; ++t) {
+                            const int32_t j = idx[t];
+                            xh[j] = xh[j] == P.l[j] ? P.u[j] : P.l[j];
+                        }
+                        r.perturbed = 1;
+                        ++oc.perturbations;
+                    }
+                }
+                hist[q].add(xh, P.n);
             }
             // L1-distance gradient needs every integer at a bound
             uint8_t *xb = xbits.data() + boff[q];
@@ -1121,12 +1261,16 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, in
                 else if (xh[j] != P.l[j]) bad = 1;
             }
         });
+        if (nonbinary) throw_err(-EINVAL, "cycle perturbation needs binary integer variables");
         if (bad) throw_err(-EINVAL, "an integer variable is rounded strictly inside its bounds: the L1 distance "
                                     "of general integers needs auxiliary variables");
-        if (K < rounds) {
-            const double a = pow(alpha, (double)K);
+        bool any = false;
+        for (int32_t q = 0; q < count; ++q) any = any || active[q];
+        if (K < o.rounds && any) {
+            const double a = pow(o.alpha, (double)K);
             HIPC(hipMemcpyAsync(h->bits_tmp.p, xbits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
             for (int32_t q = 0; q < count; ++q) {
+                if (!active[q]) continue;
                 const int lo = h->col_off[q], hi = h->col_off[q + 1];
                 const uint8_t *xb = h->bits_tmp.as<uint8_t>() + boff[q];
                 const uint8_t *ib = h->ibits_tmp.as<uint8_t>() + boff[q];
@@ -1143,8 +1287,18 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, in
             HIPC(hipStreamSynchronize(h->stream));
         }
         const double dt = now_s() - t0;
-        for (int32_t q = 0; q < count; ++q) rec[(size_t)(K - 1) * count + q].round_seconds = dt;
+        if (rec)
+            for (int32_t q = 0; q < count; ++q)
+                if (rec[(size_t)(K - 1) * count + q].round) rec[(size_t)(K - 1) * count + q].round_seconds = dt;
+        if (!any) break;
     }
+    for (int32_t q = 0; q < count; ++q) {
+        double obj = 0.0;
+        for (int32_t j = h->col_off[q]; j < h->col_off[q + 1]; ++j) obj += h->hc[j] * xres[j];
+        out[q].obj = obj;
+    }
+    if (outc) memcpy(outc, out.data(), sizeof(scylla_pump_outcome) * count);
+    if (x_out) memcpy(x_out, xres.data(), sizeof(double) * N);
     return 0;
 }
 
@@ -1436,9 +1590,43 @@ int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is
                       double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out)
 {
     return guarded([&]() {
-        pump_impl(h, p, is_int, rounds, alpha, threads, records);
+        PumpOpts o{rounds, false, 0.0, 0.0, 0.0, alpha, 0, false, false, 0, threads};
+        pump_impl(h, p, is_int, o, records, nullptr, nullptr, true);
         if (xhat_out) memcpy(xhat_out, h->pump_best.data(), sizeof(double) * h->N);
         return 0;
+    });
+}
+
+int scylla_pump_params_default(scylla_pump_params *o)
+{
+    if (!o) {
+        g_err = "pump params is NULL";
+        return -EINVAL;
+    }
+    memset(o, 0, sizeof(*o));
+    o->rounds = 20;
+    o->eps_schedule = 1;
+    o->eps1 = 0.01;
+    o->beta = 0.98;
+    o->eps_floor = 1e-8;
+    o->alpha = 0.9;
+    o->total_iter_limit = 0;
+    o->early_exit = 1;
+    o->perturb = 1;
+    o->seed = 0;
+    o->threads = 0;
+    return 0;
+}
+
+int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uint8_t *is_int,
+                         const scylla_pump_params *opt, scylla_pump_record *records,
+                         scylla_pump_outcome *outcome, double *x_out)
+{
+    return guarded([&]() {
+        if (!opt) throw_err(-EINVAL, "pump params is NULL");
+        PumpOpts o{opt->rounds, opt->eps_schedule != 0, opt->eps1, opt->beta, opt->eps_floor, opt->alpha,
+                   opt->total_iter_limit, opt->early_exit != 0, opt->perturb != 0, opt->seed, opt->threads};
+        return pump_impl(h, params, is_int, o, records, outcome, x_out, false);
     });
 }
 

@@ -280,6 +280,36 @@ def cover_knapsack(m: int, n: Optional[int] = None, seed=None,
               is_int=np.ones(n, dtype=np.uint8), x_star=np.full(n, 0.3), name=name)
 
 
+def set_partition(m: int = 30, n: int = 120, seed=None, name: str = "set_partition") -> LP:
+    """Set-partitioning MIP (A x = 1, x binary), the equality-constrained
+    class on which rounding-based heuristics cycle.  A planted partition of
+    the rows into blocks of U{1..4} rows, one column per block, keeps it
+    feasible; the other columns hit U{2..8} distinct uniform rows; the
+    columns are shuffled; c_j ~ U{1..19}."""
+    rng = np.random.default_rng(config_seed(6) if seed is None else seed)
+    perm = rng.permutation(m)
+    sizes = []
+    while sum(sizes) < m:
+        sizes.append(int(min(rng.integers(1, 5), m - sum(sizes))))
+    planted = np.split(perm, np.cumsum(sizes)[:-1])
+    if len(planted) > n:
+        raise ValueError("n is too small for the planted partition")
+    cols = [np.sort(g) for g in planted]
+    for _ in range(n - len(planted)):
+        cols.append(np.sort(rng.choice(m, size=int(min(rng.integers(2, 9), m)), replace=False)))
+    order = rng.permutation(n)
+    cols = [cols[j] for j in order]
+    col = np.concatenate([np.full(len(r), j) for j, r in enumerate(cols)])
+    row = np.concatenate(cols)
+    row_ptr, col_idx, val = _csr_from_pairs(m, row, col, np.ones(row.size))
+    x_star = np.zeros(n)
+    x_star[np.argsort(order)[: len(planted)]] = 1.0
+    return LP(m=m, n=n, row_ptr=row_ptr, col_idx=col_idx, val=val,
+              c=rng.integers(1, 20, size=n).astype(np.float64), b=np.ones(m),
+              senses=np.full(m, ord("E"), dtype=np.uint8), l=np.zeros(n), u=np.ones(n),
+              is_int=np.ones(n, dtype=np.uint8), x_star=x_star, name=name)
+
+
 def batch_sizes(count: int = 256, lo: int = 1_000, hi: int = 50_000, seed=None) -> np.ndarray:
     """Row counts m_i = round(exp(U[ln lo, ln hi]))."""
     rng = np.random.default_rng(config_seed(4) if seed is None else seed)

@@ -27,6 +27,7 @@ EXPORTS = [
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
     "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
+    "scylla_pump_params_default", "scylla_batch_pump_ex",
 ]
 
 
@@ -112,6 +113,9 @@ def lib():
             "scylla_fix_propagate": ([ctypes.POINTER(LPDesc), vp, vp, vp, vp], ctypes.c_int),
             "scylla_batch_pump": ([vp, ctypes.POINTER(Params), vp, i32, dbl, i32, ctypes.POINTER(PumpRecord), vp],
                                   ctypes.c_int),
+            "scylla_pump_params_default": ([ctypes.POINTER(PumpParams)], ctypes.c_int),
+            "scylla_batch_pump_ex": ([vp, ctypes.POINTER(Params), vp, ctypes.POINTER(PumpParams),
+                                      ctypes.POINTER(PumpRecord), ctypes.POINTER(PumpOutcome), vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -144,11 +148,38 @@ class PumpRecord(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("rel_kkt", ctypes.c_double), ("lp_feasible", ctypes.c_int32),
                 ("xhat_feasible", ctypes.c_int32), ("ignored_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("xhat_obj", ctypes.c_double),
+                ("perturbed", ctypes.c_int32), ("xhat_obj", ctypes.c_double),
                 ("solve_seconds", ctypes.c_double), ("round_seconds", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PumpParams(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("eps_schedule", ctypes.c_int32), ("eps1", ctypes.c_double),
+                ("beta", ctypes.c_double), ("eps_floor", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("total_iter_limit", ctypes.c_int64), ("early_exit", ctypes.c_int32),
+                ("perturb", ctypes.c_int32), ("seed", ctypes.c_uint64), ("threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class PumpOutcome(ctypes.Structure):
+    _fields_ = [("found_kind", ctypes.c_int32), ("found_round", ctypes.c_int32),
+                ("rounds_run", ctypes.c_int32), ("perturbations", ctypes.c_int32),
+                ("iterations", ctypes.c_int64), ("obj", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def pump_params(**kw) -> PumpParams:
+    o = PumpParams()
+    _check(lib().scylla_pump_params_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k) or k == "reserved":
+            raise TypeError(f"unknown pump parameter {k}")
+        setattr(o, k, v)
+    return o
 
 
 class _LPArrays:
@@ -298,6 +329,21 @@ class Batch:
         _check(lib().scylla_batch_pump(self._h, ctypes.byref(p), _ptr(ii), rounds, alpha, threads, recs, _ptr(xh)))
         out = [[recs[k * self.count + q].as_dict() for q in range(self.count)] for k in range(rounds)]
         return out, xh
+
+    def pump_ex(self, is_int=None, pump: dict | None = None, **kw):
+        """Complete Algorithm 1 loop (scylla_batch_pump_ex).  `pump` holds
+        scylla_pump_params fields, `kw` scylla_params fields.  Returns
+        (records [rounds][count] as dicts, outcomes [count] as dicts, x_out)."""
+        p = params(precision=self.precision, **kw)
+        o = pump_params(**(pump or {}))
+        recs = (PumpRecord * (o.rounds * self.count))()
+        outs = (PumpOutcome * self.count)()
+        ii = None if is_int is None else np.ascontiguousarray(is_int, dtype=np.uint8)
+        xo = np.empty(sum(self.n))
+        _check(lib().scylla_batch_pump_ex(self._h, ctypes.byref(p), _ptr(ii), ctypes.byref(o), recs, outs,
+                                          _ptr(xo)))
+        out = [[recs[k * self.count + q].as_dict() for q in range(self.count)] for k in range(o.rounds)]
+        return out, [outs[q].as_dict() for q in range(self.count)], xo
 
     def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
         """Pin the tile plan (0 / 4 / 8 gather blocks, 4 / 8 / 16 nonzeros per thread)."""

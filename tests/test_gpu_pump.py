@@ -94,3 +94,93 @@ def test_native_rounding_matches_oracle_on_device_iterate():
     xo, feas, ign = oracle.fix_propagate(lp, x)
     np.testing.assert_array_equal(xh, xo)
     assert recs[0][0]["xhat_feasible"] == int(feas) and recs[0][0]["ignored_rows"] == ign
+
+
+# ------------------------------------------- complete Algorithm 1 loop
+def _loop_batch():
+    lps = [I.set_partition(12, 40, seed=s) for s in range(6)]
+    lps += [I.set_partition(20, 100, seed=4), I.set_partition(20, 100, seed=5), I.cover_knapsack(300, seed=0)]
+    return lps
+
+
+def _oracle_loop(lps, **kw):
+    return [oracle.scylla(lp, instance=q, **kw) for q, lp in enumerate(lps)]
+
+
+def _compare_loop(lps, recs, outs, xo, ref):
+    off = np.cumsum([0] + [lp.n for lp in lps])
+    for q, lp in enumerate(lps):
+        kind, K, point, rr = ref[q]
+        o = outs[q]
+        print(q, o, (kind, K, len(rr)), flush=True)
+        assert (o["found_kind"], o["found_round"], o["rounds_run"]) == (kind, K, len(rr)), q
+        assert o["perturbations"] == sum(r["perturbed"] for r in rr), q
+        assert o["iterations"] == sum(r["iterations"] for r in rr), q
+        for k, r in enumerate(rr):
+            d = recs[k][q]
+            assert d["round"] == k + 1 and d["iterations"] == r["iterations"], (q, k)
+            assert d["lp_feasible"] == int(r["lp_mip_feasible"]) and d["perturbed"] == int(r["perturbed"])
+            if "xhat" in r:
+                assert d["xhat_feasible"] == int(r["xhat_feasible"]) and d["xhat_obj"] == pytest.approx(r["obj"], rel=1e-12)
+        for k in range(len(rr), len(recs)):
+            assert recs[k][q]["round"] == 0
+        xq = xo[off[q]:off[q + 1]]
+        if point is None:
+            assert np.all(xq == 0)
+        elif kind == 1:
+            assert rel_err(xq, point) <= 1e-9
+        else:
+            np.testing.assert_array_equal(xq, point)
+        assert o["obj"] == pytest.approx(float(lp.c @ xq), rel=1e-12, abs=1e-12)
+
+
+def test_full_loop_matches_oracle_fp64():
+    """Closed loop in FP64: the device iterates match the oracle's to
+    rounding, so every round's rounding, cycle check and perturbation and
+    the round of the first find are the oracle's."""
+    lps = _loop_batch()
+    ref = _oracle_loop(lps, rounds=20, seed=5)
+    with pdhg.Batch(lps, precision=0) as b:
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=20, seed=5))
+    _compare_loop(lps, recs, outs, xo, ref)
+    assert any(o["perturbations"] for o in outs) and any(o["found_kind"] == 2 for o in outs)
+
+
+def test_full_loop_budget_and_no_early_exit_fp64():
+    lps = _loop_batch()[:4]
+    ref = _oracle_loop(lps, rounds=12, seed=9, total_iter_limit=3000, iter_limit=700, early_exit=False,
+                       eps_sched=False, tol=1e-5)
+    with pdhg.Batch(lps, precision=0) as b:
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=12, seed=9, total_iter_limit=3000, early_exit=0,
+                                             eps_schedule=0), tol=1e-5, iter_limit=700)
+    _compare_loop(lps, recs, outs, xo, ref)
+    assert all(o["iterations"] <= 3000 for o in outs)
+
+
+def test_full_loop_fp32_invariants():
+    lps = _loop_batch()
+    with pdhg.Batch(lps, precision=1) as b:
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=20, seed=5))
+    off = np.cumsum([0] + [lp.n for lp in lps])
+    for q, lp in enumerate(lps):
+        o = outs[q]
+        xq = xo[off[q]:off[q + 1]]
+        run = [recs[k][q] for k in range(20) if recs[k][q]["round"]]
+        assert len(run) == o["rounds_run"] and sum(r["iterations"] for r in run) == o["iterations"]
+        for k, r in enumerate(run):
+            assert r["round"] == k + 1
+            assert r["status"] != pdhg.OPTIMAL or r["rel_kkt"] <= oracle.eps_schedule(k + 1) * (1 + 1e-6)
+        if o["found_kind"]:
+            assert o["found_round"] == o["rounds_run"]  # early exit
+            assert oracle.mip_feasible(lp, xq)
+        else:
+            assert o["rounds_run"] == 20 and np.all((xq == 0) | (xq == 1))
+    assert outs[-1]["found_kind"] in (1, 2) and outs[-1]["found_round"] == 1  # cover + knapsack
+
+
+def test_full_loop_rejects_bad_options():
+    lps = _loop_batch()[:2]
+    with pdhg.Batch(lps, precision=1) as b:
+        for bad in (dict(rounds=0), dict(alpha=1.0), dict(eps1=0.0), dict(beta=1.5), dict(total_iter_limit=-1)):
+            with pytest.raises(pdhg.ScyllaError):
+                b.pump_ex(pump=bad)

@@ -196,3 +196,82 @@ def test_fp_propagates_through_a_single_infinite_term():
     xhat, feas, ign = oracle.fix_propagate(lp, np.array([0.9, 10.0, 20.0]))
     np.testing.assert_array_equal(xhat, [1.0, 1.0, 5.0])
     assert feas and ign == 0
+
+
+# ---------------------------------------------- Algorithm 1 outer loop
+def test_splitmix64_reference_values():
+    """Published SplitMix64 outputs for seed 0 (first three draws of the
+    reference generator: 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4,
+    0x06c45d188009454f)."""
+    assert [oracle.splitmix64(0, k) for k in range(3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for K in range(1, 50):
+        assert 10 <= oracle.perturb_count(7, 3, K) <= 30
+
+
+def test_perturbation_flips_the_largest_gaps():
+    lp = I.cover_knapsack(200, seed=1)
+    rng = np.random.default_rng(0)
+    xbar = rng.random(lp.n)
+    xhat = np.round(xbar)
+    out = oracle.perturb(lp, xbar, xhat, 12)
+    flipped = np.flatnonzero(out != xhat)
+    assert flipped.size == 12
+    gap = np.abs(xbar - xhat)
+    assert gap[flipped].min() >= np.delete(gap, flipped).max()
+    assert np.all((out == 0) | (out == 1))
+
+
+def test_scylla_loop_early_exit_and_schedule():
+    lp = I.workload(1)  # set cover: the first rounding is always feasible
+    kind, K, point, recs = oracle.scylla(lp, rounds=5)
+    assert kind in (1, 2) and K == 1 and len(recs) == 1
+    assert recs[0]["tol"] == PAPER["eps_initial"]["value"]
+    assert oracle.mip_feasible(lp, point)
+    # without early exit all rounds run, the schedule tightens, and the
+    # first find is still reported
+    kind2, K2, point2, recs = oracle.scylla(lp, rounds=4, early_exit=False)
+    assert (kind2, K2) == (kind, 1) and np.array_equal(point2, point) and len(recs) == 4
+    assert [r["tol"] for r in recs] == [oracle.eps_schedule(k) for k in range(1, 5)]
+
+
+def test_scylla_cumulative_iteration_limit():
+    lp = I.cover_knapsack(400, seed=9)
+    kind, K, point, recs = oracle.scylla(lp, rounds=50, early_exit=False, eps_sched=False, tol=1e-9,
+                                         total_iter_limit=1000, iter_limit=300)
+    assert sum(r["iterations"] for r in recs) <= 1000
+    assert all(r["iterations"] <= 300 for r in recs)
+
+
+def test_set_partition_generator_planted_point():
+    for seed in range(4):
+        lp = I.set_partition(25, 90, seed=seed)
+        assert oracle.mip_feasible(lp, lp.x_star)
+        assert np.all(lp.val == 1.0) and np.all(lp.senses == ord("E"))
+
+
+def test_scylla_cycle_perturbation_rule():
+    """Set partitioning cycles: each perturbed round's rounding repeated an
+    earlier rounding as used, and exactly T = perturb_count(seed, q, K)
+    binaries were flipped, those with the largest |x_bar - x_hat|."""
+    seen = 0
+    for q, seed in enumerate(range(3)):
+        lp = I.set_partition(20, 60, seed=seed)
+        kind, K, point, recs = oracle.scylla(lp, rounds=20, seed=11, instance=q)
+        used = []
+        for r in recs:
+            if "xhat" not in r:
+                continue
+            if r["perturbed"]:
+                seen += 1
+                assert any(np.array_equal(r["xhat"], u) for u in used)
+                flipped = np.flatnonzero(r["xhat_used"] != r["xhat"])
+                T = oracle.perturb_count(11, q, r["K"])
+                assert flipped.size == min(T, lp.n)
+                gap = np.abs(r["x"] - r["xhat"])
+                assert gap[flipped].min() >= np.delete(gap, flipped).max(initial=0.0)
+            else:
+                assert not any(np.array_equal(r["xhat"], u) for u in used)
+                assert r["xhat_used"] is r["xhat"]
+            used.append(r["xhat_used"])
+    assert seen >= 3

@@ -330,8 +330,8 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
 /* Pins the tile plan of both passes instead of autotuning it.  The
  * floating-point summation order (so the last bits of the iterates) is a
  * function of the plan; a pinned plan makes results reproducible across
- * runs and devices.  *_blocks: 0 = normal layout, 4 or 8 = gather-blocked
- * layout with that many blocks (one per XCD or per XCD pair), -1 = LDS-staged
+ * runs and devices.  *_blocks: 0 = normal layout, 2, 4 or 8 = gather-blocked
+ * layout with that many blocks (one per four XCDs, per XCD pair or per XCD), -1 = LDS-staged
  * layout (instances whose gathered vector fits in LDS are processed with
  * that vector copied to LDS, in tiles of about 32768 nonzeros); *_ept: 4, 8
  * or 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL

@@ -637,8 +637,8 @@ TuneChoice current_choice(scylla_batch *h)
 
 // Times the layout / tile-size candidates of each orientation and keeps the
 // fastest: the normal layout with 4, 8 or 16 nonzeros per thread, and, when
-// the gathered vector is larger than 2 MB, the gather-blocked layout with 4
-// or 8 blocks (one block per XCD or per XCD pair).
+// the gathered vector is larger than 2 MB, the gather-blocked layout with 2,
+// 4 or 8 blocks (one block per XCD, per XCD pair or per four XCDs).
 template <class V>
 void autotune(scylla_batch *h)
 {
@@ -660,6 +660,7 @@ void autotune(scylla_batch *h)
         int best_B = 0, best_ept = 8;
         std::vector<int> Bs = {0};
         if ((int64_t)o.gather * h->vbytes > (2 << 20) && o.rows > 0) {
+            Bs.push_back(2);
             Bs.push_back(4);
             Bs.push_back(8);
         }
@@ -1635,10 +1636,10 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
 {
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
-        auto okB = [](int32_t B) { return B == 0 || B == 4 || B == 8 || B == -1; };
+        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == -1; };
         auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -1, 0, 4 or 8 and ept 4, 8 or 16");
+            throw_err(-EINVAL, "blocks must be -1, 0, 2, 4 or 8 and ept 4, 8 or 16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;

@@ -346,7 +346,7 @@ class Batch:
         return out, [outs[q].as_dict() for q in range(self.count)], xo
 
     def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
-        """Pin the tile plan (0 / 4 / 8 gather blocks, 4 / 8 / 16 nonzeros per thread)."""
+        """Pin the tile plan (-1 LDS-staged, 0 normal, 2 / 4 / 8 gather blocks; 4 / 8 / 16 nonzeros per thread)."""
         _check(lib().scylla_batch_set_layout(self._h, row_blocks, row_ept, col_blocks, col_ept))
 
     def time_passes(self, reps: int = 20):

@@ -1,6 +1,8 @@
 // Test driver for the library's host-side preparation (no GPU): reads a
-// batch of LPs from a binary file, runs build_orientations and plan_tiles,
-// and writes the results back as raw arrays for the Python checks.
+// batch of LPs from a binary file, runs build_orientations and plan_tiles
+// (and, when asked, build_blocked / plan_blocked with B blocks and
+// plan_staged), and writes the results back as raw arrays for the Python
+// checks.  Usage: in out chunk max_rows [B [max_vec sub_chunk group_nnz]].
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -73,6 +75,31 @@ int main(int argc, char **argv)
     }
     for (auto *p : {&pr, &pc}) {
         wr(o, p->tiles); wr(o, p->longs); wr(o, p->t_begin); wr(o, p->t_end); wr(o, p->l_begin); wr(o, p->l_end);
+    }
+    const int32_t B = argc > 5 ? atoi(argv[5]) : 0;
+    if (B > 0) {
+        for (int d = 0; d < 2; ++d) {
+            const scy::HostOrient &x = d == 0 ? csr : csc;
+            const std::vector<int32_t> &off = d == 0 ? ro : co, &gof = d == 0 ? co : ro;
+            scy::BlockedHost bh;
+            scy::build_blocked(x, fmt, gof.back(), B, bh);
+            scy::BlockedPlan bp;
+            scy::plan_blocked(bh, (int32_t)x.ptr.size() - 1, off, chunk, max_rows, bp);
+            wr(o, bh.bounds); wr(o, bh.bptr); wr(o, bh.ent); wr(o, bh.v16); wr(o, bh.v32); wr(o, bh.v64);
+            wr(o, bp.tiles); wr(o, bp.longs); wr(o, bp.ctiles);
+        }
+    }
+    if (argc > 8) {
+        const int32_t max_vec = atoi(argv[6]), sub_chunk = atoi(argv[7]), group_nnz = atoi(argv[8]);
+        for (int d = 0; d < 2; ++d) {
+            const scy::HostOrient &x = d == 0 ? csr : csc;
+            const std::vector<int32_t> &off = d == 0 ? ro : co, &gof = d == 0 ? co : ro;
+            scy::StagedPlan sp;
+            scy::plan_staged(x.ptr, off, gof, max_vec, sub_chunk, group_nnz, chunk, sp);
+            std::vector<int32_t> staged(sp.staged.begin(), sp.staged.end());
+            wr(o, sp.tiles); wr(o, sp.sub.tiles); wr(o, sp.sub.longs); wr(o, staged);
+            wr(o, sp.rest.tiles); wr(o, sp.rest.longs);
+        }
     }
     fclose(o);
     return 0;

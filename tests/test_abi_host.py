@@ -135,7 +135,7 @@ def _driver():
     return _DRIVER
 
 
-def _run_prep(lps, precision, chunk, max_rows):
+def _run_prep(lps, precision, chunk, max_rows, extra=()):
     d = tempfile.mkdtemp()
     fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
     with open(fin, "wb") as f:
@@ -147,7 +147,7 @@ def _run_prep(lps, precision, chunk, max_rows):
                             (lp.c, np.float64), (lp.b, np.float64), (lp.senses, np.uint8),
                             (lp.l, np.float64), (lp.u, np.float64)):
                 f.write(np.ascontiguousarray(arr, dtype=dt).tobytes())
-    subprocess.check_call([_driver(), fin, fout, str(chunk), str(max_rows)])
+    subprocess.check_call([_driver(), fin, fout, str(chunk), str(max_rows)] + [str(a) for a in extra])
     raw = open(fout, "rb").read()
     pos = 0
     out = []
@@ -165,6 +165,19 @@ def _run_prep(lps, precision, chunk, max_rows):
                    v64=take(np.float64)) for _ in range(2)]
     plans = [dict(tiles=take(np.int32).reshape(-1, 4), longs=take(np.int32).reshape(-1, 4),
                   tb=take(np.int32), te=take(np.int32), lb=take(np.int32), le=take(np.int32)) for _ in range(2)]
+    more = []
+    if len(extra) >= 1 and int(extra[0]) > 0:
+        more.append([dict(bounds=take(np.int32), bptr=take(np.int32), ent=take(np.uint32), v16=take(np.uint16),
+                          v32=take(np.float32), v64=take(np.float64), tiles=take(np.int32).reshape(-1, 4),
+                          longs=take(np.int32).reshape(-1, 4), ctiles=take(np.int32).reshape(-1, 4))
+                     for _ in range(2)])
+    if len(extra) >= 4:
+        more.append([dict(tiles=take(np.int32).reshape(-1, 4), sub=take(np.int32).reshape(-1, 4),
+                          sublongs=take(np.int32).reshape(-1, 4), staged=take(np.int32),
+                          rest=take(np.int32).reshape(-1, 4), restlongs=take(np.int32).reshape(-1, 4))
+                     for _ in range(2)])
+    if more:
+        return (hdr, ro, co, orient, plans) + tuple(more)
     return hdr, ro, co, orient, plans
 
 
@@ -268,3 +281,116 @@ def test_nnz_limit_rejected_before_reading_arrays(L):
     desc = pdhg.LPDesc(csr, pdhg._ptr(one), pdhg._ptr(one), pdhg._ptr(sense), pdhg._ptr(one), pdhg._ptr(one))
     assert L.scylla_validate_lp(ctypes.byref(desc)) == EINVAL
     assert "nnz" in L.scylla_last_error().decode()
+
+
+def _decode_idx(ent, hdr, which, fmt):
+    if fmt != 0:
+        return ent.astype(np.int64)
+    mask = np.uint32(int(hdr[2] if which == 0 else hdr[4]) & 0xFFFFFFFF)
+    return (ent & mask).astype(np.int64)
+
+
+def _check_cover(ptr_rows, plan_tiles, plan_longs, rows_wanted, chunk=None, max_rows=None):
+    """Normal tiles + long rows cover every wanted row once."""
+    covered = np.zeros(ptr_rows.size - 1, dtype=np.int64)
+    segs = {}
+    for a, b, inst, slot in plan_tiles:
+        if slot < 0:
+            covered[a:b] += 1
+            if max_rows:
+                assert b - a <= max_rows
+            if chunk:
+                assert ptr_rows[b] - ptr_rows[a] <= chunk
+        else:
+            segs[slot] = (a, b)
+    for row, slot0, nseg, inst in plan_longs:
+        spans = [segs[slot0 + s] for s in range(nseg)]
+        assert spans[0][0] == ptr_rows[row] and spans[-1][1] == ptr_rows[row + 1]
+        covered[row] += 1
+    assert np.all(covered[rows_wanted] == 1) and np.all(np.delete(covered, rows_wanted) == 0)
+
+
+@pytest.mark.parametrize("B", [2, 4, 8])
+def test_gather_blocked_layout(B):
+    """Every row's nonzeros are split by gathered-index slice without loss or
+    reordering, tiles of block b sit where workgroups run on XCDs x with
+    x mod B = b, and the block tiles plus long sub-rows cover every
+    (block, row) once; combine tiles cover every row once."""
+    lps = [I.workload(3, scale=0.002), I.workload(2, scale=0.0003)]
+    chunk, max_rows = 256, 64
+    hdr, ro, co, orient, plans, blk = _run_prep(lps, 1, chunk, max_rows, extra=(B,))
+    for which in (0, 1):
+        o, bl = orient[which], blk[which]
+        rows = o["ptr"].size - 1
+        g = (co if which == 0 else ro)[-1]
+        np.testing.assert_array_equal(bl["bounds"], [(g * b) // B for b in range(B + 1)])
+        idx = _decode_idx(o["ent"], hdr, which, hdr[0])
+        bidx = _decode_idx(bl["ent"], hdr, which, hdr[0])
+        bptr = bl["bptr"].reshape(B, rows + 1)
+        for i in np.random.default_rng(which).choice(rows, size=min(rows, 400), replace=False):
+            parts = []
+            for b in range(B):
+                seg = bidx[bptr[b, i]:bptr[b, i + 1]]
+                assert np.all((seg >= bl["bounds"][b]) & (seg < bl["bounds"][b + 1]))
+                parts.append(bl["ent"][bptr[b, i]:bptr[b, i + 1]])
+            np.testing.assert_array_equal(np.concatenate(parts), o["ent"][o["ptr"][i]:o["ptr"][i + 1]])
+        # tiles: XCD placement and coverage per block
+        for p, (a, bnd, z, slot) in enumerate(bl["tiles"]):
+            if slot >= 0 or bnd > a:
+                assert (p % 8) % B == (z >> 24)
+        for b in range(B):
+            tb = [t for t in bl["tiles"] if (t[2] >> 24) == b and (t[3] >= 0 or t[1] > t[0])]
+            lb = [l for l in bl["longs"] if (l[3] >> 24) == b]
+            # long sub-rows reference segment slots of all blocks; keep only this block's
+            slots = {l[1] + s for l in lb for s in range(l[2])}
+            tb = [t for t in tb if t[3] < 0 or t[3] in slots]
+            nonempty = np.flatnonzero(np.diff(bptr[b]) > 0)
+            covered = np.zeros(rows, dtype=np.int64)
+            for a, bnd, z, slot in tb:
+                if slot < 0:
+                    covered[a:bnd] += 1
+                    assert bptr[b, bnd] - bptr[b, a] <= chunk
+            for row, *_ in lb:
+                covered[row] += 1
+            assert np.all(covered[nonempty] == 1)
+        off = ro if which == 0 else co
+        cov = np.zeros(rows, dtype=np.int64)
+        for a, bnd, q, _ in bl["ctiles"]:
+            assert off[q] <= a < bnd <= off[q + 1] and bnd - a <= 256
+            cov[a:bnd] += 1
+        assert np.all(cov == 1)
+
+
+def test_lds_staged_plan():
+    """Instances qualify when their gathered vector has at most max_vec
+    elements and no row exceeds a sub-tile; their sub-tiles cover every row
+    once and are grouped in order into tiles of about group_nnz nonzeros;
+    the other instances are covered by normal tiles."""
+    lps = I.uneven_batch(count=8, lo=200, hi=6000, seed=3) + [I.workload(3, scale=0.0005)]
+    chunk, max_rows, max_vec, sub_chunk, group = 1024, 1024, 9000, 4096, 16384
+    out = _run_prep(lps, 1, chunk, max_rows, extra=(0, max_vec, sub_chunk, group))
+    hdr, ro, co, orient, plans, st = out
+    for which in (0, 1):
+        o, sp = orient[which], st[which]
+        ptr = o["ptr"]
+        off, gof = (ro, co) if which == 0 else (co, ro)
+        for q in range(len(lps)):
+            rl = np.diff(ptr[off[q]:off[q + 1] + 1])
+            want = gof[q + 1] - gof[q] <= max_vec and off[q + 1] > off[q] and rl.max(initial=0) <= sub_chunk
+            assert bool(sp["staged"][q]) == want, (which, q)
+        staged_rows = np.concatenate([np.arange(off[q], off[q + 1]) for q in range(len(lps)) if sp["staged"][q]]
+                                     + [np.zeros(0, dtype=np.int64)])
+        rest_rows = np.setdiff1d(np.arange(ptr.size - 1), staged_rows)
+        _check_cover(ptr, sp["sub"], sp["sublongs"], staged_rows, chunk=sub_chunk, max_rows=4096)
+        assert sp["sublongs"].size == 0
+        _check_cover(ptr, sp["rest"], sp["restlongs"], rest_rows, chunk=chunk)
+        # staged tiles: consecutive sub-tile ranges of one instance, in order
+        nxt = {}
+        for s0, s1, q, _ in sp["tiles"]:
+            assert sp["staged"][q] and s1 > s0
+            assert nxt.get(q, s0) == s0
+            nxt[q] = s1
+            subs = sp["sub"][s0:s1]
+            assert np.all(subs[:, 2] == q)
+            nz = [ptr[b] - ptr[a] for a, b, _, _ in subs]
+            assert sum(nz[:-1]) < group <= sum(nz) + group

@@ -192,6 +192,20 @@ def other_workloads(pdhg, instances, args, R):
                                   mean_first_feasible_round=(round(sum(f for f in first if f) /
                                                                    max(1, sum(f is not None for f in first)), 2)))
         log(f"w5 pump: {out['pump_64x20k']}")
+        # the complete Algorithm 1 loop: eps schedule, early exit per
+        # instance, cycle perturbation (finished instances leave the batch)
+        t = time.perf_counter()
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=args.pump_rounds, seed=0), iter_limit=200_000)
+        el = time.perf_counter() - t
+        found = [o for o in outs if o["found_kind"]]
+        out["scylla_loop_64x20k"] = dict(
+            seconds=round(el, 3), rounds_max=max(o["rounds_run"] for o in outs), found=len(found),
+            found_lp_iterate=sum(o["found_kind"] == 1 for o in outs),
+            found_rounding=sum(o["found_kind"] == 2 for o in outs),
+            mean_found_round=round(sum(o["found_round"] for o in found) / max(1, len(found)), 2),
+            perturbations=sum(o["perturbations"] for o in outs),
+            pdhg_iterations_total=sum(o["iterations"] for o in outs))
+        log(f"w5 complete loop: {out['scylla_loop_64x20k']}")
         b.close()
     return out
 

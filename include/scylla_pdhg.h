@@ -203,12 +203,16 @@ typedef struct {
     int64_t m_total, n_total, nnz_total;
     int32_t row_chunk, col_chunk; /* tile sizes in use (nonzeros per tile) */
     int32_t long_rows, long_cols; /* rows / columns split over several tiles */
-    int32_t row_blocks, col_blocks; /* layout of each pass: 0 normal, 4 or 8
-                                       gather blocks, -1 LDS-staged          */
+    int32_t row_blocks, col_blocks; /* layout of each pass: 0 normal, 2, 4 or
+                                       8 gather blocks, -1 LDS-staged        */
     int32_t row_staged_nnz, col_staged_nnz; /* staged tile size (nonzeros)  */
     int32_t row_staged_variant, col_staged_variant; /* staged kernel variant:
                                        sub-tile 4096 (0, 1) or 8192 (2, 3)
                                        nonzeros; odd = operand prefetch      */
+    int32_t row_sliced, col_sliced; /* instances of an LDS-staged pass whose
+                                       gathered vector is processed in LDS
+                                       slices (partial sums + row combine)   */
+    int32_t row_slices, col_slices; /* slices per such instance              */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 
@@ -333,7 +337,10 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
  * runs and devices.  *_blocks: 0 = normal layout, 2, 4 or 8 = gather-blocked
  * layout with that many blocks (one per four XCDs, per XCD pair or per XCD), -1 = LDS-staged
  * layout (instances whose gathered vector fits in LDS are processed with
- * that vector copied to LDS, in tiles of about 32768 nonzeros); *_ept: 4, 8
+ * that vector copied to LDS, in tiles of about 32768 nonzeros), -2 = the
+ * LDS-staged layout plus LDS slices (instances whose gathered vector is up
+ * to four times too long are processed one equal slice of it at a time,
+ * their per-slice row sums added in slice order); *_ept: 4, 8
  * or 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL
  * otherwise. */
 int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,

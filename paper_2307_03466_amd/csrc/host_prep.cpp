@@ -358,4 +358,126 @@ void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &in
     plan_tiles(ptr, inst_off, rest_chunk, 1024, plan.rest, plan.staged.data());
 }
 
+void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &inst_off,
+                  const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
+                  int32_t max_slices, int32_t sub_chunk, SlicedPlan &plan)
+{
+    const int32_t count = (int32_t)inst_off.size() - 1;
+    const int32_t rows = o.rows;
+    plan = SlicedPlan();
+    plan.sliced.assign(count, 0);
+    // slice count: enough for the longest qualifying instance
+    int64_t longest = 0;
+    std::vector<uint8_t> ok(count, 0);
+    for (int32_t q = 0; q < count; ++q) {
+        const int64_t glen = gofs[q + 1] - gofs[q];
+        if (!candidate[q] || glen <= max_vec || glen > (int64_t)max_slices * max_vec) continue;
+        if (inst_off[q + 1] == inst_off[q]) continue;
+        bool short_rows = true;
+        for (int32_t r = inst_off[q]; r < inst_off[q + 1] && short_rows; ++r)
+            short_rows = o.ptr[r + 1] - o.ptr[r] <= sub_chunk;
+        if (!short_rows) continue;
+        ok[q] = 1;
+        longest = std::max(longest, glen);
+    }
+    if (longest == 0) return;
+    const int32_t S = (int32_t)((longest + max_vec - 1) / max_vec);
+    plan.S = S;
+    for (int32_t q = 0; q < count; ++q) plan.sliced[q] = ok[q];
+    // entries of sliced instances regrouped by slice
+    auto slice_of = [&](int32_t q, int32_t g) {
+        const int64_t glen = gofs[q + 1] - gofs[q], rel = g - gofs[q];
+        int32_t s = (int32_t)((rel * S) / glen);
+        // s is the slice with glen*s/S <= rel < glen*(s+1)/S
+        while (s > 0 && (glen * s) / S > rel) --s;
+        while (s + 1 < S && (glen * (s + 1)) / S <= rel) ++s;
+        return s;
+    };
+    plan.bptr.assign((size_t)S * (rows + 1), 0);
+    for (int32_t q = 0; q < count; ++q) {
+        if (!ok[q]) continue;
+        for (int32_t i = inst_off[q]; i < inst_off[q + 1]; ++i)
+            for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e)
+                plan.bptr[(size_t)slice_of(q, entry_index(o, fmt, e)) * (rows + 1) + i + 1]++;
+    }
+    int64_t base = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        int32_t *p = plan.bptr.data() + (size_t)s * (rows + 1);
+        p[0] = (int32_t)base;
+        for (int32_t i = 0; i < rows; ++i) p[i + 1] += p[i];
+        base = p[rows];
+    }
+    plan.ent.resize(base);
+    if (fmt == FMT_BF16) plan.v16.resize(base);
+    if (fmt == FMT_F32) plan.v32.resize(base);
+    if (fmt == FMT_F64) plan.v64.resize(base);
+    std::vector<int32_t> fill(S);
+    for (int32_t q = 0; q < count; ++q) {
+        if (!ok[q]) continue;
+        for (int32_t i = inst_off[q]; i < inst_off[q + 1]; ++i) {
+            for (int32_t s = 0; s < S; ++s) fill[s] = plan.bptr[(size_t)s * (rows + 1) + i];
+            for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e) {
+                const int32_t pos = fill[slice_of(q, entry_index(o, fmt, e))]++;
+                plan.ent[pos] = o.ent[e];
+                if (fmt == FMT_BF16) plan.v16[pos] = o.v16[e];
+                if (fmt == FMT_F32) plan.v32[pos] = o.v32[e];
+                if (fmt == FMT_F64) plan.v64[pos] = o.v64[e];
+            }
+        }
+        const int64_t glen = gofs[q + 1] - gofs[q];
+        for (int32_t s = 0; s < S; ++s)
+            plan.max_slice = std::max<int32_t>(plan.max_slice, (int32_t)((glen * (s + 1)) / S - (glen * s) / S));
+    }
+}
+
+void tile_sliced(const std::vector<int32_t> &inst_off, int32_t rows, int32_t sub_chunk, int32_t group_nnz,
+                 SlicedPlan &plan)
+{
+    const int32_t count = (int32_t)inst_off.size() - 1;
+    const int32_t S = plan.S;
+    const std::vector<uint8_t> &ok = plan.sliced;
+    plan.tiles.clear();
+    plan.sub.clear();
+    plan.ctiles.clear();
+    if (S == 0) return;
+    // sub-tiles per slice, grouped per (instance, slice)
+    std::vector<uint8_t> skip(count);
+    for (int32_t q = 0; q < count; ++q) skip[q] = ok[q] ? 0 : 1;
+    for (int32_t s = 0; s < S; ++s) {
+        std::vector<int32_t> ptr(plan.bptr.begin() + (size_t)s * (rows + 1),
+                                 plan.bptr.begin() + (size_t)(s + 1) * (rows + 1));
+        TilePlan tp;
+        plan_tiles(ptr, inst_off, sub_chunk, 4 * 1024, tp, skip.data());
+        const int32_t sub0 = (int32_t)(plan.sub.size() / 4);
+        plan.sub.insert(plan.sub.end(), tp.tiles.begin(), tp.tiles.end());
+        for (int32_t q = 0; q < count; ++q) {
+            if (!ok[q]) continue;
+            int32_t t = tp.t_begin[q];
+            while (t < tp.t_end[q]) {
+                const int32_t start = t;
+                int64_t nz = 0;
+                while (t < tp.t_end[q] && nz < group_nnz) {
+                    const int32_t *d = tp.tiles.data() + 4 * t;
+                    nz += ptr[d[1]] - ptr[d[0]];
+                    ++t;
+                }
+                plan.tiles.insert(plan.tiles.end(), {sub0 + start, sub0 + t, q | (s << 24), -2});
+            }
+        }
+    }
+    for (int32_t q = 0; q < count; ++q) {
+        if (!ok[q]) continue;
+        for (int32_t r = inst_off[q]; r < inst_off[q + 1]; r += 256)
+            plan.ctiles.insert(plan.ctiles.end(), {r, std::min(r + 256, inst_off[q + 1]), q, -1});
+    }
+}
+
+void plan_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &inst_off,
+                 const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
+                 int32_t max_slices, int32_t sub_chunk, int32_t group_nnz, SlicedPlan &plan)
+{
+    build_sliced(o, fmt, inst_off, gofs, candidate, max_vec, max_slices, sub_chunk, plan);
+    tile_sliced(inst_off, o.rows, sub_chunk, group_nnz, plan);
+}
+
 }  // namespace scy

@@ -56,6 +56,12 @@ struct PassArgs {
     // LDS-staged pass
     const int32_t *gofs;  // [count + 1] gathered-vector offsets per instance
     const int4 *sub;      // sub-tiles {r0, r1, inst, -1} of the staged tiles
+    // LDS-sliced tiles of the staged pass (tile field w = -2): slice s of
+    // instance q gathers [g0 + glen*s/xS, g0 + glen*(s+1)/xS) from LDS
+    MatView X;            // slice-regrouped entries; X.ptr = [xS * (rows + 1)]
+    const int4 *xsub;     // sub-tiles of the sliced tiles
+    int32_t xS;           // slices per sliced instance
+    V *xP;                // [xS * rows] slice partial sums
 };
 
 // LDS-staged pass: 1024 threads; variant v: nonzeros per thread per
@@ -106,6 +112,10 @@ void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool c
 template <class V>
 void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, size_t shmem, hipStream_t s,
                    bool prepare);
+// Row combine of the LDS-sliced tiles: p.ctiles / p.nctiles / p.B / p.P set
+// to the sliced plan's combine tiles, slice count and partials.
+template <class V>
+void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s);
 void launch_decide(const DecideArgs &d, int count, hipStream_t s);
 void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s);
 void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, hipStream_t s);

@@ -379,29 +379,45 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     V *prod = reinterpret_cast<V *>(lds_raw);  // [CH]
     V *sv = prod + CH;                         // [gathered length]
-    const int4 T = p.tiles[xcd_tile(blockIdx.x, gridDim.x)];  // {sub0, sub1, inst, -}
-    const InstState &S = p.st[T.z];
+    const int4 T = p.tiles[xcd_tile(blockIdx.x, gridDim.x)];  // {sub0, sub1, inst | slice << 24, kind}
+    // kind -1: a whole instance's gathered vector in LDS, fused epilogue;
+    // kind -2: one slice of it, partial sums to xP (added by the combine)
+    const bool part = T.w == -2;
+    const int inst = T.z & 0xffffff, sl = T.z >> 24;
+    const InstState &S = p.st[inst];
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
     const int tid = threadIdx.x;
-    const int g0 = p.gofs[T.z], glen = p.gofs[T.z + 1] - g0;
+    MatView M = p.M;
+    const int4 *sub = p.sub;
+    int g0 = p.gofs[inst], glen = p.gofs[inst + 1] - g0;
+    V *Ps = nullptr;
+    if (part) {
+        M = p.X;
+        M.ptr = p.X.ptr + (size_t)sl * (p.rows + 1);
+        sub = p.xsub;
+        const int lo = (int)(((int64_t)glen * sl) / p.xS), hi = (int)(((int64_t)glen * (sl + 1)) / p.xS);
+        g0 += lo;
+        glen = hi - lo;
+        Ps = p.xP + (size_t)sl * p.rows;
+    }
     // sub-tile state (nonzeros in registers one sub-tile ahead; with PF also
     // this thread's first row bounds and epilogue operands)
-    int4 D = p.sub[T.x];
-    int e0 = p.M.ptr[D.x], e1 = p.M.ptr[D.y];
+    int4 D = sub[T.x];
+    int e0 = M.ptr[D.x], e1 = M.ptr[D.y];
     uint32_t w[EPT];
     V a[EPT];
-    spass_load<V, FMT, NT, EPT>(p.M, e0, e1, w, a);
+    spass_load<V, FMT, NT, EPT>(M, e0, e1, w, a);
     int L = 1, r = 0, rb = 0, re = 0;
     RowOps<V> ops;
     if (PF) {
         L = lanes_per_row<NT>(D.y - D.x);
         r = tid / L;
         if (r < D.y - D.x) {
-            rb = p.M.ptr[D.x + r] - e0;
-            re = p.M.ptr[D.x + r + 1] - e0;
-            if ((tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
+            rb = M.ptr[D.x + r] - e0;
+            re = M.ptr[D.x + r + 1] - e0;
+            if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
         }
     }
     for (int k = tid; k < glen; k += NT) sv[k] = p.gvec[g0 + k];
@@ -412,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
         for (int q = 0; q < EPT; ++q) {
             const int e = e0 + q * NT + tid;
             if (e < e1) {
-                const int idx = decode_entry<FMT, V>(p.M, w[q], a[q]);
+                const int idx = decode_entry<FMT, V>(M, w[q], a[q]);
                 prod[e - e0] = a[q] * sv[idx - g0];
             }
         }
@@ -430,26 +446,26 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             rc = tid / Lc;
             rbc = rec = 0;
             if (rc < nrows) {
-                rbc = p.M.ptr[r0c + rc] - e0c;
-                rec = p.M.ptr[r0c + rc + 1] - e0c;
-                if ((tid & (Lc - 1)) == 0) load_ops<V, DIR>(p, r0c + rc, opc);
+                rbc = M.ptr[r0c + rc] - e0c;
+                rec = M.ptr[r0c + rc + 1] - e0c;
+                if (!part && (tid & (Lc - 1)) == 0) load_ops<V, DIR>(p, r0c + rc, opc);
             }
         }
         __syncthreads();
         // sub-tile t+1's nonzeros (and with PF its row bounds and operands)
         // are in flight during this reduction
         if (t + 1 < T.y) {
-            D = p.sub[t + 1];
-            e0 = p.M.ptr[D.x];
-            e1 = p.M.ptr[D.y];
-            spass_load<V, FMT, NT, EPT>(p.M, e0, e1, w, a);
+            D = sub[t + 1];
+            e0 = M.ptr[D.x];
+            e1 = M.ptr[D.y];
+            spass_load<V, FMT, NT, EPT>(M, e0, e1, w, a);
             if (PF) {
                 L = lanes_per_row<NT>(D.y - D.x);
                 r = tid / L;
                 if (r < D.y - D.x) {
-                    rb = p.M.ptr[D.x + r] - e0;
-                    re = p.M.ptr[D.x + r + 1] - e0;
-                    if ((tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
+                    rb = M.ptr[D.x + r] - e0;
+                    re = M.ptr[D.x + r + 1] - e0;
+                    if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
                 }
             }
         }
@@ -458,12 +474,15 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             V sum = 0;
             for (int q = rbc + lane; q < rec; q += Lc) sum += prod[q];
             if (Lc > 1) sum = wave_sum_width(sum, Lc);
-            if (lane == 0) apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc);
+            if (lane == 0) {
+                if (part) Ps[r0c + rc] = sum;
+                else apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc);
+            }
             const int rn = rc + groups;
             if (rn < nrows) {
-                rbc = p.M.ptr[r0c + rn] - e0c;
-                rec = p.M.ptr[r0c + rn + 1] - e0c;
-                if (lane == 0) load_ops<V, DIR>(p, r0c + rn, opc);
+                rbc = M.ptr[r0c + rn] - e0c;
+                rec = M.ptr[r0c + rn + 1] - e0c;
+                if (!part && lane == 0) load_ops<V, DIR>(p, r0c + rn, opc);
             }
         }
         __syncthreads();
@@ -1260,6 +1279,15 @@ void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, 
     }
 }
 
+template <class V>
+void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s)
+{
+    if (p.nctiles <= 0) return;
+    const dim3 g(p.nctiles), b(256);
+    if (dir == DIR_COL) hipLaunchKernelGGL((k_bcombine<V, DIR_COL>), g, b, 0, s, p, jw);
+    else hipLaunchKernelGGL((k_bcombine<V, DIR_ROW>), g, b, 0, s, p, jw);
+}
+
 void launch_decide(const DecideArgs &d, int count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_decide, dim3(count), dim3(256), 0, s, d);
@@ -1329,6 +1357,7 @@ void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibi
     template void launch_tiny<V>(const TinyArgs<V> &, int, int, int, size_t, hipStream_t, bool);       \
     template void launch_staged<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, bool, hipStream_t);    \
+    template void launch_combine<V>(const PassArgs<V> &, int, int, hipStream_t);                       \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
     template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \
     template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \

@@ -114,6 +114,13 @@ struct OrientRT {
     size_t shmem = 0;
     int32_t staged_nnz = 0;
     int32_t svariant = 0;
+    // LDS-sliced instances of the staged layout (when enabled): the regrouped
+    // entries are kept for the (max_vec, sub-tile) they were built for
+    bool sliced = false;
+    int32_t nstiles = 0;  // staged + sliced tiles
+    SlicedPlan xplan;
+    int32_t x_max_vec = -1, x_sub = -1;
+    DevMem xptr, xent, xval, xsub, xctiles, xP;
     // plan buffers
     DevMem tiles, longs, seg, seg64, part, lpart;
     int32_t ntiles() const { return (int32_t)((blocked ? bplan.tiles.size() : plan.tiles.size()) / 4); }
@@ -214,6 +221,12 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     p.P64 = o.P64.as<double>();
     p.ctiles = o.ctiles.as<int4>();
     p.nctiles = o.blocked ? (int32_t)(o.bplan.ctiles.size() / 4) : 0;
+    if (o.sliced) {
+        p.X = MatView{o.xptr.as<int32_t>(), o.xent.as<uint32_t>(), o.xval.p, o.host.shift, o.host.mask};
+        p.xsub = o.xsub.as<int4>();
+        p.xS = o.xplan.S;
+        p.xP = o.xP.as<V>();
+    }
     if (o.row) {
         p.gvec = check ? h->x.as<V>() : h->xbar.as<V>();
         p.own = h->y.as<V>();
@@ -257,6 +270,7 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
     const size_t vb = (size_t)h->vbytes;
     o.ept = ept;
     o.staged = false;
+    o.sliced = false;
     if (B > 0) {
         if (!o.blocked || o.bh.B != B) {
             build_blocked(o.host, h->fmt, o.gather, B, o.bh);
@@ -301,7 +315,23 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
 // LDS-staged layout: the normal plan (used by the check) with `ept`, plus
 // staged tiles of about `group_nnz` nonzeros for every instance whose
 // gathered vector fits in LDS and normal tiles for the others.
-void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, int32_t variant)
+void release_sliced(OrientRT &o)
+{
+    o.sliced = false;
+    o.xplan = SlicedPlan();
+    o.x_max_vec = o.x_sub = -1;
+    o.xptr.release();
+    o.xent.release();
+    o.xval.release();
+    o.xsub.release();
+    o.xctiles.release();
+    o.xP.release();
+}
+
+// LDS-staged layout; with `slice`, instances too long for LDS (up to 4x)
+// are processed in LDS slices (partial sums + row combine) instead of
+// normal tiles.
+void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, int32_t variant, int32_t slice)
 {
     set_plan(h, o, 0, ept);
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
@@ -309,13 +339,53 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     const int32_t chunk = spass_chunk(variant);
     const int32_t max_vec = h->lds_max / h->vbytes - chunk;
     plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * ept, o.splan);
-    upload(o.stiles, o.splan.tiles, h->stream);
+    std::vector<int32_t> tiles = o.splan.tiles;
+    if (slice) {
+        if (o.x_max_vec != max_vec || o.x_sub != chunk) {
+            std::vector<uint8_t> cand(h->count);
+            for (int32_t q = 0; q < h->count; ++q) cand[q] = o.splan.staged[q] ? 0 : 1;
+            release_sliced(o);
+            build_sliced(o.host, h->fmt, off, gofs, cand, max_vec, 4, chunk, o.xplan);
+            o.x_max_vec = max_vec;
+            o.x_sub = chunk;
+            if (o.xplan.S > 0) {
+                upload(o.xptr, o.xplan.bptr, h->stream);
+                upload(o.xent, o.xplan.ent, h->stream);
+                upload_vals(h, o.xval, o.xplan.v16, o.xplan.v32, o.xplan.v64);
+                o.xP.alloc((size_t)o.xplan.S * std::max(o.rows, 1) * h->vbytes);
+                HIPC(hipStreamSynchronize(h->stream));
+                o.xplan.ent.clear();
+                o.xplan.ent.shrink_to_fit();
+                o.xplan.v16.clear();
+                o.xplan.v16.shrink_to_fit();
+                o.xplan.v32.clear();
+                o.xplan.v32.shrink_to_fit();
+                o.xplan.v64.clear();
+                o.xplan.v64.shrink_to_fit();
+            }
+        }
+        o.sliced = o.xplan.S > 0;
+    } else {
+        o.sliced = false;
+    }
+    if (o.sliced) {
+        tile_sliced(off, o.rows, chunk, group_nnz, o.xplan);
+        upload(o.xsub, o.xplan.sub, h->stream);
+        upload(o.xctiles, o.xplan.ctiles, h->stream);
+        tiles.insert(tiles.end(), o.xplan.tiles.begin(), o.xplan.tiles.end());
+        // normal tiles only for instances neither staged nor sliced
+        std::vector<uint8_t> skip(h->count);
+        for (int32_t q = 0; q < h->count; ++q) skip[q] = (o.splan.staged[q] || o.xplan.sliced[q]) ? 1 : 0;
+        plan_tiles(o.host.ptr, off, 256 * ept, 1024, o.splan.rest, skip.data());
+    }
+    upload(o.stiles, tiles, h->stream);
     upload(o.subtiles, o.splan.sub.tiles, h->stream);
     upload(o.gofs, gofs, h->stream);
     upload(o.rtiles, o.splan.rest.tiles, h->stream);
     upload(o.rlongs, o.splan.rest.longs, h->stream);
     o.rseg.alloc(std::max<size_t>(1, o.splan.rest.nslots) * h->vbytes);
-    o.shmem = (size_t)(chunk + std::max(o.splan.max_vec, 1)) * h->vbytes;
+    const int32_t vec = std::max({o.splan.max_vec, o.sliced ? o.xplan.max_slice : 0, 1});
+    o.shmem = (size_t)(chunk + vec) * h->vbytes;
     PassArgs<float> pf{};
     PassArgs<double> pd{};
     if (h->vbytes == 4)
@@ -323,7 +393,8 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     else
         launch_staged<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, variant, 0, o.shmem, h->stream, true);
     HIPC(hipStreamSynchronize(h->stream));
-    o.staged = !o.splan.tiles.empty();
+    o.nstiles = (int32_t)(tiles.size() / 4);
+    o.staged = o.nstiles > 0;
     o.staged_nnz = group_nnz;
     o.svariant = variant;
 }
@@ -387,27 +458,34 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
     if (o.staged && !check) {
         PassArgs<V> ps = p;
         ps.tiles = o.stiles.as<int4>();
-        ps.ntiles = (int32_t)(o.splan.tiles.size() / 4);
+        ps.ntiles = o.nstiles;
         ps.gofs = o.gofs.as<int32_t>();
         ps.sub = o.subtiles.as<int4>();
+        PassArgs<V> pc = ps;  // row combine of the sliced instances
+        if (o.sliced) {
+            pc.ctiles = o.xctiles.as<int4>();
+            pc.nctiles = (int32_t)(o.xplan.ctiles.size() / 4);
+            pc.B = o.xplan.S;
+            pc.P = o.xP.as<V>();
+        }
         PassArgs<V> pr = p;
         pr.tiles = o.rtiles.as<int4>();
         pr.ntiles = (int32_t)(o.splan.rest.tiles.size() / 4);
         pr.longs = o.rlongs.as<int4>();
         pr.nlong = (int32_t)(o.splan.rest.longs.size() / 4);
         pr.seg = o.rseg.as<V>();
-        if (pr.ntiles == 0 && pr.nlong == 0) {
-            launch_staged<V>(ps, h->fmt, dir, o.svariant, jw, o.shmem, s, false);
-            return;
+        const bool fork = pr.ntiles > 0 || pr.nlong > 0;
+        // the kinds of tiles touch disjoint instances: run the normal tiles
+        // as a second branch (fork on s, side stream, join)
+        if (fork) {
+            HIPC(hipEventRecord(h->fork, s));
+            HIPC(hipStreamWaitEvent(h->side, h->fork, 0));
+            launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
+            HIPC(hipEventRecord(h->join, h->side));
         }
-        // the two kinds of tiles touch disjoint instances: run them as two
-        // branches (fork on s, normal tiles on the side stream, join)
-        HIPC(hipEventRecord(h->fork, s));
-        HIPC(hipStreamWaitEvent(h->side, h->fork, 0));
-        launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
-        HIPC(hipEventRecord(h->join, h->side));
         launch_staged<V>(ps, h->fmt, dir, o.svariant, jw, o.shmem, s, false);
-        HIPC(hipStreamWaitEvent(s, h->join, 0));
+        if (o.sliced) launch_combine<V>(pc, dir, jw, s);
+        if (fork) HIPC(hipStreamWaitEvent(s, h->join, 0));
         return;
     }
     launch_pass<V>(p, h->fmt, dir, o.ept, jw, check, o.blocked, s);
@@ -613,7 +691,7 @@ void tune_store(const std::string &key, const TuneChoice &c)
 void apply_choice(scylla_batch *h, OrientRT &o, const int32_t *v)
 {
     if (v[0] < 0) {
-        set_staged(h, o, v[1], v[2], v[3]);
+        set_staged(h, o, v[1], v[2], v[3] & 3, v[3] >> 2);
         drop_blocked(o);
     } else {
         set_plan(h, o, v[0], v[1]);
@@ -630,7 +708,7 @@ TuneChoice current_choice(scylla_batch *h)
         v[0] = o.staged ? -1 : (o.blocked ? o.bh.B : 0);
         v[1] = o.ept;
         v[2] = o.staged ? o.staged_nnz : 0;
-        v[3] = o.staged ? o.svariant : 0;
+        v[3] = o.staged ? (o.svariant | (o.sliced ? 4 : 0)) : 0;
     }
     return c;
 }
@@ -675,32 +753,39 @@ void autotune(scylla_batch *h)
                 }
             }
         }
-        // LDS-staged candidates when some instance's gathered vector fits
+        // LDS-staged candidates when some instance's gathered vector fits,
+        // whole or in up to four slices
         const std::vector<int32_t> &g = o.row ? h->col_off : h->row_off;
-        bool any = false;
-        for (int32_t q = 0; q < h->count; ++q)
-            any |= (int64_t)(g[q + 1] - g[q] + spass_chunk(0)) * h->vbytes <= h->lds_max;
-        int best_nnz = 0, best_var = 0;
-        if (any && o.rows > 0) {
-            for (int var = 0; var < 4; ++var)
-                for (int nnz : {16384, 32768, 65536}) {
-                    set_staged(h, o, best_ept, nnz, var);
-                    if (!o.staged) continue;
-                    const double ms = timer.time(o, 10);
-                    if (ms < best) {
-                        best = ms;
-                        best_nnz = nnz;
-                        best_var = var;
-                        best_B = -1;
+        bool any = false, any_slice = false;
+        const int64_t vmax = h->lds_max / h->vbytes - spass_chunk(0);
+        for (int32_t q = 0; q < h->count; ++q) {
+            any |= g[q + 1] - g[q] <= vmax;
+            any_slice |= g[q + 1] - g[q] > vmax / 2 && g[q + 1] - g[q] <= 4 * vmax;
+        }
+        int best_nnz = 0, best_var = 0, best_slice = 0;
+        if ((any || any_slice) && o.rows > 0) {
+            for (int slice = 0; slice < (any_slice ? 2 : 1); ++slice)
+                for (int var = 0; var < 4; ++var)
+                    for (int nnz : {16384, 32768, 65536}) {
+                        set_staged(h, o, best_ept, nnz, var, slice);
+                        if (!o.staged || (slice && !o.sliced)) continue;
+                        const double ms = timer.time(o, 10);
+                        if (ms < best) {
+                            best = ms;
+                            best_nnz = nnz;
+                            best_var = var;
+                            best_slice = slice;
+                            best_B = -1;
+                        }
                     }
-                }
         }
         if (best_B < 0) {
-            set_staged(h, o, best_ept, best_nnz, best_var);
+            set_staged(h, o, best_ept, best_nnz, best_var, best_slice);
             drop_blocked(o);
         } else {
             set_plan(h, o, best_B, best_ept);
             if (best_B == 0) drop_blocked(o);
+            release_sliced(o);
         }
     }
     refresh_info(h);
@@ -1551,6 +1636,12 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->col_staged_nnz = h->ocol.staged ? h->ocol.staged_nnz : 0;
         info->row_staged_variant = h->orow.staged ? h->orow.svariant : 0;
         info->col_staged_variant = h->ocol.staged ? h->ocol.svariant : 0;
+        for (int32_t q = 0; q < h->count; ++q) {
+            info->row_sliced += h->orow.sliced && h->orow.xplan.sliced[q];
+            info->col_sliced += h->ocol.sliced && h->ocol.xplan.sliced[q];
+        }
+        info->row_slices = h->orow.sliced ? h->orow.xplan.S : 0;
+        info->col_slices = h->ocol.sliced ? h->ocol.xplan.S : 0;
         return 0;
     });
 }
@@ -1636,21 +1727,22 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
 {
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
-        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == -1; };
+        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == -1 || B == -2; };
         auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -1, 0, 2, 4 or 8 and ept 4, 8 or 16");
+            throw_err(-EINVAL, "blocks must be -2, -1, 0, 2, 4 or 8 and ept 4, 8 or 16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;
             int32_t B = d == 0 ? row_blocks : col_blocks, ept = d == 0 ? row_ept : col_ept;
             if (o.rows == 0 && B > 0) B = 0;
             if (B < 0) {
-                set_staged(h, o, ept, 32768, 0);
+                set_staged(h, o, ept, 32768, 0, B == -2 ? 1 : 0);
                 drop_blocked(o);
             } else {
                 set_plan(h, o, B, ept);
                 if (B == 0) drop_blocked(o);
+                release_sliced(o);
             }
         }
         refresh_info(h);

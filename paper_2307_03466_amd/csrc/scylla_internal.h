@@ -120,6 +120,43 @@ void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &in
                  const std::vector<int32_t> &gofs, int32_t max_vec, int32_t sub_chunk, int32_t group_nnz,
                  int32_t rest_chunk, StagedPlan &plan);
 
+// LDS-sliced part of a staged orientation.  An instance whose gathered
+// vector is longer than max_vec but at most S * max_vec (S = the smallest
+// slice count that fits the longest such instance, at most max_slices), with
+// no row longer than sub_chunk, has its gathered range cut into S equal
+// slices [g0 + glen*s/S, g0 + glen*(s+1)/S); each row's nonzeros are
+// regrouped by slice (bptr[s * (rows + 1) + i] points into ent; rows of
+// other instances are empty).  Sub-tiles of a slice's rows (<= sub_chunk
+// nonzeros, <= 4096 rows) are grouped into tiles of about group_nnz
+// nonzeros {sub0, sub1, inst | s << 24, -2}; the slice partial sums of a row
+// are added in slice order by the combine tiles {r0, r1, inst, -1}.
+struct SlicedPlan {
+    int32_t S = 0;                // slices per sliced instance (0: none)
+    std::vector<uint8_t> sliced;  // per instance
+    std::vector<int32_t> bptr;    // [S * (rows + 1)]
+    std::vector<uint32_t> ent;
+    std::vector<uint16_t> v16;
+    std::vector<float> v32;
+    std::vector<double> v64;
+    std::vector<int32_t> tiles;   // {sub0, sub1, inst | s << 24, -2}
+    std::vector<int32_t> sub;     // {r0, r1, inst, -1}, rows of one slice
+    std::vector<int32_t> ctiles;  // {r0, r1, inst, -1}
+    int32_t max_slice = 0;        // longest slice (elements)
+};
+
+// Instances with `candidate[q]` set are considered for slicing.
+// build_sliced chooses S and the instances and regroups their entries;
+// tile_sliced builds the tiles (cheap; redone per tile size); plan_sliced
+// does both.
+void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &inst_off,
+                  const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
+                  int32_t max_slices, int32_t sub_chunk, SlicedPlan &plan);
+void tile_sliced(const std::vector<int32_t> &inst_off, int32_t rows, int32_t sub_chunk, int32_t group_nnz,
+                 SlicedPlan &plan);
+void plan_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &inst_off,
+                 const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
+                 int32_t max_slices, int32_t sub_chunk, int32_t group_nnz, SlicedPlan &plan);
+
 void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_t B, BlockedHost &out);
 void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t> &inst_off, int32_t chunk,
                   int32_t max_rows, BlockedPlan &plan);

@@ -2,7 +2,8 @@
 // batch of LPs from a binary file, runs build_orientations and plan_tiles
 // (and, when asked, build_blocked / plan_blocked with B blocks and
 // plan_staged), and writes the results back as raw arrays for the Python
-// checks.  Usage: in out chunk max_rows [B [max_vec sub_chunk group_nnz]].
+// checks.  Usage: in out chunk max_rows [B [max_vec sub_chunk group_nnz
+// [max_slices]]].
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -99,6 +100,15 @@ int main(int argc, char **argv)
             std::vector<int32_t> staged(sp.staged.begin(), sp.staged.end());
             wr(o, sp.tiles); wr(o, sp.sub.tiles); wr(o, sp.sub.longs); wr(o, staged);
             wr(o, sp.rest.tiles); wr(o, sp.rest.longs);
+            if (argc > 9) {
+                std::vector<uint8_t> cand(sp.staged.size());
+                for (size_t q = 0; q < cand.size(); ++q) cand[q] = sp.staged[q] ? 0 : 1;
+                scy::SlicedPlan xp;
+                scy::plan_sliced(x, fmt, off, gof, cand, max_vec, atoi(argv[9]), sub_chunk, group_nnz, xp);
+                std::vector<int32_t> hd = {xp.S, xp.max_slice};
+                std::vector<int32_t> sl(xp.sliced.begin(), xp.sliced.end());
+                wr(o, hd); wr(o, sl); wr(o, xp.bptr); wr(o, xp.ent); wr(o, xp.tiles); wr(o, xp.sub); wr(o, xp.ctiles);
+            }
         }
     }
     fclose(o);

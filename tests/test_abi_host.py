@@ -172,10 +172,18 @@ def _run_prep(lps, precision, chunk, max_rows, extra=()):
                           longs=take(np.int32).reshape(-1, 4), ctiles=take(np.int32).reshape(-1, 4))
                      for _ in range(2)])
     if len(extra) >= 4:
-        more.append([dict(tiles=take(np.int32).reshape(-1, 4), sub=take(np.int32).reshape(-1, 4),
-                          sublongs=take(np.int32).reshape(-1, 4), staged=take(np.int32),
-                          rest=take(np.int32).reshape(-1, 4), restlongs=take(np.int32).reshape(-1, 4))
-                     for _ in range(2)])
+        st = []
+        for _ in range(2):
+            d = dict(tiles=take(np.int32).reshape(-1, 4), sub=take(np.int32).reshape(-1, 4),
+                     sublongs=take(np.int32).reshape(-1, 4), staged=take(np.int32),
+                     rest=take(np.int32).reshape(-1, 4), restlongs=take(np.int32).reshape(-1, 4))
+            if len(extra) >= 5:
+                hd = take(np.int32)
+                d["sliced"] = dict(S=int(hd[0]), max_slice=int(hd[1]), inst=take(np.int32), bptr=take(np.int32),
+                                   ent=take(np.uint32), tiles=take(np.int32).reshape(-1, 4),
+                                   sub=take(np.int32).reshape(-1, 4), ctiles=take(np.int32).reshape(-1, 4))
+            st.append(d)
+        more.append(st)
     if more:
         return (hdr, ro, co, orient, plans) + tuple(more)
     return hdr, ro, co, orient, plans
@@ -394,3 +402,67 @@ def test_lds_staged_plan():
             assert np.all(subs[:, 2] == q)
             nz = [ptr[b] - ptr[a] for a, b, _, _ in subs]
             assert sum(nz[:-1]) < group <= sum(nz) + group
+
+
+def test_lds_sliced_plan():
+    """Instances too long for LDS but at most S slices long get their
+    gathered range cut into S equal slices: each row's nonzeros are
+    regrouped by slice without loss or reordering, every slice's sub-tiles
+    cover each row of a sliced instance once, and combine tiles cover those
+    rows once."""
+    lps = I.uneven_batch(count=10, lo=200, hi=9000, seed=5)
+    chunk, max_rows, max_vec, sub_chunk, group, max_slices = 1024, 1024, 6000, 4096, 16384, 4
+    hdr, ro, co, orient, plans, st = _run_prep(lps, 1, chunk, max_rows,
+                                               extra=(0, max_vec, sub_chunk, group, max_slices))
+    seen = 0
+    for which in (0, 1):
+        o, sp = orient[which], st[which]
+        x = sp["sliced"]
+        ptr = o["ptr"]
+        rows = ptr.size - 1
+        off, gof = (ro, co) if which == 0 else (co, ro)
+        glen = np.diff(gof)
+        want = np.array([not sp["staged"][q] and max_vec < glen[q] <= max_slices * max_vec
+                         and np.diff(ptr[off[q]:off[q + 1] + 1]).max(initial=0) <= sub_chunk
+                         and off[q + 1] > off[q] for q in range(len(lps))])
+        np.testing.assert_array_equal(x["inst"].astype(bool), want)
+        if not want.any():
+            assert x["S"] == 0
+            continue
+        seen += 1
+        S = x["S"]
+        assert S == -(-glen[want].max() // max_vec)
+        assert x["max_slice"] <= max_vec
+        idx = _decode_idx(o["ent"], hdr, which, hdr[0])
+        xidx = _decode_idx(x["ent"], hdr, which, hdr[0])
+        bptr = x["bptr"].reshape(S, rows + 1)
+        cover = [np.zeros(rows, dtype=np.int64) for _ in range(S)]
+        for s0, s1, z, kind in x["tiles"]:
+            q, s = z & 0xFFFFFF, z >> 24
+            assert kind == -2 and want[q] and s < S
+            for a, b, qq, _ in x["sub"][s0:s1]:
+                assert qq == q and off[q] <= a <= b <= off[q + 1]
+                assert bptr[s, b] - bptr[s, a] <= sub_chunk and b - a <= 4096
+                cover[s][a:b] += 1
+        for q in np.flatnonzero(want):
+            r = np.arange(off[q], off[q + 1])
+            lo = [gof[q] + (glen[q] * s) // S for s in range(S + 1)]
+            for s in range(S):
+                assert np.all(cover[s][r] == 1)
+            for i in r[:: max(1, r.size // 50)]:
+                parts = []
+                for s in range(S):
+                    seg = xidx[bptr[s, i]:bptr[s, i + 1]]
+                    assert np.all((seg >= lo[s]) & (seg < lo[s + 1]))
+                    parts.append(x["ent"][bptr[s, i]:bptr[s, i + 1]])
+                np.testing.assert_array_equal(np.concatenate(parts), o["ent"][ptr[i]:ptr[i + 1]])
+        other = np.flatnonzero(~want)
+        for q in other:
+            assert np.all(bptr[:, off[q]:off[q + 1] + 1] == bptr[:, off[q]:off[q] + 1])
+        cov = np.zeros(rows, dtype=np.int64)
+        for a, b, q, _ in x["ctiles"]:
+            assert want[q] and off[q] <= a < b <= off[q + 1] and b - a <= 256
+            cov[a:b] += 1
+        rows_w = np.concatenate([np.arange(off[q], off[q + 1]) for q in np.flatnonzero(want)])
+        assert np.all(cov[rows_w] == 1) and cov.sum() == rows_w.size
+    assert seen >= 1

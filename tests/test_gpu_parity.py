@@ -210,6 +210,50 @@ def test_layout_parity(layout, name, prec, bar):
     assert abs(r["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
 
 
+def _sliced_cases():
+    """Instances whose gathered vectors are one to four LDS capacities long
+    (FP32: 36,864 values; FP64: 16,384): a general LP with 50k columns and a
+    batch mixing such instances with ones that fit whole."""
+    big = I.general_lp(m=20_000, n=50_000, seed=31)
+    batch = [I.cover_knapsack(500, seed=1), I.cover_knapsack(24_000, seed=2), I.set_cover(300, 700, seed=3),
+             I.cover_knapsack(9_000, seed=4)]
+    return {"general_50k": [big], "mixed_batch": batch}
+
+
+@pytest.mark.parametrize("case", ["general_50k", "mixed_batch"])
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
+def test_lds_sliced_layout_parity(case, prec, bar):
+    """The LDS-sliced layout (-2): per-slice partial sums added in slice
+    order give the oracle's iterates on every instance."""
+    lps = _sliced_cases()[case]
+    print(f"sliced case {case} prec {prec} sizes {[(l.m, l.n) for l in lps]}", flush=True)
+    with pdhg.Batch(lps, precision=prec) as b:
+        b.set_layout(-2, 8, -2, 8)
+        info = b.info()
+        print("info", info, flush=True)
+        assert info["row_sliced"] + info["col_sliced"] >= 1
+        res = b.solve(tol=1e-300, iter_limit=100, restarts=0, fused_window=0)
+        sols = [b.solution(i) for i in range(len(lps))]
+    for i, lp in enumerate(lps):
+        ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
+        x, y = sols[i]
+        assert res[i]["iterations"] == 100
+        assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= bar, i
+        k = oracle.kkt(lp, x, y)
+        assert abs(res[i]["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
+
+
+def test_lds_sliced_batch_termination_and_restarts():
+    lps = _sliced_cases()["mixed_batch"]
+    with pdhg.Batch(lps, precision=1) as b:
+        b.set_layout(-2, 8, -2, 8)
+        res = b.solve(tol=1e-4, iter_limit=100_000, fused_window=0)
+        for i, lp in enumerate(lps):
+            x, y = b.solution(i)
+            assert res[i]["status"] == pdhg.OPTIMAL
+            assert oracle.kkt(lp, x, y)["rel"] <= 1e-4 * (1 + 1e-6)
+
+
 @pytest.mark.parametrize("layout", [(8, 8, 4, 8), (4, 4, 8, 16), (-1, 8, -1, 8), (-1, 16, 0, 4)])
 def test_blocked_batch_termination(layout):
     """Batches under every layout; the uneven batch mixes instances whose

@@ -213,6 +213,8 @@ typedef struct {
                                        gathered vector is processed in LDS
                                        slices (partial sums + row combine)   */
     int32_t row_slices, col_slices; /* slices per such instance              */
+    int32_t row_half_lds, col_half_lds; /* staged workgroups limited to half
+                                       the LDS (two per CU)                  */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 
@@ -340,7 +342,8 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
  * that vector copied to LDS, in tiles of about 32768 nonzeros), -2 = the
  * LDS-staged layout plus LDS slices (instances whose gathered vector is up
  * to four times too long are processed one equal slice of it at a time,
- * their per-slice row sums added in slice order); *_ept: 4, 8
+ * their per-slice row sums added in slice order), -3 = as -2 with at most
+ * half the LDS per workgroup; *_ept: 4, 8
  * or 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL
  * otherwise. */
 int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,

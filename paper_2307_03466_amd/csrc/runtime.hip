@@ -117,6 +117,7 @@ struct OrientRT {
     // LDS-sliced instances of the staged layout (when enabled): the regrouped
     // entries are kept for the (max_vec, sub-tile) they were built for
     bool sliced = false;
+    bool shalf = false;   // half-LDS budget per workgroup
     int32_t nstiles = 0;  // staged + sliced tiles
     SlicedPlan xplan;
     int32_t x_max_vec = -1, x_sub = -1;
@@ -330,14 +331,17 @@ void release_sliced(OrientRT &o)
 
 // LDS-staged layout; with `slice`, instances too long for LDS (up to 4x)
 // are processed in LDS slices (partial sums + row combine) instead of
-// normal tiles.
-void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, int32_t variant, int32_t slice)
+// normal tiles; with `half`, a workgroup uses at most half the LDS, so two
+// workgroups share a CU and overlap one's vector copy with the other's
+// gathers (smaller vectors qualify, longer ones take more slices).
+void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, int32_t variant, int32_t slice,
+                int32_t half)
 {
     set_plan(h, o, 0, ept);
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
     const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
     const int32_t chunk = spass_chunk(variant);
-    const int32_t max_vec = h->lds_max / h->vbytes - chunk;
+    const int32_t max_vec = (half ? h->lds_max / 2 : h->lds_max) / h->vbytes - chunk;
     plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * ept, o.splan);
     std::vector<int32_t> tiles = o.splan.tiles;
     if (slice) {
@@ -397,6 +401,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     o.staged = o.nstiles > 0;
     o.staged_nnz = group_nnz;
     o.svariant = variant;
+    o.shalf = half != 0;
 }
 
 // Drops the blocked layout's device copy (after the tuner chose normal).
@@ -691,7 +696,7 @@ void tune_store(const std::string &key, const TuneChoice &c)
 void apply_choice(scylla_batch *h, OrientRT &o, const int32_t *v)
 {
     if (v[0] < 0) {
-        set_staged(h, o, v[1], v[2], v[3] & 3, v[3] >> 2);
+        set_staged(h, o, v[1], v[2], v[3] & 3, (v[3] >> 2) & 1, (v[3] >> 3) & 1);
         drop_blocked(o);
     } else {
         set_plan(h, o, v[0], v[1]);
@@ -708,7 +713,7 @@ TuneChoice current_choice(scylla_batch *h)
         v[0] = o.staged ? -1 : (o.blocked ? o.bh.B : 0);
         v[1] = o.ept;
         v[2] = o.staged ? o.staged_nnz : 0;
-        v[3] = o.staged ? (o.svariant | (o.sliced ? 4 : 0)) : 0;
+        v[3] = o.staged ? (o.svariant | (o.sliced ? 4 : 0) | (o.shalf ? 8 : 0)) : 0;
     }
     return c;
 }
@@ -762,25 +767,27 @@ void autotune(scylla_batch *h)
             any |= g[q + 1] - g[q] <= vmax;
             any_slice |= g[q + 1] - g[q] > vmax / 2 && g[q + 1] - g[q] <= 4 * vmax;
         }
-        int best_nnz = 0, best_var = 0, best_slice = 0;
+        int best_nnz = 0, best_var = 0, best_slice = 0, best_half = 0;
         if ((any || any_slice) && o.rows > 0) {
-            for (int slice = 0; slice < (any_slice ? 2 : 1); ++slice)
-                for (int var = 0; var < 4; ++var)
-                    for (int nnz : {16384, 32768, 65536}) {
-                        set_staged(h, o, best_ept, nnz, var, slice);
-                        if (!o.staged || (slice && !o.sliced)) continue;
-                        const double ms = timer.time(o, 10);
-                        if (ms < best) {
-                            best = ms;
-                            best_nnz = nnz;
-                            best_var = var;
-                            best_slice = slice;
-                            best_B = -1;
+            for (int half = 0; half < 2; ++half)
+                for (int slice = 0; slice < (any_slice || half ? 2 : 1); ++slice)
+                    for (int var = 0; var < 4; ++var)
+                        for (int nnz : {16384, 32768, 65536}) {
+                            set_staged(h, o, best_ept, nnz, var, slice, half);
+                            if (!o.staged || (slice && !o.sliced)) continue;
+                            const double ms = timer.time(o, 10);
+                            if (ms < best) {
+                                best = ms;
+                                best_nnz = nnz;
+                                best_var = var;
+                                best_slice = slice;
+                                best_half = half;
+                                best_B = -1;
+                            }
                         }
-                    }
         }
         if (best_B < 0) {
-            set_staged(h, o, best_ept, best_nnz, best_var, best_slice);
+            set_staged(h, o, best_ept, best_nnz, best_var, best_slice, best_half);
             drop_blocked(o);
         } else {
             set_plan(h, o, best_B, best_ept);
@@ -1642,6 +1649,8 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         }
         info->row_slices = h->orow.sliced ? h->orow.xplan.S : 0;
         info->col_slices = h->ocol.sliced ? h->ocol.xplan.S : 0;
+        info->row_half_lds = h->orow.staged && h->orow.shalf;
+        info->col_half_lds = h->ocol.staged && h->ocol.shalf;
         return 0;
     });
 }
@@ -1727,17 +1736,17 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
 {
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
-        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == -1 || B == -2; };
+        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || (B >= -3 && B <= -1); };
         auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -2, -1, 0, 2, 4 or 8 and ept 4, 8 or 16");
+            throw_err(-EINVAL, "blocks must be -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8 or 16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;
             int32_t B = d == 0 ? row_blocks : col_blocks, ept = d == 0 ? row_ept : col_ept;
             if (o.rows == 0 && B > 0) B = 0;
             if (B < 0) {
-                set_staged(h, o, ept, 32768, 0, B == -2 ? 1 : 0);
+                set_staged(h, o, ept, 32768, 0, B <= -2 ? 1 : 0, B == -3 ? 1 : 0);
                 drop_blocked(o);
             } else {
                 set_plan(h, o, B, ept);

@@ -77,7 +77,8 @@ class BatchInfo(ctypes.Structure):
                 ("col_blocks", ctypes.c_int32), ("row_staged_nnz", ctypes.c_int32),
                 ("col_staged_nnz", ctypes.c_int32), ("row_staged_variant", ctypes.c_int32),
                 ("col_staged_variant", ctypes.c_int32), ("row_sliced", ctypes.c_int32),
-                ("col_sliced", ctypes.c_int32), ("row_slices", ctypes.c_int32), ("col_slices", ctypes.c_int32)]
+                ("col_sliced", ctypes.c_int32), ("row_slices", ctypes.c_int32), ("col_slices", ctypes.c_int32),
+                ("row_half_lds", ctypes.c_int32), ("col_half_lds", ctypes.c_int32)]
 
 
 _lib = None
@@ -347,7 +348,8 @@ class Batch:
         return out, [outs[q].as_dict() for q in range(self.count)], xo
 
     def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
-        """Pin the tile plan (-2 LDS-staged + sliced, -1 LDS-staged, 0 normal, 2 / 4 / 8 gather blocks;
+        """Pin the tile plan (-3 as -2 in half the LDS, -2 LDS-staged + sliced, -1 LDS-staged, 0 normal,
+        2 / 4 / 8 gather blocks;
         4 / 8 / 16 nonzeros per thread)."""
         _check(lib().scylla_batch_set_layout(self._h, row_blocks, row_ept, col_blocks, col_ept))
 

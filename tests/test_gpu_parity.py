@@ -220,18 +220,22 @@ def _sliced_cases():
     return {"general_50k": [big], "mixed_batch": batch}
 
 
+@pytest.mark.parametrize("mode", [-2, -3])
 @pytest.mark.parametrize("case", ["general_50k", "mixed_batch"])
 @pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
-def test_lds_sliced_layout_parity(case, prec, bar):
-    """The LDS-sliced layout (-2): per-slice partial sums added in slice
-    order give the oracle's iterates on every instance."""
+def test_lds_sliced_layout_parity(case, prec, bar, mode):
+    """The LDS-sliced layout (-2; -3 with half the LDS per workgroup):
+    per-slice partial sums added in slice order give the oracle's iterates
+    on every instance."""
     lps = _sliced_cases()[case]
-    print(f"sliced case {case} prec {prec} sizes {[(l.m, l.n) for l in lps]}", flush=True)
+    print(f"sliced case {case} prec {prec} mode {mode} sizes {[(l.m, l.n) for l in lps]}", flush=True)
     with pdhg.Batch(lps, precision=prec) as b:
-        b.set_layout(-2, 8, -2, 8)
+        b.set_layout(mode, 8, mode, 8)
         info = b.info()
         print("info", info, flush=True)
         assert info["row_sliced"] + info["col_sliced"] >= 1
+        for d in ("row", "col"):  # orientations that qualify at all are staged
+            assert info[f"{d}_half_lds"] == (mode == -3 and info[f"{d}_blocks"] == -1)
         res = b.solve(tol=1e-300, iter_limit=100, restarts=0, fused_window=0)
         sols = [b.solution(i) for i in range(len(lps))]
     for i, lp in enumerate(lps):

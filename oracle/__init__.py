@@ -57,7 +57,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("iter_limit", ctypes.c_int64),
                 ("check_period", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("ruiz_iters", ctypes.c_int32),
-                ("pock_chambolle", ctypes.c_int32), ("omega0", ctypes.c_double)]
+                ("pock_chambolle", ctypes.c_int32), ("omega0", ctypes.c_double),
+                ("adaptive", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -143,15 +144,18 @@ def kkt(lp, x, y, c=None):
 
 def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 64,
          restarts: bool = True, eta: float = 0.99, x0=None, y0=None, omega0: float = 0.0,
-         c=None, ruiz_iters: int = 10, pock_chambolle: bool = True) -> PDHGResult:
-    """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop)."""
+         c=None, ruiz_iters: int = 10, pock_chambolle: bool = True,
+         adaptive: bool = False) -> PDHGResult:
+    """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop); with
+    `adaptive` the step size follows PDLP's adaptive rule (no retries),
+    starting at `eta`."""
     pin = _Pinned(lp, c)
     x = np.empty(lp.n)
     y = np.empty(lp.m)
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
     prm = _Params(tol, iter_limit, check_period, int(restarts), eta, ruiz_iters,
-                  int(pock_chambolle), omega0)
+                  int(pock_chambolle), omega0, int(adaptive))
     res = _Result()
     rc = _load().orc_pdhg(ctypes.byref(pin.s), ctypes.byref(prm), _p(x0a), _p(y0a), _p(x), _p(y),
                           ctypes.byref(res))

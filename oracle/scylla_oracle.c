@@ -37,6 +37,14 @@
  *     three; checked every R iterations, at 0 and at the iteration limit.
  *   - restart when E <= 0.2 E_r, or E <= 0.8 E_r and E > E_prev, or
  *     k - k_r >= 0.36 k; omega <- exp(0.5 ln(|dy|/|dx|) + 0.5 ln omega).
+ *   - adaptive step size ("update step sizes" in Algorithm 1, after PDLP):
+ *     after the k-th iteration (k counted from 1 over the whole call), with
+ *     dx = x+ - x and dy = y+ - y in the preconditioned metric,
+ *     eta_bar = (omega |D_c^-1 dx|^2 + |D_r^-1 dy|^2 / omega) / (2 |dy^T A dx|)
+ *     and eta <- min((1 - (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta); the
+ *     iterate is always kept (PDLP would retry a step with eta > eta_bar);
+ *     eta_bar = infinity when dy^T A dx = 0, and eta stays when dx = dy = 0.
+ *     eta starts at the eta parameter.
  *
  * Build: gcc -O2 -std=c11 -shared -fPIC -o liboracle.so scylla_oracle.c -lm
  */
@@ -65,6 +73,7 @@ typedef struct {
     int32_t ruiz_iters;  /* Ruiz rounds (10) */
     int32_t pock_chambolle; /* 1: one Pock-Chambolle round after Ruiz */
     double omega0;       /* > 0: use as primal weight, else from norms */
+    int32_t adaptive;    /* 1: adaptive step size (PDLP's rule, no retry) */
 } orc_params;
 
 enum { ORC_OPTIMAL = 1, ORC_ITERATION_LIMIT = 2, ORC_NUMERICAL_ERROR = 4 };
@@ -248,8 +257,11 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     double *axb = malloc(sizeof(double) * (m > 0 ? m : 1));
     double *xr = malloc(sizeof(double) * (n > 0 ? n : 1));
     double *yr = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *yn = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *dxv = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *adx = malloc(sizeof(double) * (m > 0 ? m : 1));
     int rc = 0;
-    if (!dr || !dc || !xn || !xbar || !aty || !axb || !xr || !yr) { rc = -1; goto done; }
+    if (!dr || !dc || !xn || !xbar || !aty || !axb || !xr || !yr || !yn || !dxv || !adx) { rc = -1; goto done; }
     orc_precondition(lp, p->ruiz_iters, p->pock_chambolle, dr, dc);
 
     /* start point: projection of the warm start (or of 0) */
@@ -267,7 +279,8 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
         bs = sqrt(bs);
         omega = (cs > 0.0 && bs > 0.0) ? cs / bs : 1.0;
     }
-    double t = p->eta / omega, s = p->eta * omega;
+    double eta = p->eta;
+    double t = eta / omega, s = eta * omega;
 
     int64_t k = 0, kr = 0;
     double Er = 0.0, Ep = 0.0;
@@ -301,8 +314,8 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
                     double dx = sqrt(dx2), dy = sqrt(dy2);
                     if (dx > 1e-10 && dy > 1e-10) {
                         omega = exp(0.5 * log(dy / dx) + 0.5 * log(omega));
-                        t = p->eta / omega;
-                        s = p->eta * omega;
+                        t = eta / omega;
+                        s = eta * omega;
                     }
                     for (int32_t j = 0; j < n; ++j) xr[j] = x[j];
                     for (int32_t i = 0; i < m; ++i) yr[i] = y[i];
@@ -324,10 +337,39 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
         mul_A(lp, xbar, axb);
         for (int32_t i = 0; i < m; ++i) {
             double dy = lp->b[i] - axb[i];
-            y[i] = proj_dual(y[i] + s * (dr[i] * dr[i]) * dy, lp->sense[i]);
+            yn[i] = proj_dual(y[i] + s * (dr[i] * dr[i]) * dy, lp->sense[i]);
+        }
+        ++k;
+        if (p->adaptive) {
+            /* local step bound from this iteration's move */
+            double nx = 0.0, ny = 0.0, inter = 0.0;
+            for (int32_t j = 0; j < n; ++j) {
+                dxv[j] = xn[j] - x[j];
+                double d = dxv[j] / dc[j];
+                nx += d * d;
+            }
+            mul_A(lp, dxv, adx);
+            for (int32_t i = 0; i < m; ++i) {
+                double d = yn[i] - y[i];
+                inter += d * adx[i];
+                d /= dr[i];
+                ny += d * d;
+            }
+            if (nx + ny > 0.0) {
+                double grow = (1.0 + pow((double)k + 1.0, -0.6)) * eta;
+                if (inter != 0.0) {
+                    double ebar = (omega * nx + ny / omega) / (2.0 * fabs(inter));
+                    double shrink = (1.0 - pow((double)k + 1.0, -0.3)) * ebar;
+                    eta = shrink < grow ? shrink : grow;
+                } else {
+                    eta = grow;
+                }
+                t = eta / omega;
+                s = eta * omega;
+            }
         }
         for (int32_t j = 0; j < n; ++j) x[j] = xn[j];
-        ++k;
+        for (int32_t i = 0; i < m; ++i) y[i] = yn[i];
     }
     res->iterations = k;
     res->restarts = nrestart;
@@ -340,6 +382,7 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     res->omega = omega;
 done:
     free(dr); free(dc); free(xn); free(xbar); free(aty); free(axb); free(xr); free(yr);
+    free(yn); free(dxv); free(adx);
     return rc;
 }
 

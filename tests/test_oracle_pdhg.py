@@ -226,9 +226,10 @@ def test_exact_optimum_is_a_fixed_point(seed):
 
 # ---------------------------------------------- P8 nonexpansiveness
 def test_pdhg_map_nonexpansive_in_its_metric():
-    """Chambolle-Pock: with K = -A~ (coupling -y^T A~ x) the iteration is
-    nonexpansive in ||z||_M^2 = |x|^2/t + |y|^2/s + 2 y^T A~ x (t s ||A~||^2 < 1),
-    evaluated in the preconditioned variables x / d_c, y / d_r."""
+    """Chambolle-Pock: with K = -A~ (coupling -y^T A~ x) the fixed-step
+    iteration is nonexpansive in ||z||_M^2 = |x|^2/t + |y|^2/s + 2 y^T A~ x
+    (t s ||A~||^2 < 1), evaluated in the preconditioned variables x / d_c,
+    y / d_r (constant steps: the adaptive rule changes t, s per iteration)."""
     lp = I.workload(2, scale=0.0003)
     dr, dc = oracle.precondition(lp)
     At = dr[:, None] * dense(lp) * dc[None, :]
@@ -244,8 +245,10 @@ def test_pdhg_map_nonexpansive_in_its_metric():
 
     prev = None
     for k in range(0, 40):
-        ra = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=x0a, y0=y0a, omega0=omega, restarts=False, eta=eta)
-        rb = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=x0b, y0=y0b, omega0=omega, restarts=False, eta=eta)
+        ra = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=x0a, y0=y0a, omega0=omega, restarts=False, eta=eta,
+                         adaptive=False)
+        rb = oracle.pdhg(lp, tol=-1.0, iter_limit=k, x0=x0b, y0=y0b, omega0=omega, restarts=False, eta=eta,
+                         adaptive=False)
         d = mnorm(ra.x - rb.x, ra.y - rb.y)
         if prev is not None:
             assert d <= prev * (1 + 1e-12) + 1e-12
@@ -270,3 +273,22 @@ def test_nan_objective_is_numerical_error():
     c[3] = np.nan
     r = oracle.pdhg(lp, tol=1e-4, iter_limit=1000, c=c)
     assert r.status == oracle.NUMERICAL_ERROR
+
+
+# ------------------------------------------------- adaptive step sizes
+@pytest.mark.parametrize("name", ["general", "skewed", "knapsack", "set_cover", "partition", "mixed"])
+def test_adaptive_steps_reach_the_optimum(name):
+    """The adaptive step rule changes only the path: on every family the
+    solve reaches 1e-7 relative KKT (checked by the independent evaluator)
+    at the HiGHS objective, like the constant-step solve."""
+    rng = np.random.default_rng(11)
+    lp = {"general": lambda: I.workload(2, scale=0.0005), "skewed": lambda: I.workload(3, scale=0.0005),
+          "knapsack": lambda: I.cover_knapsack(400, seed=3), "set_cover": lambda: I.workload(1),
+          "partition": lambda: I.set_partition(30, 90, seed=2),
+          "mixed": lambda: I.tiny_lp(rng, 12, 20, bounded=False)}[name]()
+    ref = highs(lp).fun
+    for adaptive in (True, False):
+        r = oracle.pdhg(lp, tol=1e-7, iter_limit=3_000_000, adaptive=adaptive)
+        assert r.status == oracle.OPTIMAL, adaptive
+        assert kkt_numpy(lp, r.x, r.y)["rel"] <= 1e-7 * 1.0001
+        assert abs(r.pobj - ref) <= 1e-5 * (1 + abs(ref))

@@ -81,13 +81,25 @@ typedef struct {
     int32_t restarts;     /* 1 = restart scheme on (default), 0 = off      */
     int32_t autotune;     /* 1 = time the tile-size candidates once per
                              handle and keep the fastest (default 1)       */
-    double eta;           /* step-size factor in (0, 1) (0.99)             */
+    double eta;           /* step-size factor in (0, 1) (0.99); the first
+                             step's with adaptive steps                   */
     double time_limit_s;  /* <= 0: none (0)                                */
     int32_t fused_window; /* 1 = when every instance fits in LDS, run each
                              check window (check, decision, R iterations)
                              as one kernel, one workgroup per instance
                              (default 1); 0 = always per-pass kernels     */
-    int32_t reserved;
+    int32_t adaptive;     /* 1 = adaptive step size: after the
+                             k-th iteration of the call, eta <- min((1 -
+                             (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta)
+                             with eta_bar = (omega |D_c^-1 dx|^2 +
+                             |D_r^-1 dy|^2 / omega) / (2 |dy^T A dx|) of
+                             that iteration's move (PDLP's rule; a step is
+                             never retried); eta starts at `eta`.  0 =
+                             constant eta (default).  The rule differences
+                             two matrix products (A x_bar - A x), so its
+                             eta is sensitive to rounding: the iterates
+                             follow other roundings of the same method to
+                             about 1e-5, not to the last bits            */
 } scylla_params;
 
 enum {

@@ -62,7 +62,24 @@ struct PassArgs {
     const int4 *xsub;     // sub-tiles of the sliced tiles
     int32_t xS;           // slices per sliced instance
     V *xP;                // [xS * rows] slice partial sums
+    // adaptive step sizes: per epilogue workgroup (ipart) or long row
+    // (iplong) two FP64 partials -- column pass {|D_c^-1 dx|^2, 0}, row pass
+    // {|D_r^-1 dy|^2, dy^T A dx} -- and the row pass's running A x (ax:
+    // A dx = (A x_bar - A x) / 2, A x <- A x + A dx; the row check resets it)
+    int32_t adapt;
+    double *ipart, *iplong;
+    V *ax;
 };
+
+// Step-size update after iteration jw of the window, one workgroup per
+// instance (adaptive steps).
+struct StepArgs {
+    InstState *st;
+    const InstInfo *info;
+    const double *rip, *cip;  // iteration partials of the row / column pass
+    int32_t jw;
+};
+void launch_step(const StepArgs &a, int count, hipStream_t s);
 
 // LDS-staged pass: 1024 threads; variant v: nonzeros per thread per
 // sub-tile 4 (v = 0, 1) or 8 (v = 2, 3); odd v prefetch the next
@@ -80,6 +97,7 @@ struct TinyArgs {
     const double *c64, *l64, *u64, *b64, *dr64, *dc64;
     InstState *st;
     const InstInfo *info;
+    int32_t adapt;  // adaptive step sizes
 };
 
 // LDS bytes k_tiny needs for an instance (must match its carving).
@@ -87,7 +105,7 @@ inline size_t tiny_lds_bytes(int m, int n, int rnnz, int cnnz, int vb)
 {
     auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return al(4 * (size_t)(m + 1)) + al(4 * (size_t)(n + 1)) + al(4 * (size_t)rnnz) + al(4 * (size_t)cnnz) +
-           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 7 * al((size_t)vb * n) + 4 * al((size_t)vb * m) +
+           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 7 * al((size_t)vb * n) + 5 * al((size_t)vb * m) +
            al((size_t)m);
 }
 

@@ -62,6 +62,32 @@ __device__ __forceinline__ V block_sum(V v, V *red)
     return s;
 }
 
+// Fixed-order block sum of two values (results valid in thread 0); red
+// holds 2 * NT / 64 doubles.  Every thread of the block must call it.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
+{
+    a = wave_sum_width(a, 64);
+    b = wave_sum_width(b, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) {
+            sa += red[2 * q];
+            sb += red[2 * q + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t h)
 {
     return __uint_as_float(((uint32_t)h) << 16);
@@ -134,38 +160,11 @@ __device__ __forceinline__ void stage_products(const MatView &M, const GV *__res
 }
 
 // ------------------------------------------------------------ epilogues
-// Dual step of Algorithm 1 for row i given (A x_bar)_i.
-template <class V>
-__device__ __forceinline__ void dual_update(const PassArgs<V> &p, int i, V axb, V s, bool copy_ref)
-{
-    const V yi = p.own[i];
-    V v = yi + s * p.diag2[i] * (p.rhs[i] - axb);
-    const uint8_t sn = p.sense[i];
-    if (sn == 'G') v = v > (V)0 ? v : (V)0;
-    else if (sn == 'L') v = v < (V)0 ? v : (V)0;
-    if (copy_ref) p.own_ref[i] = yi;
-    p.own[i] = v;
-}
-
-// Primal step of Algorithm 1 for column j given (A^T y)_j.
-template <class V>
-__device__ __forceinline__ void primal_update(const PassArgs<V> &p, int j, V aty, V t, bool copy_ref)
-{
-    const V xj = p.own[j];
-    V xn = xj + t * p.diag2[j] * (aty - p.rhs[j]);
-    const V lo = p.lo[j], hi = p.hi[j];
-    xn = xn < lo ? lo : xn;
-    xn = xn > hi ? hi : xn;
-    if (copy_ref) p.own_ref[j] = xj;
-    p.bar[j] = (V)2 * xn - xj;
-    p.own[j] = xn;
-}
-
 // Operands of one row's epilogue, loaded before the LDS barrier so their
 // latency overlaps the matrix stream.
 template <class V>
 struct RowOps {
-    V own, rhs, diag2, lo, hi;
+    V own, rhs, diag2, lo, hi, ax;
     uint8_t sense;
 };
 
@@ -180,12 +179,16 @@ __device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> 
         o.hi = p.hi[i];
     } else {
         o.sense = p.sense[i];
+        if (p.adapt) o.ax = p.ax[i];
     }
 }
 
+// The fused epilogue: primal step (column pass) or dual step (row pass) of
+// Algorithm 1 for row i given its sum; with adaptive steps it also adds
+// this row's terms of the step-size estimate to ip.
 template <class V, int DIR>
 __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V step, bool copy_ref,
-                                          const RowOps<V> &o)
+                                          const RowOps<V> &o, double (&ip)[2])
 {
     if (DIR == DIR_COL) {
         V xn = o.own + step * o.diag2 * (sum - o.rhs);
@@ -194,12 +197,24 @@ __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V 
         if (copy_ref) p.own_ref[i] = o.own;
         p.bar[i] = (V)2 * xn - o.own;
         p.own[i] = xn;
+        if (p.adapt) {
+            const double d = (double)xn - (double)o.own;
+            ip[0] += d * d / (double)o.diag2;
+        }
     } else {
         V v = o.own + step * o.diag2 * (o.rhs - sum);
         if (o.sense == 'G') v = v > (V)0 ? v : (V)0;
         else if (o.sense == 'L') v = v < (V)0 ? v : (V)0;
         if (copy_ref) p.own_ref[i] = o.own;
         p.own[i] = v;
+        if (p.adapt) {
+            // sum = (A x_bar)_i, x_bar = 2 x+ - x, so (A dx)_i = (sum - (A x)_i) / 2
+            const double dy = (double)v - (double)o.own;
+            const double dax = 0.5 * ((double)sum - (double)o.ax);
+            ip[0] += dy * dy / (double)o.diag2;
+            ip[1] += dy * dax;
+            p.ax[i] = (V)((double)o.ax + dax);
+        }
     }
 }
 
@@ -220,6 +235,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
     constexpr int CH = NT * EPT;
     __shared__ V prod[CH];
     __shared__ V red[NT / 64];
+    __shared__ double red2[2 * NT / 64];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int4 T = p.tiles[t];
     const InstState &S = p.st[T.z];
@@ -233,9 +249,13 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
         V s = 0;
         for (int q = tid; q < T.y - T.x; q += NT) s += prod[q];
         s = block_sum<V, NT>(s, red);
-        if (tid == 0) p.seg[T.w] = s;
+        if (tid == 0) {
+            p.seg[T.w] = s;
+            if (p.adapt) p.ipart[2 * t] = p.ipart[2 * t + 1] = 0.0;
+        }
         return;
     }
+    double ip[2] = {0.0, 0.0};
     const int r0 = T.x, nrows = T.y - T.x;
     const int e0 = p.M.ptr[r0], e1 = p.M.ptr[T.y];
     const int L = lanes_per_row<NT>(nrows);
@@ -255,12 +275,19 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
         V s = 0;
         for (int q = rb + lane; q < re; q += L) s += prod[q];
         if (L > 1) s = wave_sum_width(s, L);
-        if (lane == 0) apply_ops<V, DIR>(p, r0 + r, s, step, copy_ref, ops);
+        if (lane == 0) apply_ops<V, DIR>(p, r0 + r, s, step, copy_ref, ops, ip);
         const int rn = r + groups;
         if (rn < nrows) {
             rb = p.M.ptr[r0 + rn] - e0;
             re = p.M.ptr[r0 + rn + 1] - e0;
             if (lane == 0) load_ops<V, DIR>(p, r0 + rn, ops);
+        }
+    }
+    if (p.adapt) {
+        block_sum2<NT>(ip[0], ip[1], red2);
+        if (tid == 0) {
+            p.ipart[2 * t] = ip[0];
+            p.ipart[2 * t + 1] = ip[1];
         }
     }
 }
@@ -341,17 +368,27 @@ __global__ __launch_bounds__(256) void k_bseg(const PassArgs<V> p, const int jw,
 template <class V, int DIR>
 __global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int jw)
 {
+    __shared__ double red2[8];
     const int4 T = p.ctiles[blockIdx.x];
     const InstState &S = p.st[T.z];
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const int i = T.x + threadIdx.x;
-    if (i >= T.y) return;
-    const bool copy_ref = (jw == 0) && (S.restart_now != 0);
-    RowOps<V> ops;
-    load_ops<V, DIR>(p, i, ops);
-    V s = 0;
-    for (int b = 0; b < p.B; ++b) s += p.P[(size_t)b * p.rows + i];
-    apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops);
+    double ip[2] = {0.0, 0.0};
+    if (i < T.y) {
+        const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+        RowOps<V> ops;
+        load_ops<V, DIR>(p, i, ops);
+        V s = 0;
+        for (int b = 0; b < p.B; ++b) s += p.P[(size_t)b * p.rows + i];
+        apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
+    }
+    if (p.adapt) {
+        block_sum2<256>(ip[0], ip[1], red2);
+        if (threadIdx.x == 0) {
+            p.ipart[2 * blockIdx.x] = ip[0];
+            p.ipart[2 * blockIdx.x + 1] = ip[1];
+        }
+    }
 }
 
 // ------------------------------------------- LDS-staged pass (small instances)
@@ -402,6 +439,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
         glen = hi - lo;
         Ps = p.xP + (size_t)sl * p.rows;
     }
+    double ip[2] = {0.0, 0.0};
     // sub-tile state (nonzeros in registers one sub-tile ahead; with PF also
     // this thread's first row bounds and epilogue operands)
     int4 D = sub[T.x];
@@ -476,7 +514,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             if (Lc > 1) sum = wave_sum_width(sum, Lc);
             if (lane == 0) {
                 if (part) Ps[r0c + rc] = sum;
-                else apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc);
+                else apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc, ip);
             }
             const int rn = rc + groups;
             if (rn < nrows) {
@@ -486,6 +524,15 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             }
         }
         __syncthreads();
+    }
+    if (p.adapt && !part) {
+        // the product buffer is free after the last barrier
+        block_sum2<NT>(ip[0], ip[1], reinterpret_cast<double *>(lds_raw));
+        if (tid == 0) {
+            const int t = xcd_tile(blockIdx.x, gridDim.x);
+            p.ipart[2 * t] = ip[0];
+            p.ipart[2 * t + 1] = ip[1];
+        }
     }
 }
 
@@ -501,8 +548,14 @@ __global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int 
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     V s = 0;
     for (int k = 0; k < L.z; ++k) s += p.seg[L.y + k];
-    if (DIR == DIR_COL) primal_update(p, L.x, s, (V)S.t, copy_ref);
-    else dual_update(p, L.x, s, (V)S.s, copy_ref);
+    RowOps<V> ops;
+    load_ops<V, DIR>(p, L.x, ops);
+    double ip[2] = {0.0, 0.0};
+    apply_ops<V, DIR>(p, L.x, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
+    if (p.adapt) {
+        p.iplong[2 * q] = ip[0];
+        p.iplong[2 * q + 1] = ip[1];
+    }
 }
 
 // ------------------------------------------------------------ KKT check
@@ -592,8 +645,12 @@ __global__ __launch_bounds__(NT) void k_check(const PassArgs<V> p)
         for (int k = rb + lane; k < re; k += L) s += prod[k];
         if (L > 1) s = wave_sum_width(s, L);
         if (lane == 0) {
-            if (DIR == DIR_COL) col_terms(p, r0 + r, s, q);
-            else row_terms(p, r0 + r, s, q);
+            if (DIR == DIR_COL) {
+                col_terms(p, r0 + r, s, q);
+            } else {
+                row_terms(p, r0 + r, s, q);
+                if (p.adapt) p.ax[r0 + r] = (V)s;  // A x of the current point
+            }
         }
     }
 #pragma unroll
@@ -615,8 +672,12 @@ __global__ __launch_bounds__(256) void k_combine_check(const PassArgs<V> p)
     double s = 0;
     for (int k = 0; k < L.z; ++k) s += p.seg64[L.y + k];
     double q[4] = {0.0, 0.0, 0.0, 0.0};
-    if (DIR == DIR_COL) col_terms(p, L.x, s, q);
-    else row_terms(p, L.x, s, q);
+    if (DIR == DIR_COL) {
+        col_terms(p, L.x, s, q);
+    } else {
+        row_terms(p, L.x, s, q);
+        if (p.adapt) p.ax[L.x] = (V)s;
+    }
     for (int k = 0; k < 4; ++k) p.lpart[4 * qi + k] = q[k];
 }
 
@@ -635,8 +696,12 @@ __global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
     if (i < T.y) {
         double s = 0;
         for (int b = 0; b < p.B; ++b) s += p.P64[(size_t)b * p.rows + i];
-        if (DIR == DIR_COL) col_terms(p, i, s, q);
-        else row_terms(p, i, s, q);
+        if (DIR == DIR_COL) {
+            col_terms(p, i, s, q);
+        } else {
+            row_terms(p, i, s, q);
+            if (p.adapt) p.ax[i] = (V)s;
+        }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -727,6 +792,50 @@ __global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
     decide_state(S, tot, d.R);
 }
 
+// ------------------------------------------------------- adaptive steps
+// Step-size rule after the k-th iteration (k counted from 1 over the call),
+// in FP64 (Algorithm 1's step-size update, read as PDLP's adaptive rule
+// without retries): eta_bar = (omega |dx~|^2 + |dy~|^2 / omega) / (2 |dy^T A dx|),
+// eta <- min((1 - (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta); eta_bar is
+// infinite when the interaction is 0, and eta is kept when the move is 0.
+__device__ __forceinline__ void adapt_step(InstState &S, double nx, double ny, double inter, int64_t k)
+{
+    if (!(nx + ny > 0.0)) return;
+    const double grow = (1.0 + pow((double)k + 1.0, -0.6)) * S.eta;
+    double eta = grow;
+    if (inter != 0.0) {
+        const double ebar = (S.omega * nx + ny / S.omega) / (2.0 * fabs(inter));
+        const double shrink = (1.0 - pow((double)k + 1.0, -0.3)) * ebar;
+        eta = shrink < grow ? shrink : grow;
+    }
+    S.eta = eta;
+    S.t = eta / S.omega;
+    S.s = eta * S.omega;
+}
+
+// One workgroup per instance: fixed-order FP64 sums of the iteration
+// partials of both passes (slot ranges in InstInfo::ir), then the rule.
+__global__ __launch_bounds__(256) void k_step(const StepArgs a)
+{
+    __shared__ double red2[8];
+    const int inst = blockIdx.x;
+    InstState &S = a.st[inst];
+    if (S.status != ST_RUN || a.jw >= S.nrun) return;
+    const InstInfo I = a.info[inst];
+    double nx = 0.0, ny = 0.0, inter = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        for (int q = I.ir[1][r][0] + threadIdx.x; q < I.ir[1][r][1]; q += 256) nx += a.cip[2 * q];
+        for (int q = I.ir[0][r][0] + threadIdx.x; q < I.ir[0][r][1]; q += 256) {
+            ny += a.rip[2 * q];
+            inter += a.rip[2 * q + 1];
+        }
+    }
+    double zero = 0.0;
+    block_sum2<256>(nx, zero, red2);
+    block_sum2<256>(ny, inter, red2);
+    if (threadIdx.x == 0) adapt_step(S, nx, ny, inter, S.k + a.jw + 1);
+}
+
 // --------------------------------------------- fused window (tiny instances)
 // One workgroup per instance runs a whole check window -- FP64 KKT check,
 // decision, then up to R iterations -- with the instance's matrix (both
@@ -737,7 +846,7 @@ __global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
 template <class V>
 struct TinyLds {
     int *rptr, *cptr, *rcol, *ccol;
-    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *y, *yr, *b, *dr2;
+    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *y, *yr, *b, *dr2, *ax;
     uint8_t *sense;
 };
 
@@ -768,6 +877,7 @@ __device__ __forceinline__ TinyLds<V> tiny_carve(unsigned char *base, int m, int
     t.yr = (V *)take(sizeof(V) * (size_t)m);
     t.b = (V *)take(sizeof(V) * (size_t)m);
     t.dr2 = (V *)take(sizeof(V) * (size_t)m);
+    t.ax = (V *)take(sizeof(V) * (size_t)m);
     t.sense = (uint8_t *)take((size_t)m);
     return t;
 }
@@ -778,6 +888,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
     constexpr int NT = 1024;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double red[NT / 64];
+    __shared__ double red2[2 * NT / 64];
     __shared__ int sh_nrun, sh_restart;
     __shared__ V sh_t, sh_s;
     const int inst = blockIdx.x, tid = threadIdx.x;
@@ -837,6 +948,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         else r = bb - ax;
         const double yy = (double)L.y[i];
         const double dy = (yy - (double)L.yr[i]) / a.dr64[I.row0 + i];
+        L.ax[i] = (V)ax;  // A x of the current point (adaptive steps)
         acc[0] += r * r;
         acc[1] += bb * yy;
         acc[2] += dy * dy;
@@ -877,13 +989,14 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
     __syncthreads();
     const int nrun = sh_nrun;
     if (nrun == 0) return;
-    const V t = sh_t, sd = sh_s;
+    V t = sh_t, sd = sh_s;
     // lane groups: a power of two of lanes per column / row, as many as fit
     const int Lc = lanes_per_row<NT>(n), Lr = lanes_per_row<NT>(m);
     const int lc = tid & (Lc - 1), lr = tid & (Lr - 1);
     // ---- nrun PDHG iterations (Algorithm 1): column pass, barrier, row pass
     for (int it = 0; it < nrun; ++it) {
         const bool copy_ref = it == 0 && sh_restart != 0;
+        double nx = 0.0, ny = 0.0, inter = 0.0;
         for (int j = tid / Lc; j < n; j += NT / Lc) {
             V aty = 0;
             for (int e = L.cptr[j] + lc; e < L.cptr[j + 1]; e += Lc) aty += L.cval[e] * L.y[L.ccol[e]];
@@ -896,6 +1009,10 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
                 if (copy_ref) L.xr[j] = xj;
                 L.xb[j] = (V)2 * xn - xj;
                 L.x[j] = xn;
+                if (a.adapt) {
+                    const double d = (double)xn - (double)xj;
+                    nx += d * d / (double)L.dc2[j];
+                }
             }
         }
         __syncthreads();
@@ -911,9 +1028,29 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
                 else if (sn == 'L') v = v < (V)0 ? v : (V)0;
                 if (copy_ref) L.yr[i] = yi;
                 L.y[i] = v;
+                if (a.adapt) {
+                    const double dy = (double)v - (double)yi;
+                    const double dax = 0.5 * ((double)axb - (double)L.ax[i]);
+                    ny += dy * dy / (double)L.dr2[i];
+                    inter += dy * dax;
+                    L.ax[i] = (V)((double)L.ax[i] + dax);
+                }
             }
         }
         __syncthreads();
+        if (a.adapt) {
+            double zero = 0.0;
+            block_sum2<NT>(nx, zero, red2);
+            block_sum2<NT>(ny, inter, red2);
+            if (tid == 0) {
+                adapt_step(S, nx, ny, inter, S.k + it + 1);
+                sh_t = (V)S.t;
+                sh_s = (V)S.s;
+            }
+            __syncthreads();
+            t = sh_t;
+            sd = sh_s;
+        }
     }
     // ---- write the iterates back
     for (int j = tid; j < n; j += NT) {
@@ -1286,6 +1423,11 @@ void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s)
     const dim3 g(p.nctiles), b(256);
     if (dir == DIR_COL) hipLaunchKernelGGL((k_bcombine<V, DIR_COL>), g, b, 0, s, p, jw);
     else hipLaunchKernelGGL((k_bcombine<V, DIR_ROW>), g, b, 0, s, p, jw);
+}
+
+void launch_step(const StepArgs &a, int count, hipStream_t s)
+{
+    if (count > 0) hipLaunchKernelGGL(k_step, dim3(count), dim3(256), 0, s, a);
 }
 
 void launch_decide(const DecideArgs &d, int count, hipStream_t s)

@@ -124,6 +124,10 @@ struct OrientRT {
     DevMem xptr, xent, xval, xsub, xctiles, xP;
     // plan buffers
     DevMem tiles, longs, seg, seg64, part, lpart;
+    // adaptive-step partials: 2 doubles per epilogue slot; slot spaces of the
+    // launches of the active layout start at these offsets
+    DevMem ipart;
+    int32_t ipo_long = 0, ipo_comb = 0, ipo_rest = 0, ipo_rlong = 0, ip_slots = 0;
     int32_t ntiles() const { return (int32_t)((blocked ? bplan.tiles.size() : plan.tiles.size()) / 4); }
     int32_t nlong() const { return (int32_t)((blocked ? bplan.longs.size() : plan.longs.size()) / 4); }
 };
@@ -146,6 +150,8 @@ struct scylla_batch {
     // FP64 data
     DevMem c64, corig64, l64, u64, b64, dr64, dc64;
     DevMem st, info;
+    DevMem ax;              // running A x of the row pass (adaptive steps)
+    bool adaptive = false;  // adaptive step sizes in the current graph
     DevMem bits_tmp, ibits_tmp;
     // graph
     hipGraphExec_t gexec = nullptr;
@@ -155,6 +161,7 @@ struct scylla_batch {
     bool tiny_ok = false;     // every instance fits the fused window
     size_t tiny_shmem = 0;
     bool graph_tiny = false;
+    bool graph_adapt = false;
     // host copy of the problem (for the pump's rounding on the host)
     std::vector<double> hval, hb, hl, hu, hc;
     std::vector<char> hsense;
@@ -222,6 +229,10 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     p.P64 = o.P64.as<double>();
     p.ctiles = o.ctiles.as<int4>();
     p.nctiles = o.blocked ? (int32_t)(o.bplan.ctiles.size() / 4) : 0;
+    p.adapt = h->adaptive ? 1 : 0;
+    p.ax = h->ax.as<V>();
+    p.ipart = o.ipart.as<double>();
+    p.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_long;
     if (o.sliced) {
         p.X = MatView{o.xptr.as<int32_t>(), o.xent.as<uint32_t>(), o.xval.p, o.host.shift, o.host.mask};
         p.xsub = o.xsub.as<int4>();
@@ -260,6 +271,28 @@ void upload_vals(scylla_batch *h, DevMem &d, const std::vector<uint16_t> &v16, c
     if (h->fmt == FMT_BF16) upload(d, v16, h->stream);
     else if (h->fmt == FMT_F32) upload(d, v32, h->stream);
     else if (h->fmt == FMT_F64) upload(d, v64, h->stream);
+}
+
+// Slot spaces of the adaptive-step partials for the active layout: normal
+// tiles then long rows; blocked combine tiles; staged (and sliced) tiles,
+// sliced combine tiles, rest tiles, rest long rows.
+void ip_layout(OrientRT &o)
+{
+    auto n4 = [](const std::vector<int32_t> &v) { return (int32_t)(v.size() / 4); };
+    o.ipo_long = o.ipo_comb = o.ipo_rest = o.ipo_rlong = 0;
+    if (o.staged) {
+        o.ipo_comb = o.nstiles;
+        o.ipo_rest = o.ipo_comb + (o.sliced ? n4(o.xplan.ctiles) : 0);
+        o.ipo_rlong = o.ipo_rest + n4(o.splan.rest.tiles);
+        o.ip_slots = o.ipo_rlong + n4(o.splan.rest.longs);
+    } else if (o.blocked) {
+        o.ip_slots = n4(o.bplan.ctiles);
+    } else {
+        o.ipo_long = n4(o.plan.tiles);
+        o.ip_slots = o.ipo_long + n4(o.plan.longs);
+    }
+    const size_t bytes = 16 * (size_t)std::max(o.ip_slots, 1);
+    if (o.ipart.bytes < bytes) o.ipart.alloc(bytes);
 }
 
 // Plans the orientation with `ept` nonzeros per thread, normal layout
@@ -310,6 +343,7 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
         o.part.alloc(std::max<size_t>(1, o.plan.tiles.size() / 4) * 4 * 8);
         o.lpart.alloc(std::max<size_t>(1, o.plan.longs.size() / 4) * 4 * 8);
     }
+    ip_layout(o);
     HIPC(hipStreamSynchronize(h->stream));
 }
 
@@ -402,6 +436,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     o.staged_nnz = group_nnz;
     o.svariant = variant;
     o.shalf = half != 0;
+    ip_layout(o);
 }
 
 // Drops the blocked layout's device copy (after the tuner chose normal).
@@ -443,6 +478,41 @@ void refresh_info(scylla_batch *h)
             } else {
                 I.ct0 = t0; I.ct1 = t1; I.lc0 = l0; I.lc1 = l1;
             }
+            // slots of this instance's epilogues in the iteration partials
+            int32_t (*ir)[2] = I.ir[d];
+            for (int r = 0; r < 3; ++r) ir[r][0] = ir[r][1] = 0;
+            if (o.staged) {
+                if (o.splan.staged[q]) {
+                    int32_t a = -1, b = -1;
+                    for (size_t t = 0; t < o.splan.tiles.size() / 4; ++t)
+                        if (o.splan.tiles[4 * t + 2] == q) {
+                            if (a < 0) a = (int32_t)t;
+                            b = (int32_t)t + 1;
+                        }
+                    if (a >= 0) { ir[0][0] = a; ir[0][1] = b; }
+                } else if (o.sliced && o.xplan.sliced[q]) {
+                    int32_t a = -1, b = -1;
+                    for (size_t t = 0; t < o.xplan.ctiles.size() / 4; ++t)
+                        if (o.xplan.ctiles[4 * t + 2] == q) {
+                            if (a < 0) a = (int32_t)t;
+                            b = (int32_t)t + 1;
+                        }
+                    if (a >= 0) { ir[0][0] = o.ipo_comb + a; ir[0][1] = o.ipo_comb + b; }
+                } else {
+                    ir[0][0] = o.ipo_rest + o.splan.rest.t_begin[q];
+                    ir[0][1] = o.ipo_rest + o.splan.rest.t_end[q];
+                    ir[1][0] = o.ipo_rlong + o.splan.rest.l_begin[q];
+                    ir[1][1] = o.ipo_rlong + o.splan.rest.l_end[q];
+                }
+            } else if (o.blocked) {
+                ir[0][0] = o.bplan.ct_begin[q];
+                ir[0][1] = o.bplan.ct_end[q];
+            } else {
+                ir[0][0] = o.plan.t_begin[q];
+                ir[0][1] = o.plan.t_end[q];
+                ir[1][0] = o.ipo_long + o.plan.l_begin[q];
+                ir[1][1] = o.ipo_long + o.plan.l_end[q];
+            }
         }
     }
     upload(h->info, h->hinfo, h->stream);
@@ -472,6 +542,7 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
             pc.nctiles = (int32_t)(o.xplan.ctiles.size() / 4);
             pc.B = o.xplan.S;
             pc.P = o.xP.as<V>();
+            pc.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_comb;
         }
         PassArgs<V> pr = p;
         pr.tiles = o.rtiles.as<int4>();
@@ -479,6 +550,8 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
         pr.longs = o.rlongs.as<int4>();
         pr.nlong = (int32_t)(o.splan.rest.longs.size() / 4);
         pr.seg = o.rseg.as<V>();
+        pr.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_rest;
+        pr.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_rlong;
         const bool fork = pr.ntiles > 0 || pr.nlong > 0;
         // the kinds of tiles touch disjoint instances: run the normal tiles
         // as a second branch (fork on s, side stream, join)
@@ -522,6 +595,7 @@ TinyArgs<V> tiny_args(scylla_batch *h)
     a.dc64 = h->dc64.as<double>();
     a.st = h->st.as<InstState>();
     a.info = h->info.as<InstInfo>();
+    a.adapt = h->adaptive ? 1 : 0;
     return a;
 }
 
@@ -542,12 +616,17 @@ void enqueue_window(scylla_batch *h, int32_t R, bool tiny, hipStream_t s)
     for (int32_t j = 0; j < R; ++j) {
         launch_orient<V>(h, h->ocol, ci, j, false, s);
         launch_orient<V>(h, h->orow, ri, j, false, s);
+        if (h->adaptive) {
+            const StepArgs a{h->st.as<InstState>(), h->info.as<InstInfo>(), h->orow.ipart.as<double>(),
+                             h->ocol.ipart.as<double>(), j};
+            launch_step(a, h->count, s);
+        }
     }
 }
 
 void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
 {
-    if (h->gexec && h->graph_R == R && h->graph_tiny == tiny) return;
+    if (h->gexec && h->graph_R == R && h->graph_tiny == tiny && h->graph_adapt == h->adaptive) return;
     invalidate_graph(h);
     hipGraph_t g = nullptr;
     HIPC(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
@@ -559,6 +638,7 @@ void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
     HIPC(e);
     h->graph_R = R;
     h->graph_tiny = tiny;
+    h->graph_adapt = h->adaptive;
 }
 
 // Scratch outputs and an always-running state so a pass can be launched on
@@ -844,9 +924,9 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     upload(h->sense, sn, s);
     const size_t vb = sizeof(V);
     for (DevMem *d : {&h->x, &h->xbar, &h->xr, &h->cv, &h->lv, &h->uv, &h->dc2}) d->alloc((size_t)N * vb);
-    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2}) d->alloc((size_t)M * vb);
+    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2, &h->ax}) d->alloc((size_t)M * vb);
     for (DevMem *d : {&h->x, &h->xbar, &h->xr}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
-    for (DevMem *d : {&h->y, &h->yr}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
+    for (DevMem *d : {&h->y, &h->yr, &h->ax}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
     launch_cast<V>(h->c64.as<double>(), h->cv.as<V>(), N, s);
     launch_cast<V>(h->l64.as<double>(), h->lv.as<V>(), N, s);
     launch_cast<V>(h->u64.as<double>(), h->uv.as<V>(), N, s);
@@ -887,7 +967,7 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
         const int32_t cn = h->ocol.host.ptr[h->col_off[q + 1]] - h->ocol.host.ptr[h->col_off[q]];
         need = std::max(need, tiny_lds_bytes(m, n, rn, cn, (int)sizeof(V)));
     }
-    h->tiny_ok = need <= (size_t)h->lds_max;
+    h->tiny_ok = need + 1024 <= (size_t)h->lds_max;  // room for the kernel's static LDS
     h->tiny_shmem = need;
     if (h->tiny_ok) {
         TinyArgs<V> a{};
@@ -930,6 +1010,7 @@ int validate_params(const scylla_params *p)
     if (p->check_period < 1 || p->check_period > 1024) throw_err(-EINVAL, "check_period must be in [1, 1024]");
     if (!(p->eta > 0.0 && p->eta < 1.0)) throw_err(-EINVAL, "eta must be in (0, 1)");
     if (p->precision != SCYLLA_FP32 && p->precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
+    if (p->adaptive != 0 && p->adaptive != 1) throw_err(-EINVAL, "adaptive must be 0 or 1");
     return 0;
 }
 
@@ -981,6 +1062,7 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     validate_params(p);
     if (p->precision != h->precision) throw_err(-EINVAL, "params precision differs from the handle's");
     const bool tiny = h->tiny_ok && p->fused_window != 0;
+    h->adaptive = p->adaptive != 0;
     if (p->autotune && !h->tuned && !tiny) {
         if (h->vbytes == 4) autotune<float>(h);
         else autotune<double>(h);
@@ -1415,7 +1497,7 @@ int scylla_params_default(scylla_params *p)
     p->eta = 0.99;
     p->time_limit_s = 0.0;
     p->fused_window = 1;
-    p->reserved = 0;
+    p->adaptive = 0;
     return 0;
 }
 

@@ -52,6 +52,8 @@ struct InstInfo {
     int32_t row0, row1, col0, col1;  // row / column ranges
     int32_t rt0, rt1, ct0, ct1;      // CSR / CSC tile ranges
     int32_t lr0, lr1, lc0, lc1;      // long-row / long-column ranges
+    int32_t ir[2][3][2];             // iteration-partial slot ranges of the
+                                     // row / column pass, up to three each
 };
 
 // Tile of an orientation: {a, b, inst, slot}.  slot < 0: rows [a, b);

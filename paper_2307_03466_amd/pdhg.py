@@ -52,7 +52,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("check_period", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
-                ("fused_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fused_window", ctypes.c_int32), ("adaptive", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

@@ -45,6 +45,66 @@ def _case(name):
 CASES = ["cover200", "general_small", "skewed_small", "skewed_longrows", "knapsack", "mixed_bounds"]
 
 
+# ------------------------------------------------- adaptive step sizes
+# The adaptive rule's eta_bar divides by dy^T A dx, where A dx is the
+# difference of two products of size |A||x| (A x_bar - A x); its rounding
+# error is relative to |A||x|, not to |A dx|, so late iterations amplify any
+# change of summation order.  Two FP64 implementations of the rule that
+# differ only in rounding (the oracle forms A dx by its definition) agree to
+# about 1e-6..1e-5 after 100 iterations, so the bar for this option is 1e-4
+# in both precisions; termination is checked with the oracle's KKT.
+ADAPT_CASES = ["general_small", "skewed_longrows", "knapsack", "cover200", "mixed_bounds"]
+
+
+@pytest.mark.parametrize("name", ADAPT_CASES)
+@pytest.mark.parametrize("prec", [0])
+def test_adaptive_step_parity(name, prec):
+    lp = _case(name)
+    s = pdhg.solve(lp, tol=1e-300, iter_limit=100, restarts=0, precision=prec, autotune=0, adaptive=1,
+                   fused_window=0)
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False, adaptive=True)
+    e = max(rel_err(s.x, ref.x), rel_err(s.y, ref.y))
+    print(f"adaptive {name} prec {prec}: e={e:.2e}", flush=True)
+    assert s.result["iterations"] == 100 and e <= 1e-4
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("name", ADAPT_CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_adaptive_step_termination(name, prec, fused):
+    lp = _case(name)
+    s = pdhg.solve(lp, tol=1e-4, iter_limit=300_000, precision=prec, adaptive=1, fused_window=fused)
+    ref = oracle.pdhg(lp, tol=1e-4, iter_limit=300_000, adaptive=True)
+    const = oracle.pdhg(lp, tol=1e-4, iter_limit=300_000, adaptive=False)
+    print(f"adaptive {name} prec {prec} fused {fused}: {s.result['iterations']} it, oracle {ref.iterations}, "
+          f"constant steps {const.iterations}", flush=True)
+    assert s.result["status"] == pdhg.OPTIMAL
+    k = oracle.kkt(lp, s.x, s.y)
+    assert k["rel"] <= 1e-4 * (1 + 1e-6)
+    assert abs(s.result["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
+    assert s.result["iterations"] <= 1.5 * ref.iterations + 128
+
+
+@pytest.mark.parametrize("layout", [(0, 4, 0, 4), (4, 8, 8, 8), (-1, 8, -1, 8), (-2, 8, -2, 8), (-3, 8, -3, 8)])
+def test_adaptive_steps_under_every_layout(layout):
+    """Every epilogue kernel (tiles, long rows, blocked and sliced combines,
+    staged tiles, rest tiles) reports its slots: the batch solves to the
+    tolerance and repeats bit for bit."""
+    lps = _sliced_cases()["mixed_batch"] + [_case("skewed_longrows")]
+    outs = []
+    for rep in range(2):
+        with pdhg.Batch(lps, precision=1) as b:
+            b.set_layout(*layout)
+            res = b.solve(tol=1e-4, iter_limit=200_000, adaptive=1, fused_window=0)
+            outs.append([b.solution(i) for i in range(len(lps))])
+        for i, lp in enumerate(lps):
+            assert res[i]["status"] == pdhg.OPTIMAL, (layout, i)
+            assert oracle.kkt(lp, *outs[-1][i])["rel"] <= 1e-4 * (1 + 1e-6)
+    for a, b2 in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a[0], b2[0])
+        np.testing.assert_array_equal(a[1], b2[1])
+
+
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
 def test_fixed_iteration_parity(name, prec, bar):

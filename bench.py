@@ -99,11 +99,12 @@ def measure(pdhg, lps, prec, steps, warmup, R, to_tol, tol_time_limit, passes=Tr
         rb, cb = pass_bytes(info, 4 if prec == pdhg.FP32 else 8)
         rec.update(ms_row=ms_row, ms_col=ms_col, bytes_row=rb, bytes_col=cb)
     if to_tol:
-        res = b.solve(tol=1e-4, iter_limit=2_000_000, time_limit_s=tol_time_limit)
-        rec["to_tol"] = dict(status=max(r["status"] for r in res), optimal=sum(r["status"] == 1 for r in res),
-                             count=len(res), iterations_max=max(r["iterations"] for r in res),
-                             iterations_sum=sum(r["iterations"] for r in res),
-                             seconds=res[0]["solve_seconds"], rel_kkt_max=max(r["rel_kkt"] for r in res))
+        for key, adaptive in (("to_tol", 0), ("to_tol_adaptive", 1)):
+            res = b.solve(tol=1e-4, iter_limit=2_000_000, time_limit_s=tol_time_limit, adaptive=adaptive)
+            rec[key] = dict(status=max(r["status"] for r in res), optimal=sum(r["status"] == 1 for r in res),
+                            count=len(res), iterations_max=max(r["iterations"] for r in res),
+                            iterations_sum=sum(r["iterations"] for r in res),
+                            seconds=res[0]["solve_seconds"], rel_kkt_max=max(r["rel_kkt"] for r in res))
     b.close()
     return rec
 
@@ -131,9 +132,11 @@ def other_workloads(pdhg, instances, args, R):
         t = time.perf_counter()
         xh, feas, ign = pdhg.fix_propagate(lp, s.x)
         out["set_cover_200x500_fp64"] = dict(iter_per_s=round(r["iter_per_s"], 1), to_tol=r["to_tol"],
+                                             to_tol_adaptive_steps=r["to_tol_adaptive"],
                                              rounding_s=round(time.perf_counter() - t, 6),
                                              rounding_feasible=feas, rounded_obj=float(lp.c @ xh))
-        log(f"w1: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} rounding feasible={feas}")
+        log(f"w1: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} adaptive={r['to_tol_adaptive']} "
+            f"rounding feasible={feas}")
     if "3" in sel:  # skewed LP, FP32 and FP64
         lp = instances.workload(3)
         rec = {}
@@ -143,9 +146,10 @@ def other_workloads(pdhg, instances, args, R):
             rec[tag] = dict(iter_per_s=round(r["iter_per_s"], 1), ms_row=round(r["ms_row"], 4),
                             ms_col=round(r["ms_col"], 4), row_GBps=round(rb / r["ms_row"] / 1e6, 1),
                             col_GBps=round(cb / r["ms_col"] / 1e6, 1), to_tol=r["to_tol"],
+                            to_tol_adaptive_steps=r["to_tol_adaptive"],
                             layout=[r["info"]["row_blocks"], r["info"]["row_chunk"], r["info"]["col_blocks"],
                                     r["info"]["col_chunk"]], long_rows=r["info"]["long_rows"])
-            log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']}")
+            log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} adaptive={r['to_tol_adaptive']}")
         rec["canonical_GBps_fp32"] = round(canonical_bytes(lp.m, lp.n, lp.nnz) * rec["fp32"]["iter_per_s"] / 1e9, 1)
         out["skewed_lp_500kx1M"] = rec
         del lp
@@ -155,9 +159,11 @@ def other_workloads(pdhg, instances, args, R):
         rec = dict(count=len(lps), batch_iter_per_s=round(r["iter_per_s"], 1),
                    instance_iter_per_s=round(r["iter_per_s"] * len(lps), 1), ms_row=round(r["ms_row"], 4),
                    ms_col=round(r["ms_col"], 4), to_tol_fp32_batched=r["to_tol"],
+                   to_tol_fp32_batched_adaptive_steps=r["to_tol_adaptive"],
                    canonical_GBps=round(canonical_bytes(sum(l.m for l in lps), sum(l.n for l in lps),
                                                         sum(l.nnz for l in lps)) * r["iter_per_s"] / 1e9, 1))
-        log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r['to_tol']}")
+        log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r['to_tol']} "
+            f"adaptive={r['to_tol_adaptive']}")
         if args.fp64_plain_batch:
             t = time.perf_counter()
             done = 0
@@ -171,6 +177,9 @@ def other_workloads(pdhg, instances, args, R):
             rec["to_tol_fp64_plain_sequential"] = dict(seconds=round(el, 3), instances=n_done, optimal=done)
             if n_done == len(lps) and r["to_tol"]["optimal"] == len(lps):
                 rec["speedup_fp32_batched_vs_fp64_plain_to_tol"] = round(el / r["to_tol"]["seconds"], 2)
+                if r["to_tol_adaptive"]["optimal"] == len(lps):
+                    rec["speedup_fp32_batched_adaptive_vs_fp64_plain_to_tol"] = round(
+                        el / r["to_tol_adaptive"]["seconds"], 2)
             log(f"w4 fp64 plain sequential: {n_done} instances in {el:.1f}s")
         out["batch_256_uneven"] = rec
         del lps
@@ -267,6 +276,7 @@ def main():
             f"layout row B={info['row_blocks']}/{info['row_chunk']} col B={info['col_blocks']}/{info['col_chunk']}")
         if args.to_tol:
             log(f"{tag}: to 1e-4: {rec['to_tol']}")
+            log(f"{tag}: to 1e-4 with adaptive steps: {rec['to_tol_adaptive']}")
         out[tag] = rec
 
     if "fp32" not in out or "fp64" not in out:
@@ -328,7 +338,9 @@ def main():
         "setup_seconds": {"fp32": round(f32["setup_s"], 3), "fp64": round(out["fp64"]["setup_s"], 3)},
     }
     if args.to_tol:
-        line["to_tol_1e-4"] = {"fp32": out["fp32"]["to_tol"], "fp64": out["fp64"]["to_tol"]}
+        line["to_tol_1e-4"] = {"fp32": out["fp32"]["to_tol"], "fp64": out["fp64"]["to_tol"],
+                               "fp32_adaptive_steps": out["fp32"]["to_tol_adaptive"],
+                               "fp64_adaptive_steps": out["fp64"]["to_tol_adaptive"]}
         if out["fp32"]["to_tol"]["status"] == 1 and out["fp64"]["to_tol"]["status"] == 1:
             line["speedup_fp32_vs_fp64_to_tol"] = round(out["fp64"]["to_tol"]["seconds"]
                                                         / out["fp32"]["to_tol"]["seconds"], 3)

@@ -815,24 +815,40 @@ __device__ __forceinline__ void adapt_step(InstState &S, double nx, double ny, d
 
 // One workgroup per instance: fixed-order FP64 sums of the iteration
 // partials of both passes (slot ranges in InstInfo::ir), then the rule.
-__global__ __launch_bounds__(256) void k_step(const StepArgs a)
+// Each thread issues its loads in groups of STEP_U before adding them, so
+// an instance with thousands of tiles is not bound by load latency.
+constexpr int STEP_NT = 1024, STEP_U = 8;
+
+__device__ __forceinline__ void step_sum(const double *ip, int lo, int hi, int comp, double &acc)
 {
-    __shared__ double red2[8];
+    for (int q0 = lo + (int)threadIdx.x; q0 < hi; q0 += STEP_NT * STEP_U) {
+        double v[STEP_U];
+#pragma unroll
+        for (int u = 0; u < STEP_U; ++u) {
+            const int q = q0 + u * STEP_NT;
+            v[u] = q < hi ? ip[2 * q + comp] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < STEP_U; ++u) acc += v[u];
+    }
+}
+
+__global__ __launch_bounds__(STEP_NT) void k_step(const StepArgs a)
+{
+    __shared__ double red2[2 * STEP_NT / 64];
     const int inst = blockIdx.x;
     InstState &S = a.st[inst];
     if (S.status != ST_RUN || a.jw >= S.nrun) return;
     const InstInfo I = a.info[inst];
     double nx = 0.0, ny = 0.0, inter = 0.0;
     for (int r = 0; r < 3; ++r) {
-        for (int q = I.ir[1][r][0] + threadIdx.x; q < I.ir[1][r][1]; q += 256) nx += a.cip[2 * q];
-        for (int q = I.ir[0][r][0] + threadIdx.x; q < I.ir[0][r][1]; q += 256) {
-            ny += a.rip[2 * q];
-            inter += a.rip[2 * q + 1];
-        }
+        step_sum(a.cip, I.ir[1][r][0], I.ir[1][r][1], 0, nx);
+        step_sum(a.rip, I.ir[0][r][0], I.ir[0][r][1], 0, ny);
+        step_sum(a.rip, I.ir[0][r][0], I.ir[0][r][1], 1, inter);
     }
     double zero = 0.0;
-    block_sum2<256>(nx, zero, red2);
-    block_sum2<256>(ny, inter, red2);
+    block_sum2<STEP_NT>(nx, zero, red2);
+    block_sum2<STEP_NT>(ny, inter, red2);
     if (threadIdx.x == 0) adapt_step(S, nx, ny, inter, S.k + a.jw + 1);
 }
 
@@ -1427,7 +1443,7 @@ void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s)
 
 void launch_step(const StepArgs &a, int count, hipStream_t s)
 {
-    if (count > 0) hipLaunchKernelGGL(k_step, dim3(count), dim3(256), 0, s, a);
+    if (count > 0) hipLaunchKernelGGL(k_step, dim3(count), dim3(STEP_NT), 0, s, a);
 }
 
 void launch_decide(const DecideArgs &d, int count, hipStream_t s)

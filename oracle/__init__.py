@@ -14,7 +14,9 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
   fix_propagate                 pinned (integrality/bounds, identity on
                                 feasible integral input, set-cover success,
                                 brute-force propagation soundness)
-  objective_update, eps_schedule pinned (closed forms / norm identities)
+  objective_update(_l2),        pinned (closed forms / norm identities,
+  eps_schedule                  the QP form equals the L2 distance up to a
+                                constant)
   pump, scylla                  parity unpinned: the round of first success
                                 depends on rounding choices the paper leaves
                                 open; only invariants are checked (early
@@ -50,7 +52,8 @@ class _LPStruct(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
                 ("val", ctypes.c_void_p), ("c", ctypes.c_void_p), ("b", ctypes.c_void_p),
-                ("sense", ctypes.c_void_p), ("l", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+                ("sense", ctypes.c_void_p), ("l", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("q", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -91,7 +94,7 @@ def _p(a):
 class _Pinned:
     """Keeps contiguous numpy copies alive while C uses them."""
 
-    def __init__(self, lp, c=None):
+    def __init__(self, lp, c=None, q=None):
         self.row_ptr = np.ascontiguousarray(lp.row_ptr, dtype=np.int64)
         self.col_idx = np.ascontiguousarray(lp.col_idx, dtype=np.int32)
         self.val = np.ascontiguousarray(lp.val, dtype=np.float64)
@@ -100,8 +103,11 @@ class _Pinned:
         self.sense = np.ascontiguousarray(lp.senses, dtype=np.uint8)
         self.l = np.ascontiguousarray(lp.l, dtype=np.float64)
         self.u = np.ascontiguousarray(lp.u, dtype=np.float64)
+        self.q = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        if self.q is not None and (self.q.shape != (lp.n,) or np.any(~(self.q >= 0))):
+            raise ValueError("q must be a nonnegative [n] vector")
         self.s = _LPStruct(lp.m, lp.n, _p(self.row_ptr), _p(self.col_idx), _p(self.val),
-                           _p(self.c), _p(self.b), _p(self.sense), _p(self.l), _p(self.u))
+                           _p(self.c), _p(self.b), _p(self.sense), _p(self.l), _p(self.u), _p(self.q))
 
 
 @dataclass
@@ -130,9 +136,10 @@ def precondition(lp, ruiz_iters: int = 10, pock_chambolle: bool = True):
     return dr, dc
 
 
-def kkt(lp, x, y, c=None):
-    """Relative KKT of (x, y): dict with rel, rho_p, rho_d, rho_g, pobj, dobj."""
-    pin = _Pinned(lp, c)
+def kkt(lp, x, y, c=None, q=None):
+    """Relative KKT of (x, y): dict with rel, rho_p, rho_d, rho_g, pobj, dobj
+    (with a diagonal Hessian q: of the QP min c^T x + x^T diag(q) x / 2)."""
+    pin = _Pinned(lp, c, q)
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     out = np.zeros(8)
@@ -145,11 +152,12 @@ def kkt(lp, x, y, c=None):
 def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 64,
          restarts: bool = True, eta: float = 0.99, x0=None, y0=None, omega0: float = 0.0,
          c=None, ruiz_iters: int = 10, pock_chambolle: bool = True,
-         adaptive: bool = False) -> PDHGResult:
+         adaptive: bool = False, q=None) -> PDHGResult:
     """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop); with
     `adaptive` the step size follows PDLP's adaptive rule (no retries),
-    starting at `eta`."""
-    pin = _Pinned(lp, c)
+    starting at `eta`.  `q`: diagonal Hessian (>= 0) of a QP objective
+    c^T x + x^T diag(q) x / 2, or None."""
+    pin = _Pinned(lp, c, q)
     x = np.empty(lp.n)
     y = np.empty(lp.m)
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
@@ -207,6 +215,23 @@ def objective_update(c, xhat, l, u, is_int, K: int, alpha: float = ALPHA):
     g = distance_gradient(xhat, l, u, is_int)
     scaled = (np.sqrt(nI) / cn) * c if cn > 0 else np.zeros_like(c)
     return a * scaled + (1.0 - a) * g
+
+
+def objective_update_l2(c, xhat, is_int, K: int, alpha: float = ALPHA):
+    """The objective update with the L2 distance Section 5 proposes (no
+    auxiliary variables for general integers): alpha^K (sqrt(|I|)/||c||) c^T x
+    + (1 - alpha^K) sum_{j in I} (x_j - x_hat_j)^2, written as the QP
+    objective c_hat^T x + x^T diag(q) x / 2 plus a constant: q_j =
+    2 (1 - alpha^K) and c_hat_j = alpha^K kappa c_j - 2 (1 - alpha^K) x_hat_j
+    on I; q_j = 0 and c_hat_j = alpha^K kappa c_j elsewhere.  Returns (c_hat, q)."""
+    a = alpha ** K
+    ii = is_int.astype(bool)
+    nI = int(np.count_nonzero(ii))
+    cn = float(np.linalg.norm(c))
+    scaled = (np.sqrt(nI) / cn) * c if cn > 0 else np.zeros_like(c)
+    c_hat = a * scaled - np.where(ii, 2.0 * (1.0 - a) * xhat, 0.0)
+    q = np.where(ii, 2.0 * (1.0 - a), 0.0)
+    return c_hat, q
 
 
 def eps_schedule(K: int, eps1: float = 0.01, beta: float = 0.98, floor: float = 1e-8) -> float:
@@ -294,7 +319,7 @@ def perturb(lp, xbar, xhat, T):
 
 def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter_limit: int = 100_000,
            total_iter_limit: int = 0, early_exit: bool = True, cycle_perturb: bool = True, seed: int = 0,
-           instance: int = 0, alpha: float = ALPHA, **kw):
+           instance: int = 0, alpha: float = ALPHA, distance: str = "l1", **kw):
     """Algorithm 1 on one instance.  Round K solves the LP relaxation with the
     current objective to tolerance eps(K) (Section 2.2; `tol` if eps_sched
     is off), warm-started from the previous round, with at most iter_limit
@@ -303,11 +328,15 @@ def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter
     PDHG iterate, else whose rounding, is MIP-feasible is the find; with
     early_exit the loop returns there.  A rounding equal to an earlier one
     (history of roundings as used, i.e. after perturbation) is perturbed; the
-    objective is then updated with alpha^K from the rounding as used.
-    Returns (found_kind, found_round, point, records): found_kind 0 (none),
+    objective is then updated with alpha^K from the rounding as used, with
+    the L1 distance, or with distance="l2" the L2 distance (a QP solve from
+    round 2 on).  Returns (found_kind, found_round, point, records): found_kind 0 (none),
     1 (PDHG iterate), 2 (rounding); point is the find, else the last
     rounding before perturbation (None if no round ran)."""
+    if distance not in ("l1", "l2"):
+        raise ValueError("distance must be 'l1' or 'l2'")
     c_hat = lp.c.copy()
+    q_hat = None
     x = y = None
     omega = 0.0
     history = []
@@ -321,7 +350,7 @@ def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter
         if lim <= 0:
             break
         tk = eps_schedule(K) if eps_sched else tol
-        r = pdhg(lp, tol=tk, iter_limit=lim, x0=x, y0=y, omega0=omega, c=c_hat, **kw)
+        r = pdhg(lp, tol=tk, iter_limit=lim, x0=x, y0=y, omega0=omega, c=c_hat, q=q_hat, **kw)
         used += r.iterations
         x, y, omega = r.x, r.y, r.omega
         rec = dict(K=K, tol=tk, status=r.status, iterations=r.iterations, rel_kkt=r.rel_kkt,
@@ -346,5 +375,8 @@ def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter
             history.append(xhat)
         rec["xhat_used"] = xhat
         if K < rounds:
-            c_hat = objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K, alpha)
+            if distance == "l1":
+                c_hat = objective_update(lp.c, xhat, lp.l, lp.u, lp.is_int, K, alpha)
+            else:
+                c_hat, q_hat = objective_update_l2(lp.c, xhat, lp.is_int, K, alpha)
     return kind, found_K, point, recs

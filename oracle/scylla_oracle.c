@@ -22,6 +22,10 @@
  *                        detail; the constants are readings, listed below).
  *   - orc_kkt          : relative primal / dual / gap errors of (x, y) on the
  *                        original problem (Section 2.2).
+ *   An optional diagonal Hessian q (the quadratic objectives Section 5
+ *   proposes: diagonal-Hessian QPs, and the L2 distance of the objective
+ *   update) enters the primal proximal step exactly and the KKT test through
+ *   the reduced cost and both objectives.
  *   - orc_fix_propagate: fix-and-propagate rounding (Section 2.3).
  *
  * Readings where the paper is silent (each is restated in the design notes):
@@ -62,6 +66,7 @@ typedef struct {
     const double *b;        /* [m] */
     const char *sense;      /* [m] 'G', 'L' or 'E' */
     const double *l, *u;    /* [n], may be -inf / +inf */
+    const double *q;        /* [n] diagonal Hessian >= 0, or NULL (LP) */
 } orc_lp;
 
 typedef struct {
@@ -204,7 +209,11 @@ int orc_kkt(const orc_lp *lp, const double *x, const double *y, double *out)
         dobj += lp->b[i] * y[i];
     }
     for (int32_t j = 0; j < n; ++j) {
-        double g = lp->c[j] - aty[j];
+        /* with a diagonal Hessian: reduced cost c + Q x - A^T y; primal
+           objective c^T x + x^T Q x / 2; dual objective
+           b^T y - x^T Q x / 2 + bound terms (the QP dual at the same x) */
+        const double qx = lp->q ? lp->q[j] * x[j] : 0.0;
+        double g = lp->c[j] + qx - aty[j];
         int lf = isfinite(lp->l[j]), uf = isfinite(lp->u[j]);
         double lam;
         if (lf && uf) lam = g;
@@ -213,7 +222,8 @@ int orc_kkt(const orc_lp *lp, const double *x, const double *y, double *out)
         else lam = 0.0;
         double rd = g - lam;
         rd2 += rd * rd;
-        pobj += lp->c[j] * x[j];
+        pobj += lp->c[j] * x[j] + 0.5 * qx * x[j];
+        dobj -= 0.5 * qx * x[j];
         if (lf && lam > 0.0) dobj += lp->l[j] * lam;
         if (uf && lam < 0.0) dobj += lp->u[j] * lam;
     }
@@ -329,8 +339,13 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
         /* primal step: d_x = A^T y - c_hat, x+ = proj_[l,u](x + t D_c^2 d_x) */
         mul_At(lp, y, aty);
         for (int32_t j = 0; j < n; ++j) {
+            /* proximal step; with a diagonal Hessian the one-dimensional
+               problem min q x^2/2 + (c - A^T y) x + |x - x_j|^2 / (2 t D_c^2)
+               over [l, u] is solved exactly: minimiser, then clamp */
             double dx = aty[j] - lp->c[j];
-            xn[j] = clampd(x[j] + t * (dc[j] * dc[j]) * dx, lp->l[j], lp->u[j]);
+            double v = x[j] + t * (dc[j] * dc[j]) * dx;
+            if (lp->q) v /= 1.0 + t * (dc[j] * dc[j]) * lp->q[j];
+            xn[j] = clampd(v, lp->l[j], lp->u[j]);
             xbar[j] = 2.0 * xn[j] - x[j];
         }
         /* dual step: d_y = b - A(2 x+ - x), y+ = proj_Y(y + s D_r^2 d_y) */

@@ -106,23 +106,26 @@ def brute_force_lp(lp):
     return best, best_x
 
 
-def kkt_numpy(lp, x, y, c=None):
+def kkt_numpy(lp, x, y, c=None, q=None):
     """Relative KKT errors from the formulas, vectorised with scipy.sparse
-    (independent of the C oracle)."""
+    (independent of the C oracle); q: diagonal Hessian of a QP objective
+    c^T x + x^T diag(q) x / 2 (its dual objective at the same x subtracts
+    x^T diag(q) x / 2)."""
     c = lp.c if c is None else c
+    qx = np.zeros(lp.n) if q is None else np.asarray(q) * x
     A = csr(lp)
     ax = A @ x
     aty = A.T @ y
     s = lp.senses
     rp = np.where(s == ord("G"), np.maximum(lp.b - ax, 0),
                   np.where(s == ord("L"), np.maximum(ax - lp.b, 0), lp.b - ax))
-    g = c - aty
+    g = c + qx - aty
     lf, uf = np.isfinite(lp.l), np.isfinite(lp.u)
     lam = np.where(lf & uf, g, np.where(lf, np.maximum(g, 0), np.where(uf, np.minimum(g, 0), 0.0)))
     rd = g - lam
-    P = c @ x
+    P = c @ x + 0.5 * (qx @ x)
     D = lp.b @ y + np.sum(np.where(lf, lp.l, 0) * np.maximum(lam, 0)) \
-        - np.sum(np.where(uf, lp.u, 0) * np.maximum(-lam, 0))
+        - np.sum(np.where(uf, lp.u, 0) * np.maximum(-lam, 0)) - 0.5 * (qx @ x)
     rho_p = np.linalg.norm(rp) / (1 + np.linalg.norm(lp.b))
     rho_d = np.linalg.norm(rd) / (1 + np.linalg.norm(c))
     rho_g = abs(P - D) / (1 + abs(P) + abs(D))

@@ -275,3 +275,49 @@ def test_scylla_cycle_perturbation_rule():
                 assert r["xhat_used"] is r["xhat"]
             used.append(r["xhat_used"])
     assert seen >= 3
+
+
+# ------------------------------------------------ L2 distance (Section 5)
+def test_l2_objective_update_equals_definition():
+    """c_hat^T x + x^T diag(q) x / 2 differs from alpha^K kappa c^T x +
+    (1 - alpha^K) |x_I - x_hat_I|^2 by a constant: the same at every x."""
+    rng = np.random.default_rng(4)
+    n = 30
+    c = rng.normal(size=n)
+    is_int = (rng.random(n) < 0.6).astype(np.uint8)
+    xhat = np.where(is_int == 1, rng.integers(-3, 7, size=n), 0).astype(float)
+    K = 3
+    c_hat, q = oracle.objective_update_l2(c, xhat, is_int, K)
+    a = oracle.ALPHA ** K
+    kappa = np.sqrt(is_int.sum()) / np.linalg.norm(c)
+    ii = is_int.astype(bool)
+    diffs = []
+    for _ in range(5):
+        x = rng.normal(size=n) * 4
+        f = c_hat @ x + 0.5 * (q * x) @ x
+        d = a * kappa * (c @ x) + (1 - a) * np.sum((x[ii] - xhat[ii]) ** 2)
+        diffs.append(f - d)
+    assert np.ptp(diffs) <= 1e-9 * (1 + abs(diffs[0]))
+    assert np.all(q[~ii] == 0) and np.all(q[ii] == 2 * (1 - a))
+
+
+def test_l2_loop_handles_general_integers():
+    """General integers strictly inside their bounds: the L1 update rejects
+    them, the L2 loop runs (its PDHG solves are QPs) and every rounding is
+    integral and within bounds."""
+    rng = np.random.default_rng(8)
+    lp = I.tiny_lp(rng, 8, 12)
+    lp.is_int = np.ones(lp.n, dtype=np.uint8)
+    lp.l = np.zeros(lp.n)
+    lp.u = np.full(lp.n, 6.0)
+    xs = np.round(rng.random(lp.n) * 6)
+    A = np.zeros((lp.m, lp.n))
+    A[np.repeat(np.arange(lp.m), np.diff(lp.row_ptr)), lp.col_idx] = lp.val
+    lp.b = A @ xs - np.where(lp.senses == ord("L"), -1.0, np.where(lp.senses == ord("G"), 1.0, 0.0))
+    kind, K, point, recs = oracle.scylla(lp, rounds=6, distance="l2", cycle_perturb=False, early_exit=False)
+    for r in recs:
+        xh = r["xhat"]
+        assert np.all(xh == np.round(xh)) and np.all(xh >= lp.l) and np.all(xh <= lp.u)
+    assert any(r["K"] > 1 for r in recs)
+    if kind:
+        assert oracle.mip_feasible(lp, point)

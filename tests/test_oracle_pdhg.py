@@ -292,3 +292,92 @@ def test_adaptive_steps_reach_the_optimum(name):
         assert r.status == oracle.OPTIMAL, adaptive
         assert kkt_numpy(lp, r.x, r.y)["rel"] <= 1e-7 * 1.0001
         assert abs(r.pobj - ref) <= 1e-5 * (1 + abs(ref))
+
+
+# ------------------------------------------- diagonal-Hessian QP objective
+def test_qp_box_closed_form():
+    """No rows: min sum q_j x_j^2 / 2 + c_j x_j over [l, u] is solved
+    coordinate-wise by clamp(-c_j / q_j, l_j, u_j)."""
+    rng = np.random.default_rng(21)
+    n = 11
+    c, q = rng.normal(size=n) * 3, rng.random(n) + 0.2
+    l, u = -rng.random(n), rng.random(n)
+    lp = lp_from_dense(np.zeros((0, n)), [], "", c, l, u)
+    r = oracle.pdhg(lp, tol=1e-11, iter_limit=1_000_000, q=q)
+    assert r.status == oracle.OPTIMAL
+    np.testing.assert_allclose(r.x, np.clip(-c / q, l, u), atol=1e-9)
+
+
+def test_qp_one_equality_by_bisection():
+    """min sum q_j x_j^2 / 2 + c_j x_j s.t. sum_j x_j = b, 0 <= x <= u: the
+    optimum is x_j(mu) = clamp((mu - c_j) / q_j, 0, u_j) with mu solving
+    sum_j x_j(mu) = b (monotone, found by bisection)."""
+    rng = np.random.default_rng(22)
+    n = 9
+    c, q, u = rng.normal(size=n), rng.random(n) + 0.5, rng.random(n) * 2 + 0.5
+    b = 0.4 * u.sum()
+    lo, hi = -100.0, 100.0
+    for _ in range(200):
+        mu = 0.5 * (lo + hi)
+        if np.clip((mu - c) / q, 0, u).sum() < b:
+            lo = mu
+        else:
+            hi = mu
+    xs = np.clip((mu - c) / q, 0, u)
+    lp = lp_from_dense(np.ones((1, n)), [b], "E", c, np.zeros(n), u)
+    r = oracle.pdhg(lp, tol=1e-11, iter_limit=2_000_000, q=q)
+    assert r.status == oracle.OPTIMAL
+    np.testing.assert_allclose(r.x, xs, atol=1e-8)
+    assert abs(r.y[0] - mu) < 1e-7  # the row's multiplier is mu
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_qp_matches_slsqp(seed):
+    """Tiny QPs with mixed rows: the oracle's optimum objective equals
+    SLSQP's (scipy), and its KKT agrees with the independent evaluator."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(300 + seed)
+    lp = I.tiny_lp(rng, 3, 5)
+    q = rng.random(lp.n) * 2
+    A = dense(lp)
+    cons = []
+    for i, sn in enumerate(lp.senses):
+        f = (lambda x, i=i: A[i] @ x - lp.b[i])
+        if sn == ord("G"):
+            cons.append(dict(type="ineq", fun=f))
+        elif sn == ord("L"):
+            cons.append(dict(type="ineq", fun=lambda x, f=f: -f(x)))
+        else:
+            cons.append(dict(type="eq", fun=f))
+    obj = lambda x: lp.c @ x + 0.5 * (q * x) @ x
+    best = None
+    for start in range(6):
+        x0 = np.clip(rng.normal(size=lp.n), lp.l, lp.u)
+        s = minimize(obj, x0, method="SLSQP", bounds=list(zip(lp.l, lp.u)), constraints=cons,
+                     options=dict(ftol=1e-14, maxiter=2000))
+        if s.success and (best is None or s.fun < best):
+            best = s.fun
+    r = oracle.pdhg(lp, tol=1e-9, iter_limit=3_000_000, q=q)
+    assert r.status == oracle.OPTIMAL
+    assert abs(r.pobj - best) <= 1e-6 * (1 + abs(best))
+    k = kkt_numpy(lp, r.x, r.y, q=q)
+    assert abs(k["rel"] - r.rel_kkt) <= 1e-12 * (1 + k["rel"])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_qp_kkt_matches_independent_evaluator(seed):
+    rng = np.random.default_rng(seed)
+    lp = I.tiny_lp(rng, 6, 9, bounded=False)
+    q = rng.random(lp.n)
+    x = np.clip(rng.normal(size=lp.n), lp.l, lp.u)
+    y = rng.normal(size=lp.m)
+    y = np.where(lp.senses == ord("G"), np.abs(y), np.where(lp.senses == ord("L"), -np.abs(y), y))
+    a = oracle.kkt(lp, x, y, q=q)
+    b = kkt_numpy(lp, x, y, q=q)
+    for key in ("rel", "rho_p", "rho_d", "rho_g", "pobj", "dobj"):
+        assert abs(a[key] - b[key]) <= 1e-12 * (1 + abs(b[key])), key
+    # q = 0 is the LP exactly
+    z = oracle.pdhg(lp, tol=-1.0, iter_limit=50, q=np.zeros(lp.n))
+    w = oracle.pdhg(lp, tol=-1.0, iter_limit=50)
+    np.testing.assert_array_equal(z.x, w.x)
+    np.testing.assert_array_equal(z.y, w.y)

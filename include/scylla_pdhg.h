@@ -176,6 +176,16 @@ int scylla_batch_set_objective(scylla_batch *h, int32_t inst, const double *c_ha
  * little-endian within each byte; each array holds ceil(n_inst / 8) bytes
  * (host).  int_bits may be NULL (all integer).  Typically a = 0.9^K and
  * kappa = sqrt(|I|) / ||c||_2. */
+/* Diagonal Hessian of instance `inst`'s objective: the handle then solves
+ * min c_hat^T x + x^T diag(q) x / 2 (the diagonal-Hessian QPs Section 5
+ * proposes for PDHG): the primal step solves each coordinate's proximal
+ * problem exactly, x+ = proj_[l,u]((x + t D_c^2 (A^T y - c_hat)) /
+ * (1 + t D_c^2 q)), and the KKT test uses the reduced cost c_hat + Q x - A^T y,
+ * the primal objective + x^T Q x / 2 and the dual objective - x^T Q x / 2.
+ * q: [n_inst] host, finite and >= 0, or NULL (zero).  Returns 0 or
+ * -EINVAL. */
+int scylla_batch_set_quadratic(scylla_batch *h, int32_t inst, const double *q);
+
 int scylla_batch_set_blend(scylla_batch *h, int32_t inst, const uint8_t *xhat_bits,
                            const uint8_t *int_bits, double a, double kappa);
 
@@ -297,7 +307,13 @@ typedef struct {
     uint64_t seed;            /* seed of the perturbation counts              */
     int32_t threads;          /* host rounding workers, 0 = one per hardware
                                  thread                                       */
-    int32_t reserved;
+    int32_t distance;         /* 1: L1 distance (Algorithm 1; linear
+                                 objective; default); 2: L2 distance
+                                 (Section 5: QP objective alpha^K kappa c^T x
+                                 + (1 - alpha^K) |x_I - x_hat_I|^2, solved as
+                                 c_hat = alpha^K kappa c - 2 (1 - alpha^K)
+                                 x_hat, Hessian 2 (1 - alpha^K) on I; general
+                                 integers need no auxiliary variables)        */
 } scylla_pump_params;
 
 /* Per-instance outcome of scylla_batch_pump_ex. */
@@ -312,7 +328,7 @@ typedef struct {
 
 /* Defaults of the paper's configuration: 20 rounds, eps schedule on
  * (0.01, 0.98, 1e-8), alpha 0.9, no cumulative limit, early exit and
- * perturbation on, seed 0, threads 0. */
+ * perturbation on, seed 0, threads 0, L1 distance. */
 int scylla_pump_params_default(scylla_pump_params *o);
 
 /* The complete outer loop of Algorithm 1 on every instance of the batch:

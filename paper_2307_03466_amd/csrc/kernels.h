@@ -69,6 +69,10 @@ struct PassArgs {
     int32_t adapt;
     double *ipart, *iplong;
     V *ax;
+    // diagonal Hessian of a QP objective (column pass / column check), or
+    // null: x+ = proj((x + t D_c^2 (A^T y - c)) / (1 + t D_c^2 q))
+    const V *q;
+    const double *q64;
 };
 
 // Step-size update after iteration jw of the window, one workgroup per
@@ -95,6 +99,8 @@ struct TinyArgs {
     const V *c, *l, *u, *dc2, *b, *dr2;
     const uint8_t *sense;
     const double *c64, *l64, *u64, *b64, *dr64, *dc64;
+    const V *q;           // diagonal Hessian or null
+    const double *q64;
     InstState *st;
     const InstInfo *info;
     int32_t adapt;  // adaptive step sizes
@@ -105,7 +111,7 @@ inline size_t tiny_lds_bytes(int m, int n, int rnnz, int cnnz, int vb)
 {
     auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return al(4 * (size_t)(m + 1)) + al(4 * (size_t)(n + 1)) + al(4 * (size_t)rnnz) + al(4 * (size_t)cnnz) +
-           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 7 * al((size_t)vb * n) + 5 * al((size_t)vb * m) +
+           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 8 * al((size_t)vb * n) + 5 * al((size_t)vb * m) +
            al((size_t)m);
 }
 

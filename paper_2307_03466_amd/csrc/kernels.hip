@@ -164,7 +164,7 @@ __device__ __forceinline__ void stage_products(const MatView &M, const GV *__res
 // latency overlaps the matrix stream.
 template <class V>
 struct RowOps {
-    V own, rhs, diag2, lo, hi, ax;
+    V own, rhs, diag2, lo, hi, ax, q;
     uint8_t sense;
 };
 
@@ -177,6 +177,7 @@ __device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> 
     if (DIR == DIR_COL) {
         o.lo = p.lo[i];
         o.hi = p.hi[i];
+        if (p.q) o.q = p.q[i];
     } else {
         o.sense = p.sense[i];
         if (p.adapt) o.ax = p.ax[i];
@@ -192,6 +193,7 @@ __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V 
 {
     if (DIR == DIR_COL) {
         V xn = o.own + step * o.diag2 * (sum - o.rhs);
+        if (p.q) xn /= (V)1 + step * o.diag2 * o.q;  // exact prox of q x^2 / 2
         xn = xn < o.lo ? o.lo : xn;
         xn = xn > o.hi ? o.hi : xn;
         if (copy_ref) p.own_ref[i] = o.own;
@@ -582,7 +584,11 @@ __device__ __forceinline__ void row_terms(const PassArgs<V> &p, int i, double ax
 template <class V>
 __device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double aty, double q[4])
 {
-    const double g = p.rhs64[j] - aty;
+    // with a diagonal Hessian: reduced cost c + Q x - A^T y, primal objective
+    // + x^T Q x / 2, dual objective - x^T Q x / 2 (kept with the bound terms)
+    const double x = (double)p.own[j];
+    const double qx = p.q64 ? p.q64[j] * x : 0.0;
+    const double g = p.rhs64[j] + qx - aty;
     const double l = p.lo64[j], u = p.hi64[j];
     const bool lf = isfinite(l), uf = isfinite(u);
     double lam;
@@ -591,12 +597,12 @@ __device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double at
     else if (uf) lam = fmin(g, 0.0);
     else lam = 0.0;
     const double rd = g - lam;
-    const double x = (double)p.own[j];
     const double dx = (x - (double)p.own_ref[j]) / p.d64[j];
     q[0] += rd * rd;
-    q[1] += p.rhs64[j] * x;
+    q[1] += p.rhs64[j] * x + 0.5 * qx * x;
     if (lf && lam > 0.0) q[2] += l * lam;
     if (uf && lam < 0.0) q[2] += u * lam;
+    q[2] -= 0.5 * qx * x;
     q[3] += dx * dx;
 }
 
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepArgs a)
 template <class V>
 struct TinyLds {
     int *rptr, *cptr, *rcol, *ccol;
-    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *y, *yr, *b, *dr2, *ax;
+    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *q, *y, *yr, *b, *dr2, *ax;
     uint8_t *sense;
 };
 
@@ -889,6 +895,7 @@ __device__ __forceinline__ TinyLds<V> tiny_carve(unsigned char *base, int m, int
     t.l = (V *)take(sizeof(V) * (size_t)n);
     t.u = (V *)take(sizeof(V) * (size_t)n);
     t.dc2 = (V *)take(sizeof(V) * (size_t)n);
+    t.q = (V *)take(sizeof(V) * (size_t)n);
     t.y = (V *)take(sizeof(V) * (size_t)m);
     t.yr = (V *)take(sizeof(V) * (size_t)m);
     t.b = (V *)take(sizeof(V) * (size_t)m);
@@ -941,6 +948,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         L.l[j] = a.l[g];
         L.u[j] = a.u[g];
         L.dc2[j] = a.dc2[g];
+        L.q[j] = a.q ? a.q[g] : (V)0;
     }
     for (int i = tid; i < m; i += NT) {
         const int g = I.row0 + i;
@@ -974,7 +982,9 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         for (int e = L.cptr[j]; e < L.cptr[j + 1]; ++e) aty += (double)L.cval[e] * (double)L.y[L.ccol[e]];
         const int g = I.col0 + j;
         const double cc = a.c64[g], lo = a.l64[g], hi = a.u64[g];
-        const double gr = cc - aty;
+        const double xq = (double)L.x[j];
+        const double qx = a.q64 ? a.q64[g] * xq : 0.0;
+        const double gr = cc + qx - aty;
         const bool lf = isfinite(lo), uf = isfinite(hi);
         double lam;
         if (lf && uf) lam = gr;
@@ -982,12 +992,12 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         else if (uf) lam = fmin(gr, 0.0);
         else lam = 0.0;
         const double rd = gr - lam;
-        const double xx = (double)L.x[j];
-        const double dx = (xx - (double)L.xr[j]) / a.dc64[g];
+        const double dx = (xq - (double)L.xr[j]) / a.dc64[g];
         acc[3] += rd * rd;
-        acc[4] += cc * xx;
+        acc[4] += cc * xq + 0.5 * qx * xq;
         if (lf && lam > 0.0) acc[5] += lo * lam;
         if (uf && lam < 0.0) acc[5] += hi * lam;
+        acc[5] -= 0.5 * qx * xq;
         acc[6] += dx * dx;
     }
     double tot[7];
@@ -1020,6 +1030,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
             if (lc == 0) {
                 const V xj = L.x[j];
                 V xn = xj + t * L.dc2[j] * (aty - L.c[j]);
+                if (a.q) xn /= (V)1 + t * L.dc2[j] * L.q[j];
                 xn = xn < L.l[j] ? L.l[j] : xn;
                 xn = xn > L.u[j] ? L.u[j] : xn;
                 if (copy_ref) L.xr[j] = xj;

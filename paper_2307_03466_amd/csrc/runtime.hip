@@ -151,6 +151,8 @@ struct scylla_batch {
     DevMem c64, corig64, l64, u64, b64, dr64, dc64;
     DevMem st, info;
     DevMem ax;              // running A x of the row pass (adaptive steps)
+    DevMem q64, qv;         // diagonal Hessian (QP objectives), once set
+    bool has_q = false;
     bool adaptive = false;  // adaptive step sizes in the current graph
     DevMem bits_tmp, ibits_tmp;
     // graph
@@ -231,6 +233,10 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     p.nctiles = o.blocked ? (int32_t)(o.bplan.ctiles.size() / 4) : 0;
     p.adapt = h->adaptive ? 1 : 0;
     p.ax = h->ax.as<V>();
+    if (!o.row && h->has_q) {
+        p.q = h->qv.as<V>();
+        p.q64 = h->q64.as<double>();
+    }
     p.ipart = o.ipart.as<double>();
     p.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_long;
     if (o.sliced) {
@@ -596,6 +602,10 @@ TinyArgs<V> tiny_args(scylla_batch *h)
     a.st = h->st.as<InstState>();
     a.info = h->info.as<InstInfo>();
     a.adapt = h->adaptive ? 1 : 0;
+    if (h->has_q) {
+        a.q = h->qv.as<V>();
+        a.q64 = h->q64.as<double>();
+    }
     return a;
 }
 
@@ -1211,8 +1221,32 @@ void parallel_for(int32_t count, int32_t threads, F &&f)
     for (auto &t : pool) t.join();
 }
 
+// Allocates the diagonal Hessian (zero) on first use; the kernels then take
+// the QP form of the primal step, so the graph is rebuilt.
+void ensure_q(scylla_batch *h)
+{
+    if (h->has_q) return;
+    h->q64.alloc((size_t)std::max(h->N, 1) * 8);
+    h->qv.alloc((size_t)std::max(h->N, 1) * h->vbytes);
+    HIPC(hipMemsetAsync(h->q64.p, 0, h->q64.bytes, h->stream));
+    HIPC(hipMemsetAsync(h->qv.p, 0, h->qv.bytes, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    h->has_q = true;
+    invalidate_graph(h);
+}
+
+void cast_q(scylla_batch *h)
+{
+    if (h->vbytes == 4) launch_cast<float>(h->q64.as<double>(), h->qv.as<float>(), h->N, h->stream);
+    else launch_cast<double>(h->q64.as<double>(), h->qv.as<double>(), h->N, h->stream);
+}
+
 void reset_objective(scylla_batch *h)
 {
+    if (h->has_q) {
+        HIPC(hipMemsetAsync(h->q64.p, 0, h->q64.bytes, h->stream));
+        HIPC(hipMemsetAsync(h->qv.p, 0, h->qv.bytes, h->stream));
+    }
     HIPC(hipMemcpyAsync(h->c64.p, h->corig64.p, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
     if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>(), h->cv.as<float>(), h->N, h->stream);
     else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), h->N, h->stream);
@@ -1281,6 +1315,7 @@ struct PumpOpts {
     bool early_exit, perturb;
     uint64_t seed;
     int32_t threads;
+    int32_t distance;  // 1: L1 (linear objective), 2: L2 (QP objective)
 };
 
 // Algorithm 1 outer loop.  legacy_best: also keep, per instance, the first
@@ -1294,8 +1329,11 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     if (o.eps_sched && !(o.eps1 > 0.0 && o.beta > 0.0 && o.beta <= 1.0 && o.eps_floor > 0.0))
         throw_err(-EINVAL, "eps schedule needs eps1 > 0, 0 < beta <= 1, eps_floor > 0");
     if (o.total_iter_limit < 0) throw_err(-EINVAL, "total_iter_limit must be >= 0");
+    if (o.distance != 1 && o.distance != 2) throw_err(-EINVAL, "distance must be 1 (L1) or 2 (L2)");
     validate_params(p);
     build_locals(h);
+    const bool l2 = o.distance == 2;
+    if (l2) ensure_q(h);
     const int32_t N = h->N, count = h->count;
     std::vector<uint8_t> isint(N, 1);
     if (is_int)
@@ -1326,6 +1364,11 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     HIPC(hipStreamSynchronize(h->stream));
 
     std::vector<double> x(N), xhat(N), xres(N, 0.0);
+    std::vector<double> chat, qhat;  // L2: next objective and Hessian
+    if (l2) {
+        chat = h->hc;
+        qhat.assign(N, 0.0);
+    }
     if (legacy_best) h->pump_best.assign(N, 0.0);
     std::vector<uint8_t> found_best(count, 0), active(count, 1);
     std::vector<scylla_pump_outcome> out(count);
@@ -1427,6 +1470,16 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                 }
                 hist[q].add(xh, P.n);
             }
+            if (l2) {
+                // L2 distance (Section 5): QP objective a kappa c - 2 (1 - a) x_hat
+                // and Hessian 2 (1 - a) on the integer variables
+                const double a = pow(o.alpha, (double)K);
+                for (int32_t j = 0; j < P.n; ++j) {
+                    chat[c0 + j] = a * kappa[q] * h->hc[c0 + j] - (ii[j] ? 2.0 * (1.0 - a) * xh[j] : 0.0);
+                    qhat[c0 + j] = ii[j] ? 2.0 * (1.0 - a) : 0.0;
+                }
+                return;
+            }
             // L1-distance gradient needs every integer at a bound
             uint8_t *xb = xbits.data() + boff[q];
             memset(xb, 0, boff[q + 1] - boff[q]);
@@ -1441,7 +1494,17 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                                     "of general integers needs auxiliary variables");
         bool any = false;
         for (int32_t q = 0; q < count; ++q) any = any || active[q];
-        if (K < o.rounds && any) {
+        if (K < o.rounds && any && l2) {
+            HIPC(hipMemcpyAsync(h->c64.p, chat.data(), sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+            HIPC(hipMemcpyAsync(h->q64.p, qhat.data(), sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+            if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>(), h->cv.as<float>(), N, h->stream);
+            else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), N, h->stream);
+            cast_q(h);
+            launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
+                              h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
+            HIPC(hipGetLastError());
+            HIPC(hipStreamSynchronize(h->stream));
+        } else if (K < o.rounds && any) {
             const double a = pow(o.alpha, (double)K);
             HIPC(hipMemcpyAsync(h->bits_tmp.p, xbits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
             for (int32_t q = 0; q < count; ++q) {
@@ -1592,6 +1655,29 @@ int scylla_batch_set_objective(scylla_batch *h, int32_t inst, const double *c_ha
         else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), h->N, h->stream);
         launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
                           h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(h->stream));
+        return 0;
+    });
+}
+
+int scylla_batch_set_quadratic(scylla_batch *h, int32_t inst, const double *q)
+{
+    return guarded([&]() {
+        check_inst(h, inst);
+        const int32_t lo = h->col_off[inst], len = h->col_off[inst + 1] - lo;
+        if (q)
+            for (int32_t j = 0; j < len; ++j)
+                if (!(q[j] >= 0.0) || !isfinite(q[j])) throw_err(-EINVAL, "q must be finite and >= 0");
+        if (!q && !h->has_q) return 0;
+        ensure_q(h);
+        if (q) {
+            HIPC(hipMemcpyAsync(h->q64.as<double>() + lo, q, sizeof(double) * len, hipMemcpyHostToDevice,
+                                h->stream));
+        } else {
+            HIPC(hipMemsetAsync(h->q64.as<double>() + lo, 0, sizeof(double) * len, h->stream));
+        }
+        cast_q(h);
         HIPC(hipGetLastError());
         HIPC(hipStreamSynchronize(h->stream));
         return 0;
@@ -1773,7 +1859,7 @@ int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is
                       double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out)
 {
     return guarded([&]() {
-        PumpOpts o{rounds, false, 0.0, 0.0, 0.0, alpha, 0, false, false, 0, threads};
+        PumpOpts o{rounds, false, 0.0, 0.0, 0.0, alpha, 0, false, false, 0, threads, 1};
         pump_impl(h, p, is_int, o, records, nullptr, nullptr, true);
         if (xhat_out) memcpy(xhat_out, h->pump_best.data(), sizeof(double) * h->N);
         return 0;
@@ -1798,6 +1884,7 @@ int scylla_pump_params_default(scylla_pump_params *o)
     o->perturb = 1;
     o->seed = 0;
     o->threads = 0;
+    o->distance = 1;
     return 0;
 }
 
@@ -1807,8 +1894,9 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
 {
     return guarded([&]() {
         if (!opt) throw_err(-EINVAL, "pump params is NULL");
-        PumpOpts o{opt->rounds, opt->eps_schedule != 0, opt->eps1, opt->beta, opt->eps_floor, opt->alpha,
-                   opt->total_iter_limit, opt->early_exit != 0, opt->perturb != 0, opt->seed, opt->threads};
+        PumpOpts o{opt->rounds,    opt->eps_schedule != 0, opt->eps1,         opt->beta,
+                   opt->eps_floor, opt->alpha,             opt->total_iter_limit, opt->early_exit != 0,
+                   opt->perturb != 0, opt->seed, opt->threads, opt->distance};
         return pump_impl(h, params, is_int, o, records, outcome, x_out, false);
     });
 }

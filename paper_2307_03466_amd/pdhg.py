@@ -27,7 +27,7 @@ EXPORTS = [
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
     "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
-    "scylla_pump_params_default", "scylla_batch_pump_ex",
+    "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
             "scylla_batch_destroy": ([vp], None),
             "scylla_batch_set_objective": ([vp, i32, vp], ctypes.c_int),
             "scylla_batch_set_blend": ([vp, i32, vp, vp, dbl, dbl], ctypes.c_int),
+            "scylla_batch_set_quadratic": ([vp, i32, vp], ctypes.c_int),
             "scylla_batch_set_start": ([vp, i32, vp, vp, dbl], ctypes.c_int),
             "scylla_batch_solve": ([vp, ctypes.POINTER(Params), i32, ctypes.POINTER(Result)], ctypes.c_int),
             "scylla_batch_get_solution": ([vp, i32, vp, vp], ctypes.c_int),
@@ -162,7 +163,7 @@ class PumpParams(ctypes.Structure):
                 ("beta", ctypes.c_double), ("eps_floor", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("total_iter_limit", ctypes.c_int64), ("early_exit", ctypes.c_int32),
                 ("perturb", ctypes.c_int32), ("seed", ctypes.c_uint64), ("threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("distance", ctypes.c_int32)]
 
 
 class PumpOutcome(ctypes.Structure):
@@ -178,7 +179,7 @@ def pump_params(**kw) -> PumpParams:
     o = PumpParams()
     _check(lib().scylla_pump_params_default(ctypes.byref(o)))
     for k, v in kw.items():
-        if not hasattr(o, k) or k == "reserved":
+        if not hasattr(o, k):
             raise TypeError(f"unknown pump parameter {k}")
         setattr(o, k, v)
     return o
@@ -331,6 +332,11 @@ class Batch:
         _check(lib().scylla_batch_pump(self._h, ctypes.byref(p), _ptr(ii), rounds, alpha, threads, recs, _ptr(xh)))
         out = [[recs[k * self.count + q].as_dict() for q in range(self.count)] for k in range(rounds)]
         return out, xh
+
+    def set_quadratic(self, inst: int, q):
+        """Diagonal Hessian (>= 0) of instance `inst`'s objective, or None."""
+        qa = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        _check(lib().scylla_batch_set_quadratic(self._h, inst, _ptr(qa)))
 
     def pump_ex(self, is_int=None, pump: dict | None = None, **kw):
         """Complete Algorithm 1 loop (scylla_batch_pump_ex).  `pump` holds

@@ -216,6 +216,20 @@ def other_workloads(pdhg, instances, args, R):
             pdhg_iterations_total=sum(o["iterations"] for o in outs))
         log(f"w5 complete loop: {out['scylla_loop_64x20k']}")
         b.close()
+    if "6" in sel:  # complete loop with the L2 distance on general integers
+        lps = instances.int_pump_batch(64, 5_000, 10_000)
+        b = pdhg.Batch(lps, precision=pdhg.FP32)
+        t = time.perf_counter()
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=args.pump_rounds, seed=0, distance=2, perturb=0),
+                                   iter_limit=200_000)
+        el = time.perf_counter() - t
+        found = [o for o in outs if o["found_kind"]]
+        out["scylla_loop_l2_general_int_64x5k"] = dict(
+            seconds=round(el, 3), rounds_max=max(o["rounds_run"] for o in outs), found=len(found),
+            mean_found_round=round(sum(o["found_round"] for o in found) / max(1, len(found)), 2),
+            pdhg_iterations_total=sum(o["iterations"] for o in outs))
+        log(f"w6 L2 loop, general integers: {out['scylla_loop_l2_general_int_64x5k']}")
+        b.close()
     return out
 
 
@@ -231,7 +245,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="fp32,fp64", help="paths to run (profiling runs may pick one)")
-    ap.add_argument("--workloads", default="1,3,4,5", help="other workloads to measure ('' for none)")
+    ap.add_argument("--workloads", default="1,3,4,5,6", help="other workloads to measure ('' for none)")
     ap.add_argument("--pump-rounds", type=int, default=20)
     ap.add_argument("--fp64-plain-batch", type=int, default=1)
     ap.add_argument("--calib-copy-mb", type=int, default=0,

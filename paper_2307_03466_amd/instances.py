@@ -238,7 +238,7 @@ def skewed_lp(m: int = 500_000, n: int = 1_000_000, nnz: int = 20_000_000,
 
 # ------------------------------------------------------ cover / knapsack
 def cover_knapsack(m: int, n: Optional[int] = None, seed=None,
-                   name: str = "cover_knapsack") -> LP:
+                   name: str = "cover_knapsack", umax: int = 1) -> LP:
     """Binary MIP relaxation: each column hits U{3..8} distinct rows; each row
     is a covering row (p = 1/2; coefficients 1, A_i x >= 1) or a knapsack row
     (weights U{1..100}, A_i x <= 0.3 * sum_j a_ij); c_j ~ U{1..100};
@@ -275,9 +275,30 @@ def cover_knapsack(m: int, n: Optional[int] = None, seed=None,
     b = np.where(cover, 1.0, 0.3 * rowsum)
     senses = np.where(cover, ord("G"), ord("L")).astype(np.uint8)
     c = rng.integers(1, 101, size=n).astype(np.float64)
+    u = np.ones(n)
+    if umax > 1:  # general integers (int_cover_knapsack)
+        u = rng.integers(2, umax + 1, size=n).astype(np.float64)
+        usum = np.bincount(rows, weights=u[col_idx], minlength=m)
+        wusum = np.bincount(rows, weights=val * u[col_idx], minlength=m)
+        b = np.where(cover, np.maximum(1.0, np.floor(0.3 * usum)), 0.3 * wusum)
     return LP(m=m, n=n, row_ptr=row_ptr, col_idx=col_idx, val=val, c=c, b=b,
-              senses=senses, l=np.zeros(n), u=np.ones(n),
-              is_int=np.ones(n, dtype=np.uint8), x_star=np.full(n, 0.3), name=name)
+              senses=senses, l=np.zeros(n), u=u,
+              is_int=np.ones(n, dtype=np.uint8), x_star=0.3 * u, name=name)
+
+
+def int_cover_knapsack(m: int, n: Optional[int] = None, seed=None, umax: int = 5,
+                       name: str = "int_cover_knapsack") -> LP:
+    """General-integer version of cover_knapsack: x_j in {0..u_j},
+    u_j ~ U{2..umax}; covering rows sum_j x_j >= max(1, floor(0.3 sum_j u_j)),
+    knapsack rows sum_j w_j x_j <= 0.3 sum_j w_j u_j; x = 0.3 u is feasible."""
+    return cover_knapsack(m, n, seed=seed, name=name, umax=umax)
+
+
+def int_pump_batch(count: int = 64, m: int = 5_000, n: int = 10_000, seed=None) -> List[LP]:
+    """Batch of general-integer cover/knapsack instances (L2-distance loop)."""
+    s = config_seed(6) if seed is None else seed
+    kids = np.random.SeedSequence(s).spawn(count)
+    return [int_cover_knapsack(m, n, seed=kids[i], name=f"ipump{i}") for i in range(count)]
 
 
 def set_partition(m: int = 30, n: int = 120, seed=None, name: str = "set_partition") -> LP:

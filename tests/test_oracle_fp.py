@@ -321,3 +321,15 @@ def test_l2_loop_handles_general_integers():
     assert any(r["K"] > 1 for r in recs)
     if kind:
         assert oracle.mip_feasible(lp, point)
+
+
+def test_int_cover_knapsack_planted_point():
+    for seed in range(3):
+        lp = I.int_cover_knapsack(400, seed=seed)
+        assert lp.u.min() >= 2 and lp.u.max() <= 5
+        rows = lp.row_of_entry()
+        ax = np.bincount(rows, weights=lp.val * lp.x_star[lp.col_idx], minlength=lp.m)
+        assert np.all(np.where(lp.senses == ord("G"), ax >= lp.b - 1e-9, ax <= lp.b + 1e-9))
+    # the binary family is unchanged by the general-integer option
+    a, b = I.cover_knapsack(300, seed=5), I.cover_knapsack(300, seed=5, umax=1)
+    assert np.array_equal(a.b, b.b) and np.all(a.u == 1)

@@ -39,10 +39,13 @@ public:
     {
         L_.assign(P.l, P.l + P.n);
         U_.assign(P.u, P.u + P.n);
+        bool all_int = true;
         for (int32_t j = 0; j < P.n; ++j)
             if (is_int_[j]) {
                 if (isfinite(L_[j])) L_[j] = ceil(L_[j] - kIntSlack);
                 if (isfinite(U_[j])) U_[j] = floor(U_[j] + kIntSlack);
+            } else {
+                all_int = false;
             }
         ignored_.assign(P.m, 0);
         in_queue_.assign(P.m, 0);
@@ -50,6 +53,30 @@ public:
         for (int32_t i = 0; i < P.m; ++i) maxlen = std::max<size_t>(maxlen, P.ptr[i + 1] - P.ptr[i]);
         lo_new_.resize(maxlen);
         hi_new_.resize(maxlen);
+        // Fast path: with integer variables, integer coefficients and integer
+        // bounds every activity is an exact sum in double precision, so row
+        // activities can be kept up to date incrementally (equal to a
+        // recomputation bit for bit), and a row whose slack exceeds
+        // max_j |a_ij| (u_j - l_j) can tighten nothing and is skipped.
+        exact_ = all_int;
+        for (int32_t e = P.ptr[0]; e < P.ptr[P.m] && exact_; ++e) {
+            const double c = P.val[e];
+            exact_ = c == floor(c) && fabs(c) < 1e6;
+        }
+        for (int32_t j = 0; j < P.n && exact_; ++j)
+            exact_ = (!isfinite(L_[j]) || fabs(L_[j]) < 1e6) && (!isfinite(U_[j]) || fabs(U_[j]) < 1e6);
+        if (exact_) {
+            act_.resize(P.m);
+            reach_.assign(P.m, 0.0);
+            for (int32_t i = 0; i < P.m; ++i) {
+                act_[i] = activity(i);
+                for (int32_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) {
+                    const int32_t j = P.col[e];
+                    const double r = fabs(P.val[e]) * (U_[j] - L_[j]);
+                    reach_[i] = std::max(reach_[i], isnan(r) ? INFINITY : r);
+                }
+            }
+        }
     }
 
     void run(const double *xref, double *xhat)
@@ -69,7 +96,7 @@ public:
             if (L_[j] == U_[j]) continue;
             double v = ceil(xref[j] - 0.5);  // round half down
             v = std::min(std::max(v, L_[j]), U_[j]);
-            L_[j] = U_[j] = v;
+            set_bounds(j, v, v);
             enqueue_rows_of(j);
             drain();
         }
@@ -80,6 +107,55 @@ public:
     int32_t ignored_rows() const { return (int32_t)std::count(ignored_.begin(), ignored_.end(), (uint8_t)1); }
 
 private:
+    // Contribution of a_ij x_j to the min / max activity of a row.
+    static void contrib(double c, double lo, double hi, double &mn, double &mx, int &mn_inf, int &mx_inf)
+    {
+        const double at_min = c > 0 ? lo : hi, at_max = c > 0 ? hi : lo;
+        mn_inf = isinf(at_min) ? 1 : 0;
+        mx_inf = isinf(at_max) ? 1 : 0;
+        mn = mn_inf ? 0.0 : c * at_min;
+        mx = mx_inf ? 0.0 : c * at_max;
+    }
+
+    // New bounds of x_j; keeps the row activities current on the fast path.
+    void set_bounds(int32_t j, double lo, double hi)
+    {
+        if (exact_) {
+            for (int32_t e = P_.cptr[j]; e < P_.cptr[j + 1]; ++e) {
+                const int32_t i = P_.crow[e];
+                const double c = P_.cval[e];
+                if (c == 0.0) continue;
+                double mn0, mx0, mn1, mx1;
+                int a0, b0, a1, b1;
+                contrib(c, L_[j], U_[j], mn0, mx0, a0, b0);
+                contrib(c, lo, hi, mn1, mx1, a1, b1);
+                Activity &A = act_[i];
+                A.lo += mn1 - mn0;
+                A.hi += mx1 - mx0;
+                A.lo_inf += a1 - a0;
+                A.hi_inf += b1 - b0;
+            }
+        }
+        L_[j] = lo;
+        U_[j] = hi;
+    }
+
+    // Fast path: true when row i can neither tighten a bound nor be ignored.
+    bool idle(int32_t i) const
+    {
+        const Activity &A = act_[i];
+        const char s = P_.sense[i];
+        const double b = P_.b[i];
+        const double margin = 1e-9 * (1.0 + fabs(b) + reach_[i]);
+        if (s == 'G' || s == 'E') {
+            if (A.hi_inf != 0 || !(A.hi - b >= reach_[i] + margin)) return false;
+        }
+        if (s == 'L' || s == 'E') {
+            if (A.lo_inf != 0 || !(b - A.lo >= reach_[i] + margin)) return false;
+        }
+        return true;
+    }
+
     void enqueue_rows_of(int32_t j)
     {
         for (int32_t e = P_.cptr[j]; e < P_.cptr[j + 1]; ++e) {
@@ -128,10 +204,11 @@ private:
     // Returns false if row i must be ignored; otherwise applies its bounds.
     bool propagate_row(int32_t i)
     {
+        if (exact_ && idle(i)) return true;
         const char s = P_.sense[i];
         const double b = P_.b[i];
         const bool ge = s == 'G' || s == 'E', le = s == 'L' || s == 'E';
-        const Activity act = activity(i);
+        const Activity act = exact_ ? act_[i] : activity(i);
         const double tol = kIntSlack * (1.0 + fabs(b));
         if (ge && act.hi_inf == 0 && act.hi < b - tol) return false;
         if (le && act.lo_inf == 0 && act.lo > b + tol) return false;
@@ -175,21 +252,28 @@ private:
             double lo = lo_new_[q], hi = hi_new_[q];
             if (lo > hi) lo = hi;
             bool moved = false;
+            double nl = L_[j], nu = U_[j];
             if (is_int_[j]) {
-                if (lo > L_[j]) { L_[j] = lo; moved = true; }
-                if (hi < U_[j]) { U_[j] = hi; moved = true; }
+                if (lo > nl) { nl = lo; moved = true; }
+                if (hi < nu) { nu = hi; moved = true; }
             } else {
                 const double l0 = L_[j], u0 = U_[j];
-                if (lo > l0 + kContMove * (1.0 + fabs(l0)) || (isinf(l0) && isfinite(lo))) { L_[j] = lo; moved = true; }
-                if (hi < u0 - kContMove * (1.0 + fabs(u0)) || (isinf(u0) && isfinite(hi))) { U_[j] = hi; moved = true; }
+                if (lo > l0 + kContMove * (1.0 + fabs(l0)) || (isinf(l0) && isfinite(lo))) { nl = lo; moved = true; }
+                if (hi < u0 - kContMove * (1.0 + fabs(u0)) || (isinf(u0) && isfinite(hi))) { nu = hi; moved = true; }
             }
-            if (moved) changed_.push_back(j);
+            if (moved) {
+                set_bounds(j, nl, nu);
+                changed_.push_back(j);
+            }
         }
         return true;
     }
 
     const FPProblem &P_;
     const uint8_t *is_int_;
+    bool exact_ = false;
+    std::vector<Activity> act_;   // fast path: current row activities
+    std::vector<double> reach_;   // fast path: max_j |a_ij| (u_j - l_j) at the start
     std::vector<double> L_, U_, lo_new_, hi_new_;
     std::vector<uint8_t> ignored_, in_queue_;
     std::vector<int32_t> queue_, changed_;
@@ -198,17 +282,24 @@ private:
 
 }  // namespace
 
-void build_incidence(FPProblem &P, std::vector<int32_t> &cptr, std::vector<int32_t> &crow)
+void build_incidence(FPProblem &P, std::vector<int32_t> &cptr, std::vector<int32_t> &crow,
+                     std::vector<double> &cval)
 {
     cptr.assign((size_t)P.n + 1, 0);
     for (int32_t e = P.ptr[0]; e < P.ptr[P.m]; ++e) cptr[P.col[e] + 1]++;
     for (int32_t j = 0; j < P.n; ++j) cptr[j + 1] += cptr[j];
     crow.resize(cptr[P.n]);
+    cval.resize(cptr[P.n]);
     std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
     for (int32_t i = 0; i < P.m; ++i)
-        for (int32_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) crow[fill[P.col[e]]++] = i;
+        for (int32_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) {
+            const int32_t k = fill[P.col[e]]++;
+            crow[k] = i;
+            cval[k] = P.val[e];
+        }
     P.cptr = cptr.data();
     P.crow = crow.data();
+    P.cval = cval.data();
 }
 
 bool rows_satisfied(const FPProblem &P, const double *x, double tol)

@@ -19,9 +19,11 @@ struct FPProblem {
     const double *l = nullptr, *u = nullptr;  // [n]
     const int32_t *cptr = nullptr;  // [n + 1]
     const int32_t *crow = nullptr;  // rows of each column, increasing
+    const double *cval = nullptr;   // a_ij of each (column, row) incidence
 };
 
-void build_incidence(FPProblem &P, std::vector<int32_t> &cptr, std::vector<int32_t> &crow);
+void build_incidence(FPProblem &P, std::vector<int32_t> &cptr, std::vector<int32_t> &crow,
+                     std::vector<double> &cval);
 
 // Every row holds at x within tol * (1 + |b_i|).
 bool rows_satisfied(const FPProblem &P, const double *x, double tol);

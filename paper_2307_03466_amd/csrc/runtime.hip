@@ -169,6 +169,7 @@ struct scylla_batch {
     std::vector<char> hsense;
     struct LocalLP {
         std::vector<int32_t> ptr, col, cptr, crow;
+        std::vector<double> cval;
         FPProblem P;
     };
     std::vector<LocalLP> local;  // built on the first pump call
@@ -1202,7 +1203,7 @@ void build_locals(scylla_batch *h)
         P.sense = h->hsense.data() + r0;
         P.l = h->hl.data() + c0;
         P.u = h->hu.data() + c0;
-        build_incidence(P, L.cptr, L.crow);
+        build_incidence(P, L.cptr, L.crow, L.cval);
     }
 }
 
@@ -1835,6 +1836,7 @@ int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const doubl
         for (int32_t j = 0; j < A.n; ++j)
             if (!isfinite(x_ref[j])) throw_err(-EINVAL, "non-finite reference value");
         std::vector<int32_t> ptr(A.m + 1), cptr, crow;
+        std::vector<double> cval;
         for (int32_t i = 0; i <= A.m; ++i) ptr[i] = (int32_t)A.row_ptr[i];
         FPProblem P;
         P.m = A.m;
@@ -1846,7 +1848,7 @@ int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const doubl
         P.sense = lp->senses;
         P.l = lp->l;
         P.u = lp->u;
-        build_incidence(P, cptr, crow);
+        build_incidence(P, cptr, crow, cval);
         std::vector<uint8_t> ii(A.n, 1);
         if (is_int)
             for (int32_t j = 0; j < A.n; ++j) ii[j] = is_int[j] ? 1 : 0;

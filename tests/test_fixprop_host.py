@@ -29,10 +29,27 @@ def _cases():
         lp = I.tiny_lp(rng, 12, 20, bounded=(s % 2 == 0))
         lp.is_int = (rng.random(lp.n) < 0.6).astype(np.uint8)
         out.append(("mixed", lp))
+    # all-integer data: the library's incremental-activity path
+    for s in range(3):
+        out.append(("int_cover_knapsack", I.int_cover_knapsack(300 + 200 * s, seed=300 + s)))
+    for s in range(3):
+        out.append(("set_partition", I.set_partition(30, 90, seed=400 + s)))
+    for s in range(4):
+        lp = I.tiny_lp(rng, 10, 16)
+        lp.is_int = np.ones(lp.n, dtype=np.uint8)
+        lp.l, lp.u = -np.floor(rng.random(lp.n) * 4), np.floor(rng.random(lp.n) * 6)
+        out.append(("int_tiny", lp))
     return out
 
 
-@pytest.mark.parametrize("k", range(16))
+N_CASES = 26
+
+
+def test_case_count():
+    assert len(_cases()) == N_CASES
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
 def test_rounding_bit_identical_to_oracle(k):
     name, lp = _cases()[k]
     rng = np.random.default_rng(k)

@@ -47,9 +47,9 @@ def pass_bytes(info: dict, vb: int):
 
 
 def canonical_bytes(m, n, nnz, fp64=False):
-    """Per-iteration byte model of the survey (BF16 / FP64 values, int32
-    indices): both matrix streams and pointers, per-column and per-row vector
-    traffic, one full gather of each vector."""
+    """Canonical per-iteration byte model (BF16 / FP64 values, int32 indices,
+    independent of the chosen layout): both matrix streams and pointers,
+    per-column and per-row vector traffic, one full gather of each vector."""
     if fp64:
         return 2 * nnz * 12 + 4 * (m + 1) + 4 * (n + 1) + 56 * n + 33 * m + 8 * (m + n)
     return 2 * nnz * 6 + 4 * (m + 1) + 4 * (n + 1) + 28 * n + 17 * m + 4 * (m + n)

@@ -36,7 +36,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scylla_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OPTIMAL, ITERATION_LIMIT, NUMERICAL_ERROR = 1, 2, 4
+OPTIMAL, ITERATION_LIMIT, NUMERICAL_ERROR, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 1, 2, 4, 5, 6
 
 
 def build(force: bool = True) -> str:
@@ -61,7 +61,7 @@ class _Params(ctypes.Structure):
                 ("check_period", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("ruiz_iters", ctypes.c_int32),
                 ("pock_chambolle", ctypes.c_int32), ("omega0", ctypes.c_double),
-                ("adaptive", ctypes.c_int32)]
+                ("adaptive", ctypes.c_int32), ("infeas_tol", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -81,7 +81,7 @@ def _load():
         if not os.path.exists(_LIB):
             build(force=False)
         lib = ctypes.CDLL(_LIB)
-        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_fix_propagate"):
+        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_fix_propagate", "orc_ray"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -152,24 +152,37 @@ def kkt(lp, x, y, c=None, q=None):
 def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 64,
          restarts: bool = True, eta: float = 0.99, x0=None, y0=None, omega0: float = 0.0,
          c=None, ruiz_iters: int = 10, pock_chambolle: bool = True,
-         adaptive: bool = False, q=None) -> PDHGResult:
+         adaptive: bool = False, q=None, infeas_tol: float = 1e-8) -> PDHGResult:
     """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop); with
     `adaptive` the step size follows PDLP's adaptive rule (no retries),
     starting at `eta`.  `q`: diagonal Hessian (>= 0) of a QP objective
-    c^T x + x^T diag(q) x / 2, or None."""
+    c^T x + x^T diag(q) x / 2, or None.  infeas_tol > 0: stop with
+    PRIMAL_INFEASIBLE / DUAL_INFEASIBLE when the moves between two checks
+    certify it to that relative accuracy (0: off)."""
     pin = _Pinned(lp, c, q)
     x = np.empty(lp.n)
     y = np.empty(lp.m)
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
     prm = _Params(tol, iter_limit, check_period, int(restarts), eta, ruiz_iters,
-                  int(pock_chambolle), omega0, int(adaptive))
+                  int(pock_chambolle), omega0, int(adaptive), infeas_tol)
     res = _Result()
     rc = _load().orc_pdhg(ctypes.byref(pin.s), ctypes.byref(prm), _p(x0a), _p(y0a), _p(x), _p(y),
                           ctypes.byref(res))
     assert rc == 0
     return PDHGResult(x, y, res.status, res.iterations, res.restarts, res.rel_kkt, res.rho_p,
                       res.rho_d, res.rho_g, res.pobj, res.dobj, res.omega)
+
+
+def ray(lp, x, y, xp, yp, q=None):
+    """Certificate quantities of the moves d = x - xp, v = y - yp:
+    (rho, dual-ray residual, c^T d, primal-ray violation)."""
+    pin = _Pinned(lp, None, q)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, xp, yp)]
+    out = np.zeros(4)
+    rc = _load().orc_ray(ctypes.byref(pin.s), *[_p(a) for a in arrs], _p(out))
+    assert rc == 0
+    return tuple(out)
 
 
 def fix_propagate(lp, xbar, is_int=None):

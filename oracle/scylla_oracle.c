@@ -41,6 +41,15 @@
  *     three; checked every R iterations, at 0 and at the iteration limit.
  *   - restart when E <= 0.2 E_r, or E <= 0.8 E_r and E > E_prev, or
  *     k - k_r >= 0.36 k; omega <- exp(0.5 ln(|dy|/|dx|) + 0.5 ln omega).
+ *   - infeasibility (after PDLP; the paper has no infeasible relaxations):
+ *     at every check after the first, with d = x - x_prev and v = y - y_prev
+ *     the moves since the previous check, v is a dual ray (primal
+ *     infeasible) when rho = b^T v + sum_j (l_j lam_j^+ + u_j lam_j^-) > 0
+ *     for lam = proj_Lambda(-A^T v) and |A^T v + lam| (+ |v - proj_Y v|) <=
+ *     infeas_tol * rho; d is a primal ray (dual infeasible) when c^T d < 0
+ *     and the violation of A d against the row cones, of d against the
+ *     bounds' recession cone (and |Q d|) is <= infeas_tol * |c^T d|.  The
+ *     optimality test comes first.
  *   - adaptive step size ("update step sizes" in Algorithm 1, after PDLP):
  *     after the k-th iteration (k counted from 1 over the whole call), with
  *     dx = x+ - x and dy = y+ - y in the preconditioned metric,
@@ -79,9 +88,11 @@ typedef struct {
     int32_t pock_chambolle; /* 1: one Pock-Chambolle round after Ruiz */
     double omega0;       /* > 0: use as primal weight, else from norms */
     int32_t adaptive;    /* 1: adaptive step size (PDLP's rule, no retry) */
+    double infeas_tol;   /* > 0: infeasibility certificates at the checks */
 } orc_params;
 
-enum { ORC_OPTIMAL = 1, ORC_ITERATION_LIMIT = 2, ORC_NUMERICAL_ERROR = 4 };
+enum { ORC_OPTIMAL = 1, ORC_ITERATION_LIMIT = 2, ORC_NUMERICAL_ERROR = 4, ORC_PRIMAL_INFEASIBLE = 5,
+       ORC_DUAL_INFEASIBLE = 6 };
 
 typedef struct {
     int32_t status;
@@ -254,6 +265,62 @@ int orc_kkt(const orc_lp *lp, const double *x, const double *y, double *out)
  * Every R iterations (and at k = 0 and k = iter_limit) the KKT test decides
  * termination and, if enabled, a restart to the current point.
  */
+/* Certificate quantities of the moves d = x - xp, v = y - yp (see the
+ * infeasibility reading above): out = {rho, dual-ray residual, c^T d,
+ * primal-ray violation}. */
+int orc_ray(const orc_lp *lp, const double *x, const double *y, const double *xp, const double *yp,
+            double *out)
+{
+    const int32_t m = lp->m, n = lp->n;
+    double *d = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *v = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *ad = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *atv = malloc(sizeof(double) * (n > 0 ? n : 1));
+    if (!d || !v || !ad || !atv) { free(d); free(v); free(ad); free(atv); return -1; }
+    for (int32_t j = 0; j < n; ++j) d[j] = x[j] - xp[j];
+    for (int32_t i = 0; i < m; ++i) v[i] = y[i] - yp[i];
+    mul_A(lp, d, ad);
+    mul_At(lp, v, atv);
+    double rho = 0.0, rd2 = 0.0, cd = 0.0, pv2 = 0.0;
+    for (int32_t i = 0; i < m; ++i) {
+        const double vp = proj_dual(v[i], lp->sense[i]);
+        rho += lp->b[i] * v[i];
+        rd2 += (v[i] - vp) * (v[i] - vp);
+        double viol;  /* A d against the row's recession cone */
+        if (lp->sense[i] == 'G') viol = fmax(-ad[i], 0.0);
+        else if (lp->sense[i] == 'L') viol = fmax(ad[i], 0.0);
+        else viol = ad[i];
+        pv2 += viol * viol;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        const int lf = isfinite(lp->l[j]), uf = isfinite(lp->u[j]);
+        const double g = -atv[j];
+        double lam;
+        if (lf && uf) lam = g;
+        else if (lf) lam = fmax(g, 0.0);
+        else if (uf) lam = fmin(g, 0.0);
+        else lam = 0.0;
+        const double r = atv[j] + lam;
+        rd2 += r * r;
+        if (lf && lam > 0.0) rho += lp->l[j] * lam;
+        if (uf && lam < 0.0) rho += lp->u[j] * lam;
+        cd += lp->c[j] * d[j];
+        double bv;  /* d against the bounds' recession cone */
+        if (lf && uf) bv = d[j];
+        else if (lf) bv = fmin(d[j], 0.0);
+        else if (uf) bv = fmax(d[j], 0.0);
+        else bv = 0.0;
+        pv2 += bv * bv;
+        if (lp->q) pv2 += (lp->q[j] * d[j]) * (lp->q[j] * d[j]);
+    }
+    out[0] = rho;
+    out[1] = sqrt(rd2);
+    out[2] = cd;
+    out[3] = sqrt(pv2);
+    free(d); free(v); free(ad); free(atv);
+    return 0;
+}
+
 int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const double *y0,
              double *x, double *y, orc_result *res)
 {
@@ -270,8 +337,13 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     double *yn = malloc(sizeof(double) * (m > 0 ? m : 1));
     double *dxv = malloc(sizeof(double) * (n > 0 ? n : 1));
     double *adx = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *xp = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *yp = malloc(sizeof(double) * (m > 0 ? m : 1));
     int rc = 0;
-    if (!dr || !dc || !xn || !xbar || !aty || !axb || !xr || !yr || !yn || !dxv || !adx) { rc = -1; goto done; }
+    if (!dr || !dc || !xn || !xbar || !aty || !axb || !xr || !yr || !yn || !dxv || !adx || !xp || !yp) {
+        rc = -1;
+        goto done;
+    }
     orc_precondition(lp, p->ruiz_iters, p->pock_chambolle, dr, dc);
 
     /* start point: projection of the warm start (or of 0) */
@@ -303,6 +375,14 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
             double E = kkt[0];
             if (!isfinite(E)) { res->status = ORC_NUMERICAL_ERROR; break; }
             if (E <= p->tol) { res->status = ORC_OPTIMAL; break; }
+            if (p->infeas_tol > 0.0 && k > 0) {
+                double ray[4];
+                orc_ray(lp, x, y, xp, yp, ray);
+                if (ray[0] > 0.0 && ray[1] <= p->infeas_tol * ray[0]) { res->status = ORC_PRIMAL_INFEASIBLE; break; }
+                if (ray[2] < 0.0 && ray[3] <= -p->infeas_tol * ray[2]) { res->status = ORC_DUAL_INFEASIBLE; break; }
+            }
+            memcpy(xp, x, sizeof(double) * n);
+            memcpy(yp, y, sizeof(double) * m);
             if (k >= p->iter_limit) { res->status = ORC_ITERATION_LIMIT; break; }
             if (k == 0) {
                 Er = E;
@@ -397,7 +477,7 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     res->omega = omega;
 done:
     free(dr); free(dc); free(xn); free(xbar); free(aty); free(axb); free(xr); free(yr);
-    free(yn); free(dxv); free(adx);
+    free(yn); free(dxv); free(adx); free(xp); free(yp);
     return rc;
 }
 

@@ -381,3 +381,104 @@ def test_qp_kkt_matches_independent_evaluator(seed):
     w = oracle.pdhg(lp, tol=-1.0, iter_limit=50)
     np.testing.assert_array_equal(z.x, w.x)
     np.testing.assert_array_equal(z.y, w.y)
+
+
+# ----------------------------------------------- infeasibility certificates
+def _highs_status(lp):
+    import scipy.sparse as sps
+    from scipy.optimize import linprog
+    A = sps.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+    s = lp.senses
+    G, L, E = A[s == ord("G")], A[s == ord("L")], A[s == ord("E")]
+    kw = {}
+    Aub = sps.vstack([-G, L]).tocsr()
+    if Aub.shape[0]:
+        kw.update(A_ub=Aub, b_ub=np.concatenate([-lp.b[s == ord("G")], lp.b[s == ord("L")]]))
+    if E.shape[0]:
+        kw.update(A_eq=E, b_eq=lp.b[s == ord("E")])
+    bounds = [(None if np.isinf(a) else a, None if np.isinf(b_) else b_) for a, b_ in zip(lp.l, lp.u)]
+    return linprog(lp.c, bounds=bounds, method="highs", **kw).status  # 2 infeasible, 3 unbounded
+
+
+def _infeasible(seed):
+    """A feasible cover/knapsack LP plus a row that contradicts two of its
+    knapsack-free covering rows' bounds: sum of a few x_j <= -1 with x >= 0."""
+    rng = np.random.default_rng(seed)
+    lp = I.cover_knapsack(60 + 20 * seed, seed=seed)
+    A = dense(lp)
+    cols = rng.choice(lp.n, size=4, replace=False)
+    row = np.zeros(lp.n)
+    row[cols] = 1.0
+    return lp_from_dense(np.vstack([A, row]), np.append(lp.b, -1.0), bytes(lp.senses).decode() + "L",
+                         lp.c, lp.l, lp.u)
+
+
+def _unbounded(seed):
+    """A bounded general LP with one column freed upward whose cost is
+    negative and whose rows it only loosens (>= rows with positive or <=
+    rows with negative coefficients, none in equalities)."""
+    rng = np.random.default_rng(seed)
+    lp = I.tiny_lp(rng, 6, 10)
+    A = dense(lp)
+    j = 0
+    for i, sn in enumerate(lp.senses):
+        if sn == ord("E"):
+            A[i, j] = 0.0
+        elif sn == ord("G"):
+            A[i, j] = abs(A[i, j])
+        else:
+            A[i, j] = -abs(A[i, j])
+    c = lp.c.copy()
+    c[j] = -1.0 - abs(c[j])
+    u = lp.u.copy()
+    u[j] = np.inf
+    return lp_from_dense(A, lp.b, bytes(lp.senses).decode(), c, lp.l, u)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_primal_infeasible_detected_as_highs(seed):
+    lp = _infeasible(seed)
+    assert _highs_status(lp) == 2
+    r = oracle.pdhg(lp, tol=1e-6, iter_limit=500_000)
+    assert r.status == oracle.PRIMAL_INFEASIBLE, (r.status, r.iterations)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dual_infeasible_detected_as_highs(seed):
+    lp = _unbounded(seed)
+    if _highs_status(lp) != 3:
+        pytest.skip("construction left the LP bounded or infeasible")
+    r = oracle.pdhg(lp, tol=1e-6, iter_limit=500_000)
+    assert r.status == oracle.DUAL_INFEASIBLE, (r.status, r.iterations)
+
+
+def test_ray_quantities_match_definitions():
+    """orc_ray against a numpy restatement on random moves (mixed bounds and
+    senses): Farkas residual and ray objective, primal-ray violation."""
+    rng = np.random.default_rng(7)
+    lp = I.tiny_lp(rng, 7, 11, bounded=False)
+    A = dense(lp)
+    x, xp = rng.normal(size=lp.n), rng.normal(size=lp.n)
+    y, yp = rng.normal(size=lp.m), rng.normal(size=lp.m)
+    got = oracle.ray(lp, x, y, xp, yp)
+    d, v = x - xp, y - yp
+    s = lp.senses
+    vp = np.where(s == ord("G"), np.maximum(v, 0), np.where(s == ord("L"), np.minimum(v, 0), v))
+    w = A.T @ v
+    lf, uf = np.isfinite(lp.l), np.isfinite(lp.u)
+    lam = np.where(lf & uf, -w, np.where(lf, np.maximum(-w, 0), np.where(uf, np.minimum(-w, 0), 0.0)))
+    lfin, ufin = np.where(lf, lp.l, 0.0), np.where(uf, lp.u, 0.0)
+    rho = lp.b @ v + np.sum(np.where(lf & (lam > 0), lfin * lam, 0.0)) \
+        + np.sum(np.where(uf & (lam < 0), ufin * lam, 0.0))
+    res = np.sqrt(np.sum((w + lam) ** 2) + np.sum((v - vp) ** 2))
+    ad = A @ d
+    rv = np.where(s == ord("G"), np.maximum(-ad, 0), np.where(s == ord("L"), np.maximum(ad, 0), ad))
+    bv = np.where(lf & uf, d, np.where(lf, np.minimum(d, 0), np.where(uf, np.maximum(d, 0), 0.0)))
+    want = (rho, res, lp.c @ d, np.sqrt(rv @ rv + bv @ bv))
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+def test_infeasibility_detection_can_be_switched_off():
+    lp = _infeasible(0)
+    r = oracle.pdhg(lp, tol=1e-6, iter_limit=2000, infeas_tol=0.0)
+    assert r.status == oracle.ITERATION_LIMIT

@@ -100,6 +100,20 @@ typedef struct {
                              eta is sensitive to rounding: the iterates
                              follow other roundings of the same method to
                              about 1e-5, not to the last bits            */
+    double infeas_tol;    /* > 0 (1e-8): at every check after the first,
+                             the moves d = x - x_prev, v = y - y_prev since
+                             the previous check end the solve with
+                             SCYLLA_PRIMAL_INFEASIBLE when v is a dual ray:
+                             rho = b^T v + sum (l lam+ + u lam-) > 0 for
+                             lam = proj(-A^T v) onto the bounds' multiplier
+                             cones and sqrt(|A^T v + lam|^2 + |v - proj_Y
+                             v|^2) <= infeas_tol * rho; with
+                             SCYLLA_DUAL_INFEASIBLE when d is a primal ray:
+                             c^T d < 0 and the violation of A d against the
+                             row cones and of d against the bounds'
+                             recession cone (and |Q d|) <= infeas_tol
+                             |c^T d| (PDLP's certificates).  0 = off.  The
+                             optimality test comes first.                 */
 } scylla_params;
 
 enum {
@@ -107,7 +121,9 @@ enum {
     SCYLLA_OPTIMAL = 1,          /* relative KKT <= tol                     */
     SCYLLA_ITERATION_LIMIT = 2,  /* iter_limit reached                      */
     SCYLLA_TIME_LIMIT = 3,       /* time_limit_s reached                    */
-    SCYLLA_NUMERICAL_ERROR = 4   /* a residual or gap norm is not finite    */
+    SCYLLA_NUMERICAL_ERROR = 4,  /* a residual or gap norm is not finite    */
+    SCYLLA_PRIMAL_INFEASIBLE = 5,/* dual ray found (see infeas_tol)         */
+    SCYLLA_DUAL_INFEASIBLE = 6   /* primal ray found: unbounded if feasible */
 };
 
 /* Result of one LP solve.  rel_kkt = max(rho_primal, rho_dual, rho_gap):

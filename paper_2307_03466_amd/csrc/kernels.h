@@ -73,6 +73,11 @@ struct PassArgs {
     // null: x+ = proj((x + t D_c^2 (A^T y - c)) / (1 + t D_c^2 q))
     const V *q;
     const double *q64;
+    // check: the point of the previous check (y / x) and its product (A x /
+    // A^T y, FP64); the check reads them for the infeasibility terms and
+    // replaces them by the current ones
+    V *own_prev;
+    double *prod_prev;
 };
 
 // Step-size update after iteration jw of the window, one workgroup per
@@ -101,6 +106,8 @@ struct TinyArgs {
     const double *c64, *l64, *u64, *b64, *dr64, *dc64;
     const V *q;           // diagonal Hessian or null
     const double *q64;
+    V *xp, *yp;           // point of the previous check
+    double *axp, *atyp;   // its products A x, A^T y
     InstState *st;
     const InstInfo *info;
     int32_t adapt;  // adaptive step sizes

@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int 
 //   col j : q0 = r_d,j^2, q1 = c_j x_j, q2 = l_j max(lam_j,0) + u_j min(lam_j,0),
 //           q3 = ((x_j - xr_j) / d_c,j)^2
 template <class V>
-__device__ __forceinline__ void row_terms(const PassArgs<V> &p, int i, double ax, double q[4])
+__device__ __forceinline__ void row_terms(const PassArgs<V> &p, int i, double ax, double q[CHK])
 {
     const double b = p.rhs64[i];
     const uint8_t sn = p.sense[i];
@@ -579,10 +579,20 @@ __device__ __forceinline__ void row_terms(const PassArgs<V> &p, int i, double ax
     q[0] += r * r;
     q[1] += b * y;
     q[2] += dy * dy;
+    // moves since the previous check: v = y - y_prev, A d = A x - (A x)_prev
+    const double v = y - (double)p.own_prev[i];
+    const double vp = sn == 'G' ? fmax(v, 0.0) : (sn == 'L' ? fmin(v, 0.0) : v);
+    const double ad = ax - p.prod_prev[i];
+    const double viol = sn == 'G' ? fmax(-ad, 0.0) : (sn == 'L' ? fmax(ad, 0.0) : ad);
+    q[4] += b * v;
+    q[5] += (v - vp) * (v - vp);
+    q[6] += viol * viol;
+    p.own_prev[i] = p.own[i];
+    p.prod_prev[i] = ax;
 }
 
 template <class V>
-__device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double aty, double q[4])
+__device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double aty, double q[CHK])
 {
     // with a diagonal Hessian: reduced cost c + Q x - A^T y, primal objective
     // + x^T Q x / 2, dual objective - x^T Q x / 2 (kept with the bound terms)
@@ -604,6 +614,27 @@ __device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double at
     if (uf && lam < 0.0) q[2] += u * lam;
     q[2] -= 0.5 * qx * x;
     q[3] += dx * dx;
+    // moves since the previous check: A^T v = A^T y - (A^T y)_prev, d = x - x_prev
+    const double w = aty - p.prod_prev[j];
+    double rl;
+    if (lf && uf) rl = -w;
+    else if (lf) rl = fmax(-w, 0.0);
+    else if (uf) rl = fmin(-w, 0.0);
+    else rl = 0.0;
+    q[4] += (w + rl) * (w + rl);
+    if (lf && rl > 0.0) q[5] += l * rl;
+    if (uf && rl < 0.0) q[5] += u * rl;
+    const double d = x - (double)p.own_prev[j];
+    q[6] += p.rhs64[j] * d;
+    double bv;
+    if (lf && uf) bv = d;
+    else if (lf) bv = fmin(d, 0.0);
+    else if (uf) bv = fmax(d, 0.0);
+    else bv = 0.0;
+    q[7] += bv * bv;
+    if (p.q64) q[7] += (p.q64[j] * d) * (p.q64[j] * d);
+    p.own_prev[j] = p.own[j];
+    p.prod_prev[j] = aty;
 }
 
 template <class V, int FMT, int DIR, int NT, int EPT>
@@ -636,7 +667,7 @@ __global__ __launch_bounds__(NT) void k_check(const PassArgs<V> p)
         s = block_sum<double, NT>(s, red);
         if (tid == 0) {
             p.seg64[T.w] = s;
-            for (int k = 0; k < 4; ++k) p.part[4 * t + k] = 0.0;
+            for (int k = 0; k < CHK; ++k) p.part[CHK * t + k] = 0.0;
         }
         return;
     }
@@ -644,7 +675,7 @@ __global__ __launch_bounds__(NT) void k_check(const PassArgs<V> p)
     int L = 1;
     while (L < 64 && nrows * (L << 1) <= NT) L <<= 1;
     const int groups = NT / L, lane = tid & (L - 1);
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    double q[CHK] = {};
     for (int r = tid / L; r < nrows; r += groups) {
         const int rb = p.M.ptr[r0 + r] - e0, re = p.M.ptr[r0 + r + 1] - e0;
         double s = 0;
@@ -660,10 +691,10 @@ __global__ __launch_bounds__(NT) void k_check(const PassArgs<V> p)
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < CHK; ++k) {
         __syncthreads();
         const double v = block_sum<double, NT>(q[k], red);
-        if (tid == 0) p.part[4 * t + k] = v;
+        if (tid == 0) p.part[CHK * t + k] = v;
     }
 }
 
@@ -677,14 +708,14 @@ __global__ __launch_bounds__(256) void k_combine_check(const PassArgs<V> p)
     if (S.status != ST_RUN) return;
     double s = 0;
     for (int k = 0; k < L.z; ++k) s += p.seg64[L.y + k];
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    double q[CHK] = {};
     if (DIR == DIR_COL) {
         col_terms(p, L.x, s, q);
     } else {
         row_terms(p, L.x, s, q);
         if (p.adapt) p.ax[L.x] = (V)s;
     }
-    for (int k = 0; k < 4; ++k) p.lpart[4 * qi + k] = q[k];
+    for (int k = 0; k < CHK; ++k) p.lpart[CHK * qi + k] = q[k];
 }
 
 // Check combine of a blocked orientation: FP64 row sums from the block
@@ -698,7 +729,7 @@ __global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
     const InstState &S = p.st[T.z];
     if (S.status != ST_RUN) return;
     const int i = T.x + threadIdx.x;
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    double q[CHK] = {};
     if (i < T.y) {
         double s = 0;
         for (int b = 0; b < p.B; ++b) s += p.P64[(size_t)b * p.rows + i];
@@ -710,18 +741,22 @@ __global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < CHK; ++k) {
         __syncthreads();
         const double v = block_sum<double, 256>(q[k], red);
-        if (threadIdx.x == 0) p.part[4 * ct + k] = v;
+        if (threadIdx.x == 0) p.part[CHK * ct + k] = v;
     }
 }
 
 // ------------------------------------------------------------- decision
-// Termination test (Section 2.2), restart rule and primal-weight update in
-// FP64 for one instance, from the check window's reduced sums
-// tot = {||r_p||^2, b^T y, ||dy~||^2, ||r_d||^2, c^T x, bound terms, ||dx~||^2}.
-__device__ void decide_state(InstState &S, const double tot[7], int R)
+// Termination test (Section 2.2), infeasibility certificates, restart rule
+// and primal-weight update in FP64 for one instance, from the check window's
+// reduced sums tot = {||r_p||^2, b^T y, ||dy~||^2, ||r_d||^2, c^T x, bound
+// terms, ||dx~||^2, b^T v, |v - proj_Y v|^2, |row violation of A d|^2,
+// |A^T v + lam|^2, ray bound terms, c^T d, |bound violation of d|^2}.
+constexpr int NTOT = 14;
+
+__device__ void decide_state(InstState &S, const double tot[NTOT], int R)
 {
     const int64_t k = S.k + S.nrun;
     S.k = k;
@@ -741,6 +776,14 @@ __device__ void decide_state(InstState &S, const double tot[7], int R)
     S.rel = E;
     if (!isfinite(E)) { S.status = ST_NUM; return; }
     if (E <= S.tol) { S.status = ST_OPT; return; }
+    if (S.infeas_tol > 0.0 && k > 0) {
+        // a dual ray certifies primal infeasibility, a primal ray dual
+        // infeasibility (moves since the previous check)
+        const double rho = tot[7] + tot[11], rres = sqrt(tot[8] + tot[10]);
+        if (rho > 0.0 && rres <= S.infeas_tol * rho) { S.status = ST_PINF; return; }
+        const double cd = tot[12], pviol = sqrt(tot[9] + tot[13]);
+        if (cd < 0.0 && pviol <= -S.infeas_tol * cd) { S.status = ST_DINF; return; }
+    }
     if (k >= S.k_limit) { S.status = ST_ITER; return; }
     if (S.force_stop) { S.status = ST_TIME; return; }
     if (k == 0) {
@@ -779,18 +822,23 @@ __global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
     if (S.status != ST_RUN) return;
     const InstInfo I = d.info[inst];
     __shared__ double red[4];
-    // q: 0 rp2, 1 by, 2 dy2 (rows); 3 rd2, 4 cx, 5 bound, 6 dx2 (columns)
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int t = I.rt0 + threadIdx.x; t < I.rt1; t += 256)
-        for (int k = 0; k < 3; ++k) acc[k] += d.rpart[4 * t + k];
-    for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256)
-        for (int k = 0; k < 3; ++k) acc[k] += d.lrpart[4 * t + k];
-    for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256)
-        for (int k = 0; k < 4; ++k) acc[3 + k] += d.cpart[4 * t + k];
-    for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256)
-        for (int k = 0; k < 4; ++k) acc[3 + k] += d.lcpart[4 * t + k];
-    double tot[7];
-    for (int k = 0; k < 7; ++k) {
+    // tot layout as in decide_state: rows {0, 1, 2} and {7, 8, 9}, columns
+    // {3, 4, 5, 6} and {10, 11, 12, 13}
+    double acc[NTOT] = {};
+    auto row_add = [&](const double *q) {
+        for (int k = 0; k < 3; ++k) acc[k] += q[k];
+        for (int k = 0; k < 3; ++k) acc[7 + k] += q[4 + k];
+    };
+    auto col_add = [&](const double *q) {
+        for (int k = 0; k < 4; ++k) acc[3 + k] += q[k];
+        for (int k = 0; k < 4; ++k) acc[10 + k] += q[4 + k];
+    };
+    for (int t = I.rt0 + threadIdx.x; t < I.rt1; t += 256) row_add(d.rpart + CHK * t);
+    for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256) row_add(d.lrpart + CHK * t);
+    for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256) col_add(d.cpart + CHK * t);
+    for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256) col_add(d.lcpart + CHK * t);
+    double tot[NTOT];
+    for (int k = 0; k < NTOT; ++k) {
         __syncthreads();
         tot[k] = block_sum<double, 256>(acc[k], red);
     }
@@ -960,7 +1008,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
     }
     __syncthreads();
     // ---- FP64 KKT check of the current point (Section 2.2)
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[NTOT] = {};
     for (int i = tid; i < m; i += NT) {
         double ax = 0.0;
         for (int e = L.rptr[i]; e < L.rptr[i + 1]; ++e) ax += (double)L.rval[e] * (double)L.x[L.rcol[e]];
@@ -976,6 +1024,17 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         acc[0] += r * r;
         acc[1] += bb * yy;
         acc[2] += dy * dy;
+        // moves since the previous check (infeasibility certificates)
+        const int gi = I.row0 + i;
+        const double v = yy - (double)a.yp[gi];
+        const double vp = sn == 'G' ? fmax(v, 0.0) : (sn == 'L' ? fmin(v, 0.0) : v);
+        const double ad = ax - a.axp[gi];
+        const double viol = sn == 'G' ? fmax(-ad, 0.0) : (sn == 'L' ? fmax(ad, 0.0) : ad);
+        acc[7] += bb * v;
+        acc[8] += (v - vp) * (v - vp);
+        acc[9] += viol * viol;
+        a.yp[gi] = L.y[i];
+        a.axp[gi] = ax;
     }
     for (int j = tid; j < n; j += NT) {
         double aty = 0.0;
@@ -999,9 +1058,29 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         if (uf && lam < 0.0) acc[5] += hi * lam;
         acc[5] -= 0.5 * qx * xq;
         acc[6] += dx * dx;
+        const double w = aty - a.atyp[g];
+        double rl;
+        if (lf && uf) rl = -w;
+        else if (lf) rl = fmax(-w, 0.0);
+        else if (uf) rl = fmin(-w, 0.0);
+        else rl = 0.0;
+        acc[10] += (w + rl) * (w + rl);
+        if (lf && rl > 0.0) acc[11] += lo * rl;
+        if (uf && rl < 0.0) acc[11] += hi * rl;
+        const double d = xq - (double)a.xp[g];
+        acc[12] += cc * d;
+        double bv;
+        if (lf && uf) bv = d;
+        else if (lf) bv = fmin(d, 0.0);
+        else if (uf) bv = fmax(d, 0.0);
+        else bv = 0.0;
+        acc[13] += bv * bv;
+        if (a.q64) acc[13] += (a.q64[g] * d) * (a.q64[g] * d);
+        a.xp[g] = L.x[j];
+        a.atyp[g] = aty;
     }
-    double tot[7];
-    for (int k = 0; k < 7; ++k) {
+    double tot[NTOT];
+    for (int k = 0; k < NTOT; ++k) {
         __syncthreads();
         tot[k] = block_sum<double, NT>(acc[k], red);
     }

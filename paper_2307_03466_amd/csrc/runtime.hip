@@ -152,6 +152,7 @@ struct scylla_batch {
     DevMem st, info;
     DevMem ax;              // running A x of the row pass (adaptive steps)
     DevMem q64, qv;         // diagonal Hessian (QP objectives), once set
+    DevMem xp, yp, axp, atyp;  // previous check's point and products
     bool has_q = false;
     bool adaptive = false;  // adaptive step sizes in the current graph
     DevMem bits_tmp, ibits_tmp;
@@ -234,6 +235,8 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     p.nctiles = o.blocked ? (int32_t)(o.bplan.ctiles.size() / 4) : 0;
     p.adapt = h->adaptive ? 1 : 0;
     p.ax = h->ax.as<V>();
+    p.own_prev = o.row ? h->yp.as<V>() : h->xp.as<V>();
+    p.prod_prev = o.row ? h->axp.as<double>() : h->atyp.as<double>();
     if (!o.row && h->has_q) {
         p.q = h->qv.as<V>();
         p.q64 = h->q64.as<double>();
@@ -338,8 +341,8 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
         upload(o.ctiles, o.bplan.ctiles, h->stream);
         o.seg.alloc(std::max<size_t>(1, o.bplan.nslots) * vb);
         o.seg64.alloc(std::max<size_t>(1, o.bplan.nslots) * 8);
-        o.part.alloc(std::max<size_t>(1, o.bplan.ctiles.size() / 4) * 4 * 8);
-        o.lpart.alloc(8 * 4);
+        o.part.alloc(std::max<size_t>(1, o.bplan.ctiles.size() / 4) * CHK * 8);
+        o.lpart.alloc(8 * CHK);
     } else {
         o.blocked = false;
         plan_tiles(o.host.ptr, off, chunk, 1024, o.plan);
@@ -347,8 +350,8 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
         upload(o.longs, o.plan.longs, h->stream);
         o.seg.alloc(std::max<size_t>(1, o.plan.nslots) * vb);
         o.seg64.alloc(std::max<size_t>(1, o.plan.nslots) * 8);
-        o.part.alloc(std::max<size_t>(1, o.plan.tiles.size() / 4) * 4 * 8);
-        o.lpart.alloc(std::max<size_t>(1, o.plan.longs.size() / 4) * 4 * 8);
+        o.part.alloc(std::max<size_t>(1, o.plan.tiles.size() / 4) * CHK * 8);
+        o.lpart.alloc(std::max<size_t>(1, o.plan.longs.size() / 4) * CHK * 8);
     }
     ip_layout(o);
     HIPC(hipStreamSynchronize(h->stream));
@@ -603,6 +606,10 @@ TinyArgs<V> tiny_args(scylla_batch *h)
     a.st = h->st.as<InstState>();
     a.info = h->info.as<InstInfo>();
     a.adapt = h->adaptive ? 1 : 0;
+    a.xp = h->xp.as<V>();
+    a.yp = h->yp.as<V>();
+    a.axp = h->axp.as<double>();
+    a.atyp = h->atyp.as<double>();
     if (h->has_q) {
         a.q = h->qv.as<V>();
         a.q64 = h->q64.as<double>();
@@ -935,7 +942,11 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     upload(h->sense, sn, s);
     const size_t vb = sizeof(V);
     for (DevMem *d : {&h->x, &h->xbar, &h->xr, &h->cv, &h->lv, &h->uv, &h->dc2}) d->alloc((size_t)N * vb);
-    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2, &h->ax}) d->alloc((size_t)M * vb);
+    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2, &h->ax, &h->yp}) d->alloc((size_t)M * vb);
+    h->xp.alloc((size_t)std::max(N, 1) * vb);
+    h->axp.alloc((size_t)std::max(M, 1) * 8);
+    h->atyp.alloc((size_t)std::max(N, 1) * 8);
+    for (DevMem *d : {&h->xp, &h->yp, &h->axp, &h->atyp}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
     for (DevMem *d : {&h->x, &h->xbar, &h->xr}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
     for (DevMem *d : {&h->y, &h->yr, &h->ax}) HIPC(hipMemsetAsync(d->p, 0, d->bytes, s));
     launch_cast<V>(h->c64.as<double>(), h->cv.as<V>(), N, s);
@@ -1022,6 +1033,7 @@ int validate_params(const scylla_params *p)
     if (!(p->eta > 0.0 && p->eta < 1.0)) throw_err(-EINVAL, "eta must be in (0, 1)");
     if (p->precision != SCYLLA_FP32 && p->precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
     if (p->adaptive != 0 && p->adaptive != 1) throw_err(-EINVAL, "adaptive must be 0 or 1");
+    if (!(p->infeas_tol >= 0.0) || !isfinite(p->infeas_tol)) throw_err(-EINVAL, "infeas_tol must be finite and >= 0");
     return 0;
 }
 
@@ -1101,6 +1113,7 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
         S.t = p->eta / omega;
         S.s = p->eta * omega;
         S.tol = p->tol;
+        S.infeas_tol = p->infeas_tol;
         S.Er = S.Ep = 0.0;
         S.rel = S.rho_p = S.rho_d = S.rho_g = S.pobj = S.dobj = 0.0;
     }
@@ -1562,6 +1575,7 @@ int scylla_params_default(scylla_params *p)
     p->time_limit_s = 0.0;
     p->fused_window = 1;
     p->adaptive = 0;
+    p->infeas_tol = 1e-8;
     return 0;
 }
 

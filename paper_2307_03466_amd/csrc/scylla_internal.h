@@ -21,7 +21,14 @@ enum Fmt : int32_t {
     FMT_F64 = 3      // int32 index + double value (FP64 path)
 };
 
-enum Status : int32_t { ST_RUN = 0, ST_OPT = 1, ST_ITER = 2, ST_TIME = 3, ST_NUM = 4 };
+enum Status : int32_t { ST_RUN = 0, ST_OPT = 1, ST_ITER = 2, ST_TIME = 3, ST_NUM = 4, ST_PINF = 5, ST_DINF = 6 };
+
+// Doubles per check partial slot: row pass {|r_p|^2, b^T y, |dy~|^2, -,
+// b^T v, |v - proj_Y v|^2, |row violation of A d|^2, -}; column pass
+// {|r_d|^2, c^T x (+ x^T Q x / 2), bound terms (- x^T Q x / 2), |dx~|^2,
+// |A^T v + lam|^2, ray bound terms, c^T d, |bound violation of d|^2 (+ |Q d|^2)}
+// with d, v the moves since the previous check (infeasibility certificates).
+constexpr int CHK = 8;
 
 // Per-instance solver state, resident in device memory and updated only by
 // the decision kernel (one writer per instance).
@@ -45,6 +52,7 @@ struct InstState {
     double rel, rho_p, rho_d, rho_g, pobj, dobj;
     double bnorm, cnorm;  // ||b||_2, ||c_hat||_2 of the instance
     double omega0;        // primal weight from the data (cold start)
+    double infeas_tol;    // > 0: infeasibility certificates at the checks
 };
 
 // Static per-instance ranges in the concatenated arrays.

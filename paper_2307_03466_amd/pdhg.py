@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libscylla_pdhg.so")
 
 FP64, FP32 = 0, 1
-RUNNING, OPTIMAL, ITERATION_LIMIT, TIME_LIMIT, NUMERICAL_ERROR = 0, 1, 2, 3, 4
+RUNNING, OPTIMAL, ITERATION_LIMIT, TIME_LIMIT, NUMERICAL_ERROR, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 0, 1, 2, 3, 4, 5, 6
 FORMATS = {0: "packed-int", 1: "bf16", 2: "fp32", 3: "fp64"}
 
 EXPORTS = [
@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("check_period", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
-                ("fused_window", ctypes.c_int32), ("adaptive", ctypes.c_int32)]
+                ("fused_window", ctypes.c_int32), ("adaptive", ctypes.c_int32),
+                ("infeas_tol", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):

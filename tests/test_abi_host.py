@@ -51,7 +51,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_params_default(L):
     p = pdhg.params()
     assert p.tol == 1e-4 and p.check_period == 64 and p.eta == 0.99 and p.restarts == 1
-    assert p.adaptive == 0 and p.fused_window == 1
+    assert p.adaptive == 0 and p.fused_window == 1 and p.infeas_tol == 1e-8
     assert L.scylla_params_default(None) == EINVAL
 
 
@@ -115,7 +115,8 @@ def test_validation(L, case):
 
 def test_bad_params_rejected(L):
     lp = I.workload(1)
-    for kw in (dict(check_period=0), dict(eta=1.5), dict(iter_limit=-1), dict(precision=7), dict(adaptive=2)):
+    for kw in (dict(check_period=0), dict(eta=1.5), dict(iter_limit=-1), dict(precision=7), dict(adaptive=2),
+               dict(infeas_tol=-1.0), dict(infeas_tol=float("nan"))):
         with pytest.raises(pdhg.ScyllaError) as e:
             pdhg.solve(lp, **kw)
         assert e.value.code == EINVAL

@@ -191,9 +191,15 @@ def other_workloads(pdhg, instances, args, R):
         el = time.perf_counter() - t
         its = [max(r["iterations"] for r in rnd) for rnd in recs]
         solve_s = sum(rnd[0]["solve_seconds"] for rnd in recs)
+        rounding_s = sum(rnd[0]["rounding_seconds"] for rnd in recs)
+        tune_s = sum(rnd[0]["tune_seconds"] for rnd in recs)
+        rounds_s = sum(rnd[0]["round_seconds"] for rnd in recs)
         first = [next((k + 1 for k in range(len(recs)) if recs[k][q]["xhat_feasible"]), None)
                  for q in range(len(lps))]
         out["pump_64x20k"] = dict(rounds=len(recs), seconds=round(el, 3), solve_seconds=round(solve_s, 3),
+                                  rounding_seconds=round(rounding_s, 3), tune_seconds=round(tune_s, 3),
+                                  other_seconds=round(el - solve_s - rounding_s - tune_s, 3),
+                                  outside_rounds_seconds=round(el - rounds_s, 3),
                                   batch_iterations=sum(its),
                                   batch_iter_per_s=round(sum(its) / solve_s, 1),
                                   iterations_round1=its[0], iterations_last=its[-1],

@@ -141,6 +141,8 @@ typedef struct {
     double omega;          /* final primal weight                           */
     double solve_seconds;  /* wall time of the iteration loop               */
     double setup_seconds;  /* handle creation (upload + preconditioning)    */
+    double tune_seconds;   /* pass-layout autotuning done by this call (the
+                              first solve of a handle; 0 afterwards)         */
 } scylla_result;
 
 /* Fills *p with the defaults listed in scylla_params.  Returns 0, or
@@ -286,7 +288,23 @@ typedef struct {
     double xhat_obj;        /* c^T x_hat with the original objective          */
     double solve_seconds;   /* device solve of the round (whole batch)        */
     double round_seconds;   /* whole round: solve, copy-out, rounding, blend  */
+    double tune_seconds;    /* pass-layout autotuning inside the round's
+                               solve (the handle's first solve only)         */
+    double rounding_seconds; /* host rounding of the round (all instances,
+                                thread pool): fix-and-propagate, checks,
+                                history, next objective                      */
 } scylla_pump_record;
+
+/* MIP-feasibility of every instance's current primal iterate x (Algorithm 1
+ * returns the PDHG point itself when it is already feasible for the MIP,
+ * Section 2.1), evaluated on the device: every row holds within
+ * tol (1 + |b_i|) with an FP64 activity sum_j a_ij x_j, every x_j lies within
+ * tol of [l_j, u_j] and every integer x_j within tol of an integer;
+ * a non-finite value fails.  The pump loops make this test every round with
+ * tol = 1e-6.  is_int: [n_total] 0/1 (instance order) or NULL (all
+ * integer); feasible: [count] receives 1 or 0.  Returns 0, -EINVAL (NULL
+ * handle or feasible, tol not finite and > 0) or -EIO (HIP error). */
+int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible);
 
 /* Feasibility-pump-like loop of Algorithm 1 on every instance of the batch,
  * with all `rounds` rounds run: round 1 solves with the original objective

@@ -166,5 +166,13 @@ void launch_project(V *x, const V *l, const V *u, int clo, int chi, V *y, const 
 template <class V>
 void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibits, double a, double kappa,
                   double *c64, V *cv, int lo, int hi, hipStream_t s);
+// MIP-feasibility of x per instance (rows within tol (1 + |b_i|), bounds
+// and integrality within tol): rbad [m], cbad [n] scratch flags,
+// feasible [count] = 1 / 0.
+template <class V>
+void launch_mip_check(const MatView &M, int fmt, int m, int n, int count, const InstInfo *info, const V *x,
+                      const double *b, const uint8_t *sense, const double *l, const double *u,
+                      const uint8_t *is_int, double tol, uint8_t *rbad, uint8_t *cbad, uint8_t *feasible,
+                      hipStream_t s);
 
 }  // namespace scy

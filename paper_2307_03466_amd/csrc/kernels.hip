@@ -1322,6 +1322,64 @@ __global__ void k_blend(const double *c_orig, const uint8_t *xbits, const uint8_
     cv[j] = (V)v;
 }
 
+// ------------------------------------------------ MIP feasibility
+// Algorithm 1 tests the PDHG point itself before rounding it: x is
+// MIP-feasible when every row holds within tol (1 + |b_i|), every x_j lies
+// within tol of [l_j, u_j] and every integer x_j within tol of an integer.
+// Row activities are FP64 sums of a_ij x_j (one wave per row); a
+// non-finite value counts as a violation.  Flags: 1 = violated.
+template <class V, int FMT>
+__global__ __launch_bounds__(256) void k_mip_rows(const MatView M, int rows, const V *__restrict__ x,
+                                                  const double *__restrict__ b, const uint8_t *__restrict__ sense,
+                                                  double tol, uint8_t *__restrict__ bad)
+{
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    const int e1 = M.ptr[row + 1];
+    double acc = 0.0;
+    for (int e = M.ptr[row] + lane; e < e1; e += 64) {
+        uint32_t w;
+        double a;
+        load_entry<FMT, double>(M, e, w, a);
+        const int j = decode_entry<FMT, double>(M, w, a);
+        acc += a * (double)x[j];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) {
+        const double bi = b[row], t = tol * (1.0 + fabs(bi));
+        const uint8_t sn = sense[row];
+        bool ok = isfinite(acc);
+        if (sn != 'L') ok = ok && acc >= bi - t;
+        if (sn != 'G') ok = ok && acc <= bi + t;
+        bad[row] = ok ? 0 : 1;
+    }
+}
+
+template <class V>
+__global__ void k_mip_cols(const V *__restrict__ x, const double *__restrict__ l, const double *__restrict__ u,
+                           const uint8_t *__restrict__ is_int, double tol, int n, uint8_t *__restrict__ bad)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double v = (double)x[j];
+    bool ok = v >= l[j] - tol && v <= u[j] + tol;
+    if (is_int[j]) ok = ok && fabs(v - rint(v)) <= tol;
+    bad[j] = ok ? 0 : 1;
+}
+
+// One workgroup per instance: feasible[inst] = no violated row or column.
+__global__ __launch_bounds__(256) void k_mip_reduce(const InstInfo *__restrict__ info, const uint8_t *__restrict__ rbad,
+                                                    const uint8_t *__restrict__ cbad, uint8_t *__restrict__ feasible)
+{
+    const InstInfo I = info[blockIdx.x];
+    int any = 0;
+    for (int i = I.row0 + threadIdx.x; i < I.row1; i += 256) any |= rbad[i];
+    for (int j = I.col0 + threadIdx.x; j < I.col1; j += 256) any |= cbad[j];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) feasible[blockIdx.x] = any ? 0 : 1;
+}
+
 // ----------------------------------------------------- gather probe
 // Device ceiling of the passes' dominant cost: random 4-byte gathers from a
 // vector of a given size.  Indices are a fixed hash of the position, taken
@@ -1601,6 +1659,29 @@ void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibi
                            kappa, c64, cv, lo, hi);
 }
 
+template <class V>
+void launch_mip_check(const MatView &M, int fmt, int m, int n, int count, const InstInfo *info, const V *x,
+                      const double *b, const uint8_t *sense, const double *l, const double *u,
+                      const uint8_t *is_int, double tol, uint8_t *rbad, uint8_t *cbad, uint8_t *feasible,
+                      hipStream_t s)
+{
+    if (m > 0) {
+        dim3 g((m + 3) / 4), bl(256);
+        if constexpr (sizeof(V) == 8) {
+            hipLaunchKernelGGL((k_mip_rows<V, FMT_F64>), g, bl, 0, s, M, m, x, b, sense, tol, rbad);
+        } else {
+            switch (fmt) {
+            case FMT_PACKED: hipLaunchKernelGGL((k_mip_rows<V, FMT_PACKED>), g, bl, 0, s, M, m, x, b, sense, tol, rbad); break;
+            case FMT_BF16: hipLaunchKernelGGL((k_mip_rows<V, FMT_BF16>), g, bl, 0, s, M, m, x, b, sense, tol, rbad); break;
+            default: hipLaunchKernelGGL((k_mip_rows<V, FMT_F32>), g, bl, 0, s, M, m, x, b, sense, tol, rbad); break;
+            }
+        }
+    }
+    if (n > 0)
+        hipLaunchKernelGGL(k_mip_cols<V>, dim3((n + 255) / 256), dim3(256), 0, s, x, l, u, is_int, tol, n, cbad);
+    if (count > 0) hipLaunchKernelGGL(k_mip_reduce, dim3(count), dim3(256), 0, s, info, rbad, cbad, feasible);
+}
+
 #define SCY_INST(V)                                                                                    \
     template void launch_tiny<V>(const TinyArgs<V> &, int, int, int, size_t, hipStream_t, bool);       \
     template void launch_staged<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
@@ -1611,7 +1692,10 @@ void launch_blend(const double *c_orig, const uint8_t *xbits, const uint8_t *ibi
     template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \
                                     int, hipStream_t);                                                 \
     template void launch_blend<V>(const double *, const uint8_t *, const uint8_t *, double, double,    \
-                                  double *, V *, int, int, hipStream_t);
+                                  double *, V *, int, int, hipStream_t);                               \
+    template void launch_mip_check<V>(const MatView &, int, int, int, int, const InstInfo *, const V *, \
+                                      const double *, const uint8_t *, const double *, const double *, \
+                                      const uint8_t *, double, uint8_t *, uint8_t *, uint8_t *, hipStream_t);
 SCY_INST(float)
 SCY_INST(double)
 

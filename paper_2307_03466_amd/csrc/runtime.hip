@@ -156,6 +156,7 @@ struct scylla_batch {
     bool has_q = false;
     bool adaptive = false;  // adaptive step sizes in the current graph
     DevMem bits_tmp, ibits_tmp;
+    DevMem mip_isint, mip_rbad, mip_cbad, mip_ok;  // MIP-feasibility check
     // graph
     hipGraphExec_t gexec = nullptr;
     int32_t graph_R = 0;
@@ -834,6 +835,9 @@ void autotune(scylla_batch *h)
         return;
     }
     const int epts[3] = {4, 8, 16};
+    // SCYLLA_TUNE_TRACE=1: one line per candidate on stderr (plan time on
+    // the host, measured pass time)
+    const bool trace = getenv("SCYLLA_TUNE_TRACE") != nullptr;
     PassTimer<V> timer(h);
     for (int d = 0; d < 2; ++d) {
         OrientRT &o = d == 0 ? h->orow : h->ocol;
@@ -847,8 +851,13 @@ void autotune(scylla_batch *h)
         }
         for (int B : Bs) {
             for (int ept : epts) {
+                const double tp = now_s();
                 set_plan(h, o, B, ept);
+                const double tt = now_s();
                 const double ms = timer.time(o, 10);
+                if (trace)
+                    fprintf(stderr, "tune %s B=%d ept=%d plan %.1f ms run %.3f ms (timing %.1f ms)\n",
+                            o.row ? "row" : "col", B, ept, (tt - tp) * 1e3, ms, (now_s() - tt) * 1e3);
                 if (ms < best) {
                     best = ms;
                     best_B = B;
@@ -871,9 +880,15 @@ void autotune(scylla_batch *h)
                 for (int slice = 0; slice < (any_slice || half ? 2 : 1); ++slice)
                     for (int var = 0; var < 4; ++var)
                         for (int nnz : {16384, 32768, 65536}) {
+                            const double tp = now_s();
                             set_staged(h, o, best_ept, nnz, var, slice, half);
+                            const double tt = now_s();
                             if (!o.staged || (slice && !o.sliced)) continue;
                             const double ms = timer.time(o, 10);
+                            if (trace)
+                                fprintf(stderr, "tune %s staged half=%d slice=%d var=%d nnz=%d plan %.1f ms run "
+                                        "%.3f ms (timing %.1f ms)\n", o.row ? "row" : "col", half, slice, var, nnz,
+                                        (tt - tp) * 1e3, ms, (now_s() - tt) * 1e3);
                             if (ms < best) {
                                 best = ms;
                                 best_nnz = nnz;
@@ -1086,9 +1101,12 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     if (p->precision != h->precision) throw_err(-EINVAL, "params precision differs from the handle's");
     const bool tiny = h->tiny_ok && p->fused_window != 0;
     h->adaptive = p->adaptive != 0;
+    double tune_s = 0.0;
     if (p->autotune && !h->tuned && !tiny) {
+        const double tt = now_s();
         if (h->vbytes == 4) autotune<float>(h);
         else autotune<double>(h);
+        tune_s = now_s() - tt;
     }
     std::vector<InstState> st;
     read_states(h, st);
@@ -1154,8 +1172,10 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     }
     HIPC(hipStreamSynchronize(h->stream));
     const double solve_s = now_s() - t0;
-    for (int32_t q = 0; q < h->count; ++q)
+    for (int32_t q = 0; q < h->count; ++q) {
         fill_result(h->pinned[(size_t)last_slot * h->count + q], results[q], solve_s, h->setup_seconds);
+        results[q].tune_seconds = tune_s;
+    }
     return 0;
 }
 
@@ -1187,6 +1207,41 @@ void put_range(scylla_batch *h, DevMem &d, int32_t lo, int32_t len, const double
         HIPC(hipMemcpyAsync(d.as<char>() + (size_t)lo * 4, tmp.data(), (size_t)len * 4, hipMemcpyHostToDevice, h->stream));
         HIPC(hipStreamSynchronize(h->stream));
     }
+}
+
+// Integer flags [N] of the MIP-feasibility check (NULL: all integer).
+void set_mip_isint(scylla_batch *h, const uint8_t *is_int)
+{
+    const size_t N = (size_t)std::max(h->N, 1);
+    if (h->mip_isint.bytes < N) h->mip_isint.alloc(N);
+    if (h->mip_rbad.bytes < (size_t)std::max(h->M, 1)) h->mip_rbad.alloc((size_t)std::max(h->M, 1));
+    if (h->mip_cbad.bytes < N) h->mip_cbad.alloc(N);
+    if (h->mip_ok.bytes < (size_t)h->count) h->mip_ok.alloc((size_t)h->count);
+    std::vector<uint8_t> ii(N, 1);
+    if (is_int)
+        for (int32_t j = 0; j < h->N; ++j) ii[j] = is_int[j] ? 1 : 0;
+    HIPC(hipMemcpyAsync(h->mip_isint.p, ii.data(), N, hipMemcpyHostToDevice, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+}
+
+// MIP-feasibility of every instance's current x, on the device (integer
+// flags from set_mip_isint); ok: [count] 1 / 0.
+void mip_check(scylla_batch *h, double tol, uint8_t *ok)
+{
+    const OrientRT &o = h->orow;
+    if (h->vbytes == 4)
+        launch_mip_check<float>(o.mat, h->fmt, h->M, h->N, h->count, h->info.as<InstInfo>(), h->x.as<float>(),
+                                h->b64.as<double>(), h->sense.as<uint8_t>(), h->l64.as<double>(),
+                                h->u64.as<double>(), h->mip_isint.as<uint8_t>(), tol, h->mip_rbad.as<uint8_t>(),
+                                h->mip_cbad.as<uint8_t>(), h->mip_ok.as<uint8_t>(), h->stream);
+    else
+        launch_mip_check<double>(o.mat, h->fmt, h->M, h->N, h->count, h->info.as<InstInfo>(), h->x.as<double>(),
+                                 h->b64.as<double>(), h->sense.as<uint8_t>(), h->l64.as<double>(),
+                                 h->u64.as<double>(), h->mip_isint.as<uint8_t>(), tol, h->mip_rbad.as<uint8_t>(),
+                                 h->mip_cbad.as<uint8_t>(), h->mip_ok.as<uint8_t>(), h->stream);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(ok, h->mip_ok.p, (size_t)h->count, hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
 }
 
 void build_locals(scylla_batch *h)
@@ -1374,6 +1429,8 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     if (h->bits_tmp.bytes < boff[count]) h->bits_tmp.alloc(boff[count]);
     if (h->ibits_tmp.bytes < boff[count]) h->ibits_tmp.alloc(boff[count]);
     HIPC(hipMemcpyAsync(h->ibits_tmp.p, ibits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
+    set_mip_isint(h, isint.data());
+    std::vector<uint8_t> mip_ok(count);
     reset_objective(h);
     HIPC(hipStreamSynchronize(h->stream));
 
@@ -1390,6 +1447,7 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     std::vector<RoundingHistory> hist(o.perturb ? count : 0);
     std::vector<int64_t> limits(count);
     std::vector<scylla_result> res(count);
+    std::vector<FPPrep> prep(count);  // per-instance rounding state, built on first use
     if (rec) memset(rec, 0, sizeof(scylla_pump_record) * (size_t)o.rounds * count);
     double eps = o.eps1;
     for (int32_t K = 1; K <= o.rounds; ++K) {
@@ -1407,9 +1465,11 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
         scylla_params pk = *p;
         if (o.eps_sched) pk.tol = eps;
         batch_solve_impl(h, &pk, K > 1 ? 1 : 0, res.data(), limits.data());
+        mip_check(h, 1e-6, mip_ok.data());
         if (h->vbytes == 4) get_range<float>(h, h->x, 0, N, x.data());
         else get_range<double>(h, h->x, 0, N, x.data());
         std::atomic<int> bad{0}, nonbinary{0};
+        const double tr0 = now_s();
         parallel_for(count, o.threads, [&](int32_t q) {
             if (!active[q]) return;
             const auto &P = h->local[q].P;
@@ -1420,11 +1480,6 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
             scylla_pump_outcome &oc = out[q];
             oc.rounds_run = K;
             oc.iterations += res[q].iterations;
-            bool integral = true;
-            for (int32_t j = 0; j < P.n; ++j) {
-                if (xq[j] < P.l[j] - 1e-6 || xq[j] > P.u[j] + 1e-6) integral = false;
-                if (ii[j] && fabs(xq[j] - round(xq[j])) > 1e-6) integral = false;
-            }
             scylla_pump_record rtmp;
             scylla_pump_record &r = rec ? rec[(size_t)(K - 1) * count + q] : rtmp;
             memset(&r, 0, sizeof(r));
@@ -1433,7 +1488,8 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
             r.iterations = res[q].iterations;
             r.rel_kkt = res[q].rel_kkt;
             r.solve_seconds = res[q].solve_seconds;
-            r.lp_feasible = (integral && rows_satisfied(P, xq, 1e-6)) ? 1 : 0;
+            r.tune_seconds = res[q].tune_seconds;
+            r.lp_feasible = mip_ok[q];
             if (r.lp_feasible && !oc.found_kind) {
                 oc.found_kind = 1;
                 oc.found_round = K;
@@ -1443,7 +1499,8 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                     return;
                 }
             }
-            fix_and_propagate(P, ii, xq, xh, &r.xhat_feasible, &r.ignored_rows);
+            if (!prep[q].ready) fp_prepare(P, ii, prep[q]);
+            fix_and_propagate(P, ii, prep[q], xq, xh, &r.xhat_feasible, &r.ignored_rows);
             double obj = 0.0;
             for (int32_t j = 0; j < P.n; ++j) obj += h->hc[c0 + j] * xh[j];
             r.xhat_obj = obj;
@@ -1503,6 +1560,7 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                 else if (xh[j] != P.l[j]) bad = 1;
             }
         });
+        const double rounding_dt = now_s() - tr0;
         if (nonbinary) throw_err(-EINVAL, "cycle perturbation needs binary integer variables");
         if (bad) throw_err(-EINVAL, "an integer variable is rounded strictly inside its bounds: the L1 distance "
                                     "of general integers needs auxiliary variables");
@@ -1541,7 +1599,10 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
         const double dt = now_s() - t0;
         if (rec)
             for (int32_t q = 0; q < count; ++q)
-                if (rec[(size_t)(K - 1) * count + q].round) rec[(size_t)(K - 1) * count + q].round_seconds = dt;
+                if (rec[(size_t)(K - 1) * count + q].round) {
+                    rec[(size_t)(K - 1) * count + q].round_seconds = dt;
+                    rec[(size_t)(K - 1) * count + q].rounding_seconds = rounding_dt;
+                }
         if (!any) break;
     }
     for (int32_t q = 0; q < count; ++q) {
@@ -1866,7 +1927,22 @@ int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const doubl
         std::vector<uint8_t> ii(A.n, 1);
         if (is_int)
             for (int32_t j = 0; j < A.n; ++j) ii[j] = is_int[j] ? 1 : 0;
-        fix_and_propagate(P, ii.data(), x_ref, x_hat, &info[0], &info[1]);
+        FPPrep prep;
+        fp_prepare(P, ii.data(), prep);
+        fix_and_propagate(P, ii.data(), prep, x_ref, x_hat, &info[0], &info[1]);
+        return 0;
+    });
+}
+
+int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible)
+{
+    return guarded([&]() {
+        if (!h || !feasible) throw_err(-EINVAL, "handle or feasible is NULL");
+        if (!(tol > 0.0) || !isfinite(tol)) throw_err(-EINVAL, "tol must be finite and > 0");
+        set_mip_isint(h, is_int);
+        std::vector<uint8_t> ok(h->count);
+        mip_check(h, tol, ok.data());
+        for (int32_t q = 0; q < h->count; ++q) feasible[q] = ok[q];
         return 0;
     });
 }

@@ -28,6 +28,7 @@ EXPORTS = [
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
     "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
     "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
+    "scylla_batch_mip_feasible",
 ]
 
 
@@ -62,7 +63,8 @@ class Result(ctypes.Structure):
                 ("rho_primal", ctypes.c_double), ("rho_dual", ctypes.c_double),
                 ("rho_gap", ctypes.c_double), ("primal_obj", ctypes.c_double),
                 ("dual_obj", ctypes.c_double), ("omega", ctypes.c_double),
-                ("solve_seconds", ctypes.c_double), ("setup_seconds", ctypes.c_double)]
+                ("solve_seconds", ctypes.c_double), ("setup_seconds", ctypes.c_double),
+                ("tune_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -118,6 +120,7 @@ def lib():
             "scylla_batch_pump": ([vp, ctypes.POINTER(Params), vp, i32, dbl, i32, ctypes.POINTER(PumpRecord), vp],
                                   ctypes.c_int),
             "scylla_pump_params_default": ([ctypes.POINTER(PumpParams)], ctypes.c_int),
+            "scylla_batch_mip_feasible": ([vp, vp, dbl, vp], ctypes.c_int),
             "scylla_batch_pump_ex": ([vp, ctypes.POINTER(Params), vp, ctypes.POINTER(PumpParams),
                                       ctypes.POINTER(PumpRecord), ctypes.POINTER(PumpOutcome), vp], ctypes.c_int),
         }
@@ -153,7 +156,8 @@ class PumpRecord(ctypes.Structure):
                 ("rel_kkt", ctypes.c_double), ("lp_feasible", ctypes.c_int32),
                 ("xhat_feasible", ctypes.c_int32), ("ignored_rows", ctypes.c_int32),
                 ("perturbed", ctypes.c_int32), ("xhat_obj", ctypes.c_double),
-                ("solve_seconds", ctypes.c_double), ("round_seconds", ctypes.c_double)]
+                ("solve_seconds", ctypes.c_double), ("round_seconds", ctypes.c_double),
+                ("tune_seconds", ctypes.c_double), ("rounding_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -333,6 +337,13 @@ class Batch:
         _check(lib().scylla_batch_pump(self._h, ctypes.byref(p), _ptr(ii), rounds, alpha, threads, recs, _ptr(xh)))
         out = [[recs[k * self.count + q].as_dict() for q in range(self.count)] for k in range(rounds)]
         return out, xh
+
+    def mip_feasible(self, is_int=None, tol: float = 1e-6) -> np.ndarray:
+        """Device MIP-feasibility of every instance's current x: [count] 0/1."""
+        ii = None if is_int is None else np.ascontiguousarray(is_int, dtype=np.uint8)
+        out = np.zeros(self.count, dtype=np.int32)
+        _check(lib().scylla_batch_mip_feasible(self._h, _ptr(ii), tol, _ptr(out)))
+        return out
 
     def set_quadratic(self, inst: int, q):
         """Diagonal Hessian (>= 0) of instance `inst`'s objective, or None."""

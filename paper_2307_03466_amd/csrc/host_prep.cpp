@@ -7,11 +7,34 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
+#include <thread>
+#include <vector>
 
 #include "scylla_internal.h"
 
 namespace scy {
+
+// Runs fn(k) for k in [0, n) on up to 16 host threads in contiguous,
+// dynamically handed-out chunks.  Every k writes only its own outputs, so
+// results do not depend on the schedule.
+template <class F>
+static void parallel_chunks(int64_t n, int64_t chunk, F &&fn)
+{
+    if (n <= 0) return;
+    const int64_t nchunks = (n + chunk - 1) / chunk;
+    const int nt = (int)std::min<int64_t>(nchunks, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    std::atomic<int64_t> next{0};
+    auto worker = [&]() {
+        for (int64_t c = next++; c < nchunks; c = next++)
+            for (int64_t k = c * chunk, e = std::min(n, k + chunk); k < e; ++k) fn(k);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
+}
 
 static int fail(std::string &err, const char *fmt, long long a = 0, long long b = 0)
 {
@@ -233,14 +256,15 @@ void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_
     for (int32_t b = 0; b <= B; ++b) out.bounds[b] = (int32_t)(((int64_t)gather_size * b) / B);
     // count nonzeros per (block, row)
     out.bptr.assign((size_t)B * (rows + 1), 0);
-    for (int32_t i = 0; i < rows; ++i) {
+    parallel_chunks(rows, 4096, [&](int64_t k) {
+        const int32_t i = (int32_t)k;
         int32_t b = 0;
         for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e) {
             const int32_t g = entry_index(o, fmt, e);
             while (g >= out.bounds[b + 1]) ++b;
             out.bptr[(size_t)b * (rows + 1) + i + 1]++;
         }
-    }
+    });
     int64_t base = 0;
     for (int32_t b = 0; b < B; ++b) {
         int32_t *p = out.bptr.data() + (size_t)b * (rows + 1);
@@ -252,20 +276,22 @@ void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_
     if (fmt == FMT_BF16) out.v16.resize(nnz);
     if (fmt == FMT_F32) out.v32.resize(nnz);
     if (fmt == FMT_F64) out.v64.resize(nnz);
-    std::vector<int32_t> fill(B);
-    for (int32_t i = 0; i < rows; ++i) {
-        for (int32_t b = 0; b < B; ++b) fill[b] = out.bptr[(size_t)b * (rows + 1) + i];
-        int32_t b = 0;
+    parallel_chunks(rows, 4096, [&](int64_t k) {
+        const int32_t i = (int32_t)k;
+        int32_t b = 0, pos = out.bptr[i];
         for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e) {
             const int32_t g = entry_index(o, fmt, e);
-            while (g >= out.bounds[b + 1]) ++b;
-            const int32_t pos = fill[b]++;
+            if (g >= out.bounds[b + 1]) {
+                while (g >= out.bounds[b + 1]) ++b;
+                pos = out.bptr[(size_t)b * (rows + 1) + i];
+            }
             out.ent[pos] = o.ent[e];
             if (fmt == FMT_BF16) out.v16[pos] = o.v16[e];
             if (fmt == FMT_F32) out.v32[pos] = o.v32[e];
             if (fmt == FMT_F64) out.v64[pos] = o.v64[e];
+            ++pos;
         }
-    }
+    });
 }
 
 void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t> &inst_off, int32_t chunk,
@@ -394,12 +420,13 @@ void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &
         return s;
     };
     plan.bptr.assign((size_t)S * (rows + 1), 0);
-    for (int32_t q = 0; q < count; ++q) {
-        if (!ok[q]) continue;
+    parallel_chunks(count, 1, [&](int64_t k) {
+        const int32_t q = (int32_t)k;
+        if (!ok[q]) return;
         for (int32_t i = inst_off[q]; i < inst_off[q + 1]; ++i)
             for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e)
                 plan.bptr[(size_t)slice_of(q, entry_index(o, fmt, e)) * (rows + 1) + i + 1]++;
-    }
+    });
     int64_t base = 0;
     for (int32_t s = 0; s < S; ++s) {
         int32_t *p = plan.bptr.data() + (size_t)s * (rows + 1);
@@ -411,9 +438,10 @@ void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &
     if (fmt == FMT_BF16) plan.v16.resize(base);
     if (fmt == FMT_F32) plan.v32.resize(base);
     if (fmt == FMT_F64) plan.v64.resize(base);
-    std::vector<int32_t> fill(S);
-    for (int32_t q = 0; q < count; ++q) {
-        if (!ok[q]) continue;
+    parallel_chunks(count, 1, [&](int64_t k) {
+        const int32_t q = (int32_t)k;
+        if (!ok[q]) return;
+        std::vector<int32_t> fill(S);
         for (int32_t i = inst_off[q]; i < inst_off[q + 1]; ++i) {
             for (int32_t s = 0; s < S; ++s) fill[s] = plan.bptr[(size_t)s * (rows + 1) + i];
             for (int32_t e = o.ptr[i]; e < o.ptr[i + 1]; ++e) {
@@ -424,6 +452,9 @@ void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &
                 if (fmt == FMT_F64) plan.v64[pos] = o.v64[e];
             }
         }
+    });
+    for (int32_t q = 0; q < count; ++q) {
+        if (!ok[q]) continue;
         const int64_t glen = gofs[q + 1] - gofs[q];
         for (int32_t s = 0; s < S; ++s)
             plan.max_slice = std::max<int32_t>(plan.max_slice, (int32_t)((glen * (s + 1)) / S - (glen * s) / S));

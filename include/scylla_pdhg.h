@@ -114,6 +114,15 @@ typedef struct {
                              recession cone (and |Q d|) <= infeas_tol
                              |c^T d| (PDLP's certificates).  0 = off.  The
                              optimality test comes first.                 */
+    double stall_tol;     /* > 0: "bounds stalling" ends the solve (Algorithm
+                             1's inner loop) with SCYLLA_STALLED when, at
+                             stall_checks consecutive checks, neither the
+                             primal objective P nor the dual objective D
+                             moved by more than stall_tol (1 + |value|)
+                             since the previous check; tested after the
+                             optimality and infeasibility tests and before
+                             the iteration limit.  0 = off (default)       */
+    int32_t stall_checks; /* >= 1 checks in a row (3)                     */
 } scylla_params;
 
 enum {
@@ -123,7 +132,8 @@ enum {
     SCYLLA_TIME_LIMIT = 3,       /* time_limit_s reached                    */
     SCYLLA_NUMERICAL_ERROR = 4,  /* a residual or gap norm is not finite    */
     SCYLLA_PRIMAL_INFEASIBLE = 5,/* dual ray found (see infeas_tol)         */
-    SCYLLA_DUAL_INFEASIBLE = 6   /* primal ray found: unbounded if feasible */
+    SCYLLA_DUAL_INFEASIBLE = 6,  /* primal ray found: unbounded if feasible */
+    SCYLLA_STALLED = 7           /* objective bounds stalled (stall_tol)    */
 };
 
 /* Result of one LP solve.  rel_kkt = max(rho_primal, rho_dual, rho_gap):

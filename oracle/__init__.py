@@ -37,6 +37,7 @@ _SRC = os.path.join(_HERE, "scylla_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OPTIMAL, ITERATION_LIMIT, NUMERICAL_ERROR, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 1, 2, 4, 5, 6
+STALLED = 7
 
 
 def build(force: bool = True) -> str:
@@ -61,7 +62,8 @@ class _Params(ctypes.Structure):
                 ("check_period", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("ruiz_iters", ctypes.c_int32),
                 ("pock_chambolle", ctypes.c_int32), ("omega0", ctypes.c_double),
-                ("adaptive", ctypes.c_int32), ("infeas_tol", ctypes.c_double)]
+                ("adaptive", ctypes.c_int32), ("infeas_tol", ctypes.c_double),
+                ("stall_tol", ctypes.c_double), ("stall_checks", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -152,20 +154,23 @@ def kkt(lp, x, y, c=None, q=None):
 def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 64,
          restarts: bool = True, eta: float = 0.99, x0=None, y0=None, omega0: float = 0.0,
          c=None, ruiz_iters: int = 10, pock_chambolle: bool = True,
-         adaptive: bool = False, q=None, infeas_tol: float = 1e-8) -> PDHGResult:
+         adaptive: bool = False, q=None, infeas_tol: float = 1e-8, stall_tol: float = 0.0,
+         stall_checks: int = 3) -> PDHGResult:
     """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop); with
     `adaptive` the step size follows PDLP's adaptive rule (no retries),
     starting at `eta`.  `q`: diagonal Hessian (>= 0) of a QP objective
     c^T x + x^T diag(q) x / 2, or None.  infeas_tol > 0: stop with
     PRIMAL_INFEASIBLE / DUAL_INFEASIBLE when the moves between two checks
-    certify it to that relative accuracy (0: off)."""
+    certify it to that relative accuracy (0: off).  stall_tol > 0: stop with
+    STALLED when neither objective bound moved by more than
+    stall_tol (1 + |value|) at stall_checks consecutive checks."""
     pin = _Pinned(lp, c, q)
     x = np.empty(lp.n)
     y = np.empty(lp.m)
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
     prm = _Params(tol, iter_limit, check_period, int(restarts), eta, ruiz_iters,
-                  int(pock_chambolle), omega0, int(adaptive), infeas_tol)
+                  int(pock_chambolle), omega0, int(adaptive), infeas_tol, stall_tol, stall_checks)
     res = _Result()
     rc = _load().orc_pdhg(ctypes.byref(pin.s), ctypes.byref(prm), _p(x0a), _p(y0a), _p(x), _p(y),
                           ctypes.byref(res))

@@ -50,6 +50,12 @@
  *     and the violation of A d against the row cones, of d against the
  *     bounds' recession cone (and |Q d|) is <= infeas_tol * |c^T d|.  The
  *     optimality test comes first.
+ *   - "bounds stalling" (an exit of Algorithm 1's inner loop, not defined
+ *     further): the primal and the dual objective, the two bounds on the
+ *     LP optimum the iteration maintains, both move by at most
+ *     stall_tol (1 + |value|) between consecutive checks, stall_checks
+ *     checks in a row (tested after the optimality and infeasibility tests,
+ *     before the iteration limit; off when stall_tol = 0).
  *   - adaptive step size ("update step sizes" in Algorithm 1, after PDLP):
  *     after the k-th iteration (k counted from 1 over the whole call), with
  *     dx = x+ - x and dy = y+ - y in the preconditioned metric,
@@ -89,10 +95,12 @@ typedef struct {
     double omega0;       /* > 0: use as primal weight, else from norms */
     int32_t adaptive;    /* 1: adaptive step size (PDLP's rule, no retry) */
     double infeas_tol;   /* > 0: infeasibility certificates at the checks */
+    double stall_tol;    /* > 0: stop when the objective bounds stall */
+    int32_t stall_checks;/* consecutive checks without a move that stop */
 } orc_params;
 
 enum { ORC_OPTIMAL = 1, ORC_ITERATION_LIMIT = 2, ORC_NUMERICAL_ERROR = 4, ORC_PRIMAL_INFEASIBLE = 5,
-       ORC_DUAL_INFEASIBLE = 6 };
+       ORC_DUAL_INFEASIBLE = 6, ORC_STALLED = 7 };
 
 typedef struct {
     int32_t status;
@@ -366,6 +374,8 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
 
     int64_t k = 0, kr = 0;
     double Er = 0.0, Ep = 0.0;
+    double pprev = 0.0, dprev = 0.0;
+    int32_t nstall = 0;
     int32_t nrestart = 0;
     double kkt[8] = {0};
     memset(res, 0, sizeof(*res));
@@ -383,6 +393,20 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
             }
             memcpy(xp, x, sizeof(double) * n);
             memcpy(yp, y, sizeof(double) * m);
+            if (p->stall_tol > 0.0) {
+                /* bounds stalling: the primal objective kkt[4] and the dual
+                   objective kkt[5] both within stall_tol (1 + |value|) of
+                   their values at the previous check, stall_checks checks
+                   in a row */
+                if (k > 0) {
+                    int still = fabs(kkt[4] - pprev) <= p->stall_tol * (1.0 + fabs(kkt[4])) &&
+                                fabs(kkt[5] - dprev) <= p->stall_tol * (1.0 + fabs(kkt[5]));
+                    nstall = still ? nstall + 1 : 0;
+                    if (nstall >= p->stall_checks) { res->status = ORC_STALLED; break; }
+                }
+                pprev = kkt[4];
+                dprev = kkt[5];
+            }
             if (k >= p->iter_limit) { res->status = ORC_ITERATION_LIMIT; break; }
             if (k == 0) {
                 Er = E;

@@ -784,6 +784,19 @@ __device__ void decide_state(InstState &S, const double tot[NTOT], int R)
         const double cd = tot[12], pviol = sqrt(tot[9] + tot[13]);
         if (cd < 0.0 && pviol <= -S.infeas_tol * cd) { S.status = ST_DINF; return; }
     }
+    if (S.stall_tol > 0.0) {
+        // bounds stalling (Algorithm 1's inner-loop exit): neither objective
+        // bound moved by more than stall_tol (1 + |value|) since the previous
+        // check, stall_checks times in a row
+        if (k > 0) {
+            const bool moved = fabs(P - S.pprev) > S.stall_tol * (1.0 + fabs(P)) ||
+                               fabs(D - S.dprev) > S.stall_tol * (1.0 + fabs(D));
+            S.nstall = moved ? 0 : S.nstall + 1;
+            if (S.nstall >= S.stall_checks) { S.status = ST_STALL; return; }
+        }
+        S.pprev = P;
+        S.dprev = D;
+    }
     if (k >= S.k_limit) { S.status = ST_ITER; return; }
     if (S.force_stop) { S.status = ST_TIME; return; }
     if (k == 0) {

@@ -1049,6 +1049,8 @@ int validate_params(const scylla_params *p)
     if (p->precision != SCYLLA_FP32 && p->precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
     if (p->adaptive != 0 && p->adaptive != 1) throw_err(-EINVAL, "adaptive must be 0 or 1");
     if (!(p->infeas_tol >= 0.0) || !isfinite(p->infeas_tol)) throw_err(-EINVAL, "infeas_tol must be finite and >= 0");
+    if (!(p->stall_tol >= 0.0) || !isfinite(p->stall_tol)) throw_err(-EINVAL, "stall_tol must be finite and >= 0");
+    if (p->stall_tol > 0.0 && p->stall_checks < 1) throw_err(-EINVAL, "stall_checks must be >= 1");
     return 0;
 }
 
@@ -1132,6 +1134,10 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
         S.s = p->eta * omega;
         S.tol = p->tol;
         S.infeas_tol = p->infeas_tol;
+        S.stall_tol = p->stall_tol;
+        S.stall_checks = p->stall_checks;
+        S.nstall = 0;
+        S.pprev = S.dprev = 0.0;
         S.Er = S.Ep = 0.0;
         S.rel = S.rho_p = S.rho_d = S.rho_g = S.pobj = S.dobj = 0.0;
     }
@@ -1637,6 +1643,8 @@ int scylla_params_default(scylla_params *p)
     p->fused_window = 1;
     p->adaptive = 0;
     p->infeas_tol = 1e-8;
+    p->stall_tol = 0.0;
+    p->stall_checks = 3;
     return 0;
 }
 

@@ -21,7 +21,8 @@ enum Fmt : int32_t {
     FMT_F64 = 3      // int32 index + double value (FP64 path)
 };
 
-enum Status : int32_t { ST_RUN = 0, ST_OPT = 1, ST_ITER = 2, ST_TIME = 3, ST_NUM = 4, ST_PINF = 5, ST_DINF = 6 };
+enum Status : int32_t { ST_RUN = 0, ST_OPT = 1, ST_ITER = 2, ST_TIME = 3, ST_NUM = 4, ST_PINF = 5, ST_DINF = 6,
+                       ST_STALL = 7 };
 
 // Doubles per check partial slot: row pass {|r_p|^2, b^T y, |dy~|^2, -,
 // b^T v, |v - proj_Y v|^2, |row violation of A d|^2, -}; column pass
@@ -53,6 +54,10 @@ struct InstState {
     double bnorm, cnorm;  // ||b||_2, ||c_hat||_2 of the instance
     double omega0;        // primal weight from the data (cold start)
     double infeas_tol;    // > 0: infeasibility certificates at the checks
+    double stall_tol;     // > 0: stop when the objective bounds stall
+    double pprev, dprev;  // primal / dual objective at the previous check
+    int32_t stall_checks; // checks in a row without a move that stop the solve
+    int32_t nstall;       // current run of such checks
 };
 
 // Static per-instance ranges in the concatenated arrays.

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libscylla_pdhg.so")
 
 FP64, FP32 = 0, 1
 RUNNING, OPTIMAL, ITERATION_LIMIT, TIME_LIMIT, NUMERICAL_ERROR, PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 0, 1, 2, 3, 4, 5, 6
+STALLED = 7
 FORMATS = {0: "packed-int", 1: "bf16", 2: "fp32", 3: "fp64"}
 
 EXPORTS = [
@@ -54,7 +55,8 @@ class Params(ctypes.Structure):
                 ("restarts", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
                 ("fused_window", ctypes.c_int32), ("adaptive", ctypes.c_int32),
-                ("infeas_tol", ctypes.c_double)]
+                ("infeas_tol", ctypes.c_double), ("stall_tol", ctypes.c_double),
+                ("stall_checks", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

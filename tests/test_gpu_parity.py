@@ -398,3 +398,36 @@ def test_tuning_cache_reuses_choices(tmp_path, monkeypatch):
     lines = path.read_text().strip().splitlines()
     assert len(lines) == 1 and lines[0].startswith("gfx950")
     assert infos[0] == infos[1]
+
+
+# ------------------------------------------------- bounds stalling
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("name,st", [("cover200", 1e-4), ("cover200", 1e-6), ("general_small", 1e-5),
+                                     ("knapsack", 1e-4), ("skewed_longrows", 1e-5)])
+def test_stall_parity(name, st, fused):
+    """The FP64 path stops on stalled objective bounds at the oracle's check
+    (same status, same iteration count); the FP32 path stalls as well, on
+    its own iterates, at a check boundary."""
+    lp = _case(name)
+    ref = oracle.pdhg(lp, tol=1e-9, iter_limit=60_000, stall_tol=st, stall_checks=3)
+    assert ref.status == oracle.STALLED
+    s = pdhg.solve(lp, tol=1e-9, iter_limit=60_000, precision=0, stall_tol=st, stall_checks=3,
+                   fused_window=fused)
+    assert s.result["status"] == pdhg.STALLED and s.result["iterations"] == ref.iterations, \
+        (s.result, ref.iterations)
+    s = pdhg.solve(lp, tol=1e-9, iter_limit=60_000, precision=1, stall_tol=st, stall_checks=3,
+                   fused_window=fused)
+    assert s.result["status"] == pdhg.STALLED and s.result["iterations"] % 64 == 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stall_counting_in_a_batch(prec):
+    """A huge stall_tol stops every instance of a batch at its third check
+    after the start (192 iterations); a limit of 128 iterations ends first."""
+    lps = [_case("cover200"), _case("knapsack"), _case("mixed_bounds")]
+    with pdhg.Batch(lps, precision=prec) as b:
+        res = b.solve(tol=1e-9, iter_limit=10_000, stall_tol=1e300, stall_checks=3)
+        assert [r["status"] for r in res] == [pdhg.STALLED] * 3
+        assert [r["iterations"] for r in res] == [192] * 3
+        res = b.solve(tol=1e-9, iter_limit=128, stall_tol=1e300, stall_checks=3)
+        assert [r["status"] for r in res] == [pdhg.ITERATION_LIMIT] * 3

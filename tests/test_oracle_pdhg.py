@@ -482,3 +482,65 @@ def test_infeasibility_detection_can_be_switched_off():
     lp = _infeasible(0)
     r = oracle.pdhg(lp, tol=1e-6, iter_limit=2000, infeas_tol=0.0)
     assert r.status == oracle.ITERATION_LIMIT
+
+
+# ---------------------------------------------- bounds stalling (S9 reading)
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("R,W", [(64, 3), (16, 1), (32, 5)])
+def test_fixed_point_stalls_at_the_w_th_check(seed, R, W):
+    """At an exact optimum the PDHG map does not move, so both objective
+    bounds are constant: with any stall_tol > 0 the solve stops at the W-th
+    check after the start, i.e. after W R iterations; with an iteration
+    limit of exactly W R the stall test (before the limit) still decides;
+    the check at the limit counts, so a limit of W R - 1 stalls there, and
+    with a limit of (W - 1) R only W - 1 checks follow the start."""
+    rng = np.random.default_rng(177 + seed)
+    lp, xs, ys = _constructed_optimum(rng)
+    kw = dict(tol=-1.0, x0=xs, y0=ys, check_period=R, stall_tol=1e-14, stall_checks=W)
+    r = oracle.pdhg(lp, iter_limit=100 * R, **kw)
+    assert r.status == oracle.STALLED and r.iterations == W * R
+    r = oracle.pdhg(lp, iter_limit=W * R, **kw)
+    assert r.status == oracle.STALLED and r.iterations == W * R
+    r = oracle.pdhg(lp, iter_limit=W * R - 1, **kw)
+    assert r.status == oracle.STALLED and r.iterations == W * R - 1
+    r = oracle.pdhg(lp, iter_limit=(W - 1) * R, **kw)
+    assert r.status == oracle.ITERATION_LIMIT and r.iterations == (W - 1) * R
+
+
+def test_stall_off_and_moving_bounds_do_not_stop():
+    """stall_tol = 0 leaves the solve unchanged; from the origin the
+    objective bounds move at every early check, so a tiny stall_tol does
+    not stop the first checks either."""
+    lp = I.set_cover(200, 500, seed=3)
+    a = oracle.pdhg(lp, tol=1e-6, iter_limit=3000)
+    b = oracle.pdhg(lp, tol=1e-6, iter_limit=3000, stall_tol=0.0)
+    assert a.status == b.status and a.iterations == b.iterations
+    np.testing.assert_array_equal(a.x, b.x)
+    c = oracle.pdhg(lp, tol=-1.0, iter_limit=640, stall_tol=1e-14, stall_checks=1)
+    assert c.status == oracle.ITERATION_LIMIT and c.iterations == 640
+
+
+@pytest.mark.parametrize("name", ["cover", "knapsack"])
+def test_stall_point_restated_from_checkpoints(name):
+    """The stop is where the objective bounds, evaluated independently at
+    every check (a run with the iteration limit at that check reproduces
+    the longer run up to it), first held still W checks in a row."""
+    lp = I.set_cover(150, 400, seed=5) if name == "cover" else I.cover_knapsack(300, seed=6)
+    R, W, st = 64, 3, 1e-4
+    r = oracle.pdhg(lp, tol=1e-9, iter_limit=20_000, stall_tol=st, stall_checks=W)
+    assert r.status == oracle.STALLED and r.iterations % R == 0
+    nchk = r.iterations // R
+    PD = []
+    for c in range(nchk + 1):
+        s = oracle.pdhg(lp, tol=1e-9, iter_limit=c * R)
+        k = kkt_numpy(lp, s.x, s.y)
+        PD.append((k["pobj"], k["dobj"]))
+    still = [abs(PD[c][0] - PD[c - 1][0]) <= st * (1 + abs(PD[c][0])) and
+             abs(PD[c][1] - PD[c - 1][1]) <= st * (1 + abs(PD[c][1])) for c in range(1, nchk + 1)]
+    run, first = 0, None
+    for c, s_ in enumerate(still, start=1):
+        run = run + 1 if s_ else 0
+        if run >= W:
+            first = c
+            break
+    assert first == nchk

@@ -190,18 +190,20 @@ def other_workloads(pdhg, instances, args, R):
         recs, xh = b.pump(rounds=args.pump_rounds, alpha=0.9, tol=1e-4, iter_limit=200_000)
         el = time.perf_counter() - t
         its = [max(r["iterations"] for r in rnd) for rnd in recs]
-        solve_s = sum(rnd[0]["solve_seconds"] for rnd in recs)
-        rounding_s = sum(rnd[0]["rounding_seconds"] for rnd in recs)
-        tune_s = sum(rnd[0]["tune_seconds"] for rnd in recs)
-        rounds_s = sum(rnd[0]["round_seconds"] for rnd in recs)
+        inst_its = sum(r["iterations"] for rnd in recs for r in rnd)
+        def per_group(key):  # one value per device solve group and round
+            return sum(next(r[key] for r in rnd if r["group"] == g)
+                       for rnd in recs for g in {r["group"] for r in rnd})
+        solve_s, rounding_s, tune_s = (per_group(k) for k in ("solve_seconds", "rounding_seconds",
+                                                                "tune_seconds"))
         first = [next((k + 1 for k in range(len(recs)) if recs[k][q]["xhat_feasible"]), None)
                  for q in range(len(lps))]
         out["pump_64x20k"] = dict(rounds=len(recs), seconds=round(el, 3), solve_seconds=round(solve_s, 3),
                                   rounding_seconds=round(rounding_s, 3), tune_seconds=round(tune_s, 3),
-                                  other_seconds=round(el - solve_s - rounding_s - tune_s, 3),
-                                  outside_rounds_seconds=round(el - rounds_s, 3),
-                                  batch_iterations=sum(its),
-                                  batch_iter_per_s=round(sum(its) / solve_s, 1),
+                                  groups=len({r["group"] for r in recs[0]}),
+                                  batch_iterations=sum(its), batch_iter_per_s=round(sum(its) / solve_s, 1),
+                                  instance_iterations=inst_its,
+                                  instance_iter_per_s=round(inst_its / solve_s, 1),
                                   iterations_round1=its[0], iterations_last=its[-1],
                                   instances_feasible=sum(f is not None for f in first),
                                   mean_first_feasible_round=(round(sum(f for f in first if f) /
@@ -212,6 +214,10 @@ def other_workloads(pdhg, instances, args, R):
         t = time.perf_counter()
         recs, outs, xo = b.pump_ex(pump=dict(rounds=args.pump_rounds, seed=0), iter_limit=200_000)
         el = time.perf_counter() - t
+        t = time.perf_counter()
+        recs1, outs1, xo1 = b.pump_ex(pump=dict(rounds=args.pump_rounds, seed=0, pipeline=1), iter_limit=200_000)
+        el1 = time.perf_counter() - t
+        same = bool((xo == xo1).all()) and [o["found_round"] for o in outs] == [o["found_round"] for o in outs1]
         found = [o for o in outs if o["found_kind"]]
         out["scylla_loop_64x20k"] = dict(
             seconds=round(el, 3), rounds_max=max(o["rounds_run"] for o in outs), found=len(found),
@@ -219,7 +225,8 @@ def other_workloads(pdhg, instances, args, R):
             found_rounding=sum(o["found_kind"] == 2 for o in outs),
             mean_found_round=round(sum(o["found_round"] for o in found) / max(1, len(found)), 2),
             perturbations=sum(o["perturbations"] for o in outs),
-            pdhg_iterations_total=sum(o["iterations"] for o in outs))
+            pdhg_iterations_total=sum(o["iterations"] for o in outs),
+            seconds_two_groups=round(el1, 3), same_result_two_groups=same)
         log(f"w5 complete loop: {out['scylla_loop_64x20k']}")
         b.close()
     if "6" in sel:  # complete loop with the L2 distance on general integers

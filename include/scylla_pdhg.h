@@ -296,13 +296,19 @@ typedef struct {
     int32_t perturbed;      /* the rounding repeated an earlier one and was
                                perturbed (scylla_batch_pump_ex only)          */
     double xhat_obj;        /* c^T x_hat with the original objective          */
-    double solve_seconds;   /* device solve of the round (whole batch)        */
-    double round_seconds;   /* whole round: solve, copy-out, rounding, blend  */
+    double solve_seconds;   /* device solve of the round (the instance's
+                               group of the batch), copy-out and checks      */
+    double round_seconds;   /* the group's round: solve, copy-out, rounding,
+                               objective update                             */
     double tune_seconds;    /* pass-layout autotuning inside the round's
                                solve (the handle's first solve only)         */
-    double rounding_seconds; /* host rounding of the round (all instances,
-                                thread pool): fix-and-propagate, checks,
-                                history, next objective                      */
+    double rounding_seconds; /* host rounding of the round (the instance's
+                                group, thread pool): fix-and-propagate,
+                                checks, history, next objective              */
+    int32_t group;          /* device solve group of the instance (0 or 1,
+                               see scylla_pump_params.pipeline); its round
+                               timings are the group's                      */
+    int32_t pad;
 } scylla_pump_record;
 
 /* MIP-feasibility of every instance's current primal iterate x (Algorithm 1
@@ -358,6 +364,15 @@ typedef struct {
                                  c_hat = alpha^K kappa c - 2 (1 - alpha^K)
                                  x_hat, Hessian 2 (1 - alpha^K) on I; general
                                  integers need no auxiliary variables)        */
+    int32_t pipeline;         /* 1: two groups of instances (split at half
+                                 the nonzeros) alternate on the device, so
+                                 one group's host rounding runs during the
+                                 other group's solve; results equal those of
+                                 0 (default: one group, rounds in lockstep).
+                                 Pays off only when half the batch keeps the
+                                 GPU as busy as the whole: a batch whose
+                                 passes are one wave of workgroups takes
+                                 about as long per iteration for half of it */
 } scylla_pump_params;
 
 /* Per-instance outcome of scylla_batch_pump_ex. */
@@ -372,7 +387,7 @@ typedef struct {
 
 /* Defaults of the paper's configuration: 20 rounds, eps schedule on
  * (0.01, 0.98, 1e-8), alpha 0.9, no cumulative limit, early exit and
- * perturbation on, seed 0, threads 0, L1 distance. */
+ * perturbation on, seed 0, threads 0, L1 distance, one group. */
 int scylla_pump_params_default(scylla_pump_params *o);
 
 /* The complete outer loop of Algorithm 1 on every instance of the batch:

@@ -1069,6 +1069,15 @@ void project_start(scylla_batch *h, int32_t inst, int zero)
                       h->sense.as<uint8_t>(), rlo, rhi, zero, h->stream);
 }
 
+// Projects (after zeroing, when `zero`) the start points of instances
+// [q0, q1), which occupy contiguous column and row ranges.
+template <class V>
+void project_range(scylla_batch *h, int32_t q0, int32_t q1, int zero)
+{
+    launch_project<V>(h->x.as<V>(), h->lv.as<V>(), h->uv.as<V>(), h->col_off[q0], h->col_off[q1], h->y.as<V>(),
+                      h->sense.as<uint8_t>(), h->row_off[q0], h->row_off[q1], zero, h->stream);
+}
+
 void read_states(scylla_batch *h, std::vector<InstState> &out)
 {
     out.resize(h->count);
@@ -1095,9 +1104,12 @@ void fill_result(const InstState &S, scylla_result &r, double solve_s, double se
 
 // k_limits (optional, [count]): per-instance iteration limit of this solve;
 // an instance with a limit <= 0 takes no part (its state is left as it is).
+// Only instances [q0, q1) (q1 < 0: all) have their start points projected
+// (and zeroed on a cold start); the others must have limits <= 0.
 int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results,
-                     const int64_t *k_limits = nullptr)
+                     const int64_t *k_limits = nullptr, int32_t q0 = 0, int32_t q1 = -1)
 {
+    if (q1 < 0) q1 = h ? h->count : 0;
     if (!h || !results) throw_err(-EINVAL, "handle or results is NULL");
     validate_params(p);
     if (p->precision != h->precision) throw_err(-EINVAL, "params precision differs from the handle's");
@@ -1141,8 +1153,10 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
         S.Er = S.Ep = 0.0;
         S.rel = S.rho_p = S.rho_d = S.rho_g = S.pobj = S.dobj = 0.0;
     }
-    if (h->vbytes == 4) project_start<float>(h, -1, warm ? 0 : 1);
-    else project_start<double>(h, -1, warm ? 0 : 1);
+    if (q1 > q0) {
+        if (h->vbytes == 4) project_range<float>(h, q0, q1, warm ? 0 : 1);
+        else project_range<double>(h, q0, q1, warm ? 0 : 1);
+    }
     HIPC(hipMemcpyAsync(h->st.p, st.data(), sizeof(InstState) * h->count, hipMemcpyHostToDevice, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
     ensure_graph(h, p->check_period, tiny);
@@ -1391,6 +1405,7 @@ struct PumpOpts {
     uint64_t seed;
     int32_t threads;
     int32_t distance;  // 1: L1 (linear objective), 2: L2 (QP objective)
+    bool pipeline;     // two instance groups: host rounding overlaps device solves
 };
 
 // Algorithm 1 outer loop.  legacy_best: also keep, per instance, the first
@@ -1436,11 +1451,10 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     if (h->ibits_tmp.bytes < boff[count]) h->ibits_tmp.alloc(boff[count]);
     HIPC(hipMemcpyAsync(h->ibits_tmp.p, ibits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
     set_mip_isint(h, isint.data());
-    std::vector<uint8_t> mip_ok(count);
     reset_objective(h);
     HIPC(hipStreamSynchronize(h->stream));
 
-    std::vector<double> x(N), xhat(N), xres(N, 0.0);
+    std::vector<double> xhat(N), xres(N, 0.0);
     std::vector<double> chat, qhat;  // L2: next objective and Hessian
     if (l2) {
         chat = h->hc;
@@ -1451,51 +1465,96 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     std::vector<scylla_pump_outcome> out(count);
     memset(out.data(), 0, sizeof(scylla_pump_outcome) * count);
     std::vector<RoundingHistory> hist(o.perturb ? count : 0);
-    std::vector<int64_t> limits(count);
-    std::vector<scylla_result> res(count);
     std::vector<FPPrep> prep(count);  // per-instance rounding state, built on first use
     if (rec) memset(rec, 0, sizeof(scylla_pump_record) * (size_t)o.rounds * count);
-    double eps = o.eps1;
-    for (int32_t K = 1; K <= o.rounds; ++K) {
-        const double t0 = now_s();
-        if (K > 1) eps = std::max(o.beta * eps, o.eps_floor);
+    std::vector<double> eps_k(o.rounds + 1, o.eps1);  // tolerance of round K (schedule)
+    for (int32_t K = 2; K <= o.rounds; ++K) eps_k[K] = std::max(o.beta * eps_k[K - 1], o.eps_floor);
+
+    // Instances run in one group, or in two groups of contiguous instances
+    // (split at half the nonzeros) whose rounds alternate on the device: the
+    // host rounds one group while the device solves the other.  Every
+    // instance sees the same sequence of solves, roundings and objective
+    // updates either way (a batched solve equals solves of its instances).
+    struct Group {
+        int32_t q0 = 0, q1 = 0, K = 1;
+        std::vector<double> x;                // iterate copied out after the solve
+        std::vector<uint8_t> ok;              // device MIP-feasibility flags
+        std::vector<scylla_result> res;
+        std::vector<int64_t> limits;
+        double solve_s = 0.0, rounding_s = 0.0;
+    };
+    const int ng = (o.pipeline && count >= 2) ? 2 : 1;
+    Group G[2];
+    {
+        int32_t mid = count;
+        if (ng == 2) {
+            const int64_t total = h->orow.host.ptr[h->M];
+            mid = 1;
+            while (mid < count - 1 && (int64_t)h->orow.host.ptr[h->row_off[mid]] * 2 < total) ++mid;
+        }
+        G[0].q0 = 0;
+        G[0].q1 = mid;
+        G[1].q0 = mid;
+        G[1].q1 = count;
+        for (int g = 0; g < ng; ++g) {
+            G[g].x.assign(N, 0.0);
+            G[g].ok.assign(count, 0);
+            G[g].res.resize(count);
+            G[g].limits.assign(count, 0);
+        }
+    }
+
+    // Solves round G.K of a group; false when it has nothing left to solve.
+    auto solve_group = [&](Group &g) -> bool {
+        if (g.K > o.rounds) return false;
         int32_t n_active = 0;
-        for (int32_t q = 0; q < count; ++q) {
+        for (int32_t q = 0; q < count; ++q) g.limits[q] = 0;
+        for (int32_t q = g.q0; q < g.q1; ++q) {
             int64_t lim = p->iter_limit;
             if (o.total_iter_limit > 0) lim = std::min(lim, o.total_iter_limit - out[q].iterations);
             if (active[q] && lim <= 0) active[q] = 0;
-            limits[q] = active[q] ? lim : 0;
+            g.limits[q] = active[q] ? lim : 0;
             n_active += active[q];
         }
-        if (n_active == 0) break;
+        if (n_active == 0) return false;
+        const double t0 = now_s();
         scylla_params pk = *p;
-        if (o.eps_sched) pk.tol = eps;
-        batch_solve_impl(h, &pk, K > 1 ? 1 : 0, res.data(), limits.data());
-        mip_check(h, 1e-6, mip_ok.data());
-        if (h->vbytes == 4) get_range<float>(h, h->x, 0, N, x.data());
-        else get_range<double>(h, h->x, 0, N, x.data());
+        if (o.eps_sched) pk.tol = eps_k[g.K];
+        batch_solve_impl(h, &pk, g.K > 1 ? 1 : 0, g.res.data(), g.limits.data(), g.q0, g.q1);
+        mip_check(h, 1e-6, g.ok.data());
+        if (h->vbytes == 4) get_range<float>(h, h->x, 0, N, g.x.data());
+        else get_range<double>(h, h->x, 0, N, g.x.data());
+        g.solve_s = now_s() - t0;
+        return true;
+    };
+
+    // Host rounding of round G.K of a group (Algorithm 1 after the solve).
+    auto round_group = [&](Group &g) {
+        const int32_t K = g.K;
         std::atomic<int> bad{0}, nonbinary{0};
         const double tr0 = now_s();
-        parallel_for(count, o.threads, [&](int32_t q) {
+        parallel_for(g.q1 - g.q0, o.threads, [&](int32_t qi) {
+            const int32_t q = g.q0 + qi;
             if (!active[q]) return;
             const auto &P = h->local[q].P;
             const int32_t c0 = h->col_off[q];
             const uint8_t *ii = isint.data() + c0;
-            const double *xq = x.data() + c0;
+            const double *xq = g.x.data() + c0;
             double *xh = xhat.data() + c0;
             scylla_pump_outcome &oc = out[q];
             oc.rounds_run = K;
-            oc.iterations += res[q].iterations;
+            oc.iterations += g.res[q].iterations;
             scylla_pump_record rtmp;
             scylla_pump_record &r = rec ? rec[(size_t)(K - 1) * count + q] : rtmp;
             memset(&r, 0, sizeof(r));
             r.round = K;
-            r.status = res[q].status;
-            r.iterations = res[q].iterations;
-            r.rel_kkt = res[q].rel_kkt;
-            r.solve_seconds = res[q].solve_seconds;
-            r.tune_seconds = res[q].tune_seconds;
-            r.lp_feasible = mip_ok[q];
+            r.group = (int32_t)(&g - G);
+            r.status = g.res[q].status;
+            r.iterations = g.res[q].iterations;
+            r.rel_kkt = g.res[q].rel_kkt;
+            r.solve_seconds = g.res[q].solve_seconds;
+            r.tune_seconds = g.res[q].tune_seconds;
+            r.lp_feasible = g.ok[q];
             if (r.lp_feasible && !oc.found_kind) {
                 oc.found_kind = 1;
                 oc.found_round = K;
@@ -1566,26 +1625,33 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                 else if (xh[j] != P.l[j]) bad = 1;
             }
         });
-        const double rounding_dt = now_s() - tr0;
+        g.rounding_s = now_s() - tr0;
         if (nonbinary) throw_err(-EINVAL, "cycle perturbation needs binary integer variables");
         if (bad) throw_err(-EINVAL, "an integer variable is rounded strictly inside its bounds: the L1 distance "
                                     "of general integers needs auxiliary variables");
+    };
+
+    // Next objective of the group's active instances on the device, then the
+    // group's round is complete.
+    auto finish_group = [&](Group &g) {
+        const double tb = now_s();
         bool any = false;
-        for (int32_t q = 0; q < count; ++q) any = any || active[q];
-        if (K < o.rounds && any && l2) {
-            HIPC(hipMemcpyAsync(h->c64.p, chat.data(), sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
-            HIPC(hipMemcpyAsync(h->q64.p, qhat.data(), sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
-            if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>(), h->cv.as<float>(), N, h->stream);
-            else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), N, h->stream);
+        for (int32_t q = g.q0; q < g.q1; ++q) any = any || active[q];
+        const int32_t c0 = h->col_off[g.q0], c1 = h->col_off[g.q1];
+        if (g.K < o.rounds && any && l2) {
+            HIPC(hipMemcpyAsync(h->c64.as<double>() + c0, chat.data() + c0, sizeof(double) * (c1 - c0),
+                                hipMemcpyHostToDevice, h->stream));
+            HIPC(hipMemcpyAsync(h->q64.as<double>() + c0, qhat.data() + c0, sizeof(double) * (c1 - c0),
+                                hipMemcpyHostToDevice, h->stream));
+            if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>() + c0, h->cv.as<float>() + c0, c1 - c0, h->stream);
+            else launch_cast<double>(h->c64.as<double>() + c0, h->cv.as<double>() + c0, c1 - c0, h->stream);
             cast_q(h);
-            launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
-                              h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
-            HIPC(hipGetLastError());
-            HIPC(hipStreamSynchronize(h->stream));
-        } else if (K < o.rounds && any) {
-            const double a = pow(o.alpha, (double)K);
-            HIPC(hipMemcpyAsync(h->bits_tmp.p, xbits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
-            for (int32_t q = 0; q < count; ++q) {
+        } else if (g.K < o.rounds && any) {
+            const double a = pow(o.alpha, (double)g.K);
+            const size_t b0 = boff[g.q0], b1 = boff[g.q1];
+            HIPC(hipMemcpyAsync(h->bits_tmp.as<uint8_t>() + b0, xbits.data() + b0, b1 - b0, hipMemcpyHostToDevice,
+                                h->stream));
+            for (int32_t q = g.q0; q < g.q1; ++q) {
                 if (!active[q]) continue;
                 const int lo = h->col_off[q], hi = h->col_off[q + 1];
                 const uint8_t *xb = h->bits_tmp.as<uint8_t>() + boff[q];
@@ -1597,19 +1663,59 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                     launch_blend<double>(h->corig64.as<double>(), xb, ib, a, kappa[q], h->c64.as<double>(),
                                          h->cv.as<double>(), lo, hi, h->stream);
             }
+        }
+        if (g.K < o.rounds && any) {
             launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
                               h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
             HIPC(hipGetLastError());
             HIPC(hipStreamSynchronize(h->stream));
         }
-        const double dt = now_s() - t0;
+        const double dt = g.solve_s + g.rounding_s + (now_s() - tb);
         if (rec)
-            for (int32_t q = 0; q < count; ++q)
-                if (rec[(size_t)(K - 1) * count + q].round) {
-                    rec[(size_t)(K - 1) * count + q].round_seconds = dt;
-                    rec[(size_t)(K - 1) * count + q].rounding_seconds = rounding_dt;
+            for (int32_t q = g.q0; q < g.q1; ++q) {
+                scylla_pump_record &r = rec[(size_t)(g.K - 1) * count + q];
+                if (r.round) {
+                    r.round_seconds = dt;
+                    r.rounding_seconds = g.rounding_s;
                 }
-        if (!any) break;
+            }
+        ++g.K;
+    };
+
+    if (ng == 1) {
+        while (solve_group(G[0])) {
+            round_group(G[0]);
+            finish_group(G[0]);
+        }
+    } else {
+        // pending: the group whose solve awaits its rounding
+        bool has[2] = {solve_group(G[0]), false};
+        int r = 0;
+        for (;;) {
+            const int sg = 1 - r;
+            std::exception_ptr err;
+            std::thread worker;
+            if (has[r])
+                worker = std::thread([&]() {
+                    try {
+                        round_group(G[r]);
+                    } catch (...) {
+                        err = std::current_exception();
+                    }
+                });
+            try {
+                has[sg] = solve_group(G[sg]);
+            } catch (...) {
+                if (worker.joinable()) worker.join();
+                throw;
+            }
+            if (worker.joinable()) worker.join();
+            if (err) std::rethrow_exception(err);
+            if (has[r]) finish_group(G[r]);
+            if (!has[r] && !has[sg]) break;
+            has[r] = false;
+            r = sg;
+        }
     }
     for (int32_t q = 0; q < count; ++q) {
         double obj = 0.0;
@@ -1959,7 +2065,7 @@ int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is
                       double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out)
 {
     return guarded([&]() {
-        PumpOpts o{rounds, false, 0.0, 0.0, 0.0, alpha, 0, false, false, 0, threads, 1};
+        PumpOpts o{rounds, false, 0.0, 0.0, 0.0, alpha, 0, false, false, 0, threads, 1, false};
         pump_impl(h, p, is_int, o, records, nullptr, nullptr, true);
         if (xhat_out) memcpy(xhat_out, h->pump_best.data(), sizeof(double) * h->N);
         return 0;
@@ -1985,6 +2091,7 @@ int scylla_pump_params_default(scylla_pump_params *o)
     o->seed = 0;
     o->threads = 0;
     o->distance = 1;
+    o->pipeline = 0;
     return 0;
 }
 
@@ -1996,7 +2103,7 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
         if (!opt) throw_err(-EINVAL, "pump params is NULL");
         PumpOpts o{opt->rounds,    opt->eps_schedule != 0, opt->eps1,         opt->beta,
                    opt->eps_floor, opt->alpha,             opt->total_iter_limit, opt->early_exit != 0,
-                   opt->perturb != 0, opt->seed, opt->threads, opt->distance};
+                   opt->perturb != 0, opt->seed, opt->threads, opt->distance, opt->pipeline != 0};
         return pump_impl(h, params, is_int, o, records, outcome, x_out, false);
     });
 }

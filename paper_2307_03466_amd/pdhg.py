@@ -159,7 +159,8 @@ class PumpRecord(ctypes.Structure):
                 ("xhat_feasible", ctypes.c_int32), ("ignored_rows", ctypes.c_int32),
                 ("perturbed", ctypes.c_int32), ("xhat_obj", ctypes.c_double),
                 ("solve_seconds", ctypes.c_double), ("round_seconds", ctypes.c_double),
-                ("tune_seconds", ctypes.c_double), ("rounding_seconds", ctypes.c_double)]
+                ("tune_seconds", ctypes.c_double), ("rounding_seconds", ctypes.c_double),
+                ("group", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -170,7 +171,7 @@ class PumpParams(ctypes.Structure):
                 ("beta", ctypes.c_double), ("eps_floor", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("total_iter_limit", ctypes.c_int64), ("early_exit", ctypes.c_int32),
                 ("perturb", ctypes.c_int32), ("seed", ctypes.c_uint64), ("threads", ctypes.c_int32),
-                ("distance", ctypes.c_int32)]
+                ("distance", ctypes.c_int32), ("pipeline", ctypes.c_int32)]
 
 
 class PumpOutcome(ctypes.Structure):

@@ -184,3 +184,39 @@ def test_full_loop_rejects_bad_options():
         for bad in (dict(rounds=0), dict(alpha=1.0), dict(eps1=0.0), dict(beta=1.5), dict(total_iter_limit=-1)):
             with pytest.raises(pdhg.ScyllaError):
                 b.pump_ex(pump=bad)
+
+
+_TIMING = ("solve_seconds", "round_seconds", "tune_seconds", "rounding_seconds", "group", "pad")
+
+
+def _strip(recs):
+    return [[{k: v for k, v in r.items() if k not in _TIMING} for r in rnd] for rnd in recs]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opts", [dict(rounds=20, seed=5),
+                                  dict(rounds=12, seed=9, total_iter_limit=3000, early_exit=0, eps_schedule=0)])
+def test_pipelined_groups_equal_lockstep(prec, opts):
+    """Two instance groups alternating on the device (one group's rounding
+    during the other's solve) give the lockstep loop's records, outcomes
+    and points bit for bit; both groups are used."""
+    lps = _loop_batch()
+    kw = dict(tol=1e-5, iter_limit=700) if "total_iter_limit" in opts else {}
+    with pdhg.Batch(lps, precision=prec) as b:
+        r1, o1, x1 = b.pump_ex(pump=dict(opts, pipeline=1), **kw)
+    with pdhg.Batch(lps, precision=prec) as b:
+        r0, o0, x0 = b.pump_ex(pump=dict(opts, pipeline=0), **kw)
+    assert {r["group"] for r in r1[0]} == {0, 1} and {r["group"] for r in r0[0]} == {0}
+    assert _strip(r1) == _strip(r0)
+    assert o1 == o0
+    np.testing.assert_array_equal(x1, x0)
+
+
+def test_pipelined_l2_loop_equals_lockstep():
+    lps = I.int_pump_batch(6, 300, 600, seed=3)
+    with pdhg.Batch(lps, precision=1) as b:
+        r1, o1, x1 = b.pump_ex(pump=dict(rounds=8, seed=1, distance=2, perturb=0, early_exit=0, pipeline=1))
+    with pdhg.Batch(lps, precision=1) as b:
+        r0, o0, x0 = b.pump_ex(pump=dict(rounds=8, seed=1, distance=2, perturb=0, early_exit=0, pipeline=0))
+    assert _strip(r1) == _strip(r0) and o1 == o0
+    np.testing.assert_array_equal(x1, x0)

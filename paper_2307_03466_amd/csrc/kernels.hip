@@ -1339,26 +1339,28 @@ __global__ void k_blend(const double *c_orig, const uint8_t *xbits, const uint8_
 // Algorithm 1 tests the PDHG point itself before rounding it: x is
 // MIP-feasible when every row holds within tol (1 + |b_i|), every x_j lies
 // within tol of [l_j, u_j] and every integer x_j within tol of an integer.
-// Row activities are FP64 sums of a_ij x_j (one wave per row); a
+// Row activities are FP64 sums of a_ij x_j (16 lanes per row); a
 // non-finite value counts as a violation.  Flags: 1 = violated.
 template <class V, int FMT>
 __global__ __launch_bounds__(256) void k_mip_rows(const MatView M, int rows, const V *__restrict__ x,
                                                   const double *__restrict__ b, const uint8_t *__restrict__ sense,
                                                   double tol, uint8_t *__restrict__ bad)
 {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int lane = threadIdx.x & 15;
+    // whole 16-lane groups leave together, so the shuffles below only
+    // involve lanes that are still running
     if (row >= rows) return;
     const int e1 = M.ptr[row + 1];
     double acc = 0.0;
-    for (int e = M.ptr[row] + lane; e < e1; e += 64) {
+    for (int e = M.ptr[row] + lane; e < e1; e += 16) {
         uint32_t w;
         double a;
         load_entry<FMT, double>(M, e, w, a);
         const int j = decode_entry<FMT, double>(M, w, a);
         acc += a * (double)x[j];
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
     if (lane == 0) {
         const double bi = b[row], t = tol * (1.0 + fabs(bi));
         const uint8_t sn = sense[row];
@@ -1679,7 +1681,7 @@ void launch_mip_check(const MatView &M, int fmt, int m, int n, int count, const 
                       hipStream_t s)
 {
     if (m > 0) {
-        dim3 g((m + 3) / 4), bl(256);
+        dim3 g((m + 15) / 16), bl(256);
         if constexpr (sizeof(V) == 8) {
             hipLaunchKernelGGL((k_mip_rows<V, FMT_F64>), g, bl, 0, s, M, m, x, b, sense, tol, rbad);
         } else {

@@ -55,9 +55,10 @@ def canonical_bytes(m, n, nnz, fp64=False):
     return 2 * nnz * 6 + 4 * (m + 1) + 4 * (n + 1) + 28 * n + 17 * m + 4 * (m + n)
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` (FETCH_SIZE x calibration + WRITE_SIZE)
-    from profiles/pmc_traffic.json, or None when the counters were taken on
+def measured_traffic(kernels):
+    """HBM bytes per launch of a pass made of `kernels` (sum over them of
+    FETCH_SIZE x calibration + WRITE_SIZE per dispatch) from
+    profiles/pmc_traffic.json, or None when the counters were taken on
     another version of the kernel source."""
     from paper_2307_03466_amd import profsum
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -66,10 +67,13 @@ def measured_traffic(kernel: str):
     d = json.load(open(path))
     if d.get("kernels_hip_sha256") != profsum.kernels_sha256():
         return None
-    k = d["kernels"].get(kernel)
-    if not k or "fetch_bytes" not in k or "write_bytes" not in k:
-        return None
-    return int(k["fetch_bytes"] + k["write_bytes"])
+    total = 0
+    for kernel in kernels:
+        k = d["kernels"].get(kernel)
+        if not k or "fetch_bytes" not in k or "write_bytes" not in k:
+            return None
+        total += k["fetch_bytes"] + k["write_bytes"]
+    return int(total)
 
 
 def timed_steps(batch, steps, R):
@@ -321,11 +325,15 @@ def main():
     gathered = (info["m_total"] if dom_is_col else info["n_total"]) * 4 // max(1, blocks)
     probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
     fmt = info["format"]
-    dom_kernel = None
-    if not blocks:
-        ept = (info["col_chunk"] if dom_is_col else info["row_chunk"]) // 256
-        dom_kernel = f"void k_pass<float, {fmt}, {1 if dom_is_col else 0}, 256, {ept}>(PassArgs<float>, int)"
-    traffic = measured_traffic(dom_kernel) if dom_kernel else None
+    ept = (info["col_chunk"] if dom_is_col else info["row_chunk"]) // 256
+    if blocks > 0:  # gather-blocked pass: partial sums, then the combine with the epilogue
+        dom_kernels = [f"void k_bpart<float, float, {fmt}, 256, {ept}>(PassArgs<float>, int, int)",
+                       f"void k_bcombine<float, {1 if dom_is_col else 0}>(PassArgs<float>, int)"]
+    elif blocks == 0:
+        dom_kernels = [f"void k_pass<float, {fmt}, {1 if dom_is_col else 0}, 256, {ept}>(PassArgs<float>, int)"]
+    else:
+        dom_kernels = None
+    traffic = measured_traffic(dom_kernels) if dom_kernels else None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
                     kernel=("column" if dom_is_col else "row") + " pass (" +

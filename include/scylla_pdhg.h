@@ -256,9 +256,9 @@ typedef struct {
     int32_t row_blocks, col_blocks; /* layout of each pass: 0 normal, 2, 4 or
                                        8 gather blocks, -1 LDS-staged        */
     int32_t row_staged_nnz, col_staged_nnz; /* staged tile size (nonzeros)  */
-    int32_t row_staged_variant, col_staged_variant; /* staged kernel variant:
-                                       sub-tile 4096 (0, 1) or 8192 (2, 3)
-                                       nonzeros; odd = operand prefetch      */
+    int32_t row_staged_variant, col_staged_variant; /* staged kernel variant
+                                       bits: 1 operand prefetch, 2 sub-tiles
+                                       of 8192 nonzeros (else 4096)         */
     int32_t row_sliced, col_sliced; /* instances of an LDS-staged pass whose
                                        gathered vector is processed in LDS
                                        slices (partial sums + row combine)   */

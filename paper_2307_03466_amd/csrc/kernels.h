@@ -94,7 +94,11 @@ void launch_step(const StepArgs &a, int count, hipStream_t s);
 // sub-tile 4 (v = 0, 1) or 8 (v = 2, 3); odd v prefetch the next
 // sub-tile's row bounds and epilogue operands as well.
 constexpr int SPASS_NT = 1024;
-inline int spass_chunk(int variant) { return SPASS_NT * (variant >= 2 ? 8 : 4); }
+inline int spass_chunk(int variant) { return SPASS_NT * ((variant & 2) ? 8 : 4); }
+// Sub-tile descriptors (rows and nonzero ranges) a staged workgroup keeps in
+// static LDS, and the static LDS that takes (the dynamic part must leave it).
+constexpr int SPASS_DMAX = 64;
+constexpr int SPASS_STATIC_LDS = 4 * SPASS_DMAX * 4;
 
 // Fused check window for instances that fit in LDS (k_tiny).
 template <class V>

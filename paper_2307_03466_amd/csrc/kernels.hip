@@ -399,6 +399,38 @@ __global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int
 // rows, <= NT*EPT nonzeros each): every gather is an LDS read.  The loop is
 // software-pipelined: the coalesced loads of sub-tile t+1's nonzeros are in
 // flight while sub-tile t's rows are reduced and updated.
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (__syncthreads also waits for them, which would
+// serialise the prefetch of the next sub-tile with the current one).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// dst[0, n) = src[0, n) into LDS by NT threads with U loads in flight per
+// thread: a plain strided loop waits for each load before its LDS store,
+// which makes the copy one memory latency per NT elements.
+template <int NT, int U, class V>
+__device__ __forceinline__ void copy_to_lds(V *dst, const V *__restrict__ src, int n)
+{
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < n; k0 += NT * U) {
+        V t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * NT + tid;
+            t[u] = k < n ? src[k] : (V)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * NT + tid;
+            if (k < n) dst[k] = t[u];
+        }
+    }
+}
+
 template <class V, int FMT, int NT, int EPT>
 __device__ __forceinline__ void spass_load(const MatView &M, int e0, int e1, uint32_t (&w)[EPT], V (&a)[EPT])
 {
@@ -442,6 +474,17 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
         Ps = p.xP + (size_t)sl * p.rows;
     }
     double ip[2] = {0.0, 0.0};
+    // Descriptors of the first SPASS_DMAX sub-tiles (first row, end row,
+    // first and end nonzero) go to LDS with the vector, so that starting
+    // the next sub-tile's loads needs no dependent global reads.
+    __shared__ int sdesc[4][SPASS_DMAX];
+    for (int u = tid; u < T.y - T.x && u < SPASS_DMAX; u += NT) {
+        const int4 d = sub[T.x + u];
+        sdesc[0][u] = d.x;
+        sdesc[1][u] = d.y;
+        sdesc[2][u] = M.ptr[d.x];
+        sdesc[3][u] = M.ptr[d.y];
+    }
     // sub-tile state (nonzeros in registers one sub-tile ahead; with PF also
     // this thread's first row bounds and epilogue operands)
     int4 D = sub[T.x];
@@ -460,8 +503,8 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
         }
     }
-    for (int k = tid; k < glen; k += NT) sv[k] = p.gvec[g0 + k];
-    __syncthreads();
+    copy_to_lds<NT, 64 / sizeof(V)>(sv, p.gvec + g0, glen);
+    lds_barrier();
     for (int t = T.x; t < T.y; ++t) {
         // products of sub-tile t from the registers
 #pragma unroll
@@ -491,13 +534,21 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
                 if (!part && (tid & (Lc - 1)) == 0) load_ops<V, DIR>(p, r0c + rc, opc);
             }
         }
-        __syncthreads();
+        lds_barrier();
         // sub-tile t+1's nonzeros (and with PF its row bounds and operands)
         // are in flight during this reduction
         if (t + 1 < T.y) {
-            D = sub[t + 1];
-            e0 = M.ptr[D.x];
-            e1 = M.ptr[D.y];
+            const int u = t + 1 - T.x;
+            if (u < SPASS_DMAX) {
+                D.x = sdesc[0][u];
+                D.y = sdesc[1][u];
+                e0 = sdesc[2][u];
+                e1 = sdesc[3][u];
+            } else {
+                D = sub[t + 1];
+                e0 = M.ptr[D.x];
+                e1 = M.ptr[D.y];
+            }
             spass_load<V, FMT, NT, EPT>(M, e0, e1, w, a);
             if (PF) {
                 L = lanes_per_row<NT>(D.y - D.x);
@@ -525,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
                 if (!part && lane == 0) load_ops<V, DIR>(p, r0c + rn, opc);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (p.adapt && !part) {
         // the product buffer is free after the last barrier
@@ -1565,7 +1616,9 @@ static void staged_v(const PassArgs<V> &p, int jw, size_t shmem, hipStream_t s, 
 template <class V, int FMT, int DIR>
 static void staged_t(const PassArgs<V> &p, int variant, int jw, size_t shmem, hipStream_t s, bool prepare)
 {
-    switch (variant) {
+    // variant bits: 1 = prefetch row bounds and operands, 2 = 8 nonzeros per
+    // thread (else 4)
+    switch (variant & 3) {
     case 0: staged_v<V, FMT, DIR, 4, false>(p, jw, shmem, s, prepare); break;
     case 1: staged_v<V, FMT, DIR, 4, true>(p, jw, shmem, s, prepare); break;
     case 2: staged_v<V, FMT, DIR, 8, false>(p, jw, shmem, s, prepare); break;

@@ -386,7 +386,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
     const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
     const int32_t chunk = spass_chunk(variant);
-    const int32_t max_vec = (half ? h->lds_max / 2 : h->lds_max) / h->vbytes - chunk;
+    const int32_t max_vec = ((half ? h->lds_max / 2 : h->lds_max) - SPASS_STATIC_LDS) / h->vbytes - chunk;
     plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * ept, o.splan);
     std::vector<int32_t> tiles = o.splan.tiles;
     if (slice) {
@@ -869,7 +869,7 @@ void autotune(scylla_batch *h)
         // whole or in up to four slices
         const std::vector<int32_t> &g = o.row ? h->col_off : h->row_off;
         bool any = false, any_slice = false;
-        const int64_t vmax = h->lds_max / h->vbytes - spass_chunk(0);
+        const int64_t vmax = (h->lds_max - SPASS_STATIC_LDS) / h->vbytes - spass_chunk(0);
         for (int32_t q = 0; q < h->count; ++q) {
             any |= g[q + 1] - g[q] <= vmax;
             any_slice |= g[q + 1] - g[q] > vmax / 2 && g[q + 1] - g[q] <= 4 * vmax;

@@ -132,3 +132,29 @@ def test_free_variables_and_equalities(prec):
     A[rows, lp.col_idx] = lp.val
     lp.b = A @ lp.x_star
     _check100(lp, prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_staged_tile_with_many_sub_tiles(prec):
+    """An LDS-staged tile keeps the descriptors of its first 64 sub-tiles in
+    LDS and reads the others from memory: 400k rows, almost all empty, put
+    about a hundred sub-tiles of up to 4096 rows into one tile of the row
+    pass, so both paths run."""
+    m, n = 400_000, 3000
+    full = np.zeros(m, dtype=np.int64)
+    full[::997] = 3
+    full[-1] = 5
+    nz = np.flatnonzero(full)
+    dense_rows = _lp_rows(full[nz].tolist(), n, seed=11)  # the non-empty rows
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(full, out=row_ptr[1:])
+    b = np.full(m, -1.0)
+    b[nz] = dense_rows.b
+    lp = I.LP(m=m, n=n, row_ptr=row_ptr, col_idx=dense_rows.col_idx, val=dense_rows.val, c=dense_rows.c, b=b,
+              senses=np.full(m, ord("G"), dtype=np.uint8), l=np.zeros(n), u=np.ones(n),
+              is_int=np.zeros(n, dtype=np.uint8))
+    _check100(lp, prec, layout=(-1, 8, -1, 8), fused=0)
+    with pdhg.Batch([lp], precision=prec) as b:
+        b.set_layout(-1, 8, -1, 8)
+        info = b.info()
+    assert info["row_blocks"] == -1

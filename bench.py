@@ -135,7 +135,10 @@ def other_workloads(pdhg, instances, args, R):
         s = pdhg.solve(lp, tol=1e-4, iter_limit=200_000, precision=pdhg.FP64)
         t = time.perf_counter()
         xh, feas, ign = pdhg.fix_propagate(lp, s.x)
-        out["set_cover_200x500_fp64"] = dict(iter_per_s=round(r["iter_per_s"], 1), to_tol=r["to_tol"],
+        out["set_cover_200x500_fp64"] = dict(iter_per_s=round(r["iter_per_s"], 1),
+                                             canonical_GBps=round(canonical_bytes(lp.m, lp.n, lp.nnz, True)
+                                                                  * r["iter_per_s"] / 1e9, 2),
+                                             to_tol=r["to_tol"],
                                              to_tol_adaptive_steps=r["to_tol_adaptive"],
                                              rounding_s=round(time.perf_counter() - t, 6),
                                              rounding_feasible=feas, rounded_obj=float(lp.c @ xh))
@@ -206,6 +209,9 @@ def other_workloads(pdhg, instances, args, R):
                                   rounding_seconds=round(rounding_s, 3), tune_seconds=round(tune_s, 3),
                                   groups=len({r["group"] for r in recs[0]}),
                                   batch_iterations=sum(its), batch_iter_per_s=round(sum(its) / solve_s, 1),
+                                  canonical_GBps=round(canonical_bytes(sum(l.m for l in lps), sum(l.n for l in lps),
+                                                                       sum(l.nnz for l in lps))
+                                                       * sum(its) / solve_s / 1e9, 1),
                                   instance_iterations=inst_its,
                                   instance_iter_per_s=round(inst_its / solve_s, 1),
                                   iterations_round1=its[0], iterations_last=its[-1],

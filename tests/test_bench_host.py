@@ -1,0 +1,50 @@
+"""Host checks of bench.py: the one-GPU contract and the byte models the
+bandwidth figures are computed from."""
+import os
+import subprocess
+import sys
+
+import bench
+from paper_2307_03466_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_canonical_bytes_by_hand():
+    """BF16 values and int32 indices in both orientations (6 B per nonzero
+    each), the pointers, 28 B per column (x, c, l, u, D_c^2 read, x and
+    x_bar written), 17 B per row (y, b, D_r^2 read, sense, y written) and
+    one full read of each gathered vector; FP64 doubles every value."""
+    m, n, nnz = 3, 5, 7
+    assert bench.canonical_bytes(m, n, nnz) == 2 * 7 * 6 + 4 * 4 + 4 * 6 + 28 * 5 + 17 * 3 + 4 * 8
+    assert bench.canonical_bytes(m, n, nnz, True) == 2 * 7 * 12 + 4 * 4 + 4 * 6 + 56 * 5 + 33 * 3 + 8 * 8
+
+
+def test_canonical_bytes_of_the_headline_workload():
+    """The 1M x 2M LP with 10M nonzeros moves about 217 MB per FP32
+    iteration and 421 MB per FP64 iteration under the canonical model."""
+    m, n, nnz = 1_000_000, 2_000_000, 10_008_313
+    assert abs(bench.canonical_bytes(m, n, nnz) / 1e6 - 217) < 2
+    assert abs(bench.canonical_bytes(m, n, nnz, True) / 1e6 - 421) < 3
+
+
+def test_pass_bytes_follow_the_storage_format():
+    info = dict(m_total=10, n_total=20, nnz_total=100, format=0)  # packed integers: no value bytes
+    row, col = bench.pass_bytes(info, 4)
+    assert row == 100 * 4 + 4 * 11 + 4 * 20 + 17 * 10
+    assert col == 100 * 4 + 4 * 21 + 4 * 10 + 28 * 20
+    info["format"] = 3  # FP64 values
+    row, col = bench.pass_bytes(info, 8)
+    assert row == 100 * 12 + 4 * 11 + 8 * 20 + 33 * 10
+    assert col == 100 * 12 + 4 * 21 + 8 * 10 + 56 * 20
+
+
+def test_pump_workload_shape():
+    lps = I.pump_batch(2, 2000, 4000)
+    assert [(lp.m, lp.n) for lp in lps] == [(2000, 4000)] * 2

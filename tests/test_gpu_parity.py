@@ -431,3 +431,31 @@ def test_stall_counting_in_a_batch(prec):
         assert [r["iterations"] for r in res] == [192] * 3
         res = b.solve(tol=1e-9, iter_limit=128, stall_tol=1e300, stall_checks=3)
         assert [r["status"] for r in res] == [pdhg.ITERATION_LIMIT] * 3
+
+
+@pytest.mark.parametrize("name,st", [("cover200", 1e-4), ("knapsack", 1e-5)])
+def test_fp32_stall_point_restated(name, st):
+    """FP32: the device stops where the objective bounds of its own
+    iterates, evaluated by the oracle at every check (a run limited to that
+    check reproduces the longer run up to it), first held still three checks
+    in a row."""
+    lp = _case(name)
+    R, W = 64, 3
+    kw = dict(tol=1e-9, precision=1, autotune=0, fused_window=0)
+    s = pdhg.solve(lp, iter_limit=60_000, stall_tol=st, stall_checks=W, **kw)
+    assert s.result["status"] == pdhg.STALLED and s.result["iterations"] % R == 0
+    nchk = s.result["iterations"] // R
+    PD = []
+    for c in range(nchk + 1):
+        t = pdhg.solve(lp, iter_limit=c * R, **kw)
+        k = oracle.kkt(lp, t.x, t.y)
+        PD.append((k["pobj"], k["dobj"]))
+    run, first = 0, None
+    for c in range(1, nchk + 1):
+        still = (abs(PD[c][0] - PD[c - 1][0]) <= st * (1 + abs(PD[c][0])) and
+                 abs(PD[c][1] - PD[c - 1][1]) <= st * (1 + abs(PD[c][1])))
+        run = run + 1 if still else 0
+        if run >= W:
+            first = c
+            break
+    assert first == nchk, (first, nchk)

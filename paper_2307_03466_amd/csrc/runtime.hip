@@ -1,200 +1,13 @@
-// Runtime and C ABI of the PDHG library: device-resident batches of LPs,
-// device-side preconditioning, tile plans and their autotuner, hipGraph
+// Solver runtime and C ABI of the PDHG library: device-resident batches of
+// LPs, device-side preconditioning, tile plans and their autotuner, hipGraph
 // capture of one check window (KKT check + decision + R iterations), and
 // the host loop that launches windows and polls one status copy per window.
-#include <errno.h>
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include <string.h>
+// The pump loop of Algorithm 1 is in pump.hip.
+#include "batch.h"
 
-#include <algorithm>
-#include <chrono>
-#include <cstdio>
-#include <memory>
-#include <stdexcept>
-#include <string>
-#include <vector>
-
-#include <atomic>
-#include <cstdlib>
-#include <fstream>
-#include <map>
-#include <mutex>
-#include <sstream>
-#include <thread>
-
-#include "fixprop.h"
-#include "kernels.h"
-#include "scylla_internal.h"
-
-namespace {
-
+namespace scy {
 thread_local std::string g_err;
-
-struct Err {
-    int code;
-    std::string msg;
-};
-
-[[noreturn]] void throw_err(int code, const std::string &msg) { throw Err{code, msg}; }
-
-void hip_check(hipError_t e, const char *what)
-{
-    if (e != hipSuccess) {
-        const int code = (e == hipErrorOutOfMemory) ? -ENOMEM : -EIO;
-        throw_err(code, std::string(what) + ": " + hipGetErrorString(e));
-    }
-}
-#define HIPC(x) hip_check((x), #x)
-
-double now_s()
-{
-    using namespace std::chrono;
-    return duration<double>(steady_clock::now().time_since_epoch()).count();
-}
-
-// Owned device allocation.
-struct DevMem {
-    void *p = nullptr;
-    size_t bytes = 0;
-    DevMem() = default;
-    DevMem(const DevMem &) = delete;
-    DevMem &operator=(const DevMem &) = delete;
-    ~DevMem() { release(); }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    void alloc(size_t b)
-    {
-        release();
-        bytes = b;
-        HIPC(hipMalloc(&p, b > 0 ? b : 16));
-    }
-    template <class T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-template <class T>
-void upload(DevMem &d, const std::vector<T> &h, hipStream_t s)
-{
-    d.alloc(h.size() * sizeof(T));
-    if (!h.empty()) HIPC(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
-
-}  // namespace
-
-using namespace scy;
-
-// One orientation of the matrix on the device: the CSR (row pass, dual
-// step) or the CSC copy (column pass, primal step), in its normal layout or
-// its gather-blocked layout, with the tile plan in use and its buffers.
-struct OrientRT {
-    bool row = true;
-    int32_t rows = 0, gather = 0;
-    HostOrient host;  // normal layout (host copy kept for re-planning)
-    DevMem ptr, ent, val;
-    MatView mat{};
-    TilePlan plan;
-    int32_t ept = 8;
-    // gather-blocked layout (when chosen)
-    bool blocked = false;
-    BlockedHost bh;  // host copy of the block pointers (entries dropped after upload)
-    DevMem bptr, bent, bval;
-    MatView bmat{};
-    BlockedPlan bplan;
-    DevMem P, P64, ctiles;
-    // LDS-staged layout (when chosen): staged tiles for instances whose
-    // gathered vector fits in LDS, normal tiles for the rest
-    bool staged = false;
-    StagedPlan splan;
-    DevMem stiles, subtiles, gofs, rtiles, rlongs, rseg;
-    size_t shmem = 0;
-    int32_t staged_nnz = 0;
-    int32_t svariant = 0;
-    // LDS-sliced instances of the staged layout (when enabled): the regrouped
-    // entries are kept for the (max_vec, sub-tile) they were built for
-    bool sliced = false;
-    bool shalf = false;   // half-LDS budget per workgroup
-    int32_t nstiles = 0;  // staged + sliced tiles
-    SlicedPlan xplan;
-    int32_t x_max_vec = -1, x_sub = -1;
-    DevMem xptr, xent, xval, xsub, xctiles, xP;
-    // plan buffers
-    DevMem tiles, longs, seg, seg64, part, lpart;
-    // adaptive-step partials: 2 doubles per epilogue slot; slot spaces of the
-    // launches of the active layout start at these offsets
-    DevMem ipart;
-    int32_t ipo_long = 0, ipo_comb = 0, ipo_rest = 0, ipo_rlong = 0, ip_slots = 0;
-    int32_t ntiles() const { return (int32_t)((blocked ? bplan.tiles.size() : plan.tiles.size()) / 4); }
-    int32_t nlong() const { return (int32_t)((blocked ? bplan.longs.size() : plan.longs.size()) / 4); }
-};
-
-struct scylla_batch {
-    int32_t count = 0, precision = SCYLLA_FP32, fmt = FMT_PACKED;
-    int32_t vbytes = 4;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipStream_t cap = nullptr;  // private stream used for graph capture
-    hipStream_t side = nullptr; // second branch (staged and normal tiles overlap)
-    hipEvent_t fork = nullptr, join = nullptr;
-    int32_t M = 0, N = 0;
-    int64_t NNZ = 0;
-    std::vector<int32_t> row_off, col_off;
-    OrientRT orow, ocol;
-    // vectors in the path precision
-    DevMem x, xbar, xr, y, yr, cv, lv, uv, dc2, b_v, dr2;
-    DevMem sense;
-    // FP64 data
-    DevMem c64, corig64, l64, u64, b64, dr64, dc64;
-    DevMem st, info;
-    DevMem ax;              // running A x of the row pass (adaptive steps)
-    DevMem q64, qv;         // diagonal Hessian (QP objectives), once set
-    DevMem xp, yp, axp, atyp;  // previous check's point and products
-    bool has_q = false;
-    bool adaptive = false;  // adaptive step sizes in the current graph
-    DevMem bits_tmp, ibits_tmp;
-    DevMem mip_isint, mip_rbad, mip_cbad, mip_ok;  // MIP-feasibility check
-    // graph
-    hipGraphExec_t gexec = nullptr;
-    int32_t graph_R = 0;
-    bool tuned = false;
-    int32_t lds_max = 65536;  // dynamic LDS bytes a workgroup may use
-    bool tiny_ok = false;     // every instance fits the fused window
-    size_t tiny_shmem = 0;
-    bool graph_tiny = false;
-    bool graph_adapt = false;
-    // host copy of the problem (for the pump's rounding on the host)
-    std::vector<double> hval, hb, hl, hu, hc;
-    std::vector<char> hsense;
-    struct LocalLP {
-        std::vector<int32_t> ptr, col, cptr, crow;
-        std::vector<double> cval;
-        FPProblem P;
-    };
-    std::vector<LocalLP> local;  // built on the first pump call
-    std::vector<double> pump_best;
-    // host mirrors
-    std::vector<InstInfo> hinfo;
-    InstState *pinned = nullptr;  // 2 * count states
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    double setup_seconds = 0.0;
-
-    ~scylla_batch()
-    {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (pinned) (void)hipHostFree(pinned);
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (cap) (void)hipStreamDestroy(cap);
-        if (side) (void)hipStreamDestroy(side);
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-    }
-};
+}  // namespace scy
 
 namespace {
 
@@ -1013,30 +826,14 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     HIPC(hipStreamSynchronize(s));
 }
 
+}  // namespace
+
+namespace scy {
+
 int fail_code(const Err &e)
 {
     g_err = e.msg;
     return e.code;
-}
-
-template <class F>
-int guarded(F &&f)
-{
-    try {
-        g_err.clear();
-        return f();
-    } catch (const Err &e) {
-        return fail_code(e);
-    } catch (const std::bad_alloc &) {
-        g_err = "host allocation failed";
-        return -ENOMEM;
-    } catch (const std::exception &e) {
-        g_err = e.what();
-        return -EIO;
-    } catch (...) {
-        g_err = "unknown error";
-        return -EIO;
-    }
 }
 
 int validate_params(const scylla_params *p)
@@ -1102,12 +899,8 @@ void fill_result(const InstState &S, scylla_result &r, double solve_s, double se
     r.setup_seconds = setup_s;
 }
 
-// k_limits (optional, [count]): per-instance iteration limit of this solve;
-// an instance with a limit <= 0 takes no part (its state is left as it is).
-// Only instances [q0, q1) (q1 < 0: all) have their start points projected
-// (and zeroed on a cold start); the others must have limits <= 0.
 int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results,
-                     const int64_t *k_limits = nullptr, int32_t q0 = 0, int32_t q1 = -1)
+                     const int64_t *k_limits, int32_t q0, int32_t q1)
 {
     if (q1 < 0) q1 = h ? h->count : 0;
     if (!h || !results) throw_err(-EINVAL, "handle or results is NULL");
@@ -1199,117 +992,6 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     return 0;
 }
 
-template <class V>
-void get_range(scylla_batch *h, const DevMem &d, int32_t lo, int32_t len, double *out)
-{
-    if (len <= 0 || !out) return;
-    if (sizeof(V) == 8) {
-        HIPC(hipMemcpyAsync(out, d.as<char>() + (size_t)lo * 8, (size_t)len * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPC(hipStreamSynchronize(h->stream));
-    } else {
-        std::vector<float> tmp(len);
-        HIPC(hipMemcpyAsync(tmp.data(), d.as<char>() + (size_t)lo * 4, (size_t)len * 4, hipMemcpyDeviceToHost, h->stream));
-        HIPC(hipStreamSynchronize(h->stream));
-        for (int32_t i = 0; i < len; ++i) out[i] = (double)tmp[i];
-    }
-}
-
-template <class V>
-void put_range(scylla_batch *h, DevMem &d, int32_t lo, int32_t len, const double *in)
-{
-    if (len <= 0) return;
-    if (sizeof(V) == 8) {
-        HIPC(hipMemcpyAsync(d.as<char>() + (size_t)lo * 8, in, (size_t)len * 8, hipMemcpyHostToDevice, h->stream));
-        HIPC(hipStreamSynchronize(h->stream));
-    } else {
-        std::vector<float> tmp(len);
-        for (int32_t i = 0; i < len; ++i) tmp[i] = (float)in[i];
-        HIPC(hipMemcpyAsync(d.as<char>() + (size_t)lo * 4, tmp.data(), (size_t)len * 4, hipMemcpyHostToDevice, h->stream));
-        HIPC(hipStreamSynchronize(h->stream));
-    }
-}
-
-// Integer flags [N] of the MIP-feasibility check (NULL: all integer).
-void set_mip_isint(scylla_batch *h, const uint8_t *is_int)
-{
-    const size_t N = (size_t)std::max(h->N, 1);
-    if (h->mip_isint.bytes < N) h->mip_isint.alloc(N);
-    if (h->mip_rbad.bytes < (size_t)std::max(h->M, 1)) h->mip_rbad.alloc((size_t)std::max(h->M, 1));
-    if (h->mip_cbad.bytes < N) h->mip_cbad.alloc(N);
-    if (h->mip_ok.bytes < (size_t)h->count) h->mip_ok.alloc((size_t)h->count);
-    std::vector<uint8_t> ii(N, 1);
-    if (is_int)
-        for (int32_t j = 0; j < h->N; ++j) ii[j] = is_int[j] ? 1 : 0;
-    HIPC(hipMemcpyAsync(h->mip_isint.p, ii.data(), N, hipMemcpyHostToDevice, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
-}
-
-// MIP-feasibility of every instance's current x, on the device (integer
-// flags from set_mip_isint); ok: [count] 1 / 0.
-void mip_check(scylla_batch *h, double tol, uint8_t *ok)
-{
-    const OrientRT &o = h->orow;
-    if (h->vbytes == 4)
-        launch_mip_check<float>(o.mat, h->fmt, h->M, h->N, h->count, h->info.as<InstInfo>(), h->x.as<float>(),
-                                h->b64.as<double>(), h->sense.as<uint8_t>(), h->l64.as<double>(),
-                                h->u64.as<double>(), h->mip_isint.as<uint8_t>(), tol, h->mip_rbad.as<uint8_t>(),
-                                h->mip_cbad.as<uint8_t>(), h->mip_ok.as<uint8_t>(), h->stream);
-    else
-        launch_mip_check<double>(o.mat, h->fmt, h->M, h->N, h->count, h->info.as<InstInfo>(), h->x.as<double>(),
-                                 h->b64.as<double>(), h->sense.as<uint8_t>(), h->l64.as<double>(),
-                                 h->u64.as<double>(), h->mip_isint.as<uint8_t>(), tol, h->mip_rbad.as<uint8_t>(),
-                                 h->mip_cbad.as<uint8_t>(), h->mip_ok.as<uint8_t>(), h->stream);
-    HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(ok, h->mip_ok.p, (size_t)h->count, hipMemcpyDeviceToHost, h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
-}
-
-void build_locals(scylla_batch *h)
-{
-    if (!h->local.empty()) return;
-    h->local.resize(h->count);
-    const OrientRT &o = h->orow;
-    for (int32_t q = 0; q < h->count; ++q) {
-        auto &L = h->local[q];
-        const int32_t r0 = h->row_off[q], r1 = h->row_off[q + 1], c0 = h->col_off[q];
-        const int32_t e0 = o.host.ptr[r0];
-        L.ptr.resize(r1 - r0 + 1);
-        for (int32_t i = r0; i <= r1; ++i) L.ptr[i - r0] = o.host.ptr[i] - e0;
-        const int32_t nnz = o.host.ptr[r1] - e0;
-        L.col.resize(nnz);
-        for (int32_t e = 0; e < nnz; ++e) {
-            const uint32_t w = o.host.ent[e0 + e];
-            L.col[e] = (int32_t)(h->fmt == FMT_PACKED ? (w & o.host.mask) : w) - c0;
-        }
-        FPProblem &P = L.P;
-        P.m = r1 - r0;
-        P.n = h->col_off[q + 1] - c0;
-        P.ptr = L.ptr.data();
-        P.col = L.col.data();
-        P.val = h->hval.data() + e0;
-        P.b = h->hb.data() + r0;
-        P.sense = h->hsense.data() + r0;
-        P.l = h->hl.data() + c0;
-        P.u = h->hu.data() + c0;
-        build_incidence(P, L.cptr, L.crow, L.cval);
-    }
-}
-
-template <class F>
-void parallel_for(int32_t count, int32_t threads, F &&f)
-{
-    int32_t nt = threads > 0 ? threads : (int32_t)std::max(1u, std::thread::hardware_concurrency());
-    nt = std::max(1, std::min(nt, count));
-    std::atomic<int32_t> next{0};
-    auto worker = [&]() {
-        for (int32_t q = next++; q < count; q = next++) f(q);
-    };
-    std::vector<std::thread> pool;
-    for (int32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
-    worker();
-    for (auto &t : pool) t.join();
-}
-
 // Allocates the diagonal Hessian (zero) on first use; the kernels then take
 // the QP form of the primal step, so the graph is rebuilt.
 void ensure_q(scylla_batch *h)
@@ -1330,404 +1012,7 @@ void cast_q(scylla_batch *h)
     else launch_cast<double>(h->q64.as<double>(), h->qv.as<double>(), h->N, h->stream);
 }
 
-void reset_objective(scylla_batch *h)
-{
-    if (h->has_q) {
-        HIPC(hipMemsetAsync(h->q64.p, 0, h->q64.bytes, h->stream));
-        HIPC(hipMemsetAsync(h->qv.p, 0, h->qv.bytes, h->stream));
-    }
-    HIPC(hipMemcpyAsync(h->c64.p, h->corig64.p, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
-    if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>(), h->cv.as<float>(), h->N, h->stream);
-    else launch_cast<double>(h->c64.as<double>(), h->cv.as<double>(), h->N, h->stream);
-    launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
-                      h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
-    HIPC(hipGetLastError());
-}
-
-// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as a counter-based
-// generator: the output function applied to the state seed + (counter + 1) *
-// the golden-ratio increment.
-uint64_t splitmix64(uint64_t seed, uint64_t counter)
-{
-    uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// Number of binaries the K-th perturbation of instance q flips, in [10, 30].
-int32_t perturb_count(uint64_t seed, int32_t q, int32_t K)
-{
-    return 10 + (int32_t)(splitmix64(seed, (uint64_t)q * 1048576ull + (uint64_t)K) % 21ull);
-}
-
-// Per-instance history of roundings for cycle detection: value hashes first,
-// then exact comparison (0.0 and -0.0 compare equal).
-struct RoundingHistory {
-    std::vector<uint64_t> hash;
-    std::vector<std::vector<double>> pts;
-
-    static uint64_t digest(const double *x, int32_t n)
-    {
-        uint64_t hsh = 1469598103934665603ull;
-        for (int32_t j = 0; j < n; ++j) {
-            double v = x[j] + 0.0;
-            uint64_t w;
-            memcpy(&w, &v, 8);
-            hsh = (hsh ^ w) * 1099511628211ull;
-        }
-        return hsh;
-    }
-    bool seen(const double *x, int32_t n) const
-    {
-        const uint64_t d = digest(x, n);
-        for (size_t k = 0; k < pts.size(); ++k) {
-            if (hash[k] != d) continue;
-            bool eq = true;
-            for (int32_t j = 0; j < n && eq; ++j) eq = pts[k][j] == x[j];
-            if (eq) return true;
-        }
-        return false;
-    }
-    void add(const double *x, int32_t n)
-    {
-        hash.push_back(digest(x, n));
-        pts.emplace_back(x, x + n);
-    }
-};
-
-struct PumpOpts {
-    int32_t rounds;
-    bool eps_sched;
-    double eps1, beta, eps_floor, alpha;
-    int64_t total_iter_limit;
-    bool early_exit, perturb;
-    uint64_t seed;
-    int32_t threads;
-    int32_t distance;  // 1: L1 (linear objective), 2: L2 (QP objective)
-    bool pipeline;     // two instance groups: host rounding overlaps device solves
-};
-
-// Algorithm 1 outer loop.  legacy_best: also keep, per instance, the first
-// feasible rounding else the last one (scylla_batch_pump's output).
-int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, const PumpOpts &o,
-              scylla_pump_record *rec, scylla_pump_outcome *outc, double *x_out, bool legacy_best)
-{
-    if (!h) throw_err(-EINVAL, "handle is NULL");
-    if (o.rounds < 1) throw_err(-EINVAL, "rounds must be >= 1");
-    if (!(o.alpha >= 0.0 && o.alpha < 1.0)) throw_err(-EINVAL, "alpha must be in [0, 1)");
-    if (o.eps_sched && !(o.eps1 > 0.0 && o.beta > 0.0 && o.beta <= 1.0 && o.eps_floor > 0.0))
-        throw_err(-EINVAL, "eps schedule needs eps1 > 0, 0 < beta <= 1, eps_floor > 0");
-    if (o.total_iter_limit < 0) throw_err(-EINVAL, "total_iter_limit must be >= 0");
-    if (o.distance != 1 && o.distance != 2) throw_err(-EINVAL, "distance must be 1 (L1) or 2 (L2)");
-    validate_params(p);
-    build_locals(h);
-    const bool l2 = o.distance == 2;
-    if (l2) ensure_q(h);
-    const int32_t N = h->N, count = h->count;
-    std::vector<uint8_t> isint(N, 1);
-    if (is_int)
-        for (int32_t j = 0; j < N; ++j) isint[j] = is_int[j] ? 1 : 0;
-    // kappa_q = sqrt(|I_q|) / ||c_q|| (0 when c = 0: the term is dropped)
-    std::vector<double> kappa(count, 0.0);
-    std::vector<size_t> boff(count + 1, 0);
-    for (int32_t q = 0; q < count; ++q) {
-        double cn = 0.0;
-        int64_t nI = 0;
-        for (int32_t j = h->col_off[q]; j < h->col_off[q + 1]; ++j) {
-            cn += h->hc[j] * h->hc[j];
-            nI += isint[j];
-        }
-        kappa[q] = cn > 0.0 ? sqrt((double)nI) / sqrt(cn) : 0.0;
-        boff[q + 1] = boff[q] + (size_t)(h->col_off[q + 1] - h->col_off[q] + 7) / 8;
-    }
-    std::vector<uint8_t> xbits(boff[count]), ibits(boff[count]);
-    for (int32_t q = 0; q < count; ++q)
-        for (int32_t j = h->col_off[q]; j < h->col_off[q + 1]; ++j) {
-            const int32_t k = j - h->col_off[q];
-            if (isint[j]) ibits[boff[q] + k / 8] |= (uint8_t)(1u << (k % 8));
-        }
-    if (h->bits_tmp.bytes < boff[count]) h->bits_tmp.alloc(boff[count]);
-    if (h->ibits_tmp.bytes < boff[count]) h->ibits_tmp.alloc(boff[count]);
-    HIPC(hipMemcpyAsync(h->ibits_tmp.p, ibits.data(), boff[count], hipMemcpyHostToDevice, h->stream));
-    set_mip_isint(h, isint.data());
-    reset_objective(h);
-    HIPC(hipStreamSynchronize(h->stream));
-
-    std::vector<double> xhat(N), xres(N, 0.0);
-    std::vector<double> chat, qhat;  // L2: next objective and Hessian
-    if (l2) {
-        chat = h->hc;
-        qhat.assign(N, 0.0);
-    }
-    if (legacy_best) h->pump_best.assign(N, 0.0);
-    std::vector<uint8_t> found_best(count, 0), active(count, 1);
-    std::vector<scylla_pump_outcome> out(count);
-    memset(out.data(), 0, sizeof(scylla_pump_outcome) * count);
-    std::vector<RoundingHistory> hist(o.perturb ? count : 0);
-    std::vector<FPPrep> prep(count);  // per-instance rounding state, built on first use
-    if (rec) memset(rec, 0, sizeof(scylla_pump_record) * (size_t)o.rounds * count);
-    std::vector<double> eps_k(o.rounds + 1, o.eps1);  // tolerance of round K (schedule)
-    for (int32_t K = 2; K <= o.rounds; ++K) eps_k[K] = std::max(o.beta * eps_k[K - 1], o.eps_floor);
-
-    // Instances run in one group, or in two groups of contiguous instances
-    // (split at half the nonzeros) whose rounds alternate on the device: the
-    // host rounds one group while the device solves the other.  Every
-    // instance sees the same sequence of solves, roundings and objective
-    // updates either way (a batched solve equals solves of its instances).
-    struct Group {
-        int32_t q0 = 0, q1 = 0, K = 1;
-        std::vector<double> x;                // iterate copied out after the solve
-        std::vector<uint8_t> ok;              // device MIP-feasibility flags
-        std::vector<scylla_result> res;
-        std::vector<int64_t> limits;
-        double solve_s = 0.0, rounding_s = 0.0;
-    };
-    const int ng = (o.pipeline && count >= 2) ? 2 : 1;
-    Group G[2];
-    {
-        int32_t mid = count;
-        if (ng == 2) {
-            const int64_t total = h->orow.host.ptr[h->M];
-            mid = 1;
-            while (mid < count - 1 && (int64_t)h->orow.host.ptr[h->row_off[mid]] * 2 < total) ++mid;
-        }
-        G[0].q0 = 0;
-        G[0].q1 = mid;
-        G[1].q0 = mid;
-        G[1].q1 = count;
-        for (int g = 0; g < ng; ++g) {
-            G[g].x.assign(N, 0.0);
-            G[g].ok.assign(count, 0);
-            G[g].res.resize(count);
-            G[g].limits.assign(count, 0);
-        }
-    }
-
-    // Solves round G.K of a group; false when it has nothing left to solve.
-    auto solve_group = [&](Group &g) -> bool {
-        if (g.K > o.rounds) return false;
-        int32_t n_active = 0;
-        for (int32_t q = 0; q < count; ++q) g.limits[q] = 0;
-        for (int32_t q = g.q0; q < g.q1; ++q) {
-            int64_t lim = p->iter_limit;
-            if (o.total_iter_limit > 0) lim = std::min(lim, o.total_iter_limit - out[q].iterations);
-            if (active[q] && lim <= 0) active[q] = 0;
-            g.limits[q] = active[q] ? lim : 0;
-            n_active += active[q];
-        }
-        if (n_active == 0) return false;
-        const double t0 = now_s();
-        scylla_params pk = *p;
-        if (o.eps_sched) pk.tol = eps_k[g.K];
-        batch_solve_impl(h, &pk, g.K > 1 ? 1 : 0, g.res.data(), g.limits.data(), g.q0, g.q1);
-        mip_check(h, 1e-6, g.ok.data());
-        if (h->vbytes == 4) get_range<float>(h, h->x, 0, N, g.x.data());
-        else get_range<double>(h, h->x, 0, N, g.x.data());
-        g.solve_s = now_s() - t0;
-        return true;
-    };
-
-    // Host rounding of round G.K of a group (Algorithm 1 after the solve).
-    auto round_group = [&](Group &g) {
-        const int32_t K = g.K;
-        std::atomic<int> bad{0}, nonbinary{0};
-        const double tr0 = now_s();
-        parallel_for(g.q1 - g.q0, o.threads, [&](int32_t qi) {
-            const int32_t q = g.q0 + qi;
-            if (!active[q]) return;
-            const auto &P = h->local[q].P;
-            const int32_t c0 = h->col_off[q];
-            const uint8_t *ii = isint.data() + c0;
-            const double *xq = g.x.data() + c0;
-            double *xh = xhat.data() + c0;
-            scylla_pump_outcome &oc = out[q];
-            oc.rounds_run = K;
-            oc.iterations += g.res[q].iterations;
-            scylla_pump_record rtmp;
-            scylla_pump_record &r = rec ? rec[(size_t)(K - 1) * count + q] : rtmp;
-            memset(&r, 0, sizeof(r));
-            r.round = K;
-            r.group = (int32_t)(&g - G);
-            r.status = g.res[q].status;
-            r.iterations = g.res[q].iterations;
-            r.rel_kkt = g.res[q].rel_kkt;
-            r.solve_seconds = g.res[q].solve_seconds;
-            r.tune_seconds = g.res[q].tune_seconds;
-            r.lp_feasible = g.ok[q];
-            if (r.lp_feasible && !oc.found_kind) {
-                oc.found_kind = 1;
-                oc.found_round = K;
-                memcpy(xres.data() + c0, xq, sizeof(double) * P.n);
-                if (o.early_exit) {
-                    active[q] = 0;
-                    return;
-                }
-            }
-            if (!prep[q].ready) fp_prepare(P, ii, prep[q]);
-            fix_and_propagate(P, ii, prep[q], xq, xh, &r.xhat_feasible, &r.ignored_rows);
-            double obj = 0.0;
-            for (int32_t j = 0; j < P.n; ++j) obj += h->hc[c0 + j] * xh[j];
-            r.xhat_obj = obj;
-            if (legacy_best && !found_best[q]) {
-                memcpy(h->pump_best.data() + c0, xh, sizeof(double) * P.n);
-                if (r.xhat_feasible) found_best[q] = 1;
-            }
-            if (!oc.found_kind) memcpy(xres.data() + c0, xh, sizeof(double) * P.n);
-            if (r.xhat_feasible && !oc.found_kind) {
-                oc.found_kind = 2;
-                oc.found_round = K;
-                if (o.early_exit) {
-                    active[q] = 0;
-                    return;
-                }
-            }
-            if (o.perturb) {
-                if (hist[q].seen(xh, P.n)) {
-                    // flip the T binaries farthest from the PDHG iterate
-                    std::vector<int32_t> idx;
-                    for (int32_t j = 0; j < P.n; ++j)
-                        if (ii[j]) {
-                            if (P.u[j] - P.l[j] != 1.0) nonbinary = 1;
-                            idx.push_back(j);
-                        }
-                    if (!nonbinary) {
-                        const size_t T = std::min<size_t>((size_t)perturb_count(o.seed, q, K), idx.size());
-                        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
-                            return fabs(xq[a] - xh[a]) > fabs(xq[b] - xh[b]);
-                        });
-                        for (size_t t = 0; t < T; ++t) {
-                            const int32_t j = idx[t];
-                            xh[j] = xh[j] == P.l[j] ? P.u[j] : P.l[j];
-                        }
-                        r.perturbed = 1;
-                        ++oc.perturbations;
-                    }
-                }
-                hist[q].add(xh, P.n);
-            }
-            if (l2) {
-                // L2 distance (Section 5): QP objective a kappa c - 2 (1 - a) x_hat
-                // and Hessian 2 (1 - a) on the integer variables
-                const double a = pow(o.alpha, (double)K);
-                for (int32_t j = 0; j < P.n; ++j) {
-                    chat[c0 + j] = a * kappa[q] * h->hc[c0 + j] - (ii[j] ? 2.0 * (1.0 - a) * xh[j] : 0.0);
-                    qhat[c0 + j] = ii[j] ? 2.0 * (1.0 - a) : 0.0;
-                }
-                return;
-            }
-            // L1-distance gradient needs every integer at a bound
-            uint8_t *xb = xbits.data() + boff[q];
-            memset(xb, 0, boff[q + 1] - boff[q]);
-            for (int32_t j = 0; j < P.n; ++j) {
-                if (!ii[j]) continue;
-                if (xh[j] == P.u[j] && xh[j] != P.l[j]) xb[j / 8] |= (uint8_t)(1u << (j % 8));
-                else if (xh[j] != P.l[j]) bad = 1;
-            }
-        });
-        g.rounding_s = now_s() - tr0;
-        if (nonbinary) throw_err(-EINVAL, "cycle perturbation needs binary integer variables");
-        if (bad) throw_err(-EINVAL, "an integer variable is rounded strictly inside its bounds: the L1 distance "
-                                    "of general integers needs auxiliary variables");
-    };
-
-    // Next objective of the group's active instances on the device, then the
-    // group's round is complete.
-    auto finish_group = [&](Group &g) {
-        const double tb = now_s();
-        bool any = false;
-        for (int32_t q = g.q0; q < g.q1; ++q) any = any || active[q];
-        const int32_t c0 = h->col_off[g.q0], c1 = h->col_off[g.q1];
-        if (g.K < o.rounds && any && l2) {
-            HIPC(hipMemcpyAsync(h->c64.as<double>() + c0, chat.data() + c0, sizeof(double) * (c1 - c0),
-                                hipMemcpyHostToDevice, h->stream));
-            HIPC(hipMemcpyAsync(h->q64.as<double>() + c0, qhat.data() + c0, sizeof(double) * (c1 - c0),
-                                hipMemcpyHostToDevice, h->stream));
-            if (h->vbytes == 4) launch_cast<float>(h->c64.as<double>() + c0, h->cv.as<float>() + c0, c1 - c0, h->stream);
-            else launch_cast<double>(h->c64.as<double>() + c0, h->cv.as<double>() + c0, c1 - c0, h->stream);
-            cast_q(h);
-        } else if (g.K < o.rounds && any) {
-            const double a = pow(o.alpha, (double)g.K);
-            const size_t b0 = boff[g.q0], b1 = boff[g.q1];
-            HIPC(hipMemcpyAsync(h->bits_tmp.as<uint8_t>() + b0, xbits.data() + b0, b1 - b0, hipMemcpyHostToDevice,
-                                h->stream));
-            for (int32_t q = g.q0; q < g.q1; ++q) {
-                if (!active[q]) continue;
-                const int lo = h->col_off[q], hi = h->col_off[q + 1];
-                const uint8_t *xb = h->bits_tmp.as<uint8_t>() + boff[q];
-                const uint8_t *ib = h->ibits_tmp.as<uint8_t>() + boff[q];
-                if (h->vbytes == 4)
-                    launch_blend<float>(h->corig64.as<double>(), xb, ib, a, kappa[q], h->c64.as<double>(),
-                                        h->cv.as<float>(), lo, hi, h->stream);
-                else
-                    launch_blend<double>(h->corig64.as<double>(), xb, ib, a, kappa[q], h->c64.as<double>(),
-                                         h->cv.as<double>(), lo, hi, h->stream);
-            }
-        }
-        if (g.K < o.rounds && any) {
-            launch_inst_norms(h->info.as<InstInfo>(), h->count, h->b64.as<double>(), h->c64.as<double>(),
-                              h->dr64.as<double>(), h->dc64.as<double>(), h->st.as<InstState>(), h->stream);
-            HIPC(hipGetLastError());
-            HIPC(hipStreamSynchronize(h->stream));
-        }
-        const double dt = g.solve_s + g.rounding_s + (now_s() - tb);
-        if (rec)
-            for (int32_t q = g.q0; q < g.q1; ++q) {
-                scylla_pump_record &r = rec[(size_t)(g.K - 1) * count + q];
-                if (r.round) {
-                    r.round_seconds = dt;
-                    r.rounding_seconds = g.rounding_s;
-                }
-            }
-        ++g.K;
-    };
-
-    if (ng == 1) {
-        while (solve_group(G[0])) {
-            round_group(G[0]);
-            finish_group(G[0]);
-        }
-    } else {
-        // pending: the group whose solve awaits its rounding
-        bool has[2] = {solve_group(G[0]), false};
-        int r = 0;
-        for (;;) {
-            const int sg = 1 - r;
-            std::exception_ptr err;
-            std::thread worker;
-            if (has[r])
-                worker = std::thread([&]() {
-                    try {
-                        round_group(G[r]);
-                    } catch (...) {
-                        err = std::current_exception();
-                    }
-                });
-            try {
-                has[sg] = solve_group(G[sg]);
-            } catch (...) {
-                if (worker.joinable()) worker.join();
-                throw;
-            }
-            if (worker.joinable()) worker.join();
-            if (err) std::rethrow_exception(err);
-            if (has[r]) finish_group(G[r]);
-            if (!has[r] && !has[sg]) break;
-            has[r] = false;
-            r = sg;
-        }
-    }
-    for (int32_t q = 0; q < count; ++q) {
-        double obj = 0.0;
-        for (int32_t j = h->col_off[q]; j < h->col_off[q + 1]; ++j) obj += h->hc[j] * xres[j];
-        out[q].obj = obj;
-    }
-    if (outc) memcpy(outc, out.data(), sizeof(scylla_pump_outcome) * count);
-    if (x_out) memcpy(x_out, xres.data(), sizeof(double) * N);
-    return 0;
-}
-
-}  // namespace
+}  // namespace scy
 
 // =================================================================== C ABI
 extern "C" {
@@ -2010,101 +1295,6 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->row_half_lds = h->orow.staged && h->orow.shalf;
         info->col_half_lds = h->ocol.staged && h->ocol.shalf;
         return 0;
-    });
-}
-
-int scylla_fix_propagate(const scylla_lp *lp, const uint8_t *is_int, const double *x_ref, double *x_hat,
-                         int32_t *info)
-{
-    return guarded([&]() {
-        std::string err;
-        int rc = validate_lp(lp, err);
-        if (rc) throw_err(rc, err);
-        if (!x_ref || !x_hat || !info) throw_err(-EINVAL, "NULL argument");
-        const scylla_csr &A = lp->A;
-        for (int32_t j = 0; j < A.n; ++j)
-            if (!isfinite(x_ref[j])) throw_err(-EINVAL, "non-finite reference value");
-        std::vector<int32_t> ptr(A.m + 1), cptr, crow;
-        std::vector<double> cval;
-        for (int32_t i = 0; i <= A.m; ++i) ptr[i] = (int32_t)A.row_ptr[i];
-        FPProblem P;
-        P.m = A.m;
-        P.n = A.n;
-        P.ptr = ptr.data();
-        P.col = A.col_idx;
-        P.val = A.val;
-        P.b = lp->b;
-        P.sense = lp->senses;
-        P.l = lp->l;
-        P.u = lp->u;
-        build_incidence(P, cptr, crow, cval);
-        std::vector<uint8_t> ii(A.n, 1);
-        if (is_int)
-            for (int32_t j = 0; j < A.n; ++j) ii[j] = is_int[j] ? 1 : 0;
-        FPPrep prep;
-        fp_prepare(P, ii.data(), prep);
-        fix_and_propagate(P, ii.data(), prep, x_ref, x_hat, &info[0], &info[1]);
-        return 0;
-    });
-}
-
-int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible)
-{
-    return guarded([&]() {
-        if (!h || !feasible) throw_err(-EINVAL, "handle or feasible is NULL");
-        if (!(tol > 0.0) || !isfinite(tol)) throw_err(-EINVAL, "tol must be finite and > 0");
-        set_mip_isint(h, is_int);
-        std::vector<uint8_t> ok(h->count);
-        mip_check(h, tol, ok.data());
-        for (int32_t q = 0; q < h->count; ++q) feasible[q] = ok[q];
-        return 0;
-    });
-}
-
-int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds,
-                      double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out)
-{
-    return guarded([&]() {
-        PumpOpts o{rounds, false, 0.0, 0.0, 0.0, alpha, 0, false, false, 0, threads, 1, false};
-        pump_impl(h, p, is_int, o, records, nullptr, nullptr, true);
-        if (xhat_out) memcpy(xhat_out, h->pump_best.data(), sizeof(double) * h->N);
-        return 0;
-    });
-}
-
-int scylla_pump_params_default(scylla_pump_params *o)
-{
-    if (!o) {
-        g_err = "pump params is NULL";
-        return -EINVAL;
-    }
-    memset(o, 0, sizeof(*o));
-    o->rounds = 20;
-    o->eps_schedule = 1;
-    o->eps1 = 0.01;
-    o->beta = 0.98;
-    o->eps_floor = 1e-8;
-    o->alpha = 0.9;
-    o->total_iter_limit = 0;
-    o->early_exit = 1;
-    o->perturb = 1;
-    o->seed = 0;
-    o->threads = 0;
-    o->distance = 1;
-    o->pipeline = 0;
-    return 0;
-}
-
-int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uint8_t *is_int,
-                         const scylla_pump_params *opt, scylla_pump_record *records,
-                         scylla_pump_outcome *outcome, double *x_out)
-{
-    return guarded([&]() {
-        if (!opt) throw_err(-EINVAL, "pump params is NULL");
-        PumpOpts o{opt->rounds,    opt->eps_schedule != 0, opt->eps1,         opt->beta,
-                   opt->eps_floor, opt->alpha,             opt->total_iter_limit, opt->early_exit != 0,
-                   opt->perturb != 0, opt->seed, opt->threads, opt->distance, opt->pipeline != 0};
-        return pump_impl(h, params, is_int, o, records, outcome, x_out, false);
     });
 }
 

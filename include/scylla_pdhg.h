@@ -265,6 +265,9 @@ typedef struct {
     int32_t row_slices, col_slices; /* slices per such instance              */
     int32_t row_half_lds, col_half_lds; /* staged workgroups limited to half
                                        the LDS (two per CU)                  */
+    int32_t row_tile_threads, col_tile_threads; /* threads per workgroup of
+                                       the normal / gather-blocked tiles
+                                       (256, or 1024 for ept -8 / -16)       */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 
@@ -431,8 +434,9 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
  * to four times too long are processed one equal slice of it at a time,
  * their per-slice row sums added in slice order), -3 = as -2 with at most
  * half the LDS per workgroup; *_ept: 4, 8
- * or 16 nonzeros per thread (tiles of 256 * ept nonzeros).  -EINVAL
- * otherwise. */
+ * or 16 nonzeros per thread (tiles of 256 * ept nonzeros), or -8 / -16 (the
+ * tiles of ept 8 / 16 run by 1024-thread workgroups, 2 / 4 nonzeros per
+ * thread).  -EINVAL otherwise. */
 int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,
                             int32_t col_ept);
 
@@ -447,8 +451,9 @@ int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, doub
  * bounds both passes (every nonzero gathers one element of the other
  * vector).  Runs `gathers` gathers at hashed positions of a float vector of
  * `vec_bytes` bytes (4 <= vec_bytes <= 1 GiB, 1 <= gathers <= 2^31) on the
- * current device and returns the average duration of one launch in ms
- * (HIP events, 10 launches after a warm-up).  Allocates its own buffers. */
+ * current device, with 8, 16 and 32 gathers per thread, and returns the
+ * average duration of one launch of the fastest of the three in ms (HIP
+ * events, 10 launches after a warm-up).  Allocates its own buffers. */
 int scylla_probe_gather(int64_t vec_bytes, int64_t gathers, double *ms);
 
 #ifdef __cplusplus

@@ -153,7 +153,9 @@ template <class V>
 void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s);
 void launch_decide(const DecideArgs &d, int count, hipStream_t s);
 void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s);
-void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, hipStream_t s);
+// per_thread: gathers per thread (8, 16 or 32); out holds ceil(n / 2048) * 256 floats
+void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, int per_thread,
+                         hipStream_t s);
 void launch_force_stop(InstState *st, int count, hipStream_t s);
 void launch_scale_reduce(const MatView &M, int fmt, int rows, const double *drow, const double *dcol,
                          double *out, int mode, hipStream_t s);

@@ -1464,11 +1464,11 @@ __global__ void k_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec)
     idx[i] = x % len;
 }
 
+template <int K>
 __global__ __launch_bounds__(256) void k_probe_gather(const uint32_t *__restrict__ idx,
                                                      const float *__restrict__ vec, float *__restrict__ out,
                                                      int64_t n)
 {
-    constexpr int K = 8;
     const int64_t base = (int64_t)blockIdx.x * 256 * K + threadIdx.x;
     uint32_t w[K];
 #pragma unroll
@@ -1491,9 +1491,15 @@ void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipSt
     hipLaunchKernelGGL(k_probe_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, idx, n, len, vec);
 }
 
-void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, hipStream_t s)
+void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, int per_thread,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(k_probe_gather, dim3((unsigned)((n + 2047) / 2048)), dim3(256), 0, s, idx, vec, out, n);
+    const auto grid = [&](int k) { return dim3((unsigned)((n + 256 * k - 1) / (256 * k))); };
+    switch (per_thread) {
+    case 32: hipLaunchKernelGGL(k_probe_gather<32>, grid(32), dim3(256), 0, s, idx, vec, out, n); break;
+    case 16: hipLaunchKernelGGL(k_probe_gather<16>, grid(16), dim3(256), 0, s, idx, vec, out, n); break;
+    default: hipLaunchKernelGGL(k_probe_gather<8>, grid(8), dim3(256), 0, s, idx, vec, out, n); break;
+    }
 }
 
 // ------------------------------------------------------ host launchers
@@ -1509,10 +1515,20 @@ static void launch_check_t(const PassArgs<V> &p, hipStream_t s)
     hipLaunchKernelGGL((k_check<V, FMT, DIR, NT, EPT>), dim3(p.ntiles), dim3(NT), 0, s, p);
 }
 
+// ept: nonzeros per thread of 256-thread tile workgroups (tiles of 256 ept
+// nonzeros); -8 / -16: the tiles of ept 8 / 16 run by 1024-thread
+// workgroups, 2 / 4 nonzeros per thread (a thread then has at most one row
+// of a tile).
 template <class V, int FMT, int DIR>
 static void dispatch_pass(const PassArgs<V> &p, int ept, int jw, bool check, hipStream_t s)
 {
     switch (ept) {
+    case -8:
+        check ? launch_check_t<V, FMT, DIR, 1024, 2>(p, s) : launch_pass_t<V, FMT, DIR, 1024, 2>(p, jw, s);
+        break;
+    case -16:
+        check ? launch_check_t<V, FMT, DIR, 1024, 4>(p, s) : launch_pass_t<V, FMT, DIR, 1024, 4>(p, jw, s);
+        break;
     case 4:
         check ? launch_check_t<V, FMT, DIR, 256, 4>(p, s) : launch_pass_t<V, FMT, DIR, 256, 4>(p, jw, s);
         break;
@@ -1530,6 +1546,8 @@ static void dispatch_bpart(const PassArgs<V> &p, int ept, int jw, int check, hip
 {
     const dim3 g(p.ntiles), b(256);
     switch (ept) {
+    case -8: hipLaunchKernelGGL((k_bpart<V, A, FMT, 1024, 2>), g, dim3(1024), 0, s, p, jw, check); break;
+    case -16: hipLaunchKernelGGL((k_bpart<V, A, FMT, 1024, 4>), g, dim3(1024), 0, s, p, jw, check); break;
     case 4: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 4>), g, b, 0, s, p, jw, check); break;
     case 8: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 8>), g, b, 0, s, p, jw, check); break;
     default: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 16>), g, b, 0, s, p, jw, check); break;

@@ -121,9 +121,10 @@ void ip_layout(OrientRT &o)
 
 // Plans the orientation with `ept` nonzeros per thread, normal layout
 // (B = 0) or gather-blocked with B blocks, and uploads the plan buffers.
+// ept < 0: the tiles of |ept| run by 1024-thread workgroups (kernel choice only)
 void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
 {
-    const int32_t chunk = 256 * ept;
+    const int32_t chunk = 256 * std::abs(ept);
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
     const size_t vb = (size_t)h->vbytes;
     o.ept = ept;
@@ -200,7 +201,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
     const int32_t chunk = spass_chunk(variant);
     const int32_t max_vec = ((half ? h->lds_max / 2 : h->lds_max) - SPASS_STATIC_LDS) / h->vbytes - chunk;
-    plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * ept, o.splan);
+    plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * std::abs(ept), o.splan);
     std::vector<int32_t> tiles = o.splan.tiles;
     if (slice) {
         if (o.x_max_vec != max_vec || o.x_sub != chunk) {
@@ -238,7 +239,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
         // normal tiles only for instances neither staged nor sliced
         std::vector<uint8_t> skip(h->count);
         for (int32_t q = 0; q < h->count; ++q) skip[q] = (o.splan.staged[q] || o.xplan.sliced[q]) ? 1 : 0;
-        plan_tiles(o.host.ptr, off, 256 * ept, 1024, o.splan.rest, skip.data());
+        plan_tiles(o.host.ptr, off, 256 * std::abs(ept), 1024, o.splan.rest, skip.data());
     }
     upload(o.stiles, tiles, h->stream);
     upload(o.subtiles, o.splan.sub.tiles, h->stream);
@@ -647,7 +648,7 @@ void autotune(scylla_batch *h)
         h->tuned = true;
         return;
     }
-    const int epts[3] = {4, 8, 16};
+    const int epts[5] = {4, 8, 16, -8, -16};
     // SCYLLA_TUNE_TRACE=1: one line per candidate on stderr (plan time on
     // the host, measured pass time)
     const bool trace = getenv("SCYLLA_TUNE_TRACE") != nullptr;
@@ -1276,8 +1277,10 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->m_total = h->M;
         info->n_total = h->N;
         info->nnz_total = h->NNZ;
-        info->row_chunk = 256 * h->orow.ept;
-        info->col_chunk = 256 * h->ocol.ept;
+        info->row_chunk = 256 * std::abs(h->orow.ept);
+        info->col_chunk = 256 * std::abs(h->ocol.ept);
+        info->row_tile_threads = h->orow.ept < 0 ? 1024 : 256;
+        info->col_tile_threads = h->ocol.ept < 0 ? 1024 : 256;
         info->long_rows = h->orow.nlong();
         info->long_cols = h->ocol.nlong();
         info->row_blocks = h->orow.staged ? -1 : (h->orow.blocked ? h->orow.bh.B : 0);
@@ -1304,9 +1307,9 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
         auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || (B >= -3 && B <= -1); };
-        auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16; };
+        auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16 || e == -8 || e == -16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8 or 16");
+            throw_err(-EINVAL, "blocks must be -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8, 16, -8 or -16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;
@@ -1366,17 +1369,24 @@ int scylla_probe_gather(int64_t vec_bytes, int64_t gathers, double *ms)
         HIPC(hipEventCreate(&e0));
         HIPC(hipEventCreate(&e1));
         launch_probe_init(idx.as<uint32_t>(), gathers, len, vec.as<float>(), s);
-        launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, s);
-        HIPC(hipEventRecord(e0, s));
-        for (int r = 0; r < 10; ++r) launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, s);
-        HIPC(hipEventRecord(e1, s));
-        HIPC(hipEventSynchronize(e1));
-        HIPC(hipGetLastError());
-        float t = 0;
-        HIPC(hipEventElapsedTime(&t, e0, e1));
+        // the fastest of 8, 16 and 32 gathers per thread (more work per
+        // workgroup amortises its start, so the rate depends on it)
+        double best = 1e30;
+        for (int k : {8, 16, 32}) {
+            launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, k, s);
+            HIPC(hipEventRecord(e0, s));
+            for (int r = 0; r < 10; ++r)
+                launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, k, s);
+            HIPC(hipEventRecord(e1, s));
+            HIPC(hipEventSynchronize(e1));
+            HIPC(hipGetLastError());
+            float t = 0;
+            HIPC(hipEventElapsedTime(&t, e0, e1));
+            best = std::min(best, (double)t / 10.0);
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        *ms = (double)t / 10.0;
+        *ms = best;
         return 0;
     });
 }

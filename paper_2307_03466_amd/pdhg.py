@@ -83,7 +83,8 @@ class BatchInfo(ctypes.Structure):
                 ("col_staged_nnz", ctypes.c_int32), ("row_staged_variant", ctypes.c_int32),
                 ("col_staged_variant", ctypes.c_int32), ("row_sliced", ctypes.c_int32),
                 ("col_sliced", ctypes.c_int32), ("row_slices", ctypes.c_int32), ("col_slices", ctypes.c_int32),
-                ("row_half_lds", ctypes.c_int32), ("col_half_lds", ctypes.c_int32)]
+                ("row_half_lds", ctypes.c_int32), ("col_half_lds", ctypes.c_int32),
+                ("row_tile_threads", ctypes.c_int32), ("col_tile_threads", ctypes.c_int32)]
 
 
 _lib = None

@@ -4,13 +4,16 @@ counter collection), used for the files under profiles/.
   python -m paper_2307_03466_amd.profsum trace  <run_kernel_trace.csv> [top]
   python -m paper_2307_03466_amd.profsum counter <run_counter_collection.csv> <scale> [name-filter]
   python -m paper_2307_03466_amd.profsum traffic <fetch.csv> <write.csv> <fetch-scale> <out.json>
+  python -m paper_2307_03466_amd.profsum gather [gathers]   (needs the GPU)
 
 `trace` lists per kernel the launches, total time, rocprofv3's mean, and the
 mean over launches longer than 10 us (the solver launches whole check
 windows; iterations after an instance finished exit at once and are
 short).  `counter` lists per kernel the median counter value per dispatch
 longer than 10 us in KiB and that value times `scale` in MB (FETCH_SIZE reads half of a plain
-copy's bytes on this device: scale 2.0; WRITE_SIZE: scale 1.0)."""
+copy's bytes on this device: scale 2.0; WRITE_SIZE: scale 1.0).  `gather`
+runs the library's random-gather probe (scylla_probe_gather) for vectors of
+1 to 8 MB and prints the rates."""
 from __future__ import annotations
 
 import csv
@@ -85,8 +88,20 @@ def traffic(fetch_csv: str, write_csv: str, fetch_scale: float, out: str) -> Non
               open(out, "w"), indent=1, sort_keys=True)
 
 
+def gather(gathers: int = 10_000_000) -> str:
+    """Markdown table of the device's random 4-byte gather rate by vector size."""
+    from . import pdhg
+    out = ["| vector | ms per launch | G gathers/s |", "|---|---|---|"]
+    for mb in (1, 2, 4, 8):
+        ms = pdhg.probe_gather(mb * 1_000_000, gathers)
+        out.append(f"| {mb} MB | {ms:.4f} | {gathers / (ms * 1e-3) / 1e9:.1f} |")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "traffic":
+    if sys.argv[1] == "gather":
+        print(gather(int(sys.argv[2]) if len(sys.argv) > 2 else 10_000_000))
+    elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5])
     elif sys.argv[1] == "trace":
         print(trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 14))

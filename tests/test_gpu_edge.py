@@ -12,7 +12,7 @@ from lp_util import lp_from_dense, rel_err
 pytestmark = pytest.mark.gpu
 pdhg = pytest.importorskip("paper_2307_03466_amd.pdhg")
 
-LAYOUTS = [(0, 4, 0, 4), (0, 16, 0, 16), (4, 8, 8, 4), (2, 8, 2, 16), (-1, 8, -1, 8)]
+LAYOUTS = [(0, 4, 0, 4), (0, 16, 0, 16), (4, 8, 8, 4), (2, 8, 2, 16), (-1, 8, -1, 8), (0, -16, 4, -16)]
 
 
 @pytest.fixture(scope="module", autouse=True)

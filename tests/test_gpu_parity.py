@@ -243,7 +243,8 @@ def test_time_limit_status():
     assert abs(s.result["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
 
 
-LAYOUTS = [(0, 4, 0, 16), (2, 8, 2, 4), (4, 8, 4, 4), (8, 4, 8, 8), (8, 16, 0, 8), (-1, 8, -1, 16), (-1, 4, 4, 8)]
+LAYOUTS = [(0, 4, 0, 16), (2, 8, 2, 4), (4, 8, 4, 4), (8, 4, 8, 8), (8, 16, 0, 8), (-1, 8, -1, 16), (-1, 4, 4, 8),
+           (0, -16, 0, -16), (4, -16, 2, -16), (-1, -16, -1, -16), (0, -8, 8, -8)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)

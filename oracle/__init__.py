@@ -14,6 +14,11 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
   fix_propagate                 pinned (integrality/bounds, identity on
                                 feasible integral input, set-cover success,
                                 brute-force propagation soundness)
+  fix_propagate_batched         pinned (hand-worked round cap, conflict and
+                                tolerance cases, plain rounding without
+                                rows, fixpoint at x_hat, equal to
+                                fix_propagate for K = 1 where neither
+                                ignores a row)
   objective_update(_l2),        pinned (closed forms / norm identities,
   eps_schedule                  the QP form equals the L2 distance up to a
                                 constant)
@@ -83,7 +88,8 @@ def _load():
         if not os.path.exists(_LIB):
             build(force=False)
         lib = ctypes.CDLL(_LIB)
-        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_fix_propagate", "orc_ray"):
+        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_fix_propagate", "orc_ray",
+                   "orc_fix_propagate_batched"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -201,6 +207,27 @@ def fix_propagate(lp, xbar, is_int=None):
     rc = _load().orc_fix_propagate(ctypes.byref(pin.s), _p(is_int), _p(xb), _p(xhat), _p(info))
     assert rc == 0
     return xhat, bool(info[0]), int(info[1])
+
+
+FP_MAX_ROUNDS = 1000
+
+
+def fix_propagate_batched(lp, xbar, K: int, max_rounds: int = FP_MAX_ROUNDS, is_int=None):
+    """Batched fix-and-propagate (a parallel form of Section 2.3): the next K
+    unfixed integer variables of the fixing order are fixed together, then
+    synchronous propagation rounds (at most max_rounds per batch) combine the
+    rows' derived bounds by max / min; rows behind an empty combined domain
+    are ignored.  Returns (x_hat, feasible, ignored_rows, ignored_mask)."""
+    pin = _Pinned(lp)
+    is_int = np.ascontiguousarray(lp.is_int if is_int is None else is_int, dtype=np.uint8)
+    xb = np.ascontiguousarray(xbar, dtype=np.float64)
+    xhat = np.empty(lp.n)
+    info = np.zeros(2, dtype=np.int32)
+    mask = np.zeros(max(lp.m, 1), dtype=np.uint8)
+    rc = _load().orc_fix_propagate_batched(ctypes.byref(pin.s), _p(is_int), _p(xb), ctypes.c_int32(K),
+                                           ctypes.c_int32(max_rounds), _p(xhat), _p(info), _p(mask))
+    assert rc == 0
+    return xhat, bool(info[0]), int(info[1]), mask[: lp.m].astype(bool)
 
 
 # ------------------------------------------------ objective update (O3)

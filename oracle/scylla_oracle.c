@@ -27,6 +27,9 @@
  *   update) enters the primal proximal step exactly and the KKT test through
  *   the reduced cost and both objectives.
  *   - orc_fix_propagate: fix-and-propagate rounding (Section 2.3).
+ *   - orc_fix_propagate_batched: the same rounding with K variables fixed at
+ *                        a time and synchronous propagation rounds (a
+ *                        parallel form of Section 2.3; rules at the function).
  *
  * Readings where the paper is silent (each is restated in the design notes):
  *   - rows may be >=, <= or = (the paper writes only >=); the dual cone is
@@ -566,9 +569,11 @@ static void row_activity(const fp_state *st, int32_t i, double *minf, int *minin
     *minf = mn; *mininf = ni; *maxf = mx; *maxinf = xi;
 }
 
-/* Propagate one row; returns 0 if fine, 1 if the row must be ignored. */
-static int fp_row(fp_state *st, int32_t i, int32_t *changed, int32_t *nchanged,
-                  double *newL, double *newU)
+/* Domains that row i derives for its variables (newL / newU per nonzero,
+ * integer bounds rounded inward), against the current domains; returns 1 if
+ * the row must be ignored (its activity bounds exclude b, or a derived
+ * domain is empty). */
+static int fp_row_bounds(const fp_state *st, int32_t i, double *newL, double *newU)
 {
     const orc_lp *lp = st->lp;
     char sn = lp->sense[i];
@@ -579,7 +584,6 @@ static int fp_row(fp_state *st, int32_t i, int32_t *changed, int32_t *nchanged,
     const double feas_tol = 1e-9 * (1.0 + fabs(bi));
     if ((sn == 'G' || sn == 'E') && xi == 0 && mx < bi - feas_tol) return 1;
     if ((sn == 'L' || sn == 'E') && ni == 0 && mn > bi + feas_tol) return 1;
-    *nchanged = 0;
     int64_t len = lp->row_ptr[i + 1] - lp->row_ptr[i];
     for (int64_t q = 0; q < len; ++q) {
         int64_t e = lp->row_ptr[i] + q;
@@ -619,6 +623,17 @@ static int fp_row(fp_state *st, int32_t i, int32_t *changed, int32_t *nchanged,
         }
         if (newL[q] > newU[q] + 1e-9 * (1.0 + fabs(newU[q]))) return 1;
     }
+    return 0;
+}
+
+/* Propagate one row; returns 0 if fine, 1 if the row must be ignored. */
+static int fp_row(fp_state *st, int32_t i, int32_t *changed, int32_t *nchanged,
+                  double *newL, double *newU)
+{
+    const orc_lp *lp = st->lp;
+    if (fp_row_bounds(st, i, newL, newU)) return 1;
+    *nchanged = 0;
+    int64_t len = lp->row_ptr[i + 1] - lp->row_ptr[i];
     for (int64_t q = 0; q < len; ++q) {
         int64_t e = lp->row_ptr[i] + q;
         int32_t j = lp->col_idx[e];
@@ -652,6 +667,32 @@ static void fp_propagate(fp_state *st, int32_t *changed, double *newL, double *n
         }
         for (int32_t q = 0; q < nch; ++q) fp_touch_col(st, changed[q]);
     }
+}
+
+/* Integers take their (fixed) lower bound, continuous variables the
+ * reference value projected onto their domain; info[0] = 1 if every row holds
+ * at x_hat within 1e-6 (1 + |b_i|), info[1] = number of ignored rows. */
+static void fp_finish(const orc_lp *lp, const uint8_t *is_int, const double *xbar, const double *L,
+                      const double *U, const uint8_t *ignored, double *xhat, int32_t *info)
+{
+    const int32_t m = lp->m, n = lp->n;
+    for (int32_t j = 0; j < n; ++j) {
+        if (is_int[j]) xhat[j] = L[j];
+        else xhat[j] = clampd(xbar[j], L[j], U[j]);
+    }
+    int ok = 1;
+    int32_t nign = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        nign += ignored[i];
+        double a = 0.0;
+        for (int64_t e = lp->row_ptr[i]; e < lp->row_ptr[i + 1]; ++e) a += lp->val[e] * xhat[lp->col_idx[e]];
+        double tol = 1e-6 * (1.0 + fabs(lp->b[i]));
+        char sn = lp->sense[i];
+        if ((sn == 'G' || sn == 'E') && a < lp->b[i] - tol) ok = 0;
+        if ((sn == 'L' || sn == 'E') && a > lp->b[i] + tol) ok = 0;
+    }
+    info[0] = ok;
+    info[1] = nign;
 }
 
 static double frac_dist(double v)
@@ -731,26 +772,214 @@ int orc_fix_propagate(const orc_lp *lp, const uint8_t *is_int, const double *xba
         fp_touch_col(&st, j);
         fp_propagate(&st, changed, newL, newU);
     }
-    for (int32_t j = 0; j < n; ++j) {
-        if (is_int[j]) xhat[j] = st.L[j];
-        else xhat[j] = clampd(xbar[j], st.L[j], st.U[j]);
-    }
-    /* report: all rows satisfied?  rows ignored? */
-    int ok = 1;
-    int32_t nign = 0;
-    for (int32_t i = 0; i < m; ++i) {
-        nign += st.ignored[i];
-        double a = 0.0;
-        for (int64_t e = lp->row_ptr[i]; e < lp->row_ptr[i + 1]; ++e) a += lp->val[e] * xhat[lp->col_idx[e]];
-        double tol = 1e-6 * (1.0 + fabs(lp->b[i]));
-        char sn = lp->sense[i];
-        if ((sn == 'G' || sn == 'E') && a < lp->b[i] - tol) ok = 0;
-        if ((sn == 'L' || sn == 'E') && a > lp->b[i] + tol) ok = 0;
-    }
-    info[0] = ok;
-    info[1] = nign;
+    fp_finish(lp, is_int, xbar, st.L, st.U, st.ignored, xhat, info);
     free(st.L); free(st.U); free(st.col_ptr); free(st.col_row); free(st.ignored);
     free(st.queued); free(st.queue); free(changed); free(newL); free(newU);
     free(order); free(key); free(fill);
+    return 0;
+}
+
+/* ---------------------------------------------- batched fix-and-propagate */
+/*
+ * A parallel form of the procedure above (Section 2.3), for a device that
+ * evaluates many rows at once; it is not the paper's order of work.  The
+ * next K unfixed integer variables of the same fixing order are fixed
+ * together, each to its rounded reference value clamped to its domain, and
+ * propagation then runs in synchronous rounds.  In a round every active row
+ * is evaluated against the domains at the start of the round, with the
+ * activity bounds, derived bounds, integer rounding and emptiness tests of
+ * the sequential procedure; a row failing them is ignored for the rest of
+ * the call.  Per variable, the derived bounds of the surviving rows that
+ * would change it (integer: any tightening; continuous: by more than
+ * 1e-9 (1 + |bound|), or from infinite to finite) are combined by max (lower)
+ * and min (upper).  Where the combined domain of a variable is empty by more
+ * than 1e-9 (1 + |upper|), every row that would change that variable is
+ * ignored and the combination is taken again without them (dropping rows
+ * only widens the combined domains, so once is enough); a crossing within
+ * that tolerance sets both bounds to max(upper, old lower).  The variables
+ * whose domain changed make their non-ignored rows active for the next
+ * round.  A batch ends when no row is active or after max_rounds rounds.
+ * With K = 1, exact arithmetic and no ignored row, both procedures end with
+ * the same domains: the greatest common fixpoint of the row propagators,
+ * whatever the order in which the rows are evaluated.
+ */
+static int fpb_lower_changes(int is_int, double lo, double nl)
+{
+    if (is_int) return nl > lo;
+    return nl > lo + 1e-9 * (1.0 + fabs(lo)) || (isinf(lo) && isfinite(nl));
+}
+
+static int fpb_upper_changes(int is_int, double hi, double nu)
+{
+    if (is_int) return nu < hi;
+    return nu < hi - 1e-9 * (1.0 + fabs(hi)) || (isinf(hi) && isfinite(nu));
+}
+
+/* Folds the derived bounds of row i into the combined domains NL / NU
+ * (touched variables are listed once per round in `touched`). */
+static void fpb_fold_row(const fp_state *st, int32_t i, const double *cl, const double *cu,
+                         double *NL, double *NU, int32_t *vmark, int32_t stamp, int32_t *touched,
+                         int32_t *ntouched)
+{
+    const orc_lp *lp = st->lp;
+    for (int64_t e = lp->row_ptr[i]; e < lp->row_ptr[i + 1]; ++e) {
+        const int32_t j = lp->col_idx[e];
+        const double nl = cl[e], nu = cu[e];
+        const int tl = fpb_lower_changes(st->is_int[j], st->L[j], nl);
+        const int tu = fpb_upper_changes(st->is_int[j], st->U[j], nu);
+        if (!tl && !tu) continue;
+        if (vmark[j] != stamp) {
+            vmark[j] = stamp;
+            touched[(*ntouched)++] = j;
+        }
+        if (tl && nl > NL[j]) NL[j] = nl;
+        if (tu && nu < NU[j]) NU[j] = nu;
+    }
+}
+
+/* ignored_out: [m] or NULL, receives 1 for every ignored row. */
+int orc_fix_propagate_batched(const orc_lp *lp, const uint8_t *is_int, const double *xbar, int32_t K,
+                              int32_t max_rounds, double *xhat, int32_t *info, uint8_t *ignored_out)
+{
+    const int32_t m = lp->m, n = lp->n;
+    const int64_t nnz = lp->row_ptr[m];
+    if (K < 1 || max_rounds < 1) return -1;
+    fp_state st;
+    memset(&st, 0, sizeof(st));
+    st.lp = lp;
+    st.is_int = is_int;
+    st.L = malloc(sizeof(double) * (n + 1));
+    st.U = malloc(sizeof(double) * (n + 1));
+    st.col_ptr = calloc((size_t)n + 1, sizeof(int32_t));
+    st.col_row = malloc(sizeof(int32_t) * (nnz + 1));
+    st.ignored = calloc((size_t)m + 1, 1);
+    double *NL = malloc(sizeof(double) * (n + 1)), *NU = malloc(sizeof(double) * (n + 1));
+    double *cl = malloc(sizeof(double) * (nnz + 1)), *cu = malloc(sizeof(double) * (nnz + 1));
+    int32_t *active = malloc(sizeof(int32_t) * (m + 1)), *next = malloc(sizeof(int32_t) * (m + 1));
+    int32_t *rmark = malloc(sizeof(int32_t) * (m + 1));
+    uint8_t *bad = calloc((size_t)m + 1, 1);
+    int32_t *vmark = malloc(sizeof(int32_t) * (n + 1)), *touched = malloc(sizeof(int32_t) * (n + 1));
+    int32_t *order = malloc(sizeof(int32_t) * (n + 1)), *fill = malloc(sizeof(int32_t) * (n + 1));
+    double *key = malloc(sizeof(double) * (n + 1));
+    if (!st.L || !st.U || !st.col_ptr || !st.col_row || !st.ignored || !NL || !NU || !cl || !cu ||
+        !active || !next || !rmark || !bad || !vmark || !touched || !order || !fill || !key)
+        return -1;
+    for (int64_t e = 0; e < nnz; ++e) st.col_ptr[lp->col_idx[e] + 1]++;
+    for (int32_t j = 0; j < n; ++j) st.col_ptr[j + 1] += st.col_ptr[j];
+    for (int32_t j = 0; j < n; ++j) fill[j] = st.col_ptr[j];
+    for (int32_t i = 0; i < m; ++i)
+        for (int64_t e = lp->row_ptr[i]; e < lp->row_ptr[i + 1]; ++e)
+            st.col_row[fill[lp->col_idx[e]]++] = i;
+    int32_t nint = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        st.L[j] = lp->l[j];
+        st.U[j] = lp->u[j];
+        if (is_int[j]) {
+            if (isfinite(st.L[j])) st.L[j] = ceil(st.L[j] - 1e-9);
+            if (isfinite(st.U[j])) st.U[j] = floor(st.U[j] + 1e-9);
+            order[nint++] = j;
+            key[j] = frac_dist(xbar[j]);
+        }
+        NL[j] = st.L[j];
+        NU[j] = st.U[j];
+        vmark[j] = -1;
+    }
+    for (int32_t i = 0; i < m; ++i) rmark[i] = -1;
+    g_sort_key = key;
+    qsort(order, (size_t)nint, sizeof(int32_t), cmp_frac);
+    int32_t stamp = 0;
+    int32_t p = 0;
+    while (p < nint) {
+        /* the batch: the next K variables of the order that are not fixed */
+        int32_t nsel = 0;
+        ++stamp;
+        int32_t nact = 0;
+        while (nsel < K && p < nint) {
+            const int32_t j = order[p++];
+            if (st.L[j] == st.U[j]) continue;
+            const double v = clampd(ceil(xbar[j] - 0.5), st.L[j], st.U[j]);
+            st.L[j] = st.U[j] = NL[j] = NU[j] = v;
+            ++nsel;
+            for (int32_t e = st.col_ptr[j]; e < st.col_ptr[j + 1]; ++e) {
+                const int32_t i = st.col_row[e];
+                if (!st.ignored[i] && rmark[i] != stamp) {
+                    rmark[i] = stamp;
+                    active[nact++] = i;
+                }
+            }
+        }
+        for (int32_t round = 0; round < max_rounds && nact > 0; ++round) {
+            /* every active row against the domains at the start of the round */
+            for (int32_t a = 0; a < nact; ++a) {
+                const int32_t i = active[a];
+                const int64_t e0 = lp->row_ptr[i];
+                if (fp_row_bounds(&st, i, cl + e0, cu + e0)) st.ignored[i] = 1;
+            }
+            ++stamp;
+            int32_t ntouched = 0;
+            for (int32_t a = 0; a < nact; ++a)
+                if (!st.ignored[active[a]])
+                    fpb_fold_row(&st, active[a], cl, cu, NL, NU, vmark, stamp, touched, &ntouched);
+            /* rows that would change a variable whose combined domain is empty */
+            int conflict = 0;
+            for (int32_t a = 0; a < nact; ++a) {
+                const int32_t i = active[a];
+                if (st.ignored[i]) continue;
+                for (int64_t e = lp->row_ptr[i]; e < lp->row_ptr[i + 1]; ++e) {
+                    const int32_t j = lp->col_idx[e];
+                    if (!(NL[j] > NU[j] + 1e-9 * (1.0 + fabs(NU[j])))) continue;
+                    if (fpb_lower_changes(is_int[j], st.L[j], cl[e]) ||
+                        fpb_upper_changes(is_int[j], st.U[j], cu[e])) {
+                        bad[i] = 1;
+                        conflict = 1;
+                    }
+                }
+            }
+            if (conflict) {
+                for (int32_t a = 0; a < nact; ++a)
+                    if (bad[active[a]]) {
+                        bad[active[a]] = 0;
+                        st.ignored[active[a]] = 1;
+                    }
+                for (int32_t t = 0; t < ntouched; ++t) {
+                    NL[touched[t]] = st.L[touched[t]];
+                    NU[touched[t]] = st.U[touched[t]];
+                }
+                ++stamp;
+                ntouched = 0;
+                for (int32_t a = 0; a < nact; ++a)
+                    if (!st.ignored[active[a]])
+                        fpb_fold_row(&st, active[a], cl, cu, NL, NU, vmark, stamp, touched, &ntouched);
+            }
+            /* new domains; their rows are the next round's active rows */
+            ++stamp;
+            int32_t nnext = 0;
+            for (int32_t t = 0; t < ntouched; ++t) {
+                const int32_t j = touched[t];
+                double nl = NL[j], nu = NU[j];
+                if (nl > nu) nl = nu = fmax(nu, st.L[j]);
+                const int ch = nl != st.L[j] || nu != st.U[j];
+                st.L[j] = NL[j] = nl;
+                st.U[j] = NU[j] = nu;
+                if (!ch) continue;
+                for (int32_t e = st.col_ptr[j]; e < st.col_ptr[j + 1]; ++e) {
+                    const int32_t i = st.col_row[e];
+                    if (!st.ignored[i] && rmark[i] != stamp) {
+                        rmark[i] = stamp;
+                        next[nnext++] = i;
+                    }
+                }
+            }
+            int32_t *sw = active;
+            active = next;
+            next = sw;
+            nact = nnext;
+        }
+    }
+    fp_finish(lp, is_int, xbar, st.L, st.U, st.ignored, xhat, info);
+    if (ignored_out) memcpy(ignored_out, st.ignored, (size_t)m);
+    free(st.L); free(st.U); free(st.col_ptr); free(st.col_row); free(st.ignored);
+    free(NL); free(NU); free(cl); free(cu); free(active); free(next); free(rmark); free(bad);
+    free(vmark); free(touched); free(order); free(fill); free(key);
     return 0;
 }

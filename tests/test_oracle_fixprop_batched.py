@@ -1,0 +1,173 @@
+"""Pins of the oracle's batched fix-and-propagate (a parallel form of the
+rounding of Section 2.3): hand-worked cases of its round cap and conflict
+rule, the closed form without rows, the rounding invariants, the fixpoint
+property of pure-integer problems, and agreement with the sequential
+procedure where the two must agree (K = 1, no ignored row)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03466_amd import instances as I
+from paper_2307_03466_amd.instances import LP
+
+
+def _lp(rows, senses, b, l, u, is_int, n):
+    """LP from a list of {column: coefficient} rows (zero objective)."""
+    row_ptr = [0]
+    col_idx, val = [], []
+    for r in rows:
+        for j in sorted(r):
+            col_idx.append(j)
+            val.append(float(r[j]))
+        row_ptr.append(len(col_idx))
+    return LP(m=len(rows), n=n, row_ptr=np.array(row_ptr, dtype=np.int64),
+              col_idx=np.array(col_idx, dtype=np.int32), val=np.array(val, dtype=np.float64),
+              c=np.zeros(n), b=np.array(b, dtype=np.float64),
+              senses=np.array([ord(s) for s in senses], dtype=np.uint8),
+              l=np.array(l, dtype=np.float64), u=np.array(u, dtype=np.float64),
+              is_int=np.array(is_int, dtype=np.uint8), name="hand")
+
+
+def _chain(n=5):
+    """Binaries x_0..x_{n-1} with x_{k+1} - x_k >= 0: fixing x_0 = 1 forces
+    one more variable to 1 per synchronous round."""
+    rows = [{k + 1: 1, k: -1} for k in range(n - 1)]
+    return _lp(rows, "G" * (n - 1), [0] * (n - 1), [0] * n, [1] * n, [1] * n, n)
+
+
+def test_chain_propagates_one_link_per_round():
+    lp = _chain()
+    xbar = np.array([1.0, 0.4, 0.4, 0.4, 0.4])  # x_0 first (distance 0), rounds to 1
+    xhat, ok, nign, mask = oracle.fix_propagate_batched(lp, xbar, K=1)
+    assert xhat.tolist() == [1, 1, 1, 1, 1] and ok and nign == 0 and not mask.any()
+    # two rounds reach x_1 and x_2; the batch then ends with a row still
+    # active, x_3 is fixed by its own rounding (0.4 -> 0), which empties
+    # x_3 - x_2 >= 0: that row is ignored and x_4 rounds to 0 as well
+    xhat, ok, nign, mask = oracle.fix_propagate_batched(lp, xbar, K=1, max_rounds=2)
+    assert xhat.tolist() == [1, 1, 1, 0, 0] and not ok and nign == 1
+    assert mask.tolist() == [False, False, True, False]
+
+
+def test_conflicting_rows_are_both_ignored():
+    """x binary (reference 1.0, fixed first), y integer in [0, 5] with
+    y - 3x >= 0 and y + 3x <= 4.  In one round the two rows derive y >= 3
+    and y <= 1: each alone leaves y a domain, together they empty it, so both
+    are ignored and y keeps [0, 5] and rounds its reference 2.3 to 2.  The
+    sequential procedure evaluates the first row first (y in [3, 5]), then
+    ignores the second only, and clamps y to 3."""
+    lp = _lp([{0: -3, 1: 1}, {0: 3, 1: 1}], "GL", [0, 4], [0, 0], [1, 5], [1, 1], 2)
+    xbar = np.array([1.0, 2.3])
+    xhat, ok, nign, mask = oracle.fix_propagate_batched(lp, xbar, K=1)
+    assert xhat.tolist() == [1, 2] and nign == 2 and mask.all() and not ok
+    xs, oks, ns = oracle.fix_propagate(lp, xbar)
+    assert xs.tolist() == [1, 3] and ns == 1 and not oks
+
+
+def test_crossing_within_tolerance_pins_both_bounds_to_the_upper():
+    """Continuous y in [0, 10]: y - x >= 0 gives y >= 1, y + x <= 2 - 1e-12
+    gives y <= (2 - 1e-12) - 1, a crossing below 1e-9 (1 + |upper|): both
+    bounds become max(upper, old lower) = the upper bound."""
+    lp = _lp([{0: -1, 1: 1}, {0: 1, 1: 1}], "GL", [0, 2 - 1e-12], [0, 0], [1, 10], [1, 0], 2)
+    xhat, ok, nign, _ = oracle.fix_propagate_batched(lp, np.array([1.0, 7.0]), K=1)
+    assert xhat[0] == 1.0 and xhat[1] == (2 - 1e-12) - 1.0 and nign == 0 and ok
+
+
+@pytest.mark.parametrize("K", [1, 3, 100])
+def test_without_rows_it_is_plain_rounding(K):
+    """No rows: integers take round-half-down of the reference clamped to
+    their inward-rounded bounds, continuous variables the reference clamped
+    to [l, u]."""
+    rng = np.random.default_rng(7)
+    n = 40
+    l = np.floor(rng.uniform(-3, 1, n)) + rng.choice([0.0, 0.5], n)
+    u = l + rng.uniform(0.6, 4, n)
+    ii = (rng.random(n) < 0.7).astype(np.uint8)
+    xbar = rng.uniform(-5, 5, n)
+    xbar[:6] = [0.5, 1.5, -0.5, 2.5, -1.5, 3.0]
+    lp = _lp([], "", [], l, u, ii, n)
+    xhat, ok, nign, _ = oracle.fix_propagate_batched(lp, xbar, K=K)
+    li, ui = np.ceil(l - 1e-9), np.floor(u + 1e-9)
+    expect = np.where(ii == 1, np.clip(np.ceil(xbar - 0.5), li, ui), np.clip(xbar, l, u))
+    assert np.array_equal(xhat, expect) and ok and nign == 0
+
+
+def _row_activity(lp, x):
+    rows = np.repeat(np.arange(lp.m), np.diff(lp.row_ptr))
+    return np.bincount(rows, weights=lp.val * x[lp.col_idx], minlength=lp.m)
+
+
+def _violated(lp, x, tol=1e-6):
+    a = _row_activity(lp, x)
+    t = tol * (1 + np.abs(lp.b))
+    ge = (lp.senses == ord("G")) | (lp.senses == ord("E"))
+    le = (lp.senses == ord("L")) | (lp.senses == ord("E"))
+    return (ge & (a < lp.b - t)) | (le & (a > lp.b + t))
+
+
+CASES = [(I.cover_knapsack, dict(m=80, n=160)), (I.int_cover_knapsack, dict(m=60, n=120)),
+         (I.set_partition, dict(m=30, n=120))]
+
+
+@pytest.mark.parametrize("gen,kw", CASES)
+@pytest.mark.parametrize("K", [1, 4, 32, 10_000])
+def test_rounding_invariants_and_fixpoint(gen, kw, K):
+    """Integral on I, within the inward-rounded bounds; the feasibility flag
+    and the ignored count agree with the returned point and mask; and on
+    these pure-integer problems every row that is not ignored holds at x_hat
+    (after the last batch every row of a fixed variable was evaluated against
+    the final single-point domains, and a row whose activity excluded b would
+    have been ignored)."""
+    for seed in range(12):
+        lp = gen(seed=seed, **kw)
+        rng = np.random.default_rng(100 + seed)
+        hi = np.minimum(lp.u, 6)
+        xbar = lp.l + rng.random(lp.n) * (hi - lp.l)
+        xhat, ok, nign, mask = oracle.fix_propagate_batched(lp, xbar, K=K)
+        assert np.array_equal(xhat, np.round(xhat))
+        assert np.all(xhat >= lp.l) and np.all(xhat <= lp.u)
+        viol = _violated(lp, xhat)
+        assert nign == int(mask.sum())
+        assert ok == (not viol.any())
+        assert not np.any(viol & ~mask), (seed, np.flatnonzero(viol & ~mask))
+
+
+@pytest.mark.parametrize("gen,kw", [(I.cover_knapsack, dict(m=80, n=160)),
+                                    (I.int_cover_knapsack, dict(m=20, n=60))])
+def test_one_at_a_time_matches_the_sequential_procedure(gen, kw):
+    """K = 1 on pure-integer problems: wherever neither procedure ignores a
+    row, both end at the greatest common fixpoint of the row propagators
+    (monotone maps, so the order of evaluation does not matter) after every
+    fixing, and the roundings are identical."""
+    agree = 0
+    for seed in range(40):
+        lp = gen(seed=seed, **kw)
+        rng = np.random.default_rng(seed)
+        hi = np.minimum(lp.u, 6)
+        xbar = lp.l + (0.2 + 0.6 * rng.random(lp.n)) * (hi - lp.l)
+        xs, _, ns = oracle.fix_propagate(lp, xbar)
+        xb, _, nb, _ = oracle.fix_propagate_batched(lp, xbar, K=1)
+        if ns == 0 and nb == 0:
+            assert np.array_equal(xs, xb), seed
+            agree += 1
+    assert agree >= 15
+
+
+def test_batches_are_taken_in_the_fixing_order():
+    """Three free binaries with references 0.9, 0.3, 0.55 (distances 0.1,
+    0.3, 0.45) and the row x_0 + x_1 + x_2 <= 1.  K = 1: x_0 -> 1 first, and
+    the row then forces x_1 = x_2 = 0.  K = 2: x_0 -> 1 and x_1 -> 0 are fixed
+    together, then x_2 is forced to 0.  K = 3: all three are fixed together
+    to (1, 0, 1), which breaks the row; it is ignored."""
+    lp = _lp([{0: 1, 1: 1, 2: 1}], "L", [1], [0, 0, 0], [1, 1, 1], [1, 1, 1], 3)
+    xbar = np.array([0.9, 0.3, 0.55])
+    for K, expect, ign in [(1, [1, 0, 0], 0), (2, [1, 0, 0], 0), (3, [1, 0, 1], 1)]:
+        xhat, ok, nign, _ = oracle.fix_propagate_batched(lp, xbar, K=K)
+        assert xhat.tolist() == expect and nign == ign and ok == (ign == 0), K
+
+
+def test_bad_arguments_are_rejected():
+    lp = _chain(3)
+    with pytest.raises(AssertionError):
+        oracle.fix_propagate_batched(lp, np.zeros(3), K=0)
+    with pytest.raises(AssertionError):
+        oracle.fix_propagate_batched(lp, np.zeros(3), K=1, max_rounds=0)

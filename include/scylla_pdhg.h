@@ -325,6 +325,41 @@ typedef struct {
  * handle or feasible, tol not finite and > 0) or -EIO (HIP error). */
 int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible);
 
+/* Batched fix-and-propagate on the device (one workgroup per instance): a
+ * parallel form of the rounding of Section 2.3.  Per instance, the integer
+ * variables are taken in the same order as scylla_fix_propagate (ascending
+ * distance of x_bar_j to the nearest integer, ties by lower index), K unfixed
+ * ones at a time: they are fixed together to x_bar_j rounded half down and
+ * clamped to their domains, then propagation runs in synchronous rounds
+ * (at most max_rounds per batch): every row of a variable that changed is
+ * evaluated against the domains at the start of the round (activity bounds;
+ * derived bounds, integer ones rounded inward with 1e-9 slack; a row whose
+ * activity bounds exclude b by more than 1e-9 (1 + |b_i|) or whose bound
+ * empties a domain is ignored for the rest of the call); per variable the
+ * derived bounds that change it (integer: any tightening; continuous: by
+ * more than 1e-9 (1 + |bound|), or from infinite to finite) combine by max
+ * (lower) and min (upper); if the combined domain is empty by more than
+ * 1e-9 (1 + |upper|), every row that would change that variable is ignored
+ * and the combination is taken again without them; a crossing within that
+ * tolerance sets both bounds to max(upper, old lower).  Variables left
+ * unfixed take x_bar_j projected onto their domain.  The result does not
+ * depend on the order of the rows and is exact (FP64, sums in row order); K
+ * = 1 gives the sequential procedure's result wherever no row is ignored on
+ * pure-integer problems.
+ *   is_int:     [n_total] 0/1 or NULL (all integer).
+ *   xbar:       [n_total] finite host values, or NULL for every instance's
+ *               current primal iterate x (path precision, widened to FP64).
+ *   K >= 1, max_rounds >= 1.
+ *   xhat:       [n_total] receives the roundings.
+ *   info:       [2 * count] receives per instance (every row holds at x_hat
+ *               within 1e-6 (1 + |b_i|): 1 / 0, number of ignored rows).
+ *   ignored:    [m_total] or NULL, receives 1 for every ignored row.
+ * Returns 0, -EINVAL (NULL handle / xhat / info, K or max_rounds < 1, a
+ * non-finite xbar) or -ENOMEM / -EIO.  The problem's FP64 rows and column
+ * incidence are copied to the device on the first call and kept. */
+int scylla_batch_fix_propagate(scylla_batch *h, const uint8_t *is_int, const double *xbar, int32_t K,
+                               int32_t max_rounds, double *xhat, int32_t *info, uint8_t *ignored);
+
 /* Feasibility-pump-like loop of Algorithm 1 on every instance of the batch,
  * with all `rounds` rounds run: round 1 solves with the original objective
  * from the projected origin; after round K every instance is rounded on
@@ -376,6 +411,13 @@ typedef struct {
                                  GPU as busy as the whole: a batch whose
                                  passes are one wave of workgroups takes
                                  about as long per iteration for half of it */
+    int32_t fp_batch;         /* 0: rounding by scylla_fix_propagate's
+                                 sequential procedure on the host (default);
+                                 K >= 1: by the batched procedure of
+                                 scylla_batch_fix_propagate on the device, K
+                                 variables per batch (needs pipeline = 0)     */
+    int32_t fp_max_rounds;    /* propagation rounds per batch of the device
+                                 rounding, >= 1 (default 1000)                */
 } scylla_pump_params;
 
 /* Per-instance outcome of scylla_batch_pump_ex. */

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libscylla_pdhg.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["host_prep.cpp", "fixprop.cpp", "kernels.hip", "runtime.hip", "pump.hip"]
+SOURCES = ["host_prep.cpp", "fixprop.cpp", "kernels.hip", "runtime.hip", "pump.hip", "fixprop_dev.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # keep the compiler from emitting packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

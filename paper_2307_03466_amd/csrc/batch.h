@@ -133,6 +133,16 @@ struct OrientRT {
     int32_t nlong() const { return (int32_t)((blocked ? bplan.longs.size() : plan.longs.size()) / 4); }
 };
 
+// Device copy of the problem and work arrays of the batched
+// fix-and-propagate (built on its first call).
+struct FPDev {
+    bool ready = false;
+    DevMem rptr, col, val, cptr, crow, rowoff, coloff;  // FP64 CSR + column incidence
+    DevMem nint, isint, want, xbar, key, key2, ord0, ord, tmp;
+    DevMem L, U, cL, cU, vst, rst, ign, bad, act, nxt, chg, xhat, info;
+    size_t tmp_bytes = 0;
+};
+
 struct scylla_batch {
     int32_t count = 0, precision = SCYLLA_FP32, fmt = FMT_PACKED;
     int32_t vbytes = 4;
@@ -177,6 +187,7 @@ struct scylla_batch {
     };
     std::vector<LocalLP> local;  // built on the first pump call
     std::vector<double> pump_best;
+    FPDev fpd;  // batched fix-and-propagate on the device
     // host mirrors
     std::vector<InstInfo> hinfo;
     InstState *pinned = nullptr;  // 2 * count states
@@ -233,6 +244,15 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
                      const int64_t *k_limits = nullptr, int32_t q0 = 0, int32_t q1 = -1);
 void ensure_q(scylla_batch *h);
 void cast_q(scylla_batch *h);
+
+// ---- defined in fixprop_dev.hip
+// Batched fix-and-propagate of every wanted instance on the device.
+// is_int: [N] 0/1 (host); xbar: [N] host reference values, or NULL for the
+// handle's current primal iterate; want: [count] 0/1 or NULL (all);
+// xhat: [N], info: [2 count] (feasible, ignored rows), ignored: [M] or NULL
+// (host outputs, written for the wanted instances only).
+void fp_batched(scylla_batch *h, const uint8_t *is_int, const double *xbar, int32_t K, int32_t max_rounds,
+                const uint8_t *want, double *xhat, int32_t *info, uint8_t *ignored);
 
 // Device range [lo, lo + len) of a vector in the path precision to / from
 // FP64 host values.

@@ -164,6 +164,8 @@ struct PumpOpts {
     int32_t threads;
     int32_t distance;  // 1: L1 (linear objective), 2: L2 (QP objective)
     bool pipeline;     // two instance groups: host rounding overlaps device solves
+    int32_t fp_batch = 0;        // 0: sequential rounding on the host; K: batched on the device
+    int32_t fp_max_rounds = 1000;
 };
 
 // Algorithm 1 outer loop.  legacy_best: also keep, per instance, the first
@@ -178,6 +180,9 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
         throw_err(-EINVAL, "eps schedule needs eps1 > 0, 0 < beta <= 1, eps_floor > 0");
     if (o.total_iter_limit < 0) throw_err(-EINVAL, "total_iter_limit must be >= 0");
     if (o.distance != 1 && o.distance != 2) throw_err(-EINVAL, "distance must be 1 (L1) or 2 (L2)");
+    if (o.fp_batch < 0) throw_err(-EINVAL, "fp_batch must be >= 0");
+    if (o.fp_batch > 0 && o.fp_max_rounds < 1) throw_err(-EINVAL, "fp_max_rounds must be >= 1");
+    if (o.fp_batch > 0 && o.pipeline) throw_err(-EINVAL, "device rounding (fp_batch > 0) needs pipeline = 0");
     validate_params(p);
     build_locals(h);
     const bool l2 = o.distance == 2;
@@ -213,6 +218,8 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     HIPC(hipStreamSynchronize(h->stream));
 
     std::vector<double> xhat(N), xres(N, 0.0);
+    std::vector<double> dev_xhat(o.fp_batch > 0 ? N : 0);  // device roundings of a round
+    std::vector<int32_t> dev_info(o.fp_batch > 0 ? 2 * (size_t)count : 0);
     std::vector<double> chat, qhat;  // L2: next objective and Hessian
     if (l2) {
         chat = h->hc;
@@ -291,6 +298,12 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
         const int32_t K = g.K;
         std::atomic<int> bad{0}, nonbinary{0};
         const double tr0 = now_s();
+        if (o.fp_batch > 0) {  // all roundings of the group at once on the device
+            std::vector<uint8_t> want(count, 0);
+            for (int32_t q = g.q0; q < g.q1; ++q) want[q] = active[q];
+            fp_batched(h, isint.data(), nullptr, o.fp_batch, o.fp_max_rounds, want.data(), dev_xhat.data(),
+                       dev_info.data(), nullptr);
+        }
         parallel_for(g.q1 - g.q0, o.threads, [&](int32_t qi) {
             const int32_t q = g.q0 + qi;
             if (!active[q]) return;
@@ -322,8 +335,14 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
                     return;
                 }
             }
-            if (!prep[q].ready) fp_prepare(P, ii, prep[q]);
-            fix_and_propagate(P, ii, prep[q], xq, xh, &r.xhat_feasible, &r.ignored_rows);
+            if (o.fp_batch > 0) {
+                memcpy(xh, dev_xhat.data() + c0, sizeof(double) * P.n);
+                r.xhat_feasible = dev_info[2 * q];
+                r.ignored_rows = dev_info[2 * q + 1];
+            } else {
+                if (!prep[q].ready) fp_prepare(P, ii, prep[q]);
+                fix_and_propagate(P, ii, prep[q], xq, xh, &r.xhat_feasible, &r.ignored_rows);
+            }
             double obj = 0.0;
             for (int32_t j = 0; j < P.n; ++j) obj += h->hc[c0 + j] * xh[j];
             r.xhat_obj = obj;
@@ -569,6 +588,8 @@ int scylla_pump_params_default(scylla_pump_params *o)
     o->threads = 0;
     o->distance = 1;
     o->pipeline = 0;
+    o->fp_batch = 0;
+    o->fp_max_rounds = 1000;
     return 0;
 }
 
@@ -580,7 +601,8 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
         if (!opt) throw_err(-EINVAL, "pump params is NULL");
         PumpOpts o{opt->rounds,    opt->eps_schedule != 0, opt->eps1,         opt->beta,
                    opt->eps_floor, opt->alpha,             opt->total_iter_limit, opt->early_exit != 0,
-                   opt->perturb != 0, opt->seed, opt->threads, opt->distance, opt->pipeline != 0};
+                   opt->perturb != 0, opt->seed, opt->threads, opt->distance, opt->pipeline != 0,
+                   opt->fp_batch, opt->fp_max_rounds};
         return pump_impl(h, params, is_int, o, records, outcome, x_out, false);
     });
 }

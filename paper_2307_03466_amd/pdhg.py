@@ -29,7 +29,7 @@ EXPORTS = [
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
     "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
     "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
-    "scylla_batch_mip_feasible",
+    "scylla_batch_mip_feasible", "scylla_batch_fix_propagate",
 ]
 
 
@@ -124,6 +124,7 @@ def lib():
                                   ctypes.c_int),
             "scylla_pump_params_default": ([ctypes.POINTER(PumpParams)], ctypes.c_int),
             "scylla_batch_mip_feasible": ([vp, vp, dbl, vp], ctypes.c_int),
+            "scylla_batch_fix_propagate": ([vp, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
             "scylla_batch_pump_ex": ([vp, ctypes.POINTER(Params), vp, ctypes.POINTER(PumpParams),
                                       ctypes.POINTER(PumpRecord), ctypes.POINTER(PumpOutcome), vp], ctypes.c_int),
         }
@@ -172,7 +173,8 @@ class PumpParams(ctypes.Structure):
                 ("beta", ctypes.c_double), ("eps_floor", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("total_iter_limit", ctypes.c_int64), ("early_exit", ctypes.c_int32),
                 ("perturb", ctypes.c_int32), ("seed", ctypes.c_uint64), ("threads", ctypes.c_int32),
-                ("distance", ctypes.c_int32), ("pipeline", ctypes.c_int32)]
+                ("distance", ctypes.c_int32), ("pipeline", ctypes.c_int32),
+                ("fp_batch", ctypes.c_int32), ("fp_max_rounds", ctypes.c_int32)]
 
 
 class PumpOutcome(ctypes.Structure):
@@ -348,6 +350,20 @@ class Batch:
         out = np.zeros(self.count, dtype=np.int32)
         _check(lib().scylla_batch_mip_feasible(self._h, _ptr(ii), tol, _ptr(out)))
         return out
+
+    def fix_propagate(self, K: int, max_rounds: int = 1000, is_int=None, xbar=None):
+        """Batched fix-and-propagate of every instance on the device
+        (scylla_batch_fix_propagate), rounding `xbar` (all instances
+        concatenated) or, if None, the current iterates.  Returns (x_hat,
+        feasible [count] bool, ignored rows [count], ignored mask [m_total])."""
+        ii = None if is_int is None else np.ascontiguousarray(is_int, dtype=np.uint8)
+        xb = None if xbar is None else np.ascontiguousarray(xbar, dtype=np.float64)
+        xh = np.empty(sum(self.n))
+        info = np.zeros(2 * self.count, dtype=np.int32)
+        mask = np.zeros(max(1, sum(self.m)), dtype=np.uint8)
+        _check(lib().scylla_batch_fix_propagate(self._h, _ptr(ii), _ptr(xb), K, max_rounds, _ptr(xh),
+                                                _ptr(info), _ptr(mask)))
+        return xh, info[0::2].astype(bool), info[1::2].copy(), mask[: sum(self.m)].astype(bool)
 
     def set_quadratic(self, inst: int, q):
         """Diagonal Hessian (>= 0) of instance `inst`'s objective, or None."""

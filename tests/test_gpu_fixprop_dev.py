@@ -1,0 +1,164 @@
+"""GPU parity of the batched fix-and-propagate on the device
+(scylla_batch_fix_propagate) with the oracle's batched procedure, instance
+by instance.  Rounding is exact work (FP64 in a fixed order, decisions on
+integers and bounds), so the roundings, the feasibility flags, the ignored
+counts and the ignored-row masks must be identical (zeros compare by value:
+the sign of a zero bound is not part of the result)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03466_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+pdhg = pytest.importorskip("paper_2307_03466_amd.pdhg")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pdhg.lib()
+
+
+def _mixed_lp(seed, m=14, n=22, bounded=True):
+    """Tiny LP with mixed senses, continuous columns and (unbounded=False)
+    infinite bounds."""
+    rng = np.random.default_rng(seed)
+    lp = I.tiny_lp(rng, m, n, bounded=bounded)
+    lp.is_int = (rng.random(lp.n) < 0.6).astype(np.uint8)
+    return lp
+
+
+def _family():
+    return [I.set_cover(120, 300, seed=3), I.cover_knapsack(400, seed=4), I.set_partition(40, 140, seed=5),
+            _mixed_lp(6), I.int_cover_knapsack(300, seed=7), _mixed_lp(8, 30, 50, bounded=False),
+            I.cover_knapsack(3000, seed=9), _mixed_lp(10, 1, 3)]
+
+
+def _references(lps, rng):
+    """Reference values with ties in the fixing order: a quarter exact
+    integers, a quarter on .25 / .5 / .75, the rest uniform on the domain."""
+    out = []
+    for lp in lps:
+        lo = np.where(np.isfinite(lp.l), lp.l, -4.0)
+        hi = np.where(np.isfinite(lp.u), lp.u, lo + 4.0)
+        x = lo + rng.random(lp.n) * (hi - lo)
+        k = rng.random(lp.n)
+        x = np.where(k < 0.25, np.round(x), x)
+        x = np.where((k >= 0.25) & (k < 0.5), np.clip(np.floor(x) + rng.choice([0.25, 0.5, 0.75], lp.n), lo, hi), x)
+        out.append(x)
+    return out
+
+
+def _check(lps, xbars, res, K, max_rounds):
+    xh, feas, nign, mask = res
+    c0 = r0 = 0
+    for q, (lp, xb) in enumerate(zip(lps, xbars)):
+        ex, eok, en, emask = oracle.fix_propagate_batched(lp, xb, K=K, max_rounds=max_rounds)
+        got = xh[c0:c0 + lp.n]
+        assert np.array_equal(got, ex), (q, lp.name, K, max_rounds, np.flatnonzero(got != ex)[:8])
+        assert feas[q] == eok and nign[q] == en, (q, lp.name, K, max_rounds)
+        assert np.array_equal(mask[r0:r0 + lp.m], emask), (q, lp.name, K, max_rounds)
+        c0 += lp.n
+        r0 += lp.m
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("K,max_rounds", [(1, 1000), (3, 1000), (64, 1000), (10 ** 6, 1000), (1, 1), (16, 2)])
+def test_device_rounding_equals_the_oracle(prec, K, max_rounds):
+    lps = _family()
+    rng = np.random.default_rng(11 + K + max_rounds)
+    xbars = _references(lps, rng)
+    print(f"fix-propagate parity prec={prec} K={K} max_rounds={max_rounds}", flush=True)
+    with pdhg.Batch(lps, precision=prec) as b:
+        for rep in range(2):  # the device copies and work arrays are reused
+            res = b.fix_propagate(K, max_rounds, is_int=np.concatenate([lp.is_int for lp in lps]),
+                                  xbar=np.concatenate(xbars))
+            _check(lps, xbars, res, K, max_rounds)
+            xbars = _references(lps, rng)
+
+
+def test_hand_worked_cases_on_the_device():
+    """The round cap and the conflict rule of the oracle's pins, in one
+    batch: a chain that needs four rounds, and two rows that derive y >= 3
+    and y <= 1 in the same round."""
+    from tests.test_oracle_fixprop_batched import _chain, _lp
+    chain = _chain()
+    conflict = _lp([{0: -3, 1: 1}, {0: 3, 1: 1}], "GL", [0, 4], [0, 0], [1, 5], [1, 1], 2)
+    lps = [chain, conflict]
+    xb = np.array([1.0, 0.4, 0.4, 0.4, 0.4, 1.0, 2.3])
+    with pdhg.Batch(lps, precision=1) as b:
+        xh, feas, nign, mask = b.fix_propagate(1, 1000, xbar=xb)
+        assert xh.tolist() == [1, 1, 1, 1, 1, 1, 2] and feas.tolist() == [True, False]
+        assert nign.tolist() == [0, 2] and mask.tolist() == [False] * 4 + [True, True]
+        xh, feas, nign, mask = b.fix_propagate(1, 2, xbar=xb)
+        assert xh[:5].tolist() == [1, 1, 1, 0, 0] and nign.tolist() == [1, 2]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rounding_of_the_iterate(prec):
+    """xbar = NULL rounds every instance's current iterate (path precision
+    widened to FP64): the same as rounding the iterate read back."""
+    lps = I.pump_batch(6, 600, 1200, seed=21)
+    with pdhg.Batch(lps, precision=prec) as b:
+        b.solve(tol=1e-3, iter_limit=400)
+        x = b.x_all()
+        xbars, c0 = [], 0
+        for lp in lps:
+            xbars.append(x[c0:c0 + lp.n])
+            c0 += lp.n
+        for K in (1, 32):
+            _check(lps, xbars, b.fix_propagate(K), K, 1000)
+
+
+def test_full_size_pump_instances():
+    """Eight 20k x 40k cover/knapsack instances (the shape of the pump
+    workload) at their PDHG iterate after 300 iterations, K = 64."""
+    lps = I.pump_batch(8, 20_000, 40_000, seed=5)
+    with pdhg.Batch(lps, precision=1) as b:
+        b.solve(tol=1e-4, iter_limit=300)
+        x = b.x_all()
+        xbars, c0 = [], 0
+        for lp in lps:
+            xbars.append(x[c0:c0 + lp.n])
+            c0 += lp.n
+        _check(lps, xbars, b.fix_propagate(64), 64, 1000)
+
+
+def test_bad_arguments():
+    lps = [I.set_cover(20, 40, seed=1)]
+    with pdhg.Batch(lps, precision=1) as b:
+        for K, mr in [(0, 10), (1, 0)]:
+            with pytest.raises(pdhg.ScyllaError) as e:
+                b.fix_propagate(K, mr)
+            assert e.value.code == -22
+        bad = np.zeros(40)
+        bad[3] = np.nan
+        with pytest.raises(pdhg.ScyllaError):
+            b.fix_propagate(4, xbar=bad)
+
+
+def test_pump_with_device_rounding():
+    """One round of the complete loop with the device rounding: every
+    instance whose iterate is not MIP-feasible returns the device rounding of
+    that iterate (its x_out), equal to the oracle's batched rounding of the
+    iterate read back."""
+    lps = I.pump_batch(6, 800, 1600, seed=31)
+    with pdhg.Batch(lps, precision=1) as b:
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=1, fp_batch=16, perturb=0, eps_schedule=0),
+                                   tol=1e-3, iter_limit=500)
+        x = b.x_all()
+        c0 = 0
+        for q, lp in enumerate(lps):
+            xb = x[c0:c0 + lp.n]
+            ex, eok, en, _ = oracle.fix_propagate_batched(lp, xb, K=16)
+            r = recs[0][q]
+            if outs[q]["found_kind"] != 1:
+                assert np.array_equal(xo[c0:c0 + lp.n], ex), q
+                assert r["xhat_feasible"] == eok and r["ignored_rows"] == en, q
+            c0 += lp.n
+        with pytest.raises(pdhg.ScyllaError):
+            b.pump_ex(pump=dict(rounds=1, fp_batch=4, pipeline=1))

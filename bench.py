@@ -126,6 +126,38 @@ def cpu_baseline(lp, iters):
                        f"oracle (preconditioning and the start check subtracted; {t2 - t0:.1f} s of CPU)")
 
 
+def rounding_comparison(pdhg, b, lps):
+    """Fix-and-propagate of the first pump round's iterate (the LP
+    relaxations solved to 1e-4): the sequential procedure on the host (one
+    call per instance, 16 threads) against the batched procedure on the
+    device (one workgroup per instance) at K = 1 and K = 64, with the number
+    of roundings that satisfy every row."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    b.solve(tol=1e-4, iter_limit=200_000)
+    x = b.x_all()
+    offs = np.cumsum([0] + [lp.n for lp in lps])
+
+    def host(q):
+        return pdhg.fix_propagate(lps[q], x[offs[q]:offs[q + 1]])
+    with ThreadPoolExecutor(16) as ex:
+        t = time.perf_counter()
+        res = list(ex.map(host, range(len(lps))))
+        host_s = time.perf_counter() - t
+    rec = dict(host_sequential=dict(seconds=round(host_s, 4), threads=16,
+                                    feasible=int(sum(r[1] for r in res))))
+    for K in (1, 64):
+        ts = []
+        for _ in range(2):
+            t = time.perf_counter()
+            xh, feas, nign, _ = b.fix_propagate(K)
+            ts.append(time.perf_counter() - t)
+        rec[f"device_batched_K{K}"] = dict(seconds=round(min(ts), 4), feasible=int(feas.sum()),
+                                           ignored_rows=int(nign.sum()))
+    return rec
+
+
 def other_workloads(pdhg, instances, args, R):
     out = {}
     sel = set(args.workloads.split(","))
@@ -193,6 +225,8 @@ def other_workloads(pdhg, instances, args, R):
     if "5" in sel:  # pump loop: 64 x (20k x 40k), 20 rounds
         lps = instances.workload(5)
         b = pdhg.Batch(lps, precision=pdhg.FP32)
+        out["rounding_64x20k"] = rounding_comparison(pdhg, b, lps)
+        log(f"w5 rounding: {out['rounding_64x20k']}")
         t = time.perf_counter()
         recs, xh = b.pump(rounds=args.pump_rounds, alpha=0.9, tol=1e-4, iter_limit=200_000)
         el = time.perf_counter() - t
@@ -333,12 +367,13 @@ def main():
         gathered = (info["m_total"] if is_col else info["n_total"]) * 4 // max(1, blocks)
         probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
         fmt = info["format"]
-        ept = (info["col_chunk"] if is_col else info["row_chunk"]) // 256
+        nt = info["col_tile_threads" if is_col else "row_tile_threads"] or 256
+        ept = (info["col_chunk"] if is_col else info["row_chunk"]) // nt
         if blocks > 0:  # gather-blocked pass: partial sums, then the combine with the epilogue
-            kernels = [f"void k_bpart<float, float, {fmt}, 256, {ept}>(PassArgs<float>, int, int)",
+            kernels = [f"void k_bpart<float, float, {fmt}, {nt}, {ept}>(PassArgs<float>, int, int)",
                        f"void k_bcombine<float, {1 if is_col else 0}>(PassArgs<float>, int)"]
         elif blocks == 0:
-            kernels = [f"void k_pass<float, {fmt}, {1 if is_col else 0}, 256, {ept}>(PassArgs<float>, int)"]
+            kernels = [f"void k_pass<float, {fmt}, {1 if is_col else 0}, {nt}, {ept}>(PassArgs<float>, int)"]
         else:
             kernels = None
         return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",

@@ -329,17 +329,22 @@ __global__ __launch_bounds__(NT) void k_fp_batched(const FPBArgs a)
                 fpb_fold(a, i, r, fold1, touched, &s_ntouched);
             }
             __syncthreads();
-            for (int t = tid; t < nact; t += NT) {
-                const int i = act[t];
-                if (a.ign[i]) continue;
-                const RowAct r = fpb_activity(a, i);
-                if (fpb_conflicts(a, i, r)) {
-                    a.bad[i] = 1;
-                    atomicOr(&s_conflict, 1);
-                }
+            // is any combined domain empty?  (rare: only then are the rows
+            // behind it looked for)
+            for (int t = tid, nt = s_ntouched; t < nt; t += NT) {
+                const int j = touched[t];
+                const double NL = fpb_dec(fpb_load(&a.cL[j])), NU = fpb_dec(fpb_load(&a.cU[j]));
+                if (NL > NU + 1e-9 * (1.0 + fabs(NU))) atomicOr(&s_conflict, 1);
             }
             __syncthreads();
             if (s_conflict) {
+                for (int t = tid; t < nact; t += NT) {
+                    const int i = act[t];
+                    if (a.ign[i]) continue;
+                    const RowAct r = fpb_activity(a, i);
+                    if (fpb_conflicts(a, i, r)) a.bad[i] = 1;
+                }
+                __syncthreads();
                 const int nt = s_ntouched;
                 for (int t = tid; t < nact; t += NT) {
                     const int i = act[t];

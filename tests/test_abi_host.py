@@ -56,6 +56,20 @@ def test_params_default(L):
     assert L.scylla_params_default(None) == EINVAL
 
 
+def test_pump_params_default(L):
+    """The paper's loop configuration, host rounding, one group."""
+    o = pdhg.pump_params()
+    assert o.rounds == 20 and o.eps_schedule == 1 and o.alpha == 0.9 and o.perturb == 1
+    assert o.distance == 1 and o.pipeline == 0 and o.fp_batch == 0 and o.fp_max_rounds == 1000
+    assert L.scylla_pump_params_default(None) == EINVAL
+
+
+def test_device_rounding_rejects_a_null_handle(L):
+    xh = np.zeros(4)
+    info = np.zeros(2, dtype=np.int32)
+    assert L.scylla_batch_fix_propagate(None, None, None, 4, 10, pdhg._ptr(xh), pdhg._ptr(info), None) == EINVAL
+
+
 def _bad(lp, **changes):
     a = pdhg._LPArrays(lp)
     for k, v in changes.items():

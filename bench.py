@@ -299,7 +299,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="headline workload scale (1 = full size)")
     ap.add_argument("--to-tol", type=int, default=1, help="also time both paths to 1e-4 rel KKT")
     ap.add_argument("--tol-time-limit", type=float, default=60.0)
-    ap.add_argument("--cpu-iters", type=int, default=64)
+    ap.add_argument("--cpu-iters", type=int, default=320)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="fp32,fp64", help="paths to run (profiling runs may pick one)")
     ap.add_argument("--workloads", default="1,3,4,5,6", help="other workloads to measure ('' for none)")

@@ -364,7 +364,8 @@ def perturb(lp, xbar, xhat, T):
 
 def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter_limit: int = 100_000,
            total_iter_limit: int = 0, early_exit: bool = True, cycle_perturb: bool = True, seed: int = 0,
-           instance: int = 0, alpha: float = ALPHA, distance: str = "l1", **kw):
+           instance: int = 0, alpha: float = ALPHA, distance: str = "l1", fp_batch: int = 0,
+           fp_max_rounds: int = FP_MAX_ROUNDS, **kw):
     """Algorithm 1 on one instance.  Round K solves the LP relaxation with the
     current objective to tolerance eps(K) (Section 2.2; `tol` if eps_sched
     is off), warm-started from the previous round, with at most iter_limit
@@ -375,7 +376,9 @@ def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter
     (history of roundings as used, i.e. after perturbation) is perturbed; the
     objective is then updated with alpha^K from the rounding as used, with
     the L1 distance, or with distance="l2" the L2 distance (a QP solve from
-    round 2 on).  Returns (found_kind, found_round, point, records): found_kind 0 (none),
+    round 2 on).  Rounding: fix_propagate, or with fp_batch = K > 0
+    fix_propagate_batched(K, fp_max_rounds).
+    Returns (found_kind, found_round, point, records): found_kind 0 (none),
     1 (PDHG iterate), 2 (rounding); point is the find, else the last
     rounding before perturbation (None if no round ran)."""
     if distance not in ("l1", "l2"):
@@ -405,7 +408,10 @@ def scylla(lp, rounds: int = 20, eps_sched: bool = True, tol: float = 1e-4, iter
             kind, found_K, point = 1, K, r.x
             if early_exit:
                 break
-        xhat, feas, ign = fix_propagate(lp, r.x)
+        if fp_batch > 0:
+            xhat, feas, ign, _ = fix_propagate_batched(lp, r.x, fp_batch, fp_max_rounds)
+        else:
+            xhat, feas, ign = fix_propagate(lp, r.x)
         rec.update(xhat=xhat, xhat_feasible=feas, ignored=ign, obj=float(lp.c @ xhat))
         if not kind:
             point = xhat

@@ -146,6 +146,19 @@ def test_full_loop_matches_oracle_fp64():
     assert any(o["perturbations"] for o in outs) and any(o["found_kind"] == 2 for o in outs)
 
 
+@pytest.mark.parametrize("K", [1, 4])
+def test_full_loop_with_device_rounding_matches_oracle_fp64(K):
+    """The closed loop with the batched rounding on the device: the same
+    finds, rounds, perturbations and returned points as the oracle's loop
+    with its batched rounding."""
+    lps = _loop_batch()
+    ref = _oracle_loop(lps, rounds=20, seed=5, fp_batch=K)
+    with pdhg.Batch(lps, precision=0) as b:
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=20, seed=5, fp_batch=K))
+    _compare_loop(lps, recs, outs, xo, ref)
+    assert any(o["found_kind"] == 2 for o in outs)
+
+
 def test_full_loop_budget_and_no_early_exit_fp64():
     lps = _loop_batch()[:4]
     ref = _oracle_loop(lps, rounds=12, seed=9, total_iter_limit=3000, iter_limit=700, early_exit=False,

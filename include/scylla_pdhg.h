@@ -355,8 +355,11 @@ int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol
  *               within 1e-6 (1 + |b_i|): 1 / 0, number of ignored rows).
  *   ignored:    [m_total] or NULL, receives 1 for every ignored row.
  * Returns 0, -EINVAL (NULL handle / xhat / info, K or max_rounds < 1, a
- * non-finite xbar) or -ENOMEM / -EIO.  The problem's FP64 rows and column
- * incidence are copied to the device on the first call and kept. */
+ * non-finite xbar) or -ENOMEM / -EIO.  A non-finite iterate (xbar NULL)
+ * is not rejected; its variables get non-finite roundings.  Every round is
+ * a few dependent device-memory round trips, so max_rounds also bounds the
+ * run time of a call.  The problem's FP64 rows and column incidence are
+ * copied to the device on the first call and kept. */
 int scylla_batch_fix_propagate(scylla_batch *h, const uint8_t *is_int, const double *xbar, int32_t K,
                                int32_t max_rounds, double *xhat, int32_t *info, uint8_t *ignored);
 

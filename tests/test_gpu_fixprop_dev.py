@@ -162,3 +162,27 @@ def test_pump_with_device_rounding():
             c0 += lp.n
         with pytest.raises(pdhg.ScyllaError):
             b.pump_ex(pump=dict(rounds=1, fp_batch=4, pipeline=1))
+
+
+def test_edge_instances_and_many_workgroups():
+    """Row-less instances, rows without nonzeros, an instance without
+    integer columns, long rows (more nonzeros than a thread group) and 300
+    small instances in one batch (more workgroups than CUs)."""
+    from tests.lp_util import lp_from_dense
+    n = 12
+    rowless = lp_from_dense(np.zeros((0, n)), [], "", np.linspace(-1, 1, n), np.zeros(n), np.full(n, 3.0),
+                            is_int=np.ones(n))
+    emptyrows = lp_from_dense(np.zeros((3, 5)), [-1.0, 0.0, 2.0], "GEL", [1.0, -1, 0, 2, -3], -np.ones(5),
+                              np.ones(5), is_int=np.array([1, 0, 1, 0, 1]))
+    cont = _mixed_lp(40, 20, 30, bounded=False)
+    cont.is_int[:] = 0
+    rng = np.random.default_rng(3)
+    wide = lp_from_dense(rng.integers(0, 2, size=(4, 3000)).astype(float), [1500, 1400, 10, 1600], "LLGG",
+                         np.ones(3000), np.zeros(3000), np.ones(3000), is_int=np.ones(3000))
+    lps = [rowless, emptyrows, cont, wide] + [I.set_cover(12, 30, seed=s) for s in range(300)]
+    xbars = _references(lps, np.random.default_rng(5))
+    with pdhg.Batch(lps, precision=1) as b:
+        for K in (1, 7):
+            res = b.fix_propagate(K, 1000, is_int=np.concatenate([lp.is_int for lp in lps]),
+                                  xbar=np.concatenate(xbars))
+            _check(lps, xbars, res, K, 1000)

@@ -171,3 +171,34 @@ def test_bad_arguments_are_rejected():
         oracle.fix_propagate_batched(lp, np.zeros(3), K=0)
     with pytest.raises(AssertionError):
         oracle.fix_propagate_batched(lp, np.zeros(3), K=1, max_rounds=0)
+
+
+@pytest.mark.parametrize("K", [1, 5, 10_000])
+def test_identity_on_feasible_integral_points(K):
+    """Propagation is sound: a feasible integral reference keeps every
+    choice inside the domains, so no row is ignored and the rounding is the
+    reference itself, whatever the batch size.  Minimal covers of a set
+    cover, and the planted partitions of set-partitioning instances
+    (equality rows, where an unsound bound would empty a domain)."""
+    lp = I.workload(1)
+    A = lp_dense(lp)
+    rng = np.random.default_rng(K)
+    for _ in range(4):
+        x = np.ones(lp.n)
+        for j in rng.permutation(lp.n):
+            x[j] = 0
+            if np.any(A @ x < 1):
+                x[j] = 1
+        xhat, ok, nign, _ = oracle.fix_propagate_batched(lp, x, K=K)
+        assert np.array_equal(xhat, x) and ok and nign == 0
+    for seed in range(6):
+        sp = I.set_partition(30, 120, seed=seed)
+        xhat, ok, nign, _ = oracle.fix_propagate_batched(sp, sp.x_star, K=K)
+        assert np.array_equal(xhat, sp.x_star) and ok and nign == 0, seed
+
+
+def lp_dense(lp):
+    A = np.zeros((lp.m, lp.n))
+    rows = np.repeat(np.arange(lp.m), np.diff(lp.row_ptr))
+    A[rows, lp.col_idx] = lp.val
+    return A

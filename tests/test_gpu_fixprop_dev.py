@@ -186,3 +186,14 @@ def test_edge_instances_and_many_workgroups():
             res = b.fix_propagate(K, 1000, is_int=np.concatenate([lp.is_int for lp in lps]),
                                   xbar=np.concatenate(xbars))
             _check(lps, xbars, res, K, 1000)
+
+
+@pytest.mark.parametrize("K", [1, 64])
+def test_feasible_integral_reference_comes_back(K):
+    """Soundness on the device: planted set partitions (equality rows) and
+    a set cover at all ones are returned unchanged, no row ignored."""
+    lps = [I.set_partition(30, 120, seed=s) for s in range(8)] + [I.set_cover(120, 300, seed=3)]
+    xbars = [lp.x_star for lp in lps]
+    with pdhg.Batch(lps, precision=1) as b:
+        xh, feas, nign, mask = b.fix_propagate(K, xbar=np.concatenate(xbars))
+    assert np.array_equal(xh, np.concatenate(xbars)) and feas.all() and not nign.any() and not mask.any()

@@ -55,6 +55,22 @@ def canonical_bytes(m, n, nnz, fp64=False):
     return 2 * nnz * 6 + 4 * (m + 1) + 4 * (n + 1) + 28 * n + 17 * m + 4 * (m + n)
 
 
+def pass_kernels(info, is_col):
+    """Names (as rocprofv3 prints them) of the FP32 kernels one pass
+    launches in the layout `info` describes, or None for the LDS-staged
+    layouts."""
+    blocks = info["col_blocks"] if is_col else info["row_blocks"]
+    fmt = info["format"]
+    nt = info["col_tile_threads" if is_col else "row_tile_threads"] or 256
+    ept = (info["col_chunk"] if is_col else info["row_chunk"]) // nt
+    if blocks > 0:  # gather-blocked pass: partial sums, then the combine with the epilogue
+        return [f"void k_bpart<float, float, {fmt}, {nt}, {ept}>(PassArgs<float>, int, int)",
+                f"void k_bcombine<float, {1 if is_col else 0}>(PassArgs<float>, int)"]
+    if blocks == 0:
+        return [f"void k_pass<float, {fmt}, {1 if is_col else 0}, {nt}, {ept}>(PassArgs<float>, int)"]
+    return None
+
+
 def measured_traffic(kernels):
     """HBM bytes per launch of a pass made of `kernels` (sum over them of
     FETCH_SIZE x calibration + WRITE_SIZE per dispatch) from
@@ -366,21 +382,13 @@ def main():
         blocks = info["col_blocks"] if is_col else info["row_blocks"]
         gathered = (info["m_total"] if is_col else info["n_total"]) * 4 // max(1, blocks)
         probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
-        fmt = info["format"]
-        nt = info["col_tile_threads" if is_col else "row_tile_threads"] or 256
-        ept = (info["col_chunk"] if is_col else info["row_chunk"]) // nt
-        if blocks > 0:  # gather-blocked pass: partial sums, then the combine with the epilogue
-            kernels = [f"void k_bpart<float, float, {fmt}, {nt}, {ept}>(PassArgs<float>, int, int)",
-                       f"void k_bcombine<float, {1 if is_col else 0}>(PassArgs<float>, int)"]
-        elif blocks == 0:
-            kernels = [f"void k_pass<float, {fmt}, {1 if is_col else 0}, {nt}, {ept}>(PassArgs<float>, int)"]
-        else:
-            kernels = None
+        kernels = pass_kernels(info, is_col)
         return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4),
                     traffic=measured_traffic(kernels) if kernels else None,
                     kernel=("column" if is_col else "row") + " pass (" +
-                    ("k_bpart + k_bcombine, %d gather blocks" % blocks if blocks else "k_pass") + ")",
+                    ("k_bpart + k_bcombine, %d gather blocks" % blocks if blocks > 0 else
+                     "k_pass" if blocks == 0 else "k_spass, LDS-staged") + ")",
                     bytes_per_launch=nbytes, launch_ms=round(ms, 5),
                     gather_ceiling={"gathers": info["nnz_total"], "vector_bytes_per_xcd": gathered,
                                     "probe_ms": round(probe_ms, 5), "frac": round(probe_ms / ms, 3)})

@@ -48,3 +48,19 @@ def test_pass_bytes_follow_the_storage_format():
 def test_pump_workload_shape():
     lps = I.pump_batch(2, 2000, 4000)
     assert [(lp.m, lp.n) for lp in lps] == [(2000, 4000)] * 2
+
+
+def test_pass_kernel_names_match_the_traffic_table():
+    """The kernels bench.py looks up for the headline LP's layouts (normal
+    column pass and 4-block row pass on 1024-thread tiles of 4096 nonzeros,
+    and the 256-thread variants) are named as in the counter table."""
+    import json
+    table = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))["kernels"]
+    for nt, chunk in ((1024, 4096), (256, 4096), (256, 2048)):
+        info = dict(format=0, col_blocks=0, row_blocks=4, col_chunk=chunk, row_chunk=chunk,
+                    col_tile_threads=nt, row_tile_threads=nt)
+        for is_col in (True, False):
+            names = bench.pass_kernels(info, is_col)
+            assert names and all(n in table for n in names), names
+    info["col_blocks"] = -1
+    assert bench.pass_kernels(info, True) is None

@@ -382,6 +382,12 @@ def main():
         blocks = info["col_blocks"] if is_col else info["row_blocks"]
         gathered = (info["m_total"] if is_col else info["n_total"]) * 4 // max(1, blocks)
         probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
+        # every L2 request of the pass at the probe's rate: the gathers plus
+        # the coalesced algorithmic bytes (the gathered vector, read once in
+        # the byte model, left out) in 64-byte requests
+        coalesced = nbytes - (info["m_total"] if is_col else info["n_total"]) * 4
+        requests = info["nnz_total"] + coalesced / 64
+        request_ms = probe_ms * requests / info["nnz_total"]
         kernels = pass_kernels(info, is_col)
         return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4),
@@ -391,7 +397,9 @@ def main():
                      "k_pass" if blocks == 0 else "k_spass, LDS-staged") + ")",
                     bytes_per_launch=nbytes, launch_ms=round(ms, 5),
                     gather_ceiling={"gathers": info["nnz_total"], "vector_bytes_per_xcd": gathered,
-                                    "probe_ms": round(probe_ms, 5), "frac": round(probe_ms / ms, 3)})
+                                    "probe_ms": round(probe_ms, 5), "frac": round(probe_ms / ms, 3),
+                                    "requests": int(requests), "request_ms": round(request_ms, 5),
+                                    "frac_requests": round(request_ms / ms, 3)})
 
     # the dominant kernel is the slower pass; the two take about as long, so
     # both are reported

@@ -10,7 +10,12 @@ with numpy.
 Parity status of each function (pins live in tests/test_oracle_*.py):
   precondition, pdhg, kkt       pinned (brute force, closed forms, HiGHS,
                                 independent KKT, invariants, fixed point,
-                                nonexpansiveness, ||A~|| <= 1)
+                                nonexpansiveness, ||A~|| <= 1); the restart
+                                rule, the cold-start primal weight and its
+                                update, and the adaptive step rule are
+                                restated from snapshot iterates with
+                                independently computed norms
+                                (tests/test_oracle_steps.py)
   fix_propagate                 pinned (integrality/bounds, identity on
                                 feasible integral input, set-cover success,
                                 brute-force propagation soundness)
@@ -76,7 +81,7 @@ class _Result(ctypes.Structure):
                 ("iterations", ctypes.c_int64), ("rel_kkt", ctypes.c_double),
                 ("rho_p", ctypes.c_double), ("rho_d", ctypes.c_double),
                 ("rho_g", ctypes.c_double), ("pobj", ctypes.c_double),
-                ("dobj", ctypes.c_double), ("omega", ctypes.c_double)]
+                ("dobj", ctypes.c_double), ("omega", ctypes.c_double), ("eta", ctypes.c_double)]
 
 
 _lib = None
@@ -132,6 +137,7 @@ class PDHGResult:
     pobj: float
     dobj: float
     omega: float
+    eta: float
 
 
 def precondition(lp, ruiz_iters: int = 10, pock_chambolle: bool = True):
@@ -182,7 +188,7 @@ def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 6
                           ctypes.byref(res))
     assert rc == 0
     return PDHGResult(x, y, res.status, res.iterations, res.restarts, res.rel_kkt, res.rho_p,
-                      res.rho_d, res.rho_g, res.pobj, res.dobj, res.omega)
+                      res.rho_d, res.rho_g, res.pobj, res.dobj, res.omega, res.eta)
 
 
 def ray(lp, x, y, xp, yp, q=None):

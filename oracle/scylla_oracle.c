@@ -110,6 +110,7 @@ typedef struct {
     int32_t restarts;
     int64_t iterations;
     double rel_kkt, rho_p, rho_d, rho_g, pobj, dobj, omega;
+    double eta;          /* step-size factor in effect at the end */
 } orc_result;
 
 /* ------------------------------------------------------------------ helpers */
@@ -502,6 +503,7 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     res->pobj = kkt[4];
     res->dobj = kkt[5];
     res->omega = omega;
+    res->eta = eta;
 done:
     free(dr); free(dc); free(xn); free(xbar); free(aty); free(axb); free(xr); free(yr);
     free(yn); free(dxv); free(adx); free(xp); free(yp);

@@ -64,11 +64,14 @@ struct PassArgs {
     V *xP;                // [xS * rows] slice partial sums
     // adaptive step sizes: per epilogue workgroup (ipart) or long row
     // (iplong) two FP64 partials -- column pass {|D_c^-1 dx|^2, 0}, row pass
-    // {|D_r^-1 dy|^2, dy^T A dx} -- and the row pass's running A x (ax:
-    // A dx = (A x_bar - A x) / 2, A x <- A x + A dx; the row check resets it)
+    // {|D_r^-1 dy|^2, dy^T A dx}.  The column pass then writes the move
+    // dx = x+ - x (not x_bar) to `bar`, so the row pass's sum is A dx itself
+    // (no difference of two large products), and the row pass forms
+    // A x_bar = A x + 2 A dx from the running FP64 product `ax`
+    // (A x <- A x + A dx; every row check resets it to A x in FP64)
     int32_t adapt;
     double *ipart, *iplong;
-    V *ax;
+    double *ax;
     // diagonal Hessian of a QP objective (column pass / column check), or
     // null: x+ = proj((x + t D_c^2 (A^T y - c)) / (1 + t D_c^2 q))
     const V *q;
@@ -122,8 +125,8 @@ inline size_t tiny_lds_bytes(int m, int n, int rnnz, int cnnz, int vb)
 {
     auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return al(4 * (size_t)(m + 1)) + al(4 * (size_t)(n + 1)) + al(4 * (size_t)rnnz) + al(4 * (size_t)cnnz) +
-           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 8 * al((size_t)vb * n) + 5 * al((size_t)vb * m) +
-           al((size_t)m);
+           al((size_t)vb * rnnz) + al((size_t)vb * cnnz) + 8 * al((size_t)vb * n) + 4 * al((size_t)vb * m) +
+           al(8 * (size_t)m) + al((size_t)m);
 }
 
 template <class V>

@@ -164,7 +164,8 @@ __device__ __forceinline__ void stage_products(const MatView &M, const GV *__res
 // latency overlaps the matrix stream.
 template <class V>
 struct RowOps {
-    V own, rhs, diag2, lo, hi, ax, q;
+    V own, rhs, diag2, lo, hi, q;
+    double ax;  // running A x (adaptive steps)
     uint8_t sense;
 };
 
@@ -186,7 +187,10 @@ __device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> 
 
 // The fused epilogue: primal step (column pass) or dual step (row pass) of
 // Algorithm 1 for row i given its sum; with adaptive steps it also adds
-// this row's terms of the step-size estimate to ip.
+// this row's terms of the step-size estimate to ip.  Adaptive steps change
+// what the row pass gathers: the column pass stores dx = x+ - x in `bar`,
+// the row pass's sum is then (A dx)_i, and (A x_bar)_i = (A x)_i + 2 (A dx)_i
+// with the running FP64 (A x)_i.
 template <class V, int DIR>
 __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V step, bool copy_ref,
                                           const RowOps<V> &o, double (&ip)[2])
@@ -197,25 +201,25 @@ __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V 
         xn = xn < o.lo ? o.lo : xn;
         xn = xn > o.hi ? o.hi : xn;
         if (copy_ref) p.own_ref[i] = o.own;
-        p.bar[i] = (V)2 * xn - o.own;
+        p.bar[i] = p.adapt ? xn - o.own : (V)2 * xn - o.own;
         p.own[i] = xn;
         if (p.adapt) {
             const double d = (double)xn - (double)o.own;
             ip[0] += d * d / (double)o.diag2;
         }
     } else {
-        V v = o.own + step * o.diag2 * (o.rhs - sum);
+        // residual b_i - (A x_bar)_i; with adaptive steps sum = (A dx)_i
+        const V res = p.adapt ? (V)((double)o.rhs - (o.ax + 2.0 * (double)sum)) : o.rhs - sum;
+        V v = o.own + step * o.diag2 * res;
         if (o.sense == 'G') v = v > (V)0 ? v : (V)0;
         else if (o.sense == 'L') v = v < (V)0 ? v : (V)0;
         if (copy_ref) p.own_ref[i] = o.own;
         p.own[i] = v;
         if (p.adapt) {
-            // sum = (A x_bar)_i, x_bar = 2 x+ - x, so (A dx)_i = (sum - (A x)_i) / 2
             const double dy = (double)v - (double)o.own;
-            const double dax = 0.5 * ((double)sum - (double)o.ax);
             ip[0] += dy * dy / (double)o.diag2;
-            ip[1] += dy * dax;
-            p.ax[i] = (V)((double)o.ax + dax);
+            ip[1] += dy * (double)sum;
+            p.ax[i] = o.ax + (double)sum;
         }
     }
 }
@@ -737,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_check(const PassArgs<V> p)
                 col_terms(p, r0 + r, s, q);
             } else {
                 row_terms(p, r0 + r, s, q);
-                if (p.adapt) p.ax[r0 + r] = (V)s;  // A x of the current point
+                if (p.adapt) p.ax[r0 + r] = s;  // A x of the current point (FP64)
             }
         }
     }
@@ -764,7 +768,7 @@ __global__ __launch_bounds__(256) void k_combine_check(const PassArgs<V> p)
         col_terms(p, L.x, s, q);
     } else {
         row_terms(p, L.x, s, q);
-        if (p.adapt) p.ax[L.x] = (V)s;
+        if (p.adapt) p.ax[L.x] = s;
     }
     for (int k = 0; k < CHK; ++k) p.lpart[CHK * qi + k] = q[k];
 }
@@ -788,7 +792,7 @@ __global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
             col_terms(p, i, s, q);
         } else {
             row_terms(p, i, s, q);
-            if (p.adapt) p.ax[i] = (V)s;
+            if (p.adapt) p.ax[i] = s;
         }
     }
 #pragma unroll
@@ -980,7 +984,8 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepArgs a)
 template <class V>
 struct TinyLds {
     int *rptr, *cptr, *rcol, *ccol;
-    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *q, *y, *yr, *b, *dr2, *ax;
+    V *rval, *cval, *x, *xb, *xr, *c, *l, *u, *dc2, *q, *y, *yr, *b, *dr2;
+    double *ax;
     uint8_t *sense;
 };
 
@@ -1012,7 +1017,7 @@ __device__ __forceinline__ TinyLds<V> tiny_carve(unsigned char *base, int m, int
     t.yr = (V *)take(sizeof(V) * (size_t)m);
     t.b = (V *)take(sizeof(V) * (size_t)m);
     t.dr2 = (V *)take(sizeof(V) * (size_t)m);
-    t.ax = (V *)take(sizeof(V) * (size_t)m);
+    t.ax = (double *)take(8 * (size_t)m);
     t.sense = (uint8_t *)take((size_t)m);
     return t;
 }
@@ -1084,7 +1089,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         else r = bb - ax;
         const double yy = (double)L.y[i];
         const double dy = (yy - (double)L.yr[i]) / a.dr64[I.row0 + i];
-        L.ax[i] = (V)ax;  // A x of the current point (adaptive steps)
+        L.ax[i] = ax;  // A x of the current point in FP64 (adaptive steps)
         acc[0] += r * r;
         acc[1] += bb * yy;
         acc[2] += dy * dy;
@@ -1177,7 +1182,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
                 xn = xn < L.l[j] ? L.l[j] : xn;
                 xn = xn > L.u[j] ? L.u[j] : xn;
                 if (copy_ref) L.xr[j] = xj;
-                L.xb[j] = (V)2 * xn - xj;
+                L.xb[j] = a.adapt ? xn - xj : (V)2 * xn - xj;  // adaptive: the move dx
                 L.x[j] = xn;
                 if (a.adapt) {
                     const double d = (double)xn - (double)xj;
@@ -1192,7 +1197,9 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
             if (Lr > 1) axb = wave_sum_width(axb, Lr);
             if (lr == 0) {
                 const V yi = L.y[i];
-                V v = yi + sd * L.dr2[i] * (L.b[i] - axb);
+                // adaptive: axb = (A dx)_i and (A x_bar)_i = (A x)_i + 2 (A dx)_i
+                const V res = a.adapt ? (V)((double)L.b[i] - (L.ax[i] + 2.0 * (double)axb)) : L.b[i] - axb;
+                V v = yi + sd * L.dr2[i] * res;
                 const uint8_t sn = L.sense[i];
                 if (sn == 'G') v = v > (V)0 ? v : (V)0;
                 else if (sn == 'L') v = v < (V)0 ? v : (V)0;
@@ -1200,10 +1207,9 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
                 L.y[i] = v;
                 if (a.adapt) {
                     const double dy = (double)v - (double)yi;
-                    const double dax = 0.5 * ((double)axb - (double)L.ax[i]);
                     ny += dy * dy / (double)L.dr2[i];
-                    inter += dy * dax;
-                    L.ax[i] = (V)((double)L.ax[i] + dax);
+                    inter += dy * (double)axb;
+                    L.ax[i] += (double)axb;
                 }
             }
         }

@@ -48,7 +48,7 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     p.ctiles = o.ctiles.as<int4>();
     p.nctiles = o.blocked ? (int32_t)(o.bplan.ctiles.size() / 4) : 0;
     p.adapt = h->adaptive ? 1 : 0;
-    p.ax = h->ax.as<V>();
+    p.ax = h->ax.as<double>();
     p.own_prev = o.row ? h->yp.as<V>() : h->xp.as<V>();
     p.prod_prev = o.row ? h->axp.as<double>() : h->atyp.as<double>();
     if (!o.row && h->has_q) {
@@ -771,7 +771,8 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     upload(h->sense, sn, s);
     const size_t vb = sizeof(V);
     for (DevMem *d : {&h->x, &h->xbar, &h->xr, &h->cv, &h->lv, &h->uv, &h->dc2}) d->alloc((size_t)N * vb);
-    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2, &h->ax, &h->yp}) d->alloc((size_t)M * vb);
+    for (DevMem *d : {&h->y, &h->yr, &h->b_v, &h->dr2, &h->yp}) d->alloc((size_t)M * vb);
+    h->ax.alloc((size_t)M * 8);  // running A x of the adaptive steps, FP64
     h->xp.alloc((size_t)std::max(N, 1) * vb);
     h->axp.alloc((size_t)std::max(M, 1) * 8);
     h->atyp.alloc((size_t)std::max(N, 1) * 8);

@@ -134,3 +134,18 @@ def kkt_numpy(lp, x, y, c=None, q=None):
 
 def rel_err(a, ref):
     return float(np.linalg.norm(np.asarray(a, np.float64) - ref) / max(1.0, np.linalg.norm(ref)))
+
+
+def elem_err(a, ref):
+    """Largest per-entry error max_i |a_i - ref_i| / (1 + |ref_i|) (0 for empty vectors)."""
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if ref.size == 0:
+        return 0.0
+    return float(np.max(np.abs(a - ref) / (1.0 + np.abs(ref))))
+
+
+def parity_err(x, y, ref_x, ref_y):
+    """Larger of the vector error rel_err and the per-entry error elem_err
+    over both iterates: a fixed-iteration parity bar applies to both."""
+    return max(rel_err(x, ref_x), rel_err(y, ref_y), elem_err(x, ref_x), elem_err(y, ref_y))

@@ -2,15 +2,19 @@
 benchmark times (autotuned layout), through the C ABI.
 
 100 iterations with restarts off against the FP64 oracle (full vectors:
-the oracle finishes them in seconds), FP32 bar 1e-4 and FP64 bar 1e-10;
-device KKT against the oracle's KKT of the returned iterate; batches are
-checked on sampled instances plus invariants on all of them."""
+the oracle finishes them in seconds), FP32 bar 1e-4 and FP64 bar 1e-10,
+in norm and per entry; device KKT against the oracle's KKT of the returned
+iterate; every instance of the batches against its own oracle run.  Solves
+to 1e-4 relative KKT (constant and adaptive steps) have every returned
+iterate evaluated by the oracle's KKT."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_2307_03466_amd import instances as I
-from lp_util import rel_err
+from lp_util import elem_err, parity_err, rel_err
 
 pytestmark = pytest.mark.gpu
 pdhg = pytest.importorskip("paper_2307_03466_amd.pdhg")
@@ -45,8 +49,9 @@ def test_single_lp_full_size(k):
         x, y = sols[0]
         assert res[0]["iterations"] == 100
         ex, ey = rel_err(x, ref.x), rel_err(y, ref.y)
-        print(f"prec {prec}: e_x={ex:.3e} e_y={ey:.3e}", flush=True)
-        assert max(ex, ey) <= bar
+        px, py = elem_err(x, ref.x), elem_err(y, ref.y)
+        print(f"prec {prec}: e_x={ex:.3e} e_y={ey:.3e} per-entry {px:.3e} {py:.3e}", flush=True)
+        assert max(ex, ey, px, py) <= bar
         assert np.all(x >= lp.l) and np.all(x <= lp.u)
         assert np.all(y[lp.senses == ord("G")] >= 0) and np.all(y[lp.senses == ord("L")] <= 0)
         kk = oracle.kkt(lp, x, y)
@@ -64,15 +69,45 @@ def test_batch_full_size(k):
         assert res[i]["iterations"] == 100
         assert np.all(x >= lp.l) and np.all(x <= lp.u)
         assert np.all(y[lp.senses == ord("G")] >= 0) and np.all(y[lp.senses == ord("L")] <= 0)
-    sample = sorted(set(np.linspace(0, len(lps) - 1, 6).astype(int).tolist()
-                        + [int(np.argmax([l.m for l in lps]))]))
-    for i in sample:
-        lp = lps[i]
-        ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
+    # every instance against its own oracle run (the C oracle releases the
+    # interpreter lock, so the runs share the host cores)
+    def one(i):
+        ref = oracle.pdhg(lps[i], tol=-1.0, iter_limit=100, restarts=False)
         x, y = sols[i]
-        assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= 1e-4, i
-        kk = oracle.kkt(lp, x, y)
-        assert abs(res[i]["rel_kkt"] - kk["rel"]) <= 1e-9 * max(1, kk["rel"])
+        return parity_err(x, y, ref.x, ref.y), oracle.kkt(lps[i], x, y)["rel"]
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        out = list(ex.map(one, range(len(lps))))
+    worst = max(range(len(lps)), key=lambda i: out[i][0])
+    print(f"worst instance {worst}: e={out[worst][0]:.3e}", flush=True)
+    for i, (e, krel) in enumerate(out):
+        assert e <= 1e-4, (i, e)
+        assert abs(res[i]["rel_kkt"] - krel) <= 1e-9 * max(1, krel), i
+
+
+def _kkt_all(lps, sols):
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        return list(ex.map(lambda i: oracle.kkt(lps[i], *sols[i])["rel"], range(len(lps))))
+
+
+@pytest.mark.parametrize("adaptive", [0, 1])
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_full_size_to_tolerance_oracle_kkt(k, adaptive):
+    """The benchmark's FP32 solves to 1e-4 relative KKT: every returned
+    iterate meets the tolerance under the oracle's own KKT evaluation
+    (Section 2.2), and the device's reported KKT equals the oracle's."""
+    w = I.workload(k)
+    lps = w if isinstance(w, list) else [w]
+    with pdhg.Batch(lps, precision=1) as b:
+        res = b.solve(tol=1e-4, iter_limit=400_000, adaptive=adaptive)
+        sols = [b.solution(i) for i in range(len(lps))]
+    rel = _kkt_all(lps, sols)
+    its = [r["iterations"] for r in res]
+    print(f"workload {k} adaptive {adaptive}: {len(lps)} instances, iterations {min(its)}..{max(its)}, "
+          f"oracle KKT max {max(rel):.3e}", flush=True)
+    for i, r in enumerate(res):
+        assert r["status"] == pdhg.OPTIMAL, (i, r)
+        assert rel[i] <= 1e-4 * (1 + 1e-6), (i, rel[i])
+        assert abs(r["rel_kkt"] - rel[i]) <= 1e-9 * max(1, rel[i]), i
 
 
 def test_pump_full_size_two_rounds():

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2307_03466_amd import instances as I
-from lp_util import kkt_numpy, rel_err
+from lp_util import elem_err, kkt_numpy, parity_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -46,26 +46,49 @@ CASES = ["cover200", "general_small", "skewed_small", "skewed_longrows", "knapsa
 
 
 # ------------------------------------------------- adaptive step sizes
-# The adaptive rule's eta_bar divides by dy^T A dx, where A dx is the
-# difference of two products of size |A||x| (A x_bar - A x); its rounding
-# error is relative to |A||x|, not to |A dx|, so late iterations amplify any
-# change of summation order.  Two FP64 implementations of the rule that
-# differ only in rounding (the oracle forms A dx by its definition) agree to
-# about 1e-6..1e-5 after 100 iterations, so the bar for this option is 1e-4
-# in both precisions; termination is checked with the oracle's KKT.
-ADAPT_CASES = ["general_small", "skewed_longrows", "knapsack", "cover200", "mixed_bounds"]
+# The adaptive rule lets eta exceed the global step bound whenever the last
+# move allowed it, so the PDHG map stops being nonexpansive: the oracle's
+# own iterate moves by 1e-9..5e-7 after 100 adaptive iterations when c is
+# perturbed by 1e-15, and by 2e-2 when c and b are perturbed by FP32 storage
+# rounding (test_oracle_pdhg.py pins this).  No FP32 implementation can
+# therefore match the oracle to 1e-4 after 100 adaptive iterations; the
+# horizons below are where the benchmark spec's bars are attainable with margin
+# (measured spread of the oracle itself under FP32 rounding of c and b:
+# <= 4e-7 in norm and <= 1.2e-5 per entry after 10 iterations).  The FP64
+# path differs from the oracle only in summation order (it forms A x_bar as
+# A x + 2 A dx): 1e-10 in norm and per entry after 30 iterations.  FP32:
+# 1e-4 in norm, 1e-3 per entry (the per-entry spread of the oracle itself
+# under FP32 rounding of its data, times the per-iteration rounding of the
+# iterates) after 10 iterations.  Termination is checked with the oracle's
+# KKT on the full run.
+ADAPT_CASES = ["general_small", "skewed_longrows", "knapsack", "cover200", "mixed_bounds", "skewed_small"]
 
 
 @pytest.mark.parametrize("name", ADAPT_CASES)
-@pytest.mark.parametrize("prec", [0])
-def test_adaptive_step_parity(name, prec):
+@pytest.mark.parametrize("prec,iters,bar,ebar", [(0, 30, 1e-10, 1e-10), (1, 10, 1e-4, 1e-3)])
+def test_adaptive_step_parity(name, prec, iters, bar, ebar):
     lp = _case(name)
-    s = pdhg.solve(lp, tol=1e-300, iter_limit=100, restarts=0, precision=prec, autotune=0, adaptive=1,
+    s = pdhg.solve(lp, tol=1e-300, iter_limit=iters, restarts=0, precision=prec, autotune=0, adaptive=1,
                    fused_window=0)
-    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False, adaptive=True)
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=iters, restarts=False, adaptive=True)
     e = max(rel_err(s.x, ref.x), rel_err(s.y, ref.y))
-    print(f"adaptive {name} prec {prec}: e={e:.2e}", flush=True)
-    assert s.result["iterations"] == 100 and e <= 1e-4
+    ee = max(elem_err(s.x, ref.x), elem_err(s.y, ref.y))
+    print(f"adaptive {name} prec {prec} {iters} it: e={e:.2e} per-entry {ee:.2e}", flush=True)
+    assert s.result["iterations"] == iters and e <= bar and ee <= ebar
+
+
+@pytest.mark.parametrize("name", ["general_small", "knapsack", "cover200"])
+@pytest.mark.parametrize("prec,iters,bar", [(0, 30, 1e-10), (1, 10, 1e-4)])
+def test_adaptive_step_parity_fused_window(name, prec, iters, bar):
+    """The fused window (one workgroup per instance in LDS) takes the same
+    adaptive steps."""
+    lp = _case(name)
+    s = pdhg.solve(lp, tol=1e-300, iter_limit=iters, restarts=0, precision=prec, autotune=0, adaptive=1,
+                   fused_window=1)
+    ref = oracle.pdhg(lp, tol=-1.0, iter_limit=iters, restarts=False, adaptive=True)
+    e = max(rel_err(s.x, ref.x), rel_err(s.y, ref.y))
+    print(f"adaptive fused {name} prec {prec} {iters} it: e={e:.2e}", flush=True)
+    assert s.result["iterations"] == iters and e <= bar
 
 
 @pytest.mark.parametrize("fused", [1, 0])
@@ -115,6 +138,10 @@ def test_fixed_iteration_parity(name, prec, bar):
     assert s.result["iterations"] == 100 and s.result["status"] == pdhg.ITERATION_LIMIT
     ex, ey = rel_err(s.x, ref.x), rel_err(s.y, ref.y)
     assert max(ex, ey) <= bar, (ex, ey)
+    # per entry: max_i |v_i - ref_i| / (1 + |ref_i|) under the same bar
+    px, py = elem_err(s.x, ref.x), elem_err(s.y, ref.y)
+    print(f"  e_x {ex:.2e} e_y {ey:.2e} per-entry {px:.2e} {py:.2e}", flush=True)
+    assert max(px, py) <= bar, (px, py)
     # invariants hold exactly on the device iterates too
     assert np.all(s.x >= lp.l) and np.all(s.x <= lp.u)
     assert np.all(s.y[lp.senses == ord("G")] >= 0) and np.all(s.y[lp.senses == ord("L")] <= 0)
@@ -207,7 +234,7 @@ def test_blend_objective_parity():
             b.set_blend(0, xhat == lp.u, oracle.ALPHA ** K, kappa)
             r = b.solve(tol=1e-300, iter_limit=100, restarts=0, autotune=0)[0]
             x, y = b.solution(0)
-        assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= bar
+        assert parity_err(x, y, ref.x, ref.y) <= bar
         k = oracle.kkt(lp, x, y, c=c_hat)
         assert abs(r["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
 
@@ -225,7 +252,7 @@ def test_set_objective_and_warm_start_parity():
         b.set_start(0, x0, y0, omega0=2.5)
         b.solve(warm=True, tol=1e-300, iter_limit=100, restarts=0, autotune=0)
         x, y = b.solution(0)
-    assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= 1e-10
+    assert parity_err(x, y, ref.x, ref.y) <= 1e-10
 
 
 def test_numerical_error_status():
@@ -266,7 +293,7 @@ def test_layout_parity(layout, name, prec, bar):
         r = b.solve(tol=1e-300, iter_limit=100, restarts=0)[0]
         x, y = b.solution(0)
     assert r["iterations"] == 100
-    assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= bar
+    assert parity_err(x, y, ref.x, ref.y) <= bar
     k = oracle.kkt(lp, x, y)
     assert abs(r["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
 
@@ -303,7 +330,7 @@ def test_lds_sliced_layout_parity(case, prec, bar, mode):
         ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
         x, y = sols[i]
         assert res[i]["iterations"] == 100
-        assert max(rel_err(x, ref.x), rel_err(y, ref.y)) <= bar, i
+        assert parity_err(x, y, ref.x, ref.y) <= bar, i
         k = oracle.kkt(lp, x, y)
         assert abs(res[i]["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
 
@@ -361,7 +388,7 @@ def test_fused_window_parity(prec, bar):
         for i, lp in enumerate(lps):
             ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
             assert res[i]["iterations"] == 100
-            assert max(rel_err(sols[i][0], ref.x), rel_err(sols[i][1], ref.y)) <= bar, (fused, i)
+            assert parity_err(sols[i][0], sols[i][1], ref.x, ref.y) <= bar, (fused, i)
             k = oracle.kkt(lp, *sols2[i])
             assert res2[i]["status"] == pdhg.OPTIMAL and k["rel"] <= 1e-4 * (1 + 1e-6)
             if prec == 0:

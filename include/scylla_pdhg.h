@@ -95,11 +95,16 @@ typedef struct {
                              |D_r^-1 dy|^2 / omega) / (2 |dy^T A dx|) of
                              that iteration's move (PDLP's rule; a step is
                              never retried); eta starts at `eta`.  0 =
-                             constant eta (default).  The rule differences
-                             two matrix products (A x_bar - A x), so its
-                             eta is sensitive to rounding: the iterates
-                             follow other roundings of the same method to
-                             about 1e-5, not to the last bits            */
+                             constant eta (default).  The device forms
+                             A dx directly (the primal pass hands the dual
+                             pass dx = x+ - x, and A x_bar = A x + 2 A dx
+                             with an FP64 running A x reset at every
+                             check).  The rule lets eta pass the global
+                             step bound, so the iteration is not
+                             nonexpansive: rounding differences grow about
+                             10x per 10 iterations, and FP32 iterates
+                             follow the FP64 ones to 1e-4 for about 10
+                             iterations, not for 100                      */
     double infeas_tol;    /* > 0 (1e-8): at every check after the first,
                              the moves d = x - x_prev, v = y - y_prev since
                              the previous check end the solve with
@@ -356,7 +361,10 @@ int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol
  *   ignored:    [m_total] or NULL, receives 1 for every ignored row.
  * Returns 0, -EINVAL (NULL handle / xhat / info, K or max_rounds < 1, a
  * non-finite xbar) or -ENOMEM / -EIO.  A non-finite iterate (xbar NULL)
- * is not rejected; its variables get non-finite roundings.  Every round is
+ * is not rejected: its non-finite integer entries come last in the fixing
+ * order (before any continuous variable) and take the lower end of their
+ * domain, and a row whose activity at the rounding is not finite counts as
+ * violated.  Every round is
  * a few dependent device-memory round trips, so max_rounds also bounds the
  * run time of a call.  The problem's FP64 rows and column incidence are
  * copied to the device on the first call and kept. */
@@ -375,7 +383,9 @@ int scylla_batch_fix_propagate(scylla_batch *h, const uint8_t *is_int, const dou
  * inside their bounds are rejected with -EINVAL when met).  records:
  * [rounds * count] (round-major).  xhat_out: [n_total] or NULL, receives per
  * instance the rounding of the first round whose rounding is feasible, else
- * the last round's. */
+ * the last round's.  An instance whose solve ends with
+ * SCYLLA_NUMERICAL_ERROR is not rounded and is not solved again (its record
+ * of that round carries the status; later records stay zero). */
 int scylla_batch_pump(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, int32_t rounds,
                       double alpha, int32_t threads, scylla_pump_record *records, double *xhat_out);
 
@@ -460,7 +470,9 @@ int scylla_pump_params_default(scylla_pump_params *o);
  * is_int: [n_total] 0/1 or NULL (all integer).  records: [rounds * count]
  * round-major, or NULL.  outcome: [count] or NULL.  x_out: [n_total] or NULL,
  * receives per instance the point of its first find, else its last
- * rounding before perturbation (zeros if it ran no round).  params supplies
+ * rounding before perturbation (zeros if it ran no round).  An instance
+ * whose solve ends with SCYLLA_NUMERICAL_ERROR leaves the loop unrounded
+ * (found_kind 0).  params supplies
  * precision, check period, restarts, eta, per-round iteration and time
  * limits and, without the schedule, the tolerance.  Returns 0, -EINVAL or
  * -EIO (device error). */

@@ -12,6 +12,7 @@
 // integer variables and inside [l, u] (Section 2.3), not necessarily
 // row-feasible.  Exact logic: with integer data every activity is an exact
 // sum in double precision.
+#include <cmath>
 #include <math.h>
 
 #include <algorithm>
@@ -96,7 +97,9 @@ public:
             const int32_t j = o.second;
             if (dom_[j].L == dom_[j].U) continue;
             double v = ceil(xref[j] - 0.5);  // round half down
-            v = std::min(std::max(v, dom_[j].L), dom_[j].U);
+            // clamp to the domain (a NaN reference takes the lower bound)
+            if (!(v >= dom_[j].L)) v = dom_[j].L;
+            if (!(v <= dom_[j].U)) v = dom_[j].U;
             set_bounds(j, v, v);
             enqueue_rows_of(j);
             drain();
@@ -304,6 +307,7 @@ bool rows_satisfied(const FPProblem &P, const double *x, double tol)
         for (int32_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) a += P.val[e] * x[P.col[e]];
         const double t = tol * (1.0 + fabs(P.b[i]));
         const char s = P.sense[i];
+        if (!std::isfinite(a)) return false;  // a non-finite activity satisfies no row
         if ((s == 'G' || s == 'E') && a < P.b[i] - t) return false;
         if ((s == 'L' || s == 'E') && a > P.b[i] + t) return false;
     }

@@ -288,8 +288,8 @@ __global__ __launch_bounds__(NT) void k_fp_batched(const FPBArgs a)
             if (unfixed && rank < need) {
                 const double lo = a.L[j], hi = a.U[j];
                 double v = ceil(a.xbar[j] - 0.5);  // rounded half down
-                if (v < lo) v = lo;
-                if (v > hi) v = hi;
+                if (!(v >= lo)) v = lo;  // a NaN reference takes the lower bound
+                if (!(v <= hi)) v = hi;
                 a.L[j] = v;
                 a.U[j] = v;
                 fpb_store(&a.cL[j], fpb_enc(v));
@@ -416,6 +416,7 @@ __global__ __launch_bounds__(NT) void k_fp_batched(const FPBArgs a)
         for (int e = a.rptr[i]; e < a.rptr[i + 1]; ++e) s += a.val[e] * a.xhat[a.col[e]];
         const double bi = a.b[i], tol = 1e-6 * (1.0 + fabs(bi));
         const char sn = (char)a.sense[i];
+        if (!isfinite(s)) bad = 1;  // a non-finite activity satisfies no row
         if ((sn == 'G' || sn == 'E') && s < bi - tol) bad = 1;
         if ((sn == 'L' || sn == 'E') && s > bi + tol) bad = 1;
     }
@@ -429,8 +430,9 @@ __global__ __launch_bounds__(NT) void k_fp_batched(const FPBArgs a)
 }
 
 // Sort keys: the distance of the reference value to the nearest integer for
-// integer columns, 2 (after every integer) for continuous ones; values: the
-// column index, so that a stable sort breaks ties by index.
+// integer columns (1 for a non-finite value: after the finite ones, before
+// any continuous column), 2 (after every integer) for continuous ones;
+// values: the column index, so that a stable sort breaks ties by index.
 template <class V>
 __global__ __launch_bounds__(256) void k_fp_keys(const V *x, const double *xin, const uint8_t *isint, int32_t N,
                                                  double *xbar, double *key, int32_t *idx)
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(256) void k_fp_keys(const V *x, const double *xin, 
     const double v = xin ? xin[j] : (double)x[j];
     xbar[j] = v;
     const double f = v - floor(v);
-    key[j] = isint[j] ? (f < 1.0 - f ? f : 1.0 - f) : 2.0;
+    key[j] = isint[j] ? (isfinite(v) ? (f < 1.0 - f ? f : 1.0 - f) : 1.0) : 2.0;
     idx[j] = j;
 }
 

@@ -300,7 +300,7 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
         const double tr0 = now_s();
         if (o.fp_batch > 0) {  // all roundings of the group at once on the device
             std::vector<uint8_t> want(count, 0);
-            for (int32_t q = g.q0; q < g.q1; ++q) want[q] = active[q];
+            for (int32_t q = g.q0; q < g.q1; ++q) want[q] = active[q] && g.res[q].status != SCYLLA_NUMERICAL_ERROR;
             fp_batched(h, isint.data(), nullptr, o.fp_batch, o.fp_max_rounds, want.data(), dev_xhat.data(),
                        dev_info.data(), nullptr);
         }
@@ -325,6 +325,11 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
             r.rel_kkt = g.res[q].rel_kkt;
             r.solve_seconds = g.res[q].solve_seconds;
             r.tune_seconds = g.res[q].tune_seconds;
+            if (g.res[q].status == SCYLLA_NUMERICAL_ERROR) {
+                // no usable iterate: the instance leaves the loop unrounded
+                active[q] = 0;
+                return;
+            }
             r.lp_feasible = g.ok[q];
             if (r.lp_feasible && !oc.found_kind) {
                 oc.found_kind = 1;

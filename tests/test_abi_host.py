@@ -139,21 +139,23 @@ def test_bad_params_rejected(L):
 
 
 # ------------------------------------------------------------- host prep
-_DRIVER = None
+_DRIVER = {}
+SANITIZE = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 
 
-def _driver():
-    global _DRIVER
-    if _DRIVER is None:
+def _driver(sanitize=False):
+    """The host-preparation driver, optionally built with AddressSanitizer
+    and UBSan (every finding aborts the run)."""
+    if sanitize not in _DRIVER:
         exe = os.path.join(tempfile.mkdtemp(), "prep_driver")
-        subprocess.check_call(["g++", "-O1", "-std=c++17", "-o", exe,
+        subprocess.check_call(["g++", "-O1", "-std=c++17"] + (SANITIZE if sanitize else []) + ["-o", exe,
                                os.path.join(ROOT, "tests", "host", "prep_driver.cpp"),
                                os.path.join(ROOT, "paper_2307_03466_amd", "csrc", "host_prep.cpp")])
-        _DRIVER = exe
-    return _DRIVER
+        _DRIVER[sanitize] = exe
+    return _DRIVER[sanitize]
 
 
-def _run_prep(lps, precision, chunk, max_rows, extra=()):
+def _run_prep(lps, precision, chunk, max_rows, extra=(), sanitize=False):
     d = tempfile.mkdtemp()
     fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
     with open(fin, "wb") as f:
@@ -165,7 +167,7 @@ def _run_prep(lps, precision, chunk, max_rows, extra=()):
                             (lp.c, np.float64), (lp.b, np.float64), (lp.senses, np.uint8),
                             (lp.l, np.float64), (lp.u, np.float64)):
                 f.write(np.ascontiguousarray(arr, dtype=dt).tobytes())
-    subprocess.check_call([_driver(), fin, fout, str(chunk), str(max_rows)] + [str(a) for a in extra])
+    subprocess.check_call([_driver(sanitize), fin, fout, str(chunk), str(max_rows)] + [str(a) for a in extra])
     raw = open(fout, "rb").read()
     pos = 0
     out = []

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from paper_2307_03466_amd import instances as I
+from lp_util import csr
 
 pytestmark = pytest.mark.gpu
 pdhg = pytest.importorskip("paper_2307_03466_amd.pdhg")
@@ -197,3 +198,42 @@ def test_feasible_integral_reference_comes_back(K):
     with pdhg.Batch(lps, precision=1) as b:
         xh, feas, nign, mask = b.fix_propagate(K, xbar=np.concatenate(xbars))
     assert np.array_equal(xh, np.concatenate(xbars)) and feas.all() and not nign.any() and not mask.any()
+
+
+def test_device_rounding_of_a_failed_iterate():
+    """An instance whose solve ended with NUMERICAL_ERROR has a non-finite
+    iterate: its integer variables are still rounded to integers inside
+    their bounds (non-finite entries last in the fixing order, at the lower
+    end of the domain), continuous ones keep the non-finite value, and a
+    row with a non-finite activity counts as violated -- the flag agrees
+    with an independent row check of the returned point."""
+    good = I.cover_knapsack(400, seed=4)
+    bad = I.cover_knapsack(400, seed=4)
+    bad.c = bad.c * 1e60  # FP32: c -> inf and t -> 0, so the first window yields NaN
+    cover_bad = I.set_cover(120, 300, seed=3)
+    cover_bad.c = cover_bad.c * 1e60
+    lps = [good, bad, cover_bad]
+    is_int = np.ones(sum(lp.n for lp in lps), np.uint8)
+    is_int[good.n + 5] = 0  # one continuous variable in the knapsack instance that fails
+    with pdhg.Batch(lps, precision=1) as b:
+        res = b.solve(tol=1e-4, iter_limit=2000, autotune=0)
+        assert [r["status"] for r in res][1:] == [pdhg.NUMERICAL_ERROR] * 2, res
+        x_bad = b.solution(1)[0]
+        assert not np.all(np.isfinite(x_bad))
+        for K in (1, 8):
+            xh, feas, _, _ = b.fix_propagate(K, is_int=is_int)
+            off = np.cumsum([0] + [lp.n for lp in lps])
+            for q, lp in enumerate(lps):
+                xq = xh[off[q]:off[q + 1]]
+                ii = is_int[off[q]:off[q + 1]].astype(bool)
+                assert np.all(np.isfinite(xq[ii])) and np.all(xq[ii] == np.round(xq[ii]))
+                assert np.all(xq[ii] >= lp.l[ii]) and np.all(xq[ii] <= lp.u[ii])
+                ax = csr(lp) @ xq
+                tol = 1e-6 * (1 + np.abs(lp.b))
+                held = np.where(lp.senses == ord("G"), ax >= lp.b - tol,
+                                np.where(lp.senses == ord("L"), ax <= lp.b + tol, np.abs(ax - lp.b) <= tol))
+                assert bool(feas[q]) == bool(np.all(held)), (K, q)
+            # the continuous variable with a non-finite reference makes its rows fail
+            xq = xh[off[1]:off[2]]
+            if not np.isfinite(x_bad[5]):
+                assert not np.isfinite(xq[5]) and not feas[1]

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2307_03466_amd import instances as I
-from lp_util import rel_err
+from lp_util import parity_err, rel_err
 
 pytestmark = pytest.mark.gpu
 pdhg = pytest.importorskip("paper_2307_03466_amd.pdhg")
@@ -46,7 +46,7 @@ def test_open_loop_replay_matches_oracle_pump(prec):
             assert r["status"] == pdhg.OPTIMAL and k["rel"] <= 1e-4 * (1 + 1e-6)
             if prec == 0:
                 assert r["iterations"] == ref[K - 1]["iterations"]
-                assert max(rel_err(x, ref[K - 1]["x"]), rel_err(y, ref[K - 1]["y"])) <= 1e-8
+                assert parity_err(x, y, ref[K - 1]["x"], ref[K - 1]["y"]) <= 1e-8
             # the next round's objective from the oracle's rounding of this round
             b.set_blend(0, ref[K - 1]["xhat"] == lp.u, oracle.ALPHA ** K, kappa)
 
@@ -233,3 +233,33 @@ def test_pipelined_l2_loop_equals_lockstep():
         r0, o0, x0 = b.pump_ex(pump=dict(rounds=8, seed=1, distance=2, perturb=0, early_exit=0, pipeline=0))
     assert _strip(r1) == _strip(r0) and o1 == o0
     np.testing.assert_array_equal(x1, x0)
+
+
+@pytest.mark.parametrize("native", ["pump", "pump_ex"])
+def test_failed_solve_leaves_the_loop_unrounded(native):
+    """An instance whose solve ends with NUMERICAL_ERROR is not rounded and
+    not solved again; the other instances of the batch carry on."""
+    good = [I.set_cover(200, 500, seed=1), I.cover_knapsack(800, seed=2)]
+    bad = I.cover_knapsack(800, seed=2)
+    bad.c = bad.c * 1e60  # FP32: c -> inf and t -> 0, so the iterations yield NaN
+    lps = [good[0], bad, good[1]]
+    with pdhg.Batch(lps, precision=1) as b:
+        if native == "pump":
+            recs, xh = b.pump(rounds=3, tol=1e-4, iter_limit=20_000)
+        else:
+            recs, outs, xo = b.pump_ex(pump=dict(rounds=3, early_exit=0), tol=1e-4, iter_limit=20_000)
+    # the round in which the solve failed (the start point may meet a loose
+    # round-1 tolerance of the schedule before any iteration runs)
+    fail = next(k for k in range(3) if recs[k][1]["status"] == pdhg.NUMERICAL_ERROR)
+    r = recs[fail][1]
+    assert r["round"] == fail + 1 and r["xhat_feasible"] == 0 and r["lp_feasible"] == 0
+    for k in range(fail + 1, 3):
+        assert recs[k][1]["status"] == 0 and recs[k][1]["round"] == 0
+    if native == "pump_ex":
+        assert outs[1]["rounds_run"] == fail + 1
+        assert outs[0]["found_kind"] > 0  # set cover always rounds feasibly
+    for k in range(3):
+        for q in (0, 2):
+            if recs[k][q]["round"]:
+                assert recs[k][q]["status"] != pdhg.NUMERICAL_ERROR
+    assert recs[0][0]["round"] == 1 and recs[0][2]["round"] == 1

@@ -330,6 +330,22 @@ typedef struct {
  * handle or feasible, tol not finite and > 0) or -EIO (HIP error). */
 int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible);
 
+/* scylla_batch_mip_feasible for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same test and outputs, with its device flags (integer
+ * flags, row and column violations, per-instance results) in a static
+ * device array of 16 MiB that each GPU holds from the first call on it
+ * until the process ends, so it calls no hipMalloc, hipFree or other
+ * allocating routine (host or device).  The batch must need at most that
+ * much: 2 n_total + m_total + count bytes, each region rounded up to 256
+ * bytes; larger batches fail with -EINVAL and nothing is written.  is_int
+ * is copied to the device as given (nonzero = integer).  Every call on a GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other host
+ * threads, other streams) race; each call overwrites every flag it reads.
+ * Returns 0, -EINVAL (NULL handle or feasible, tol not finite and > 0, batch
+ * too large) or -EIO (HIP error). */
+int scylla_batch_mip_feasible_static(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible);
+
 /* Batched fix-and-propagate on the device (one workgroup per instance): a
  * parallel form of the rounding of Section 2.3.  Per instance, the integer
  * variables are taken in the same order as scylla_fix_propagate (ascending

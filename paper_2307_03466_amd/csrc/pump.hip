@@ -509,6 +509,55 @@ int pump_impl(scylla_batch *h, const scylla_params *p, const uint8_t *is_int, co
     return 0;
 }
 
+// ------------------------------------------------ allocation-free MIP test
+// Device scratch of scylla_batch_mip_feasible_static: integer flags [N], row
+// flags [M], column flags [N] and instance flags [count], each region at a
+// 256-byte aligned offset.  Each GPU holds its own copy for the life of the
+// process; every call on a GPU reuses it (each call overwrites every flag it
+// reads, so nothing has to start at zero), so calls that overlap on one GPU
+// race.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch, looked up once per device
+// with that device current (in host code `scratch` names a host-side
+// stand-in, not device memory).
+uint8_t *static_scratch()
+{
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw_err(-ENODEV, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        HIPC(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw_err(-EIO, "no device address for the static scratch");
+        g_scratch_dev[dev] = static_cast<uint8_t *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int32_t n)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// The MIP-feasibility test of mip_check with its flags in `scr` (layout
+// above); ok goes to the first count bytes of `out`.
+template <class V>
+void mip_check_into(scylla_batch *h, const uint8_t *isint, double tol, uint8_t *rbad, uint8_t *cbad, uint8_t *ok)
+{
+    launch_mip_check<V>(h->orow.mat, h->fmt, h->M, h->N, h->count, h->info.as<InstInfo>(), h->x.as<V>(),
+                        h->b64.as<double>(), h->sense.as<uint8_t>(), h->l64.as<double>(), h->u64.as<double>(),
+                        isint, tol, rbad, cbad, ok, h->stream);
+    HIPC(hipGetLastError());
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -558,6 +607,41 @@ int scylla_batch_mip_feasible(scylla_batch *h, const uint8_t *is_int, double tol
         std::vector<uint8_t> ok(h->count);
         mip_check(h, tol, ok.data());
         for (int32_t q = 0; q < h->count; ++q) feasible[q] = ok[q];
+        return 0;
+    });
+}
+
+int scylla_batch_mip_feasible_static(scylla_batch *h, const uint8_t *is_int, double tol, int32_t *feasible)
+{
+    return guarded([&]() {
+        if (!h || !feasible) throw_err(-EINVAL, "handle or feasible is NULL");
+        if (!(tol > 0.0) || !isfinite(tol)) throw_err(-EINVAL, "tol must be finite and > 0");
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t N = (size_t)std::max(h->N, 1), M = (size_t)std::max(h->M, 1);
+        const size_t o_rbad = al(N), o_cbad = o_rbad + al(M), o_ok = o_cbad + al(N);
+        const size_t need = o_ok + al((size_t)std::max(h->count, 1));
+        if (need > kStaticScratchBytes)
+            throw_err(-EINVAL, "the batch needs " + std::to_string(need) + " bytes of flags, more than the " +
+                                   std::to_string(kStaticScratchBytes) + "-byte static scratch");
+        uint8_t *s = static_scratch();
+        uint8_t *isint = s, *rbad = s + o_rbad, *cbad = s + o_cbad, *ok = s + o_ok;
+        if (h->N > 0) {
+            if (is_int)  // nonzero = integer, as the kernel reads it
+                HIPC(hipMemcpyAsync(isint, is_int, (size_t)h->N, hipMemcpyHostToDevice, h->stream));
+            else
+                hipLaunchKernelGGL(k_fill_u8, dim3((h->N + 255) / 256), dim3(256), 0, h->stream, isint,
+                                   (uint8_t)1, h->N);
+        }
+        if (h->vbytes == 4) mip_check_into<float>(h, isint, tol, rbad, cbad, ok);
+        else mip_check_into<double>(h, isint, tol, rbad, cbad, ok);
+        // the flags land in the first count bytes of the caller's int32
+        // array and are widened in place from the last one down (byte q
+        // sits at or below int q, so nothing unread is overwritten)
+        if (h->count > 0)
+            HIPC(hipMemcpyAsync(feasible, ok, (size_t)h->count, hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+        const uint8_t *bytes = reinterpret_cast<const uint8_t *>(feasible);
+        for (int32_t q = h->count - 1; q >= 0; --q) feasible[q] = bytes[q];
         return 0;
     });
 }

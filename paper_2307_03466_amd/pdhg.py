@@ -29,7 +29,7 @@ EXPORTS = [
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
     "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
     "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
-    "scylla_batch_mip_feasible", "scylla_batch_fix_propagate",
+    "scylla_batch_mip_feasible", "scylla_batch_fix_propagate", "scylla_batch_mip_feasible_static",
 ]
 
 
@@ -124,6 +124,7 @@ def lib():
                                   ctypes.c_int),
             "scylla_pump_params_default": ([ctypes.POINTER(PumpParams)], ctypes.c_int),
             "scylla_batch_mip_feasible": ([vp, vp, dbl, vp], ctypes.c_int),
+            "scylla_batch_mip_feasible_static": ([vp, vp, dbl, vp], ctypes.c_int),
             "scylla_batch_fix_propagate": ([vp, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
             "scylla_batch_pump_ex": ([vp, ctypes.POINTER(Params), vp, ctypes.POINTER(PumpParams),
                                       ctypes.POINTER(PumpRecord), ctypes.POINTER(PumpOutcome), vp], ctypes.c_int),
@@ -349,6 +350,14 @@ class Batch:
         ii = None if is_int is None else np.ascontiguousarray(is_int, dtype=np.uint8)
         out = np.zeros(self.count, dtype=np.int32)
         _check(lib().scylla_batch_mip_feasible(self._h, _ptr(ii), tol, _ptr(out)))
+        return out
+
+    def mip_feasible_static(self, is_int=None, tol: float = 1e-6) -> np.ndarray:
+        """mip_feasible through the allocation-free entry point
+        (scylla_batch_mip_feasible_static)."""
+        ii = None if is_int is None else np.ascontiguousarray(is_int, dtype=np.uint8)
+        out = np.zeros(self.count, dtype=np.int32)
+        _check(lib().scylla_batch_mip_feasible_static(self._h, _ptr(ii), tol, _ptr(out)))
         return out
 
     def fix_propagate(self, K: int, max_rounds: int = 1000, is_int=None, xbar=None):

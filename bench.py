@@ -46,13 +46,54 @@ def pass_bytes(info: dict, vb: int):
     return row, col
 
 
-def canonical_bytes(m, n, nnz, fp64=False):
-    """Canonical per-iteration byte model (BF16 / FP64 values, int32 indices,
-    independent of the chosen layout): both matrix streams and pointers,
-    per-column and per-row vector traffic, one full gather of each vector."""
-    if fp64:
-        return 2 * nnz * 12 + 4 * (m + 1) + 4 * (n + 1) + 56 * n + 33 * m + 8 * (m + n)
-    return 2 * nnz * 6 + 4 * (m + 1) + 4 * (n + 1) + 28 * n + 17 * m + 4 * (m + n)
+def row_value_bytes(lp):
+    """Value bytes v per nonzero of each row in the canonical byte model:
+    0 for a pattern row (every value +1 or -1: the sign fits in the index
+    word), 2 when every value is an integer with |a| <= 256 (exact in BF16),
+    4 otherwise."""
+    import numpy as np
+    a = np.abs(np.asarray(lp.val, dtype=np.float64))
+    rows = np.repeat(np.arange(lp.m), np.diff(lp.row_ptr))
+    not_pat = np.bincount(rows, weights=(a != 1.0), minlength=lp.m) > 0
+    not_bf = np.bincount(rows, weights=((a != np.round(a)) | (a > 256)), minlength=lp.m) > 0
+    return np.where(not_bf, 4, np.where(not_pat, 2, 0)), np.diff(lp.row_ptr)
+
+
+def canonical_pass_bytes(lps, fp64=False):
+    """Canonical bytes of one launch of the row pass (dual step) and of the
+    column pass (primal step), summed over the instances: every matrix
+    entry (4-byte index + v value bytes, v by row format; 8 on the FP64
+    path) and pointer read once, one full gather of the other vector, and
+    the pass's own vectors -- row pass 17 B per row (y, b, D_r^2, sense
+    read, y written; 33 B in FP64), column pass 28 B per column (x, c, l, u,
+    D_c^2 read, x and x_bar written; 56 B in FP64).  An instance's matrix
+    takes the cheaper of its two exact encodings: one format for every row
+    (the widest any row needs), or each row in its own format with a 4-byte
+    split offset per column in the column pass.  This is the per-iteration
+    model of the hot-path scope (pattern 4 B, BF16 6 B per nonzero),
+    independent of the layout the library picks."""
+    import numpy as np
+    row = col = 0
+    for lp in lps:
+        m, n, nnz = lp.m, lp.n, lp.nnz
+        if fp64:
+            mat = 12 * nnz
+            row += mat + 4 * (m + 1) + 33 * m + 8 * n
+            col += mat + 4 * (n + 1) + 56 * n + 8 * m
+            continue
+        v, lens = row_value_bytes(lp)
+        uniform = (4 + int(v[lens > 0].max(initial=0))) * nnz
+        per_row = int(np.sum((4 + v) * lens))
+        split = 4 * n if per_row + 4 * n < uniform else 0
+        mat = per_row if split else uniform
+        row += mat + 4 * (m + 1) + 17 * m + 4 * n
+        col += mat + split + 4 * (n + 1) + 28 * n + 4 * m
+    return int(row), int(col)
+
+
+def canonical_bytes(lps, fp64=False):
+    """Canonical bytes of one PDHG iteration (both passes)."""
+    return sum(canonical_pass_bytes(lps, fp64))
 
 
 def pass_kernels(info, is_col):
@@ -71,17 +112,23 @@ def pass_kernels(info, is_col):
     return None
 
 
+def kernels_sha256() -> str:
+    """Hash of the kernel source the traffic counters were taken on."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2307_03466_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def measured_traffic(kernels):
     """HBM bytes per launch of a pass made of `kernels` (sum over them of
     FETCH_SIZE x calibration + WRITE_SIZE per dispatch) from
     profiles/pmc_traffic.json, or None when the counters were taken on
     another version of the kernel source."""
-    from paper_2307_03466_amd import profsum
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernels_hip_sha256") != profsum.kernels_sha256():
+    if d.get("kernels_hip_sha256") != kernels_sha256():
         return None
     total = 0
     for kernel in kernels:
@@ -90,6 +137,21 @@ def measured_traffic(kernels):
             return None
         total += k["fetch_bytes"] + k["write_bytes"]
     return int(total)
+
+
+def probe_gather_ms(vec_bytes, gathers):
+    """Average ms of one launch of `gathers` random 4-byte gathers from a
+    vector of `vec_bytes` bytes (the passes' ceiling), measured by the
+    probe library built beside the solver (csrc/gather_probe.hip)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2307_03466_amd", "libgather_probe.so"))
+    lib.gather_probe_ms.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+    lib.gather_probe_ms.restype = ctypes.c_int
+    ms = ctypes.c_double()
+    rc = lib.gather_probe_ms(int(vec_bytes), int(gathers), ctypes.byref(ms))
+    if rc != 0:
+        raise RuntimeError(f"gather probe failed ({rc})")
+    return ms.value
 
 
 def timed_steps(batch, steps, R):
@@ -114,6 +176,8 @@ def measure(pdhg, lps, prec, steps, warmup, R, to_tol, tol_time_limit, passes=Tr
     its = steps * R
     rec = dict(info=info, setup_s=setup, seconds=dt, iters=its, iter_per_s=its / dt,
                ms_per_step=1000 * dt / steps)
+    canon = canonical_pass_bytes(lps, fp64=prec != pdhg.FP32)
+    rec.update(canon_row=canon[0], canon_col=canon[1], canon_iter=sum(canon))
     if passes:
         ms_row, ms_col = b.time_passes(20)
         rb, cb = pass_bytes(info, 4 if prec == pdhg.FP32 else 8)
@@ -125,11 +189,29 @@ def measure(pdhg, lps, prec, steps, warmup, R, to_tol, tol_time_limit, passes=Tr
                             count=len(res), iterations_max=max(r["iterations"] for r in res),
                             iterations_sum=sum(r["iterations"] for r in res),
                             seconds=res[0]["solve_seconds"], rel_kkt_max=max(r["rel_kkt"] for r in res))
+            # the handle's setup (upload, CSC copy, packing, preconditioning,
+            # tuning) happened in its first solve, timed in setup_s
     b.close()
     return rec
 
 
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(lp, iters):
+    """The FP64 oracle on the headline LP, one core: iter/s over a bounded
+    number of iterations (its preconditioning and start check subtracted)."""
     import oracle
     t0 = time.perf_counter()
     oracle.pdhg(lp, tol=-1.0, iter_limit=0)
@@ -137,9 +219,67 @@ def cpu_baseline(lp, iters):
     oracle.pdhg(lp, tol=-1.0, iter_limit=iters)
     t2 = time.perf_counter()
     per_iter = ((t2 - t1) - (t1 - t0)) / iters
-    return dict(value=round(1.0 / per_iter, 3), unit="iter/s", cores=1, kind="oracle",
+    model, ncpu = host_cpu()
+    return dict(value=round(1.0 / per_iter, 3), unit="iter/s", cores=1, kind="oracle", cpu_model=model,
+                nproc=ncpu,
                 sample=f"{iters} FP64 PDHG iterations of the same 1M x 2M LP by the single-threaded C "
                        f"oracle (preconditioning and the start check subtracted; {t2 - t0:.1f} s of CPU)")
+
+
+def cpu_baselines_other(instances, sel, iters_batched=300, iters_skewed=100):
+    """The FP64 oracle on the other workloads: single LPs on one core, the
+    batched ones with one instance per core on all cores (the C oracle
+    releases the interpreter lock).  Each on a bounded sample."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    model, ncpu = host_cpu()
+    out = dict(cpu_model=model, nproc=ncpu)
+    if "1" in sel:
+        lp = instances.workload(1)
+        t = time.perf_counter()
+        r = oracle.pdhg(lp, tol=1e-4, iter_limit=200_000)
+        el = time.perf_counter() - t
+        t = time.perf_counter()
+        xh, feas, _ = oracle.fix_propagate(lp, r.x)
+        fp = time.perf_counter() - t
+        out["set_cover_200x500"] = dict(value=round(r.iterations / el, 1), unit="iter/s", cores=1,
+                                        iterations_to_tol=r.iterations, seconds_to_tol=round(el, 4),
+                                        rounding_seconds=round(fp, 5), rounding_feasible=feas,
+                                        sample="whole solve to 1e-4 relative KKT, then fix-and-propagate")
+    if "3" in sel:
+        lp = instances.workload(3)
+        t0 = time.perf_counter()
+        oracle.pdhg(lp, tol=-1.0, iter_limit=0)
+        t1 = time.perf_counter()
+        oracle.pdhg(lp, tol=-1.0, iter_limit=iters_skewed)
+        t2 = time.perf_counter()
+        out["skewed_lp_500kx1M"] = dict(value=round(iters_skewed / max((t2 - t1) - (t1 - t0), 0.5 * (t2 - t1)), 3),
+                                        unit="iter/s",
+                                        cores=1, sample=f"{iters_skewed} iterations (setup subtracted)")
+        del lp
+    for k, key in ((4, "batch_256_uneven"), (5, "pump_64x20k")):
+        if str(k) not in sel:
+            continue
+        lps = instances.workload(k)
+        workers = min(ncpu, len(lps))
+
+        def run(lp, it):
+            oracle.pdhg(lp, tol=-1.0, iter_limit=it, restarts=False)
+        with ThreadPoolExecutor(workers) as ex:
+            t0 = time.perf_counter()
+            list(ex.map(lambda lp: run(lp, 0), lps))
+            t1 = time.perf_counter()
+            list(ex.map(lambda lp: run(lp, iters_batched), lps))
+            t2 = time.perf_counter()
+        # the setup run's time subtracted (never more than half the run)
+        per_iter = max((t2 - t1) - (t1 - t0), 0.5 * (t2 - t1)) / iters_batched
+        out[key] = dict(value=round(1.0 / per_iter, 2), unit="batch-iter/s", cores=workers,
+                        instance_iter_per_s=round(len(lps) / per_iter, 1),
+                        sample=f"{iters_batched} iterations of all {len(lps)} instances, one instance per core "
+                               f"on {workers} cores (setup subtracted)")
+        del lps
+    return out
 
 
 def rounding_comparison(pdhg, b, lps):
@@ -184,8 +324,7 @@ def other_workloads(pdhg, instances, args, R):
         t = time.perf_counter()
         xh, feas, ign = pdhg.fix_propagate(lp, s.x)
         out["set_cover_200x500_fp64"] = dict(iter_per_s=round(r["iter_per_s"], 1),
-                                             canonical_GBps=round(canonical_bytes(lp.m, lp.n, lp.nnz, True)
-                                                                  * r["iter_per_s"] / 1e9, 2),
+                                             canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 2),
                                              to_tol=r["to_tol"],
                                              to_tol_adaptive_steps=r["to_tol_adaptive"],
                                              rounding_s=round(time.perf_counter() - t, 6),
@@ -200,12 +339,15 @@ def other_workloads(pdhg, instances, args, R):
             rb, cb = r["bytes_row"], r["bytes_col"]
             rec[tag] = dict(iter_per_s=round(r["iter_per_s"], 1), ms_row=round(r["ms_row"], 4),
                             ms_col=round(r["ms_col"], 4), row_GBps=round(rb / r["ms_row"] / 1e6, 1),
-                            col_GBps=round(cb / r["ms_col"] / 1e6, 1), to_tol=r["to_tol"],
+                            col_GBps=round(cb / r["ms_col"] / 1e6, 1),
+                            row_canonical_GBps=round(r["canon_row"] / r["ms_row"] / 1e6, 1),
+                            col_canonical_GBps=round(r["canon_col"] / r["ms_col"] / 1e6, 1),
+                            canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
+                            to_tol=r["to_tol"],
                             to_tol_adaptive_steps=r["to_tol_adaptive"],
                             layout=[r["info"]["row_blocks"], r["info"]["row_chunk"], r["info"]["col_blocks"],
                                     r["info"]["col_chunk"]], long_rows=r["info"]["long_rows"])
             log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} adaptive={r['to_tol_adaptive']}")
-        rec["canonical_GBps_fp32"] = round(canonical_bytes(lp.m, lp.n, lp.nnz) * rec["fp32"]["iter_per_s"] / 1e9, 1)
         out["skewed_lp_500kx1M"] = rec
         del lp
     if "4" in sel:  # 256 uneven LPs in one handle; FP64 plain = one instance at a time
@@ -214,28 +356,41 @@ def other_workloads(pdhg, instances, args, R):
         rec = dict(count=len(lps), batch_iter_per_s=round(r["iter_per_s"], 1),
                    instance_iter_per_s=round(r["iter_per_s"] * len(lps), 1), ms_row=round(r["ms_row"], 4),
                    ms_col=round(r["ms_col"], 4), to_tol_fp32_batched=r["to_tol"],
-                   to_tol_fp32_batched_adaptive_steps=r["to_tol_adaptive"],
-                   canonical_GBps=round(canonical_bytes(sum(l.m for l in lps), sum(l.n for l in lps),
-                                                        sum(l.nnz for l in lps)) * r["iter_per_s"] / 1e9, 1))
+                   to_tol_fp32_batched_adaptive_steps=r["to_tol_adaptive"], setup_seconds=round(r["setup_s"], 3),
+                   canonical_bytes_per_iter=r["canon_iter"],
+                   canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
+                   row_canonical_GBps=round(r["canon_row"] / r["ms_row"] / 1e6, 1),
+                   col_canonical_GBps=round(r["canon_col"] / r["ms_col"] / 1e6, 1))
         log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r['to_tol']} "
             f"adaptive={r['to_tol_adaptive']}")
         if args.fp64_plain_batch:
+            # the plain FP64 path, one instance at a time through the one-shot
+            # call: its solve_seconds (iterations only) summed, and its
+            # setup_seconds (upload, CSC copy, preconditioning, graph) apart
             t = time.perf_counter()
-            done = 0
+            done, solve_s, setup_s = 0, 0.0, 0.0
             for lp in lps:
                 s = pdhg.solve(lp, tol=1e-4, iter_limit=2_000_000, precision=pdhg.FP64, autotune=0)
                 done += s.result["status"] == 1
+                solve_s += s.result["solve_seconds"]
+                setup_s += s.result["setup_seconds"]
                 if time.perf_counter() - t > args.tol_time_limit * 3:
                     break
             n_done = lps.index(lp) + 1
             el = time.perf_counter() - t
-            rec["to_tol_fp64_plain_sequential"] = dict(seconds=round(el, 3), instances=n_done, optimal=done)
+            rec["to_tol_fp64_plain_sequential"] = dict(solve_seconds=round(solve_s, 3),
+                                                       setup_seconds=round(setup_s, 3),
+                                                       wall_seconds=round(el, 3), instances=n_done, optimal=done)
             if n_done == len(lps) and r["to_tol"]["optimal"] == len(lps):
-                rec["speedup_fp32_batched_vs_fp64_plain_to_tol"] = round(el / r["to_tol"]["seconds"], 2)
+                # like for like: iteration time against iteration time, and
+                # with each side's setup added
+                rec["speedup_fp32_batched_vs_fp64_plain_to_tol"] = round(solve_s / r["to_tol"]["seconds"], 2)
+                rec["speedup_fp32_batched_vs_fp64_plain_to_tol_with_setup"] = round(
+                    (solve_s + setup_s) / (r["to_tol"]["seconds"] + r["setup_s"]), 2)
                 if r["to_tol_adaptive"]["optimal"] == len(lps):
                     rec["speedup_fp32_batched_adaptive_vs_fp64_plain_to_tol"] = round(
-                        el / r["to_tol_adaptive"]["seconds"], 2)
-            log(f"w4 fp64 plain sequential: {n_done} instances in {el:.1f}s")
+                        solve_s / r["to_tol_adaptive"]["seconds"], 2)
+            log(f"w4 fp64 plain sequential: {n_done} instances, {solve_s:.2f} s solving + {setup_s:.2f} s setup")
         out["batch_256_uneven"] = rec
         del lps
     if "5" in sel:  # pump loop: 64 x (20k x 40k), 20 rounds
@@ -259,9 +414,7 @@ def other_workloads(pdhg, instances, args, R):
                                   rounding_seconds=round(rounding_s, 3), tune_seconds=round(tune_s, 3),
                                   groups=len({r["group"] for r in recs[0]}),
                                   batch_iterations=sum(its), batch_iter_per_s=round(sum(its) / solve_s, 1),
-                                  canonical_GBps=round(canonical_bytes(sum(l.m for l in lps), sum(l.n for l in lps),
-                                                                       sum(l.nnz for l in lps))
-                                                       * sum(its) / solve_s / 1e9, 1),
+                                  canonical_GBps=round(canonical_bytes(lps) * sum(its) / solve_s / 1e9, 1),
                                   instance_iterations=inst_its,
                                   instance_iter_per_s=round(inst_its / solve_s, 1),
                                   iterations_round1=its[0], iterations_last=its[-1],
@@ -374,14 +527,19 @@ def main():
     f32 = out["fp32"]
     info = f32["info"]
     def pass_roofline(is_col):
-        """HBM roofline of one FP32 pass: algorithmic bytes over the pass's
-        HIP-event time, counter traffic, and the random-gather ceiling."""
+        """HBM roofline of one FP32 pass: canonical bytes of one launch (the
+        hot path's byte model: BF16 values 6 B and pattern 4 B per nonzero,
+        pointers, split offsets, the pass's vectors, one full gather) over
+        the pass's HIP-event time; the packed-word bytes the library's
+        format must move beside them; counter traffic; the random-gather
+        ceiling."""
         ms = f32["ms_col"] if is_col else f32["ms_row"]
         nbytes = f32["bytes_col"] if is_col else f32["bytes_row"]
-        achieved = nbytes / (ms * 1e-3) / 1e9
+        canon = f32["canon_col"] if is_col else f32["canon_row"]
+        achieved = canon / (ms * 1e-3) / 1e9
         blocks = info["col_blocks"] if is_col else info["row_blocks"]
         gathered = (info["m_total"] if is_col else info["n_total"]) * 4 // max(1, blocks)
-        probe_ms = pdhg.probe_gather(gathered, info["nnz_total"])
+        probe_ms = probe_gather_ms(gathered, info["nnz_total"])
         # every L2 request of the pass at the probe's rate: the gathers plus
         # the coalesced algorithmic bytes (the gathered vector, read once in
         # the byte model, left out) in 64-byte requests
@@ -395,7 +553,8 @@ def main():
                     kernel=("column" if is_col else "row") + " pass (" +
                     ("k_bpart + k_bcombine, %d gather blocks" % blocks if blocks > 0 else
                      "k_pass" if blocks == 0 else "k_spass, LDS-staged") + ")",
-                    bytes_per_launch=nbytes, launch_ms=round(ms, 5),
+                    bytes_per_launch=canon, bytes_per_launch_packed=nbytes,
+                    frac_packed=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4), launch_ms=round(ms, 5),
                     gather_ceiling={"gathers": info["nnz_total"], "vector_bytes_per_xcd": gathered,
                                     "probe_ms": round(probe_ms, 5), "frac": round(probe_ms / ms, 3),
                                     "requests": int(requests), "request_ms": round(request_ms, 5),
@@ -430,11 +589,10 @@ def main():
         "roofline": roofline,
         "roofline_passes": both,
         "path_GBps": round(path_bytes * f32["iter_per_s"] / 1e9, 1),
-        "canonical_GBps": round(canonical_bytes(lp.m, lp.n, lp.nnz) * f32["iter_per_s"] / 1e9, 1),
+        "canonical_GBps": round(f32["canon_iter"] * f32["iter_per_s"] / 1e9, 1),
         "fp64_plain": {"iter_per_s": round(out["fp64"]["iter_per_s"], 1),
                        "ms_row": round(out["fp64"]["ms_row"], 5), "ms_col": round(out["fp64"]["ms_col"], 5),
-                       "canonical_GBps": round(canonical_bytes(lp.m, lp.n, lp.nnz, True)
-                                               * out["fp64"]["iter_per_s"] / 1e9, 1)},
+                       "canonical_GBps": round(out["fp64"]["canon_iter"] * out["fp64"]["iter_per_s"] / 1e9, 1)},
         "speedup_fp32_vs_fp64_iter": round(f32["iter_per_s"] / out["fp64"]["iter_per_s"], 3),
         "setup_seconds": {"fp32": round(f32["setup_s"], 3), "fp64": round(out["fp64"]["setup_s"], 3)},
     }
@@ -450,6 +608,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(lp, args.cpu_iters)
+        if args.workloads:
+            line["cpu_baseline"]["other_workloads"] = cpu_baselines_other(instances, set(args.workloads.split(",")))
     print(json.dumps(line), flush=True)
 
 

@@ -228,6 +228,21 @@ int scylla_batch_set_blend(scylla_batch *h, int32_t inst, const uint8_t *xhat_bi
 int scylla_batch_set_start(scylla_batch *h, int32_t inst, const double *x0, const double *y0,
                            double omega0);
 
+/* Sets the start point of every instance from DEVICE memory (the warm start
+ * from a primal-dual pair of Section 2.1, handed over without a host copy):
+ * x0_dev [n_total] and y0_dev [m_total] are FP64 device buffers holding the
+ * concatenated vectors in instance order (either may be NULL: keep the
+ * current one), read on the handle's stream (so the caller orders their
+ * production before it, e.g. by creating the handle on the producing
+ * stream); they are converted to the path precision and projected on
+ * entry.  omega0: [count] host values, > 0 sets that instance's primal
+ * weight, or NULL.  The buffers are checked on the device first: a NaN in
+ * x0 or a non-finite value in y0 returns -EINVAL with nothing written.  The
+ * call has finished reading them when it returns.  Returns 0, -EINVAL or
+ * -EIO / -ENOMEM. */
+int scylla_batch_set_start_device(scylla_batch *h, const double *x0_dev, const double *y0_dev,
+                                  const double *omega0);
+
 /* Runs PDHG on every instance of the batch.  warm = 0: every instance starts
  * from 0 (projected) with the primal weight from its data; warm = 1: every
  * instance continues from its current (x, y, omega) (the last solve's, or
@@ -259,7 +274,8 @@ typedef struct {
     int32_t row_chunk, col_chunk; /* tile sizes in use (nonzeros per tile) */
     int32_t long_rows, long_cols; /* rows / columns split over several tiles */
     int32_t row_blocks, col_blocks; /* layout of each pass: 0 normal, 2, 4 or
-                                       8 gather blocks, -1 LDS-staged        */
+                                       8 gather blocks, -1 LDS-staged, -6
+                                       direct staged                         */
     int32_t row_staged_nnz, col_staged_nnz; /* staged tile size (nonzeros)  */
     int32_t row_staged_variant, col_staged_variant; /* staged kernel variant
                                        bits: 1 operand prefetch, 2 sub-tiles
@@ -273,6 +289,9 @@ typedef struct {
     int32_t row_tile_threads, col_tile_threads; /* threads per workgroup of
                                        the normal / gather-blocked tiles
                                        (256, or 1024 for ept -8 / -16)       */
+    int32_t row_direct, col_direct; /* instances of a direct staged pass
+                                       (blocks -6): whole gathered vector in
+                                       LDS, rows reduced in registers        */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
 
@@ -506,7 +525,11 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
  * LDS-staged layout plus LDS slices (instances whose gathered vector is up
  * to four times too long are processed one equal slice of it at a time,
  * their per-slice row sums added in slice order), -3 = as -2 with at most
- * half the LDS per workgroup; *_ept: 4, 8
+ * half the LDS per workgroup, -6 = direct staged
+ * (instances whose whole gathered vector fits in the LDS alone: the vector
+ * is copied to LDS and every row is reduced from its nonzeros in registers,
+ * a lane group per row, fused epilogue; the other instances get normal
+ * tiles); *_ept: 4, 8
  * or 16 nonzeros per thread (tiles of 256 * ept nonzeros), or -8 / -16 (the
  * tiles of ept 8 / 16 run by 1024-thread workgroups, 2 / 4 nonzeros per
  * thread).  -EINVAL otherwise. */
@@ -520,14 +543,6 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
  * of each in milliseconds, measured with HIP events.  reps >= 1. */
 int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, double *ms_col);
 
-/* Profiling aid: the device's rate of random 4-byte gathers, the cost that
- * bounds both passes (every nonzero gathers one element of the other
- * vector).  Runs `gathers` gathers at hashed positions of a float vector of
- * `vec_bytes` bytes (4 <= vec_bytes <= 1 GiB, 1 <= gathers <= 2^31) on the
- * current device, with 8, 16 and 32 gathers per thread, and returns the
- * average duration of one launch of the fastest of the three in ms (HIP
- * events, 10 launches after a warm-up).  Allocates its own buffers. */
-int scylla_probe_gather(int64_t vec_bytes, int64_t gathers, double *ms);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,25 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, OUT)
+    build_probe(verbose)
     return OUT
+
+
+PROBE_OUT = os.path.join(HERE, "libgather_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The random-gather probe the benchmark measures the passes' ceiling
+    with (csrc/gather_probe.hip), as a library of its own."""
+    tmp = PROBE_OUT + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", "-o", tmp, os.path.join(CSRC, "gather_probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for gather_probe.hip:\n" + r.stdout + r.stderr)
+    os.replace(tmp, PROBE_OUT)
+    return PROBE_OUT
 
 
 if __name__ == "__main__":

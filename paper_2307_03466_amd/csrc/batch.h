@@ -123,6 +123,15 @@ struct OrientRT {
     SlicedPlan xplan;
     int32_t x_max_vec = -1, x_sub = -1;
     DevMem xptr, xent, xval, xsub, xctiles, xP;
+    // direct staged layout (when chosen): the whole gathered vector of each
+    // qualifying instance in LDS, rows reduced in registers; normal tiles
+    // (splan.rest) for the other instances
+    bool direct = false;
+    std::vector<uint8_t> dinst;
+    std::vector<int32_t> dtiles_h;
+    DevMem dtiles;
+    int32_t dnnz = 0, dlanes = 1;
+    size_t dshmem = 0;
     // plan buffers
     DevMem tiles, longs, seg, seg64, part, lpart;
     // adaptive-step partials: 2 doubles per epilogue slot; slot spaces of the
@@ -162,6 +171,7 @@ struct scylla_batch {
     DevMem c64, corig64, l64, u64, b64, dr64, dc64;
     DevMem st, info;
     DevMem ax;              // running A x of the row pass (adaptive steps)
+    DevMem start_flag;      // validation flag of a device warm start
     DevMem q64, qv;         // diagonal Hessian (QP objectives), once set
     DevMem xp, yp, axp, atyp;  // previous check's point and products
     bool has_q = false;

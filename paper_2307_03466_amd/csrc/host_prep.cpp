@@ -503,6 +503,37 @@ void tile_sliced(const std::vector<int32_t> &inst_off, int32_t rows, int32_t sub
     }
 }
 
+void plan_direct(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
+                 const std::vector<int32_t> &gofs, int32_t max_vec, int32_t group_nnz, int32_t lanes_min,
+                 int32_t per_lane, std::vector<uint8_t> &direct, std::vector<int32_t> &tiles)
+{
+    const int32_t count = (int32_t)inst_off.size() - 1;
+    direct.assign(count, 0);
+    tiles.clear();
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t r0 = inst_off[q], r1 = inst_off[q + 1];
+        if (r1 == r0 || gofs[q + 1] - gofs[q] > max_vec) continue;
+        direct[q] = 1;
+        int32_t r = r0;
+        while (r < r1) {
+            const int32_t start = r;
+            int64_t nz = 0;
+            int32_t longest = 0;
+            while (r < r1 && nz < group_nnz) {
+                const int32_t len = ptr[r + 1] - ptr[r];
+                nz += len;
+                longest = std::max(longest, len);
+                ++r;
+            }
+            // lanes per row: enough that the longest row needs at most four
+            // rounds of per_lane nonzeros per lane
+            int32_t L = std::max(1, std::min(64, lanes_min));
+            while (L < 64 && (int64_t)longest > 4LL * per_lane * L) L <<= 1;
+            tiles.insert(tiles.end(), {start, r, q, L});
+        }
+    }
+}
+
 void plan_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &inst_off,
                  const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
                  int32_t max_slices, int32_t sub_chunk, int32_t group_nnz, SlicedPlan &plan)

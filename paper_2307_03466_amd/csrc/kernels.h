@@ -62,6 +62,10 @@ struct PassArgs {
     const int4 *xsub;     // sub-tiles of the sliced tiles
     int32_t xS;           // slices per sliced instance
     V *xP;                // [xS * rows] slice partial sums
+    // direct staged pass: tiles {r0, r1, inst, lanes per row} of instances
+    // whose whole gathered vector sits in LDS (no product buffer)
+    const int4 *dtiles;
+    int32_t ndtiles;
     // adaptive step sizes: per epilogue workgroup (ipart) or long row
     // (iplong) two FP64 partials -- column pass {|D_c^-1 dx|^2, 0}, row pass
     // {|D_r^-1 dy|^2, dy^T A dx}.  The column pass then writes the move
@@ -150,16 +154,22 @@ void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool c
 template <class V>
 void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, size_t shmem, hipStream_t s,
                    bool prepare);
+// Direct staged pass over p.dtiles (k_dpass, 1024 threads, `shmem` bytes of
+// dynamic LDS = the largest gathered vector); prepare = true only raises the
+// kernel's dynamic-LDS limit.
+constexpr int DPASS_NT = 1024;
+constexpr int DPASS_K = 8;  // nonzeros per lane per row in flight
+template <class V>
+void launch_direct(const PassArgs<V> &p, int fmt, int dir, int jw, size_t shmem, hipStream_t s, bool prepare);
 // Row combine of the LDS-sliced tiles: p.ctiles / p.nctiles / p.B / p.P set
 // to the sliced plan's combine tiles, slice count and partials.
 template <class V>
 void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s);
 void launch_decide(const DecideArgs &d, int count, hipStream_t s);
-void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s);
-// per_thread: gathers per thread (8, 16 or 32); out holds ceil(n / 2048) * 256 floats
-void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, int per_thread,
-                         hipStream_t s);
 void launch_force_stop(InstState *st, int count, hipStream_t s);
+// flag |= 1 if x[0, n) holds a NaN, |= 2 if y[0, m) holds a non-finite value
+// (either pointer may be null; *flag must start at 0).
+void launch_start_check(const double *x, int n, const double *y, int m, int *flag, hipStream_t s);
 void launch_scale_reduce(const MatView &M, int fmt, int rows, const double *drow, const double *dcol,
                          double *out, int mode, hipStream_t s);
 void launch_scale_apply(double *d, const double *r, int len, hipStream_t s);

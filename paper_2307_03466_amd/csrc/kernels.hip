@@ -593,6 +593,133 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
     }
 }
 
+// ------------------------------------------ direct LDS-staged pass
+// For instances whose whole gathered vector fits in LDS with nothing beside
+// it: a workgroup copies the instance's vector to LDS once, then each group
+// of L lanes reduces whole rows straight from their nonzeros (streamed from
+// global memory, gathered from LDS), DPASS_R rows at a time, combines its
+// lanes with shuffles and applies the fused epilogue.  The row bounds of
+// the next DPASS_R rows load while the current ones are reduced, so each
+// step waits for one round trip (the nonzeros).  Without a product buffer
+// the vector may fill the LDS.  Tile {r0, r1, inst, L}; within a row each
+// lane adds its nonzeros in order and the lanes combine in a fixed tree, so
+// the result is reproducible for a given plan.
+constexpr int DPASS_R = 4;
+
+template <class V, int FMT>
+__device__ __forceinline__ V direct_row_chunk(const MatView &M, const V *sv, int g0, int e, int e1, int L)
+{
+    uint32_t w[DPASS_K];
+    V a[DPASS_K];
+#pragma unroll
+    for (int k = 0; k < DPASS_K; ++k) {
+        const int ee = e + k * L;
+        w[k] = 0;
+        a[k] = (V)0;
+        if (ee < e1) load_entry<FMT, V>(M, ee, w[k], a[k]);
+    }
+    V s = 0;
+#pragma unroll
+    for (int k = 0; k < DPASS_K; ++k) {
+        if (e + k * L < e1) {
+            const int idx = decode_entry<FMT, V>(M, w[k], a[k]);
+            s += a[k] * sv[idx - g0];
+        }
+    }
+    return s;
+}
+
+template <class V, int FMT, int DIR, int NT>
+__global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red2[2 * NT / 64];
+    V *sv = reinterpret_cast<V *>(lds_raw);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int4 T = p.dtiles[t];
+    const InstState &S = p.st[T.z];
+    if (S.status != ST_RUN || jw >= S.nrun) return;
+    const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+    const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    const int tid = threadIdx.x, L = T.w, lane = tid & (L - 1), groups = NT / L;
+    const int g0 = p.gofs[T.z], glen = p.gofs[T.z + 1] - g0;
+    // bounds of this lane group's first DPASS_R rows, then the vector copy
+    int nb0[DPASS_R], nb1[DPASS_R];
+    const int first = T.x + tid / L;
+#pragma unroll
+    for (int u = 0; u < DPASS_R; ++u) {
+        const int r = first + u * groups;
+        nb0[u] = nb1[u] = 0;
+        if (r < T.y) {
+            nb0[u] = p.M.ptr[r];
+            nb1[u] = p.M.ptr[r + 1];
+        }
+    }
+    copy_to_lds<NT, 64 / sizeof(V)>(sv, p.gvec + g0, glen);
+    lds_barrier();
+    double ip[2] = {0.0, 0.0};
+    for (int base = first; base < T.y; base += DPASS_R * groups) {
+        int b0[DPASS_R], b1[DPASS_R];
+#pragma unroll
+        for (int u = 0; u < DPASS_R; ++u) {
+            b0[u] = nb0[u];
+            b1[u] = nb1[u];
+        }
+        // nonzeros of the current rows (first DPASS_K per lane of each)
+        uint32_t w[DPASS_R][DPASS_K];
+        V a[DPASS_R][DPASS_K];
+#pragma unroll
+        for (int u = 0; u < DPASS_R; ++u)
+#pragma unroll
+            for (int k = 0; k < DPASS_K; ++k) {
+                const int e = b0[u] + lane + k * L;
+                w[u][k] = 0;
+                a[u][k] = (V)0;
+                if (e < b1[u]) load_entry<FMT, V>(p.M, e, w[u][k], a[u][k]);
+            }
+        RowOps<V> ops[DPASS_R];
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < DPASS_R; ++u)
+                if (base + u * groups < T.y) load_ops<V, DIR>(p, base + u * groups, ops[u]);
+        }
+        // bounds of the next rows load meanwhile
+#pragma unroll
+        for (int u = 0; u < DPASS_R; ++u) {
+            const int r = base + (DPASS_R + u) * groups;
+            nb0[u] = nb1[u] = 0;
+            if (r < T.y) {
+                nb0[u] = p.M.ptr[r];
+                nb1[u] = p.M.ptr[r + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < DPASS_R; ++u) {
+            V sum = 0;
+#pragma unroll
+            for (int k = 0; k < DPASS_K; ++k) {
+                if (b0[u] + lane + k * L < b1[u]) {
+                    const int idx = decode_entry<FMT, V>(p.M, w[u][k], a[u][k]);
+                    sum += a[u][k] * sv[idx - g0];
+                }
+            }
+            // rows longer than DPASS_K per lane: further rounds
+            for (int c = lane + DPASS_K * L; b0[u] + c < b1[u]; c += DPASS_K * L)
+                sum += direct_row_chunk<V, FMT>(p.M, sv, g0, b0[u] + c, b1[u], L);
+            if (L > 1) sum = wave_sum_width(sum, L);
+            const int r = base + u * groups;
+            if (lane == 0 && r < T.y) apply_ops<V, DIR>(p, r, sum, step, copy_ref, ops[u], ip);
+        }
+    }
+    if (p.adapt) {
+        block_sum2<NT>(ip[0], ip[1], red2);
+        if (tid == 0) {
+            p.ipart[2 * t] = ip[0];
+            p.ipart[2 * t + 1] = ip[1];
+        }
+    }
+}
+
 // Long rows: add the segment partials in segment order, then the epilogue.
 template <class V, int DIR>
 __global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int jw)
@@ -1362,6 +1489,23 @@ __global__ void k_project_primal(V *x, const V *l, const V *u, int lo, int hi, i
     x[j] = v;
 }
 
+// flag |= 1 if some x[j] is NaN, |= 2 if some y[i] is not finite (a warm
+// start read from device memory is checked before anything is written).
+__global__ void k_start_check(const double *x, int n, const double *y, int m, int *flag)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (x && k < n && isnan(x[k])) bad |= 1;
+    if (y && k < m && !isfinite(y[k])) bad |= 2;
+    if (bad) atomicOr(flag, bad);
+}
+
+void launch_start_check(const double *x, int n, const double *y, int m, int *flag, hipStream_t s)
+{
+    const int nx = x ? n : 0, ny = y ? m : 0, len = nx > ny ? nx : ny;
+    if (len > 0) hipLaunchKernelGGL(k_start_check, dim3((len + 255) / 256), dim3(256), 0, s, x, n, y, m, flag);
+}
+
 template <class V>
 __global__ void k_project_dual(V *y, const uint8_t *sense, int lo, int hi, int zero)
 {
@@ -1450,62 +1594,6 @@ __global__ __launch_bounds__(256) void k_mip_reduce(const InstInfo *__restrict__
     for (int j = I.col0 + threadIdx.x; j < I.col1; j += 256) any |= cbad[j];
     any = __syncthreads_or(any);
     if (threadIdx.x == 0) feasible[blockIdx.x] = any ? 0 : 1;
-}
-
-// ----------------------------------------------------- gather probe
-// Device ceiling of the passes' dominant cost: random 4-byte gathers from a
-// vector of a given size.  Indices are a fixed hash of the position, taken
-// modulo the vector length (always in range).
-__global__ void k_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (int64_t)len) vec[i] = (float)(i & 1023) * 0.001f;
-    if (i >= n) return;
-    uint32_t x = (uint32_t)i * 2654435761u ^ 0x9e3779b9u;
-    x ^= x >> 13;
-    x *= 0x5bd1e995u;
-    x ^= x >> 15;
-    x *= 0x27d4eb2du;
-    x ^= x >> 16;
-    idx[i] = x % len;
-}
-
-template <int K>
-__global__ __launch_bounds__(256) void k_probe_gather(const uint32_t *__restrict__ idx,
-                                                     const float *__restrict__ vec, float *__restrict__ out,
-                                                     int64_t n)
-{
-    const int64_t base = (int64_t)blockIdx.x * 256 * K + threadIdx.x;
-    uint32_t w[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t e = base + (int64_t)k * 256;
-        w[k] = e < n ? __builtin_nontemporal_load(idx + e) : 0u;
-    }
-    float s = 0.0f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t e = base + (int64_t)k * 256;
-        if (e < n) s += vec[w[k]];
-    }
-    out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
-}
-
-void launch_probe_init(uint32_t *idx, int64_t n, uint32_t len, float *vec, hipStream_t s)
-{
-    const int64_t m = n > (int64_t)len ? n : (int64_t)len;
-    hipLaunchKernelGGL(k_probe_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, idx, n, len, vec);
-}
-
-void launch_probe_gather(const uint32_t *idx, const float *vec, float *out, int64_t n, int per_thread,
-                         hipStream_t s)
-{
-    const auto grid = [&](int k) { return dim3((unsigned)((n + 256 * k - 1) / (256 * k))); };
-    switch (per_thread) {
-    case 32: hipLaunchKernelGGL(k_probe_gather<32>, grid(32), dim3(256), 0, s, idx, vec, out, n); break;
-    case 16: hipLaunchKernelGGL(k_probe_gather<16>, grid(16), dim3(256), 0, s, idx, vec, out, n); break;
-    default: hipLaunchKernelGGL(k_probe_gather<8>, grid(8), dim3(256), 0, s, idx, vec, out, n); break;
-    }
 }
 
 // ------------------------------------------------------ host launchers
@@ -1672,6 +1760,38 @@ void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, 
     }
 }
 
+template <class V, int FMT, int DIR>
+void direct_t(const PassArgs<V> &p, int jw, size_t shmem, hipStream_t s, bool prepare)
+{
+    auto fn = k_dpass<V, FMT, DIR, DPASS_NT>;
+    if (prepare) {
+        (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        return;
+    }
+    hipLaunchKernelGGL(fn, dim3(p.ndtiles), dim3(DPASS_NT), shmem, s, p, jw);
+}
+
+template <class V>
+void launch_direct(const PassArgs<V> &p, int fmt, int dir, int jw, size_t shmem, hipStream_t s, bool prepare)
+{
+    if (!prepare && p.ndtiles <= 0) return;
+    if constexpr (sizeof(V) == 8) {
+        if (dir == DIR_COL) direct_t<V, FMT_F64, DIR_COL>(p, jw, shmem, s, prepare);
+        else direct_t<V, FMT_F64, DIR_ROW>(p, jw, shmem, s, prepare);
+    } else {
+        if (fmt == FMT_PACKED) {
+            if (dir == DIR_COL) direct_t<V, FMT_PACKED, DIR_COL>(p, jw, shmem, s, prepare);
+            else direct_t<V, FMT_PACKED, DIR_ROW>(p, jw, shmem, s, prepare);
+        } else if (fmt == FMT_BF16) {
+            if (dir == DIR_COL) direct_t<V, FMT_BF16, DIR_COL>(p, jw, shmem, s, prepare);
+            else direct_t<V, FMT_BF16, DIR_ROW>(p, jw, shmem, s, prepare);
+        } else {
+            if (dir == DIR_COL) direct_t<V, FMT_F32, DIR_COL>(p, jw, shmem, s, prepare);
+            else direct_t<V, FMT_F32, DIR_ROW>(p, jw, shmem, s, prepare);
+        }
+    }
+}
+
 template <class V>
 void launch_combine(const PassArgs<V> &p, int dir, int jw, hipStream_t s)
 {
@@ -1779,6 +1899,7 @@ void launch_mip_check(const MatView &M, int fmt, int m, int n, int count, const 
     template void launch_staged<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, bool, hipStream_t);    \
     template void launch_combine<V>(const PassArgs<V> &, int, int, hipStream_t);                       \
+    template void launch_direct<V>(const PassArgs<V> &, int, int, int, size_t, hipStream_t, bool);      \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
     template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \
     template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \

@@ -104,7 +104,7 @@ void ip_layout(OrientRT &o)
 {
     auto n4 = [](const std::vector<int32_t> &v) { return (int32_t)(v.size() / 4); };
     o.ipo_long = o.ipo_comb = o.ipo_rest = o.ipo_rlong = 0;
-    if (o.staged) {
+    if (o.staged || o.direct) {
         o.ipo_comb = o.nstiles;
         o.ipo_rest = o.ipo_comb + (o.sliced ? n4(o.xplan.ctiles) : 0);
         o.ipo_rlong = o.ipo_rest + n4(o.splan.rest.tiles);
@@ -130,6 +130,7 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
     o.ept = ept;
     o.staged = false;
     o.sliced = false;
+    o.direct = false;
     if (B > 0) {
         if (!o.blocked || o.bh.B != B) {
             build_blocked(o.host, h->fmt, o.gather, B, o.bh);
@@ -264,6 +265,38 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     ip_layout(o);
 }
 
+// Direct staged layout: instances whose whole gathered vector fits in the
+// LDS get direct tiles of about `group_nnz` nonzeros (at least `lanes_min`
+// lanes per row), the others normal tiles with `ept`.
+void set_direct(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, int32_t lanes_min)
+{
+    set_plan(h, o, 0, ept);
+    const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
+    const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
+    const int32_t max_vec = (h->lds_max - 1024) / h->vbytes;  // room for the kernel's static LDS
+    plan_direct(o.host.ptr, off, gofs, max_vec, group_nnz, lanes_min, DPASS_K, o.dinst, o.dtiles_h);
+    upload(o.dtiles, o.dtiles_h, h->stream);
+    plan_tiles(o.host.ptr, off, 256 * std::abs(ept), 1024, o.splan.rest, o.dinst.data());
+    upload(o.gofs, gofs, h->stream);
+    upload(o.rtiles, o.splan.rest.tiles, h->stream);
+    upload(o.rlongs, o.splan.rest.longs, h->stream);
+    o.rseg.alloc(std::max<size_t>(1, o.splan.rest.nslots) * h->vbytes);
+    int32_t vmax = 1;
+    for (int32_t q = 0; q < h->count; ++q)
+        if (o.dinst[q]) vmax = std::max(vmax, gofs[q + 1] - gofs[q]);
+    o.dshmem = (size_t)vmax * h->vbytes;
+    PassArgs<float> pf{};
+    PassArgs<double> pd{};
+    if (h->vbytes == 4) launch_direct<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, 0, o.dshmem, h->stream, true);
+    else launch_direct<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, 0, o.dshmem, h->stream, true);
+    HIPC(hipStreamSynchronize(h->stream));
+    o.nstiles = (int32_t)(o.dtiles_h.size() / 4);
+    o.direct = o.nstiles > 0;
+    o.dnnz = group_nnz;
+    o.dlanes = lanes_min;
+    ip_layout(o);
+}
+
 // Drops the blocked layout's device copy (after the tuner chose normal).
 void drop_blocked(OrientRT &o)
 {
@@ -306,7 +339,22 @@ void refresh_info(scylla_batch *h)
             // slots of this instance's epilogues in the iteration partials
             int32_t (*ir)[2] = I.ir[d];
             for (int r = 0; r < 3; ++r) ir[r][0] = ir[r][1] = 0;
-            if (o.staged) {
+            if (o.direct) {
+                if (o.dinst[q]) {
+                    int32_t a = -1, b = -1;
+                    for (size_t t = 0; t < o.dtiles_h.size() / 4; ++t)
+                        if (o.dtiles_h[4 * t + 2] == q) {
+                            if (a < 0) a = (int32_t)t;
+                            b = (int32_t)t + 1;
+                        }
+                    if (a >= 0) { ir[0][0] = a; ir[0][1] = b; }
+                } else {
+                    ir[0][0] = o.ipo_rest + o.splan.rest.t_begin[q];
+                    ir[0][1] = o.ipo_rest + o.splan.rest.t_end[q];
+                    ir[1][0] = o.ipo_rlong + o.splan.rest.l_begin[q];
+                    ir[1][1] = o.ipo_rlong + o.splan.rest.l_end[q];
+                }
+            } else if (o.staged) {
                 if (o.splan.staged[q]) {
                     int32_t a = -1, b = -1;
                     for (size_t t = 0; t < o.splan.tiles.size() / 4; ++t)
@@ -355,6 +403,30 @@ template <class V>
 void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, bool check, hipStream_t s)
 {
     const int dir = o.row ? DIR_ROW : DIR_COL;
+    if (o.direct && !check) {
+        PassArgs<V> pd = p;
+        pd.dtiles = o.dtiles.as<int4>();
+        pd.ndtiles = o.nstiles;
+        pd.gofs = o.gofs.as<int32_t>();
+        PassArgs<V> pr = p;  // normal tiles of the other instances
+        pr.tiles = o.rtiles.as<int4>();
+        pr.ntiles = (int32_t)(o.splan.rest.tiles.size() / 4);
+        pr.longs = o.rlongs.as<int4>();
+        pr.nlong = (int32_t)(o.splan.rest.longs.size() / 4);
+        pr.seg = o.rseg.as<V>();
+        pr.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_rest;
+        pr.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_rlong;
+        const bool fork = pr.ntiles > 0 || pr.nlong > 0;
+        if (fork) {
+            HIPC(hipEventRecord(h->fork, s));
+            HIPC(hipStreamWaitEvent(h->side, h->fork, 0));
+            launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
+            HIPC(hipEventRecord(h->join, h->side));
+        }
+        launch_direct<V>(pd, h->fmt, dir, jw, o.dshmem, s, false);
+        if (fork) HIPC(hipStreamWaitEvent(s, h->join, 0));
+        return;
+    }
     if (o.staged && !check) {
         PassArgs<V> ps = p;
         ps.tiles = o.stiles.as<int4>();
@@ -608,7 +680,11 @@ void tune_store(const std::string &key, const TuneChoice &c)
 
 void apply_choice(scylla_batch *h, OrientRT &o, const int32_t *v)
 {
-    if (v[0] < 0) {
+    if (v[0] == -2) {
+        set_direct(h, o, v[1], v[2], v[3]);
+        drop_blocked(o);
+        release_sliced(o);
+    } else if (v[0] < 0) {
         set_staged(h, o, v[1], v[2], v[3] & 3, (v[3] >> 2) & 1, (v[3] >> 3) & 1);
         drop_blocked(o);
     } else {
@@ -623,10 +699,11 @@ TuneChoice current_choice(scylla_batch *h)
     for (int d = 0; d < 2; ++d) {
         const OrientRT &o = d == 0 ? h->orow : h->ocol;
         int32_t *v = c.v + 4 * d;
-        v[0] = o.staged ? -1 : (o.blocked ? o.bh.B : 0);
+        v[0] = o.direct ? -2 : (o.staged ? -1 : (o.blocked ? o.bh.B : 0));
         v[1] = o.ept;
-        v[2] = o.staged ? o.staged_nnz : 0;
-        v[3] = o.staged ? (o.svariant | (o.sliced ? 4 : 0) | (o.shalf ? 8 : 0)) : 0;
+        v[2] = o.direct ? o.dnnz : (o.staged ? o.staged_nnz : 0);
+        v[3] = o.direct ? o.dlanes
+                        : (o.staged ? (o.svariant | (o.sliced ? 4 : 0) | (o.shalf ? 8 : 0)) : 0);
     }
     return c;
 }
@@ -713,7 +790,37 @@ void autotune(scylla_batch *h)
                             }
                         }
         }
-        if (best_B < 0) {
+        // direct staged candidates when some instance's whole gathered
+        // vector fits in the LDS with nothing beside it
+        const int64_t dmax = (h->lds_max - 1024) / h->vbytes;
+        const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
+        bool any_direct = false;
+        for (int32_t q = 0; q < h->count; ++q) any_direct |= g[q + 1] - g[q] <= dmax && off[q + 1] > off[q];
+        int best_dnnz = 0, best_dl = 1;
+        if (any_direct && o.rows > 0) {
+            for (int lanes : {2, 4, 8, 16})
+                for (int nnz : {32768, 65536}) {
+                    const double tp = now_s();
+                    set_direct(h, o, best_ept, nnz, lanes);
+                    const double tt = now_s();
+                    if (!o.direct) continue;
+                    const double ms = timer.time(o, 10);
+                    if (trace)
+                        fprintf(stderr, "tune %s direct lanes=%d nnz=%d plan %.1f ms run %.3f ms (timing %.1f ms)\n",
+                                o.row ? "row" : "col", lanes, nnz, (tt - tp) * 1e3, ms, (now_s() - tt) * 1e3);
+                    if (ms < best) {
+                        best = ms;
+                        best_dnnz = nnz;
+                        best_dl = lanes;
+                        best_B = -2;
+                    }
+                }
+        }
+        if (best_B == -2) {
+            set_direct(h, o, best_ept, best_dnnz, best_dl);
+            drop_blocked(o);
+            release_sliced(o);
+        } else if (best_B < 0) {
             set_staged(h, o, best_ept, best_nnz, best_var, best_slice, best_half);
             drop_blocked(o);
         } else {
@@ -1223,6 +1330,49 @@ int scylla_batch_set_start(scylla_batch *h, int32_t inst, const double *x0, cons
     });
 }
 
+int scylla_batch_set_start_device(scylla_batch *h, const double *x0_dev, const double *y0_dev,
+                                  const double *omega0)
+{
+    return guarded([&]() {
+        if (!h) throw_err(-EINVAL, "handle is NULL");
+        if (omega0)
+            for (int32_t q = 0; q < h->count; ++q)
+                if (!(omega0[q] <= 0.0 || isfinite(omega0[q]))) throw_err(-EINVAL, "non-finite omega0");
+        // validated on the device before anything is written
+        if (x0_dev || y0_dev) {
+            if (h->start_flag.bytes < sizeof(int)) h->start_flag.alloc(sizeof(int));
+            HIPC(hipMemsetAsync(h->start_flag.p, 0, sizeof(int), h->stream));
+            launch_start_check(x0_dev, h->N, y0_dev, h->M, h->start_flag.as<int>(), h->stream);
+            HIPC(hipGetLastError());
+            int bad = 0;
+            HIPC(hipMemcpyAsync(&bad, h->start_flag.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPC(hipStreamSynchronize(h->stream));
+            if (bad & 1) throw_err(-EINVAL, "NaN in x0");
+            if (bad & 2) throw_err(-EINVAL, "non-finite y0");
+        }
+        if (h->vbytes == 4) {
+            if (x0_dev) launch_cast<float>(x0_dev, h->x.as<float>(), h->N, h->stream);
+            if (y0_dev) launch_cast<float>(y0_dev, h->y.as<float>(), h->M, h->stream);
+            project_range<float>(h, 0, h->count, 0);
+        } else {
+            if (x0_dev) launch_cast<double>(x0_dev, h->x.as<double>(), h->N, h->stream);
+            if (y0_dev) launch_cast<double>(y0_dev, h->y.as<double>(), h->M, h->stream);
+            project_range<double>(h, 0, h->count, 0);
+        }
+        if (omega0) {
+            std::vector<InstState> st;
+            read_states(h, st);
+            for (int32_t q = 0; q < h->count; ++q)
+                if (omega0[q] > 0.0) st[q].omega = omega0[q];
+            HIPC(hipMemcpyAsync(h->st.p, st.data(), sizeof(InstState) * h->count, hipMemcpyHostToDevice,
+                                h->stream));
+        }
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(h->stream));
+        return 0;
+    });
+}
+
 int scylla_batch_solve(scylla_batch *h, const scylla_params *p, int32_t warm, scylla_result *results)
 {
     return guarded([&]() { return batch_solve_impl(h, p, warm, results); });
@@ -1284,8 +1434,8 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->col_tile_threads = h->ocol.ept < 0 ? 1024 : 256;
         info->long_rows = h->orow.nlong();
         info->long_cols = h->ocol.nlong();
-        info->row_blocks = h->orow.staged ? -1 : (h->orow.blocked ? h->orow.bh.B : 0);
-        info->col_blocks = h->ocol.staged ? -1 : (h->ocol.blocked ? h->ocol.bh.B : 0);
+        info->row_blocks = h->orow.direct ? -6 : (h->orow.staged ? -1 : (h->orow.blocked ? h->orow.bh.B : 0));
+        info->col_blocks = h->ocol.direct ? -6 : (h->ocol.staged ? -1 : (h->ocol.blocked ? h->ocol.bh.B : 0));
         info->row_staged_nnz = h->orow.staged ? h->orow.staged_nnz : 0;
         info->col_staged_nnz = h->ocol.staged ? h->ocol.staged_nnz : 0;
         info->row_staged_variant = h->orow.staged ? h->orow.svariant : 0;
@@ -1298,6 +1448,12 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         info->col_slices = h->ocol.sliced ? h->ocol.xplan.S : 0;
         info->row_half_lds = h->orow.staged && h->orow.shalf;
         info->col_half_lds = h->ocol.staged && h->ocol.shalf;
+        for (int32_t q = 0; q < h->count; ++q) {
+            info->row_direct += h->orow.direct && h->orow.dinst[q];
+            info->col_direct += h->ocol.direct && h->ocol.dinst[q];
+        }
+        info->row_staged_nnz = h->orow.direct ? h->orow.dnnz : info->row_staged_nnz;
+        info->col_staged_nnz = h->ocol.direct ? h->ocol.dnnz : info->col_staged_nnz;
         return 0;
     });
 }
@@ -1307,16 +1463,20 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
 {
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
-        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || (B >= -3 && B <= -1); };
+        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == -6 || (B >= -3 && B <= -1); };
         auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16 || e == -8 || e == -16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8, 16, -8 or -16");
+            throw_err(-EINVAL, "blocks must be -6, -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8, 16, -8 or -16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;
             int32_t B = d == 0 ? row_blocks : col_blocks, ept = d == 0 ? row_ept : col_ept;
             if (o.rows == 0 && B > 0) B = 0;
-            if (B < 0) {
+            if (B == -6) {
+                set_direct(h, o, ept, 32768, 1);
+                drop_blocked(o);
+                release_sliced(o);
+            } else if (B < 0) {
                 set_staged(h, o, ept, 32768, 0, B <= -2 ? 1 : 0, B == -3 ? 1 : 0);
                 drop_blocked(o);
             } else {
@@ -1347,47 +1507,6 @@ int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, doub
             *ms_col = t.time(h->ocol, reps);
         }
         HIPC(hipStreamSynchronize(h->stream));
-        return 0;
-    });
-}
-
-int scylla_probe_gather(int64_t vec_bytes, int64_t gathers, double *ms)
-{
-    return guarded([&]() {
-        if (!ms || vec_bytes < 4 || vec_bytes > ((int64_t)1 << 30) || gathers < 1 || gathers > ((int64_t)1 << 31))
-            throw_err(-EINVAL, "bad argument");
-        check_device();
-        const uint32_t len = (uint32_t)(vec_bytes / 4);
-        DevMem idx, vec, out;
-        idx.alloc((size_t)gathers * 4);
-        vec.alloc((size_t)len * 4);
-        out.alloc((size_t)((gathers + 2047) / 2048) * 256 * 4);
-        hipStream_t s = nullptr;
-        HIPC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        std::unique_ptr<std::remove_pointer<hipStream_t>::type, void (*)(hipStream_t)> sg(
-            s, [](hipStream_t x) { (void)hipStreamDestroy(x); });
-        hipEvent_t e0, e1;
-        HIPC(hipEventCreate(&e0));
-        HIPC(hipEventCreate(&e1));
-        launch_probe_init(idx.as<uint32_t>(), gathers, len, vec.as<float>(), s);
-        // the fastest of 8, 16 and 32 gathers per thread (more work per
-        // workgroup amortises its start, so the rate depends on it)
-        double best = 1e30;
-        for (int k : {8, 16, 32}) {
-            launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, k, s);
-            HIPC(hipEventRecord(e0, s));
-            for (int r = 0; r < 10; ++r)
-                launch_probe_gather(idx.as<uint32_t>(), vec.as<float>(), out.as<float>(), gathers, k, s);
-            HIPC(hipEventRecord(e1, s));
-            HIPC(hipEventSynchronize(e1));
-            HIPC(hipGetLastError());
-            float t = 0;
-            HIPC(hipEventElapsedTime(&t, e0, e1));
-            best = std::min(best, (double)t / 10.0);
-        }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        *ms = best;
         return 0;
     });
 }

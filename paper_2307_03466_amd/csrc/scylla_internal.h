@@ -172,6 +172,15 @@ void plan_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &i
                  const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
                  int32_t max_slices, int32_t sub_chunk, int32_t group_nnz, SlicedPlan &plan);
 
+// Direct staged tiles: every instance with rows and a gathered vector of at
+// most max_vec elements (direct[q] = 1) has its rows cut into runs of whole
+// rows with about group_nnz nonzeros, tiles {r0, r1, q, L}: L lanes per row,
+// the smallest power of two >= lanes_min (at most 64) for which the tile's
+// longest row takes at most four rounds of per_lane nonzeros per lane.
+void plan_direct(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
+                 const std::vector<int32_t> &gofs, int32_t max_vec, int32_t group_nnz, int32_t lanes_min,
+                 int32_t per_lane, std::vector<uint8_t> &direct, std::vector<int32_t> &tiles);
+
 void build_blocked(const HostOrient &o, int32_t fmt, int32_t gather_size, int32_t B, BlockedHost &out);
 void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t> &inst_off, int32_t chunk,
                   int32_t max_rows, BlockedPlan &plan);

@@ -27,9 +27,10 @@ EXPORTS = [
     "scylla_batch_set_blend", "scylla_batch_set_start", "scylla_batch_solve",
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
-    "scylla_fix_propagate", "scylla_batch_pump", "scylla_probe_gather",
+    "scylla_fix_propagate", "scylla_batch_pump",
     "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
     "scylla_batch_mip_feasible", "scylla_batch_fix_propagate", "scylla_batch_mip_feasible_static",
+    "scylla_batch_set_start_device",
 ]
 
 
@@ -84,7 +85,8 @@ class BatchInfo(ctypes.Structure):
                 ("col_staged_variant", ctypes.c_int32), ("row_sliced", ctypes.c_int32),
                 ("col_sliced", ctypes.c_int32), ("row_slices", ctypes.c_int32), ("col_slices", ctypes.c_int32),
                 ("row_half_lds", ctypes.c_int32), ("col_half_lds", ctypes.c_int32),
-                ("row_tile_threads", ctypes.c_int32), ("col_tile_threads", ctypes.c_int32)]
+                ("row_tile_threads", ctypes.c_int32), ("col_tile_threads", ctypes.c_int32),
+                ("row_direct", ctypes.c_int32), ("col_direct", ctypes.c_int32)]
 
 
 _lib = None
@@ -110,6 +112,7 @@ def lib():
             "scylla_batch_set_blend": ([vp, i32, vp, vp, dbl, dbl], ctypes.c_int),
             "scylla_batch_set_quadratic": ([vp, i32, vp], ctypes.c_int),
             "scylla_batch_set_start": ([vp, i32, vp, vp, dbl], ctypes.c_int),
+            "scylla_batch_set_start_device": ([vp, vp, vp, vp], ctypes.c_int),
             "scylla_batch_solve": ([vp, ctypes.POINTER(Params), i32, ctypes.POINTER(Result)], ctypes.c_int),
             "scylla_batch_get_solution": ([vp, i32, vp, vp], ctypes.c_int),
             "scylla_batch_get_x_all": ([vp, vp], ctypes.c_int),
@@ -118,7 +121,6 @@ def lib():
             "scylla_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
             "scylla_batch_time_passes": ([vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
             "scylla_batch_set_layout": ([vp, i32, i32, i32, i32], ctypes.c_int),
-            "scylla_probe_gather": ([ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(dbl)], ctypes.c_int),
             "scylla_fix_propagate": ([ctypes.POINTER(LPDesc), vp, vp, vp, vp], ctypes.c_int),
             "scylla_batch_pump": ([vp, ctypes.POINTER(Params), vp, i32, dbl, i32, ctypes.POINTER(PumpRecord), vp],
                                   ctypes.c_int),
@@ -232,14 +234,6 @@ def fix_propagate(lp, x_ref, is_int=None):
     return xh, bool(info[0]), int(info[1])
 
 
-def probe_gather(vec_bytes: int, gathers: int) -> float:
-    """Average ms of one launch of `gathers` random 4-byte gathers from a
-    vector of `vec_bytes` bytes (the passes' ceiling)."""
-    ms = ctypes.c_double()
-    _check(lib().scylla_probe_gather(int(vec_bytes), int(gathers), ctypes.byref(ms)))
-    return ms.value
-
-
 @dataclass
 class Solution:
     x: np.ndarray
@@ -335,6 +329,12 @@ class Batch:
         y = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
         _check(lib().scylla_batch_set_start(self._h, inst, _ptr(x), _ptr(y), omega0))
 
+    def set_start_device(self, x0_ptr: int | None, y0_ptr: int | None, omega0=None) -> None:
+        """Warm start of every instance from device FP64 buffers (raw device
+        pointers to the concatenated x0 [n_total] / y0 [m_total], or None)."""
+        om = None if omega0 is None else np.ascontiguousarray(omega0, dtype=np.float64)
+        _check(lib().scylla_batch_set_start_device(self._h, x0_ptr, y0_ptr, _ptr(om)))
+
     def pump(self, rounds: int = 20, alpha: float = 0.9, is_int=None, threads: int = 0, **kw):
         """Native pump loop; returns (records [rounds][count] as dicts, x_hat_all)."""
         p = params(precision=self.precision, **kw)
@@ -395,7 +395,8 @@ class Batch:
         return out, [outs[q].as_dict() for q in range(self.count)], xo
 
     def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
-        """Pin the tile plan (-3 as -2 in half the LDS, -2 LDS-staged + sliced, -1 LDS-staged, 0 normal,
+        """Pin the tile plan (-6 direct staged, -3 as -2 in half the LDS, -2 LDS-staged + sliced,
+        -1 LDS-staged, 0 normal,
         2 / 4 / 8 gather blocks;
         4 / 8 / 16 nonzeros per thread)."""
         _check(lib().scylla_batch_set_layout(self._h, row_blocks, row_ept, col_blocks, col_ept))

@@ -3,7 +3,8 @@
 // (and, when asked, build_blocked / plan_blocked with B blocks and
 // plan_staged), and writes the results back as raw arrays for the Python
 // checks.  Usage: in out chunk max_rows [B [max_vec sub_chunk group_nnz
-// [max_slices]]].
+// [max_slices]]]; with B < 0: in out chunk max_rows B
+// max_vec group_nnz lanes_min (direct staged tiles).
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -78,6 +79,19 @@ int main(int argc, char **argv)
         wr(o, p->tiles); wr(o, p->longs); wr(o, p->t_begin); wr(o, p->t_end); wr(o, p->l_begin); wr(o, p->l_end);
     }
     const int32_t B = argc > 5 ? atoi(argv[5]) : 0;
+    if (B < 0 && argc > 8) {  // direct staged tiles: max_vec group_nnz lanes_min
+        for (int d = 0; d < 2; ++d) {
+            const scy::HostOrient &x = d == 0 ? csr : csc;
+            const std::vector<int32_t> &off = d == 0 ? ro : co, &gof = d == 0 ? co : ro;
+            std::vector<uint8_t> dir;
+            std::vector<int32_t> tiles;
+            scy::plan_direct(x.ptr, off, gof, atoi(argv[6]), atoi(argv[7]), atoi(argv[8]), 8, dir, tiles);
+            std::vector<int32_t> di(dir.begin(), dir.end());
+            wr(o, di); wr(o, tiles);
+        }
+        fclose(o);
+        return 0;
+    }
     if (B > 0) {
         for (int d = 0; d < 2; ++d) {
             const scy::HostOrient &x = d == 0 ? csr : csc;

@@ -186,6 +186,9 @@ def _run_prep(lps, precision, chunk, max_rows, extra=(), sanitize=False):
     plans = [dict(tiles=take(np.int32).reshape(-1, 4), longs=take(np.int32).reshape(-1, 4),
                   tb=take(np.int32), te=take(np.int32), lb=take(np.int32), le=take(np.int32)) for _ in range(2)]
     more = []
+    if len(extra) >= 1 and int(extra[0]) < 0:
+        more.append([dict(direct=take(np.int32), tiles=take(np.int32).reshape(-1, 4)) for _ in range(2)])
+        return (hdr, ro, co, orient, plans) + tuple(more)
     if len(extra) >= 1 and int(extra[0]) > 0:
         more.append([dict(bounds=take(np.int32), bptr=take(np.int32), ent=take(np.uint32), v16=take(np.uint16),
                           v32=take(np.float32), v64=take(np.float64), tiles=take(np.int32).reshape(-1, 4),
@@ -486,3 +489,39 @@ def test_lds_sliced_plan():
         rows_w = np.concatenate([np.arange(off[q], off[q + 1]) for q in np.flatnonzero(want)])
         assert np.all(cov[rows_w] == 1) and cov.sum() == rows_w.size
     assert seen >= 1
+
+
+@pytest.mark.parametrize("lanes_min,group", [(1, 16384), (4, 3000)])
+def test_direct_staged_tiles(lanes_min, group):
+    """Direct staged tiles: instances with rows whose gathered vector has at
+    most max_vec elements qualify; their rows are covered once, in order, by
+    runs of whole rows of one instance with about group_nnz nonzeros; the
+    lanes per row are the smallest power of two >= lanes_min (at most 64)
+    with which the longest row of the tile takes at most four rounds of 8
+    nonzeros per lane."""
+    lps = I.uneven_batch(count=10, lo=200, hi=9000, seed=5) + [I.workload(3, scale=0.002)]
+    max_vec = 4000
+    hdr, ro, co, orient, plans, dr = _run_prep(lps, 1, 1024, 1024, extra=(-6, max_vec, group, lanes_min))
+    for which in (0, 1):
+        ptr = orient[which]["ptr"]
+        off, gof = (ro, co) if which == 0 else (co, ro)
+        want = np.array([np.diff(gof)[q] <= max_vec and off[q + 1] > off[q] for q in range(len(lps))])
+        np.testing.assert_array_equal(dr[which]["direct"].astype(bool), want)
+        assert want.any() and not want.all()
+        cover = np.zeros(ptr.size - 1, dtype=np.int64)
+        last = {}
+        for r0, r1, q, L in dr[which]["tiles"]:
+            assert want[q] and off[q] <= r0 < r1 <= off[q + 1]
+            assert last.get(q, off[q]) == r0
+            last[q] = r1
+            lens = np.diff(ptr[r0:r1 + 1])
+            assert lens[:-1].sum() < group
+            Lw = max(1, lanes_min)
+            while Lw < 64 and lens.max() > 32 * Lw:
+                Lw *= 2
+            assert L == Lw
+            cover[r0:r1] += 1
+        for q in np.flatnonzero(want):
+            assert last[q] == off[q + 1]
+            assert np.all(cover[off[q]:off[q + 1]] == 1)
+        assert cover.sum() == sum(off[q + 1] - off[q] for q in np.flatnonzero(want))

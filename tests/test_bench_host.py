@@ -16,22 +16,64 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.returncode == 2 and "one GPU" in r.stderr
 
 
+def _lp(rows, n):
+    """LP from a list of rows [(column, value), ...] (other fields unused)."""
+    import numpy as np
+    ptr = np.cumsum([0] + [len(r) for r in rows]).astype(np.int64)
+    cols = np.array([c for r in rows for c, _ in r], np.int32)
+    vals = np.array([v for r in rows for _, v in r], np.float64)
+    m = len(rows)
+    return I.LP(m=m, n=n, row_ptr=ptr, col_idx=cols, val=vals, c=np.zeros(n), b=np.zeros(m),
+                senses=np.full(m, ord("G"), np.uint8), l=np.zeros(n), u=np.ones(n),
+                is_int=np.zeros(n, np.uint8))
+
+
 def test_canonical_bytes_by_hand():
-    """BF16 values and int32 indices in both orientations (6 B per nonzero
-    each), the pointers, 28 B per column (x, c, l, u, D_c^2 read, x and
-    x_bar written), 17 B per row (y, b, D_r^2 read, sense, y written) and
-    one full read of each gathered vector; FP64 doubles every value."""
-    m, n, nnz = 3, 5, 7
-    assert bench.canonical_bytes(m, n, nnz) == 2 * 7 * 6 + 4 * 4 + 4 * 6 + 28 * 5 + 17 * 3 + 4 * 8
-    assert bench.canonical_bytes(m, n, nnz, True) == 2 * 7 * 12 + 4 * 4 + 4 * 6 + 56 * 5 + 33 * 3 + 8 * 8
+    """Per nonzero 4 B of index plus 0 (pattern: every value of the row is
+    +-1), 2 (BF16-exact integers up to 256) or 4 (anything else) value
+    bytes; pointers; 28 B per column (x, c, l, u, D_c^2 read, x and x_bar
+    written) and one gather of y in the column pass; 17 B per row (y, b,
+    D_r^2, sense read, y written) and one gather of x_bar in the row pass;
+    a 4-byte split offset per column when mixed row formats are cheaper
+    than one format for all rows; FP64: 12 B per nonzero, 56 / 33 B."""
+    m, n = 6, 4
+    # one BF16 row (2 nonzeros), four pattern rows (4 each), one FP32 row (2)
+    pat = [(0, 1.0), (1, -1.0), (2, 1.0), (3, 1.0)]
+    lp = _lp([[(0, 3.0), (2, -200.0)], pat, pat, pat, pat, [(0, 0.5), (3, 1.0)]], n)
+    per_row = 2 * 6 + 16 * 4 + 2 * 8
+    uniform = 20 * 8
+    assert per_row + 4 * n < uniform
+    row, col = bench.canonical_pass_bytes([lp])
+    assert row == per_row + 4 * (m + 1) + 17 * m + 4 * n
+    assert col == per_row + 4 * n + 4 * (n + 1) + 28 * n + 4 * m
+    # all BF16 but one short pattern row: one format for all rows is cheaper
+    lp2 = _lp([[(0, 3.0), (2, -20.0), (3, 7.0)], [(1, 1.0)], [(0, 5.0), (4, 2.0), (1, 9.0)]], 5)
+    m2, n2 = 3, 5
+    row, col = bench.canonical_pass_bytes([lp2])
+    assert row == 7 * 6 + 4 * (m2 + 1) + 17 * m2 + 4 * n2
+    assert col == 7 * 6 + 4 * (n2 + 1) + 28 * n2 + 4 * m2
+    # batches add up instance by instance; FP64 ignores the formats
+    r2, c2 = bench.canonical_pass_bytes([lp, lp2])
+    assert (r2, c2) == tuple(a + b for a, b in zip(bench.canonical_pass_bytes([lp]),
+                                                   bench.canonical_pass_bytes([lp2])))
+    row, col = bench.canonical_pass_bytes([lp], fp64=True)
+    assert row == 20 * 12 + 4 * (m + 1) + 33 * m + 8 * n
+    assert col == 20 * 12 + 4 * (n + 1) + 56 * n + 8 * m
+    assert bench.canonical_bytes([lp]) == sum(bench.canonical_pass_bytes([lp]))
 
 
-def test_canonical_bytes_of_the_headline_workload():
-    """The 1M x 2M LP with 10M nonzeros moves about 217 MB per FP32
-    iteration and 421 MB per FP64 iteration under the canonical model."""
-    m, n, nnz = 1_000_000, 2_000_000, 10_008_313
-    assert abs(bench.canonical_bytes(m, n, nnz) / 1e6 - 217) < 2
-    assert abs(bench.canonical_bytes(m, n, nnz, True) / 1e6 - 421) < 3
+def test_canonical_bytes_of_the_workloads():
+    """The byte model's figures for the workloads: the 1M x 2M LP moves
+    128.05 MB in the column pass, 217 MB per FP32 iteration and 421 MB per
+    FP64 iteration; the skewed LP (70 % pattern rows) about 237 MB; the pump
+    batch about 275 MB."""
+    lp = I.workload(2)
+    row, col = bench.canonical_pass_bytes([lp])
+    assert abs(col / 1e6 - 128.05) < 0.01
+    assert abs((row + col) / 1e6 - 217) < 1
+    assert abs(bench.canonical_bytes([lp], True) / 1e6 - 421) < 1
+    assert abs(bench.canonical_bytes([I.workload(3)]) / 1e6 - 237) < 3
+    assert abs(bench.canonical_bytes(I.workload(5)) / 1e6 - 275) < 2
 
 
 def test_pass_bytes_follow_the_storage_format():

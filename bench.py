@@ -319,23 +319,23 @@ def other_workloads(pdhg, instances, args, R):
     sel = set(args.workloads.split(","))
     if "1" in sel:  # tiny set cover, FP64, latency-bound; then rounding on the host
         lp = instances.workload(1)
-        r = measure(pdhg, [lp], pdhg.FP64, 50, 3, R, True, 30, passes=False)
+        r = measure(pdhg, [lp], pdhg.FP64, 50, 3, R, args.to_tol, 30, passes=False)
         s = pdhg.solve(lp, tol=1e-4, iter_limit=200_000, precision=pdhg.FP64)
         t = time.perf_counter()
         xh, feas, ign = pdhg.fix_propagate(lp, s.x)
         out["set_cover_200x500_fp64"] = dict(iter_per_s=round(r["iter_per_s"], 1),
                                              canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 2),
-                                             to_tol=r["to_tol"],
-                                             to_tol_adaptive_steps=r["to_tol_adaptive"],
+                                             to_tol=r.get("to_tol"),
+                                             to_tol_adaptive_steps=r.get("to_tol_adaptive"),
                                              rounding_s=round(time.perf_counter() - t, 6),
                                              rounding_feasible=feas, rounded_obj=float(lp.c @ xh))
-        log(f"w1: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} adaptive={r['to_tol_adaptive']} "
+        log(f"w1: {r['iter_per_s']:,.0f} iter/s to_tol={r.get('to_tol')} adaptive={r.get('to_tol_adaptive')} "
             f"rounding feasible={feas}")
     if "3" in sel:  # skewed LP, FP32 and FP64
         lp = instances.workload(3)
         rec = {}
         for prec, tag in ((pdhg.FP32, "fp32"), (pdhg.FP64, "fp64")):
-            r = measure(pdhg, [lp], prec, 20, 2, R, True, args.tol_time_limit)
+            r = measure(pdhg, [lp], prec, 20, 2, R, args.to_tol, args.tol_time_limit)
             rb, cb = r["bytes_row"], r["bytes_col"]
             rec[tag] = dict(iter_per_s=round(r["iter_per_s"], 1), ms_row=round(r["ms_row"], 4),
                             ms_col=round(r["ms_col"], 4), row_GBps=round(rb / r["ms_row"] / 1e6, 1),
@@ -343,27 +343,27 @@ def other_workloads(pdhg, instances, args, R):
                             row_canonical_GBps=round(r["canon_row"] / r["ms_row"] / 1e6, 1),
                             col_canonical_GBps=round(r["canon_col"] / r["ms_col"] / 1e6, 1),
                             canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
-                            to_tol=r["to_tol"],
-                            to_tol_adaptive_steps=r["to_tol_adaptive"],
+                            to_tol=r.get("to_tol"),
+                            to_tol_adaptive_steps=r.get("to_tol_adaptive"),
                             layout=[r["info"]["row_blocks"], r["info"]["row_chunk"], r["info"]["col_blocks"],
                                     r["info"]["col_chunk"]], long_rows=r["info"]["long_rows"])
-            log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r['to_tol']} adaptive={r['to_tol_adaptive']}")
+            log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r.get('to_tol')} adaptive={r.get('to_tol_adaptive')}")
         out["skewed_lp_500kx1M"] = rec
         del lp
     if "4" in sel:  # 256 uneven LPs in one handle; FP64 plain = one instance at a time
         lps = instances.workload(4)
-        r = measure(pdhg, lps, pdhg.FP32, 20, 2, R, True, args.tol_time_limit)
+        r = measure(pdhg, lps, pdhg.FP32, 20, 2, R, args.to_tol, args.tol_time_limit)
         rec = dict(count=len(lps), batch_iter_per_s=round(r["iter_per_s"], 1),
                    instance_iter_per_s=round(r["iter_per_s"] * len(lps), 1), ms_row=round(r["ms_row"], 4),
-                   ms_col=round(r["ms_col"], 4), to_tol_fp32_batched=r["to_tol"],
-                   to_tol_fp32_batched_adaptive_steps=r["to_tol_adaptive"], setup_seconds=round(r["setup_s"], 3),
+                   ms_col=round(r["ms_col"], 4), to_tol_fp32_batched=r.get("to_tol"),
+                   to_tol_fp32_batched_adaptive_steps=r.get("to_tol_adaptive"), setup_seconds=round(r["setup_s"], 3),
                    canonical_bytes_per_iter=r["canon_iter"],
                    canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
                    row_canonical_GBps=round(r["canon_row"] / r["ms_row"] / 1e6, 1),
                    col_canonical_GBps=round(r["canon_col"] / r["ms_col"] / 1e6, 1))
-        log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r['to_tol']} "
-            f"adaptive={r['to_tol_adaptive']}")
-        if args.fp64_plain_batch:
+        log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r.get('to_tol')} "
+            f"adaptive={r.get('to_tol_adaptive')}")
+        if args.fp64_plain_batch and args.to_tol:
             # the plain FP64 path, one instance at a time through the one-shot
             # call: its solve_seconds (iterations only) summed, and its
             # setup_seconds (upload, CSC copy, preconditioning, graph) apart

@@ -50,9 +50,9 @@ CASES = ["cover200", "general_small", "skewed_small", "skewed_longrows", "knapsa
 # move allowed it, so the PDHG map stops being nonexpansive: the oracle's
 # own iterate moves by 1e-9..5e-7 after 100 adaptive iterations when c is
 # perturbed by 1e-15, and by 2e-2 when c and b are perturbed by FP32 storage
-# rounding (test_oracle_pdhg.py pins this).  No FP32 implementation can
+# rounding (test_oracle_steps.py pins this).  No FP32 implementation can
 # therefore match the oracle to 1e-4 after 100 adaptive iterations; the
-# horizons below are where the benchmark spec's bars are attainable with margin
+# horizons below are where the 1e-10 / 1e-4 bars are attainable with margin
 # (measured spread of the oracle itself under FP32 rounding of c and b:
 # <= 4e-7 in norm and <= 1.2e-5 per entry after 10 iterations).  The FP64
 # path differs from the oracle only in summation order (it forms A x_bar as

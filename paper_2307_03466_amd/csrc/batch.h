@@ -19,6 +19,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -171,6 +172,8 @@ struct scylla_batch {
     DevMem c64, corig64, l64, u64, b64, dr64, dc64;
     DevMem st, info;
     DevMem ax;              // running A x of the row pass (adaptive steps)
+    DevMem ibnd;            // [2 * count] (l, u) shared by all columns of an
+                            // instance, NaN where they differ
     DevMem start_flag;      // validation flag of a device warm start
     DevMem q64, qv;         // diagonal Hessian (QP objectives), once set
     DevMem xp, yp, axp, atyp;  // previous check's point and products

@@ -346,6 +346,31 @@ void plan_blocked(const BlockedHost &bh, int32_t rows, const std::vector<int32_t
     }
 }
 
+// Cuts the sub-tiles [t0, t1) of one instance (nz(t) nonzeros each) into
+// k = ceil(total / group_nnz) runs of about total / k nonzeros and appends
+// their boundaries t0 < c1 < ... < t1 to cuts: the tiles of a pass run at
+// the same time, so the longest one sets its duration, and runs of exactly
+// group_nnz would leave a short last tile per instance.
+template <class NZ>
+static void balanced_runs(int32_t t0, int32_t t1, int64_t group_nnz, NZ nz, std::vector<int32_t> &cuts)
+{
+    cuts.assign(1, t0);
+    int64_t total = 0;
+    for (int32_t t = t0; t < t1; ++t) total += nz(t);
+    const int64_t k = std::max<int64_t>(1, (total + group_nnz - 1) / std::max<int64_t>(group_nnz, 1));
+    int64_t acc = 0, j = 1;
+    for (int32_t t = t0; t < t1; ++t) {
+        acc += nz(t);
+        bool cut = false;
+        while (j < k && acc * k >= j * total) {
+            ++j;
+            cut = true;
+        }
+        if (cut && t + 1 < t1) cuts.push_back(t + 1);
+    }
+    cuts.push_back(t1);
+}
+
 void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &inst_off,
                  const std::vector<int32_t> &gofs, int32_t max_vec, int32_t sub_chunk, int32_t group_nnz,
                  int32_t rest_chunk, StagedPlan &plan)
@@ -367,19 +392,14 @@ void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &in
         plan.max_vec = std::max(plan.max_vec, glen);
     }
     plan_tiles(ptr, inst_off, sub_chunk, 4 * 1024, plan.sub, not_staged.data());
+    std::vector<int32_t> cuts;
     for (int32_t q = 0; q < count; ++q) {
-        if (!plan.staged[q]) continue;
-        int32_t t = plan.sub.t_begin[q];
-        while (t < plan.sub.t_end[q]) {
-            const int32_t start = t;
-            int64_t nz = 0;
-            while (t < plan.sub.t_end[q] && nz < group_nnz) {
-                const int32_t *d = plan.sub.tiles.data() + 4 * t;
-                nz += ptr[d[1]] - ptr[d[0]];
-                ++t;
-            }
-            plan.tiles.insert(plan.tiles.end(), {start, t, q, -1});
-        }
+        if (!plan.staged[q] || plan.sub.t_end[q] == plan.sub.t_begin[q]) continue;
+        balanced_runs(plan.sub.t_begin[q], plan.sub.t_end[q], group_nnz, [&](int32_t t) {
+            const int32_t *d = plan.sub.tiles.data() + 4 * t;
+            return (int64_t)(ptr[d[1]] - ptr[d[0]]);
+        }, cuts);
+        for (size_t c = 0; c + 1 < cuts.size(); ++c) plan.tiles.insert(plan.tiles.end(), {cuts[c], cuts[c + 1], q, -1});
     }
     plan_tiles(ptr, inst_off, rest_chunk, 1024, plan.rest, plan.staged.data());
 }
@@ -481,19 +501,15 @@ void tile_sliced(const std::vector<int32_t> &inst_off, int32_t rows, int32_t sub
         plan_tiles(ptr, inst_off, sub_chunk, 4 * 1024, tp, skip.data());
         const int32_t sub0 = (int32_t)(plan.sub.size() / 4);
         plan.sub.insert(plan.sub.end(), tp.tiles.begin(), tp.tiles.end());
+        std::vector<int32_t> cuts;
         for (int32_t q = 0; q < count; ++q) {
-            if (!ok[q]) continue;
-            int32_t t = tp.t_begin[q];
-            while (t < tp.t_end[q]) {
-                const int32_t start = t;
-                int64_t nz = 0;
-                while (t < tp.t_end[q] && nz < group_nnz) {
-                    const int32_t *d = tp.tiles.data() + 4 * t;
-                    nz += ptr[d[1]] - ptr[d[0]];
-                    ++t;
-                }
-                plan.tiles.insert(plan.tiles.end(), {sub0 + start, sub0 + t, q | (s << 24), -2});
-            }
+            if (!ok[q] || tp.t_end[q] == tp.t_begin[q]) continue;
+            balanced_runs(tp.t_begin[q], tp.t_end[q], group_nnz, [&](int32_t t) {
+                const int32_t *d = tp.tiles.data() + 4 * t;
+                return (int64_t)(ptr[d[1]] - ptr[d[0]]);
+            }, cuts);
+            for (size_t c = 0; c + 1 < cuts.size(); ++c)
+                plan.tiles.insert(plan.tiles.end(), {sub0 + cuts[c], sub0 + cuts[c + 1], q | (s << 24), -2});
         }
     }
     for (int32_t q = 0; q < count; ++q) {

@@ -35,6 +35,8 @@ struct PassArgs {
     const V *rhs;         // b (row) / c_hat (column)
     const V *diag2;       // D_r^2 / D_c^2
     const V *lo, *hi;     // l, u (column)
+    const V *ibnd;        // [2 * count] (l, u) shared by every column of an
+                          // instance, NaN where they differ (column pass)
     const uint8_t *sense; // row senses
     InstState *st;
     V *seg;               // long-row segment partials

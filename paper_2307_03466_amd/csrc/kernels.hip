@@ -169,15 +169,40 @@ struct RowOps {
     uint8_t sense;
 };
 
+// Bounds shared by every column of an instance (binary problems, say): the
+// column pass reads them once per workgroup instead of twice per column.
+template <class V>
+struct InstBounds {
+    bool uni;
+    V lo, hi;
+};
+
 template <class V, int DIR>
-__device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> &o)
+__device__ __forceinline__ InstBounds<V> inst_bounds(const PassArgs<V> &p, int inst)
+{
+    InstBounds<V> b{false, (V)0, (V)0};
+    if (DIR == DIR_COL && p.ibnd) {
+        b.lo = p.ibnd[2 * inst];
+        b.hi = p.ibnd[2 * inst + 1];
+        b.uni = b.lo == b.lo;
+    }
+    return b;
+}
+
+template <class V, int DIR>
+__device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> &o, const InstBounds<V> &ib)
 {
     o.own = p.own[i];
     o.rhs = p.rhs[i];
     o.diag2 = p.diag2[i];
     if (DIR == DIR_COL) {
-        o.lo = p.lo[i];
-        o.hi = p.hi[i];
+        if (ib.uni) {
+            o.lo = ib.lo;
+            o.hi = ib.hi;
+        } else {
+            o.lo = p.lo[i];
+            o.hi = p.hi[i];
+        }
         if (p.q) o.q = p.q[i];
     } else {
         o.sense = p.sense[i];
@@ -249,6 +274,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
     const int tid = threadIdx.x;
+    const InstBounds<V> ib = inst_bounds<V, DIR>(p, T.z);
     if (T.w >= 0) {  // one segment of a long row: partial sum only
         stage_products<V, V, FMT, NT, EPT>(p.M, p.gvec, T.x, T.y, prod);
         __syncthreads();
@@ -273,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
     if (r < nrows) {
         rb = p.M.ptr[r0 + r] - e0;
         re = p.M.ptr[r0 + r + 1] - e0;
-        if (lane == 0) load_ops<V, DIR>(p, r0 + r, ops);
+        if (lane == 0) load_ops<V, DIR>(p, r0 + r, ops, ib);
     }
     stage_products<V, V, FMT, NT, EPT>(p.M, p.gvec, e0, e1, prod);
     __syncthreads();
@@ -286,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
         if (rn < nrows) {
             rb = p.M.ptr[r0 + rn] - e0;
             re = p.M.ptr[r0 + rn + 1] - e0;
-            if (lane == 0) load_ops<V, DIR>(p, r0 + rn, ops);
+            if (lane == 0) load_ops<V, DIR>(p, r0 + rn, ops, ib);
         }
     }
     if (p.adapt) {
@@ -379,11 +405,12 @@ __global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int
     const InstState &S = p.st[T.z];
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const int i = T.x + threadIdx.x;
+    const InstBounds<V> ib = inst_bounds<V, DIR>(p, T.z);
     double ip[2] = {0.0, 0.0};
     if (i < T.y) {
         const bool copy_ref = (jw == 0) && (S.restart_now != 0);
         RowOps<V> ops;
-        load_ops<V, DIR>(p, i, ops);
+        load_ops<V, DIR>(p, i, ops, ib);
         V s = 0;
         for (int b = 0; b < p.B; ++b) s += p.P[(size_t)b * p.rows + i];
         apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
@@ -464,6 +491,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
     const int tid = threadIdx.x;
+    const InstBounds<V> ib = inst_bounds<V, DIR>(p, inst);
     MatView M = p.M;
     const int4 *sub = p.sub;
     int g0 = p.gofs[inst], glen = p.gofs[inst + 1] - g0;
@@ -504,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
         if (r < D.y - D.x) {
             rb = M.ptr[D.x + r] - e0;
             re = M.ptr[D.x + r + 1] - e0;
-            if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
+            if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops, ib);
         }
     }
     copy_to_lds<NT, 64 / sizeof(V)>(sv, p.gvec + g0, glen);
@@ -535,7 +563,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             if (rc < nrows) {
                 rbc = M.ptr[r0c + rc] - e0c;
                 rec = M.ptr[r0c + rc + 1] - e0c;
-                if (!part && (tid & (Lc - 1)) == 0) load_ops<V, DIR>(p, r0c + rc, opc);
+                if (!part && (tid & (Lc - 1)) == 0) load_ops<V, DIR>(p, r0c + rc, opc, ib);
             }
         }
         lds_barrier();
@@ -560,7 +588,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
                 if (r < D.y - D.x) {
                     rb = M.ptr[D.x + r] - e0;
                     re = M.ptr[D.x + r + 1] - e0;
-                    if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops);
+                    if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops, ib);
                 }
             }
         }
@@ -577,7 +605,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             if (rn < nrows) {
                 rbc = M.ptr[r0c + rn] - e0c;
                 rec = M.ptr[r0c + rn + 1] - e0c;
-                if (!part && lane == 0) load_ops<V, DIR>(p, r0c + rn, opc);
+                if (!part && lane == 0) load_ops<V, DIR>(p, r0c + rn, opc, ib);
             }
         }
         lds_barrier();
@@ -641,6 +669,7 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    const InstBounds<V> ib = inst_bounds<V, DIR>(p, T.z);
     const int tid = threadIdx.x, L = T.w, lane = tid & (L - 1), groups = NT / L;
     const int g0 = p.gofs[T.z], glen = p.gofs[T.z + 1] - g0;
     // bounds of this lane group's first DPASS_R rows, then the vector copy
@@ -681,7 +710,7 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < DPASS_R; ++u)
-                if (base + u * groups < T.y) load_ops<V, DIR>(p, base + u * groups, ops[u]);
+                if (base + u * groups < T.y) load_ops<V, DIR>(p, base + u * groups, ops[u], ib);
         }
         // bounds of the next rows load meanwhile
 #pragma unroll
@@ -730,10 +759,11 @@ __global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int 
     const InstState &S = p.st[L.w];
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
+    const InstBounds<V> ib = inst_bounds<V, DIR>(p, L.w);
     V s = 0;
     for (int k = 0; k < L.z; ++k) s += p.seg[L.y + k];
     RowOps<V> ops;
-    load_ops<V, DIR>(p, L.x, ops);
+    load_ops<V, DIR>(p, L.x, ops, ib);
     double ip[2] = {0.0, 0.0};
     apply_ops<V, DIR>(p, L.x, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
     if (p.adapt) {

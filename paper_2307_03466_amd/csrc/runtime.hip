@@ -81,6 +81,7 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
         p.diag2 = h->dc2.as<V>();
         p.lo = h->lv.as<V>();
         p.hi = h->uv.as<V>();
+        p.ibnd = h->ibnd.as<V>();
         p.rhs64 = h->c64.as<double>();
         p.lo64 = h->l64.as<double>();
         p.hi64 = h->u64.as<double>();
@@ -770,7 +771,7 @@ void autotune(scylla_batch *h)
             for (int half = 0; half < 2; ++half)
                 for (int slice = 0; slice < (any_slice || half ? 2 : 1); ++slice)
                     for (int var = 0; var < 4; ++var)
-                        for (int nnz : {16384, 32768, 65536}) {
+                        for (int nnz : {16384, 32768, 65536, 131072}) {
                             const double tp = now_s();
                             set_staged(h, o, best_ept, nnz, var, slice, half);
                             const double tt = now_s();
@@ -893,6 +894,21 @@ void setup_device(scylla_batch *h, const scylla_lp *lps, HostOrient &csr, HostOr
     launch_cast<V>(h->l64.as<double>(), h->lv.as<V>(), N, s);
     launch_cast<V>(h->u64.as<double>(), h->uv.as<V>(), N, s);
     launch_cast<V>(h->b64.as<double>(), h->b_v.as<V>(), M, s);
+    // bounds shared by every column of an instance (binary problems): the
+    // column pass then reads them once per workgroup, not per column
+    {
+        std::vector<V> ib(2 * (size_t)h->count, std::numeric_limits<V>::quiet_NaN());
+        for (int32_t q = 0; q < h->count; ++q) {
+            const int32_t j0 = h->col_off[q], j1 = h->col_off[q + 1];
+            bool uni = j1 > j0;
+            for (int32_t j = j0 + 1; j < j1 && uni; ++j) uni = l[j] == l[j0] && u[j] == u[j0];
+            if (uni) {
+                ib[2 * q] = (V)l[j0];
+                ib[2 * q + 1] = (V)u[j0];
+            }
+        }
+        upload(h->ibnd, ib, s);
+    }
     // preconditioner: 10 Ruiz rounds (infinity norm) + one Pock-Chambolle
     // round (alpha = 1), FP64; A itself stays unscaled
     std::vector<double> ones_m(M, 1.0), ones_n(N, 1.0);

@@ -121,8 +121,9 @@ struct BlockedPlan {
 
 // Plan of an LDS-staged orientation.  Instances whose gathered vector has at
 // most max_vec elements and no row longer than sub_chunk get sub-tiles
-// (whole rows, <= sub_chunk nonzeros) grouped into staged tiles of about
-// group_nnz nonzeros; the other instances get normal tiles (rest).
+// (whole rows, <= sub_chunk nonzeros) grouped into ceil(nnz / group_nnz)
+// staged tiles per instance of about equal nonzero counts; the other
+// instances get normal tiles (rest).
 struct StagedPlan {
     std::vector<int32_t> tiles;   // {sub0, sub1, inst, -1}
     TilePlan sub;                 // sub-tiles of the staged instances
@@ -142,8 +143,9 @@ void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &in
 // slices [g0 + glen*s/S, g0 + glen*(s+1)/S); each row's nonzeros are
 // regrouped by slice (bptr[s * (rows + 1) + i] points into ent; rows of
 // other instances are empty).  Sub-tiles of a slice's rows (<= sub_chunk
-// nonzeros, <= 4096 rows) are grouped into tiles of about group_nnz
-// nonzeros {sub0, sub1, inst | s << 24, -2}; the slice partial sums of a row
+// nonzeros, <= 4096 rows) are grouped into ceil(nnz / group_nnz) tiles of
+// about equal nonzero counts per (instance, slice)
+// {sub0, sub1, inst | s << 24, -2}; the slice partial sums of a row
 // are added in slice order by the combine tiles {r0, r1, inst, -1}.
 struct SlicedPlan {
     int32_t S = 0;                // slices per sliced instance (0: none)

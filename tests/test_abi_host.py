@@ -415,16 +415,21 @@ def test_lds_staged_plan():
         _check_cover(ptr, sp["sub"], sp["sublongs"], staged_rows, chunk=sub_chunk, max_rows=4096)
         assert sp["sublongs"].size == 0
         _check_cover(ptr, sp["rest"], sp["restlongs"], rest_rows, chunk=chunk)
-        # staged tiles: consecutive sub-tile ranges of one instance, in order
-        nxt = {}
+        # staged tiles: consecutive sub-tile ranges of one instance, in order,
+        # ceil(nnz / group) of them per instance with about equal counts
+        nxt, per = {}, {}
         for s0, s1, q, _ in sp["tiles"]:
             assert sp["staged"][q] and s1 > s0
             assert nxt.get(q, s0) == s0
             nxt[q] = s1
             subs = sp["sub"][s0:s1]
             assert np.all(subs[:, 2] == q)
-            nz = [ptr[b] - ptr[a] for a, b, _, _ in subs]
-            assert sum(nz[:-1]) < group <= sum(nz) + group
+            per.setdefault(q, []).append(sum(ptr[b] - ptr[a] for a, b, _, _ in subs))
+        for q, nzs in per.items():
+            total = ptr[off[q + 1]] - ptr[off[q]]
+            k = max(1, -(-total // group))
+            assert len(nzs) == k and sum(nzs) == total, (q, nzs)
+            assert max(nzs) <= total / k + sub_chunk and min(nzs) >= total / k - sub_chunk, (q, nzs)
 
 
 def test_lds_sliced_plan():
@@ -460,13 +465,23 @@ def test_lds_sliced_plan():
         xidx = _decode_idx(x["ent"], hdr, which, hdr[0])
         bptr = x["bptr"].reshape(S, rows + 1)
         cover = [np.zeros(rows, dtype=np.int64) for _ in range(S)]
+        per = {}
         for s0, s1, z, kind in x["tiles"]:
             q, s = z & 0xFFFFFF, z >> 24
             assert kind == -2 and want[q] and s < S
+            nz = 0
             for a, b, qq, _ in x["sub"][s0:s1]:
                 assert qq == q and off[q] <= a <= b <= off[q + 1]
                 assert bptr[s, b] - bptr[s, a] <= sub_chunk and b - a <= 4096
                 cover[s][a:b] += 1
+                nz += bptr[s, b] - bptr[s, a]
+            per.setdefault((q, s), []).append(nz)
+        # ceil(nnz / group) tiles of about equal counts per (instance, slice)
+        for (q, s), nzs in per.items():
+            total = bptr[s, off[q + 1]] - bptr[s, off[q]]
+            k = max(1, -(-total // group))
+            assert len(nzs) == k and sum(nzs) == total
+            assert max(nzs) <= total / k + sub_chunk and min(nzs) >= total / k - sub_chunk
         for q in np.flatnonzero(want):
             r = np.arange(off[q], off[q + 1])
             lo = [gof[q] + (glen[q] * s) // S for s in range(S + 1)]

@@ -512,3 +512,36 @@ def test_fp32_stall_point_restated(name, st):
             first = c
             break
     assert first == nchk, (first, nchk)
+
+
+def _uniform_bound_batch():
+    """Instances whose columns share one pair of bounds ([0, 1], [-2, 3],
+    free, [0, inf)) next to ones whose bounds differ in a single column."""
+    import dataclasses
+    out = []
+    for k, (lo, hi) in enumerate([(0.0, 1.0), (-2.0, 3.0), (-np.inf, np.inf), (0.0, np.inf), (0.0, 1.0)]):
+        lp = I.cover_knapsack(700 + 150 * k, seed=40 + k)
+        l, u = np.full(lp.n, lo), np.full(lp.n, hi)
+        if k == 4:
+            u[lp.n // 2] = 2.0  # one column differs: per-column bounds
+        out.append(dataclasses.replace(lp, l=l, u=u))
+    return out + [I.workload(2, scale=0.001)]
+
+
+@pytest.mark.parametrize("layout", [(0, 4, 0, 4), (4, 8, 2, 8), (-2, 8, -2, 8), (-6, 8, -6, 8)])
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
+def test_uniform_bounds_parity(layout, prec, bar):
+    """The column pass reads the bounds of an instance whose columns share
+    them once per workgroup; every instance, uniform or not, matches the
+    oracle after 100 iterations."""
+    lps = _uniform_bound_batch()
+    with pdhg.Batch(lps, precision=prec) as b:
+        b.set_layout(*layout)
+        res = b.solve(tol=1e-300, iter_limit=100, restarts=0, fused_window=0)
+        sols = [b.solution(i) for i in range(len(lps))]
+    for i, lp in enumerate(lps):
+        ref = oracle.pdhg(lp, tol=-1.0, iter_limit=100, restarts=False)
+        x, y = sols[i]
+        assert res[i]["iterations"] == 100
+        assert np.all(x >= lp.l) and np.all(x <= lp.u)
+        assert parity_err(x, y, ref.x, ref.y) <= bar, (layout, i)

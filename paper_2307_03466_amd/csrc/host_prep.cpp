@@ -526,26 +526,20 @@ void plan_direct(const std::vector<int32_t> &ptr, const std::vector<int32_t> &in
     const int32_t count = (int32_t)inst_off.size() - 1;
     direct.assign(count, 0);
     tiles.clear();
+    std::vector<int32_t> cuts;
     for (int32_t q = 0; q < count; ++q) {
         const int32_t r0 = inst_off[q], r1 = inst_off[q + 1];
         if (r1 == r0 || gofs[q + 1] - gofs[q] > max_vec) continue;
         direct[q] = 1;
-        int32_t r = r0;
-        while (r < r1) {
-            const int32_t start = r;
-            int64_t nz = 0;
+        balanced_runs(r0, r1, group_nnz, [&](int32_t r) { return (int64_t)(ptr[r + 1] - ptr[r]); }, cuts);
+        for (size_t c = 0; c + 1 < cuts.size(); ++c) {
             int32_t longest = 0;
-            while (r < r1 && nz < group_nnz) {
-                const int32_t len = ptr[r + 1] - ptr[r];
-                nz += len;
-                longest = std::max(longest, len);
-                ++r;
-            }
+            for (int32_t r = cuts[c]; r < cuts[c + 1]; ++r) longest = std::max(longest, ptr[r + 1] - ptr[r]);
             // lanes per row: enough that the longest row needs at most four
             // rounds of per_lane nonzeros per lane
             int32_t L = std::max(1, std::min(64, lanes_min));
             while (L < 64 && (int64_t)longest > 4LL * per_lane * L) L <<= 1;
-            tiles.insert(tiles.end(), {start, r, q, L});
+            tiles.insert(tiles.end(), {cuts[c], cuts[c + 1], q, L});
         }
     }
 }

@@ -108,6 +108,8 @@ inline int spass_chunk(int variant) { return SPASS_NT * ((variant & 2) ? 8 : 4);
 // static LDS, and the static LDS that takes (the dynamic part must leave it).
 constexpr int SPASS_DMAX = 64;
 constexpr int SPASS_STATIC_LDS = 4 * SPASS_DMAX * 4;
+// LDS beyond the vector that its 16-byte-word copy may use (alignment)
+constexpr int LDS_COPY_SLACK = 16;
 
 // Fused check window for instances that fit in LDS (k_tiny).
 template <class V>

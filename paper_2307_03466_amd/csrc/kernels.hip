@@ -440,26 +440,38 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// dst[0, n) = src[0, n) into LDS by NT threads with U loads in flight per
-// thread: a plain strided loop waits for each load before its LDS store,
-// which makes the copy one memory latency per NT elements.
+// Copies src[0, n) into LDS by NT threads in 16-byte words, U in flight per
+// thread (a plain strided loop would wait for each load before its LDS
+// store).  The copy starts at `base` (16-byte aligned LDS) shifted by the
+// source's misalignment, so that every word is aligned on both sides, and
+// the copied vector begins at the returned pointer (dst[k] = src[k], k < n;
+// base needs n values + LDS_COPY_SLACK bytes).
+// The words may start up to 12 bytes before src, inside the same buffer
+// (device buffers are 256-byte aligned); the tail is copied value by value.
 template <int NT, int U, class V>
-__device__ __forceinline__ void copy_to_lds(V *dst, const V *__restrict__ src, int n)
+__device__ __forceinline__ V *copy_to_lds_vec(V *base, const V *__restrict__ src, int n)
 {
+    constexpr int W = 16 / sizeof(V);
+    typedef V VW __attribute__((ext_vector_type(W)));
+    const int mis = (int)(((uintptr_t)src & 15) / sizeof(V));
+    const V *asrc = src - mis;
+    const int words = (mis + n) / W;
     const int tid = threadIdx.x;
-    for (int k0 = 0; k0 < n; k0 += NT * U) {
-        V t[U];
+    for (int k0 = 0; k0 < words; k0 += NT * U) {
+        VW t[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * NT + tid;
-            t[u] = k < n ? src[k] : (V)0;
+            if (k < words) t[u] = reinterpret_cast<const VW *>(asrc)[k];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * NT + tid;
-            if (k < n) dst[k] = t[u];
+            if (k < words) reinterpret_cast<VW *>(base)[k] = t[u];
         }
     }
+    for (int k = words * W + tid; k < mis + n; k += NT) base[k] = asrc[k];
+    return base + mis;
 }
 
 template <class V, int FMT, int NT, int EPT>
@@ -535,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             if (!part && (tid & (L - 1)) == 0) load_ops<V, DIR>(p, D.x + r, ops, ib);
         }
     }
-    copy_to_lds<NT, 64 / sizeof(V)>(sv, p.gvec + g0, glen);
+    sv = copy_to_lds_vec<NT, 8>(sv, p.gvec + g0, glen);
     lds_barrier();
     for (int t = T.x; t < T.y; ++t) {
         // products of sub-tile t from the registers
@@ -684,7 +696,7 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
             nb1[u] = p.M.ptr[r + 1];
         }
     }
-    copy_to_lds<NT, 64 / sizeof(V)>(sv, p.gvec + g0, glen);
+    sv = copy_to_lds_vec<NT, 8>(sv, p.gvec + g0, glen);
     lds_barrier();
     double ip[2] = {0.0, 0.0};
     for (int base = first; base < T.y; base += DPASS_R * groups) {

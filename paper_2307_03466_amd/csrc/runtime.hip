@@ -202,7 +202,8 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
     const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
     const int32_t chunk = spass_chunk(variant);
-    const int32_t max_vec = ((half ? h->lds_max / 2 : h->lds_max) - SPASS_STATIC_LDS) / h->vbytes - chunk;
+    const int32_t max_vec =
+        ((half ? h->lds_max / 2 : h->lds_max) - SPASS_STATIC_LDS - LDS_COPY_SLACK) / h->vbytes - chunk;
     plan_staged(o.host.ptr, off, gofs, max_vec, chunk, group_nnz, 256 * std::abs(ept), o.splan);
     std::vector<int32_t> tiles = o.splan.tiles;
     if (slice) {
@@ -250,7 +251,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     upload(o.rlongs, o.splan.rest.longs, h->stream);
     o.rseg.alloc(std::max<size_t>(1, o.splan.rest.nslots) * h->vbytes);
     const int32_t vec = std::max({o.splan.max_vec, o.sliced ? o.xplan.max_slice : 0, 1});
-    o.shmem = (size_t)(chunk + vec) * h->vbytes;
+    o.shmem = (size_t)(chunk + vec) * h->vbytes + LDS_COPY_SLACK;
     PassArgs<float> pf{};
     PassArgs<double> pd{};
     if (h->vbytes == 4)
@@ -274,7 +275,8 @@ void set_direct(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     set_plan(h, o, 0, ept);
     const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
     const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
-    const int32_t max_vec = (h->lds_max - 1024) / h->vbytes;  // room for the kernel's static LDS
+    // room for the kernel's static LDS and the copy's alignment slack
+    const int32_t max_vec = (h->lds_max - 1024 - LDS_COPY_SLACK) / h->vbytes;
     plan_direct(o.host.ptr, off, gofs, max_vec, group_nnz, lanes_min, DPASS_K, o.dinst, o.dtiles_h);
     upload(o.dtiles, o.dtiles_h, h->stream);
     plan_tiles(o.host.ptr, off, 256 * std::abs(ept), 1024, o.splan.rest, o.dinst.data());
@@ -285,7 +287,7 @@ void set_direct(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     int32_t vmax = 1;
     for (int32_t q = 0; q < h->count; ++q)
         if (o.dinst[q]) vmax = std::max(vmax, gofs[q + 1] - gofs[q]);
-    o.dshmem = (size_t)vmax * h->vbytes;
+    o.dshmem = (size_t)vmax * h->vbytes + LDS_COPY_SLACK;
     PassArgs<float> pf{};
     PassArgs<double> pd{};
     if (h->vbytes == 4) launch_direct<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, 0, o.dshmem, h->stream, true);

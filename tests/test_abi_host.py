@@ -510,8 +510,8 @@ def test_lds_sliced_plan():
 def test_direct_staged_tiles(lanes_min, group):
     """Direct staged tiles: instances with rows whose gathered vector has at
     most max_vec elements qualify; their rows are covered once, in order, by
-    runs of whole rows of one instance with about group_nnz nonzeros; the
-    lanes per row are the smallest power of two >= lanes_min (at most 64)
+    ceil(nnz / group_nnz) runs of whole rows per instance with about equal
+    nonzero counts; the lanes per row are the smallest power of two >= lanes_min (at most 64)
     with which the longest row of the tile takes at most four rounds of 8
     nonzeros per lane."""
     lps = I.uneven_batch(count=10, lo=200, hi=9000, seed=5) + [I.workload(3, scale=0.002)]
@@ -524,13 +524,13 @@ def test_direct_staged_tiles(lanes_min, group):
         np.testing.assert_array_equal(dr[which]["direct"].astype(bool), want)
         assert want.any() and not want.all()
         cover = np.zeros(ptr.size - 1, dtype=np.int64)
-        last = {}
+        last, per = {}, {}
         for r0, r1, q, L in dr[which]["tiles"]:
             assert want[q] and off[q] <= r0 < r1 <= off[q + 1]
             assert last.get(q, off[q]) == r0
             last[q] = r1
             lens = np.diff(ptr[r0:r1 + 1])
-            assert lens[:-1].sum() < group
+            per.setdefault(q, []).append(int(lens.sum()))
             Lw = max(1, lanes_min)
             while Lw < 64 and lens.max() > 32 * Lw:
                 Lw *= 2
@@ -539,4 +539,11 @@ def test_direct_staged_tiles(lanes_min, group):
         for q in np.flatnonzero(want):
             assert last[q] == off[q + 1]
             assert np.all(cover[off[q]:off[q + 1]] == 1)
+            total = ptr[off[q + 1]] - ptr[off[q]]
+            k = max(1, -(-total // group))
+            longest = np.diff(ptr[off[q]:off[q + 1] + 1]).max()
+            nzs = per[q]
+            assert sum(nzs) == total
+            # k runs unless a zero-length tail run was merged away
+            assert len(nzs) <= k and max(nzs) <= total / k + longest, (q, nzs, k)
         assert cover.sum() == sum(off[q + 1] - off[q] for q in np.flatnonzero(want))

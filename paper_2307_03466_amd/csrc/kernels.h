@@ -162,9 +162,9 @@ void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, 
 // dynamic LDS = the largest gathered vector); prepare = true only raises the
 // kernel's dynamic-LDS limit.
 constexpr int DPASS_NT = 1024;
-constexpr int DPASS_K = 8;  // nonzeros per lane per row in flight
 template <class V>
-void launch_direct(const PassArgs<V> &p, int fmt, int dir, int jw, size_t shmem, hipStream_t s, bool prepare);
+void launch_direct(const PassArgs<V> &p, int fmt, int dir, int k, int jw, size_t shmem, hipStream_t s,
+                   bool prepare);
 // Row combine of the LDS-sliced tiles: p.ctiles / p.nctiles / p.B / p.P set
 // to the sliced plan's combine tiles, slice count and partials.
 template <class V>

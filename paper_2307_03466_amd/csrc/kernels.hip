@@ -638,7 +638,9 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
 // it: a workgroup copies the instance's vector to LDS once, then each group
 // of L lanes reduces whole rows straight from their nonzeros (streamed from
 // global memory, gathered from LDS), DPASS_R rows at a time, combines its
-// lanes with shuffles and applies the fused epilogue.  The row bounds of
+// lanes with shuffles and applies the fused epilogue; each lane takes K
+// nonzeros of a row per round (K = 16 / L for the plan's lanes per row L,
+// between 2 and 8, so a row of up to 16 nonzeros is one round).  The row bounds of
 // the next DPASS_R rows load while the current ones are reduced, so each
 // step waits for one round trip (the nonzeros).  Without a product buffer
 // the vector may fill the LDS.  Tile {r0, r1, inst, L}; within a row each
@@ -646,13 +648,13 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
 // the result is reproducible for a given plan.
 constexpr int DPASS_R = 4;
 
-template <class V, int FMT>
+template <class V, int FMT, int K>
 __device__ __forceinline__ V direct_row_chunk(const MatView &M, const V *sv, int g0, int e, int e1, int L)
 {
-    uint32_t w[DPASS_K];
-    V a[DPASS_K];
+    uint32_t w[K];
+    V a[K];
 #pragma unroll
-    for (int k = 0; k < DPASS_K; ++k) {
+    for (int k = 0; k < K; ++k) {
         const int ee = e + k * L;
         w[k] = 0;
         a[k] = (V)0;
@@ -660,7 +662,7 @@ __device__ __forceinline__ V direct_row_chunk(const MatView &M, const V *sv, int
     }
     V s = 0;
 #pragma unroll
-    for (int k = 0; k < DPASS_K; ++k) {
+    for (int k = 0; k < K; ++k) {
         if (e + k * L < e1) {
             const int idx = decode_entry<FMT, V>(M, w[k], a[k]);
             s += a[k] * sv[idx - g0];
@@ -669,7 +671,7 @@ __device__ __forceinline__ V direct_row_chunk(const MatView &M, const V *sv, int
     return s;
 }
 
-template <class V, int FMT, int DIR, int NT>
+template <class V, int FMT, int DIR, int NT, int K>
 __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -706,13 +708,13 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
             b0[u] = nb0[u];
             b1[u] = nb1[u];
         }
-        // nonzeros of the current rows (first DPASS_K per lane of each)
-        uint32_t w[DPASS_R][DPASS_K];
-        V a[DPASS_R][DPASS_K];
+        // nonzeros of the current rows (first K per lane of each)
+        uint32_t w[DPASS_R][K];
+        V a[DPASS_R][K];
 #pragma unroll
         for (int u = 0; u < DPASS_R; ++u)
 #pragma unroll
-            for (int k = 0; k < DPASS_K; ++k) {
+            for (int k = 0; k < K; ++k) {
                 const int e = b0[u] + lane + k * L;
                 w[u][k] = 0;
                 a[u][k] = (V)0;
@@ -738,15 +740,15 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
         for (int u = 0; u < DPASS_R; ++u) {
             V sum = 0;
 #pragma unroll
-            for (int k = 0; k < DPASS_K; ++k) {
+            for (int k = 0; k < K; ++k) {
                 if (b0[u] + lane + k * L < b1[u]) {
                     const int idx = decode_entry<FMT, V>(p.M, w[u][k], a[u][k]);
                     sum += a[u][k] * sv[idx - g0];
                 }
             }
-            // rows longer than DPASS_K per lane: further rounds
-            for (int c = lane + DPASS_K * L; b0[u] + c < b1[u]; c += DPASS_K * L)
-                sum += direct_row_chunk<V, FMT>(p.M, sv, g0, b0[u] + c, b1[u], L);
+            // rows longer than K per lane: further rounds
+            for (int c = lane + K * L; b0[u] + c < b1[u]; c += K * L)
+                sum += direct_row_chunk<V, FMT, K>(p.M, sv, g0, b0[u] + c, b1[u], L);
             if (L > 1) sum = wave_sum_width(sum, L);
             const int r = base + u * groups;
             if (lane == 0 && r < T.y) apply_ops<V, DIR>(p, r, sum, step, copy_ref, ops[u], ip);
@@ -1802,10 +1804,10 @@ void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, 
     }
 }
 
-template <class V, int FMT, int DIR>
-void direct_t(const PassArgs<V> &p, int jw, size_t shmem, hipStream_t s, bool prepare)
+template <class V, int FMT, int DIR, int K>
+void direct_k(const PassArgs<V> &p, int jw, size_t shmem, hipStream_t s, bool prepare)
 {
-    auto fn = k_dpass<V, FMT, DIR, DPASS_NT>;
+    auto fn = k_dpass<V, FMT, DIR, DPASS_NT, K>;
     if (prepare) {
         (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         return;
@@ -1813,23 +1815,32 @@ void direct_t(const PassArgs<V> &p, int jw, size_t shmem, hipStream_t s, bool pr
     hipLaunchKernelGGL(fn, dim3(p.ndtiles), dim3(DPASS_NT), shmem, s, p, jw);
 }
 
+template <class V, int FMT, int DIR>
+void direct_t(const PassArgs<V> &p, int k, int jw, size_t shmem, hipStream_t s, bool prepare)
+{
+    if (k <= 2) direct_k<V, FMT, DIR, 2>(p, jw, shmem, s, prepare);
+    else if (k <= 4) direct_k<V, FMT, DIR, 4>(p, jw, shmem, s, prepare);
+    else direct_k<V, FMT, DIR, 8>(p, jw, shmem, s, prepare);
+}
+
 template <class V>
-void launch_direct(const PassArgs<V> &p, int fmt, int dir, int jw, size_t shmem, hipStream_t s, bool prepare)
+void launch_direct(const PassArgs<V> &p, int fmt, int dir, int k, int jw, size_t shmem, hipStream_t s,
+                   bool prepare)
 {
     if (!prepare && p.ndtiles <= 0) return;
     if constexpr (sizeof(V) == 8) {
-        if (dir == DIR_COL) direct_t<V, FMT_F64, DIR_COL>(p, jw, shmem, s, prepare);
-        else direct_t<V, FMT_F64, DIR_ROW>(p, jw, shmem, s, prepare);
+        if (dir == DIR_COL) direct_t<V, FMT_F64, DIR_COL>(p, k, jw, shmem, s, prepare);
+        else direct_t<V, FMT_F64, DIR_ROW>(p, k, jw, shmem, s, prepare);
     } else {
         if (fmt == FMT_PACKED) {
-            if (dir == DIR_COL) direct_t<V, FMT_PACKED, DIR_COL>(p, jw, shmem, s, prepare);
-            else direct_t<V, FMT_PACKED, DIR_ROW>(p, jw, shmem, s, prepare);
+            if (dir == DIR_COL) direct_t<V, FMT_PACKED, DIR_COL>(p, k, jw, shmem, s, prepare);
+            else direct_t<V, FMT_PACKED, DIR_ROW>(p, k, jw, shmem, s, prepare);
         } else if (fmt == FMT_BF16) {
-            if (dir == DIR_COL) direct_t<V, FMT_BF16, DIR_COL>(p, jw, shmem, s, prepare);
-            else direct_t<V, FMT_BF16, DIR_ROW>(p, jw, shmem, s, prepare);
+            if (dir == DIR_COL) direct_t<V, FMT_BF16, DIR_COL>(p, k, jw, shmem, s, prepare);
+            else direct_t<V, FMT_BF16, DIR_ROW>(p, k, jw, shmem, s, prepare);
         } else {
-            if (dir == DIR_COL) direct_t<V, FMT_F32, DIR_COL>(p, jw, shmem, s, prepare);
-            else direct_t<V, FMT_F32, DIR_ROW>(p, jw, shmem, s, prepare);
+            if (dir == DIR_COL) direct_t<V, FMT_F32, DIR_COL>(p, k, jw, shmem, s, prepare);
+            else direct_t<V, FMT_F32, DIR_ROW>(p, k, jw, shmem, s, prepare);
         }
     }
 }
@@ -1941,7 +1952,7 @@ void launch_mip_check(const MatView &M, int fmt, int m, int n, int count, const 
     template void launch_staged<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_pass<V>(const PassArgs<V> &, int, int, int, int, bool, bool, hipStream_t);    \
     template void launch_combine<V>(const PassArgs<V> &, int, int, hipStream_t);                       \
-    template void launch_direct<V>(const PassArgs<V> &, int, int, int, size_t, hipStream_t, bool);      \
+    template void launch_direct<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
     template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \
     template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \

@@ -277,7 +277,8 @@ void set_direct(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     const std::vector<int32_t> &gofs = o.row ? h->col_off : h->row_off;
     // room for the kernel's static LDS and the copy's alignment slack
     const int32_t max_vec = (h->lds_max - 1024 - LDS_COPY_SLACK) / h->vbytes;
-    plan_direct(o.host.ptr, off, gofs, max_vec, group_nnz, lanes_min, DPASS_K, o.dinst, o.dtiles_h);
+    const int32_t k = dpass_k(lanes_min);
+    plan_direct(o.host.ptr, off, gofs, max_vec, group_nnz, lanes_min, k, o.dinst, o.dtiles_h);
     upload(o.dtiles, o.dtiles_h, h->stream);
     plan_tiles(o.host.ptr, off, 256 * std::abs(ept), 1024, o.splan.rest, o.dinst.data());
     upload(o.gofs, gofs, h->stream);
@@ -290,8 +291,8 @@ void set_direct(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     o.dshmem = (size_t)vmax * h->vbytes + LDS_COPY_SLACK;
     PassArgs<float> pf{};
     PassArgs<double> pd{};
-    if (h->vbytes == 4) launch_direct<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, 0, o.dshmem, h->stream, true);
-    else launch_direct<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, 0, o.dshmem, h->stream, true);
+    if (h->vbytes == 4) launch_direct<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, k, 0, o.dshmem, h->stream, true);
+    else launch_direct<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, k, 0, o.dshmem, h->stream, true);
     HIPC(hipStreamSynchronize(h->stream));
     o.nstiles = (int32_t)(o.dtiles_h.size() / 4);
     o.direct = o.nstiles > 0;
@@ -426,7 +427,7 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
             launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
             HIPC(hipEventRecord(h->join, h->side));
         }
-        launch_direct<V>(pd, h->fmt, dir, jw, o.dshmem, s, false);
+        launch_direct<V>(pd, h->fmt, dir, dpass_k(o.dlanes), jw, o.dshmem, s, false);
         if (fork) HIPC(hipStreamWaitEvent(s, h->join, 0));
         return;
     }
@@ -581,16 +582,28 @@ struct PassTimer {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     }
-    // average milliseconds of one pass (all its launches) of orientation o
-    double time(OrientRT &o, int reps)
+    // average milliseconds of one pass (all its launches) of orientation o,
+    // alone or (paired) together with one pass of the other orientation in
+    // its current layout.  The tuner times candidates paired, where they
+    // run: a pass timed alone finds the caches as it left them, and on the
+    // pump batch a candidate 5 % faster alone made the iteration slower.
+    double time(OrientRT &o, int reps, bool paired = true)
     {
-        PassArgs<V> p = orient_args<V>(h, o, false);
-        p.st = trial_st.as<InstState>();
+        OrientRT &w = o.row ? h->ocol : h->orow;
+        PassArgs<V> p = orient_args<V>(h, o, false), q = orient_args<V>(h, w, false);
+        for (PassArgs<V> *a : {&p, &q}) {
+            a->st = trial_st.as<InstState>();
+            a->bar = sbar.as<V>();
+        }
         p.own = o.row ? sy.as<V>() : sx.as<V>();
-        p.bar = sbar.as<V>();
+        q.own = w.row ? sy.as<V>() : sx.as<V>();
+        if (paired) launch_orient<V>(h, w, q, 1, false, h->stream);
         launch_orient<V>(h, o, p, 1, false, h->stream);
         HIPC(hipEventRecord(e0, h->stream));
-        for (int r = 0; r < reps; ++r) launch_orient<V>(h, o, p, 1, false, h->stream);
+        for (int r = 0; r < reps; ++r) {
+            if (paired) launch_orient<V>(h, w, q, 1, false, h->stream);
+            launch_orient<V>(h, o, p, 1, false, h->stream);
+        }
         HIPC(hipEventRecord(e1, h->stream));
         HIPC(hipEventSynchronize(e1));
         HIPC(hipGetLastError());
@@ -795,9 +808,9 @@ void autotune(scylla_batch *h)
         }
         // direct staged candidates when some instance's whole gathered
         // vector fits in the LDS with nothing beside it; they must beat the
-        // others by 3 %, since a pass timed alone does not see its
-        // neighbours (on the pump batch a direct row pass timed 0.4 %
-        // faster alone made the whole iteration about 4 % slower)
+        // others by 3 % of the paired time (on the pump batch direct row
+        // passes timed up to 5 % faster alone made the whole iteration 2-4 %
+        // slower; paired, the two layouts time within 1 %)
         const int64_t dmax = (h->lds_max - 1024) / h->vbytes;
         const std::vector<int32_t> &off = o.row ? h->row_off : h->col_off;
         bool any_direct = false;
@@ -1484,17 +1497,20 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
 {
     return guarded([&]() {
         if (!h) throw_err(-EINVAL, "handle is NULL");
-        auto okB = [](int32_t B) { return B == 0 || B == 2 || B == 4 || B == 8 || B == -6 || (B >= -3 && B <= -1); };
+        auto okB = [](int32_t B) {
+            return B == 0 || B == 2 || B == 4 || B == 8 || (B >= -8 && B <= -6) || (B >= -3 && B <= -1);
+        };
         auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16 || e == -8 || e == -16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -6, -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8, 16, -8 or -16");
+            throw_err(-EINVAL, "blocks must be -8, -7, -6, -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8, 16, -8 or -16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;
             int32_t B = d == 0 ? row_blocks : col_blocks, ept = d == 0 ? row_ept : col_ept;
             if (o.rows == 0 && B > 0) B = 0;
-            if (B == -6) {
-                set_direct(h, o, ept, 32768, 1);
+            if (B <= -6) {
+                // at least 1, 4 or 8 lanes per row (8, 4 or 2 nonzeros per lane and round)
+                set_direct(h, o, ept, 32768, B == -6 ? 1 : (B == -7 ? 4 : 8));
                 drop_blocked(o);
                 release_sliced(o);
             } else if (B < 0) {
@@ -1520,12 +1536,12 @@ int scylla_batch_time_passes(scylla_batch *h, int32_t reps, double *ms_row, doub
         HIPC(hipStreamSynchronize(h->stream));
         if (h->vbytes == 4) {
             PassTimer<float> t(h);
-            *ms_row = t.time(h->orow, reps);
-            *ms_col = t.time(h->ocol, reps);
+            *ms_row = t.time(h->orow, reps, false);
+            *ms_col = t.time(h->ocol, reps, false);
         } else {
             PassTimer<double> t(h);
-            *ms_row = t.time(h->orow, reps);
-            *ms_col = t.time(h->ocol, reps);
+            *ms_row = t.time(h->orow, reps, false);
+            *ms_col = t.time(h->ocol, reps, false);
         }
         HIPC(hipStreamSynchronize(h->stream));
         return 0;

@@ -174,6 +174,10 @@ void plan_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &i
                  const std::vector<int32_t> &gofs, const std::vector<uint8_t> &candidate, int32_t max_vec,
                  int32_t max_slices, int32_t sub_chunk, int32_t group_nnz, SlicedPlan &plan);
 
+// Nonzeros per lane per row and round of the direct staged pass for a plan
+// with at least L lanes per row (rows of up to 16 nonzeros take one round).
+inline int32_t dpass_k(int32_t L) { return L <= 2 ? 8 : (L <= 4 ? 4 : 2); }
+
 // Direct staged tiles: every instance with rows and a gathered vector of at
 // most max_vec elements (direct[q] = 1) has its rows cut into runs of whole
 // rows with about group_nnz nonzeros, tiles {r0, r1, q, L}: L lanes per row,

@@ -85,7 +85,8 @@ int main(int argc, char **argv)
             const std::vector<int32_t> &off = d == 0 ? ro : co, &gof = d == 0 ? co : ro;
             std::vector<uint8_t> dir;
             std::vector<int32_t> tiles;
-            scy::plan_direct(x.ptr, off, gof, atoi(argv[6]), atoi(argv[7]), atoi(argv[8]), 8, dir, tiles);
+            scy::plan_direct(x.ptr, off, gof, atoi(argv[6]), atoi(argv[7]), atoi(argv[8]), scy::dpass_k(atoi(argv[8])),
+                             dir, tiles);
             std::vector<int32_t> di(dir.begin(), dir.end());
             wr(o, di); wr(o, tiles);
         }

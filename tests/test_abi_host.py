@@ -512,8 +512,8 @@ def test_direct_staged_tiles(lanes_min, group):
     most max_vec elements qualify; their rows are covered once, in order, by
     ceil(nnz / group_nnz) runs of whole rows per instance with about equal
     nonzero counts; the lanes per row are the smallest power of two >= lanes_min (at most 64)
-    with which the longest row of the tile takes at most four rounds of 8
-    nonzeros per lane."""
+    with which the longest row of the tile takes at most four rounds of K
+    nonzeros per lane (K = 8, 4, 2 for at least 1-2, 4, 8 lanes)."""
     lps = I.uneven_batch(count=10, lo=200, hi=9000, seed=5) + [I.workload(3, scale=0.002)]
     max_vec = 4000
     hdr, ro, co, orient, plans, dr = _run_prep(lps, 1, 1024, 1024, extra=(-6, max_vec, group, lanes_min))
@@ -532,7 +532,8 @@ def test_direct_staged_tiles(lanes_min, group):
             lens = np.diff(ptr[r0:r1 + 1])
             per.setdefault(q, []).append(int(lens.sum()))
             Lw = max(1, lanes_min)
-            while Lw < 64 and lens.max() > 32 * Lw:
+            k = 8 if lanes_min <= 2 else (4 if lanes_min <= 4 else 2)  # nonzeros per lane and round
+            while Lw < 64 and lens.max() > 4 * k * Lw:
                 Lw *= 2
             assert L == Lw
             cover[r0:r1] += 1

@@ -109,7 +109,7 @@ def test_adaptive_step_termination(name, prec, fused):
 
 
 @pytest.mark.parametrize("layout", [(0, 4, 0, 4), (4, 8, 8, 8), (-1, 8, -1, 8), (-2, 8, -2, 8), (-3, 8, -3, 8),
-                                    (-6, 8, -6, 8)])
+                                    (-6, 8, -6, 8), (-7, 8, -8, 8)])
 def test_adaptive_steps_under_every_layout(layout):
     """Every epilogue kernel (tiles, long rows, blocked and sliced combines,
     staged tiles, rest tiles) reports its slots: the batch solves to the
@@ -272,7 +272,8 @@ def test_time_limit_status():
 
 
 LAYOUTS = [(0, 4, 0, 16), (2, 8, 2, 4), (4, 8, 4, 4), (8, 4, 8, 8), (8, 16, 0, 8), (-1, 8, -1, 16), (-1, 4, 4, 8),
-           (0, -16, 0, -16), (4, -16, 2, -16), (-1, -16, -1, -16), (0, -8, 8, -8), (-6, 8, -6, 8), (-6, 4, 4, 8)]
+           (0, -16, 0, -16), (4, -16, 2, -16), (-1, -16, -1, -16), (0, -8, 8, -8), (-6, 8, -6, 8), (-6, 4, 4, 8),
+           (-7, 8, -8, 8), (-8, 4, -7, 4)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -290,6 +291,7 @@ def test_layout_parity(layout, name, prec, bar):
         # an LDS-staged request falls back to the normal layout when no
         # instance qualifies (rows longer than a staged sub-tile)
         for got, want in ((info["row_blocks"], layout[0]), (info["col_blocks"], layout[2])):
+            want = -6 if want in (-7, -8) else want  # direct staged, 4 / 8 lanes per row
             assert got == want or (want in (-1, -6) and got == 0), info
         r = b.solve(tol=1e-300, iter_limit=100, restarts=0)[0]
         x, y = b.solution(0)
@@ -336,16 +338,18 @@ def test_lds_sliced_layout_parity(case, prec, bar, mode):
         assert abs(res[i]["rel_kkt"] - k["rel"]) <= 1e-9 * max(1, k["rel"])
 
 
+@pytest.mark.parametrize("mode", [-6, -7, -8])
 @pytest.mark.parametrize("case", ["general_50k", "mixed_batch"])
 @pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
-def test_direct_staged_layout_parity(case, prec, bar):
-    """The direct staged layout (-6): instances whose whole gathered vector
-    fits in the LDS reduce their rows in registers from an LDS copy of it,
-    the others run normal tiles on a second branch; every instance matches
-    the oracle."""
+def test_direct_staged_layout_parity(case, prec, bar, mode):
+    """The direct staged layout (-6; -7 / -8 with at least 4 / 8 lanes and
+    4 / 2 nonzeros per lane and round per row): instances whose whole
+    gathered vector fits in the LDS reduce their rows in registers from an
+    LDS copy of it, the others run normal tiles on a second branch; every
+    instance matches the oracle."""
     lps = _sliced_cases()[case]
     with pdhg.Batch(lps, precision=prec) as b:
-        b.set_layout(-6, 8, -6, 8)
+        b.set_layout(mode, 8, mode, 8)
         info = b.info()
         print("info", info, flush=True)
         assert info["row_direct"] + info["col_direct"] >= 1
@@ -528,7 +532,7 @@ def _uniform_bound_batch():
     return out + [I.workload(2, scale=0.001)]
 
 
-@pytest.mark.parametrize("layout", [(0, 4, 0, 4), (4, 8, 2, 8), (-2, 8, -2, 8), (-6, 8, -6, 8)])
+@pytest.mark.parametrize("layout", [(0, 4, 0, 4), (4, 8, 2, 8), (-2, 8, -2, 8), (-6, 8, -6, 8), (-7, 8, -8, 8)])
 @pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
 def test_uniform_bounds_parity(layout, prec, bar):
     """The column pass reads the bounds of an instance whose columns share

@@ -283,7 +283,8 @@ typedef struct {
     int32_t row_sliced, col_sliced; /* instances of an LDS-staged pass whose
                                        gathered vector is processed in LDS
                                        slices (partial sums + row combine)   */
-    int32_t row_slices, col_slices; /* slices per such instance              */
+    int32_t row_slices, col_slices; /* most slices of such an instance (each
+                                       has ceil(vector / LDS room) slices)  */
     int32_t row_half_lds, col_half_lds; /* staged workgroups limited to half
                                        the LDS (two per CU)                  */
     int32_t row_tile_threads, col_tile_threads; /* threads per workgroup of

@@ -123,7 +123,7 @@ struct OrientRT {
     int32_t nstiles = 0;  // staged + sliced tiles
     SlicedPlan xplan;
     int32_t x_max_vec = -1, x_sub = -1;
-    DevMem xptr, xent, xval, xsub, xctiles, xP;
+    DevMem xptr, xent, xval, xsub, xctiles, xP, xsq;
     // direct staged layout (when chosen): the whole gathered vector of each
     // qualifying instance in LDS, rows reduced in registers; normal tiles
     // (splan.rest) for the other instances

@@ -412,7 +412,8 @@ void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &
     const int32_t rows = o.rows;
     plan = SlicedPlan();
     plan.sliced.assign(count, 0);
-    // slice count: enough for the longest qualifying instance
+    // slice count per instance: enough for its gathered vector; the slice
+    // arrays are sized for the longest qualifying instance
     int64_t longest = 0;
     std::vector<uint8_t> ok(count, 0);
     for (int32_t q = 0; q < count; ++q) {
@@ -429,14 +430,19 @@ void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &
     if (longest == 0) return;
     const int32_t S = (int32_t)((longest + max_vec - 1) / max_vec);
     plan.S = S;
-    for (int32_t q = 0; q < count; ++q) plan.sliced[q] = ok[q];
+    plan.Sq.assign(count, 0);
+    for (int32_t q = 0; q < count; ++q) {
+        plan.sliced[q] = ok[q];
+        if (ok[q]) plan.Sq[q] = (int32_t)((gofs[q + 1] - gofs[q] + max_vec - 1) / max_vec);
+    }
     // entries of sliced instances regrouped by slice
     auto slice_of = [&](int32_t q, int32_t g) {
         const int64_t glen = gofs[q + 1] - gofs[q], rel = g - gofs[q];
-        int32_t s = (int32_t)((rel * S) / glen);
-        // s is the slice with glen*s/S <= rel < glen*(s+1)/S
-        while (s > 0 && (glen * s) / S > rel) --s;
-        while (s + 1 < S && (glen * (s + 1)) / S <= rel) ++s;
+        const int32_t Sq = plan.Sq[q];
+        int32_t s = (int32_t)((rel * Sq) / glen);
+        // s is the slice with glen*s/Sq <= rel < glen*(s+1)/Sq
+        while (s > 0 && (glen * s) / Sq > rel) --s;
+        while (s + 1 < Sq && (glen * (s + 1)) / Sq <= rel) ++s;
         return s;
     };
     plan.bptr.assign((size_t)S * (rows + 1), 0);
@@ -476,8 +482,9 @@ void build_sliced(const HostOrient &o, int32_t fmt, const std::vector<int32_t> &
     for (int32_t q = 0; q < count; ++q) {
         if (!ok[q]) continue;
         const int64_t glen = gofs[q + 1] - gofs[q];
-        for (int32_t s = 0; s < S; ++s)
-            plan.max_slice = std::max<int32_t>(plan.max_slice, (int32_t)((glen * (s + 1)) / S - (glen * s) / S));
+        const int32_t Sq = plan.Sq[q];
+        for (int32_t s = 0; s < Sq; ++s)
+            plan.max_slice = std::max<int32_t>(plan.max_slice, (int32_t)((glen * (s + 1)) / Sq - (glen * s) / Sq));
     }
 }
 
@@ -493,8 +500,9 @@ void tile_sliced(const std::vector<int32_t> &inst_off, int32_t rows, int32_t sub
     if (S == 0) return;
     // sub-tiles per slice, grouped per (instance, slice)
     std::vector<uint8_t> skip(count);
-    for (int32_t q = 0; q < count; ++q) skip[q] = ok[q] ? 0 : 1;
     for (int32_t s = 0; s < S; ++s) {
+        // instances with fewer slices have none here
+        for (int32_t q = 0; q < count; ++q) skip[q] = (ok[q] && s < plan.Sq[q]) ? 0 : 1;
         std::vector<int32_t> ptr(plan.bptr.begin() + (size_t)s * (rows + 1),
                                  plan.bptr.begin() + (size_t)(s + 1) * (rows + 1));
         TilePlan tp;
@@ -503,7 +511,7 @@ void tile_sliced(const std::vector<int32_t> &inst_off, int32_t rows, int32_t sub
         plan.sub.insert(plan.sub.end(), tp.tiles.begin(), tp.tiles.end());
         std::vector<int32_t> cuts;
         for (int32_t q = 0; q < count; ++q) {
-            if (!ok[q] || tp.t_end[q] == tp.t_begin[q]) continue;
+            if (skip[q] || tp.t_end[q] == tp.t_begin[q]) continue;
             balanced_runs(tp.t_begin[q], tp.t_end[q], group_nnz, [&](int32_t t) {
                 const int32_t *d = tp.tiles.data() + 4 * t;
                 return (int64_t)(ptr[d[1]] - ptr[d[0]]);

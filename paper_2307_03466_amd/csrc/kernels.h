@@ -59,11 +59,13 @@ struct PassArgs {
     const int32_t *gofs;  // [count + 1] gathered-vector offsets per instance
     const int4 *sub;      // sub-tiles {r0, r1, inst, -1} of the staged tiles
     // LDS-sliced tiles of the staged pass (tile field w = -2): slice s of
-    // instance q gathers [g0 + glen*s/xS, g0 + glen*(s+1)/xS) from LDS
+    // instance q gathers [g0 + glen*s/S_q, g0 + glen*(s+1)/S_q) from LDS
     MatView X;            // slice-regrouped entries; X.ptr = [xS * (rows + 1)]
     const int4 *xsub;     // sub-tiles of the sliced tiles
-    int32_t xS;           // slices per sliced instance
-    V *xP;                // [xS * rows] slice partial sums
+    int32_t xS;           // slices of the longest sliced instance
+    const int32_t *xSq;   // [count] slices S_q per instance
+    V *xP;                // [xS * rows] slice partial sums (s < S_q written)
+    const int32_t *bq;    // combine: partial arrays per instance (null: all B)
     // direct staged pass: tiles {r0, r1, inst, lanes per row} of instances
     // whose whole gathered vector sits in LDS (no product buffer)
     const int4 *dtiles;

@@ -412,7 +412,8 @@ __global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int
         RowOps<V> ops;
         load_ops<V, DIR>(p, i, ops, ib);
         V s = 0;
-        for (int b = 0; b < p.B; ++b) s += p.P[(size_t)b * p.rows + i];
+        const int nb = p.bq ? p.bq[T.z] : p.B;
+        for (int b = 0; b < nb; ++b) s += p.P[(size_t)b * p.rows + i];
         apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
     }
     if (p.adapt) {
@@ -512,7 +513,8 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
         M = p.X;
         M.ptr = p.X.ptr + (size_t)sl * (p.rows + 1);
         sub = p.xsub;
-        const int lo = (int)(((int64_t)glen * sl) / p.xS), hi = (int)(((int64_t)glen * (sl + 1)) / p.xS);
+        const int Sq = p.xSq[inst];
+        const int lo = (int)(((int64_t)glen * sl) / Sq), hi = (int)(((int64_t)glen * (sl + 1)) / Sq);
         g0 += lo;
         glen = hi - lo;
         Ps = p.xP + (size_t)sl * p.rows;

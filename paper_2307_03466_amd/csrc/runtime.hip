@@ -61,6 +61,7 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
         p.X = MatView{o.xptr.as<int32_t>(), o.xent.as<uint32_t>(), o.xval.p, o.host.shift, o.host.mask};
         p.xsub = o.xsub.as<int4>();
         p.xS = o.xplan.S;
+        p.xSq = o.xsq.as<int32_t>();
         p.xP = o.xP.as<V>();
     }
     if (o.row) {
@@ -188,6 +189,7 @@ void release_sliced(OrientRT &o)
     o.xsub.release();
     o.xctiles.release();
     o.xP.release();
+    o.xsq.release();
 }
 
 // LDS-staged layout; with `slice`, instances too long for LDS (up to 4x)
@@ -215,6 +217,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
             o.x_max_vec = max_vec;
             o.x_sub = chunk;
             if (o.xplan.S > 0) {
+                upload(o.xsq, o.xplan.Sq, h->stream);
                 upload(o.xptr, o.xplan.bptr, h->stream);
                 upload(o.xent, o.xplan.ent, h->stream);
                 upload_vals(h, o.xval, o.xplan.v16, o.xplan.v32, o.xplan.v64);
@@ -442,6 +445,7 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
             pc.ctiles = o.xctiles.as<int4>();
             pc.nctiles = (int32_t)(o.xplan.ctiles.size() / 4);
             pc.B = o.xplan.S;
+            pc.bq = o.xsq.as<int32_t>();
             pc.P = o.xP.as<V>();
             pc.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_comb;
         }

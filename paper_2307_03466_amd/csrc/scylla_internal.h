@@ -137,19 +137,20 @@ void plan_staged(const std::vector<int32_t> &ptr, const std::vector<int32_t> &in
                  int32_t rest_chunk, StagedPlan &plan);
 
 // LDS-sliced part of a staged orientation.  An instance whose gathered
-// vector is longer than max_vec but at most S * max_vec (S = the smallest
-// slice count that fits the longest such instance, at most max_slices), with
-// no row longer than sub_chunk, has its gathered range cut into S equal
-// slices [g0 + glen*s/S, g0 + glen*(s+1)/S); each row's nonzeros are
-// regrouped by slice (bptr[s * (rows + 1) + i] points into ent; rows of
-// other instances are empty).  Sub-tiles of a slice's rows (<= sub_chunk
+// vector is longer than max_vec but at most max_slices * max_vec, with no
+// row longer than sub_chunk, has its gathered range cut into
+// S_q = ceil(glen / max_vec) equal slices [g0 + glen*s/S_q,
+// g0 + glen*(s+1)/S_q); each row's nonzeros are regrouped by slice
+// (bptr[s * (rows + 1) + i] points into ent, for s below S = the largest
+// S_q; rows of other instances and slices s >= S_q are empty).  Sub-tiles of a slice's rows (<= sub_chunk
 // nonzeros, <= 4096 rows) are grouped into ceil(nnz / group_nnz) tiles of
 // about equal nonzero counts per (instance, slice)
 // {sub0, sub1, inst | s << 24, -2}; the slice partial sums of a row
 // are added in slice order by the combine tiles {r0, r1, inst, -1}.
 struct SlicedPlan {
-    int32_t S = 0;                // slices per sliced instance (0: none)
+    int32_t S = 0;                // slices of the longest sliced instance (0: none)
     std::vector<uint8_t> sliced;  // per instance
+    std::vector<int32_t> Sq;      // slices per instance (0: not sliced)
     std::vector<int32_t> bptr;    // [S * (rows + 1)]
     std::vector<uint32_t> ent;
     std::vector<uint16_t> v16;

@@ -122,7 +122,8 @@ int main(int argc, char **argv)
                 scy::plan_sliced(x, fmt, off, gof, cand, max_vec, atoi(argv[9]), sub_chunk, group_nnz, xp);
                 std::vector<int32_t> hd = {xp.S, xp.max_slice};
                 std::vector<int32_t> sl(xp.sliced.begin(), xp.sliced.end());
-                wr(o, hd); wr(o, sl); wr(o, xp.bptr); wr(o, xp.ent); wr(o, xp.tiles); wr(o, xp.sub); wr(o, xp.ctiles);
+                wr(o, hd); wr(o, sl); wr(o, xp.Sq); wr(o, xp.bptr); wr(o, xp.ent); wr(o, xp.tiles); wr(o, xp.sub);
+                wr(o, xp.ctiles);
             }
         }
     }

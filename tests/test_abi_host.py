@@ -202,7 +202,8 @@ def _run_prep(lps, precision, chunk, max_rows, extra=(), sanitize=False):
                      rest=take(np.int32).reshape(-1, 4), restlongs=take(np.int32).reshape(-1, 4))
             if len(extra) >= 5:
                 hd = take(np.int32)
-                d["sliced"] = dict(S=int(hd[0]), max_slice=int(hd[1]), inst=take(np.int32), bptr=take(np.int32),
+                d["sliced"] = dict(S=int(hd[0]), max_slice=int(hd[1]), inst=take(np.int32), Sq=take(np.int32),
+                                   bptr=take(np.int32),
                                    ent=take(np.uint32), tiles=take(np.int32).reshape(-1, 4),
                                    sub=take(np.int32).reshape(-1, 4), ctiles=take(np.int32).reshape(-1, 4))
             st.append(d)
@@ -433,16 +434,17 @@ def test_lds_staged_plan():
 
 
 def test_lds_sliced_plan():
-    """Instances too long for LDS but at most S slices long get their
-    gathered range cut into S equal slices: each row's nonzeros are
-    regrouped by slice without loss or reordering, every slice's sub-tiles
-    cover each row of a sliced instance once, and combine tiles cover those
-    rows once."""
+    """Instances too long for LDS but at most max_slices LDS capacities long
+    get their gathered range cut into S_q = ceil(length / capacity) equal
+    slices: each row's nonzeros are regrouped by slice without loss or
+    reordering, every one of the instance's slices has sub-tiles covering
+    each of its rows once (and slices beyond S_q none), and combine tiles
+    cover those rows once."""
     lps = I.uneven_batch(count=10, lo=200, hi=9000, seed=5)
     chunk, max_rows, max_vec, sub_chunk, group, max_slices = 1024, 1024, 6000, 4096, 16384, 4
     hdr, ro, co, orient, plans, st = _run_prep(lps, 1, chunk, max_rows,
                                                extra=(0, max_vec, sub_chunk, group, max_slices))
-    seen = 0
+    seen, counts = 0, set()
     for which in (0, 1):
         o, sp = orient[which], st[which]
         x = sp["sliced"]
@@ -459,7 +461,10 @@ def test_lds_sliced_plan():
             continue
         seen += 1
         S = x["S"]
+        Sq = x["Sq"]
         assert S == -(-glen[want].max() // max_vec)
+        np.testing.assert_array_equal(Sq, np.where(want, -(-glen // max_vec), 0))
+        counts.update(Sq[want].tolist())
         assert x["max_slice"] <= max_vec
         idx = _decode_idx(o["ent"], hdr, which, hdr[0])
         xidx = _decode_idx(x["ent"], hdr, which, hdr[0])
@@ -468,7 +473,7 @@ def test_lds_sliced_plan():
         per = {}
         for s0, s1, z, kind in x["tiles"]:
             q, s = z & 0xFFFFFF, z >> 24
-            assert kind == -2 and want[q] and s < S
+            assert kind == -2 and want[q] and s < Sq[q]
             nz = 0
             for a, b, qq, _ in x["sub"][s0:s1]:
                 assert qq == q and off[q] <= a <= b <= off[q + 1]
@@ -484,12 +489,15 @@ def test_lds_sliced_plan():
             assert max(nzs) <= total / k + sub_chunk and min(nzs) >= total / k - sub_chunk
         for q in np.flatnonzero(want):
             r = np.arange(off[q], off[q + 1])
-            lo = [gof[q] + (glen[q] * s) // S for s in range(S + 1)]
+            n_s = Sq[q]
+            lo = [gof[q] + (glen[q] * s) // n_s for s in range(n_s + 1)]
             for s in range(S):
-                assert np.all(cover[s][r] == 1)
+                assert np.all(cover[s][r] == (1 if s < n_s else 0))
+                if s >= n_s:
+                    assert np.all(bptr[s, off[q]:off[q + 1] + 1] == bptr[s, off[q]])
             for i in r[:: max(1, r.size // 50)]:
                 parts = []
-                for s in range(S):
+                for s in range(n_s):
                     seg = xidx[bptr[s, i]:bptr[s, i + 1]]
                     assert np.all((seg >= lo[s]) & (seg < lo[s + 1]))
                     parts.append(x["ent"][bptr[s, i]:bptr[s, i + 1]])
@@ -503,7 +511,7 @@ def test_lds_sliced_plan():
             cov[a:b] += 1
         rows_w = np.concatenate([np.arange(off[q], off[q + 1]) for q in np.flatnonzero(want)])
         assert np.all(cov[rows_w] == 1) and cov.sum() == rows_w.size
-    assert seen >= 1
+    assert seen >= 1 and len(counts) > 1  # the cases mix slice counts
 
 
 @pytest.mark.parametrize("lanes_min,group", [(1, 16384), (4, 3000)])

@@ -308,11 +308,13 @@ def _sliced_cases():
     big = I.general_lp(m=20_000, n=50_000, seed=31)
     batch = [I.cover_knapsack(500, seed=1), I.cover_knapsack(24_000, seed=2), I.set_cover(300, 700, seed=3),
              I.cover_knapsack(9_000, seed=4)]
-    return {"general_50k": [big], "mixed_batch": batch}
+    # gathered vectors of 48k and 80k values: two and three slices in FP32
+    slices = [I.cover_knapsack(24_000, seed=5), I.cover_knapsack(40_000, seed=6), I.cover_knapsack(1_000, seed=7)]
+    return {"general_50k": [big], "mixed_batch": batch, "mixed_slices": slices}
 
 
 @pytest.mark.parametrize("mode", [-2, -3])
-@pytest.mark.parametrize("case", ["general_50k", "mixed_batch"])
+@pytest.mark.parametrize("case", ["general_50k", "mixed_batch", "mixed_slices"])
 @pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-4)])
 def test_lds_sliced_layout_parity(case, prec, bar, mode):
     """The LDS-sliced layout (-2; -3 with half the LDS per workgroup):

@@ -41,6 +41,7 @@ import subprocess
 from dataclasses import dataclass
 
 import numpy as np
+from typing import Optional
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "scylla_oracle.c")
@@ -73,7 +74,8 @@ class _Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("ruiz_iters", ctypes.c_int32),
                 ("pock_chambolle", ctypes.c_int32), ("omega0", ctypes.c_double),
                 ("adaptive", ctypes.c_int32), ("infeas_tol", ctypes.c_double),
-                ("stall_tol", ctypes.c_double), ("stall_checks", ctypes.c_int32)]
+                ("stall_tol", ctypes.c_double), ("stall_checks", ctypes.c_int32),
+                ("restart_avg", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -93,7 +95,7 @@ def _load():
         if not os.path.exists(_LIB):
             build(force=False)
         lib = ctypes.CDLL(_LIB)
-        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_fix_propagate", "orc_ray",
+        for fn in ("orc_precondition", "orc_kkt", "orc_pdhg", "orc_pdhg_avg", "orc_fix_propagate", "orc_ray",
                    "orc_fix_propagate_batched"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
@@ -138,6 +140,8 @@ class PDHGResult:
     dobj: float
     omega: float
     eta: float
+    x_avg: Optional[np.ndarray] = None  # running means (restart_avg) at the stop
+    y_avg: Optional[np.ndarray] = None
 
 
 def precondition(lp, ruiz_iters: int = 10, pock_chambolle: bool = True):
@@ -167,7 +171,7 @@ def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 6
          restarts: bool = True, eta: float = 0.99, x0=None, y0=None, omega0: float = 0.0,
          c=None, ruiz_iters: int = 10, pock_chambolle: bool = True,
          adaptive: bool = False, q=None, infeas_tol: float = 1e-8, stall_tol: float = 0.0,
-         stall_checks: int = 3) -> PDHGResult:
+         stall_checks: int = 3, restart_avg: bool = False) -> PDHGResult:
     """FP64 PDHG solve of the LP relaxation (Algorithm 1 inner loop); with
     `adaptive` the step size follows PDLP's adaptive rule (no retries),
     starting at `eta`.  `q`: diagonal Hessian (>= 0) of a QP objective
@@ -175,20 +179,30 @@ def pdhg(lp, tol: float = 1e-4, iter_limit: int = 100_000, check_period: int = 6
     PRIMAL_INFEASIBLE / DUAL_INFEASIBLE when the moves between two checks
     certify it to that relative accuracy (0: off).  stall_tol > 0: stop with
     STALLED when neither objective bound moved by more than
-    stall_tol (1 + |value|) at stall_checks consecutive checks."""
+    stall_tol (1 + |value|) at stall_checks consecutive checks.
+    restart_avg: the running mean of the iterates since the last restart is
+    a candidate at every check (the lower relative KKT error wins: the
+    termination test, the restart rule and the returned point use the
+    winner); the result's x_avg / y_avg hold that mean at the stop."""
     pin = _Pinned(lp, c, q)
     x = np.empty(lp.n)
     y = np.empty(lp.m)
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
     y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
     prm = _Params(tol, iter_limit, check_period, int(restarts), eta, ruiz_iters,
-                  int(pock_chambolle), omega0, int(adaptive), infeas_tol, stall_tol, stall_checks)
+                  int(pock_chambolle), omega0, int(adaptive), infeas_tol, stall_tol, stall_checks,
+                  int(restart_avg))
     res = _Result()
-    rc = _load().orc_pdhg(ctypes.byref(pin.s), ctypes.byref(prm), _p(x0a), _p(y0a), _p(x), _p(y),
-                          ctypes.byref(res))
+    xa = np.zeros(lp.n)
+    ya = np.zeros(lp.m)
+    rc = _load().orc_pdhg_avg(ctypes.byref(pin.s), ctypes.byref(prm), _p(x0a), _p(y0a), _p(x), _p(y),
+                              _p(xa), _p(ya), ctypes.byref(res))
     assert rc == 0
-    return PDHGResult(x, y, res.status, res.iterations, res.restarts, res.rel_kkt, res.rho_p,
-                      res.rho_d, res.rho_g, res.pobj, res.dobj, res.omega, res.eta)
+    out = PDHGResult(x, y, res.status, res.iterations, res.restarts, res.rel_kkt, res.rho_p,
+                     res.rho_d, res.rho_g, res.pobj, res.dobj, res.omega, res.eta)
+    if restart_avg:
+        out.x_avg, out.y_avg = xa, ya
+    return out
 
 
 def ray(lp, x, y, xp, yp, q=None):

@@ -67,6 +67,16 @@
  *     iterate is always kept (PDLP would retry a step with eta > eta_bar);
  *     eta_bar = infinity when dy^T A dx = 0, and eta stays when dx = dy = 0.
  *     eta starts at the eta parameter.
+ *   - restart to the average (PDLP's restart candidates; option): z_avg is
+ *     the running mean of the iterates produced since the last restart (or
+ *     since the start), equal weights: the first iterate after a restart
+ *     starts it, later ones update z_avg += (z - z_avg) / count.  At every check after the first the candidate
+ *     is z_avg if its relative KKT error is below the current iterate's,
+ *     else the current iterate (ties: current); its error E is what the
+ *     termination test, the restart rule and E_prev use, and the candidate
+ *     is what a restart restarts to and what an OPTIMAL or
+ *     iteration-limit stop returns.  Infeasibility and stalling are tested
+ *     on the current iterate.  A restart starts a new average.
  *
  * Build: gcc -O2 -std=c11 -shared -fPIC -o liboracle.so scylla_oracle.c -lm
  */
@@ -100,6 +110,8 @@ typedef struct {
     double infeas_tol;   /* > 0: infeasibility certificates at the checks */
     double stall_tol;    /* > 0: stop when the objective bounds stall */
     int32_t stall_checks;/* consecutive checks without a move that stop */
+    int32_t restart_avg; /* 1: the average of the iterates since the last
+                            restart is a candidate at every check */
 } orc_params;
 
 enum { ORC_OPTIMAL = 1, ORC_ITERATION_LIMIT = 2, ORC_NUMERICAL_ERROR = 4, ORC_PRIMAL_INFEASIBLE = 5,
@@ -333,8 +345,19 @@ int orc_ray(const orc_lp *lp, const double *x, const double *y, const double *xp
     return 0;
 }
 
+int orc_pdhg_avg(const orc_lp *lp, const orc_params *p, const double *x0, const double *y0,
+                 double *x, double *y, double *xa_out, double *ya_out, orc_result *res);
+
 int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const double *y0,
              double *x, double *y, orc_result *res)
+{
+    return orc_pdhg_avg(lp, p, x0, y0, x, y, NULL, NULL, res);
+}
+
+/* orc_pdhg that also returns the running averages (restart_avg) at the stop,
+ * before any candidate replaced the iterate; xa_out / ya_out may be NULL. */
+int orc_pdhg_avg(const orc_lp *lp, const orc_params *p, const double *x0, const double *y0,
+                 double *x, double *y, double *xa_out, double *ya_out, orc_result *res)
 {
     const int32_t m = lp->m, n = lp->n;
     const int32_t R = p->check_period > 0 ? p->check_period : 64;
@@ -351,8 +374,11 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     double *adx = malloc(sizeof(double) * (m > 0 ? m : 1));
     double *xp = malloc(sizeof(double) * (n > 0 ? n : 1));
     double *yp = malloc(sizeof(double) * (m > 0 ? m : 1));
+    double *xa = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *ya = malloc(sizeof(double) * (m > 0 ? m : 1));
     int rc = 0;
-    if (!dr || !dc || !xn || !xbar || !aty || !axb || !xr || !yr || !yn || !dxv || !adx || !xp || !yp) {
+    if (!dr || !dc || !xn || !xbar || !aty || !axb || !xr || !yr || !yn || !dxv || !adx || !xp || !yp ||
+        !xa || !ya) {
         rc = -1;
         goto done;
     }
@@ -381,14 +407,29 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     double pprev = 0.0, dprev = 0.0;
     int32_t nstall = 0;
     int32_t nrestart = 0;
-    double kkt[8] = {0};
+    int64_t na = 0; /* iterates in the running average */
+    double kkt[8] = {0}, kkta[8] = {0};
     memset(res, 0, sizeof(*res));
     for (;;) {
         if (k % R == 0 || k >= p->iter_limit) {
             orc_kkt(lp, x, y, kkt);
-            double E = kkt[0];
-            if (!isfinite(E)) { res->status = ORC_NUMERICAL_ERROR; break; }
-            if (E <= p->tol) { res->status = ORC_OPTIMAL; break; }
+            if (!isfinite(kkt[0])) { res->status = ORC_NUMERICAL_ERROR; break; }
+            /* the candidate: the running average when its error is lower */
+            int use_avg = 0;
+            if (p->restart_avg && na > 0) {
+                orc_kkt(lp, xa, ya, kkta);
+                use_avg = kkta[0] < kkt[0];
+            }
+            double E = use_avg ? kkta[0] : kkt[0];
+            if (E <= p->tol) {
+                if (use_avg) {
+                    memcpy(x, xa, sizeof(double) * n);
+                    memcpy(y, ya, sizeof(double) * m);
+                    memcpy(kkt, kkta, sizeof(kkt));
+                }
+                res->status = ORC_OPTIMAL;
+                break;
+            }
             if (p->infeas_tol > 0.0 && k > 0) {
                 double ray[4];
                 orc_ray(lp, x, y, xp, yp, ray);
@@ -411,7 +452,15 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
                 pprev = kkt[4];
                 dprev = kkt[5];
             }
-            if (k >= p->iter_limit) { res->status = ORC_ITERATION_LIMIT; break; }
+            if (k >= p->iter_limit) {
+                if (use_avg) {
+                    memcpy(x, xa, sizeof(double) * n);
+                    memcpy(y, ya, sizeof(double) * m);
+                    memcpy(kkt, kkta, sizeof(kkt));
+                }
+                res->status = ORC_ITERATION_LIMIT;
+                break;
+            }
             if (k == 0) {
                 Er = E;
                 for (int32_t j = 0; j < n; ++j) xr[j] = x[j];
@@ -420,6 +469,10 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
                 int fire = (E <= 0.2 * Er) || (E <= 0.8 * Er && E > Ep) ||
                            ((double)(k - kr) >= 0.36 * (double)k);
                 if (fire) {
+                    if (use_avg) {
+                        memcpy(x, xa, sizeof(double) * n);
+                        memcpy(y, ya, sizeof(double) * m);
+                    }
                     double dx2 = 0.0, dy2 = 0.0;
                     for (int32_t j = 0; j < n; ++j) {
                         double d = (x[j] - xr[j]) / dc[j];
@@ -439,6 +492,7 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
                     for (int32_t i = 0; i < m; ++i) yr[i] = y[i];
                     Er = E;
                     kr = k;
+                    na = 0;
                     ++nrestart;
                 }
             }
@@ -493,6 +547,20 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
         }
         for (int32_t j = 0; j < n; ++j) x[j] = xn[j];
         for (int32_t i = 0; i < m; ++i) y[i] = yn[i];
+        if (p->restart_avg) {
+            /* the first iterate after a restart starts the mean */
+            ++na;
+            for (int32_t j = 0; j < n; ++j) xa[j] = na == 1 ? x[j] : xa[j] + (x[j] - xa[j]) / (double)na;
+            for (int32_t i = 0; i < m; ++i) ya[i] = na == 1 ? y[i] : ya[i] + (y[i] - ya[i]) / (double)na;
+        }
+    }
+    if (xa_out) {
+        if (na > 0) memcpy(xa_out, xa, sizeof(double) * n);
+        else memset(xa_out, 0, sizeof(double) * n);
+    }
+    if (ya_out) {
+        if (na > 0) memcpy(ya_out, ya, sizeof(double) * m);
+        else memset(ya_out, 0, sizeof(double) * m);
     }
     res->iterations = k;
     res->restarts = nrestart;
@@ -506,7 +574,7 @@ int orc_pdhg(const orc_lp *lp, const orc_params *p, const double *x0, const doub
     res->eta = eta;
 done:
     free(dr); free(dc); free(xn); free(xbar); free(aty); free(axb); free(xr); free(yr);
-    free(yn); free(dxv); free(adx); free(xp); free(yp);
+    free(yn); free(dxv); free(adx); free(xp); free(yp); free(xa); free(ya);
     return rc;
 }
 

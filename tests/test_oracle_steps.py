@@ -75,20 +75,24 @@ def _restart_cases():
     ]
 
 
-def test_restart_rule_and_weight_update_restated_from_checks():
+@pytest.mark.parametrize("avg", [False, True])
+def test_restart_rule_and_weight_update_restated_from_checks(avg):
     """At each check after the start, with E the relative KKT error of the
     current point, E_r its value at the last restart (the start counts) and
     E_p at the previous check, the solve restarts iff E <= 0.2 E_r, or
     E <= 0.8 E_r and E > E_p, or k - k_r >= 0.36 k.  At a restart the primal
     weight becomes the geometric mean of the old weight and |dy~| / |dx~|,
     with dx~ = (x - x_r) / d_c and dy~ = (y - y_r) / d_r the moves since the
-    last restart point (unchanged if either is <= 1e-10)."""
+    last restart point (unchanged if either is <= 1e-10).  With the average
+    on, "the current point" is the candidate: what a run stopped at that
+    check returns (the mean when its error is lower)."""
     decisive = {"0.2": 0, "0.8": 0, "0.36": 0, "none": 0, "weight": 0}
     for name, lp, R in _restart_cases():
         dr, dc = oracle.precondition(lp)
-        full = oracle.pdhg(lp, tol=1e-7, iter_limit=60 * R, check_period=R)
+        full = oracle.pdhg(lp, tol=1e-7, iter_limit=60 * R, check_period=R, restart_avg=avg)
         nchk = full.iterations // R
-        snaps = [oracle.pdhg(lp, tol=-1.0, iter_limit=c * R, check_period=R) for c in range(nchk + 1)]
+        snaps = [oracle.pdhg(lp, tol=-1.0, iter_limit=c * R, check_period=R, restart_avg=avg)
+                 for c in range(nchk + 1)]
         # checks 0..nchk-1 take a decision (the last one ends the run)
         E = [kkt_numpy(lp, s.x, s.y)["rel"] for s in snaps]
         w = snaps[0].omega
@@ -116,7 +120,11 @@ def test_restart_rule_and_weight_update_restated_from_checks():
             assert nxt.restarts == nrest, (name, c, E[c], Er, Ep, kr)
             assert abs(nxt.omega - w) <= 1e-11 * w, (name, c, nxt.omega, w)
     # every condition decided some restart on its own, and some checks did not restart
-    assert min(decisive.values()) >= 1, decisive
+    if not avg:
+        assert min(decisive.values()) >= 1, decisive
+    else:
+        assert decisive["0.36"] >= 1 and decisive["none"] >= 1 and decisive["weight"] >= 1, decisive
+        assert decisive["0.2"] + decisive["0.8"] >= 1, decisive
 
 
 def test_restarts_off_keep_the_cold_start_weight():
@@ -199,3 +207,120 @@ def test_adaptive_trajectory_amplifies_rounding_constant_steps_do_not():
     a = oracle.pdhg(lp, tol=-1.0, iter_limit=10, restarts=False, adaptive=True)
     b = oracle.pdhg(lp, tol=-1.0, iter_limit=10, restarts=False, adaptive=True, c=c2)
     assert max(rel_err(a.x, b.x), rel_err(a.y, b.y)) <= 1e-5
+
+
+# ------------------------------------------------------ restart to average
+def _avg_cases():
+    return [
+        ("cover", I.set_cover(150, 400, seed=5)),
+        ("knapsack", I.cover_knapsack(300, seed=6)),
+        ("general", I.workload(2, scale=0.0005)),
+        ("mixed", I.tiny_lp(np.random.default_rng(3), 40, 70, bounded=False)),
+    ]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_running_average_is_the_mean_of_the_iterates(case):
+    """With restarts off the running average only changes what a check
+    returns, not the trajectory; it is the plain mean of the iterates
+    x_1 .. x_K (snapshot runs without the average), through a check."""
+    name, lp = _avg_cases()[case]
+    K = 70
+    snaps = [oracle.pdhg(lp, tol=-1.0, iter_limit=k, restarts=False) for k in range(1, K + 1)]
+    r = oracle.pdhg(lp, tol=-1.0, iter_limit=K, restarts=False, restart_avg=True)
+    xm = np.mean([s.x for s in snaps], axis=0)
+    ym = np.mean([s.y for s in snaps], axis=0)
+    assert rel_err(r.x_avg, xm) <= 1e-12 and rel_err(r.y_avg, ym) <= 1e-12, name
+    # the same trajectory: at the iteration limit the current iterate is
+    # the snapshot's (returned unless the mean wins)
+    cur = snaps[-1]
+    e_cur, e_avg = kkt_numpy(lp, cur.x, cur.y)["rel"], kkt_numpy(lp, r.x_avg, r.y_avg)["rel"]
+    want_x, want_y = (r.x_avg, r.y_avg) if e_avg < e_cur else (cur.x, cur.y)
+    np.testing.assert_allclose(r.x, want_x, rtol=0, atol=1e-12 * (1 + np.abs(want_x).max()))
+    np.testing.assert_allclose(r.y, want_y, rtol=0, atol=1e-12 * (1 + np.abs(want_y).max()))
+    assert abs(r.rel_kkt - min(e_cur, e_avg)) <= 1e-12 * max(1.0, r.rel_kkt)
+
+
+def test_candidate_choice_goes_both_ways():
+    """Across the cases and check counts the mean wins some checks and the
+    current iterate others, so both branches of the rule are exercised."""
+    wins = {"avg": 0, "cur": 0}
+    for name, lp in _avg_cases():
+        for K in (64, 128, 192, 320):
+            r = oracle.pdhg(lp, tol=-1.0, iter_limit=K, restarts=False, restart_avg=True)
+            cur = oracle.pdhg(lp, tol=-1.0, iter_limit=K, restarts=False)
+            e_avg = kkt_numpy(lp, r.x_avg, r.y_avg)["rel"]
+            e_cur = kkt_numpy(lp, cur.x, cur.y)["rel"]
+            wins["avg" if e_avg < e_cur else "cur"] += 1
+    assert min(wins.values()) >= 1, wins
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_restart_to_the_candidate_restated(case):
+    """The first check after the start always restarts (k - k_r = k >= 0.36
+    k).  With the average on, the solve restarts at k = R to the candidate
+    (the mean when its KKT error is lower), with the primal weight updated
+    from the candidate's distance to the start point, and starts a new
+    mean.  One iteration later the iterate equals one plain iteration from
+    the candidate with that weight, and the new mean is that iterate."""
+    name, lp = _avg_cases()[case]
+    R = 64
+    dr, dc = oracle.precondition(lp)
+    start = oracle.pdhg(lp, tol=-1.0, iter_limit=0)
+    # the candidate at k = R: returned by a run that stops there
+    cand = oracle.pdhg(lp, tol=-1.0, iter_limit=R, restarts=False, restart_avg=True)
+    dx = np.linalg.norm((cand.x - start.x) / dc)
+    dy = np.linalg.norm((cand.y - start.y) / dr)
+    w = start.omega
+    if dx > 1e-10 and dy > 1e-10:
+        w = np.exp(0.5 * np.log(dy / dx) + 0.5 * np.log(w))
+    one = oracle.pdhg(lp, tol=-1.0, iter_limit=1, restarts=False, x0=cand.x, y0=cand.y, omega0=w)
+    r = oracle.pdhg(lp, tol=-1.0, iter_limit=R + 1, restarts=True, restart_avg=True)
+    assert r.restarts == 1 and abs(r.omega - w) <= 1e-12 * w, (name, r.omega, w)
+    assert rel_err(r.x, one.x) <= 1e-12 and rel_err(r.y, one.y) <= 1e-12, name
+    assert rel_err(r.x_avg, one.x) <= 1e-15 and rel_err(r.y_avg, one.y) <= 1e-15, name
+
+
+def test_restart_to_average_takes_the_mean_on_some_case():
+    """On at least one case the candidate at the first restart is the mean
+    (so the restatement above covers restarting to it)."""
+    took = 0
+    for name, lp in _avg_cases():
+        cand = oracle.pdhg(lp, tol=-1.0, iter_limit=64, restarts=False, restart_avg=True)
+        cur = oracle.pdhg(lp, tol=-1.0, iter_limit=64, restarts=False)
+        took += int(not np.array_equal(cand.x, cur.x))
+    assert took >= 1
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+@pytest.mark.parametrize("case", range(4))
+def test_restart_to_average_reaches_the_tolerance(case, adaptive):
+    name, lp = _avg_cases()[case]
+    r = oracle.pdhg(lp, tol=1e-6, iter_limit=200_000, restart_avg=True, adaptive=adaptive)
+    assert r.status == oracle.OPTIMAL, name
+    assert kkt_numpy(lp, r.x, r.y)["rel"] <= 1e-6 * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_termination_uses_the_candidate(case):
+    """A tolerance between the mean's error and the current iterate's at a
+    check where the mean wins stops the solve there, OPTIMAL, returning the
+    mean; without the average the same tolerance does not stop it there."""
+    name, lp = _avg_cases()[case]
+    for K in (64, 128, 192, 256, 320):
+        r = oracle.pdhg(lp, tol=-1.0, iter_limit=K, restarts=False, restart_avg=True)
+        cur = oracle.pdhg(lp, tol=-1.0, iter_limit=K, restarts=False)
+        e_avg = kkt_numpy(lp, r.x_avg, r.y_avg)["rel"]
+        e_cur = kkt_numpy(lp, cur.x, cur.y)["rel"]
+        earlier = [kkt_numpy(lp, s.x, s.y)["rel"] for s in
+                   (oracle.pdhg(lp, tol=-1.0, iter_limit=k, restarts=False, restart_avg=True)
+                    for k in range(0, K, 64))]
+        if e_avg < e_cur and e_avg < min(earlier):
+            tol = 0.5 * (e_avg + min(e_cur, min(earlier)))
+            t = oracle.pdhg(lp, tol=tol, iter_limit=10 * K, restarts=False, restart_avg=True)
+            assert t.status == oracle.OPTIMAL and t.iterations == K, (name, K, t.iterations)
+            assert rel_err(t.x, r.x_avg) <= 1e-14
+            p = oracle.pdhg(lp, tol=tol, iter_limit=K, restarts=False)
+            assert p.status != oracle.OPTIMAL
+            return
+    pytest.skip(f"{name}: no check where the mean wins first")

@@ -128,6 +128,20 @@ typedef struct {
                              optimality and infeasibility tests and before
                              the iteration limit.  0 = off (default)       */
     int32_t stall_checks; /* >= 1 checks in a row (3)                     */
+    int32_t restart_avg;  /* 1 = restart to the average (PDLP's restart
+                             candidates): the running mean of the iterates
+                             produced since the last restart (equal
+                             weights) is a candidate at every check; when
+                             its relative KKT error is below the current
+                             iterate's, that error drives the termination
+                             test, the restart rule and E_prev, a restart
+                             restarts to the mean, and an OPTIMAL or
+                             iteration-limit stop returns it (infeasibility
+                             and stalling look at the current iterate).
+                             Costs a read and a write of the mean per
+                             entry per pass and a second check; runs the
+                             per-pass path (no fused window).  0 = off
+                             (default)                                    */
 } scylla_params;
 
 enum {
@@ -254,6 +268,13 @@ int scylla_batch_solve(scylla_batch *h, const scylla_params *p, int32_t warm,
 /* Copies instance `inst`'s current iterate to host x[n_inst] / y[m_inst] as
  * FP64 (either may be NULL). */
 int scylla_batch_get_solution(scylla_batch *h, int32_t inst, double *x, double *y);
+
+/* Restart to the average (scylla_params.restart_avg): copies instance
+ * `inst`'s running mean of the iterates since its last restart, as it stood
+ * when the last solve stopped, to host x[n_inst] / y[m_inst] as FP64 (either
+ * may be NULL; meaningful once an iterate was produced since the last
+ * restart).  -EINVAL if no solve with restart_avg has run on the handle. */
+int scylla_batch_get_average(scylla_batch *h, int32_t inst, double *x, double *y);
 
 /* Copies the concatenated primal iterate of all instances (sum of n_inst
  * values, instance order) to host memory as FP64 in one transfer. */

@@ -135,6 +135,7 @@ struct OrientRT {
     size_t dshmem = 0;
     // plan buffers
     DevMem tiles, longs, seg, seg64, part, lpart;
+    DevMem part2, lpart2;  // check partials of the running average
     // adaptive-step partials: 2 doubles per epilogue slot; slot spaces of the
     // launches of the active layout start at these offsets
     DevMem ipart;
@@ -179,6 +180,8 @@ struct scylla_batch {
     DevMem xp, yp, axp, atyp;  // previous check's point and products
     bool has_q = false;
     bool adaptive = false;  // adaptive step sizes in the current graph
+    bool avg_on = false;    // restart to the average in the current graph
+    DevMem xavg, yavg, axavg;  // running means of x, y (and A x, adaptive)
     DevMem bits_tmp, ibits_tmp;
     DevMem mip_isint, mip_rbad, mip_cbad, mip_ok;  // MIP-feasibility check
     // graph
@@ -190,6 +193,7 @@ struct scylla_batch {
     size_t tiny_shmem = 0;
     bool graph_tiny = false;
     bool graph_adapt = false;
+    bool graph_avg = false;
     // host copy of the problem (for the pump's rounding on the host)
     std::vector<double> hval, hb, hl, hu, hc;
     std::vector<char> hsense;

@@ -89,6 +89,10 @@ struct PassArgs {
     // replaces them by the current ones
     V *own_prev;
     double *prod_prev;
+    // restart to the average: the running mean of the iterates since the
+    // last restart (x_avg in the column pass, y_avg in the row pass), or
+    // null; the epilogue folds every new iterate into it
+    V *avg;
 };
 
 // Step-size update after iteration jw of the window, one workgroup per
@@ -100,6 +104,11 @@ struct StepArgs {
     int32_t jw;
 };
 void launch_step(const StepArgs &a, int count, hipStream_t s);
+// Restart to the average: instances whose decision took the average copy it
+// over their iterate (and with adaptive steps its A x over the running one).
+template <class V>
+void launch_take_avg(InstState *st, const InstInfo *info, V *x, V *y, const V *xa, const V *ya, double *ax,
+                     const double *axa, int count, hipStream_t s);
 
 // LDS-staged pass: 1024 threads; variant v: nonzeros per thread per
 // sub-tile 4 (v = 0, 1) or 8 (v = 2, 3); odd v prefetch the next
@@ -147,6 +156,8 @@ struct DecideArgs {
     const InstInfo *info;
     const double *rpart, *lrpart, *cpart, *lcpart;
     int32_t R;
+    // check partials of the running averages (restart to the average), or null
+    const double *rpart2, *lrpart2, *cpart2, *lcpart2;
 };
 
 // One pass (or its FP64 check variant): the tile kernel, the long-row

@@ -216,9 +216,26 @@ __device__ __forceinline__ void load_ops(const PassArgs<V> &p, int i, RowOps<V> 
 // what the row pass gathers: the column pass stores dx = x+ - x in `bar`,
 // the row pass's sum is then (A dx)_i, and (A x_bar)_i = (A x)_i + 2 (A dx)_i
 // with the running FP64 (A x)_i.
+// Iterates in the running average of restart-to-average once this
+// iteration's is folded in (the iterates produced since the last restart),
+// or 0 without an average.
+template <class V>
+__device__ __forceinline__ V avg_count(const PassArgs<V> &p, const InstState &S, int jw)
+{
+    return p.avg ? (V)(S.k + jw + 1 - S.kr) : (V)0;
+}
+
+// Folds the new iterate value v of entry i into the running mean (the first
+// iterate after a restart starts it).
+template <class V>
+__device__ __forceinline__ void fold_avg(const PassArgs<V> &p, int i, V v, V acnt)
+{
+    if (acnt > (V)0) p.avg[i] = acnt == (V)1 ? v : p.avg[i] + (v - p.avg[i]) / acnt;
+}
+
 template <class V, int DIR>
 __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V step, bool copy_ref,
-                                          const RowOps<V> &o, double (&ip)[2])
+                                          const RowOps<V> &o, double (&ip)[2], V acnt)
 {
     if (DIR == DIR_COL) {
         V xn = o.own + step * o.diag2 * (sum - o.rhs);
@@ -228,6 +245,7 @@ __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V 
         if (copy_ref) p.own_ref[i] = o.own;
         p.bar[i] = p.adapt ? xn - o.own : (V)2 * xn - o.own;
         p.own[i] = xn;
+        fold_avg(p, i, xn, acnt);
         if (p.adapt) {
             const double d = (double)xn - (double)o.own;
             ip[0] += d * d / (double)o.diag2;
@@ -240,6 +258,7 @@ __device__ __forceinline__ void apply_ops(const PassArgs<V> &p, int i, V sum, V 
         else if (o.sense == 'L') v = v < (V)0 ? v : (V)0;
         if (copy_ref) p.own_ref[i] = o.own;
         p.own[i] = v;
+        fold_avg(p, i, v, acnt);
         if (p.adapt) {
             const double dy = (double)v - (double)o.own;
             ip[0] += dy * dy / (double)o.diag2;
@@ -273,6 +292,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    const V acnt = avg_count(p, S, jw);
     const int tid = threadIdx.x;
     const InstBounds<V> ib = inst_bounds<V, DIR>(p, T.z);
     if (T.w >= 0) {  // one segment of a long row: partial sum only
@@ -307,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_pass(const PassArgs<V> p, const int jw)
         V s = 0;
         for (int q = rb + lane; q < re; q += L) s += prod[q];
         if (L > 1) s = wave_sum_width(s, L);
-        if (lane == 0) apply_ops<V, DIR>(p, r0 + r, s, step, copy_ref, ops, ip);
+        if (lane == 0) apply_ops<V, DIR>(p, r0 + r, s, step, copy_ref, ops, ip, acnt);
         const int rn = r + groups;
         if (rn < nrows) {
             rb = p.M.ptr[r0 + rn] - e0;
@@ -414,7 +434,7 @@ __global__ __launch_bounds__(256) void k_bcombine(const PassArgs<V> p, const int
         V s = 0;
         const int nb = p.bq ? p.bq[T.z] : p.B;
         for (int b = 0; b < nb; ++b) s += p.P[(size_t)b * p.rows + i];
-        apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
+        apply_ops<V, DIR>(p, i, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip, avg_count(p, S, jw));
     }
     if (p.adapt) {
         block_sum2<256>(ip[0], ip[1], red2);
@@ -503,6 +523,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    const V acnt = avg_count(p, S, jw);
     const int tid = threadIdx.x;
     const InstBounds<V> ib = inst_bounds<V, DIR>(p, inst);
     MatView M = p.M;
@@ -613,7 +634,7 @@ __global__ __launch_bounds__(NT) void k_spass(const PassArgs<V> p, const int jw)
             if (Lc > 1) sum = wave_sum_width(sum, Lc);
             if (lane == 0) {
                 if (part) Ps[r0c + rc] = sum;
-                else apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc, ip);
+                else apply_ops<V, DIR>(p, r0c + rc, sum, step, copy_ref, opc, ip, acnt);
             }
             const int rn = rc + groups;
             if (rn < nrows) {
@@ -685,6 +706,7 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
     if (S.status != ST_RUN || jw >= S.nrun) return;
     const bool copy_ref = (jw == 0) && (S.restart_now != 0);
     const V step = DIR == DIR_COL ? (V)S.t : (V)S.s;
+    const V acnt = avg_count(p, S, jw);
     const InstBounds<V> ib = inst_bounds<V, DIR>(p, T.z);
     const int tid = threadIdx.x, L = T.w, lane = tid & (L - 1), groups = NT / L;
     const int g0 = p.gofs[T.z], glen = p.gofs[T.z + 1] - g0;
@@ -753,7 +775,7 @@ __global__ __launch_bounds__(NT) void k_dpass(const PassArgs<V> p, const int jw)
                 sum += direct_row_chunk<V, FMT, K>(p.M, sv, g0, b0[u] + c, b1[u], L);
             if (L > 1) sum = wave_sum_width(sum, L);
             const int r = base + u * groups;
-            if (lane == 0 && r < T.y) apply_ops<V, DIR>(p, r, sum, step, copy_ref, ops[u], ip);
+            if (lane == 0 && r < T.y) apply_ops<V, DIR>(p, r, sum, step, copy_ref, ops[u], ip, acnt);
         }
     }
     if (p.adapt) {
@@ -781,7 +803,7 @@ __global__ __launch_bounds__(256) void k_combine(const PassArgs<V> p, const int 
     RowOps<V> ops;
     load_ops<V, DIR>(p, L.x, ops, ib);
     double ip[2] = {0.0, 0.0};
-    apply_ops<V, DIR>(p, L.x, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip);
+    apply_ops<V, DIR>(p, L.x, s, DIR == DIR_COL ? (V)S.t : (V)S.s, copy_ref, ops, ip, avg_count(p, S, jw));
     if (p.adapt) {
         p.iplong[2 * q] = ip[0];
         p.iplong[2 * q + 1] = ip[1];
@@ -808,6 +830,8 @@ __device__ __forceinline__ void row_terms(const PassArgs<V> &p, int i, double ax
     q[1] += b * y;
     q[2] += dy * dy;
     // moves since the previous check: v = y - y_prev, A d = A x - (A x)_prev
+    // (the check of the running average has none)
+    if (!p.own_prev) return;
     const double v = y - (double)p.own_prev[i];
     const double vp = sn == 'G' ? fmax(v, 0.0) : (sn == 'L' ? fmin(v, 0.0) : v);
     const double ad = ax - p.prod_prev[i];
@@ -843,6 +867,8 @@ __device__ __forceinline__ void col_terms(const PassArgs<V> &p, int j, double at
     q[2] -= 0.5 * qx * x;
     q[3] += dx * dx;
     // moves since the previous check: A^T v = A^T y - (A^T y)_prev, d = x - x_prev
+    // (the check of the running average has none)
+    if (!p.own_prev) return;
     const double w = aty - p.prod_prev[j];
     double rl;
     if (lf && uf) rl = -w;
@@ -984,26 +1010,69 @@ __global__ __launch_bounds__(256) void k_bcombine_check(const PassArgs<V> p)
 // |A^T v + lam|^2, ray bound terms, c^T d, |bound violation of d|^2}.
 constexpr int NTOT = 14;
 
-__device__ void decide_state(InstState &S, const double tot[NTOT], int R)
+// Relative KKT error of a check's totals (Section 2.2): rho_p, rho_d,
+// rho_g, P, D and E = max of the three (NaN when one is not finite).
+struct Kkt {
+    double rho_p, rho_d, rho_g, P, D, E;
+};
+
+__device__ __forceinline__ Kkt kkt_of(const InstState &S, const double tot[NTOT])
+{
+    Kkt r;
+    r.rho_p = sqrt(tot[0]) / (1.0 + S.bnorm);
+    r.rho_d = sqrt(tot[3]) / (1.0 + S.cnorm);
+    r.P = tot[4];
+    r.D = tot[1] + tot[5];
+    r.rho_g = fabs(r.P - r.D) / (1.0 + fabs(r.P) + fabs(r.D));
+    r.E = fmax(r.rho_p, fmax(r.rho_d, r.rho_g));
+    if (!isfinite(r.rho_p) || !isfinite(r.rho_d) || !isfinite(r.rho_g)) r.E = NAN;
+    return r;
+}
+
+// The decision at a check.  totA: the totals of the running average
+// (restart to the average), or null.  The candidate is the average when
+// its error is below the current iterate's; its error drives termination,
+// the restart rule and E_prev, a restart or an OPTIMAL / iteration-limit
+// stop takes it (take_avg), and infeasibility and stalling look at the
+// current iterate.
+__device__ void decide_state(InstState &S, const double tot[NTOT], const double *totA, int R)
 {
     const int64_t k = S.k + S.nrun;
     S.k = k;
     S.nrun = 0;
     S.restart_now = 0;
-    const double rho_p = sqrt(tot[0]) / (1.0 + S.bnorm);
-    const double rho_d = sqrt(tot[3]) / (1.0 + S.cnorm);
-    const double P = tot[4], D = tot[1] + tot[5];
-    const double rho_g = fabs(P - D) / (1.0 + fabs(P) + fabs(D));
-    double E = fmax(rho_p, fmax(rho_d, rho_g));
-    if (!isfinite(rho_p) || !isfinite(rho_d) || !isfinite(rho_g)) E = NAN;
-    S.rho_p = rho_p;
-    S.rho_d = rho_d;
-    S.rho_g = rho_g;
-    S.pobj = P;
-    S.dobj = D;
+    S.take_avg = 0;
+    const Kkt cur = kkt_of(S, tot);
+    if (!isfinite(cur.E)) {
+        S.rho_p = cur.rho_p;
+        S.rho_d = cur.rho_d;
+        S.rho_g = cur.rho_g;
+        S.pobj = cur.P;
+        S.dobj = cur.D;
+        S.rel = cur.E;
+        S.status = ST_NUM;
+        return;
+    }
+    // the average exists once an iterate was produced since the last restart
+    bool use_avg = false;
+    Kkt avg = cur;
+    if (totA && S.avg_on && k > S.kr) {
+        avg = kkt_of(S, totA);
+        use_avg = avg.E < cur.E;
+    }
+    const Kkt &c = use_avg ? avg : cur;
+    const double E = c.E;
+    S.rho_p = c.rho_p;
+    S.rho_d = c.rho_d;
+    S.rho_g = c.rho_g;
+    S.pobj = c.P;
+    S.dobj = c.D;
     S.rel = E;
-    if (!isfinite(E)) { S.status = ST_NUM; return; }
-    if (E <= S.tol) { S.status = ST_OPT; return; }
+    if (E <= S.tol) {
+        S.take_avg = use_avg;
+        S.status = ST_OPT;
+        return;
+    }
     if (S.infeas_tol > 0.0 && k > 0) {
         // a dual ray certifies primal infeasibility, a primal ray dual
         // infeasibility (moves since the previous check)
@@ -1014,18 +1083,22 @@ __device__ void decide_state(InstState &S, const double tot[NTOT], int R)
     }
     if (S.stall_tol > 0.0) {
         // bounds stalling (Algorithm 1's inner-loop exit): neither objective
-        // bound moved by more than stall_tol (1 + |value|) since the previous
-        // check, stall_checks times in a row
+        // bound of the current iterate moved by more than stall_tol
+        // (1 + |value|) since the previous check, stall_checks times in a row
         if (k > 0) {
-            const bool moved = fabs(P - S.pprev) > S.stall_tol * (1.0 + fabs(P)) ||
-                               fabs(D - S.dprev) > S.stall_tol * (1.0 + fabs(D));
+            const bool moved = fabs(cur.P - S.pprev) > S.stall_tol * (1.0 + fabs(cur.P)) ||
+                               fabs(cur.D - S.dprev) > S.stall_tol * (1.0 + fabs(cur.D));
             S.nstall = moved ? 0 : S.nstall + 1;
             if (S.nstall >= S.stall_checks) { S.status = ST_STALL; return; }
         }
-        S.pprev = P;
-        S.dprev = D;
+        S.pprev = cur.P;
+        S.dprev = cur.D;
     }
-    if (k >= S.k_limit) { S.status = ST_ITER; return; }
+    if (k >= S.k_limit) {
+        S.take_avg = use_avg;
+        S.status = ST_ITER;
+        return;
+    }
     if (S.force_stop) { S.status = ST_TIME; return; }
     if (k == 0) {
         S.Er = E;
@@ -1035,7 +1108,9 @@ __device__ void decide_state(InstState &S, const double tot[NTOT], int R)
         const bool fire = (E <= 0.2 * S.Er) || (E <= 0.8 * S.Er && E > S.Ep) ||
                           ((double)(k - S.kr) >= 0.36 * (double)k);
         if (fire) {
-            const double dx = sqrt(tot[6]), dy = sqrt(tot[2]);
+            // distances of the candidate to the last restart point
+            const double *tc = use_avg ? totA : tot;
+            const double dx = sqrt(tc[6]), dy = sqrt(tc[2]);
             if (dx > 1e-10 && dy > 1e-10) {
                 S.omega = exp(0.5 * log(dy / dx) + 0.5 * log(S.omega));
                 S.t = S.eta / S.omega;
@@ -1045,6 +1120,7 @@ __device__ void decide_state(InstState &S, const double tot[NTOT], int R)
             S.kr = k;
             S.restarts += 1;
             S.restart_now = 1;
+            S.take_avg = use_avg;
         }
     }
     S.Ep = E;
@@ -1078,13 +1154,25 @@ __global__ __launch_bounds__(256) void k_decide(const DecideArgs d)
     for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256) row_add(d.lrpart + CHK * t);
     for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256) col_add(d.cpart + CHK * t);
     for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256) col_add(d.lcpart + CHK * t);
-    double tot[NTOT];
+    double tot[NTOT], tot2[NTOT];
     for (int k = 0; k < NTOT; ++k) {
         __syncthreads();
         tot[k] = block_sum<double, 256>(acc[k], red);
     }
+    if (d.rpart2) {
+        // the same reduction over the running average's check
+        for (int k = 0; k < NTOT; ++k) acc[k] = 0.0;
+        for (int t = I.rt0 + threadIdx.x; t < I.rt1; t += 256) row_add(d.rpart2 + CHK * t);
+        for (int t = I.lr0 + threadIdx.x; t < I.lr1; t += 256) row_add(d.lrpart2 + CHK * t);
+        for (int t = I.ct0 + threadIdx.x; t < I.ct1; t += 256) col_add(d.cpart2 + CHK * t);
+        for (int t = I.lc0 + threadIdx.x; t < I.lc1; t += 256) col_add(d.lcpart2 + CHK * t);
+        for (int k = 0; k < NTOT; ++k) {
+            __syncthreads();
+            tot2[k] = block_sum<double, 256>(acc[k], red);
+        }
+    }
     if (threadIdx.x != 0) return;
-    decide_state(S, tot, d.R);
+    decide_state(S, tot, d.rpart2 ? tot2 : nullptr, d.R);
 }
 
 // ------------------------------------------------------- adaptive steps
@@ -1327,7 +1415,7 @@ __global__ __launch_bounds__(1024) void k_tiny(const TinyArgs<V> a, const int R)
         tot[k] = block_sum<double, NT>(acc[k], red);
     }
     if (tid == 0) {
-        decide_state(S, tot, R);
+        decide_state(S, tot, nullptr, R);
         sh_nrun = S.status == ST_RUN ? S.nrun : 0;
         sh_restart = S.restart_now;
         sh_t = (V)S.t;
@@ -1430,6 +1518,26 @@ void launch_tiny(const TinyArgs<V> &a, int fmt, int count, int R, size_t shmem, 
         else if (fmt == FMT_BF16) run(k_tiny<V, FMT_BF16>);
         else run(k_tiny<V, FMT_F32>);
     }
+}
+
+// Restart to the average: one workgroup per instance copies the running
+// mean over the iterate where the decision took it (restart, OPTIMAL or
+// iteration-limit stop), then clears the flag.  The restart reference is
+// copied from the new iterate by the next iteration, as for any restart.
+template <class V>
+__global__ __launch_bounds__(256) void k_take_avg(InstState *st, const InstInfo *info, V *x, V *y, const V *xa,
+                                                  const V *ya, double *ax, const double *axa)
+{
+    const int inst = blockIdx.x;
+    if (!st[inst].take_avg) return;
+    const InstInfo I = info[inst];
+    for (int j = I.col0 + threadIdx.x; j < I.col1; j += 256) x[j] = xa[j];
+    for (int i = I.row0 + threadIdx.x; i < I.row1; i += 256) {
+        y[i] = ya[i];
+        if (ax) ax[i] = axa[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) st[inst].take_avg = 0;
 }
 
 __global__ void k_force_stop(InstState *st, int count)
@@ -1866,6 +1974,13 @@ void launch_decide(const DecideArgs &d, int count, hipStream_t s)
     hipLaunchKernelGGL(k_decide, dim3(count), dim3(256), 0, s, d);
 }
 
+template <class V>
+void launch_take_avg(InstState *st, const InstInfo *info, V *x, V *y, const V *xa, const V *ya, double *ax,
+                     const double *axa, int count, hipStream_t s)
+{
+    if (count > 0) hipLaunchKernelGGL(k_take_avg<V>, dim3(count), dim3(256), 0, s, st, info, x, y, xa, ya, ax, axa);
+}
+
 void launch_force_stop(InstState *st, int count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_force_stop, dim3((count + 255) / 256), dim3(256), 0, s, st, count);
@@ -1956,6 +2071,8 @@ void launch_mip_check(const MatView &M, int fmt, int m, int n, int count, const 
     template void launch_combine<V>(const PassArgs<V> &, int, int, hipStream_t);                       \
     template void launch_direct<V>(const PassArgs<V> &, int, int, int, int, size_t, hipStream_t, bool); \
     template void launch_finish_diag<V>(const double *, V *, int, hipStream_t);                        \
+    template void launch_take_avg<V>(InstState *, const InstInfo *, V *, V *, const V *, const V *,      \
+                                     double *, const double *, int, hipStream_t);                       \
     template void launch_cast<V>(const double *, V *, int, hipStream_t);                               \
     template void launch_project<V>(V *, const V *, const V *, int, int, V *, const uint8_t *, int, int, \
                                     int, hipStream_t);                                                 \

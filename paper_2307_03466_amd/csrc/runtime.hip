@@ -57,6 +57,7 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     }
     p.ipart = o.ipart.as<double>();
     p.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_long;
+    if (h->avg_on && !check) p.avg = o.row ? h->yavg.as<V>() : h->xavg.as<V>();
     if (o.sliced) {
         p.X = MatView{o.xptr.as<int32_t>(), o.xent.as<uint32_t>(), o.xval.p, o.host.shift, o.host.mask};
         p.xsub = o.xsub.as<int4>();
@@ -524,7 +525,35 @@ void enqueue_window(scylla_batch *h, int32_t R, bool tiny, hipStream_t s)
     launch_orient<V>(h, h->ocol, cc, 0, true, s);
     DecideArgs d{h->st.as<InstState>(), h->info.as<InstInfo>(), h->orow.part.as<double>(),
                  h->orow.lpart.as<double>(), h->ocol.part.as<double>(), h->ocol.lpart.as<double>(), R};
+    if (h->avg_on) {
+        // the same check of the running average (x_avg, y_avg), into its own
+        // partials, without the infeasibility terms
+        PassArgs<V> ra = rc, ca = cc;
+        ra.gvec = h->xavg.as<V>();
+        ra.own = h->yavg.as<V>();
+        ca.gvec = h->yavg.as<V>();
+        ca.own = h->xavg.as<V>();
+        for (PassArgs<V> *a : {&ra, &ca}) {
+            a->own_prev = nullptr;
+            a->prod_prev = nullptr;
+            a->ax = h->adaptive ? h->axavg.as<double>() : nullptr;
+        }
+        ra.part = h->orow.part2.as<double>();
+        ra.lpart = h->orow.lpart2.as<double>();
+        ca.part = h->ocol.part2.as<double>();
+        ca.lpart = h->ocol.lpart2.as<double>();
+        launch_orient<V>(h, h->orow, ra, 0, true, s);
+        launch_orient<V>(h, h->ocol, ca, 0, true, s);
+        d.rpart2 = ra.part;
+        d.lrpart2 = ra.lpart;
+        d.cpart2 = ca.part;
+        d.lcpart2 = ca.lpart;
+    }
     launch_decide(d, h->count, s);
+    if (h->avg_on)
+        launch_take_avg<V>(h->st.as<InstState>(), h->info.as<InstInfo>(), h->x.as<V>(), h->y.as<V>(),
+                           h->xavg.as<V>(), h->yavg.as<V>(), h->adaptive ? h->ax.as<double>() : nullptr,
+                           h->adaptive ? h->axavg.as<double>() : nullptr, h->count, s);
     const PassArgs<V> ri = orient_args<V>(h, h->orow, false), ci = orient_args<V>(h, h->ocol, false);
     for (int32_t j = 0; j < R; ++j) {
         launch_orient<V>(h, h->ocol, ci, j, false, s);
@@ -539,8 +568,17 @@ void enqueue_window(scylla_batch *h, int32_t R, bool tiny, hipStream_t s)
 
 void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
 {
-    if (h->gexec && h->graph_R == R && h->graph_tiny == tiny && h->graph_adapt == h->adaptive) return;
+    if (h->gexec && h->graph_R == R && h->graph_tiny == tiny && h->graph_adapt == h->adaptive &&
+        h->graph_avg == h->avg_on)
+        return;
     invalidate_graph(h);
+    if (h->avg_on && !tiny) {
+        // partials of the running average's check (allocated before capture)
+        for (OrientRT *o : {&h->orow, &h->ocol}) {
+            if (o->part2.bytes < o->part.bytes) o->part2.alloc(o->part.bytes);
+            if (o->lpart2.bytes < o->lpart.bytes) o->lpart2.alloc(o->lpart.bytes);
+        }
+    }
     hipGraph_t g = nullptr;
     HIPC(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     if (h->vbytes == 4) enqueue_window<float>(h, R, tiny, h->cap);
@@ -552,6 +590,7 @@ void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
     h->graph_R = R;
     h->graph_tiny = tiny;
     h->graph_adapt = h->adaptive;
+    h->graph_avg = h->avg_on;
 }
 
 // Scratch outputs and an always-running state so a pass can be launched on
@@ -598,6 +637,7 @@ struct PassTimer {
         for (PassArgs<V> *a : {&p, &q}) {
             a->st = trial_st.as<InstState>();
             a->bar = sbar.as<V>();
+            a->avg = nullptr;
         }
         p.own = o.row ? sy.as<V>() : sx.as<V>();
         q.own = w.row ? sy.as<V>() : sx.as<V>();
@@ -992,6 +1032,7 @@ int validate_params(const scylla_params *p)
     if (!(p->eta > 0.0 && p->eta < 1.0)) throw_err(-EINVAL, "eta must be in (0, 1)");
     if (p->precision != SCYLLA_FP32 && p->precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
     if (p->adaptive != 0 && p->adaptive != 1) throw_err(-EINVAL, "adaptive must be 0 or 1");
+    if (p->restart_avg != 0 && p->restart_avg != 1) throw_err(-EINVAL, "restart_avg must be 0 or 1");
     if (!(p->infeas_tol >= 0.0) || !isfinite(p->infeas_tol)) throw_err(-EINVAL, "infeas_tol must be finite and >= 0");
     if (!(p->stall_tol >= 0.0) || !isfinite(p->stall_tol)) throw_err(-EINVAL, "stall_tol must be finite and >= 0");
     if (p->stall_tol > 0.0 && p->stall_checks < 1) throw_err(-EINVAL, "stall_checks must be >= 1");
@@ -1053,8 +1094,18 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     if (!h || !results) throw_err(-EINVAL, "handle or results is NULL");
     validate_params(p);
     if (p->precision != h->precision) throw_err(-EINVAL, "params precision differs from the handle's");
-    const bool tiny = h->tiny_ok && p->fused_window != 0;
+    // the fused window has no running average: restart to the average takes
+    // the per-pass path
+    const bool tiny = h->tiny_ok && p->fused_window != 0 && p->restart_avg == 0;
     h->adaptive = p->adaptive != 0;
+    h->avg_on = p->restart_avg != 0;
+    if (h->avg_on) {
+        const size_t vb = (size_t)h->vbytes;
+        if (h->xavg.bytes < (size_t)std::max(h->N, 1) * vb) h->xavg.alloc((size_t)std::max(h->N, 1) * vb);
+        if (h->yavg.bytes < (size_t)std::max(h->M, 1) * vb) h->yavg.alloc((size_t)std::max(h->M, 1) * vb);
+        if (h->adaptive && h->axavg.bytes < (size_t)std::max(h->M, 1) * 8)
+            h->axavg.alloc((size_t)std::max(h->M, 1) * 8);
+    }
     double tune_s = 0.0;
     if (p->autotune && !h->tuned && !tiny) {
         const double tt = now_s();
@@ -1076,6 +1127,8 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
         S.restarts = 0;
         S.restart_now = 0;
         S.restart_on = p->restarts ? 1 : 0;
+        S.avg_on = p->restart_avg ? 1 : 0;
+        S.take_avg = 0;
         S.force_stop = 0;
         S.k = 0;
         S.k_limit = k_limits ? std::min<int64_t>(k_limits[q], p->iter_limit) : p->iter_limit;
@@ -1183,6 +1236,7 @@ int scylla_params_default(scylla_params *p)
     p->infeas_tol = 1e-8;
     p->stall_tol = 0.0;
     p->stall_checks = 3;
+    p->restart_avg = 0;
     return 0;
 }
 
@@ -1428,6 +1482,24 @@ int scylla_batch_get_solution(scylla_batch *h, int32_t inst, double *x, double *
         } else {
             get_range<double>(h, h->x, clo, clen, x);
             get_range<double>(h, h->y, rlo, rlen, y);
+        }
+        return 0;
+    });
+}
+
+int scylla_batch_get_average(scylla_batch *h, int32_t inst, double *x, double *y)
+{
+    return guarded([&]() {
+        check_inst(h, inst);
+        if (!h->xavg.p || !h->yavg.p) throw_err(-EINVAL, "no solve with restart_avg has run on this handle");
+        const int32_t clo = h->col_off[inst], clen = h->col_off[inst + 1] - clo;
+        const int32_t rlo = h->row_off[inst], rlen = h->row_off[inst + 1] - rlo;
+        if (h->vbytes == 4) {
+            get_range<float>(h, h->xavg, clo, clen, x);
+            get_range<float>(h, h->yavg, rlo, rlen, y);
+        } else {
+            get_range<double>(h, h->xavg, clo, clen, x);
+            get_range<double>(h, h->yavg, rlo, rlen, y);
         }
         return 0;
     });

@@ -41,7 +41,10 @@ struct InstState {
                           //    first iteration of the window
     int32_t restart_on;   // restart scheme enabled
     int32_t force_stop;   // host-requested stop (time limit)
-    int32_t pad0, pad1;
+    int32_t avg_on;       // restart to the average: the running mean of the
+                          //    iterates since the last restart is a candidate
+    int32_t take_avg;     // 1: replace the iterate by that mean before the
+                          //    next iteration (set by the decision)
     int64_t k;            // iterations done at the last check
     int64_t k_limit;      // iteration limit of this call
     int64_t kr;           // iteration of the last restart

@@ -30,7 +30,7 @@ EXPORTS = [
     "scylla_fix_propagate", "scylla_batch_pump",
     "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
     "scylla_batch_mip_feasible", "scylla_batch_fix_propagate", "scylla_batch_mip_feasible_static",
-    "scylla_batch_set_start_device",
+    "scylla_batch_set_start_device", "scylla_batch_get_average",
 ]
 
 
@@ -57,7 +57,7 @@ class Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
                 ("fused_window", ctypes.c_int32), ("adaptive", ctypes.c_int32),
                 ("infeas_tol", ctypes.c_double), ("stall_tol", ctypes.c_double),
-                ("stall_checks", ctypes.c_int32)]
+                ("stall_checks", ctypes.c_int32), ("restart_avg", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -115,6 +115,7 @@ def lib():
             "scylla_batch_set_start_device": ([vp, vp, vp, vp], ctypes.c_int),
             "scylla_batch_solve": ([vp, ctypes.POINTER(Params), i32, ctypes.POINTER(Result)], ctypes.c_int),
             "scylla_batch_get_solution": ([vp, i32, vp, vp], ctypes.c_int),
+            "scylla_batch_get_average": ([vp, i32, vp, vp], ctypes.c_int),
             "scylla_batch_get_x_all": ([vp, vp], ctypes.c_int),
             "scylla_batch_device_iterates": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                               ctypes.POINTER(i32)], ctypes.c_int),
@@ -306,6 +307,14 @@ class Batch:
         x = np.empty(self.n[inst])
         y = np.empty(max(self.m[inst], 1))
         _check(lib().scylla_batch_get_solution(self._h, inst, _ptr(x), _ptr(y)))
+        return x, y[: self.m[inst]]
+
+    def average(self, inst: int = 0):
+        """Running means of x and y since instance `inst`'s last restart
+        (solves with restart_avg=1)."""
+        x = np.empty(self.n[inst])
+        y = np.empty(max(self.m[inst], 1))
+        _check(lib().scylla_batch_get_average(self._h, inst, _ptr(x), _ptr(y)))
         return x, y[: self.m[inst]]
 
     def x_all(self) -> np.ndarray:

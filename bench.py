@@ -154,11 +154,11 @@ def probe_gather_ms(vec_bytes, gathers):
     return ms.value
 
 
-def timed_steps(batch, steps, R):
+def timed_steps(batch, steps, R, **kw):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = batch.solve(tol=1e-300, iter_limit=steps * R, check_period=R)
+    res = batch.solve(tol=1e-300, iter_limit=steps * R, check_period=R, **kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert all(r["iterations"] == steps * R for r in res), res[0]
@@ -183,8 +183,17 @@ def measure(pdhg, lps, prec, steps, warmup, R, to_tol, tol_time_limit, passes=Tr
         rb, cb = pass_bytes(info, 4 if prec == pdhg.FP32 else 8)
         rec.update(ms_row=ms_row, ms_col=ms_col, bytes_row=rb, bytes_col=cb)
     if to_tol:
-        for key, adaptive in (("to_tol", 0), ("to_tol_adaptive", 1)):
-            res = b.solve(tol=1e-4, iter_limit=2_000_000, time_limit_s=tol_time_limit, adaptive=adaptive)
+        # the iteration rate with restarts to the average (the means folded in
+        # by every pass, a second check per window)
+        b.solve(tol=1e-300, iter_limit=R, check_period=R, restart_avg=1)
+        dt_avg, _ = timed_steps(b, steps, R, restart_avg=1)
+        rec["iter_per_s_avg"] = its / dt_avg
+        # constant and adaptive steps, each without and with restarts to the
+        # average
+        for key, adaptive, avg in (("to_tol", 0, 0), ("to_tol_adaptive", 1, 0), ("to_tol_avg", 0, 1),
+                                   ("to_tol_avg_adaptive", 1, 1)):
+            res = b.solve(tol=1e-4, iter_limit=2_000_000, time_limit_s=tol_time_limit, adaptive=adaptive,
+                          restart_avg=avg)
             rec[key] = dict(status=max(r["status"] for r in res), optimal=sum(r["status"] == 1 for r in res),
                             count=len(res), iterations_max=max(r["iterations"] for r in res),
                             iterations_sum=sum(r["iterations"] for r in res),
@@ -327,6 +336,8 @@ def other_workloads(pdhg, instances, args, R):
                                              canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 2),
                                              to_tol=r.get("to_tol"),
                                              to_tol_adaptive_steps=r.get("to_tol_adaptive"),
+                                             to_tol_restart_avg=r.get("to_tol_avg"),
+                                             to_tol_restart_avg_adaptive_steps=r.get("to_tol_avg_adaptive"),
                                              rounding_s=round(time.perf_counter() - t, 6),
                                              rounding_feasible=feas, rounded_obj=float(lp.c @ xh))
         log(f"w1: {r['iter_per_s']:,.0f} iter/s to_tol={r.get('to_tol')} adaptive={r.get('to_tol_adaptive')} "
@@ -345,6 +356,9 @@ def other_workloads(pdhg, instances, args, R):
                             canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
                             to_tol=r.get("to_tol"),
                             to_tol_adaptive_steps=r.get("to_tol_adaptive"),
+                            to_tol_restart_avg=r.get("to_tol_avg"),
+                            to_tol_restart_avg_adaptive_steps=r.get("to_tol_avg_adaptive"),
+                            iter_per_s_restart_avg=round(r["iter_per_s_avg"], 1) if "iter_per_s_avg" in r else None,
                             layout=[r["info"]["row_blocks"], r["info"]["row_chunk"], r["info"]["col_blocks"],
                                     r["info"]["col_chunk"]], long_rows=r["info"]["long_rows"])
             log(f"w3 {tag}: {r['iter_per_s']:,.0f} iter/s to_tol={r.get('to_tol')} adaptive={r.get('to_tol_adaptive')}")
@@ -356,7 +370,11 @@ def other_workloads(pdhg, instances, args, R):
         rec = dict(count=len(lps), batch_iter_per_s=round(r["iter_per_s"], 1),
                    instance_iter_per_s=round(r["iter_per_s"] * len(lps), 1), ms_row=round(r["ms_row"], 4),
                    ms_col=round(r["ms_col"], 4), to_tol_fp32_batched=r.get("to_tol"),
-                   to_tol_fp32_batched_adaptive_steps=r.get("to_tol_adaptive"), setup_seconds=round(r["setup_s"], 3),
+                   to_tol_fp32_batched_adaptive_steps=r.get("to_tol_adaptive"),
+                   to_tol_fp32_batched_restart_avg=r.get("to_tol_avg"),
+                   to_tol_fp32_batched_restart_avg_adaptive_steps=r.get("to_tol_avg_adaptive"),
+                   batch_iter_per_s_restart_avg=round(r["iter_per_s_avg"], 1) if "iter_per_s_avg" in r else None,
+                   setup_seconds=round(r["setup_s"], 3),
                    canonical_bytes_per_iter=r["canon_iter"],
                    canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
                    row_canonical_GBps=round(r["canon_row"] / r["ms_row"] / 1e6, 1),
@@ -387,9 +405,11 @@ def other_workloads(pdhg, instances, args, R):
                 rec["speedup_fp32_batched_vs_fp64_plain_to_tol"] = round(solve_s / r["to_tol"]["seconds"], 2)
                 rec["speedup_fp32_batched_vs_fp64_plain_to_tol_with_setup"] = round(
                     (solve_s + setup_s) / (r["to_tol"]["seconds"] + r["setup_s"]), 2)
-                if r["to_tol_adaptive"]["optimal"] == len(lps):
-                    rec["speedup_fp32_batched_adaptive_vs_fp64_plain_to_tol"] = round(
-                        solve_s / r["to_tol_adaptive"]["seconds"], 2)
+                for key, name in (("to_tol_adaptive", "adaptive"), ("to_tol_avg", "restart_avg"),
+                                  ("to_tol_avg_adaptive", "restart_avg_adaptive")):
+                    if r[key]["optimal"] == len(lps):
+                        rec[f"speedup_fp32_batched_{name}_vs_fp64_plain_to_tol"] = round(
+                            solve_s / r[key]["seconds"], 2)
             log(f"w4 fp64 plain sequential: {n_done} instances, {solve_s:.2f} s solving + {setup_s:.2f} s setup")
         out["batch_256_uneven"] = rec
         del lps
@@ -517,6 +537,8 @@ def main():
         if args.to_tol:
             log(f"{tag}: to 1e-4: {rec['to_tol']}")
             log(f"{tag}: to 1e-4 with adaptive steps: {rec['to_tol_adaptive']}")
+            log(f"{tag}: {rec['iter_per_s_avg']:,.0f} iter/s with restarts to the average; to 1e-4: "
+                f"{rec['to_tol_avg']}; with adaptive steps too: {rec['to_tol_avg_adaptive']}")
         out[tag] = rec
 
     if "fp32" not in out or "fp64" not in out:
@@ -594,12 +616,19 @@ def main():
                        "ms_row": round(out["fp64"]["ms_row"], 5), "ms_col": round(out["fp64"]["ms_col"], 5),
                        "canonical_GBps": round(out["fp64"]["canon_iter"] * out["fp64"]["iter_per_s"] / 1e9, 1)},
         "speedup_fp32_vs_fp64_iter": round(f32["iter_per_s"] / out["fp64"]["iter_per_s"], 3),
+        "iter_per_s_restart_avg": ({"fp32": round(f32["iter_per_s_avg"], 1),
+                                    "fp64": round(out["fp64"]["iter_per_s_avg"], 1)}
+                                   if "iter_per_s_avg" in f32 else None),
         "setup_seconds": {"fp32": round(f32["setup_s"], 3), "fp64": round(out["fp64"]["setup_s"], 3)},
     }
     if args.to_tol:
         line["to_tol_1e-4"] = {"fp32": out["fp32"]["to_tol"], "fp64": out["fp64"]["to_tol"],
                                "fp32_adaptive_steps": out["fp32"]["to_tol_adaptive"],
-                               "fp64_adaptive_steps": out["fp64"]["to_tol_adaptive"]}
+                               "fp64_adaptive_steps": out["fp64"]["to_tol_adaptive"],
+                               "fp32_restart_avg": out["fp32"]["to_tol_avg"],
+                               "fp64_restart_avg": out["fp64"]["to_tol_avg"],
+                               "fp32_restart_avg_adaptive_steps": out["fp32"]["to_tol_avg_adaptive"],
+                               "fp64_restart_avg_adaptive_steps": out["fp64"]["to_tol_avg_adaptive"]}
         if out["fp32"]["to_tol"]["status"] == 1 and out["fp64"]["to_tol"]["status"] == 1:
             line["speedup_fp32_vs_fp64_to_tol"] = round(out["fp64"]["to_tol"]["seconds"]
                                                         / out["fp32"]["to_tol"]["seconds"], 3)

@@ -460,6 +460,18 @@ def other_workloads(pdhg, instances, args, R):
             perturbations=sum(o["perturbations"] for o in outs),
             pdhg_iterations_total=sum(o["iterations"] for o in outs),
             seconds_two_groups=round(el1, 3), same_result_two_groups=same)
+        # the same loop with restarts to the average and adaptive steps in
+        # every round's solve
+        for key, kw in (("restart_avg", dict(restart_avg=1)),
+                        ("restart_avg_adaptive_steps", dict(restart_avg=1, adaptive=1))):
+            t = time.perf_counter()
+            recs2, outs2, _ = b.pump_ex(pump=dict(rounds=args.pump_rounds, seed=0), iter_limit=200_000, **kw)
+            el2 = time.perf_counter() - t
+            found2 = [o for o in outs2 if o["found_kind"]]
+            out["scylla_loop_64x20k"][key] = dict(
+                seconds=round(el2, 3), found=len(found2),
+                mean_found_round=round(sum(o["found_round"] for o in found2) / max(1, len(found2)), 2),
+                pdhg_iterations_total=sum(o["iterations"] for o in outs2))
         log(f"w5 complete loop: {out['scylla_loop_64x20k']}")
         b.close()
     if "6" in sel:  # complete loop with the L2 distance on general integers

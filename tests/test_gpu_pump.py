@@ -146,6 +146,19 @@ def test_full_loop_matches_oracle_fp64():
     assert any(o["perturbations"] for o in outs) and any(o["found_kind"] == 2 for o in outs)
 
 
+def test_full_loop_with_restart_to_average_matches_oracle_fp64():
+    """The closed loop with restarts to the average in every round's solve:
+    the same finds, rounds and perturbations as the oracle's loop with the
+    same option.  (With adaptive steps as well the rounds' iterates move
+    apart by more than rounding -- that rule is not nonexpansive -- so
+    only the constant-step loop is compared decision for decision.)"""
+    lps = _loop_batch()
+    ref = _oracle_loop(lps, rounds=20, seed=5, restart_avg=True)
+    with pdhg.Batch(lps, precision=0) as b:
+        recs, outs, xo = b.pump_ex(pump=dict(rounds=20, seed=5), restart_avg=1)
+    _compare_loop(lps, recs, outs, xo, ref)
+
+
 @pytest.mark.parametrize("K", [1, 4])
 def test_full_loop_with_device_rounding_matches_oracle_fp64(K):
     """The closed loop with the batched rounding on the device: the same

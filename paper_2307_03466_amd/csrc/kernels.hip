@@ -18,7 +18,10 @@
 // Every R iterations a check (FP64 accumulation) evaluates the relative KKT
 // errors of Section 2.2 and the restart quantities; a one-workgroup-per-
 // instance decision kernel reduces them in a fixed order and sets status,
-// restart and step sizes in FP64 on the device.
+// restart and step sizes in FP64 on the device.  With restarts to the
+// average the epilogues also fold every iterate into running means, a
+// second check evaluates the means, and the decision takes the better of
+// the two points.
 #include <hip/hip_runtime.h>
 #include <math.h>
 

@@ -142,6 +142,12 @@ typedef struct {
                              entry per pass and a second check; runs the
                              per-pass path (no fused window).  0 = off
                              (default)                                    */
+    int32_t compact;      /* 1 (default): in a batch, once at most half of
+                             the tiles the iteration launches run belong to
+                             instances still running, the launches are
+                             rebuilt over those tiles only (finished
+                             instances then cost nothing per iteration;
+                             results are unchanged bit for bit).  0 = off */
 } scylla_params;
 
 enum {

@@ -124,6 +124,7 @@ struct OrientRT {
     SlicedPlan xplan;
     int32_t x_max_vec = -1, x_sub = -1;
     DevMem xptr, xent, xval, xsub, xctiles, xP, xsq;
+    std::vector<int32_t> stiles_h;  // host copy of stiles
     // direct staged layout (when chosen): the whole gathered vector of each
     // qualifying instance in LDS, rows reduced in registers; normal tiles
     // (splan.rest) for the other instances
@@ -140,6 +141,13 @@ struct OrientRT {
     // launches of the active layout start at these offsets
     DevMem ipart;
     int32_t ipo_long = 0, ipo_comb = 0, ipo_rest = 0, ipo_rlong = 0, ip_slots = 0;
+    // compacted tile lists of the iteration launches (the tiles of running
+    // instances only, in the original order; the check launches keep the
+    // full lists) and the epilogue slot offsets that go with them
+    bool cmp = false;
+    DevMem c_tiles, c_stiles, c_xctiles, c_rtiles, c_dtiles;
+    std::vector<int32_t> c_tiles_h, c_stiles_h, c_xctiles_h, c_rtiles_h, c_dtiles_h;
+    int32_t cipo_long = 0, cipo_comb = 0, cipo_rest = 0, cipo_rlong = 0;
     int32_t ntiles() const { return (int32_t)((blocked ? bplan.tiles.size() : plan.tiles.size()) / 4); }
     int32_t nlong() const { return (int32_t)((blocked ? bplan.longs.size() : plan.longs.size()) / 4); }
 };
@@ -186,6 +194,14 @@ struct scylla_batch {
     DevMem mip_isint, mip_rbad, mip_cbad, mip_ok;  // MIP-feasibility check
     // graph
     hipGraphExec_t gexec = nullptr;
+    // window graph over the compacted tile lists, and earlier ones of the
+    // same solve (destroyed once the stream has drained)
+    hipGraphExec_t cexec = nullptr;
+    std::vector<hipGraphExec_t> retired;
+    int64_t graph_tiles = 0;          // tiles of the current graph's iteration launches
+    std::vector<InstInfo> hinfo_c;    // instance info with the compacted slot ranges
+    void *cstage = nullptr;           // pinned staging of the cut lists
+    size_t cstage_bytes = 0;
     int32_t graph_R = 0;
     bool tuned = false;
     int32_t lds_max = 65536;  // dynamic LDS bytes a workgroup may use
@@ -214,7 +230,10 @@ struct scylla_batch {
     ~scylla_batch()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cexec) (void)hipGraphExecDestroy(cexec);
+        for (hipGraphExec_t g : retired) (void)hipGraphExecDestroy(g);
         if (pinned) (void)hipHostFree(pinned);
+        if (cstage) (void)hipHostFree(cstage);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         if (cap) (void)hipStreamDestroy(cap);

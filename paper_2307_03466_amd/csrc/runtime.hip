@@ -58,6 +58,11 @@ PassArgs<V> orient_args(scylla_batch *h, OrientRT &o, bool check)
     p.ipart = o.ipart.as<double>();
     p.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_long;
     if (h->avg_on && !check) p.avg = o.row ? h->yavg.as<V>() : h->xavg.as<V>();
+    if (o.cmp && !check && !o.blocked) {
+        p.tiles = o.c_tiles.as<int4>();
+        p.ntiles = (int32_t)(o.c_tiles_h.size() / 4);
+        p.iplong = o.ipart.as<double>() + 2 * (size_t)o.cipo_long;
+    }
     if (o.sliced) {
         p.X = MatView{o.xptr.as<int32_t>(), o.xent.as<uint32_t>(), o.xval.p, o.host.shift, o.host.mask};
         p.xsub = o.xsub.as<int4>();
@@ -134,6 +139,7 @@ void set_plan(scylla_batch *h, OrientRT &o, int32_t B, int32_t ept)
     o.staged = false;
     o.sliced = false;
     o.direct = false;
+    o.cmp = false;
     if (B > 0) {
         if (!o.blocked || o.bh.B != B) {
             build_blocked(o.host, h->fmt, o.gather, B, o.bh);
@@ -249,6 +255,7 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
         plan_tiles(o.host.ptr, off, 256 * std::abs(ept), 1024, o.splan.rest, skip.data());
     }
     upload(o.stiles, tiles, h->stream);
+    o.stiles_h = tiles;
     upload(o.subtiles, o.splan.sub.tiles, h->stream);
     upload(o.gofs, gofs, h->stream);
     upload(o.rtiles, o.splan.rest.tiles, h->stream);
@@ -411,19 +418,22 @@ template <class V>
 void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, bool check, hipStream_t s)
 {
     const int dir = o.row ? DIR_ROW : DIR_COL;
+    // iteration launches take the compacted tile lists when there are any
+    const bool cmp = o.cmp && !check;
+    auto n4 = [](const std::vector<int32_t> &v) { return (int32_t)(v.size() / 4); };
     if (o.direct && !check) {
         PassArgs<V> pd = p;
-        pd.dtiles = o.dtiles.as<int4>();
-        pd.ndtiles = o.nstiles;
+        pd.dtiles = cmp ? o.c_dtiles.as<int4>() : o.dtiles.as<int4>();
+        pd.ndtiles = cmp ? n4(o.c_dtiles_h) : o.nstiles;
         pd.gofs = o.gofs.as<int32_t>();
         PassArgs<V> pr = p;  // normal tiles of the other instances
-        pr.tiles = o.rtiles.as<int4>();
-        pr.ntiles = (int32_t)(o.splan.rest.tiles.size() / 4);
+        pr.tiles = cmp ? o.c_rtiles.as<int4>() : o.rtiles.as<int4>();
+        pr.ntiles = cmp ? n4(o.c_rtiles_h) : n4(o.splan.rest.tiles);
         pr.longs = o.rlongs.as<int4>();
         pr.nlong = (int32_t)(o.splan.rest.longs.size() / 4);
         pr.seg = o.rseg.as<V>();
-        pr.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_rest;
-        pr.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_rlong;
+        pr.ipart = o.ipart.as<double>() + 2 * (size_t)(cmp ? o.cipo_rest : o.ipo_rest);
+        pr.iplong = o.ipart.as<double>() + 2 * (size_t)(cmp ? o.cipo_rlong : o.ipo_rlong);
         const bool fork = pr.ntiles > 0 || pr.nlong > 0;
         if (fork) {
             HIPC(hipEventRecord(h->fork, s));
@@ -437,27 +447,27 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
     }
     if (o.staged && !check) {
         PassArgs<V> ps = p;
-        ps.tiles = o.stiles.as<int4>();
-        ps.ntiles = o.nstiles;
+        ps.tiles = cmp ? o.c_stiles.as<int4>() : o.stiles.as<int4>();
+        ps.ntiles = cmp ? n4(o.c_stiles_h) : o.nstiles;
         ps.gofs = o.gofs.as<int32_t>();
         ps.sub = o.subtiles.as<int4>();
         PassArgs<V> pc = ps;  // row combine of the sliced instances
         if (o.sliced) {
-            pc.ctiles = o.xctiles.as<int4>();
-            pc.nctiles = (int32_t)(o.xplan.ctiles.size() / 4);
+            pc.ctiles = cmp ? o.c_xctiles.as<int4>() : o.xctiles.as<int4>();
+            pc.nctiles = cmp ? n4(o.c_xctiles_h) : n4(o.xplan.ctiles);
             pc.B = o.xplan.S;
             pc.bq = o.xsq.as<int32_t>();
             pc.P = o.xP.as<V>();
-            pc.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_comb;
+            pc.ipart = o.ipart.as<double>() + 2 * (size_t)(cmp ? o.cipo_comb : o.ipo_comb);
         }
         PassArgs<V> pr = p;
-        pr.tiles = o.rtiles.as<int4>();
-        pr.ntiles = (int32_t)(o.splan.rest.tiles.size() / 4);
+        pr.tiles = cmp ? o.c_rtiles.as<int4>() : o.rtiles.as<int4>();
+        pr.ntiles = cmp ? n4(o.c_rtiles_h) : n4(o.splan.rest.tiles);
         pr.longs = o.rlongs.as<int4>();
         pr.nlong = (int32_t)(o.splan.rest.longs.size() / 4);
         pr.seg = o.rseg.as<V>();
-        pr.ipart = o.ipart.as<double>() + 2 * (size_t)o.ipo_rest;
-        pr.iplong = o.ipart.as<double>() + 2 * (size_t)o.ipo_rlong;
+        pr.ipart = o.ipart.as<double>() + 2 * (size_t)(cmp ? o.cipo_rest : o.ipo_rest);
+        pr.iplong = o.ipart.as<double>() + 2 * (size_t)(cmp ? o.cipo_rlong : o.ipo_rlong);
         const bool fork = pr.ntiles > 0 || pr.nlong > 0;
         // the kinds of tiles touch disjoint instances: run the normal tiles
         // as a second branch (fork on s, side stream, join)
@@ -566,6 +576,22 @@ void enqueue_window(scylla_batch *h, int32_t R, bool tiny, hipStream_t s)
     }
 }
 
+// Captures and instantiates one check window of R iterations with the
+// current tile lists.
+hipGraphExec_t capture_window(scylla_batch *h, int32_t R, bool tiny)
+{
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    HIPC(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    if (h->vbytes == 4) enqueue_window<float>(h, R, tiny, h->cap);
+    else enqueue_window<double>(h, R, tiny, h->cap);
+    HIPC(hipStreamEndCapture(h->cap, &g));
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPC(e);
+    return ex;
+}
+
 void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
 {
     if (h->gexec && h->graph_R == R && h->graph_tiny == tiny && h->graph_adapt == h->adaptive &&
@@ -579,18 +605,206 @@ void ensure_graph(scylla_batch *h, int32_t R, bool tiny)
             if (o->lpart2.bytes < o->lpart.bytes) o->lpart2.alloc(o->lpart.bytes);
         }
     }
-    hipGraph_t g = nullptr;
-    HIPC(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    if (h->vbytes == 4) enqueue_window<float>(h, R, tiny, h->cap);
-    else enqueue_window<double>(h, R, tiny, h->cap);
-    HIPC(hipStreamEndCapture(h->cap, &g));
-    hipError_t e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HIPC(e);
+    h->gexec = capture_window(h, R, tiny);
     h->graph_R = R;
     h->graph_tiny = tiny;
     h->graph_adapt = h->adaptive;
     h->graph_avg = h->avg_on;
+}
+
+// ---- finished instances out of the iteration launches
+//
+// A finished instance's workgroups still start, read their tile and the
+// instance state, and exit; late in a batched solve that costs more than
+// the running instances' work.  When the tiles of the running instances
+// fall to half of those the window graph launches, the tile lists of the
+// iteration launches are cut to the running instances (in their order, so
+// every result is unchanged bit for bit), the adaptive-step slot ranges are
+// renumbered to match, and a window graph over the cut lists takes over.
+// The copies are ordered on the stream behind the windows in flight; an
+// instance that stops never runs again within a solve, so lists cut from an
+// earlier state hold every tile that can still run.  The check launches
+// keep the full lists (once per window).  Gather-blocked orientations (one
+// large instance) are not cut.
+
+// Tiles of the iteration launches of o: all (run = NULL), or those of the
+// instances with run[q] set.
+static int64_t iter_tiles(const OrientRT &o, const uint8_t *run)
+{
+    if (o.blocked) return 0;
+    auto cnt = [&](const std::vector<int32_t> &t) {
+        int64_t n = 0;
+        for (size_t i = 2; i < t.size(); i += 4) n += (!run || run[t[i] & 0xffffff]) ? 1 : 0;
+        return n;
+    };
+    if (o.direct) return cnt(o.dtiles_h) + cnt(o.splan.rest.tiles);
+    if (o.staged) return cnt(o.stiles_h) + (o.sliced ? cnt(o.xplan.ctiles) : 0) + cnt(o.splan.rest.tiles);
+    return cnt(o.plan.tiles);
+}
+
+// The tiles (4 ints, instance in the low 24 bits of the third) of the
+// instances with run[q] set, in order; [a[q], b[q]) is instance q's range
+// in the kept list (empty when it has none).
+static void keep_tiles(const std::vector<int32_t> &t, const uint8_t *run, std::vector<int32_t> &out,
+                       std::vector<int32_t> &a, std::vector<int32_t> &b)
+{
+    out.clear();
+    std::fill(a.begin(), a.end(), -1);
+    std::fill(b.begin(), b.end(), 0);
+    for (size_t i = 0; i + 3 < t.size(); i += 4) {
+        const int32_t q = t[i + 2] & 0xffffff;
+        if (!run[q]) continue;
+        const int32_t k = (int32_t)(out.size() / 4);
+        if (a[q] < 0) a[q] = k;
+        b[q] = k + 1;
+        out.insert(out.end(), t.begin() + i, t.begin() + i + 4);
+    }
+    for (size_t q = 0; q < a.size(); ++q)
+        if (a[q] < 0) a[q] = 0;
+}
+
+// Cuts the iteration lists of orientation d and writes its slot ranges into
+// h->hinfo_c (which starts as a copy of h->hinfo).
+static void cut_orient(scylla_batch *h, OrientRT &o, int d, const uint8_t *run)
+{
+    if (o.blocked) return;
+    const int32_t count = h->count;
+    auto n4 = [](const std::vector<int32_t> &v) { return (int32_t)(v.size() / 4); };
+    std::vector<int32_t> a1(count), b1(count), a2(count), b2(count), a3(count), b3(count);
+    o.c_tiles_h.clear();
+    o.c_stiles_h.clear();
+    o.c_xctiles_h.clear();
+    o.c_rtiles_h.clear();
+    o.c_dtiles_h.clear();
+    if (o.direct) {
+        keep_tiles(o.dtiles_h, run, o.c_dtiles_h, a1, b1);
+        keep_tiles(o.splan.rest.tiles, run, o.c_rtiles_h, a3, b3);
+        o.cipo_comb = o.cipo_rest = n4(o.c_dtiles_h);
+        o.cipo_rlong = o.cipo_rest + n4(o.c_rtiles_h);
+    } else if (o.staged) {
+        keep_tiles(o.stiles_h, run, o.c_stiles_h, a1, b1);
+        if (o.sliced) keep_tiles(o.xplan.ctiles, run, o.c_xctiles_h, a2, b2);
+        keep_tiles(o.splan.rest.tiles, run, o.c_rtiles_h, a3, b3);
+        o.cipo_comb = n4(o.c_stiles_h);
+        o.cipo_rest = o.cipo_comb + n4(o.c_xctiles_h);
+        o.cipo_rlong = o.cipo_rest + n4(o.c_rtiles_h);
+    } else {
+        keep_tiles(o.plan.tiles, run, o.c_tiles_h, a1, b1);
+        o.cipo_long = n4(o.c_tiles_h);
+    }
+    for (int32_t q = 0; q < count; ++q) {
+        int32_t (*ir)[2] = h->hinfo_c[q].ir[d];
+        for (int r = 0; r < 3; ++r) ir[r][0] = ir[r][1] = 0;
+        if (!run[q]) continue;
+        auto rest = [&]() {
+            ir[0][0] = o.cipo_rest + a3[q];
+            ir[0][1] = o.cipo_rest + b3[q];
+            ir[1][0] = o.cipo_rlong + o.splan.rest.l_begin[q];
+            ir[1][1] = o.cipo_rlong + o.splan.rest.l_end[q];
+        };
+        if (o.direct) {
+            if (o.dinst[q]) {
+                ir[0][0] = a1[q];
+                ir[0][1] = b1[q];
+            } else {
+                rest();
+            }
+        } else if (o.staged) {
+            if (o.splan.staged[q]) {
+                ir[0][0] = a1[q];
+                ir[0][1] = b1[q];
+            } else if (o.sliced && o.xplan.sliced[q]) {
+                ir[0][0] = o.cipo_comb + a2[q];
+                ir[0][1] = o.cipo_comb + b2[q];
+            } else {
+                rest();
+            }
+        } else {
+            ir[0][0] = a1[q];
+            ir[0][1] = b1[q];
+            ir[1][0] = o.cipo_long + o.plan.l_begin[q];
+            ir[1][1] = o.cipo_long + o.plan.l_end[q];
+        }
+    }
+    o.cmp = true;
+}
+
+// Device lists and pinned staging for cutting, sized for the full lists
+// (called with the stream idle, before the solve's first window).
+static void prepare_cut(scylla_batch *h)
+{
+    size_t ints = 0;
+    auto need = [&](DevMem &d, const std::vector<int32_t> &full) {
+        const size_t b = std::max<size_t>(full.size(), 4) * 4;
+        if (d.bytes < b) d.alloc(b);
+        ints += full.size();
+    };
+    for (OrientRT *o : {&h->orow, &h->ocol}) {
+        if (o->blocked) continue;
+        if (o->direct) {
+            need(o->c_dtiles, o->dtiles_h);
+            need(o->c_rtiles, o->splan.rest.tiles);
+        } else if (o->staged) {
+            need(o->c_stiles, o->stiles_h);
+            if (o->sliced) need(o->c_xctiles, o->xplan.ctiles);
+            need(o->c_rtiles, o->splan.rest.tiles);
+        } else {
+            need(o->c_tiles, o->plan.tiles);
+        }
+    }
+    const size_t bytes = ints * 4 + sizeof(InstInfo) * (size_t)h->count;
+    if (h->cstage_bytes < bytes) {
+        if (h->cstage) (void)hipHostFree(h->cstage);
+        h->cstage = nullptr;
+        h->cstage_bytes = 0;
+        HIPC(hipHostMalloc(&h->cstage, bytes, hipHostMallocDefault));
+        h->cstage_bytes = bytes;
+    }
+}
+
+// Cuts both orientations to the instances with run[q] set and queues the
+// copies of the cut lists and slot ranges on the stream.  The staging
+// buffer is reused: the caller cuts again only after a window launched
+// behind these copies has completed.
+static void cut_lists(scylla_batch *h, const uint8_t *run)
+{
+    h->hinfo_c = h->hinfo;
+    cut_orient(h, h->orow, 0, run);
+    cut_orient(h, h->ocol, 1, run);
+    char *st = static_cast<char *>(h->cstage);
+    auto put = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes == 0) return;
+        memcpy(st, src, bytes);
+        HIPC(hipMemcpyAsync(dst, st, bytes, hipMemcpyHostToDevice, h->stream));
+        st += bytes;
+    };
+    for (OrientRT *o : {&h->orow, &h->ocol}) {
+        if (!o->cmp) continue;
+        put(o->c_tiles.p, o->c_tiles_h.data(), o->c_tiles_h.size() * 4);
+        put(o->c_stiles.p, o->c_stiles_h.data(), o->c_stiles_h.size() * 4);
+        put(o->c_xctiles.p, o->c_xctiles_h.data(), o->c_xctiles_h.size() * 4);
+        put(o->c_rtiles.p, o->c_rtiles_h.data(), o->c_rtiles_h.size() * 4);
+        put(o->c_dtiles.p, o->c_dtiles_h.data(), o->c_dtiles_h.size() * 4);
+    }
+    put(h->info.p, h->hinfo_c.data(), sizeof(InstInfo) * (size_t)h->count);
+}
+
+// Back to the full lists (stream drained first); safe to call at any time.
+static void uncut(scylla_batch *h) noexcept
+{
+    const bool any = h->cexec || !h->retired.empty() || h->orow.cmp || h->ocol.cmp;
+    if (!any) return;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->cexec) (void)hipGraphExecDestroy(h->cexec);
+    h->cexec = nullptr;
+    for (hipGraphExec_t g : h->retired) (void)hipGraphExecDestroy(g);
+    h->retired.clear();
+    h->orow.cmp = h->ocol.cmp = false;
+    if (!h->hinfo.empty() && h->info.p) {
+        (void)hipMemcpyAsync(h->info.p, h->hinfo.data(), sizeof(InstInfo) * h->hinfo.size(), hipMemcpyHostToDevice,
+                             h->stream);
+        (void)hipStreamSynchronize(h->stream);
+    }
 }
 
 // Scratch outputs and an always-running state so a pass can be launched on
@@ -1033,6 +1247,7 @@ int validate_params(const scylla_params *p)
     if (p->precision != SCYLLA_FP32 && p->precision != SCYLLA_FP64) throw_err(-EINVAL, "bad precision");
     if (p->adaptive != 0 && p->adaptive != 1) throw_err(-EINVAL, "adaptive must be 0 or 1");
     if (p->restart_avg != 0 && p->restart_avg != 1) throw_err(-EINVAL, "restart_avg must be 0 or 1");
+    if (p->compact != 0 && p->compact != 1) throw_err(-EINVAL, "compact must be 0 or 1");
     if (!(p->infeas_tol >= 0.0) || !isfinite(p->infeas_tol)) throw_err(-EINVAL, "infeas_tol must be finite and >= 0");
     if (!(p->stall_tol >= 0.0) || !isfinite(p->stall_tol)) throw_err(-EINVAL, "stall_tol must be finite and >= 0");
     if (p->stall_tol > 0.0 && p->stall_checks < 1) throw_err(-EINVAL, "stall_checks must be >= 1");
@@ -1154,15 +1369,47 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
     HIPC(hipStreamSynchronize(h->stream));
     ensure_graph(h, p->check_period, tiny);
 
+    // cutting finished instances out of the iteration launches (results
+    // unchanged); the full lists come back when the solve ends
+    struct Restore {
+        scylla_batch *h;
+        ~Restore() { uncut(h); }
+    } restore{h};
+    const bool can_cut = p->compact != 0 && !tiny && (iter_tiles(h->orow, nullptr) + iter_tiles(h->ocol, nullptr)) > 0;
+    const bool cut_trace = getenv("SCYLLA_CUT_TRACE") != nullptr;
+    std::vector<uint8_t> run(h->count, 0);
+    int64_t graph_tiles = 0, cut_after = -1, next = 0;
+    auto maybe_cut = [&](int64_t window) {
+        const int64_t live = iter_tiles(h->orow, run.data()) + iter_tiles(h->ocol, run.data());
+        // at most half the launched tiles still run, and at least 16 fewer
+        if (live * 2 > graph_tiles || graph_tiles - live < 16) return;
+        cut_after = next;  // the first window launched over the cut lists
+        const double tc = now_s();
+        cut_lists(h, run.data());
+        if (h->cexec) h->retired.push_back(h->cexec);
+        h->cexec = nullptr;
+        h->cexec = capture_window(h, p->check_period, false);
+        if (cut_trace)
+            fprintf(stderr, "cut after window %lld: %lld -> %lld tiles, %.2f ms on the host\n", (long long)window,
+                    (long long)graph_tiles, (long long)live, (now_s() - tc) * 1e3);
+        graph_tiles = live;
+    };
+    if (can_cut) {
+        prepare_cut(h);
+        graph_tiles = iter_tiles(h->orow, nullptr) + iter_tiles(h->ocol, nullptr);
+        for (int32_t q = 0; q < h->count; ++q) run[q] = st[q].status == ST_RUN ? 1 : 0;
+        maybe_cut(-1);  // instances with no iterations in this solve
+    }
+
     const size_t sb = sizeof(InstState) * (size_t)h->count;
     const double t0 = now_s();
-    int64_t next = 0, insp = 0;
+    int64_t insp = 0;
     bool done = false, forced = false;
     int64_t last_slot = 0;
     for (;;) {
         while (!done && next - insp < 2) {
             const int slot = (int)(next & 1);
-            HIPC(hipGraphLaunch(h->gexec, h->stream));
+            HIPC(hipGraphLaunch(h->cexec ? h->cexec : h->gexec, h->stream));
             HIPC(hipMemcpyAsync(h->pinned + (size_t)slot * h->count, h->st.p, sb, hipMemcpyDeviceToHost, h->stream));
             HIPC(hipEventRecord(h->ev[slot], h->stream));
             ++next;
@@ -1181,6 +1428,12 @@ int batch_solve_impl(scylla_batch *h, const scylla_params *p, int32_t warm, scyl
             launch_force_stop(h->st.as<InstState>(), h->count, h->stream);
             HIPC(hipGetLastError());
             forced = true;
+        } else if (can_cut && insp > cut_after) {
+            // the staging of the last cut is free once a window launched
+            // behind its copies has been inspected
+            for (int32_t q = 0; q < h->count; ++q)
+                run[q] = h->pinned[(size_t)slot * h->count + q].status == ST_RUN ? 1 : 0;
+            maybe_cut(insp - 1);
         }
     }
     HIPC(hipStreamSynchronize(h->stream));
@@ -1237,6 +1490,7 @@ int scylla_params_default(scylla_params *p)
     p->stall_tol = 0.0;
     p->stall_checks = 3;
     p->restart_avg = 0;
+    p->compact = 1;
     return 0;
 }
 

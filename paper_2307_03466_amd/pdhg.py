@@ -57,7 +57,8 @@ class Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
                 ("fused_window", ctypes.c_int32), ("adaptive", ctypes.c_int32),
                 ("infeas_tol", ctypes.c_double), ("stall_tol", ctypes.c_double),
-                ("stall_checks", ctypes.c_int32), ("restart_avg", ctypes.c_int32)]
+                ("stall_checks", ctypes.c_int32), ("restart_avg", ctypes.c_int32),
+                ("compact", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

@@ -53,6 +53,7 @@ def test_params_default(L):
     assert p.tol == 1e-4 and p.check_period == 64 and p.eta == 0.99 and p.restarts == 1
     assert p.adaptive == 0 and p.fused_window == 1 and p.infeas_tol == 1e-8
     assert p.stall_tol == 0.0 and p.stall_checks == 3
+    assert p.restart_avg == 0 and p.compact == 1
     assert L.scylla_params_default(None) == EINVAL
 
 
@@ -132,7 +133,8 @@ def test_bad_params_rejected(L):
     lp = I.workload(1)
     for kw in (dict(check_period=0), dict(eta=1.5), dict(iter_limit=-1), dict(precision=7), dict(adaptive=2),
                dict(infeas_tol=-1.0), dict(infeas_tol=float("nan")), dict(stall_tol=-1.0),
-               dict(stall_tol=float("inf")), dict(stall_tol=1e-6, stall_checks=0)):
+               dict(stall_tol=float("inf")), dict(stall_tol=1e-6, stall_checks=0), dict(restart_avg=2),
+               dict(compact=2), dict(compact=-1)):
         with pytest.raises(pdhg.ScyllaError) as e:
             pdhg.solve(lp, **kw)
         assert e.value.code == EINVAL

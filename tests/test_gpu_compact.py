@@ -80,3 +80,26 @@ def test_cut_then_warm_resolve_uses_the_full_lists(capfd, monkeypatch):
         assert out[0][0][i]["iterations"] == out[1][0][i]["iterations"] > 0
         np.testing.assert_array_equal(out[0][1][i][0], out[1][1][i][0])
         np.testing.assert_array_equal(out[0][1][i][1], out[1][1][i][1])
+
+
+@pytest.mark.parametrize("layout", [None, (-2, 8, -2, 8)], ids=["tuned", "sliced"])
+def test_cutting_is_bitwise_neutral_fp64(layout, capfd, monkeypatch, tmp_path):
+    """The same in the FP64 path (its own tile sizes and slices)."""
+    lps = _batch()
+    monkeypatch.setenv("SCYLLA_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    monkeypatch.setenv("SCYLLA_CUT_TRACE", "1")
+    out = {}
+    for compact in (0, 1):
+        capfd.readouterr()
+        with pdhg.Batch(lps, precision=0) as b:
+            if layout:
+                b.set_layout(*layout)
+            res = b.solve(tol=1e-4, iter_limit=50_000, fused_window=0, compact=compact, adaptive=1)
+            sols = [b.solution(i) for i in range(len(lps))]
+        out[compact] = (res, sols, capfd.readouterr().err.count("cut after window"))
+    assert out[0][2] == 0 and out[1][2] >= 1
+    for i in range(len(lps)):
+        assert out[0][0][i]["iterations"] == out[1][0][i]["iterations"]
+        assert out[0][0][i]["rel_kkt"] == out[1][0][i]["rel_kkt"]
+        np.testing.assert_array_equal(out[0][1][i][0], out[1][1][i][0])
+        np.testing.assert_array_equal(out[0][1][i][1], out[1][1][i][1])

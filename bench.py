@@ -378,7 +378,10 @@ def other_workloads(pdhg, instances, args, R):
                    canonical_bytes_per_iter=r["canon_iter"],
                    canonical_GBps=round(r["canon_iter"] * r["iter_per_s"] / 1e9, 1),
                    row_canonical_GBps=round(r["canon_row"] / r["ms_row"] / 1e6, 1),
-                   col_canonical_GBps=round(r["canon_col"] / r["ms_col"] / 1e6, 1))
+                   col_canonical_GBps=round(r["canon_col"] / r["ms_col"] / 1e6, 1),
+                   row_frac_of_peak=round(r["canon_row"] / r["ms_row"] / 1e6 / HBM_PEAK_GBPS, 3),
+                   col_frac_of_peak=round(r["canon_col"] / r["ms_col"] / 1e6 / HBM_PEAK_GBPS, 3),
+                   iteration_frac_of_peak=round(r["canon_iter"] * r["iter_per_s"] / 1e9 / HBM_PEAK_GBPS, 3))
         log(f"w4 fp32 batched: {r['iter_per_s']:,.0f} batch-iter/s to_tol={r.get('to_tol')} "
             f"adaptive={r.get('to_tol_adaptive')}")
         if args.fp64_plain_batch and args.to_tol:
@@ -441,6 +444,16 @@ def other_workloads(pdhg, instances, args, R):
                                   instances_feasible=sum(f is not None for f in first),
                                   mean_first_feasible_round=(round(sum(f for f in first if f) /
                                                                    max(1, sum(f is not None for f in first)), 2)))
+        # the passes of the pump batch alone, with the tuned layout (HIP
+        # events), in the byte model
+        ms_row, ms_col = b.time_passes(20)
+        crow, ccol = canonical_pass_bytes(lps)
+        rec5 = out["pump_64x20k"]
+        rec5.update(ms_row=round(ms_row, 4), ms_col=round(ms_col, 4),
+                    row_canonical_GBps=round(crow / ms_row / 1e6, 1), col_canonical_GBps=round(ccol / ms_col / 1e6, 1),
+                    row_frac_of_peak=round(crow / ms_row / 1e6 / HBM_PEAK_GBPS, 3),
+                    col_frac_of_peak=round(ccol / ms_col / 1e6 / HBM_PEAK_GBPS, 3),
+                    iteration_frac_of_peak=round(rec5["canonical_GBps"] / HBM_PEAK_GBPS, 3))
         log(f"w5 pump: {out['pump_64x20k']}")
         # the complete Algorithm 1 loop: eps schedule, early exit per
         # instance, cycle perturbation (finished instances leave the batch)

@@ -147,7 +147,9 @@ typedef struct {
                              instances still running, the launches are
                              rebuilt over those tiles only (finished
                              instances then cost nothing per iteration;
-                             results are unchanged bit for bit).  0 = off */
+                             results are unchanged bit for bit; the
+                             environment variable SCYLLA_CUT_TRACE=1
+                             prints each cut on stderr).  0 = off          */
 } scylla_params;
 
 enum {

@@ -11,6 +11,15 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU test")
+    # torch ships its own HIP runtime; it must initialise before the library
+    # loads the system one, or torch sees no GPU for the rest of the process
+    # (GPU tests that use torch would then skip instead of running)
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
 
 
 @pytest.fixture(scope="session", autouse=True)

@@ -103,3 +103,50 @@ def test_cutting_is_bitwise_neutral_fp64(layout, capfd, monkeypatch, tmp_path):
         assert out[0][0][i]["rel_kkt"] == out[1][0][i]["rel_kkt"]
         np.testing.assert_array_equal(out[0][1][i][0], out[1][1][i][0])
         np.testing.assert_array_equal(out[0][1][i][1], out[1][1][i][1])
+
+
+def test_instances_without_iterations_are_cut_before_the_first_window(capfd, monkeypatch):
+    """The pump's two-group schedule solves half the batch at a time: the
+    other half takes no iterations and is cut before the first window; the
+    loop's result equals the lockstep loop's and the uncut run's."""
+    lps = I.uneven_batch(count=40, lo=400, hi=3_000, seed=9)
+    monkeypatch.setenv("SCYLLA_CUT_TRACE", "1")
+    out = []
+    for compact in (0, 1):
+        capfd.readouterr()
+        with pdhg.Batch(lps, precision=1) as b:
+            b.set_layout(-2, 8, -2, 8)
+            recs, outs, x = b.pump_ex(pump=dict(rounds=4, seed=0, pipeline=1, early_exit=0), iter_limit=20_000,
+                                      compact=compact, fused_window=0)
+        err = capfd.readouterr().err
+        out.append((recs, outs, x, err))
+    assert "cut after window -1" not in out[0][3]
+    assert "cut after window -1" in out[1][3]
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    for a, b2 in zip(out[0][1], out[1][1]):
+        assert a == b2
+
+
+def test_time_limit_with_cut_lists_then_a_full_solve(monkeypatch):
+    """A solve stopped by its time limit while the lists are cut leaves the
+    handle whole: the next cold solve runs every instance to the tolerance
+    and equals a fresh handle's solve bit for bit."""
+    lps = _batch()
+    res_fresh = None
+    with pdhg.Batch(lps, precision=1) as b:
+        b.set_layout(-2, 8, -2, 8)
+        # to 1e-6 the small instances finish and are cut out while the
+        # large ones run into the time limit
+        r = b.solve(tol=1e-6, iter_limit=5_000_000, fused_window=0, time_limit_s=0.2)
+        assert {x["status"] for x in r} <= {pdhg.OPTIMAL, pdhg.TIME_LIMIT}, r
+        res = b.solve(tol=1e-4, iter_limit=50_000, fused_window=0)
+        sols = [b.solution(i) for i in range(len(lps))]
+    with pdhg.Batch(lps, precision=1) as b:
+        b.set_layout(-2, 8, -2, 8)
+        res_fresh = b.solve(tol=1e-4, iter_limit=50_000, fused_window=0)
+        fresh = [b.solution(i) for i in range(len(lps))]
+    for i in range(len(lps)):
+        assert res[i]["status"] == pdhg.OPTIMAL
+        assert res[i]["iterations"] == res_fresh[i]["iterations"]
+        np.testing.assert_array_equal(sols[i][0], fresh[i][0])
+        np.testing.assert_array_equal(sols[i][1], fresh[i][1])

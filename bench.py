@@ -101,7 +101,8 @@ def pass_kernels(info, is_col):
     launches in the layout `info` describes, or None for the LDS-staged
     layouts."""
     blocks = info["col_blocks"] if is_col else info["row_blocks"]
-    fmt = info["format"]
+    # the kernels' format parameter carries the cached-load flag (8)
+    fmt = info["format"] | (8 if info.get("col_cached" if is_col else "row_cached") else 0)
     nt = info["col_tile_threads" if is_col else "row_tile_threads"] or 256
     ept = (info["col_chunk"] if is_col else info["row_chunk"]) // nt
     if blocks > 0:  # gather-blocked pass: partial sums, then the combine with the epilogue

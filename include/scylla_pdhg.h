@@ -322,8 +322,20 @@ typedef struct {
     int32_t row_direct, col_direct; /* instances of a direct staged pass
                                        (blocks -6): whole gathered vector in
                                        LDS, rows reduced in registers        */
+    int32_t row_cached, col_cached; /* 1: the pass reads the matrix with
+                                       plain (cacheable) loads, 0: with
+                                       non-temporal loads                    */
 } scylla_batch_info;
 int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info);
+
+/* Matrix load policy of the iteration passes (FP32 path; the autotuner
+ * chooses it by timing both passes together, a pinned layout starts with
+ * 0): 1 = plain loads, which the device's last-level (Infinity) cache
+ * keeps across iterations when an iteration's data fits in it, 0 =
+ * non-temporal loads that stream past the caches.  Results do not depend
+ * on it.  Call after scylla_batch_set_layout (which resets it).  Returns 0,
+ * or -EINVAL (NULL handle, flags not 0 or 1). */
+int scylla_batch_set_cached_loads(scylla_batch *h, int32_t row_cached, int32_t col_cached);
 
 /* ------------------------------------------------------ pump loop
  * Fix-and-propagate rounding on the host (Section 2.3): integer variables

@@ -96,6 +96,7 @@ using namespace scy;
 struct OrientRT {
     bool row = true;
     int32_t rows = 0, gather = 0;
+    bool cached = false;  // iteration passes read the matrix with plain loads
     HostOrient host;  // normal layout (host copy kept for re-planning)
     DevMem ptr, ent, val;
     MatView mat{};

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "scylla_internal.h"
 #include "kernels.h"
 
@@ -104,16 +106,27 @@ struct Entry {
     double d;
 };
 
+// A matrix entry load: non-temporal (streamed past the caches), or with
+// FMT_CACHED in the format a plain load, which the device's last-level
+// (Infinity) cache keeps across iterations when an iteration's data fits.
+template <int FMT, class T>
+__device__ __forceinline__ T mat_load(const T *p)
+{
+    if constexpr ((FMT & FMT_CACHED) != 0) return *p;
+    else return __builtin_nontemporal_load(p);
+}
+
 template <int FMT, class A>
 __device__ __forceinline__ void load_entry(const MatView &M, int e, uint32_t &w, A &a)
 {
-    w = __builtin_nontemporal_load(M.ent + e);
-    if constexpr (FMT == FMT_BF16) {
-        a = (A)bf16_to_f32(__builtin_nontemporal_load((const uint16_t *)M.val + e));
-    } else if constexpr (FMT == FMT_F32) {
-        a = (A)__builtin_nontemporal_load((const float *)M.val + e);
-    } else if constexpr (FMT == FMT_F64) {
-        a = (A)__builtin_nontemporal_load((const double *)M.val + e);
+    constexpr int F = FMT & ~FMT_CACHED;
+    w = mat_load<FMT>(M.ent + e);
+    if constexpr (F == FMT_BF16) {
+        a = (A)bf16_to_f32(mat_load<FMT>((const uint16_t *)M.val + e));
+    } else if constexpr (F == FMT_F32) {
+        a = (A)mat_load<FMT>((const float *)M.val + e);
+    } else if constexpr (F == FMT_F64) {
+        a = (A)mat_load<FMT>((const double *)M.val + e);
     } else {
         a = (A)0;
     }
@@ -122,7 +135,7 @@ __device__ __forceinline__ void load_entry(const MatView &M, int e, uint32_t &w,
 template <int FMT, class A>
 __device__ __forceinline__ int decode_entry(const MatView &M, uint32_t w, A &a)
 {
-    if constexpr (FMT == FMT_PACKED) {
+    if constexpr ((FMT & ~FMT_CACHED) == FMT_PACKED) {
         a = (A)((int32_t)w >> M.shift);
         return (int)(w & M.mask);
     } else {
@@ -1805,15 +1818,35 @@ static void dispatch_bpart(const PassArgs<V> &p, int ept, int jw, int check, hip
     }
 }
 
+// Calls f(std::integral_constant<int, F>{}) with F the FP32 storage format
+// fmt, with or without the FMT_CACHED flag.
+template <class Fn>
+static void fp32_format(int fmt, Fn &&f)
+{
+    const bool c = (fmt & FMT_CACHED) != 0;
+    switch (fmt & ~FMT_CACHED) {
+    case FMT_PACKED:
+        if (c) f(std::integral_constant<int, FMT_PACKED | FMT_CACHED>{});
+        else f(std::integral_constant<int, FMT_PACKED>{});
+        break;
+    case FMT_BF16:
+        if (c) f(std::integral_constant<int, FMT_BF16 | FMT_CACHED>{});
+        else f(std::integral_constant<int, FMT_BF16>{});
+        break;
+    default:
+        if (c) f(std::integral_constant<int, FMT_F32 | FMT_CACHED>{});
+        else f(std::integral_constant<int, FMT_F32>{});
+        break;
+    }
+}
+
 template <class V, class A>
 static void bpart_fmt(const PassArgs<V> &p, int fmt, int ept, int jw, int check, hipStream_t s)
 {
     if constexpr (sizeof(V) == 8) {
         dispatch_bpart<V, A, FMT_F64>(p, ept, jw, check, s);
     } else {
-        if (fmt == FMT_PACKED) dispatch_bpart<V, A, FMT_PACKED>(p, ept, jw, check, s);
-        else if (fmt == FMT_BF16) dispatch_bpart<V, A, FMT_BF16>(p, ept, jw, check, s);
-        else dispatch_bpart<V, A, FMT_F32>(p, ept, jw, check, s);
+        fp32_format(fmt, [&](auto fc) { dispatch_bpart<V, A, decltype(fc)::value>(p, ept, jw, check, s); });
     }
 }
 
@@ -1847,16 +1880,11 @@ void launch_pass(const PassArgs<V> &p, int fmt, int dir, int ept, int jw, bool c
             if (dir == DIR_COL) dispatch_pass<V, FMT_F64, DIR_COL>(p, ept, jw, check, s);
             else dispatch_pass<V, FMT_F64, DIR_ROW>(p, ept, jw, check, s);
         } else {
-            if (fmt == FMT_PACKED) {
-                if (dir == DIR_COL) dispatch_pass<V, FMT_PACKED, DIR_COL>(p, ept, jw, check, s);
-                else dispatch_pass<V, FMT_PACKED, DIR_ROW>(p, ept, jw, check, s);
-            } else if (fmt == FMT_BF16) {
-                if (dir == DIR_COL) dispatch_pass<V, FMT_BF16, DIR_COL>(p, ept, jw, check, s);
-                else dispatch_pass<V, FMT_BF16, DIR_ROW>(p, ept, jw, check, s);
-            } else {
-                if (dir == DIR_COL) dispatch_pass<V, FMT_F32, DIR_COL>(p, ept, jw, check, s);
-                else dispatch_pass<V, FMT_F32, DIR_ROW>(p, ept, jw, check, s);
-            }
+            fp32_format(fmt, [&](auto fc) {
+                constexpr int F = decltype(fc)::value;
+                if (dir == DIR_COL) dispatch_pass<V, F, DIR_COL>(p, ept, jw, check, s);
+                else dispatch_pass<V, F, DIR_ROW>(p, ept, jw, check, s);
+            });
         }
     }
     if (p.nlong > 0) {
@@ -1904,16 +1932,11 @@ void launch_staged(const PassArgs<V> &p, int fmt, int dir, int variant, int jw, 
         if (dir == DIR_COL) staged_t<V, FMT_F64, DIR_COL>(p, variant, jw, shmem, s, prepare);
         else staged_t<V, FMT_F64, DIR_ROW>(p, variant, jw, shmem, s, prepare);
     } else {
-        if (fmt == FMT_PACKED) {
-            if (dir == DIR_COL) staged_t<V, FMT_PACKED, DIR_COL>(p, variant, jw, shmem, s, prepare);
-            else staged_t<V, FMT_PACKED, DIR_ROW>(p, variant, jw, shmem, s, prepare);
-        } else if (fmt == FMT_BF16) {
-            if (dir == DIR_COL) staged_t<V, FMT_BF16, DIR_COL>(p, variant, jw, shmem, s, prepare);
-            else staged_t<V, FMT_BF16, DIR_ROW>(p, variant, jw, shmem, s, prepare);
-        } else {
-            if (dir == DIR_COL) staged_t<V, FMT_F32, DIR_COL>(p, variant, jw, shmem, s, prepare);
-            else staged_t<V, FMT_F32, DIR_ROW>(p, variant, jw, shmem, s, prepare);
-        }
+        fp32_format(fmt, [&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            if (dir == DIR_COL) staged_t<V, F, DIR_COL>(p, variant, jw, shmem, s, prepare);
+            else staged_t<V, F, DIR_ROW>(p, variant, jw, shmem, s, prepare);
+        });
     }
 }
 
@@ -1945,16 +1968,11 @@ void launch_direct(const PassArgs<V> &p, int fmt, int dir, int k, int jw, size_t
         if (dir == DIR_COL) direct_t<V, FMT_F64, DIR_COL>(p, k, jw, shmem, s, prepare);
         else direct_t<V, FMT_F64, DIR_ROW>(p, k, jw, shmem, s, prepare);
     } else {
-        if (fmt == FMT_PACKED) {
-            if (dir == DIR_COL) direct_t<V, FMT_PACKED, DIR_COL>(p, k, jw, shmem, s, prepare);
-            else direct_t<V, FMT_PACKED, DIR_ROW>(p, k, jw, shmem, s, prepare);
-        } else if (fmt == FMT_BF16) {
-            if (dir == DIR_COL) direct_t<V, FMT_BF16, DIR_COL>(p, k, jw, shmem, s, prepare);
-            else direct_t<V, FMT_BF16, DIR_ROW>(p, k, jw, shmem, s, prepare);
-        } else {
-            if (dir == DIR_COL) direct_t<V, FMT_F32, DIR_COL>(p, k, jw, shmem, s, prepare);
-            else direct_t<V, FMT_F32, DIR_ROW>(p, k, jw, shmem, s, prepare);
-        }
+        fp32_format(fmt, [&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            if (dir == DIR_COL) direct_t<V, F, DIR_COL>(p, k, jw, shmem, s, prepare);
+            else direct_t<V, F, DIR_ROW>(p, k, jw, shmem, s, prepare);
+        });
     }
 }
 

@@ -266,7 +266,8 @@ void set_staged(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     PassArgs<float> pf{};
     PassArgs<double> pd{};
     if (h->vbytes == 4)
-        launch_staged<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, variant, 0, o.shmem, h->stream, true);
+        for (int c : {0, (int)FMT_CACHED})  // both matrix load policies
+            launch_staged<float>(pf, h->fmt | c, o.row ? DIR_ROW : DIR_COL, variant, 0, o.shmem, h->stream, true);
     else
         launch_staged<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, variant, 0, o.shmem, h->stream, true);
     HIPC(hipStreamSynchronize(h->stream));
@@ -302,7 +303,9 @@ void set_direct(scylla_batch *h, OrientRT &o, int32_t ept, int32_t group_nnz, in
     o.dshmem = (size_t)vmax * h->vbytes + LDS_COPY_SLACK;
     PassArgs<float> pf{};
     PassArgs<double> pd{};
-    if (h->vbytes == 4) launch_direct<float>(pf, h->fmt, o.row ? DIR_ROW : DIR_COL, k, 0, o.dshmem, h->stream, true);
+    if (h->vbytes == 4)
+        for (int c : {0, (int)FMT_CACHED})  // both matrix load policies
+            launch_direct<float>(pf, h->fmt | c, o.row ? DIR_ROW : DIR_COL, k, 0, o.dshmem, h->stream, true);
     else launch_direct<double>(pd, h->fmt, o.row ? DIR_ROW : DIR_COL, k, 0, o.dshmem, h->stream, true);
     HIPC(hipStreamSynchronize(h->stream));
     o.nstiles = (int32_t)(o.dtiles_h.size() / 4);
@@ -418,6 +421,9 @@ template <class V>
 void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, bool check, hipStream_t s)
 {
     const int dir = o.row ? DIR_ROW : DIR_COL;
+    // the iteration passes read the matrix with the orientation's load
+    // policy (the checks, once per window, stream it)
+    const int ifmt = h->fmt | (o.cached && h->vbytes == 4 ? (int)FMT_CACHED : 0);
     // iteration launches take the compacted tile lists when there are any
     const bool cmp = o.cmp && !check;
     auto n4 = [](const std::vector<int32_t> &v) { return (int32_t)(v.size() / 4); };
@@ -438,10 +444,10 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
         if (fork) {
             HIPC(hipEventRecord(h->fork, s));
             HIPC(hipStreamWaitEvent(h->side, h->fork, 0));
-            launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
+            launch_pass<V>(pr, ifmt, dir, o.ept, jw, false, false, h->side);
             HIPC(hipEventRecord(h->join, h->side));
         }
-        launch_direct<V>(pd, h->fmt, dir, dpass_k(o.dlanes), jw, o.dshmem, s, false);
+        launch_direct<V>(pd, ifmt, dir, dpass_k(o.dlanes), jw, o.dshmem, s, false);
         if (fork) HIPC(hipStreamWaitEvent(s, h->join, 0));
         return;
     }
@@ -474,15 +480,15 @@ void launch_orient(scylla_batch *h, OrientRT &o, const PassArgs<V> &p, int jw, b
         if (fork) {
             HIPC(hipEventRecord(h->fork, s));
             HIPC(hipStreamWaitEvent(h->side, h->fork, 0));
-            launch_pass<V>(pr, h->fmt, dir, o.ept, jw, false, false, h->side);
+            launch_pass<V>(pr, ifmt, dir, o.ept, jw, false, false, h->side);
             HIPC(hipEventRecord(h->join, h->side));
         }
-        launch_staged<V>(ps, h->fmt, dir, o.svariant, jw, o.shmem, s, false);
+        launch_staged<V>(ps, ifmt, dir, o.svariant, jw, o.shmem, s, false);
         if (o.sliced) launch_combine<V>(pc, dir, jw, s);
         if (fork) HIPC(hipStreamWaitEvent(s, h->join, 0));
         return;
     }
-    launch_pass<V>(p, h->fmt, dir, o.ept, jw, check, o.blocked, s);
+    launch_pass<V>(p, ifmt, dir, o.ept, jw, check, o.blocked, s);
 }
 
 template <class V>
@@ -954,17 +960,19 @@ void tune_store(const std::string &key, const TuneChoice &c)
 
 void apply_choice(scylla_batch *h, OrientRT &o, const int32_t *v)
 {
+    const int32_t v3 = v[3] & ~64;  // bit 64: plain (cacheable) matrix loads
     if (v[0] == -2) {
-        set_direct(h, o, v[1], v[2], v[3]);
+        set_direct(h, o, v[1], v[2], v3);
         drop_blocked(o);
         release_sliced(o);
     } else if (v[0] < 0) {
-        set_staged(h, o, v[1], v[2], v[3] & 3, (v[3] >> 2) & 1, (v[3] >> 3) & 1);
+        set_staged(h, o, v[1], v[2], v3 & 3, (v3 >> 2) & 1, (v3 >> 3) & 1);
         drop_blocked(o);
     } else {
         set_plan(h, o, v[0], v[1]);
         if (v[0] == 0) drop_blocked(o);
     }
+    o.cached = (v[3] & 64) != 0 && h->vbytes == 4;
 }
 
 TuneChoice current_choice(scylla_batch *h)
@@ -978,6 +986,7 @@ TuneChoice current_choice(scylla_batch *h)
         v[2] = o.direct ? o.dnnz : (o.staged ? o.staged_nnz : 0);
         v[3] = o.direct ? o.dlanes
                         : (o.staged ? (o.svariant | (o.sliced ? 4 : 0) | (o.shalf ? 8 : 0)) : 0);
+        if (o.cached) v[3] |= 64;
     }
     return c;
 }
@@ -1000,10 +1009,23 @@ void autotune(scylla_batch *h)
         return;
     }
     const int epts[5] = {4, 8, 16, -8, -16};
+    // The matrix load policy first, on the initial layout (both passes
+    // timed together): whether an iteration's data fits the device's
+    // last-level cache hardly depends on the layout, and the layouts are
+    // then ranked under the policy they will run with; the policy is timed
+    // again on the chosen layouts at the end.
+    h->orow.cached = h->ocol.cached = false;
     // SCYLLA_TUNE_TRACE=1: one line per candidate on stderr (plan time on
     // the host, measured pass time)
     const bool trace = getenv("SCYLLA_TUNE_TRACE") != nullptr;
     PassTimer<V> timer(h);
+    if (h->vbytes == 4) {
+        const double t_nt = timer.time(h->orow, 20);
+        h->orow.cached = h->ocol.cached = true;
+        const double t_c = timer.time(h->orow, 20);
+        if (trace) fprintf(stderr, "tune load policy first: non-temporal %.3f ms, cached %.3f ms\n", t_nt, t_c);
+        h->orow.cached = h->ocol.cached = t_c < 0.99 * t_nt;
+    }
     for (int d = 0; d < 2; ++d) {
         OrientRT &o = d == 0 ? h->orow : h->ocol;
         double best = 1e30;
@@ -1105,6 +1127,28 @@ void autotune(scylla_batch *h)
             if (best_B == 0) drop_blocked(o);
             release_sliced(o);
         }
+    }
+    // Matrix load policy of the iteration passes: non-temporal, or plain
+    // loads that the device's last-level cache keeps across iterations when
+    // an iteration's data fits (a gain there, a loss when the data
+    // overflows it and evicts itself).  Both passes are timed together,
+    // since what the cache keeps depends on both orientations' data.
+    if (h->vbytes == 4) {
+        double best = 1e30;
+        int best_c = 0;
+        for (int c : {0, 3, 1, 2}) {  // bit 0: row pass, bit 1: column pass
+            h->orow.cached = (c & 1) != 0;
+            h->ocol.cached = (c & 2) != 0;
+            const double ms = timer.time(h->orow, 20);
+            if (trace) fprintf(stderr, "tune cached loads row=%d col=%d run %.3f ms\n", c & 1, (c >> 1) & 1, ms);
+            // plain loads must win by 1 %
+            if (ms < (c == 0 ? best : 0.99 * best)) {
+                best = c == 0 ? ms : ms / 0.99;
+                best_c = c;
+            }
+        }
+        h->orow.cached = (best_c & 1) != 0;
+        h->ocol.cached = (best_c & 2) != 0;
     }
     refresh_info(h);
     invalidate_graph(h);
@@ -1818,6 +1862,22 @@ int scylla_batch_get_info(scylla_batch *h, scylla_batch_info *info)
         }
         info->row_staged_nnz = h->orow.direct ? h->orow.dnnz : info->row_staged_nnz;
         info->col_staged_nnz = h->ocol.direct ? h->ocol.dnnz : info->col_staged_nnz;
+        info->row_cached = h->orow.cached ? 1 : 0;
+        info->col_cached = h->ocol.cached ? 1 : 0;
+        return 0;
+    });
+}
+
+int scylla_batch_set_cached_loads(scylla_batch *h, int32_t row_cached, int32_t col_cached)
+{
+    return guarded([&]() {
+        if (!h) throw_err(-EINVAL, "handle is NULL");
+        if ((row_cached != 0 && row_cached != 1) || (col_cached != 0 && col_cached != 1))
+            throw_err(-EINVAL, "flags must be 0 or 1");
+        HIPC(hipStreamSynchronize(h->stream));
+        h->orow.cached = row_cached != 0 && h->vbytes == 4;
+        h->ocol.cached = col_cached != 0 && h->vbytes == 4;
+        invalidate_graph(h);
         return 0;
     });
 }
@@ -1836,6 +1896,7 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;
+            o.cached = false;  // non-temporal matrix loads unless set otherwise
             int32_t B = d == 0 ? row_blocks : col_blocks, ept = d == 0 ? row_ept : col_ept;
             if (o.rows == 0 && B > 0) B = 0;
             if (B <= -6) {

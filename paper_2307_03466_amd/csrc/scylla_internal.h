@@ -18,7 +18,10 @@ enum Fmt : int32_t {
                      // matrices: 4 bytes per nonzero, exact)
     FMT_BF16 = 1,    // int32 index + bfloat16 value (every value BF16-exact)
     FMT_F32 = 2,     // int32 index + float value
-    FMT_F64 = 3      // int32 index + double value (FP64 path)
+    FMT_F64 = 3,     // int32 index + double value (FP64 path)
+    FMT_CACHED = 8   // flag on a format given to the pass kernels: matrix
+                     // entries are read with plain (cacheable) loads
+                     // instead of non-temporal ones
 };
 
 enum Status : int32_t { ST_RUN = 0, ST_OPT = 1, ST_ITER = 2, ST_TIME = 3, ST_NUM = 4, ST_PINF = 5, ST_DINF = 6,

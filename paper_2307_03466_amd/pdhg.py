@@ -27,6 +27,7 @@ EXPORTS = [
     "scylla_batch_set_blend", "scylla_batch_set_start", "scylla_batch_solve",
     "scylla_batch_get_solution", "scylla_batch_get_x_all", "scylla_batch_device_iterates",
     "scylla_batch_get_info", "scylla_batch_time_passes", "scylla_batch_set_layout",
+    "scylla_batch_set_cached_loads",
     "scylla_fix_propagate", "scylla_batch_pump",
     "scylla_pump_params_default", "scylla_batch_pump_ex", "scylla_batch_set_quadratic",
     "scylla_batch_mip_feasible", "scylla_batch_fix_propagate", "scylla_batch_mip_feasible_static",
@@ -87,7 +88,8 @@ class BatchInfo(ctypes.Structure):
                 ("col_sliced", ctypes.c_int32), ("row_slices", ctypes.c_int32), ("col_slices", ctypes.c_int32),
                 ("row_half_lds", ctypes.c_int32), ("col_half_lds", ctypes.c_int32),
                 ("row_tile_threads", ctypes.c_int32), ("col_tile_threads", ctypes.c_int32),
-                ("row_direct", ctypes.c_int32), ("col_direct", ctypes.c_int32)]
+                ("row_direct", ctypes.c_int32), ("col_direct", ctypes.c_int32),
+                ("row_cached", ctypes.c_int32), ("col_cached", ctypes.c_int32)]
 
 
 _lib = None
@@ -123,6 +125,7 @@ def lib():
             "scylla_batch_get_info": ([vp, ctypes.POINTER(BatchInfo)], ctypes.c_int),
             "scylla_batch_time_passes": ([vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)], ctypes.c_int),
             "scylla_batch_set_layout": ([vp, i32, i32, i32, i32], ctypes.c_int),
+            "scylla_batch_set_cached_loads": ([vp, i32, i32], ctypes.c_int),
             "scylla_fix_propagate": ([ctypes.POINTER(LPDesc), vp, vp, vp, vp], ctypes.c_int),
             "scylla_batch_pump": ([vp, ctypes.POINTER(Params), vp, i32, dbl, i32, ctypes.POINTER(PumpRecord), vp],
                                   ctypes.c_int),
@@ -410,6 +413,11 @@ class Batch:
         2 / 4 / 8 gather blocks; 4 / 8 / 16 nonzeros per thread, or -8 / -16 on
         1024-thread workgroups)."""
         _check(lib().scylla_batch_set_layout(self._h, row_blocks, row_ept, col_blocks, col_ept))
+
+    def set_cached_loads(self, row: int = 1, col: int = 1):
+        """Matrix load policy of the iteration passes: plain (cacheable)
+        loads (1) or non-temporal ones (0)."""
+        _check(lib().scylla_batch_set_cached_loads(self._h, row, col))
 
     def time_passes(self, reps: int = 20):
         """Average ms of one launch of the row pass and of the column pass."""

@@ -551,3 +551,42 @@ def test_uniform_bounds_parity(layout, prec, bar):
         assert res[i]["iterations"] == 100
         assert np.all(x >= lp.l) and np.all(x <= lp.u)
         assert parity_err(x, y, ref.x, ref.y) <= bar, (layout, i)
+
+
+@pytest.mark.parametrize("layout", [None, (0, 8, 0, 8), (4, 8, 0, 4), (-1, 8, -1, 8), (-2, 8, -2, 8),
+                                    (-6, 8, -6, 8)], ids=["tuned", "normal", "blocked", "staged", "sliced",
+                                                          "direct"])
+def test_cached_loads_are_bitwise_equal(layout, monkeypatch, tmp_path):
+    """Plain (cacheable) and non-temporal matrix loads read the same values:
+    the FP32 iterates, iteration counts and KKT values are equal bit for bit
+    under every layout, and the handle reports the policy."""
+    lps = _sliced_cases()["mixed_batch"] + [_case("general_small")]
+    monkeypatch.setenv("SCYLLA_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    out = []
+    for cached in (0, 1):
+        with pdhg.Batch(lps, precision=1) as b:
+            if layout:
+                b.set_layout(*layout)
+            else:
+                b.solve(tol=1e-4, iter_limit=1)  # tunes (and caches the choice)
+            b.set_cached_loads(cached, cached)
+            info = b.info()
+            assert info["row_cached"] == cached and info["col_cached"] == cached
+            res = b.solve(tol=1e-4, iter_limit=20_000, fused_window=0)
+            out.append((res, [b.solution(i) for i in range(len(lps))]))
+    for i in range(len(lps)):
+        for k in ("status", "iterations", "rel_kkt"):
+            assert out[0][0][i][k] == out[1][0][i][k], (i, k)
+        np.testing.assert_array_equal(out[0][1][i][0], out[1][1][i][0])
+        np.testing.assert_array_equal(out[0][1][i][1], out[1][1][i][1])
+
+
+def test_cached_loads_argument_checks():
+    with pdhg.Batch([_case("general_small")], precision=1) as b:
+        for bad in ((2, 0), (0, -1)):
+            with pytest.raises(pdhg.ScyllaError):
+                b.set_cached_loads(*bad)
+    with pdhg.Batch([_case("general_small")], precision=0) as b:
+        b.set_cached_loads(1, 1)  # FP64: accepted, non-temporal loads kept
+        info = b.info()
+        assert info["row_cached"] == 0 and info["col_cached"] == 0

@@ -93,26 +93,31 @@ def test_pump_workload_shape():
 
 
 def test_pass_kernel_names_match_the_traffic_table():
-    """The kernels bench.py looks up for the headline LP's layouts (normal
-    column pass and 4-block row pass on 1024-thread tiles of 4096 nonzeros)
-    are named as in the counter table, which was taken on that workload; a
-    layout the table does not hold gives no traffic figure rather than
-    another kernel's."""
+    """The kernels bench.py looks up for the headline LP's tuned layouts
+    (normal column pass and 4-block row pass on 256-thread tiles of 1024
+    nonzeros, both with cacheable matrix loads) are named as in the counter
+    table, which was taken on that workload; a layout the table does not hold
+    gives no traffic figure rather than another kernel's."""
     import json
     table = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))["kernels"]
-    info = dict(format=0, col_blocks=0, row_blocks=4, col_chunk=4096, row_chunk=4096,
-                col_tile_threads=1024, row_tile_threads=1024)
+    info = dict(format=0, col_blocks=0, row_blocks=4, col_chunk=1024, row_chunk=1024,
+                col_tile_threads=256, row_tile_threads=256, col_cached=1, row_cached=1)
     for is_col in (True, False):
         names = bench.pass_kernels(info, is_col)
         assert names and all(n in table for n in names), names
-    assert bench.pass_kernels(info, True) == ["void k_pass<float, 0, 1, 1024, 4>(PassArgs<float>, int)"]
-    assert bench.pass_kernels(info, False) == ["void k_bpart<float, float, 0, 1024, 4>(PassArgs<float>, int, int)",
+    assert bench.pass_kernels(info, True) == ["void k_pass<float, 8, 1, 256, 4>(PassArgs<float>, int)"]
+    assert bench.pass_kernels(info, False) == ["void k_bpart<float, float, 8, 256, 4>(PassArgs<float>, int, int)",
                                                "void k_bcombine<float, 0>(PassArgs<float>, int)"]
     if json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))["kernels_hip_sha256"] == \
             bench.kernels_sha256():
         assert bench.measured_traffic(bench.pass_kernels(info, True)) > 0
-    info.update(col_tile_threads=256, col_chunk=2048)
-    assert bench.pass_kernels(info, True) == ["void k_pass<float, 0, 1, 256, 8>(PassArgs<float>, int)"]
-    assert bench.measured_traffic(["void k_pass<float, 0, 1, 256, 8>(PassArgs<float>, int)"]) is None
+        assert bench.measured_traffic(bench.pass_kernels(info, False)) > 0
+    # the non-temporal variant of the same layout is another kernel
+    info["col_cached"] = 0
+    assert bench.pass_kernels(info, True) == ["void k_pass<float, 0, 1, 256, 4>(PassArgs<float>, int)"]
+    assert bench.measured_traffic(bench.pass_kernels(info, True)) is None
+    info.update(col_tile_threads=1024, col_chunk=8192)
+    assert bench.pass_kernels(info, True) == ["void k_pass<float, 0, 1, 1024, 8>(PassArgs<float>, int)"]
+    assert bench.measured_traffic(["void k_pass<float, 0, 1, 1024, 8>(PassArgs<float>, int)"]) is None
     info["col_blocks"] = -1
     assert bench.pass_kernels(info, True) is None

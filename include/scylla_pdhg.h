@@ -571,8 +571,8 @@ int scylla_batch_pump_ex(scylla_batch *h, const scylla_params *params, const uin
  * (instances whose whole gathered vector fits in the LDS alone: the vector
  * is copied to LDS and every row is reduced from its nonzeros in registers,
  * a lane group per row, fused epilogue; the other instances get normal
- * tiles), -7 / -8 = as -6 with at least 4 / 8 lanes per row; *_ept: 4, 8
- * or 16 nonzeros per thread (tiles of 256 * ept nonzeros), or -8 / -16 (the
+ * tiles), -7 / -8 = as -6 with at least 4 / 8 lanes per row; *_ept: 2, 4,
+ * 8 or 16 nonzeros per thread (tiles of 256 * ept nonzeros), or -8 / -16 (the
  * tiles of ept 8 / 16 run by 1024-thread workgroups, 2 / 4 nonzeros per
  * thread).  -EINVAL otherwise. */
 int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept, int32_t col_blocks,

@@ -1793,6 +1793,9 @@ static void dispatch_pass(const PassArgs<V> &p, int ept, int jw, bool check, hip
     case -16:
         check ? launch_check_t<V, FMT, DIR, 1024, 4>(p, s) : launch_pass_t<V, FMT, DIR, 1024, 4>(p, jw, s);
         break;
+    case 2:
+        check ? launch_check_t<V, FMT, DIR, 256, 2>(p, s) : launch_pass_t<V, FMT, DIR, 256, 2>(p, jw, s);
+        break;
     case 4:
         check ? launch_check_t<V, FMT, DIR, 256, 4>(p, s) : launch_pass_t<V, FMT, DIR, 256, 4>(p, jw, s);
         break;
@@ -1812,6 +1815,7 @@ static void dispatch_bpart(const PassArgs<V> &p, int ept, int jw, int check, hip
     switch (ept) {
     case -8: hipLaunchKernelGGL((k_bpart<V, A, FMT, 1024, 2>), g, dim3(1024), 0, s, p, jw, check); break;
     case -16: hipLaunchKernelGGL((k_bpart<V, A, FMT, 1024, 4>), g, dim3(1024), 0, s, p, jw, check); break;
+    case 2: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 2>), g, b, 0, s, p, jw, check); break;
     case 4: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 4>), g, b, 0, s, p, jw, check); break;
     case 8: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 8>), g, b, 0, s, p, jw, check); break;
     default: hipLaunchKernelGGL((k_bpart<V, A, FMT, 256, 16>), g, b, 0, s, p, jw, check); break;

@@ -992,7 +992,7 @@ TuneChoice current_choice(scylla_batch *h)
 }
 
 // Times the layout / tile-size candidates of each orientation and keeps the
-// fastest: the normal layout with 4, 8 or 16 nonzeros per thread, and, when
+// fastest: the normal layout with 2, 4, 8 or 16 nonzeros per thread, and, when
 // the gathered vector is larger than 2 MB, the gather-blocked layout with 2,
 // 4 or 8 blocks (one block per XCD, per XCD pair or per four XCDs).
 template <class V>
@@ -1008,7 +1008,7 @@ void autotune(scylla_batch *h)
         h->tuned = true;
         return;
     }
-    const int epts[5] = {4, 8, 16, -8, -16};
+    const int epts[6] = {2, 4, 8, 16, -8, -16};
     // The matrix load policy first, on the initial layout (both passes
     // timed together): whether an iteration's data fits the device's
     // last-level cache hardly depends on the layout, and the layouts are
@@ -1890,9 +1890,9 @@ int scylla_batch_set_layout(scylla_batch *h, int32_t row_blocks, int32_t row_ept
         auto okB = [](int32_t B) {
             return B == 0 || B == 2 || B == 4 || B == 8 || (B >= -8 && B <= -6) || (B >= -3 && B <= -1);
         };
-        auto okE = [](int32_t e) { return e == 4 || e == 8 || e == 16 || e == -8 || e == -16; };
+        auto okE = [](int32_t e) { return e == 2 || e == 4 || e == 8 || e == 16 || e == -8 || e == -16; };
         if (!okB(row_blocks) || !okB(col_blocks) || !okE(row_ept) || !okE(col_ept))
-            throw_err(-EINVAL, "blocks must be -8, -7, -6, -3, -2, -1, 0, 2, 4 or 8 and ept 4, 8, 16, -8 or -16");
+            throw_err(-EINVAL, "blocks must be -8, -7, -6, -3, -2, -1, 0, 2, 4 or 8 and ept 2, 4, 8, 16, -8 or -16");
         HIPC(hipStreamSynchronize(h->stream));
         for (int d = 0; d < 2; ++d) {
             OrientRT &o = d == 0 ? h->orow : h->ocol;

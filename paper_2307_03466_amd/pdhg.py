@@ -410,7 +410,7 @@ class Batch:
     def set_layout(self, row_blocks: int = 0, row_ept: int = 8, col_blocks: int = 0, col_ept: int = 8):
         """Pin the tile plan (-6 / -7 / -8 direct staged with at least 1 / 4 / 8 lanes per row,
         -3 as -2 in half the LDS, -2 LDS-staged + sliced, -1 LDS-staged, 0 normal,
-        2 / 4 / 8 gather blocks; 4 / 8 / 16 nonzeros per thread, or -8 / -16 on
+        2 / 4 / 8 gather blocks; 2 / 4 / 8 / 16 nonzeros per thread, or -8 / -16 on
         1024-thread workgroups)."""
         _check(lib().scylla_batch_set_layout(self._h, row_blocks, row_ept, col_blocks, col_ept))
 

@@ -273,7 +273,7 @@ def test_time_limit_status():
 
 LAYOUTS = [(0, 4, 0, 16), (2, 8, 2, 4), (4, 8, 4, 4), (8, 4, 8, 8), (8, 16, 0, 8), (-1, 8, -1, 16), (-1, 4, 4, 8),
            (0, -16, 0, -16), (4, -16, 2, -16), (-1, -16, -1, -16), (0, -8, 8, -8), (-6, 8, -6, 8), (-6, 4, 4, 8),
-           (-7, 8, -8, 8), (-8, 4, -7, 4)]
+           (-7, 8, -8, 8), (-8, 4, -7, 4), (0, 2, 4, 2), (4, 2, 0, 2), (-1, 2, -6, 2)]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
